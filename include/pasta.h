@@ -1,0 +1,206 @@
+/*
+ * pasta.h -- C ABI of libpasta, an MI355X (gfx950) implementation of the
+ * molecular-dynamics hot path of the semiclassical nuclear-pasta model of
+ * Caplan, Schneider, Horowitz and Berry, "Pasta Nucleosynthesis: Molecular
+ * dynamics simulations of nuclear statistical equilibrium" (arXiv:1412.8502).
+ *
+ * The model (Sec. II.A): N point nucleons of mass M in a periodic cube of
+ * side L(t); neutrons and protons interact through the two-body potentials
+ * of Eq. (1a-c) with the constants of Table I; the nuclear part is cut at
+ * r_nuc, the screened Coulomb part between protons is not cut; only the
+ * nearest periodic image interacts.  Positions and velocities advance by
+ * velocity Verlet; after each step the box grows as l(t) = l(0)(1 + xi_dot t)
+ * (Eq. 3a) without moving the particles; every 100 steps the velocities are
+ * rescaled to <KE> = (3/2) kT.  The cluster algorithm of Sec. II.C links
+ * protons closer than r_pp and attaches neutrons closer than r_np.
+ *
+ * Conventions for every entry point:
+ *  - Units: MeV, fm, fm/c; velocities in units of c; k_B = 1.
+ *  - d_* arguments are device pointers (HIP device memory of the current
+ *    device), h_* are host pointers.  Every buffer is owned by the caller;
+ *    the library never allocates or frees device memory.  Scratch memory is
+ *    passed in as a caller-owned workspace of at least the size the matching
+ *    *_workspace query returns (256-byte aligned).
+ *  - Particle arrays keep the caller's order: pos and vel are [n][3] FP64
+ *    (x, y, z interleaved), species is [n] uint8 (1 = proton, 0 = neutron).
+ *    Positions must lie in [0, L).
+ *  - `stream` is a hipStream_t (NULL = the null stream).  Work is enqueued
+ *    asynchronously on it; only calls that fill h_* outputs synchronise.
+ *  - Every call returns PASTA_OK (0) or a negative PASTA_E* code;
+ *    pasta_last_error() then describes the failure (thread-local string).
+ *    No C++ exception crosses the ABI.  Device-side checks (non-finite
+ *    forces or velocities, a particle moving more than a cell per step) set
+ *    an error word that the next synchronising call reports as
+ *    PASTA_EDEVICE.
+ */
+#ifndef PASTA_H
+#define PASTA_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define PASTA_OK 0
+#define PASTA_EINVAL (-1)     /* bad argument: null pointer, n < 0, bad mode  */
+#define PASTA_EBOX (-2)       /* L < 2 r_cut: the nearest image is ambiguous  */
+#define PASTA_EWORKSPACE (-3) /* workspace too small or misaligned           */
+#define PASTA_EHIP (-4)       /* a HIP runtime call failed (message has it)   */
+#define PASTA_EDEVICE (-5)    /* device error word set (see pasta_last_error) */
+#define PASTA_ENOMEM (-6)     /* host allocation failed                       */
+
+/* Precision of the pair arithmetic.
+ * PASTA_FP64:  positions, pair arithmetic (differences, exp, sqrt) and
+ *              accumulation in IEEE double.
+ * PASTA_MIXED: pair differences formed exactly from 32-bit fixed-point
+ *              coordinates (x/L * 2^32, so the nearest image is the
+ *              two's-complement wrap of the difference), pair arithmetic
+ *              (Gaussians, screened Coulomb, exp, rsqrt) in FP32, each
+ *              thread's FP32 sum over at most one source tile added into
+ *              FP64 per-particle accumulators.  Positions, velocities, the
+ *              box and the Verlet update stay FP64. */
+#define PASTA_FP64 0
+#define PASTA_MIXED 1
+
+/* Which terms a force call evaluates (bit mask). */
+#define PASTA_TERM_NUCLEAR 1 /* Eq. (1a,b), cut at r_nuc           */
+#define PASTA_TERM_COULOMB 2 /* Eq. (1c) screened Coulomb, uncut    */
+#define PASTA_TERM_ALL 3
+
+/* Interaction parameters (Eq. 1, Table I, Sec. II.A). */
+typedef struct pasta_potential {
+    double a;           /* MeV, short-range repulsion (Table I: 110)        */
+    double b;           /* MeV, intermediate-range attraction (Table I: -26) */
+    double c;           /* MeV, isospin term (Table I: 24); b - c for n-p,
+                           b + c for n-n and p-p                            */
+    double Lambda;      /* fm^2, range of the Gaussians (Table I: 1.25)     */
+    double lambda_s;    /* fm, Coulomb screening length (fixed to 10 fm)    */
+    double alpha_hbarc; /* MeV fm, alpha hbar c = 1.4399645                 */
+    double mass;        /* MeV, nucleon mass (939)                          */
+    double r_nuc;       /* fm, nuclear cutoff (11.5)                        */
+} pasta_potential;
+
+/* Integration parameters (Sec. II.A: velocity Verlet, Eq. 3 box growth,
+ * velocity rescale every 100 steps). */
+typedef struct pasta_integrator {
+    double dt;               /* fm/c time step (the paper: 2)               */
+    double xi_dot;           /* c/fm box expansion rate (0 = fixed box)     */
+    double T;                /* MeV thermostat temperature                  */
+    int32_t rescale_every;   /* rescale v to KE = 1.5 N T after every step
+                                whose index is a multiple of this; 0 = off  */
+    int32_t scale_positions; /* 0: positions not moved by the box growth
+                                (the paper); 1: x *= L_{n+1}/L_n (variant) */
+} pasta_integrator;
+
+/* Fills *out with the paper's values (Table I, lambda = 10 fm, M = 939 MeV,
+ * r_nuc = 11.5 fm, alpha hbar c = 1.4399645 MeV fm). */
+void pasta_potential_paper(pasta_potential* out);
+
+/* Thread-local description of the last error (never NULL). */
+const char* pasta_last_error(void);
+
+/* Library version string. */
+const char* pasta_version(void);
+
+/* ------------------------------------------------------------------ a1 --
+ * Cell list (Sec. II.B.2 bins the volume into cubic cells no narrower than
+ * the interaction range).  ncell = the largest integer with L/ncell >= r_cut.
+ * A particle's cell along an axis is floor(x * (ncell/L)) clamped to
+ * ncell-1; the linear cell index is (cz*ncell + cy)*ncell + cx.  Protons
+ * come first: bin = cell for a proton, ncell^3 + cell for a neutron.
+ * Outputs: d_perm[n] = particle indices in increasing (bin, index) order;
+ * d_cell_start[2*ncell^3 + 1] = first position of each bin in d_perm (the
+ * last entry is n); *h_ncell = ncell.  Requires L >= 2 r_cut. */
+int pasta_cell_list_workspace(int64_t n, double L, double r_cut, size_t* h_bytes);
+int pasta_cell_list(int64_t n, double L, double r_cut, const double* d_pos,
+                    const uint8_t* d_species, int32_t* d_cell_start, int32_t* d_perm,
+                    int32_t* h_ncell, void* d_work, size_t work_bytes, void* stream);
+
+/* -------------------------------------------------------------- a2 + a3 --
+ * One force evaluation (Eq. 1a-c): for every particle i,
+ *   F_i = sum_{j != i} -dV_ij/dr (x_i - x_j)/r   (nearest image),
+ *   E_i = (1/2) sum_{j != i} V_ij               (sum_i E_i = total energy).
+ * `terms` selects the nuclear and/or Coulomb parts.  d_force is [n][3]
+ * MeV/fm, d_epot is [n] MeV (may be NULL).  Requires L >= 2 r_nuc.
+ * Internally: a1 cell list with r_cut = r_nuc, the nuclear cell-tile
+ * kernel, and the all-pairs screened-Coulomb tile kernel. */
+int pasta_forces_workspace(const pasta_potential* pot, int32_t precision, int64_t n,
+                           double L, size_t* h_bytes);
+int pasta_forces(const pasta_potential* pot, int32_t precision, int32_t terms, int64_t n,
+                 double L, const double* d_pos, const uint8_t* d_species, double* d_force,
+                 double* d_epot, void* d_work, size_t work_bytes, void* stream);
+
+/* ------------------------------------------------------------------ a4 --
+ * Simulation handle: velocity Verlet in an expanding periodic box.
+ * Step n -> n+1 (global step index n):
+ *   v += (dt/2M) F_n;  x += dt v;
+ *   L_{n+1} = L0 (1 + xi_dot (n+1) dt)   (Eq. 3a, from the index, never
+ *                                          accumulated);
+ *   [scale_positions: x *= L_{n+1}/L_n];  wrap x into [0, L_{n+1});
+ *   F_{n+1} = F(x, L_{n+1});  v += (dt/2M) F_{n+1};
+ *   if rescale_every > 0 and (n+1) % rescale_every == 0:
+ *       v *= sqrt(1.5 N T / KE),  KE = sum (1/2) M v^2.
+ * The simulation works in place on the caller's d_pos and d_vel, which
+ * always hold the state at the current step (caller order).  d_species
+ * must stay valid and unchanged.  L_max bounds the largest box the run will
+ * reach (it sizes the cell grid); a step that would exceed it fails with
+ * PASTA_EBOX.  pasta_sim_create evaluates F at the starting state. */
+typedef struct pasta_sim pasta_sim;
+int pasta_sim_workspace(const pasta_potential* pot, const pasta_integrator* integ,
+                        int32_t precision, int64_t n, double L_max, size_t* h_bytes);
+int pasta_sim_create(const pasta_potential* pot, const pasta_integrator* integ,
+                     int32_t precision, int64_t n, double L0, int64_t step0, double L_max,
+                     double* d_pos, double* d_vel, const uint8_t* d_species, void* d_work,
+                     size_t work_bytes, void* stream, pasta_sim** out);
+/* Advances nsteps steps (asynchronous). */
+int pasta_sim_step(pasta_sim* sim, int64_t nsteps);
+/* Synchronises; returns kinetic and potential energy (MeV), the box side and
+ * the global step index of the current state.  Any pointer may be NULL. */
+int pasta_sim_energies(pasta_sim* sim, double* h_ekin, double* h_epot, double* h_L,
+                       int64_t* h_step);
+/* Copies the current forces ([n][3], caller order) and energy shares ([n])
+ * to caller buffers (asynchronous; either pointer may be NULL). */
+int pasta_sim_forces(pasta_sim* sim, double* d_force, double* d_epot);
+/* Synchronises; counts unordered pairs inside r_nuc and proton pairs whose
+ * Coulomb term is evaluated, at the current state. */
+int pasta_sim_pair_counts(pasta_sim* sim, int64_t* h_nuclear, int64_t* h_coulomb);
+/* Checkpoint/restart: the state is (d_pos, d_vel, step); L follows from the
+ * step index.  set_state re-evaluates the forces. */
+int pasta_sim_get_step(pasta_sim* sim, int64_t* h_step);
+int pasta_sim_set_state(pasta_sim* sim, const double* d_pos, const double* d_vel,
+                        int64_t step);
+/* Per-kernel timing with HIP events on the simulation's stream.  When on,
+ * every launch is bracketed by events; pasta_sim_kernel_times synchronises
+ * and returns, per kernel class, the summed milliseconds and launch counts
+ * since timing was switched on (arrays of PASTA_KERNEL_CLASSES entries). */
+#define PASTA_KERNEL_CLASSES 8
+int pasta_sim_set_timing(pasta_sim* sim, int32_t on);
+int pasta_sim_kernel_times(pasta_sim* sim, double* h_ms, int64_t* h_launches);
+const char* pasta_kernel_class_name(int32_t k);
+void pasta_sim_destroy(pasta_sim* sim);
+
+/* ------------------------------------------------------------------ a5 --
+ * Cluster algorithm (Sec. II.C).  Protons i, j are linked when their
+ * nearest-image distance satisfies |d|^2 <= r_pp^2; proton clusters are the
+ * connected components (an isolated proton is its own cluster).  A neutron
+ * joins the cluster of its nearest proton with |d|^2 <= r_np^2 (ties go to
+ * the lower proton index); otherwise it is free.  Distances are computed in
+ * FP64 as d = x_i - x_j, d -= L if d > L/2, d += L if d < -L/2,
+ * |d|^2 = (dx*dx + dy*dy) + dz*dz, without fused multiply-add.
+ * Outputs: d_label[n] = canonical cluster label (clusters numbered 0..K-1 in
+ * increasing order of their smallest proton index; -1 = free neutron);
+ * d_hist_A[n+1] and d_hist_Z[n+1]: number of clusters with mass number A and
+ * charge Z; *h_nclusters = K, *h_nfree = free neutrons.  Synchronises.
+ * Requires L >= 2 max(r_pp, r_np). */
+int pasta_cluster_workspace(int64_t n, double L, double r_pp, double r_np, size_t* h_bytes);
+int pasta_cluster(int64_t n, double L, const double* d_pos, const uint8_t* d_species,
+                  double r_pp, double r_np, int32_t* d_label, int32_t* d_hist_A,
+                  int32_t* d_hist_Z, int32_t* h_nclusters, int32_t* h_nfree, void* d_work,
+                  size_t work_bytes, void* stream);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* PASTA_H */

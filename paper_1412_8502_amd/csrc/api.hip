@@ -1,0 +1,655 @@
+// Host side of the C ABI declared in include/pasta.h: argument checks,
+// workspace layout, launch sequences, the simulation handle and the
+// per-kernel event timing.
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <new>
+#include <vector>
+
+#include "internal.hpp"
+
+namespace pasta {
+
+// ------------------------------------------------------------------ errors
+static thread_local char g_err[1024] = "no error";
+
+void set_error(const char* fmt, ...)
+{
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(g_err, sizeof(g_err), fmt, ap);
+    va_end(ap);
+}
+
+int fail(int code, const char* fmt, ...)
+{
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(g_err, sizeof(g_err), fmt, ap);
+    va_end(ap);
+    return code;
+}
+
+std::string describe_device_error(uint32_t bits)
+{
+    std::string s;
+    auto add = [&](uint32_t b, const char* m) {
+        if (bits & b) {
+            if (!s.empty())
+                s += "; ";
+            s += m;
+        }
+    };
+    add(ERR_NONFINITE_FORCE, "non-finite force");
+    add(ERR_NONFINITE_POS, "non-finite position");
+    add(ERR_WRAP, "a particle moved more than one box length in a step");
+    add(ERR_UF_LIMIT, "union-find retry bound reached");
+    add(ERR_NONFINITE_VEL, "non-finite velocity");
+    add(ERR_RANGE, "a position lies outside [0, L)");
+    add(ERR_SPECIES, "a species value is not 0 or 1");
+    if (s.empty())
+        s = "unknown device error";
+    return s;
+}
+
+// ------------------------------------------------------------------ timing
+struct Timer {
+    bool on = false;
+    std::vector<hipEvent_t> pool;
+    size_t used = 0;
+    int open[PASTA_KERNEL_CLASSES];
+    struct Rec {
+        int kc;
+        size_t b, e;
+    };
+    std::vector<Rec> recs;
+    double ms[PASTA_KERNEL_CLASSES] = {};
+    int64_t launches[PASTA_KERNEL_CLASSES] = {};
+    hipEvent_t take()
+    {
+        if (used == pool.size()) {
+            hipEvent_t ev;
+            if (hipEventCreate(&ev) != hipSuccess)
+                return nullptr;
+            pool.push_back(ev);
+        }
+        return pool[used++];
+    }
+    ~Timer()
+    {
+        for (auto ev : pool)
+            (void)hipEventDestroy(ev);
+    }
+};
+
+void timer_begin(Timer* t, int kc, hipStream_t s)
+{
+    if (!t || !t->on)
+        return;
+    hipEvent_t ev = t->take();
+    if (!ev)
+        return;
+    t->open[kc] = (int)(t->used - 1);
+    (void)hipEventRecord(ev, s);
+}
+
+void timer_end(Timer* t, int kc, hipStream_t s)
+{
+    if (!t || !t->on || t->open[kc] < 0)
+        return;
+    hipEvent_t ev = t->take();
+    if (!ev)
+        return;
+    (void)hipEventRecord(ev, s);
+    t->recs.push_back({kc, (size_t)t->open[kc], t->used - 1});
+    t->open[kc] = -1;
+}
+
+static int timer_collect(Timer* t, hipStream_t s)
+{
+    PASTA_HIP(hipStreamSynchronize(s));
+    for (const auto& r : t->recs) {
+        float ms = 0.f;
+        PASTA_HIP(hipEventElapsedTime(&ms, t->pool[r.b], t->pool[r.e]));
+        t->ms[r.kc] += ms;
+        t->launches[r.kc] += 1;
+    }
+    t->recs.clear();
+    t->used = 0;
+    return PASTA_OK;
+}
+
+static int check_pot(const pasta_potential* p)
+{
+    if (!p)
+        return fail(PASTA_EINVAL, "null potential");
+    const double v[] = {p->a, p->b, p->c, p->Lambda, p->lambda_s, p->alpha_hbarc, p->mass,
+                        p->r_nuc};
+    for (double x : v)
+        if (!std::isfinite(x))
+            return fail(PASTA_EINVAL, "non-finite potential parameter");
+    if (!(p->Lambda > 0) || !(p->lambda_s > 0) || !(p->mass > 0) || !(p->r_nuc > 0))
+        return fail(PASTA_EINVAL, "Lambda, lambda_s, mass and r_nuc must be positive");
+    return PASTA_OK;
+}
+
+static PairParams pair_params(const pasta_potential* p, double L)
+{
+    PairParams pp;
+    pp.a = p->a;
+    pp.b_like = p->b + p->c;
+    pp.b_unlike = p->b - p->c;
+    pp.Lambda = p->Lambda;
+    pp.r_nuc = p->r_nuc;
+    pp.alpha_hbarc = p->alpha_hbarc;
+    pp.lambda_s = p->lambda_s;
+    pp.L = L;
+    return pp;
+}
+
+// Shared layout of the force workspace (a1 + a2 + a3).
+struct ForceWork {
+    CellBuf cb;
+    ForceBuf fb;
+    uint32_t* err;
+    double* red;  // [256] reduction partials
+    double* scale;  // [2]
+};
+static size_t force_carve(Carver& cv, ForceWork* w, int64_t n, int C_max, int precision)
+{
+    ForceWork fw;
+    const int chunk = nuclear_chunk(precision);
+    cellbuf_carve(cv, &fw.cb, n, C_max, chunk);
+    forcebuf_carve(cv, &fw.fb, n, fw.cb.item_max, precision);
+    fw.err = cv.take<uint32_t>(1);
+    fw.red = cv.take<double>(256);
+    fw.scale = cv.take<double>(2);
+    if (w)
+        *w = fw;
+    return cv.size();
+}
+
+static int check_work(void* d_work, size_t work_bytes, size_t need, const char* who)
+{
+    if (!d_work || work_bytes < need || (reinterpret_cast<uintptr_t>(d_work) & 255))
+        return fail(PASTA_EWORKSPACE, "%s: workspace needs %zu bytes, 256-byte aligned (got %zu)",
+                    who, need, work_bytes);
+    return PASTA_OK;
+}
+
+static int read_err(uint32_t* d_err, hipStream_t s, const char* who)
+{
+    uint32_t e = 0;
+    PASTA_HIP(hipMemcpyAsync(&e, d_err, sizeof(e), hipMemcpyDeviceToHost, s));
+    PASTA_HIP(hipStreamSynchronize(s));
+    if (e & (ERR_RANGE | ERR_SPECIES))
+        return fail(PASTA_EINVAL, "%s: %s", who, describe_device_error(e).c_str());
+    if (e)
+        return fail(PASTA_EDEVICE, "%s: %s", who, describe_device_error(e).c_str());
+    return PASTA_OK;
+}
+
+// Build the cell list (+ staging) for positions at box side L and return Z.
+static int build_cells(const double* pos, const uint8_t* species, int64_t n, const Grid& g,
+                       ForceWork& w, int precision, hipStream_t s, Timer* t)
+{
+    launch_bin_count(pos, species, n, g, w.cb, w.err, s, t);
+    launch_scan(w.cb, g.C, nuclear_chunk(precision), s, t);
+    launch_scatter_rank(pos, species, n, g, w.cb, w.fb.stg64, w.fb.stgq, s, t);
+    return PASTA_OK;
+}
+
+static void eval_forces(int precision, int terms, const ForceWork& w, const Grid& g, int64_t n,
+                        int64_t Z, const PairParams& pp, double* force, double* epot,
+                        const KickArgs& kick, uint64_t* pair_counter, hipStream_t s, Timer* t)
+{
+    int S = 0;
+    if ((terms & PASTA_TERM_COULOMB) && Z > 0) {
+        launch_coulomb(precision, w.fb, Z, pp, nullptr, s, t);
+        S = coulomb_splits(Z);
+    }
+    launch_nuclear(precision, w.fb, w.cb, g, n, Z, pp, (terms & PASTA_TERM_NUCLEAR) != 0, S,
+                   force, epot, kick, pair_counter, w.err, s, t);
+}
+
+}  // namespace pasta
+
+using namespace pasta;
+
+// ===================================================================== ABI
+
+extern "C" const char* pasta_last_error(void) { return g_err; }
+
+extern "C" const char* pasta_version(void) { return "libpasta 0.1 (gfx950)"; }
+
+extern "C" void pasta_potential_paper(pasta_potential* out)
+{
+    if (!out)
+        return;
+    out->a = 110.0;
+    out->b = -26.0;
+    out->c = 24.0;
+    out->Lambda = 1.25;
+    out->lambda_s = 10.0;
+    out->alpha_hbarc = 7.2973525693e-3 * 197.3269804;
+    out->mass = 939.0;
+    out->r_nuc = 11.5;
+}
+
+extern "C" const char* pasta_kernel_class_name(int32_t k)
+{
+    static const char* names[PASTA_KERNEL_CLASSES] = {
+        "drift+bin", "scan", "scatter", "rank+stage", "coulomb", "nuclear+kick", "thermostat",
+        "other"};
+    return (k >= 0 && k < PASTA_KERNEL_CLASSES) ? names[k] : "?";
+}
+
+// ------------------------------------------------------------------- a1
+extern "C" int pasta_cell_list_workspace(int64_t n, double L, double r_cut, size_t* h_bytes)
+{
+    if (!h_bytes || n < 0 || !(L > 0.0) || !(r_cut > 0.0) || !std::isfinite(L))
+        return fail(PASTA_EINVAL, "pasta_cell_list_workspace: bad argument");
+    const Grid g = make_grid(L, r_cut);
+    Carver cv(nullptr);
+    CellBuf cb;
+    cellbuf_carve(cv, &cb, n, g.C, 0);
+    cv.take<uint32_t>(1);
+    *h_bytes = cv.size();
+    return PASTA_OK;
+}
+
+extern "C" int pasta_cell_list(int64_t n, double L, double r_cut, const double* d_pos,
+                               const uint8_t* d_species, int32_t* d_cell_start, int32_t* d_perm,
+                               int32_t* h_ncell, void* d_work, size_t work_bytes, void* stream)
+{
+    if (n < 0 || n > INT32_MAX - 1 || (n > 0 && (!d_pos || !d_species || !d_perm)) ||
+        !d_cell_start || !(L > 0.0) || !std::isfinite(L) || !(r_cut > 0.0))
+        return fail(PASTA_EINVAL, "pasta_cell_list: bad argument");
+    if (L < 2.0 * r_cut)
+        return fail(PASTA_EBOX, "pasta_cell_list: L = %g < 2 r_cut = %g", L, 2.0 * r_cut);
+    size_t need = 0;
+    PASTA_TRY(pasta_cell_list_workspace(n, L, r_cut, &need));
+    PASTA_TRY(check_work(d_work, work_bytes, need, "pasta_cell_list"));
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    const Grid g = make_grid(L, r_cut);
+    Carver cv(d_work);
+    CellBuf cb;
+    cellbuf_carve(cv, &cb, n, g.C, 0);
+    uint32_t* err = cv.take<uint32_t>(1);
+    PASTA_HIP(hipMemsetAsync(err, 0, sizeof(uint32_t), s));
+    cellbuf_zero(cb, g.C, s);
+    launch_bin_count(d_pos, d_species, n, g, cb, err, s, nullptr);
+    launch_scan(cb, g.C, 0, s, nullptr);
+    launch_scatter_rank(d_pos, d_species, n, g, cb, nullptr, nullptr, s, nullptr);
+    PASTA_HIP(hipMemcpyAsync(d_cell_start, cb.start, sizeof(int32_t) * (2 * (size_t)g.C + 1),
+                             hipMemcpyDeviceToDevice, s));
+    if (n > 0)
+        PASTA_HIP(hipMemcpyAsync(d_perm, cb.perm, sizeof(int32_t) * n, hipMemcpyDeviceToDevice, s));
+    PASTA_HIP(hipGetLastError());
+    if (h_ncell)
+        *h_ncell = g.nc;
+    return read_err(err, s, "pasta_cell_list");
+}
+
+// -------------------------------------------------------------- a2 + a3
+extern "C" int pasta_forces_workspace(const pasta_potential* pot, int32_t precision, int64_t n,
+                                      double L, size_t* h_bytes)
+{
+    PASTA_TRY(check_pot(pot));
+    if (!h_bytes || n < 0 || !(L > 0.0) || !std::isfinite(L) ||
+        (precision != PASTA_FP64 && precision != PASTA_MIXED))
+        return fail(PASTA_EINVAL, "pasta_forces_workspace: bad argument");
+    const Grid g = make_grid(L, pot->r_nuc);
+    Carver cv(nullptr);
+    *h_bytes = force_carve(cv, nullptr, n, g.C, precision);
+    return PASTA_OK;
+}
+
+extern "C" int pasta_forces(const pasta_potential* pot, int32_t precision, int32_t terms,
+                            int64_t n, double L, const double* d_pos, const uint8_t* d_species,
+                            double* d_force, double* d_epot, void* d_work, size_t work_bytes,
+                            void* stream)
+{
+    PASTA_TRY(check_pot(pot));
+    if (n < 0 || n > INT32_MAX - 1 || (n > 0 && (!d_pos || !d_species || !d_force)) ||
+        !(L > 0.0) || !std::isfinite(L) || (terms & ~PASTA_TERM_ALL) ||
+        (precision != PASTA_FP64 && precision != PASTA_MIXED))
+        return fail(PASTA_EINVAL, "pasta_forces: bad argument");
+    if (L < 2.0 * pot->r_nuc)
+        return fail(PASTA_EBOX, "pasta_forces: L = %g < 2 r_nuc = %g", L, 2.0 * pot->r_nuc);
+    size_t need = 0;
+    PASTA_TRY(pasta_forces_workspace(pot, precision, n, L, &need));
+    PASTA_TRY(check_work(d_work, work_bytes, need, "pasta_forces"));
+    if (n == 0)
+        return PASTA_OK;
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    const Grid g = make_grid(L, pot->r_nuc);
+    ForceWork w;
+    Carver cv(d_work);
+    force_carve(cv, &w, n, g.C, precision);
+    PASTA_HIP(hipMemsetAsync(w.err, 0, sizeof(uint32_t), s));
+    cellbuf_zero(w.cb, g.C, s);
+    build_cells(d_pos, d_species, n, g, w, precision, s, nullptr);
+    int32_t Z = 0;
+    PASTA_HIP(hipMemcpyAsync(&Z, w.cb.start + g.C, sizeof(int32_t), hipMemcpyDeviceToHost, s));
+    PASTA_HIP(hipStreamSynchronize(s));
+    KickArgs kick{nullptr, 0.0, pot->mass, nullptr};
+    eval_forces(precision, terms, w, g, n, Z, pair_params(pot, L), d_force, d_epot, kick,
+                nullptr, s, nullptr);
+    PASTA_HIP(hipGetLastError());
+    return read_err(w.err, s, "pasta_forces");
+}
+
+// ------------------------------------------------------------------- a4
+struct pasta_sim {
+    pasta_potential pot;
+    pasta_integrator integ;
+    int precision;
+    int64_t n, Z;
+    double L0, L_max;
+    int64_t step;
+    double* pos;
+    double* vel;
+    const uint8_t* species;
+    hipStream_t stream;
+    int C_max;
+    ForceWork w;
+    double* force;
+    double* epot;
+    Timer timer;
+};
+
+static double box_side(const pasta_sim* sim, int64_t step)
+{
+    // Eq. (3a): l(t) = l(0) (1 + xi_dot t), t = step dt, from the index
+    return sim->L0 * (1.0 + sim->integ.xi_dot * ((double)step * sim->integ.dt));
+}
+
+static size_t sim_carve(Carver& cv, ForceWork* w, double** force, double** epot, int64_t n,
+                        int C_max, int precision)
+{
+    force_carve(cv, w, n, C_max, precision);
+    double* f = cv.take<double>(3 * (size_t)n);
+    double* e = cv.take<double>((size_t)n);
+    if (force)
+        *force = f;
+    if (epot)
+        *epot = e;
+    return cv.size();
+}
+
+static int check_integ(const pasta_integrator* g)
+{
+    if (!g)
+        return fail(PASTA_EINVAL, "null integrator");
+    if (!(g->dt > 0.0) || !std::isfinite(g->dt) || !std::isfinite(g->xi_dot) ||
+        !(g->T >= 0.0) || g->rescale_every < 0)
+        return fail(PASTA_EINVAL, "bad integrator parameters");
+    return PASTA_OK;
+}
+
+extern "C" int pasta_sim_workspace(const pasta_potential* pot, const pasta_integrator* integ,
+                                   int32_t precision, int64_t n, double L_max, size_t* h_bytes)
+{
+    PASTA_TRY(check_pot(pot));
+    PASTA_TRY(check_integ(integ));
+    if (!h_bytes || n < 0 || !(L_max > 0.0) || !std::isfinite(L_max) ||
+        (precision != PASTA_FP64 && precision != PASTA_MIXED))
+        return fail(PASTA_EINVAL, "pasta_sim_workspace: bad argument");
+    const Grid g = make_grid(L_max, pot->r_nuc);
+    Carver cv(nullptr);
+    *h_bytes = sim_carve(cv, nullptr, nullptr, nullptr, n, g.C, precision);
+    return PASTA_OK;
+}
+
+static int sim_eval_initial(pasta_sim* sim)
+{
+    hipStream_t s = sim->stream;
+    const double L = box_side(sim, sim->step);
+    const Grid g = make_grid(L, sim->pot.r_nuc);
+    build_cells(sim->pos, sim->species, sim->n, g, sim->w, sim->precision, s, &sim->timer);
+    int32_t Z = 0;
+    PASTA_HIP(hipMemcpyAsync(&Z, sim->w.cb.start + g.C, sizeof(int32_t), hipMemcpyDeviceToHost, s));
+    PASTA_HIP(hipStreamSynchronize(s));
+    sim->Z = Z;
+    KickArgs kick{nullptr, 0.0, sim->pot.mass, nullptr};
+    eval_forces(sim->precision, PASTA_TERM_ALL, sim->w, g, sim->n, sim->Z,
+                pair_params(&sim->pot, L), sim->force, sim->epot, kick, nullptr, s, &sim->timer);
+    PASTA_HIP(hipGetLastError());
+    return read_err(sim->w.err, s, "pasta_sim");
+}
+
+extern "C" int pasta_sim_create(const pasta_potential* pot, const pasta_integrator* integ,
+                                int32_t precision, int64_t n, double L0, int64_t step0,
+                                double L_max, double* d_pos, double* d_vel,
+                                const uint8_t* d_species, void* d_work, size_t work_bytes,
+                                void* stream, pasta_sim** out)
+{
+    PASTA_TRY(check_pot(pot));
+    PASTA_TRY(check_integ(integ));
+    if (!out || n <= 0 || n > INT32_MAX - 1 || !d_pos || !d_vel || !d_species ||
+        !(L0 > 0.0) || !std::isfinite(L0) || step0 < 0 ||
+        (precision != PASTA_FP64 && precision != PASTA_MIXED))
+        return fail(PASTA_EINVAL, "pasta_sim_create: bad argument");
+    *out = nullptr;
+    pasta_sim* sim = new (std::nothrow) pasta_sim();
+    if (!sim)
+        return fail(PASTA_ENOMEM, "pasta_sim_create: out of host memory");
+    sim->pot = *pot;
+    sim->integ = *integ;
+    sim->precision = precision;
+    sim->n = n;
+    sim->L0 = L0;
+    sim->step = step0;
+    sim->pos = d_pos;
+    sim->vel = d_vel;
+    sim->species = d_species;
+    sim->stream = static_cast<hipStream_t>(stream);
+    const double Lstart = box_side(sim, step0);
+    sim->L_max = L_max > Lstart ? L_max : Lstart;
+    if (Lstart < 2.0 * pot->r_nuc) {
+        delete sim;
+        return fail(PASTA_EBOX, "pasta_sim_create: L = %g < 2 r_nuc", Lstart);
+    }
+    sim->C_max = make_grid(sim->L_max, pot->r_nuc).C;
+    Carver cv0(nullptr);
+    const size_t need = sim_carve(cv0, nullptr, nullptr, nullptr, n, sim->C_max, precision);
+    int rc = check_work(d_work, work_bytes, need, "pasta_sim_create");
+    if (rc != PASTA_OK) {
+        delete sim;
+        return rc;
+    }
+    Carver cv(d_work);
+    sim_carve(cv, &sim->w, &sim->force, &sim->epot, n, sim->C_max, precision);
+    for (int k = 0; k < PASTA_KERNEL_CLASSES; ++k)
+        sim->timer.open[k] = -1;
+    hipStream_t s = sim->stream;
+    if (hipMemsetAsync(sim->w.err, 0, sizeof(uint32_t), s) != hipSuccess) {
+        delete sim;
+        return fail(PASTA_EHIP, "hipMemsetAsync failed");
+    }
+    cellbuf_zero(sim->w.cb, sim->C_max, s);
+    rc = sim_eval_initial(sim);
+    if (rc != PASTA_OK) {
+        delete sim;
+        return rc;
+    }
+    *out = sim;
+    return PASTA_OK;
+}
+
+extern "C" int pasta_sim_step(pasta_sim* sim, int64_t nsteps)
+{
+    if (!sim || nsteps < 0)
+        return fail(PASTA_EINVAL, "pasta_sim_step: bad argument");
+    hipStream_t s = sim->stream;
+    const pasta_integrator& gi = sim->integ;
+    const double hdtm = gi.dt / (2.0 * sim->pot.mass);
+    for (int64_t k = 0; k < nsteps; ++k) {
+        const int64_t n0 = sim->step;
+        const double L_old = box_side(sim, n0), L_new = box_side(sim, n0 + 1);
+        if (L_new > sim->L_max * (1.0 + 1e-12) || L_new < 2.0 * sim->pot.r_nuc)
+            return fail(PASTA_EBOX, "pasta_sim_step: box side %g at step %lld is outside "
+                        "[2 r_nuc, L_max = %g]", L_new, (long long)(n0 + 1), sim->L_max);
+        const Grid g = make_grid(L_new, sim->pot.r_nuc);
+        DriftArgs da;
+        da.pos = sim->pos;
+        da.vel = sim->vel;
+        da.force = sim->force;
+        da.species = sim->species;
+        da.n = sim->n;
+        da.hdtm = hdtm;
+        da.dt = gi.dt;
+        da.L_new = L_new;
+        da.ratio = L_new / L_old;
+        da.scale_positions = gi.scale_positions;
+        launch_drift(da, g, sim->w.cb, sim->w.err, s, &sim->timer);
+        launch_scan(sim->w.cb, g.C, nuclear_chunk(sim->precision), s, &sim->timer);
+        launch_scatter_rank(sim->pos, sim->species, sim->n, g, sim->w.cb, sim->w.fb.stg64,
+                            sim->w.fb.stgq, s, &sim->timer);
+        const bool thermo = gi.rescale_every > 0 && (n0 + 1) % gi.rescale_every == 0;
+        KickArgs kick{sim->vel, hdtm, sim->pot.mass, thermo ? sim->w.fb.ke_part : nullptr};
+        eval_forces(sim->precision, PASTA_TERM_ALL, sim->w, g, sim->n, sim->Z,
+                    pair_params(&sim->pot, L_new), sim->force, sim->epot, kick, nullptr, s,
+                    &sim->timer);
+        if (thermo)
+            launch_thermostat(sim->vel, sim->n, sim->w.fb.ke_part, sim->w.cb.n_items,
+                              1.5 * (double)sim->n * gi.T, sim->w.scale, s, &sim->timer);
+        sim->step = n0 + 1;
+    }
+    PASTA_HIP(hipGetLastError());
+    return PASTA_OK;
+}
+
+static int sum_on_device(pasta_sim* sim, const double* x, int64_t n, int kind, double* out)
+{
+    hipStream_t s = sim->stream;
+    launch_partial_sums(x, n, kind, sim->pot.mass, sim->w.red, 256, s);
+    double h[256];
+    PASTA_HIP(hipMemcpyAsync(h, sim->w.red, sizeof(h), hipMemcpyDeviceToHost, s));
+    PASTA_HIP(hipStreamSynchronize(s));
+    double acc = 0.0;
+    for (double v : h)
+        acc += v;
+    *out = acc;
+    return PASTA_OK;
+}
+
+extern "C" int pasta_sim_energies(pasta_sim* sim, double* h_ekin, double* h_epot, double* h_L,
+                                  int64_t* h_step)
+{
+    if (!sim)
+        return fail(PASTA_EINVAL, "pasta_sim_energies: null sim");
+    PASTA_TRY(read_err(sim->w.err, sim->stream, "pasta_sim"));
+    if (h_ekin)
+        PASTA_TRY(sum_on_device(sim, sim->vel, sim->n, 1, h_ekin));
+    if (h_epot)
+        PASTA_TRY(sum_on_device(sim, sim->epot, sim->n, 0, h_epot));
+    if (h_L)
+        *h_L = box_side(sim, sim->step);
+    if (h_step)
+        *h_step = sim->step;
+    return PASTA_OK;
+}
+
+extern "C" int pasta_sim_forces(pasta_sim* sim, double* d_force, double* d_epot)
+{
+    if (!sim)
+        return fail(PASTA_EINVAL, "pasta_sim_forces: null sim");
+    if (d_force)
+        PASTA_HIP(hipMemcpyAsync(d_force, sim->force, sizeof(double) * 3 * sim->n,
+                                 hipMemcpyDeviceToDevice, sim->stream));
+    if (d_epot)
+        PASTA_HIP(hipMemcpyAsync(d_epot, sim->epot, sizeof(double) * sim->n,
+                                 hipMemcpyDeviceToDevice, sim->stream));
+    return PASTA_OK;
+}
+
+extern "C" int pasta_sim_pair_counts(pasta_sim* sim, int64_t* h_nuclear, int64_t* h_coulomb)
+{
+    if (!sim)
+        return fail(PASTA_EINVAL, "pasta_sim_pair_counts: null sim");
+    hipStream_t s = sim->stream;
+    const double L = box_side(sim, sim->step);
+    const Grid g = make_grid(L, sim->pot.r_nuc);
+    uint64_t* ctr = sim->w.fb.pairs;
+    PASTA_HIP(hipMemsetAsync(ctr, 0, 2 * sizeof(uint64_t), s));
+    KickArgs kick{nullptr, 0.0, sim->pot.mass, nullptr};
+    // the cell list and staging of the current state are in place
+    eval_forces(sim->precision, PASTA_TERM_ALL, sim->w, g, sim->n, sim->Z,
+                pair_params(&sim->pot, L), sim->force, sim->epot, kick, ctr, s, nullptr);
+    uint64_t h[2] = {0, 0};
+    PASTA_HIP(hipMemcpyAsync(h, ctr, sizeof(h), hipMemcpyDeviceToHost, s));
+    PASTA_HIP(hipStreamSynchronize(s));
+    if (h_nuclear)
+        *h_nuclear = (int64_t)(h[0] / 2);  // ordered -> unordered
+    if (h_coulomb)
+        *h_coulomb = sim->Z * (sim->Z - 1) / 2;
+    return PASTA_OK;
+}
+
+extern "C" int pasta_sim_get_step(pasta_sim* sim, int64_t* h_step)
+{
+    if (!sim || !h_step)
+        return fail(PASTA_EINVAL, "pasta_sim_get_step: bad argument");
+    *h_step = sim->step;
+    return PASTA_OK;
+}
+
+extern "C" int pasta_sim_set_state(pasta_sim* sim, const double* d_pos, const double* d_vel,
+                                   int64_t step)
+{
+    if (!sim || step < 0)
+        return fail(PASTA_EINVAL, "pasta_sim_set_state: bad argument");
+    const double L = box_side(sim, step);
+    if (L > sim->L_max * (1.0 + 1e-12) || L < 2.0 * sim->pot.r_nuc)
+        return fail(PASTA_EBOX, "pasta_sim_set_state: box side %g out of range", L);
+    hipStream_t s = sim->stream;
+    if (d_pos && d_pos != sim->pos)
+        PASTA_HIP(hipMemcpyAsync(sim->pos, d_pos, sizeof(double) * 3 * sim->n,
+                                 hipMemcpyDeviceToDevice, s));
+    if (d_vel && d_vel != sim->vel)
+        PASTA_HIP(hipMemcpyAsync(sim->vel, d_vel, sizeof(double) * 3 * sim->n,
+                                 hipMemcpyDeviceToDevice, s));
+    sim->step = step;
+    return sim_eval_initial(sim);
+}
+
+extern "C" int pasta_sim_set_timing(pasta_sim* sim, int32_t on)
+{
+    if (!sim)
+        return fail(PASTA_EINVAL, "pasta_sim_set_timing: null sim");
+    if (on) {
+        PASTA_TRY(timer_collect(&sim->timer, sim->stream));
+        for (int k = 0; k < PASTA_KERNEL_CLASSES; ++k) {
+            sim->timer.ms[k] = 0.0;
+            sim->timer.launches[k] = 0;
+            sim->timer.open[k] = -1;
+        }
+    }
+    sim->timer.on = on != 0;
+    return PASTA_OK;
+}
+
+extern "C" int pasta_sim_kernel_times(pasta_sim* sim, double* h_ms, int64_t* h_launches)
+{
+    if (!sim)
+        return fail(PASTA_EINVAL, "pasta_sim_kernel_times: null sim");
+    PASTA_TRY(timer_collect(&sim->timer, sim->stream));
+    for (int k = 0; k < PASTA_KERNEL_CLASSES; ++k) {
+        if (h_ms)
+            h_ms[k] = sim->timer.ms[k];
+        if (h_launches)
+            h_launches[k] = sim->timer.launches[k];
+    }
+    return PASTA_OK;
+}
+
+extern "C" void pasta_sim_destroy(pasta_sim* sim)
+{
+    if (!sim)
+        return;
+    (void)hipStreamSynchronize(sim->stream);
+    delete sim;
+}

@@ -1,0 +1,230 @@
+// Cell-list build: a stable counting sort of particles into cubic cells no
+// narrower than the interaction range (the binning of Sec. II.B.2), rebuilt
+// from scratch every step.  Memory-bound; four launches:
+//   bin/count   one thread per particle: bin = (proton ? 0 : C) + cell,
+//               integer atomic count per bin (order-independent);
+//   scan        one workgroup: exclusive scan of the 2C counts, the nuclear
+//               work list (cell, target chunk), and the reset of the counters;
+//   scatter     one thread per particle: slot = start[bin] + atomic cursor
+//               (arrival order, not yet stable);
+//   rank        one thread per slot: the stable rank inside the bin is the
+//               number of bin members with a smaller particle index, so the
+//               final order is (bin, index) whatever order the atomics took;
+//               the same thread gathers the particle's staging coordinates.
+#include "internal.hpp"
+
+namespace pasta {
+
+namespace {
+
+__global__ __launch_bounds__(256) void k_bin_count(const double* __restrict__ pos,
+                                                   const uint8_t* __restrict__ species,
+                                                   int64_t n, int nc, int C, double inv_w,
+                                                   double L, int32_t* __restrict__ key,
+                                                   int32_t* __restrict__ count,
+                                                   uint32_t* __restrict__ err)
+{
+    int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n)
+        return;
+    double x = pos[3 * i + 0], y = pos[3 * i + 1], z = pos[3 * i + 2];
+    const uint8_t sp = species[i];
+    if (!(x >= 0.0 && x < L && y >= 0.0 && y < L && z >= 0.0 && z < L))
+        atomicOr(err, (isfinite(x) && isfinite(y) && isfinite(z)) ? ERR_RANGE : ERR_NONFINITE_POS);
+    if (sp > 1)
+        atomicOr(err, ERR_SPECIES);
+    int cx = cell_coord(x, inv_w, nc), cy = cell_coord(y, inv_w, nc),
+        cz = cell_coord(z, inv_w, nc);
+    int bin = (sp == 1 ? 0 : C) + (cz * nc + cy) * nc + cx;
+    key[i] = bin;
+    atomicAdd(&count[bin], 1);
+}
+
+constexpr int SCAN_THREADS = 1024;
+
+// Exclusive scan of v[0..m) (per-thread contiguous runs + LDS scan of the
+// run totals).  Returns the grand total to every thread.
+__device__ int64_t block_scan_runs(const int32_t* v, int32_t* out, int64_t m,
+                                   int64_t* lds)
+{
+    const int tid = threadIdx.x;
+    const int64_t per = (m + SCAN_THREADS - 1) / SCAN_THREADS;
+    const int64_t b = tid * per, e = b + per < m ? b + per : m;
+    int64_t s = 0;
+    for (int64_t k = b; k < e; ++k)
+        s += v[k];
+    lds[tid] = s;
+    __syncthreads();
+    for (int off = 1; off < SCAN_THREADS; off <<= 1) {
+        int64_t t = tid >= off ? lds[tid - off] : 0;
+        __syncthreads();
+        lds[tid] += t;
+        __syncthreads();
+    }
+    int64_t run = lds[tid] - s;  // exclusive prefix of this thread's run
+    int64_t total = lds[SCAN_THREADS - 1];
+    for (int64_t k = b; k < e; ++k) {
+        int32_t c = v[k];
+        out[k] = (int32_t)run;
+        run += c;
+    }
+    __syncthreads();
+    return total;
+}
+
+__global__ __launch_bounds__(SCAN_THREADS) void k_scan(int32_t* __restrict__ count,
+                                                       int32_t* __restrict__ fill,
+                                                       int32_t* __restrict__ start, int C,
+                                                       int chunk, int32_t* __restrict__ items,
+                                                       int32_t* __restrict__ n_items,
+                                                       int32_t* __restrict__ tmpc)
+{
+    __shared__ int64_t lds[SCAN_THREADS];
+    const int tid = threadIdx.x;
+    const int64_t nb = 2 * (int64_t)C;
+    int64_t total = block_scan_runs(count, start, nb, lds);
+    if (tid == 0)
+        start[nb] = (int32_t)total;
+    __syncthreads();
+    if (chunk > 0) {
+        // chunks per cell (protons + neutrons of the cell)
+        for (int64_t c = tid; c < C; c += SCAN_THREADS) {
+            int32_t m = count[c] + count[C + c];
+            tmpc[c] = (m + chunk - 1) / chunk;
+        }
+        __syncthreads();
+        int64_t nit = block_scan_runs(tmpc, tmpc + C, C, lds);
+        for (int64_t c = tid; c < C; c += SCAN_THREADS) {
+            int32_t base = tmpc[C + c], k = tmpc[c];
+            for (int32_t q = 0; q < k; ++q) {
+                items[2 * (base + q) + 0] = (int32_t)c;
+                items[2 * (base + q) + 1] = q;
+            }
+        }
+        if (tid == 0)
+            *n_items = (int32_t)nit;
+        __syncthreads();
+    }
+    for (int64_t k = tid; k < nb; k += SCAN_THREADS) {
+        count[k] = 0;
+        fill[k] = 0;
+    }
+}
+
+__global__ __launch_bounds__(256) void k_scatter(const int32_t* __restrict__ key, int64_t n,
+                                                 const int32_t* __restrict__ start,
+                                                 int32_t* __restrict__ fill,
+                                                 int32_t* __restrict__ tmp)
+{
+    int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n)
+        return;
+    int b = key[i];
+    int slot = start[b] + atomicAdd(&fill[b], 1);
+    tmp[slot] = (int32_t)i;
+}
+
+__global__ __launch_bounds__(256) void k_rank(const int32_t* __restrict__ key,
+                                              const int32_t* __restrict__ tmp, int64_t n,
+                                              const int32_t* __restrict__ start,
+                                              int32_t* __restrict__ perm,
+                                              const double* __restrict__ pos,
+                                              const uint8_t* __restrict__ species,
+                                              double4* __restrict__ stg64,
+                                              Q4* __restrict__ stgq, double qscale)
+{
+    int64_t s = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (s >= n)
+        return;
+    int32_t id = tmp[s];
+    int b = key[id];
+    int beg = start[b], end = start[b + 1];
+    int r = 0;
+    for (int k = beg; k < end; ++k)
+        r += tmp[k] < id;
+    int dst = beg + r;
+    perm[dst] = id;
+    double x = pos[3 * (int64_t)id + 0], y = pos[3 * (int64_t)id + 1],
+           z = pos[3 * (int64_t)id + 2];
+    if (stg64)
+        stg64[dst] = make_double4(x, y, z, (double)species[id]);
+    if (stgq) {
+        Q4 q;
+        q.x = (uint32_t)(uint64_t)(x * qscale);
+        q.y = (uint32_t)(uint64_t)(y * qscale);
+        q.z = (uint32_t)(uint64_t)(z * qscale);
+        q.w = species[id];
+        stgq[dst] = q;
+    }
+}
+
+__global__ void k_zero2(int32_t* a, int32_t* b, int64_t m)
+{
+    int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (k < m) {
+        a[k] = 0;
+        b[k] = 0;
+    }
+}
+
+inline unsigned blocks_for(int64_t n, int bs) { return (unsigned)((n + bs - 1) / bs); }
+
+}  // namespace
+
+size_t cellbuf_carve(Carver& cv, CellBuf* out, int64_t n, int C_max, int chunk)
+{
+    CellBuf cb;
+    cb.key = cv.take<int32_t>(n);
+    cb.count = cv.take<int32_t>(2 * (size_t)C_max);
+    cb.fill = cv.take<int32_t>(2 * (size_t)C_max);
+    cb.start = cv.take<int32_t>(2 * (size_t)C_max + 1);
+    cb.tmp = cv.take<int32_t>(n > 2 * (int64_t)C_max ? n : 2 * (int64_t)C_max);
+    cb.perm = cv.take<int32_t>(n);
+    cb.item_max = chunk > 0 ? n / chunk + C_max + 1 : 1;
+    cb.items = cv.take<int32_t>(2 * (size_t)cb.item_max);
+    cb.n_items = cv.take<int32_t>(1);
+    if (out)
+        *out = cb;
+    return cv.size();
+}
+
+void cellbuf_zero(const CellBuf& cb, int C_max, hipStream_t s)
+{
+    int64_t m = 2 * (int64_t)C_max;
+    k_zero2<<<blocks_for(m, 256), 256, 0, s>>>(cb.count, cb.fill, m);
+}
+
+void launch_bin_count(const double* pos, const uint8_t* species, int64_t n, const Grid& g,
+                      const CellBuf& cb, uint32_t* err, hipStream_t s, Timer* t)
+{
+    timer_begin(t, KC_DRIFT, s);
+    if (n > 0)
+        k_bin_count<<<blocks_for(n, 256), 256, 0, s>>>(pos, species, n, g.nc, g.C, g.inv_w,
+                                                       g.L, cb.key, cb.count, err);
+    timer_end(t, KC_DRIFT, s);
+}
+
+void launch_scan(const CellBuf& cb, int C, int chunk, hipStream_t s, Timer* t)
+{
+    timer_begin(t, KC_SCAN, s);
+    // cb.tmp doubles as the per-cell chunk-count scratch (2C entries)
+    k_scan<<<1, SCAN_THREADS, 0, s>>>(cb.count, cb.fill, cb.start, C, chunk, cb.items,
+                                      cb.n_items, cb.tmp);
+    timer_end(t, KC_SCAN, s);
+}
+
+void launch_scatter_rank(const double* pos, const uint8_t* species, int64_t n, const Grid& g,
+                         const CellBuf& cb, double4* stg64, Q4* stgq, hipStream_t s, Timer* t)
+{
+    if (n <= 0)
+        return;
+    timer_begin(t, KC_SCATTER, s);
+    k_scatter<<<blocks_for(n, 256), 256, 0, s>>>(cb.key, n, cb.start, cb.fill, cb.tmp);
+    timer_end(t, KC_SCATTER, s);
+    timer_begin(t, KC_RANK, s);
+    k_rank<<<blocks_for(n, 256), 256, 0, s>>>(cb.key, cb.tmp, n, cb.start, cb.perm, pos,
+                                              species, stg64, stgq, 4294967296.0 / g.L);
+    timer_end(t, KC_RANK, s);
+}
+
+}  // namespace pasta

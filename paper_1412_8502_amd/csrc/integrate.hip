@@ -1,0 +1,150 @@
+// Velocity-Verlet integration in the expanding periodic box (Sec. II.A and
+// Eq. 3).  FP64 throughout.
+//
+// The drift kernel fuses, per particle (caller order): the first half kick
+// v += (dt/2M) F_n, the drift x += dt v, the optional affine scaling of the
+// variant, the wrap into [0, L_{n+1}), and the cell binning of the new
+// position with its integer atomic count (the first pass of the cell-list
+// build).  The second half kick is fused into the nuclear kernel's epilogue.
+//
+// The thermostat (every rescale_every steps) reduces the per-work-item
+// kinetic energies in fixed order in one workgroup and scales v by
+// sqrt(1.5 N T / KE).
+#include "internal.hpp"
+
+namespace pasta {
+
+namespace {
+
+__global__ __launch_bounds__(256) void k_drift(DriftArgs a, int nc, int C, double inv_w,
+                                               int32_t* __restrict__ key,
+                                               int32_t* __restrict__ count,
+                                               uint32_t* __restrict__ err)
+{
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= a.n)
+        return;
+    const double L = a.L_new;
+    int cc[3];
+    uint32_t bad = 0;
+#pragma unroll
+    for (int d = 0; d < 3; ++d) {
+        double v = a.vel[3 * i + d] + a.hdtm * a.force[3 * i + d];
+        double x = a.pos[3 * i + d] + a.dt * v;
+        if (a.scale_positions)
+            x *= a.ratio;
+        if (x < 0.0)
+            x += L;
+        if (x >= L)
+            x -= L;
+        if (!(x >= 0.0 && x < L)) {
+            bad |= isfinite(x) ? ERR_WRAP : ERR_NONFINITE_POS;
+            x = isfinite(x) ? x - L * floor(x / L) : 0.0;
+            if (!(x >= 0.0 && x < L))
+                x = 0.0;
+        }
+        if (!isfinite(v))
+            bad |= ERR_NONFINITE_VEL;
+        a.vel[3 * i + d] = v;
+        a.pos[3 * i + d] = x;
+        cc[d] = cell_coord(x, inv_w, nc);
+    }
+    if (bad)
+        atomicOr(err, bad);
+    const int bin = (a.species[i] == 1 ? 0 : C) + (cc[2] * nc + cc[1]) * nc + cc[0];
+    key[i] = bin;
+    atomicAdd(&count[bin], 1);
+}
+
+constexpr int RED = 1024;
+
+__global__ __launch_bounds__(RED) void k_thermostat_reduce(const double* __restrict__ ke_part,
+                                                           const int32_t* __restrict__ n_items,
+                                                           double target_ke,
+                                                           double* __restrict__ scale_out)
+{
+    __shared__ double lds[RED];
+    const int tid = threadIdx.x;
+    const int m = *n_items;
+    // each thread sums a contiguous run, then a fixed-shape tree: deterministic
+    const int per = (m + RED - 1) / RED;
+    double s = 0.0;
+    for (int k = tid * per; k < min(m, (tid + 1) * per); ++k)
+        s += ke_part[k];
+    lds[tid] = s;
+    __syncthreads();
+    for (int off = RED / 2; off > 0; off >>= 1) {
+        if (tid < off)
+            lds[tid] += lds[tid + off];
+        __syncthreads();
+    }
+    if (tid == 0) {
+        const double ke = lds[0];
+        scale_out[0] = ke > 0.0 ? sqrt(target_ke / ke) : 1.0;
+        scale_out[1] = ke;
+    }
+}
+
+__global__ __launch_bounds__(256) void k_scale(double* __restrict__ vel, int64_t m,
+                                               const double* __restrict__ scale)
+{
+    const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (k < m)
+        vel[k] *= scale[0];
+}
+
+__global__ __launch_bounds__(256) void k_partial(const double* __restrict__ x, int64_t n,
+                                                 int kind, double mass,
+                                                 double* __restrict__ out)
+{
+    __shared__ double lds[256];
+    const int tid = threadIdx.x;
+    double s = 0.0;
+    for (int64_t i = (int64_t)blockIdx.x * 256 + tid; i < n; i += (int64_t)gridDim.x * 256) {
+        if (kind == 0) {
+            s += x[i];
+        } else {
+            const double vx = x[3 * i], vy = x[3 * i + 1], vz = x[3 * i + 2];
+            s += 0.5 * mass * (vx * vx + vy * vy + vz * vz);
+        }
+    }
+    lds[tid] = s;
+    __syncthreads();
+    for (int off = 128; off > 0; off >>= 1) {
+        if (tid < off)
+            lds[tid] += lds[tid + off];
+        __syncthreads();
+    }
+    if (tid == 0)
+        out[blockIdx.x] = lds[0];
+}
+
+}  // namespace
+
+void launch_drift(const DriftArgs& a, const Grid& g, const CellBuf& cb, uint32_t* err,
+                  hipStream_t s, Timer* t)
+{
+    if (a.n <= 0)
+        return;
+    timer_begin(t, KC_DRIFT, s);
+    k_drift<<<(unsigned)((a.n + 255) / 256), 256, 0, s>>>(a, g.nc, g.C, g.inv_w, cb.key,
+                                                          cb.count, err);
+    timer_end(t, KC_DRIFT, s);
+}
+
+void launch_thermostat(double* vel, int64_t n, const double* ke_part, const int32_t* n_items,
+                       double target_ke, double* scale_out, hipStream_t s, Timer* t)
+{
+    timer_begin(t, KC_THERMO, s);
+    k_thermostat_reduce<<<1, RED, 0, s>>>(ke_part, n_items, target_ke, scale_out);
+    k_scale<<<(unsigned)((3 * n + 255) / 256), 256, 0, s>>>(vel, 3 * n, scale_out);
+    timer_end(t, KC_THERMO, s);
+}
+
+void launch_partial_sums(const double* x, int64_t n, int kind, double mass, double* out,
+                         int nblk, hipStream_t s)
+{
+    k_partial<<<nblk, 256, 0, s>>>(x, n, kind, mass, out);
+}
+
+}  // namespace pasta

@@ -1,0 +1,212 @@
+// Internal declarations shared by the libpasta translation units: device
+// helpers, the launch-parameter structs of every kernel, and the host-side
+// error and workspace utilities.  Nothing here is part of the C ABI.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+#include <cstddef>
+#include <cstdint>
+#include <string>
+
+#include "../../include/pasta.h"
+
+namespace pasta {
+
+// ------------------------------------------------------------------ errors
+void set_error(const char* fmt, ...);
+int fail(int code, const char* fmt, ...);
+#define PASTA_HIP(call)                                                              \
+    do {                                                                             \
+        hipError_t e_ = (call);                                                      \
+        if (e_ != hipSuccess)                                                        \
+            return ::pasta::fail(PASTA_EHIP, "%s failed: %s (%s:%d)", #call,         \
+                                 hipGetErrorString(e_), __FILE__, __LINE__);         \
+    } while (0)
+#define PASTA_TRY(expr)             \
+    do {                            \
+        int rc_ = (expr);           \
+        if (rc_ != PASTA_OK)        \
+            return rc_;             \
+    } while (0)
+
+// Device error word bits.
+enum : uint32_t {
+    ERR_NONFINITE_FORCE = 1u << 0,
+    ERR_NONFINITE_POS = 1u << 1,
+    ERR_WRAP = 1u << 2,       // a particle crossed more than one box length
+    ERR_UF_LIMIT = 1u << 3,   // union-find retry bound reached
+    ERR_NONFINITE_VEL = 1u << 4,
+    ERR_RANGE = 1u << 5,      // an input position outside [0, L)
+    ERR_SPECIES = 1u << 6,    // an input species other than 0 or 1
+};
+std::string describe_device_error(uint32_t bits);
+
+// ------------------------------------------------------------- workspace
+// Bump allocator over the caller's workspace; with base == nullptr it only
+// measures.  Every block is 256-byte aligned.
+struct Carver {
+    char* base;
+    size_t off = 0;
+    explicit Carver(void* b) : base(static_cast<char*>(b)) {}
+    template <class T>
+    T* take(size_t count)
+    {
+        off = (off + 255) & ~size_t(255);
+        T* p = base ? reinterpret_cast<T*>(base + off) : nullptr;
+        off += sizeof(T) * (count ? count : 1);
+        return p;
+    }
+    size_t size() const { return (off + 255) & ~size_t(255); }
+};
+
+// ------------------------------------------------------------- cell grid
+// ncell = the largest integer with L/ncell >= r_cut (at least 1).
+inline int cell_dims(double L, double r_cut)
+{
+    int nc = (int)std::floor(L / r_cut);
+    while (nc > 1 && L / (double)nc < r_cut)
+        nc--;
+    return nc < 1 ? 1 : nc;
+}
+
+struct Grid {
+    int nc;        // cells per side
+    int C;         // nc^3
+    double inv_w;  // nc / L  (cell coordinate = floor(x * inv_w))
+    double L;
+};
+inline Grid make_grid(double L, double r_cut)
+{
+    Grid g;
+    g.nc = cell_dims(L, r_cut);
+    g.C = g.nc * g.nc * g.nc;
+    g.inv_w = (double)g.nc / L;
+    g.L = L;
+    return g;
+}
+
+// Neighbour-cell offsets along one axis without duplicates: {-1,0,1} when
+// there are at least 3 cells per side, {0,1} for 2, {0} for 1.
+__host__ __device__ inline int axis_lo(int nc) { return nc >= 3 ? -1 : 0; }
+__host__ __device__ inline int axis_hi(int nc) { return nc >= 2 ? 1 : 0; }
+
+__device__ inline int cell_coord(double x, double inv_w, int nc)
+{
+    int k = (int)(x * inv_w);
+    k = k > nc - 1 ? nc - 1 : k;
+    return k < 0 ? 0 : k;
+}
+
+// ------------------------------------------------------ staging formats
+// FP64 staging: x, y, z in fm, w unused.
+// MIXED staging: x, y, z as 32-bit fixed point (x/L * 2^32), w = species.
+struct alignas(16) Q4 {
+    uint32_t x, y, z, w;
+};
+
+// ------------------------------------------------- kernel classes (timing)
+enum KernelClass : int {
+    KC_DRIFT = 0,
+    KC_SCAN = 1,
+    KC_SCATTER = 2,
+    KC_RANK = 3,
+    KC_COULOMB = 4,
+    KC_NUCLEAR = 5,
+    KC_THERMO = 6,
+    KC_OTHER = 7,
+};
+
+// Launch timing hook: when non-null, brackets a launch with HIP events.
+struct Timer;
+void timer_begin(Timer* t, int kc, hipStream_t s);
+void timer_end(Timer* t, int kc, hipStream_t s);
+
+// -------------------------------------------------------- cell-list build
+struct CellBuf {
+    int32_t* key;     // [n] bin of each particle (caller order)
+    int32_t* count;   // [2C_max] per-bin counts (zero between builds)
+    int32_t* fill;    // [2C_max] per-bin scatter cursors (zero between builds)
+    int32_t* start;   // [2C_max + 1]
+    int32_t* tmp;     // [n] unsorted slots
+    int32_t* perm;    // [n] slot -> particle index
+    int32_t* items;   // [2 * item_max] nuclear work items (cell, chunk)
+    int32_t* n_items; // [1]
+    int64_t item_max;
+};
+size_t cellbuf_carve(Carver& cv, CellBuf* out, int64_t n, int C_max, int chunk);
+void cellbuf_zero(const CellBuf& cb, int C_max, hipStream_t s);
+
+// Bins + counts from positions (caller order); the drift kernel does the
+// same inside the integrator.
+void launch_bin_count(const double* pos, const uint8_t* species, int64_t n, const Grid& g,
+                      const CellBuf& cb, uint32_t* err, hipStream_t s, Timer* t);
+// Exclusive scan of the 2C counts into start[]; zeroes count and fill; when
+// chunk > 0, also writes the nuclear work list.
+void launch_scan(const CellBuf& cb, int C, int chunk, hipStream_t s, Timer* t);
+// Stable scatter: slot order = (bin, particle index).  Writes perm and, when
+// staging pointers are given, the sorted staging coordinates.
+void launch_scatter_rank(const double* pos, const uint8_t* species, int64_t n, const Grid& g,
+                         const CellBuf& cb, double4* stg64, Q4* stgq, hipStream_t s, Timer* t);
+
+// ----------------------------------------------------------------- forces
+struct PairParams {
+    // nuclear (Eq. 1a,b)
+    double a, b_like, b_unlike, Lambda, r_nuc;
+    // Coulomb (Eq. 1c)
+    double alpha_hbarc, lambda_s;
+    double L;
+};
+struct KickArgs {
+    double* vel;       // [n][3] or nullptr (no kick)
+    double hdtm;       // dt / (2 M)
+    double mass;
+    double* ke_part;   // [item_max] per-work-item kinetic energy, or nullptr
+};
+struct ForceBuf {
+    double4* stg64;     // [n] FP64 staging (sorted)
+    Q4* stgq;           // [n] fixed-point staging (sorted)
+    double4* coul_part; // [coul_max] partial Coulomb sums (fx, fy, fz, V)
+    int64_t coul_max;
+    double* ke_part;    // [item_max]
+    uint64_t* pairs;    // [2] diagnostic pair counters
+};
+int coulomb_splits(int64_t Z);
+size_t forcebuf_carve(Carver& cv, ForceBuf* out, int64_t n, int64_t item_max, int precision);
+
+// Coulomb all-pairs over protons (sorted slots [0, Z)).
+void launch_coulomb(int precision, const ForceBuf& fb, int64_t Z, const PairParams& pp,
+                    uint64_t* pair_counter, hipStream_t s, Timer* t);
+// Nuclear cell-tile kernel; adds the coul_S Coulomb partials of proton
+// targets (coul_S = 0: none),
+// writes F and E in caller order, optionally applies the second half kick.
+void launch_nuclear(int precision, const ForceBuf& fb, const CellBuf& cb, const Grid& g,
+                    int64_t n, int64_t Z, const PairParams& pp, bool with_nuclear_terms,
+                    int coul_S, double* force, double* epot, const KickArgs& kick,
+                    uint64_t* pair_counter, uint32_t* err, hipStream_t s, Timer* t);
+int nuclear_chunk(int precision);
+
+// ------------------------------------------------------------- integrate
+struct DriftArgs {
+    double* pos;
+    double* vel;
+    const double* force;
+    const uint8_t* species;
+    int64_t n;
+    double hdtm, dt;
+    double L_new, ratio;  // ratio = L_new / L_old (affine variant only)
+    int scale_positions;
+};
+void launch_drift(const DriftArgs& a, const Grid& g, const CellBuf& cb, uint32_t* err,
+                  hipStream_t s, Timer* t);
+// Thermostat: reduce ke_part[0 .. *n_items) and scale velocities to
+// KE = 1.5 N T.  scale_out receives the factor.
+void launch_thermostat(double* vel, int64_t n, const double* ke_part, const int32_t* n_items,
+                       double target_ke, double* scale_out, hipStream_t s, Timer* t);
+// Deterministic partial sums: out[b] for b < nblk over x[i] (kind 0) or over
+// (1/2) M |v_i|^2 (kind 1).
+void launch_partial_sums(const double* x, int64_t n, int kind, double mass, double* out,
+                         int nblk, hipStream_t s);
+
+}  // namespace pasta

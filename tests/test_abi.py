@@ -1,0 +1,96 @@
+"""Host-side checks of the C ABI (no GPU needed): the library loads, exports
+every function include/pasta.h declares, and rejects bad arguments before
+touching the device."""
+import ctypes
+
+import pytest
+
+
+@pytest.fixture(scope="module")
+def B():
+    import os
+    from paper_1412_8502_amd import build
+    if not os.path.exists(build.LIB):
+        build.build()
+    from paper_1412_8502_amd import binding
+    return binding
+
+
+def test_exports_every_declared_function(B):
+    names = B.header_functions()
+    assert len(names) >= 20
+    missing = [f for f in names if not hasattr(B.lib, f)]
+    assert missing == []
+
+
+def test_paper_potential(B):
+    p = B.pasta_potential_paper()
+    assert (p.a, p.b, p.c, p.Lambda, p.lambda_s, p.mass, p.r_nuc) == \
+        (110.0, -26.0, 24.0, 1.25, 10.0, 939.0, 11.5)
+    assert abs(p.alpha_hbarc - 1.4399645) < 1e-7
+    assert "gfx950" in B.pasta_version()
+
+
+def test_workspace_queries(B):
+    p = B.pasta_potential_paper()
+    nb = ctypes.c_size_t()
+    for prec in (B.PASTA_FP64, B.PASTA_MIXED):
+        assert B.lib.pasta_forces_workspace(ctypes.byref(p), prec, 51200, 86.18,
+                                            ctypes.byref(nb)) == 0
+        assert nb.value > 51200 * 16 and nb.value % 256 == 0
+    g = B.pasta_integrator(2.0, 7.5e-5, 0.5, 100, 0)
+    small, big = ctypes.c_size_t(), ctypes.c_size_t()
+    assert B.lib.pasta_sim_workspace(ctypes.byref(p), ctypes.byref(g), 1, 51200, 86.18,
+                                     ctypes.byref(small)) == 0
+    assert B.lib.pasta_sim_workspace(ctypes.byref(p), ctypes.byref(g), 1, 51200, 344.71,
+                                     ctypes.byref(big)) == 0
+    assert big.value > small.value  # the cell grid grows with L_max
+    assert B.lib.pasta_cluster_workspace(3200, 43.09, 4.5, 3.0, ctypes.byref(nb)) == 0
+    assert B.lib.pasta_cell_list_workspace(3200, 43.09, 11.5, ctypes.byref(nb)) == 0
+
+
+def test_argument_errors(B):
+    p = B.pasta_potential_paper()
+    fake = ctypes.c_void_p(256 * 1024)  # never dereferenced: the calls fail first
+    # negative n
+    assert B.lib.pasta_forces(ctypes.byref(p), 0, 3, -1, 86.0, fake, fake, fake, None, fake,
+                              1 << 30, None) == -1
+    # bad precision / terms
+    assert B.lib.pasta_forces(ctypes.byref(p), 7, 3, 10, 86.0, fake, fake, fake, None, fake,
+                              1 << 30, None) == -1
+    assert B.lib.pasta_forces(ctypes.byref(p), 0, 8, 10, 86.0, fake, fake, fake, None, fake,
+                              1 << 30, None) == -1
+    # box below twice the cutoff: nearest image ambiguous
+    assert B.lib.pasta_forces(ctypes.byref(p), 0, 3, 10, 22.9, fake, fake, fake, None, fake,
+                              1 << 30, None) == -2
+    assert "2 r_nuc" in B.lib.pasta_last_error().decode()
+    # workspace too small / misaligned
+    assert B.lib.pasta_forces(ctypes.byref(p), 0, 3, 10, 30.0, fake, fake, fake, None, fake,
+                              16, None) == -3
+    assert B.lib.pasta_forces(ctypes.byref(p), 0, 3, 10, 30.0, fake, fake, fake, None,
+                              ctypes.c_void_p(256 * 1024 + 8), 1 << 30, None) == -3
+    # non-finite potential parameter
+    bad = B.pasta_potential_paper()
+    bad.Lambda = float("nan")
+    assert B.lib.pasta_forces(ctypes.byref(bad), 0, 3, 10, 30.0, fake, fake, fake, None, fake,
+                              1 << 30, None) == -1
+    # null handles
+    assert B.lib.pasta_sim_step(None, 1) == -1
+    assert B.lib.pasta_sim_energies(None, None, None, None, None) == -1
+    # cluster: box too small
+    K = ctypes.c_int32()
+    assert B.lib.pasta_cluster(10, 8.0, fake, fake, 4.5, 3.0, fake, fake, fake,
+                               ctypes.byref(K), None, fake, 1 << 30, None) == -2
+    # bad integrator
+    g = B.pasta_integrator(-1.0, 0.0, 1.0, 0, 0)
+    nb = ctypes.c_size_t()
+    assert B.lib.pasta_sim_workspace(ctypes.byref(p), ctypes.byref(g), 0, 10, 30.0,
+                                     ctypes.byref(nb)) == -1
+
+
+def test_python_binding_rejects_cpu_tensors(B):
+    import torch
+    pos = torch.zeros((4, 3), dtype=torch.float64)
+    sp = torch.zeros(4, dtype=torch.uint8)
+    with pytest.raises(ValueError):
+        B.pasta_forces(pos, sp, 30.0)
