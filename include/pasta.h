@@ -200,6 +200,43 @@ int pasta_cluster(int64_t n, double L, const double* d_pos, const uint8_t* d_spe
                   int32_t* d_hist_Z, int32_t* h_nclusters, int32_t* h_nfree, void* d_work,
                   size_t work_bytes, void* stream);
 
+/* ------------------------------------------------------------------ a6 --
+ * Batched systems: nsys independent boxes (the paper's grid of runs over Y_P
+ * and T, Sec. III.B), each with its own n, L0 and integrator, advanced
+ * together.  Particle arrays are the concatenation of the systems' arrays
+ * (system s occupies rows [sum_{k<s} n_k, ... + n_s)); each system follows
+ * exactly the pasta_sim_step definition above.  Z per system is counted from
+ * d_species at creation.
+ * mode 0: one persistent kernel launch per step whose phases are separated by
+ *         device-wide barriers (the grid is sized to be resident; a barrier
+ *         wait is bounded and reports PASTA_EDEVICE instead of hanging);
+ * mode 1: the same phases as one kernel launch each.
+ * Steps are captured once into a hipGraph of steps_per_graph steps and
+ * replayed; the batch works on an internal stream joined to `stream` by
+ * events.  d_pos and d_vel hold the state of every system after each
+ * pasta_batch_step call (stream-ordered).  h_L_max[s] bounds system s's box. */
+typedef struct pasta_batch pasta_batch;
+int pasta_batch_workspace(const pasta_potential* pot, int32_t precision, int32_t nsys,
+                          const int64_t* h_n, const double* h_L_max, size_t* h_bytes);
+int pasta_batch_create(const pasta_potential* pot, int32_t precision, int32_t nsys,
+                       const int64_t* h_n, const double* h_L0, const pasta_integrator* h_integ,
+                       int64_t step0, const double* h_L_max, double* d_pos, double* d_vel,
+                       const uint8_t* d_species, void* d_work, size_t work_bytes, int32_t mode,
+                       int32_t steps_per_graph, void* stream, pasta_batch** out);
+int pasta_batch_step(pasta_batch* b, int64_t nsteps);
+/* Synchronises; per-system kinetic and potential energies and box sides
+ * (arrays of nsys; any may be NULL) and the global step index. */
+int pasta_batch_energies(pasta_batch* b, double* h_ekin, double* h_epot, double* h_L,
+                         int64_t* h_step);
+/* Copies forces ([sum n][3]) and energy shares ([sum n]) of the current state. */
+int pasta_batch_forces(pasta_batch* b, double* d_force, double* d_epot);
+/* Synchronises; per-system unordered nuclear pairs inside r_nuc and Coulomb
+ * pairs at the current state. */
+int pasta_batch_pair_counts(pasta_batch* b, int64_t* h_nuclear, int64_t* h_coulomb);
+/* Grid size of the persistent (or per-phase) launches and the mode. */
+int pasta_batch_info(pasta_batch* b, int32_t* h_grid, int32_t* h_mode);
+void pasta_batch_destroy(pasta_batch* b);
+
 #ifdef __cplusplus
 }
 #endif

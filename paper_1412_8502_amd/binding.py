@@ -77,6 +77,15 @@ def _load():
         "pasta_kernel_class_name": (ctypes.c_char_p, [i32]),
         "pasta_sim_destroy": (None, [vp]),
         "pasta_cluster_workspace": (ctypes.c_int, [i64, d, d, d, P(sz)]),
+        "pasta_batch_workspace": (ctypes.c_int, [pot, i32, i32, vp, vp, P(sz)]),
+        "pasta_batch_create": (ctypes.c_int, [pot, i32, i32, vp, vp, vp, i64, vp, vp, vp, vp,
+                                              vp, sz, i32, i32, vp, P(vp)]),
+        "pasta_batch_step": (ctypes.c_int, [vp, i64]),
+        "pasta_batch_energies": (ctypes.c_int, [vp, vp, vp, vp, P(i64)]),
+        "pasta_batch_forces": (ctypes.c_int, [vp, vp, vp]),
+        "pasta_batch_pair_counts": (ctypes.c_int, [vp, vp, vp]),
+        "pasta_batch_info": (ctypes.c_int, [vp, P(i32), P(i32)]),
+        "pasta_batch_destroy": (None, [vp]),
         "pasta_cluster": (ctypes.c_int, [i64, d, vp, vp, d, d, vp, vp, vp, P(i32), P(i32), vp,
                                          sz, vp]),
     }
@@ -282,3 +291,82 @@ def pasta_cluster(pos, species, L: float, r_pp: float = 4.5, r_np: float = 3.0, 
                              ctypes.byref(K), ctypes.byref(nf), _p(work), work.numel(),
                              _stream(stream)))
     return dict(label=label, nclusters=K.value, hist_A=hA, hist_Z=hZ, nfree=nf.value)
+
+
+# ------------------------------------------------------------------- a6
+class Batch:
+    """Owner of a pasta_batch handle: nsys systems concatenated in `pos`,
+    `vel`, `species` (system s in rows [off_s, off_s + n_s)), advanced
+    together by one persistent launch per step (mode 0) or one launch per
+    phase (mode 1), replayed from a captured hipGraph."""
+
+    def __init__(self, pos, vel, species, ns, L0s, integs, precision=PASTA_MIXED, mode=0,
+                 steps_per_graph=10, step0=0, L_max=None, pot=None, stream=None):
+        _check_state(pos, species)
+        if vel.shape != pos.shape or vel.dtype != torch.float64 or not vel.is_contiguous():
+            raise ValueError("vel must be a contiguous float64 tensor shaped like pos")
+        self.nsys = len(ns)
+        if sum(ns) != pos.shape[0]:
+            raise ValueError("sum of system sizes != number of particles")
+        self.pos, self.vel, self.species = pos, vel, species
+        self.pot = pot or pasta_potential_paper()
+        self.ns = (ctypes.c_int64 * self.nsys)(*ns)
+        self.L0 = (ctypes.c_double * self.nsys)(*L0s)
+        self.Lmax = (ctypes.c_double * self.nsys)(*(L_max or L0s))
+        self.integ = (pasta_integrator * self.nsys)(*[
+            pasta_integrator(g.get("dt", 2.0), g.get("xi_dot", 0.0), g.get("T", 1.0),
+                             g.get("rescale_every", 0), int(bool(g.get("scale_positions", 0))))
+            for g in integs])
+        nb = ctypes.c_size_t()
+        _check(lib.pasta_batch_workspace(ctypes.byref(self.pot), precision, self.nsys,
+                                         self.ns, self.Lmax, ctypes.byref(nb)))
+        self.work = _workspace(nb.value, pos.device)
+        self.handle = ctypes.c_void_p()
+        _check(lib.pasta_batch_create(ctypes.byref(self.pot), precision, self.nsys, self.ns,
+                                      self.L0, self.integ, step0, self.Lmax, _p(pos), _p(vel),
+                                      _p(species), _p(self.work), self.work.numel(), mode,
+                                      steps_per_graph, _stream(stream),
+                                      ctypes.byref(self.handle)))
+
+    def step(self, nsteps: int = 1):
+        _check(lib.pasta_batch_step(self.handle, nsteps))
+
+    def energies(self):
+        n = self.nsys
+        ek, ep, L = (ctypes.c_double * n)(), (ctypes.c_double * n)(), (ctypes.c_double * n)()
+        st = ctypes.c_int64()
+        _check(lib.pasta_batch_energies(self.handle, ek, ep, L, ctypes.byref(st)))
+        return dict(ekin=list(ek), epot=list(ep), L=list(L), step=st.value)
+
+    def forces(self):
+        N = self.pos.shape[0]
+        f = torch.empty((N, 3), dtype=torch.float64, device=self.pos.device)
+        e = torch.empty(N, dtype=torch.float64, device=self.pos.device)
+        _check(lib.pasta_batch_forces(self.handle, _p(f), _p(e)))
+        return f, e
+
+    def pair_counts(self):
+        n = self.nsys
+        a, b = (ctypes.c_int64 * n)(), (ctypes.c_int64 * n)()
+        _check(lib.pasta_batch_pair_counts(self.handle, a, b))
+        return list(a), list(b)
+
+    def info(self):
+        g, m = ctypes.c_int32(), ctypes.c_int32()
+        _check(lib.pasta_batch_info(self.handle, ctypes.byref(g), ctypes.byref(m)))
+        return dict(grid=g.value, mode=m.value)
+
+    def close(self):
+        if self.handle:
+            lib.pasta_batch_destroy(self.handle)
+            self.handle = ctypes.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def pasta_batch_create(*args, **kw) -> Batch:
+    return Batch(*args, **kw)

@@ -15,7 +15,7 @@ CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libpasta.so")
 ARCH = "gfx950"
 
-SOURCES = ["api.hip", "cells.hip", "forces.hip", "integrate.hip", "cluster.hip"]
+SOURCES = ["api.hip", "cells.hip", "forces.hip", "integrate.hip", "cluster.hip", "batch.hip"]
 # Per-file extra flags: the cluster distances must not be contracted into FMA.
 EXTRA = {"cluster.hip": ["-ffp-contract=off"]}
 

@@ -507,7 +507,7 @@ extern "C" int pasta_sim_step(pasta_sim* sim, int64_t nsteps)
         launch_drift(da, g, sim->w.cb, sim->w.err, s, &sim->timer);
         launch_scan(sim->w.cb, g.C, nuclear_chunk(sim->precision), s, &sim->timer);
         launch_scatter_rank(sim->pos, sim->species, sim->n, g, sim->w.cb, sim->w.fb.stg64,
-                            sim->w.fb.stgq, s, &sim->timer);
+                            sim->w.fb.stgq, s, &sim->timer, true);
         const bool thermo = gi.rescale_every > 0 && (n0 + 1) % gi.rescale_every == 0;
         KickArgs kick{sim->vel, hdtm, sim->pot.mass, thermo ? sim->w.fb.ke_part : nullptr};
         eval_forces(sim->precision, PASTA_TERM_ALL, sim->w, g, sim->n, sim->Z,

@@ -1,0 +1,1123 @@
+// Batched systems: several independent boxes (the paper's grid of runs over
+// proton fraction and temperature, Sec. III.B) advanced together, one
+// velocity-Verlet step per launch of a persistent kernel whose phases are
+// separated by device-wide barriers, replayed from a captured hipGraph.
+//
+// Phases of one step (every system at once):
+//   P1 drift      first half kick, drift, wrap, box growth from the device step
+//                 counter, cell binning with wave-aggregated counts
+//   P2 scan       one workgroup per system: bin starts, nuclear work list
+//   P3 scatter    bin cursors, visiting particles in the previous cell order
+//   P4 rank       stable order (bin, index) and fixed-point staging
+//   P5 forces     one dynamic work queue holding every system's Coulomb tiles
+//                 and nuclear cell tiles (uneven systems balance on it)
+//   P6 combine    nuclear + Coulomb partials, second half kick, kinetic energy
+//   P7 thermostat one workgroup per system on rescale steps
+// The same phase functions also run as one kernel per phase ("multi-kernel"
+// form) for comparison.  Barrier waits are bounded: a grid that is not fully
+// resident sets an error bit and every workgroup leaves.
+#include "pair_items.hpp"
+
+namespace pasta {
+
+namespace {
+
+constexpr int BW = WG;  // threads per workgroup in every phase
+constexpr uint32_t ERR_BARRIER = 1u << 7;
+constexpr long BARRIER_SPIN_LIMIT = 1L << 22;
+
+struct SysDev {
+    int64_t off;          // first particle of the system in the concatenated arrays
+    int32_t n, Z;
+    double L0, xi_dot, dt, T, hdtm;
+    int32_t rescale_every, scale_positions;
+    int64_t bin_off;      // count/fill: 2*C_max entries
+    int64_t start_off;    // start: 2*C_max + 1 entries
+    int64_t item_off;     // nuclear items: item_max pairs
+    int32_t item_max;
+    int64_t coul_off;     // Coulomb partials: S*Z entries
+    int32_t S, per_split, coul_blocks;
+    int64_t chunk_off;    // particle chunks of BW
+    int32_t nchunks;
+    int64_t coul_item_off;
+    int64_t nuc_item_off;
+};
+
+struct BatchDev {
+    const SysDev* sys;
+    int nsys;
+    int64_t total_chunks, coul_items, nuc_items;
+    PairParams pp;        // L filled per system per step
+    double mass;
+    // concatenated particle arrays (caller order within each system)
+    double* pos;
+    double* vel;
+    const uint8_t* species;
+    double* force;
+    double* epot;
+    // work arrays
+    int32_t* key;
+    int32_t* tmp;
+    int32_t* perm;
+    int32_t* count;
+    int32_t* fill;
+    int32_t* start;
+    int32_t* items;
+    int32_t* n_items;
+    void* stg;            // Q4 or double4 per sorted slot
+    double4* coul_part;
+    double4* fnuc;
+    double* ke_chunk;
+    double* pending;      // per-system velocity scale pending from the thermostat
+    int64_t* step;
+    unsigned* barrier;    // [0] arrivals, [1] generation
+    unsigned* queue;      // [0] force-phase work counter
+    uint32_t* err;
+    unsigned long long* pairs;  // [nsys] diagnostic nuclear pair counts
+    double* red;          // [256] host-read reduction partials
+};
+
+__device__ __forceinline__ int find_sys_chunk(const BatchDev& B, int64_t g)
+{
+    int lo = 0, hi = B.nsys;
+    while (hi - lo > 1) {
+        const int mid = (lo + hi) >> 1;
+        if (B.sys[mid].chunk_off <= g)
+            lo = mid;
+        else
+            hi = mid;
+    }
+    return lo;
+}
+
+__device__ __forceinline__ double box_at(const SysDev& S, int64_t step)
+{
+    return S.L0 * (1.0 + S.xi_dot * ((double)step * S.dt));
+}
+
+__device__ __forceinline__ Grid grid_at(double L, double r_cut)
+{
+    Grid g;
+    int nc = (int)floor(L / r_cut);
+    while (nc > 1 && L / (double)nc < r_cut)
+        nc--;
+    g.nc = nc < 1 ? 1 : nc;
+    g.C = g.nc * g.nc * g.nc;
+    g.inv_w = (double)g.nc / L;
+    g.L = L;
+    return g;
+}
+
+// Bounded grid-wide barrier.  Returns false (and every later barrier returns
+// false at once) when the wait limit is hit.
+__device__ bool grid_sync(const BatchDev& B, int* s_flag)
+{
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        int ok = 1;
+        if (__hip_atomic_load(B.err, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) & ERR_BARRIER) {
+            ok = 0;
+        } else {
+            const unsigned nb = gridDim.x;
+            const unsigned gen =
+                __hip_atomic_load(&B.barrier[1], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
+            const unsigned arrived = __hip_atomic_fetch_add(&B.barrier[0], 1u, __ATOMIC_ACQ_REL,
+                                                            __HIP_MEMORY_SCOPE_AGENT) + 1u;
+            if (arrived == nb) {
+                __hip_atomic_store(&B.barrier[0], 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                __hip_atomic_store(&B.barrier[1], gen + 1u, __ATOMIC_RELEASE,
+                                   __HIP_MEMORY_SCOPE_AGENT);
+            } else {
+                long spins = 0;
+                while (__hip_atomic_load(&B.barrier[1], __ATOMIC_ACQUIRE,
+                                         __HIP_MEMORY_SCOPE_AGENT) == gen) {
+                    __builtin_amdgcn_s_sleep(2);
+                    if (++spins > BARRIER_SPIN_LIMIT) {
+                        atomicOr(B.err, ERR_BARRIER);
+                        ok = 0;
+                        break;
+                    }
+                    if ((spins & 1023) == 0 &&
+                        (__hip_atomic_load(B.err, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) &
+                         ERR_BARRIER)) {
+                        ok = 0;
+                        break;
+                    }
+                }
+            }
+            __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+        }
+        *s_flag = ok;
+    }
+    __syncthreads();
+    return *s_flag != 0;
+}
+
+// ------------------------------------------------------------- phases
+// mode: 0 = initial evaluation (bin the given positions, no kick),
+//       1 = a full step.
+__device__ void phase_drift(const BatchDev& B, int64_t step, int mode)
+{
+    if (blockIdx.x == 0 && threadIdx.x == 0)
+        B.queue[0] = 0u;  // work counter of this step's force phase
+    for (int64_t g = blockIdx.x; g < B.total_chunks; g += gridDim.x) {
+        const int s = find_sys_chunk(B, g);
+        const SysDev& S = B.sys[s];
+        const int64_t sl = (g - S.chunk_off) * BW + threadIdx.x;
+        if (sl >= S.n)
+            continue;
+        const double L_old = box_at(S, step);
+        const double L_new = mode ? box_at(S, step + 1) : L_old;
+        const Grid gr = grid_at(L_new, B.pp.r_nuc);
+        const int64_t i = S.off + (mode ? B.perm[S.off + sl] : sl);
+        double* x = B.pos + 3 * i;
+        double* v = B.vel + 3 * i;
+        int cc[3];
+        if (mode) {
+            const double sc = B.pending[s];
+            const double ratio = L_new / L_old;
+            uint32_t bad = 0;
+#pragma unroll
+            for (int d = 0; d < 3; ++d) {
+                double vv = v[d] * sc + S.hdtm * B.force[3 * i + d];
+                double xx = x[d] + S.dt * vv;
+                if (S.scale_positions)
+                    xx *= ratio;
+                if (xx < 0.0)
+                    xx += L_new;
+                if (xx >= L_new)
+                    xx -= L_new;
+                if (!(xx >= 0.0 && xx < L_new)) {
+                    bad |= isfinite(xx) ? ERR_WRAP : ERR_NONFINITE_POS;
+                    xx = 0.0;
+                }
+                v[d] = vv;
+                x[d] = xx;
+                cc[d] = cell_coord(xx, gr.inv_w, gr.nc);
+            }
+            if (bad)
+                atomicOr(B.err, bad);
+        } else {
+#pragma unroll
+            for (int d = 0; d < 3; ++d) {
+                const double xx = x[d];
+                if (!(xx >= 0.0 && xx < L_new))
+                    atomicOr(B.err, ERR_RANGE);
+                cc[d] = cell_coord(xx, gr.inv_w, gr.nc);
+            }
+        }
+        const int bin = (B.species[i] == 1 ? 0 : gr.C) + (cc[2] * gr.nc + cc[1]) * gr.nc + cc[0];
+        B.key[i] = bin;
+        wave_aggregated_add(B.count + S.bin_off, bin);
+    }
+}
+
+__device__ int64_t block_exscan(const int32_t* v, int32_t* out, int64_t m, int64_t* lds)
+{
+    const int tid = threadIdx.x;
+    const int64_t per = (m + BW - 1) / BW;
+    const int64_t b = tid * per, e = b + per < m ? b + per : m;
+    int64_t s = 0;
+    for (int64_t k = b; k < e; ++k)
+        s += v[k];
+    lds[tid] = s;
+    __syncthreads();
+    for (int off = 1; off < BW; off <<= 1) {
+        const int64_t t = tid >= off ? lds[tid - off] : 0;
+        __syncthreads();
+        lds[tid] += t;
+        __syncthreads();
+    }
+    int64_t run = lds[tid] - s;
+    const int64_t total = lds[BW - 1];
+    for (int64_t k = b; k < e; ++k) {
+        const int32_t c = v[k];
+        out[k] = (int32_t)run;
+        run += c;
+    }
+    __syncthreads();
+    return total;
+}
+
+__device__ void phase_scan(const BatchDev& B, int64_t step, int mode, char* lds_raw)
+{
+    int64_t* lds = reinterpret_cast<int64_t*>(lds_raw);
+    for (int s = blockIdx.x; s < B.nsys; s += gridDim.x) {
+        const SysDev& S = B.sys[s];
+        const double L = box_at(S, mode ? step + 1 : step);
+        const Grid gr = grid_at(L, B.pp.r_nuc);
+        int32_t* count = B.count + S.bin_off;
+        int32_t* fill = B.fill + S.bin_off;
+        int32_t* start = B.start + S.start_off;
+        const int64_t nb = 2 * (int64_t)gr.C;
+        const int64_t total = block_exscan(count, start, nb, lds);
+        if (threadIdx.x == 0)
+            start[nb] = (int32_t)total;
+        __syncthreads();
+        // nuclear work list: ceil(members / NUC_CHUNK) items per cell; fill
+        // doubles as scratch for the per-cell item counts
+        for (int64_t c = threadIdx.x; c < gr.C; c += BW) {
+            const int32_t m = count[c] + count[gr.C + c];
+            fill[c] = (m + NUC_CHUNK - 1) / NUC_CHUNK;
+        }
+        __syncthreads();
+        const int64_t nit = block_exscan(fill, fill + gr.C, gr.C, lds);
+        int32_t* items = B.items + 2 * S.item_off;
+        for (int64_t c = threadIdx.x; c < gr.C; c += BW) {
+            const int32_t base = fill[gr.C + c], k = fill[c];
+            for (int32_t q = 0; q < k; ++q) {
+                items[2 * (base + q) + 0] = (int32_t)c;
+                items[2 * (base + q) + 1] = q;
+            }
+        }
+        if (threadIdx.x == 0)
+            B.n_items[s] = (int32_t)nit;
+        __syncthreads();
+        for (int64_t k = threadIdx.x; k < nb; k += BW) {
+            count[k] = 0;
+            fill[k] = 0;
+        }
+        __syncthreads();
+    }
+}
+
+__device__ void phase_scatter(const BatchDev& B, int mode)
+{
+    for (int64_t g = blockIdx.x; g < B.total_chunks; g += gridDim.x) {
+        const int s = find_sys_chunk(B, g);
+        const SysDev& S = B.sys[s];
+        const int64_t sl = (g - S.chunk_off) * BW + threadIdx.x;
+        if (sl >= S.n)
+            continue;
+        const int32_t il = mode ? B.perm[S.off + sl] : (int32_t)sl;
+        const int b = B.key[S.off + il];
+        const int slot = B.start[S.start_off + b] + wave_aggregated_add(B.fill + S.bin_off, b);
+        B.tmp[S.off + slot] = il;
+    }
+}
+
+template <class P>
+__device__ void phase_rank(const BatchDev& B, int64_t step, int mode)
+{
+    auto* stg = reinterpret_cast<typename P::Src*>(B.stg);
+    for (int64_t g = blockIdx.x; g < B.total_chunks; g += gridDim.x) {
+        const int s = find_sys_chunk(B, g);
+        const SysDev& S = B.sys[s];
+        const int64_t sl = (g - S.chunk_off) * BW + threadIdx.x;
+        if (sl >= S.n)
+            continue;
+        const int32_t* tmp = B.tmp + S.off;
+        const int32_t id = tmp[sl];
+        const int b = B.key[S.off + id];
+        const int beg = B.start[S.start_off + b], end = B.start[S.start_off + b + 1];
+        int r = 0, k = beg;
+        for (; k + 8 <= end; k += 8) {
+            int32_t v[8];
+#pragma unroll
+            for (int u = 0; u < 8; ++u)
+                v[u] = tmp[k + u];
+#pragma unroll
+            for (int u = 0; u < 8; ++u)
+                r += v[u] < id;
+        }
+        for (; k < end; ++k)
+            r += tmp[k] < id;
+        const int dst = beg + r;
+        B.perm[S.off + dst] = id;
+        const int64_t i = S.off + id;
+        const double x = B.pos[3 * i], y = B.pos[3 * i + 1], z = B.pos[3 * i + 2];
+        if constexpr (sizeof(typename P::Src) == sizeof(Q4)) {
+            const double L = box_at(S, mode ? step + 1 : step);
+            const double qs = 4294967296.0 / L;
+            Q4 q;
+            q.x = (uint32_t)(uint64_t)(x * qs);
+            q.y = (uint32_t)(uint64_t)(y * qs);
+            q.z = (uint32_t)(uint64_t)(z * qs);
+            q.w = B.species[i];
+            reinterpret_cast<Q4*>(stg)[S.off + dst] = q;
+        } else {
+            reinterpret_cast<double4*>(stg)[S.off + dst] = make_double4(x, y, z, (double)B.species[i]);
+        }
+    }
+}
+
+template <class P, bool COUNT>
+__device__ void phase_forces(const BatchDev& B, int64_t step, int mode, char* lds, int* s_item)
+{
+    const auto* stg = reinterpret_cast<const typename P::Src*>(B.stg);
+    const int64_t total = B.coul_items + B.nuc_items;
+    unsigned* ctr = B.queue;
+    while (true) {
+        if (threadIdx.x == 0)
+            *s_item = (int)atomicAdd(ctr, 1u);
+        __syncthreads();
+        const int64_t it = *s_item;
+        __syncthreads();
+        if (it >= total)
+            break;
+        if (it < B.coul_items) {
+            if (COUNT)
+                continue;
+            int s = 0;
+            while (s + 1 < B.nsys && B.sys[s + 1].coul_item_off <= it)
+                ++s;
+            const SysDev& S = B.sys[s];
+            const int64_t local = it - S.coul_item_off;
+            const int tblock = (int)(local % S.coul_blocks), split = (int)(local / S.coul_blocks);
+            PairParams pp = B.pp;
+            pp.L = box_at(S, mode ? step + 1 : step);
+            const CoulConsts k = make_coul_consts(pp);
+            coulomb_item<P>(stg + S.off, S.Z, S.per_split, k, B.coul_part + S.coul_off, tblock,
+                            split, lds);
+        } else {
+            const int64_t jt = it - B.coul_items;
+            int s = 0;
+            while (s + 1 < B.nsys && B.sys[s + 1].nuc_item_off <= jt)
+                ++s;
+            const SysDev& S = B.sys[s];
+            const int local = (int)(jt - S.nuc_item_off);
+            if (local >= B.n_items[s])
+                continue;
+            PairParams pp = B.pp;
+            pp.L = box_at(S, mode ? step + 1 : step);
+            const Grid gr = grid_at(pp.L, pp.r_nuc);
+            const NucConsts k = make_nuc_consts(pp);
+            NucArgs A{};
+            A.start = B.start + S.start_off;
+            A.items = B.items + 2 * S.item_off;
+            A.perm = B.perm + S.off;
+            A.nc = gr.nc;
+            A.C = gr.C;
+            A.Z = S.Z;
+            A.fnuc = B.fnuc + S.off;  // raw nuclear part; combine adds the rest
+            A.pairs = B.pairs + s;
+            A.err = B.err;
+            nuclear_item<P, true, COUNT>(stg + S.off, A, k, local, lds);
+        }
+    }
+}
+
+__device__ void phase_combine(const BatchDev& B, int mode, char* lds_raw)
+{
+    double* red = reinterpret_cast<double*>(lds_raw);
+    for (int64_t g = blockIdx.x; g < B.total_chunks; g += gridDim.x) {
+        const int s = find_sys_chunk(B, g);
+        const SysDev& S = B.sys[s];
+        const int64_t sl = (g - S.chunk_off) * BW + threadIdx.x;
+        double ke = 0.0;
+        if (sl < S.n) {
+            const double4 fn = B.fnuc[S.off + sl];
+            double Fx = fn.x, Fy = fn.y, Fz = fn.z, V = fn.w;
+            if (sl < S.Z) {
+                for (int k = 0; k < S.S; ++k) {
+                    const double4 cp = B.coul_part[S.coul_off + (int64_t)k * S.Z + sl];
+                    Fx += cp.x;
+                    Fy += cp.y;
+                    Fz += cp.z;
+                    V += cp.w;
+                }
+            }
+            const int64_t i = S.off + B.perm[S.off + sl];
+            B.force[3 * i + 0] = Fx;
+            B.force[3 * i + 1] = Fy;
+            B.force[3 * i + 2] = Fz;
+            B.epot[i] = 0.5 * V;
+            if (!(isfinite(Fx) && isfinite(Fy) && isfinite(Fz)))
+                atomicOr(B.err, ERR_NONFINITE_FORCE);
+            if (mode) {
+                double* v = B.vel + 3 * i;
+                const double vx = v[0] + S.hdtm * Fx, vy = v[1] + S.hdtm * Fy,
+                             vz = v[2] + S.hdtm * Fz;
+                v[0] = vx;
+                v[1] = vy;
+                v[2] = vz;
+                ke = 0.5 * B.mass * (vx * vx + vy * vy + vz * vz);
+            }
+        }
+        // fixed-order block reduction of the chunk's kinetic energy
+        for (int m = 32; m >= 1; m >>= 1)
+            ke += __shfl_xor(ke, m, 64);
+        if ((threadIdx.x & 63) == 0)
+            red[threadIdx.x >> 6] = ke;
+        __syncthreads();
+        if (threadIdx.x == 0)
+            B.ke_chunk[g] = ((red[0] + red[1]) + red[2]) + red[3];
+        __syncthreads();
+    }
+}
+
+__device__ void phase_thermostat(const BatchDev& B, int64_t step, int mode, char* lds_raw)
+{
+    double* red = reinterpret_cast<double*>(lds_raw);
+    for (int s = blockIdx.x; s < B.nsys; s += gridDim.x) {
+        const SysDev& S = B.sys[s];
+        const bool thermo =
+            mode && S.rescale_every > 0 && (step + 1) % S.rescale_every == 0;
+        if (!thermo) {
+            if (threadIdx.x == 0)
+                B.pending[s] = 1.0;
+            continue;
+        }
+        double acc = 0.0;
+        for (int k = threadIdx.x; k < S.nchunks; k += BW)
+            acc += B.ke_chunk[S.chunk_off + k];
+        red[threadIdx.x] = acc;
+        __syncthreads();
+        for (int off = BW / 2; off > 0; off >>= 1) {
+            if (threadIdx.x < off)
+                red[threadIdx.x] += red[threadIdx.x + off];
+            __syncthreads();
+        }
+        if (threadIdx.x == 0) {
+            const double ke = red[0];
+            B.pending[s] = ke > 0.0 ? sqrt(1.5 * (double)S.n * S.T / ke) : 1.0;
+        }
+        __syncthreads();
+    }
+}
+
+constexpr int BATCH_LDS = 34 * 1024;
+
+template <class P>
+__global__ __launch_bounds__(BW) void k_batch_step(BatchDev B, int mode)
+{
+    __shared__ __align__(16) char lds[BATCH_LDS];
+    __shared__ int s_flag, s_item;
+    if (__hip_atomic_load(B.err, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) & ERR_BARRIER)
+        return;
+    const int64_t step = *B.step;
+    phase_drift(B, step, mode);
+    if (!grid_sync(B, &s_flag))
+        return;
+    phase_scan(B, step, mode, lds);
+    if (!grid_sync(B, &s_flag))
+        return;
+    phase_scatter(B, mode);
+    if (!grid_sync(B, &s_flag))
+        return;
+    phase_rank<P>(B, step, mode);
+    if (!grid_sync(B, &s_flag))
+        return;
+    phase_forces<P, false>(B, step, mode, lds, &s_item);
+    if (!grid_sync(B, &s_flag))
+        return;
+    phase_combine(B, mode, lds);
+    if (!grid_sync(B, &s_flag))
+        return;
+    phase_thermostat(B, step, mode, lds);
+    if (mode && blockIdx.x == 0 && threadIdx.x == 0)
+        *B.step = step + 1;
+}
+
+// ---- the same phases as separate kernels (multi-kernel form) -----------
+template <class P>
+__global__ __launch_bounds__(BW) void k_ph_drift(BatchDev B, int mode)
+{
+    phase_drift(B, *B.step, mode);
+}
+__global__ __launch_bounds__(BW) void k_ph_scan(BatchDev B, int mode)
+{
+    __shared__ __align__(16) char lds[BW * 8];
+    phase_scan(B, *B.step, mode, lds);
+}
+__global__ __launch_bounds__(BW) void k_ph_scatter(BatchDev B, int mode) { phase_scatter(B, mode); }
+template <class P>
+__global__ __launch_bounds__(BW) void k_ph_rank(BatchDev B, int mode)
+{
+    phase_rank<P>(B, *B.step, mode);
+}
+template <class P, bool COUNT>
+__global__ __launch_bounds__(BW) void k_ph_forces(BatchDev B, int mode)
+{
+    __shared__ __align__(16) char lds[BATCH_LDS];
+    __shared__ int s_item;
+    phase_forces<P, COUNT>(B, *B.step, mode, lds, &s_item);
+}
+__global__ __launch_bounds__(BW) void k_ph_combine(BatchDev B, int mode)
+{
+    __shared__ __align__(16) char lds[64];
+    phase_combine(B, mode, lds);
+}
+__global__ __launch_bounds__(BW) void k_ph_thermostat(BatchDev B, int mode)
+{
+    __shared__ __align__(16) char lds[BW * 8];
+    phase_thermostat(B, *B.step, mode, lds);
+}
+__global__ void k_ph_advance(BatchDev B)
+{
+    if (threadIdx.x == 0)
+        *B.step += 1;
+}
+
+// Apply the pending thermostat scale to the velocities (end of a step call).
+__global__ __launch_bounds__(BW) void k_apply_pending(BatchDev B)
+{
+    for (int64_t g = blockIdx.x; g < B.total_chunks; g += gridDim.x) {
+        const int s = find_sys_chunk(B, g);
+        const SysDev& S = B.sys[s];
+        const int64_t sl = (g - S.chunk_off) * BW + threadIdx.x;
+        if (sl < S.n) {
+            const double sc = B.pending[s];
+            double* v = B.vel + 3 * (S.off + sl);
+            v[0] *= sc;
+            v[1] *= sc;
+            v[2] *= sc;
+        }
+    }
+}
+__global__ void k_reset_pending(BatchDev B)
+{
+    if (threadIdx.x < (unsigned)B.nsys)
+        B.pending[threadIdx.x] = 1.0;
+}
+
+__global__ __launch_bounds__(BW) void k_batch_zero(int32_t* a, int32_t* b, int64_t m)
+{
+    for (int64_t k = (int64_t)blockIdx.x * BW + threadIdx.x; k < m; k += (int64_t)gridDim.x * BW) {
+        a[k] = 0;
+        b[k] = 0;
+    }
+}
+
+__global__ void k_batch_init_scalars(BatchDev B, int64_t step0)
+{
+    if (threadIdx.x == 0) {
+        *B.step = step0;
+        B.barrier[0] = 0u;
+        B.barrier[1] = 0u;
+        B.queue[0] = 0u;
+        B.queue[1] = 0u;
+        *B.err = 0u;
+    }
+    if (threadIdx.x < (unsigned)B.nsys) {
+        B.pending[threadIdx.x] = 1.0;
+        B.pairs[threadIdx.x] = 0ull;
+    }
+}
+
+__global__ void k_batch_zero_pairs(BatchDev B)
+{
+    if (threadIdx.x < (unsigned)B.nsys)
+        B.pairs[threadIdx.x] = 0ull;
+    if (threadIdx.x == 0) {
+        B.queue[0] = 0u;
+        B.queue[1] = 0u;
+    }
+}
+
+__global__ __launch_bounds__(BW) void k_batch_partial(const double* x, int64_t n, int kind,
+                                                      double mass, double* out)
+{
+    __shared__ double lds[BW];
+    double s = 0.0;
+    for (int64_t i = (int64_t)blockIdx.x * BW + threadIdx.x; i < n; i += (int64_t)gridDim.x * BW) {
+        if (kind == 0) {
+            s += x[i];
+        } else {
+            const double vx = x[3 * i], vy = x[3 * i + 1], vz = x[3 * i + 2];
+            s += 0.5 * mass * (vx * vx + vy * vy + vz * vz);
+        }
+    }
+    lds[threadIdx.x] = s;
+    __syncthreads();
+    for (int off = BW / 2; off > 0; off >>= 1) {
+        if (threadIdx.x < off)
+            lds[threadIdx.x] += lds[threadIdx.x + off];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0)
+        out[blockIdx.x] = lds[0];
+}
+
+}  // namespace
+}  // namespace pasta
+
+// ===================================================================== host
+#include <vector>
+
+using namespace pasta;
+
+struct pasta_batch {
+    pasta_potential pot;
+    int precision;
+    int mode;            // 0 persistent, 1 multi-kernel
+    int nsys;
+    int64_t n_total;
+    int64_t step;
+    int steps_per_graph;
+    std::vector<SysDev> sys;
+    std::vector<pasta_integrator> integ;
+    BatchDev dev;
+    hipStream_t user;    // the caller's stream
+    hipStream_t stream;  // the batch's own stream (graphs cannot be captured on
+                         // the null stream); joined to the caller's by events
+    hipEvent_t ev_in = nullptr, ev_out = nullptr;
+    unsigned grid;       // persistent grid size
+    unsigned phase_grid; // multi-kernel grid size
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t exec = nullptr;
+    double* red;         // [256]
+    ~pasta_batch()
+    {
+        if (stream)
+            (void)hipStreamSynchronize(stream);
+        if (exec)
+            (void)hipGraphExecDestroy(exec);
+        if (graph)
+            (void)hipGraphDestroy(graph);
+        if (ev_in)
+            (void)hipEventDestroy(ev_in);
+        if (ev_out)
+            (void)hipEventDestroy(ev_out);
+        if (stream)
+            (void)hipStreamDestroy(stream);
+    }
+};
+
+namespace {
+// The batch's stream waits for the work already queued on the caller's
+// stream, and the caller's stream for the batch's work.
+int join_in(pasta_batch* bt)
+{
+    PASTA_HIP(hipEventRecord(bt->ev_in, bt->user));
+    PASTA_HIP(hipStreamWaitEvent(bt->stream, bt->ev_in, 0));
+    return PASTA_OK;
+}
+int join_out(pasta_batch* bt)
+{
+    PASTA_HIP(hipEventRecord(bt->ev_out, bt->stream));
+    PASTA_HIP(hipStreamWaitEvent(bt->user, bt->ev_out, 0));
+    return PASTA_OK;
+}
+}  // namespace
+
+namespace {
+
+struct BatchLayout {
+    std::vector<SysDev> sys;
+    int64_t n_total = 0, total_chunks = 0, coul_items = 0, nuc_items = 0;
+    int64_t bins = 0, starts = 0, items = 0, coul = 0;
+};
+
+int batch_layout(const pasta_potential* pot, int nsys, const int64_t* n, const int64_t* Z,
+                 const double* L_max, BatchLayout* out)
+{
+    BatchLayout lay;
+    lay.sys.resize(nsys);
+    for (int s = 0; s < nsys; ++s) {
+        SysDev& S = lay.sys[s];
+        S = SysDev{};
+        if (n[s] <= 0 || n[s] > INT32_MAX / 2 || !(L_max[s] >= 2.0 * pot->r_nuc))
+            return fail(PASTA_EINVAL, "pasta_batch: system %d: bad n or box", s);
+        const int C_max = make_grid(L_max[s], pot->r_nuc).C;
+        S.off = lay.n_total;
+        S.n = (int32_t)n[s];
+        S.Z = Z ? (int32_t)Z[s] : (int32_t)n[s];
+        S.bin_off = lay.bins;
+        S.start_off = lay.starts;
+        S.item_max = (int32_t)(n[s] / NUC_CHUNK + C_max + 1);
+        S.item_off = lay.items;
+        S.S = coulomb_splits(S.Z);
+        S.per_split = S.S ? (int32_t)((S.Z + S.S - 1) / S.S) : 0;
+        S.coul_blocks = (int32_t)((S.Z + WG - 1) / WG);
+        S.coul_off = lay.coul;
+        S.nchunks = (int32_t)((n[s] + BW - 1) / BW);
+        S.chunk_off = lay.total_chunks;
+        S.coul_item_off = lay.coul_items;
+        S.nuc_item_off = lay.nuc_items;
+        lay.n_total += n[s];
+        lay.bins += 2 * (int64_t)C_max;
+        lay.starts += 2 * (int64_t)C_max + 1;
+        lay.items += S.item_max;
+        // capacity for any proton count Z <= n: S(Z) Z <= max(min(32 n, 2^19), n)
+        const int64_t cap32 = 32 * n[s] < 524288 ? 32 * n[s] : 524288;
+        lay.coul += cap32 > n[s] ? cap32 : n[s];
+        lay.total_chunks += S.nchunks;
+        lay.coul_items += (int64_t)S.coul_blocks * S.S;
+        lay.nuc_items += S.item_max;
+    }
+    *out = lay;
+    return PASTA_OK;
+}
+
+size_t batch_carve(Carver& cv, const BatchLayout& lay, int nsys, int precision, BatchDev* d)
+{
+    BatchDev b{};
+    const int64_t N = lay.n_total;
+    b.sys = cv.take<SysDev>(nsys);
+    b.force = cv.take<double>(3 * N);
+    b.epot = cv.take<double>(N);
+    b.key = cv.take<int32_t>(N);
+    b.tmp = cv.take<int32_t>(N);
+    b.perm = cv.take<int32_t>(N);
+    b.count = cv.take<int32_t>(lay.bins);
+    b.fill = cv.take<int32_t>(lay.bins);
+    b.start = cv.take<int32_t>(lay.starts);
+    b.items = cv.take<int32_t>(2 * lay.items);
+    b.n_items = cv.take<int32_t>(nsys);
+    b.stg = precision == PASTA_FP64 ? (void*)cv.take<double4>(N) : (void*)cv.take<Q4>(N);
+    b.coul_part = cv.take<double4>(lay.coul);
+    b.fnuc = cv.take<double4>(N);
+    b.ke_chunk = cv.take<double>(lay.total_chunks);
+    b.pending = cv.take<double>(nsys);
+    b.step = cv.take<int64_t>(1);
+    b.barrier = cv.take<unsigned>(2);
+    b.queue = cv.take<unsigned>(2);
+    b.err = cv.take<uint32_t>(1);
+    b.pairs = cv.take<unsigned long long>(nsys);
+    b.red = cv.take<double>(256);
+    if (d)
+        *d = b;
+    return cv.size();
+}
+
+template <class P>
+int launch_step(pasta_batch* bt, int mode)
+{
+    hipStream_t s = bt->stream;
+    if (bt->mode == 0) {
+        k_batch_step<P><<<bt->grid, BW, 0, s>>>(bt->dev, mode);
+    } else {
+        const unsigned g = bt->phase_grid;
+        k_ph_drift<P><<<g, BW, 0, s>>>(bt->dev, mode);
+        k_ph_scan<<<(unsigned)bt->nsys, BW, 0, s>>>(bt->dev, mode);
+        k_ph_scatter<<<g, BW, 0, s>>>(bt->dev, mode);
+        k_ph_rank<P><<<g, BW, 0, s>>>(bt->dev, mode);
+        k_ph_forces<P, false><<<g, BW, 0, s>>>(bt->dev, mode);
+        k_ph_combine<<<g, BW, 0, s>>>(bt->dev, mode);
+        k_ph_thermostat<<<(unsigned)bt->nsys, BW, 0, s>>>(bt->dev, mode);
+        if (mode)
+            k_ph_advance<<<1, 64, 0, s>>>(bt->dev);
+    }
+    PASTA_HIP(hipGetLastError());
+    return PASTA_OK;
+}
+
+int launch_one(pasta_batch* bt, int mode)
+{
+    return bt->precision == PASTA_FP64 ? launch_step<Fp64Policy>(bt, mode)
+                                       : launch_step<MixedPolicy>(bt, mode);
+}
+
+int check_batch_err(pasta_batch* bt, const char* who)
+{
+    uint32_t e = 0;
+    PASTA_HIP(hipMemcpyAsync(&e, bt->dev.err, sizeof(e), hipMemcpyDeviceToHost, bt->stream));
+    PASTA_HIP(hipStreamSynchronize(bt->stream));
+    if (e & ERR_BARRIER)
+        return fail(PASTA_EDEVICE, "%s: a device-wide barrier timed out (grid not resident)", who);
+    if (e & (ERR_RANGE | ERR_SPECIES))
+        return fail(PASTA_EINVAL, "%s: %s", who, describe_device_error(e).c_str());
+    if (e)
+        return fail(PASTA_EDEVICE, "%s: %s", who, describe_device_error(e).c_str());
+    return PASTA_OK;
+}
+
+template <class P>
+int persistent_grid(unsigned* out)
+{
+    int dev = 0, ncu = 0, occ = 0;
+    PASTA_HIP(hipGetDevice(&dev));
+    PASTA_HIP(hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev));
+    PASTA_HIP(hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ, k_batch_step<P>, BW, 0));
+    if (occ < 1)
+        return fail(PASTA_EHIP, "persistent batch kernel cannot be resident");
+    // at most two workgroups per CU: every workgroup must be resident at once
+    *out = (unsigned)ncu * (unsigned)(occ < 2 ? occ : 2);
+    return PASTA_OK;
+}
+
+}  // namespace
+
+extern "C" int pasta_batch_workspace(const pasta_potential* pot, int32_t precision, int32_t nsys,
+                                     const int64_t* h_n, const double* h_L_max, size_t* h_bytes)
+{
+    if (!pot || !h_n || !h_L_max || !h_bytes || nsys <= 0 || nsys > 1024 ||
+        (precision != PASTA_FP64 && precision != PASTA_MIXED))
+        return fail(PASTA_EINVAL, "pasta_batch_workspace: bad argument");
+    BatchLayout lay;
+    PASTA_TRY(batch_layout(pot, nsys, h_n, nullptr, h_L_max, &lay));
+    Carver cv(nullptr);
+    *h_bytes = batch_carve(cv, lay, nsys, precision, nullptr);
+    return PASTA_OK;
+}
+
+extern "C" int pasta_batch_create(const pasta_potential* pot, int32_t precision, int32_t nsys,
+                                  const int64_t* h_n, const double* h_L0,
+                                  const pasta_integrator* h_integ, int64_t step0,
+                                  const double* h_L_max, double* d_pos, double* d_vel,
+                                  const uint8_t* d_species, void* d_work, size_t work_bytes,
+                                  int32_t mode, int32_t steps_per_graph, void* stream,
+                                  pasta_batch** out)
+{
+    if (!pot || !h_n || !h_L0 || !h_integ || !h_L_max || !d_pos || !d_vel || !d_species ||
+        !out || nsys <= 0 || nsys > 1024 || step0 < 0 || (mode != 0 && mode != 1) ||
+        steps_per_graph < 1 || (precision != PASTA_FP64 && precision != PASTA_MIXED))
+        return fail(PASTA_EINVAL, "pasta_batch_create: bad argument");
+    *out = nullptr;
+    for (int s = 0; s < nsys; ++s) {
+        const pasta_integrator& g = h_integ[s];
+        if (!(g.dt > 0.0) || !std::isfinite(g.xi_dot) || !(g.T >= 0.0) || g.rescale_every < 0 ||
+            !(h_L0[s] > 0.0))
+            return fail(PASTA_EINVAL, "pasta_batch_create: system %d: bad integrator or L0", s);
+        const double Ls = h_L0[s] * (1.0 + g.xi_dot * ((double)step0 * g.dt));
+        if (Ls < 2.0 * pot->r_nuc || Ls > h_L_max[s] * (1.0 + 1e-12))
+            return fail(PASTA_EBOX, "pasta_batch_create: system %d: L = %g outside "
+                        "[2 r_nuc, L_max]", s, Ls);
+    }
+    BatchLayout lay;
+    PASTA_TRY(batch_layout(pot, nsys, h_n, nullptr, h_L_max, &lay));
+    Carver cv0(nullptr);
+    const size_t need = batch_carve(cv0, lay, nsys, precision, nullptr);
+    if (!d_work || work_bytes < need || (reinterpret_cast<uintptr_t>(d_work) & 255))
+        return fail(PASTA_EWORKSPACE, "pasta_batch_create: workspace needs %zu bytes", need);
+
+    pasta_batch* bt = new (std::nothrow) pasta_batch();
+    if (!bt)
+        return fail(PASTA_ENOMEM, "pasta_batch_create: out of host memory");
+    bt->pot = *pot;
+    bt->precision = precision;
+    bt->mode = mode;
+    bt->nsys = nsys;
+    bt->n_total = lay.n_total;
+    bt->step = step0;
+    bt->steps_per_graph = steps_per_graph;
+    bt->integ.assign(h_integ, h_integ + nsys);
+    bt->user = static_cast<hipStream_t>(stream);
+    if (hipStreamCreateWithFlags(&bt->stream, hipStreamNonBlocking) != hipSuccess ||
+        hipEventCreateWithFlags(&bt->ev_in, hipEventDisableTiming) != hipSuccess ||
+        hipEventCreateWithFlags(&bt->ev_out, hipEventDisableTiming) != hipSuccess) {
+        delete bt;
+        return fail(PASTA_EHIP, "pasta_batch_create: stream/event creation failed");
+    }
+    if (join_in(bt) != PASTA_OK) {
+        delete bt;
+        return PASTA_EHIP;
+    }
+    Carver cv(d_work);
+    batch_carve(cv, lay, nsys, precision, &bt->dev);
+    bt->red = bt->dev.red;
+    auto fail_free = [&](int rc) {
+        delete bt;
+        return rc;
+    };
+    // Z per system: count protons on the host side of a first pass
+    std::vector<int64_t> Z(nsys, 0);
+    {
+        std::vector<uint8_t> sp(lay.n_total);
+        if (hipMemcpyAsync(sp.data(), d_species, lay.n_total, hipMemcpyDeviceToHost,
+                           bt->stream) != hipSuccess ||
+            hipStreamSynchronize(bt->stream) != hipSuccess)
+            return fail_free(fail(PASTA_EHIP, "pasta_batch_create: species copy failed"));
+        for (int s = 0; s < nsys; ++s)
+            for (int64_t i = lay.sys[s].off; i < lay.sys[s].off + h_n[s]; ++i) {
+                if (sp[i] > 1)
+                    return fail_free(fail(PASTA_EINVAL, "pasta_batch_create: species not 0/1"));
+                Z[s] += sp[i];
+            }
+    }
+    BatchLayout lay2;
+    int rc = batch_layout(pot, nsys, h_n, Z.data(), h_L_max, &lay2);
+    if (rc != PASTA_OK)
+        return fail_free(rc);
+    // the Z-dependent layout must fit the carve made with Z = n (it does: S*Z
+    // and the Coulomb tiles only shrink)
+    for (int s = 0; s < nsys; ++s) {
+        SysDev& S = lay2.sys[s];
+        S.coul_off = lay.sys[s].coul_off;
+        const pasta_integrator& g = h_integ[s];
+        S.L0 = h_L0[s];
+        S.xi_dot = g.xi_dot;
+        S.dt = g.dt;
+        S.T = g.T;
+        S.hdtm = g.dt / (2.0 * pot->mass);
+        S.rescale_every = g.rescale_every;
+        S.scale_positions = g.scale_positions;
+    }
+    bt->sys = lay2.sys;
+    BatchDev& B = bt->dev;
+    B.nsys = nsys;
+    B.total_chunks = lay2.total_chunks;
+    B.coul_items = lay2.coul_items;
+    B.nuc_items = lay2.nuc_items;
+    B.pp.a = pot->a;
+    B.pp.b_like = pot->b + pot->c;
+    B.pp.b_unlike = pot->b - pot->c;
+    B.pp.Lambda = pot->Lambda;
+    B.pp.r_nuc = pot->r_nuc;
+    B.pp.alpha_hbarc = pot->alpha_hbarc;
+    B.pp.lambda_s = pot->lambda_s;
+    B.pp.L = 0.0;
+    B.mass = pot->mass;
+    B.pos = d_pos;
+    B.vel = d_vel;
+    B.species = d_species;
+    hipStream_t s = bt->stream;
+    if (hipMemcpyAsync((void*)B.sys, bt->sys.data(), sizeof(SysDev) * nsys,
+                       hipMemcpyHostToDevice, s) != hipSuccess)
+        return fail_free(fail(PASTA_EHIP, "pasta_batch_create: descriptor copy failed"));
+    k_batch_init_scalars<<<1, 1024, 0, s>>>(B, step0);
+    k_batch_zero<<<256, BW, 0, s>>>(B.count, B.fill, lay.bins);
+    rc = precision == PASTA_FP64 ? persistent_grid<Fp64Policy>(&bt->grid)
+                                 : persistent_grid<MixedPolicy>(&bt->grid);
+    if (rc != PASTA_OK)
+        return fail_free(rc);
+    bt->phase_grid = bt->grid * 2;
+    // initial forces at the starting state (mode 0: no drift, no kick)
+    rc = launch_one(bt, 0);
+    if (rc == PASTA_OK)
+        rc = check_batch_err(bt, "pasta_batch_create");
+    if (rc != PASTA_OK)
+        return fail_free(rc);
+    rc = join_out(bt);
+    if (rc != PASTA_OK)
+        return fail_free(rc);
+    *out = bt;
+    return PASTA_OK;
+}
+
+static int batch_capture(pasta_batch* bt)
+{
+    if (bt->exec)
+        return PASTA_OK;
+    hipStream_t s = bt->stream;
+    PASTA_HIP(hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal));
+    int rc = PASTA_OK;
+    for (int k = 0; k < bt->steps_per_graph && rc == PASTA_OK; ++k)
+        rc = launch_one(bt, 1);
+    hipGraph_t g = nullptr;
+    hipError_t e = hipStreamEndCapture(s, &g);
+    if (rc != PASTA_OK)
+        return rc;
+    if (e != hipSuccess)
+        return fail(PASTA_EHIP, "hipStreamEndCapture: %s", hipGetErrorString(e));
+    bt->graph = g;
+    PASTA_HIP(hipGraphInstantiate(&bt->exec, g, nullptr, nullptr, 0));
+    return PASTA_OK;
+}
+
+extern "C" int pasta_batch_step(pasta_batch* bt, int64_t nsteps)
+{
+    if (!bt || nsteps < 0)
+        return fail(PASTA_EINVAL, "pasta_batch_step: bad argument");
+    for (int s = 0; s < bt->nsys; ++s) {
+        const pasta_integrator& g = bt->integ[s];
+        const double L = bt->sys[s].L0 * (1.0 + g.xi_dot * ((double)(bt->step + nsteps) * g.dt));
+        const Grid gr = make_grid(L, bt->pot.r_nuc);
+        const double Lm = bt->sys[s].L0 * (1.0 + g.xi_dot * ((double)bt->step * g.dt));
+        const Grid g0 = make_grid(Lm, bt->pot.r_nuc);
+        const int64_t cap = (int64_t)bt->sys[s].item_max - bt->sys[s].n / NUC_CHUNK - 1;
+        if (L < 2.0 * bt->pot.r_nuc || gr.C > cap || g0.C > cap)
+            return fail(PASTA_EBOX, "pasta_batch_step: system %d leaves [2 r_nuc, L_max]", s);
+    }
+    hipStream_t st = bt->stream;
+    PASTA_TRY(join_in(bt));
+    PASTA_TRY(batch_capture(bt));
+    int64_t left = nsteps;
+    while (left >= bt->steps_per_graph) {
+        PASTA_HIP(hipGraphLaunch(bt->exec, st));
+        left -= bt->steps_per_graph;
+    }
+    for (; left > 0; --left)
+        PASTA_TRY(launch_one(bt, 1));
+    k_apply_pending<<<bt->grid, BW, 0, st>>>(bt->dev);
+    k_reset_pending<<<1, 1024, 0, st>>>(bt->dev);
+    PASTA_HIP(hipGetLastError());
+    bt->step += nsteps;
+    return join_out(bt);
+}
+
+extern "C" int pasta_batch_energies(pasta_batch* bt, double* h_ekin, double* h_epot, double* h_L,
+                                    int64_t* h_step)
+{
+    if (!bt)
+        return fail(PASTA_EINVAL, "pasta_batch_energies: null batch");
+    PASTA_TRY(join_in(bt));
+    PASTA_TRY(check_batch_err(bt, "pasta_batch"));
+    hipStream_t s = bt->stream;
+    std::vector<double> h(256);
+    for (int k = 0; k < bt->nsys; ++k) {
+        const SysDev& S = bt->sys[k];
+        for (int kind = 1; kind >= 0; --kind) {
+            double* dst = kind ? h_ekin : h_epot;
+            if (!dst)
+                continue;
+            const double* src = kind ? bt->dev.vel + 3 * S.off : bt->dev.epot + S.off;
+            k_batch_partial<<<256, BW, 0, s>>>(src, S.n, kind, bt->pot.mass, bt->red);
+            PASTA_HIP(hipMemcpyAsync(h.data(), bt->red, 256 * sizeof(double),
+                                     hipMemcpyDeviceToHost, s));
+            PASTA_HIP(hipStreamSynchronize(s));
+            double acc = 0.0;
+            for (double v : h)
+                acc += v;
+            dst[k] = acc;
+        }
+        if (h_L) {
+            const pasta_integrator& g = bt->integ[k];
+            h_L[k] = S.L0 * (1.0 + g.xi_dot * ((double)bt->step * g.dt));
+        }
+    }
+    if (h_step)
+        *h_step = bt->step;
+    return PASTA_OK;
+}
+
+extern "C" int pasta_batch_forces(pasta_batch* bt, double* d_force, double* d_epot)
+{
+    if (!bt)
+        return fail(PASTA_EINVAL, "pasta_batch_forces: null batch");
+    PASTA_TRY(join_in(bt));
+    if (d_force)
+        PASTA_HIP(hipMemcpyAsync(d_force, bt->dev.force, sizeof(double) * 3 * bt->n_total,
+                                 hipMemcpyDeviceToDevice, bt->stream));
+    if (d_epot)
+        PASTA_HIP(hipMemcpyAsync(d_epot, bt->dev.epot, sizeof(double) * bt->n_total,
+                                 hipMemcpyDeviceToDevice, bt->stream));
+    return join_out(bt);
+}
+
+extern "C" int pasta_batch_pair_counts(pasta_batch* bt, int64_t* h_nuclear, int64_t* h_coulomb)
+{
+    if (!bt || !h_nuclear || !h_coulomb)
+        return fail(PASTA_EINVAL, "pasta_batch_pair_counts: bad argument");
+    hipStream_t s = bt->stream;
+    PASTA_TRY(join_in(bt));
+    k_batch_zero_pairs<<<1, 1024, 0, s>>>(bt->dev);
+    // the cell lists and staging of the current state are in place; the
+    // count pass rewrites F (same values) without a kick
+    const unsigned g = bt->phase_grid;
+    if (bt->precision == PASTA_FP64)
+        k_ph_forces<Fp64Policy, true><<<g, BW, 0, s>>>(bt->dev, 0);
+    else
+        k_ph_forces<MixedPolicy, true><<<g, BW, 0, s>>>(bt->dev, 0);
+    PASTA_HIP(hipGetLastError());
+    std::vector<unsigned long long> h(bt->nsys);
+    PASTA_HIP(hipMemcpyAsync(h.data(), bt->dev.pairs, sizeof(unsigned long long) * bt->nsys,
+                             hipMemcpyDeviceToHost, s));
+    PASTA_HIP(hipStreamSynchronize(s));
+    for (int k = 0; k < bt->nsys; ++k) {
+        h_nuclear[k] = (int64_t)(h[k] / 2);
+        const int64_t Z = bt->sys[k].Z;
+        h_coulomb[k] = Z * (Z - 1) / 2;
+    }
+    return check_batch_err(bt, "pasta_batch_pair_counts");
+}
+
+extern "C" int pasta_batch_info(pasta_batch* bt, int32_t* h_grid, int32_t* h_mode)
+{
+    if (!bt)
+        return fail(PASTA_EINVAL, "pasta_batch_info: null batch");
+    if (h_grid)
+        *h_grid = (int32_t)(bt->mode == 0 ? bt->grid : bt->phase_grid);
+    if (h_mode)
+        *h_mode = bt->mode;
+    return PASTA_OK;
+}
+
+extern "C" void pasta_batch_destroy(pasta_batch* bt)
+{
+    if (!bt)
+        return;
+    delete bt;
+}

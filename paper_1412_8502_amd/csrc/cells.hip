@@ -37,7 +37,7 @@ __global__ __launch_bounds__(256) void k_bin_count(const double* __restrict__ po
         cz = cell_coord(z, inv_w, nc);
     int bin = (sp == 1 ? 0 : C) + (cz * nc + cy) * nc + cx;
     key[i] = bin;
-    atomicAdd(&count[bin], 1);
+    wave_aggregated_add(count, bin);
 }
 
 constexpr int SCAN_THREADS = 1024;
@@ -111,17 +111,22 @@ __global__ __launch_bounds__(SCAN_THREADS) void k_scan(int32_t* __restrict__ cou
     }
 }
 
+// order: the previous sorted order (perm of the last build) or null for the
+// caller's order.  Visiting particles in the previous cell order keeps the
+// lanes of a wave in one or two bins, so the cursor atomics aggregate.
 __global__ __launch_bounds__(256) void k_scatter(const int32_t* __restrict__ key, int64_t n,
+                                                 const int32_t* __restrict__ order,
                                                  const int32_t* __restrict__ start,
                                                  int32_t* __restrict__ fill,
                                                  int32_t* __restrict__ tmp)
 {
-    int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= n)
+    int64_t s = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (s >= n)
         return;
-    int b = key[i];
-    int slot = start[b] + atomicAdd(&fill[b], 1);
-    tmp[slot] = (int32_t)i;
+    const int32_t i = order ? order[s] : (int32_t)s;
+    const int b = key[i];
+    const int slot = start[b] + wave_aggregated_add(fill, b);
+    tmp[slot] = i;
 }
 
 __global__ __launch_bounds__(256) void k_rank(const int32_t* __restrict__ key,
@@ -136,13 +141,24 @@ __global__ __launch_bounds__(256) void k_rank(const int32_t* __restrict__ key,
     int64_t s = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (s >= n)
         return;
-    int32_t id = tmp[s];
-    int b = key[id];
-    int beg = start[b], end = start[b + 1];
-    int r = 0;
-    for (int k = beg; k < end; ++k)
+    const int32_t id = tmp[s];
+    const int b = key[id];
+    const int beg = start[b], end = start[b + 1];
+    // rank = members of the bin with a smaller index; eight independent
+    // loads per iteration keep the loop from being latency-bound
+    int r = 0, k = beg;
+    for (; k + 8 <= end; k += 8) {
+        int32_t v[8];
+#pragma unroll
+        for (int u = 0; u < 8; ++u)
+            v[u] = tmp[k + u];
+#pragma unroll
+        for (int u = 0; u < 8; ++u)
+            r += v[u] < id;
+    }
+    for (; k < end; ++k)
         r += tmp[k] < id;
-    int dst = beg + r;
+    const int dst = beg + r;
     perm[dst] = id;
     double x = pos[3 * (int64_t)id + 0], y = pos[3 * (int64_t)id + 1],
            z = pos[3 * (int64_t)id + 2];
@@ -214,12 +230,14 @@ void launch_scan(const CellBuf& cb, int C, int chunk, hipStream_t s, Timer* t)
 }
 
 void launch_scatter_rank(const double* pos, const uint8_t* species, int64_t n, const Grid& g,
-                         const CellBuf& cb, double4* stg64, Q4* stgq, hipStream_t s, Timer* t)
+                         const CellBuf& cb, double4* stg64, Q4* stgq, hipStream_t s, Timer* t,
+                         bool prev_order)
 {
     if (n <= 0)
         return;
     timer_begin(t, KC_SCATTER, s);
-    k_scatter<<<blocks_for(n, 256), 256, 0, s>>>(cb.key, n, cb.start, cb.fill, cb.tmp);
+    k_scatter<<<blocks_for(n, 256), 256, 0, s>>>(cb.key, n, prev_order ? cb.perm : nullptr,
+                                                 cb.start, cb.fill, cb.tmp);
     timer_end(t, KC_SCATTER, s);
     timer_begin(t, KC_RANK, s);
     k_rank<<<blocks_for(n, 256), 256, 0, s>>>(cb.key, cb.tmp, n, cb.start, cb.perm, pos,

@@ -16,14 +16,18 @@ namespace pasta {
 
 namespace {
 
+// Particles are visited in the order of the previous cell build (perm), so
+// the lanes of a wave mostly fall in one bin and the count atomics aggregate.
 __global__ __launch_bounds__(256) void k_drift(DriftArgs a, int nc, int C, double inv_w,
+                                               const int32_t* __restrict__ order,
                                                int32_t* __restrict__ key,
                                                int32_t* __restrict__ count,
                                                uint32_t* __restrict__ err)
 {
-    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= a.n)
+    const int64_t s = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (s >= a.n)
         return;
+    const int64_t i = order[s];
     const double L = a.L_new;
     int cc[3];
     uint32_t bad = 0;
@@ -53,7 +57,7 @@ __global__ __launch_bounds__(256) void k_drift(DriftArgs a, int nc, int C, doubl
         atomicOr(err, bad);
     const int bin = (a.species[i] == 1 ? 0 : C) + (cc[2] * nc + cc[1]) * nc + cc[0];
     key[i] = bin;
-    atomicAdd(&count[bin], 1);
+    wave_aggregated_add(count, bin);
 }
 
 constexpr int RED = 1024;
@@ -127,8 +131,8 @@ void launch_drift(const DriftArgs& a, const Grid& g, const CellBuf& cb, uint32_t
     if (a.n <= 0)
         return;
     timer_begin(t, KC_DRIFT, s);
-    k_drift<<<(unsigned)((a.n + 255) / 256), 256, 0, s>>>(a, g.nc, g.C, g.inv_w, cb.key,
-                                                          cb.count, err);
+    k_drift<<<(unsigned)((a.n + 255) / 256), 256, 0, s>>>(a, g.nc, g.C, g.inv_w, cb.perm,
+                                                          cb.key, cb.count, err);
     timer_end(t, KC_DRIFT, s);
 }
 

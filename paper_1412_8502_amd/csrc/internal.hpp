@@ -99,6 +99,31 @@ __device__ inline int cell_coord(double x, double inv_w, int nc)
     return k < 0 ? 0 : k;
 }
 
+// Wave-aggregated atomic add of 1 per lane on counters[bin]: lanes of a
+// wavefront that share a bin issue one atomic between them.  Returns the
+// counter value seen by this lane's share (old value + rank among the
+// wave's lanes with the same bin, in lane order).  Must be called by every
+// active lane of the wave (the loop below is wave-uniform).
+__device__ inline int wave_aggregated_add(int32_t* counters, int bin)
+{
+    unsigned long long todo = __ballot(1);
+    const int lane = __lane_id();
+    int result = 0;
+    while (todo) {
+        const int leader = __ffsll((unsigned long long)todo) - 1;
+        const int b = __shfl(bin, leader);
+        const unsigned long long mask = __ballot(bin == b) & todo;
+        int base = 0;
+        if (lane == leader)
+            base = atomicAdd(&counters[b], __popcll(mask));
+        base = __shfl(base, leader);
+        if (bin == b)
+            result = base + __popcll(mask & ((1ull << lane) - 1ull));
+        todo &= ~mask;
+    }
+    return result;
+}
+
 // ------------------------------------------------------ staging formats
 // FP64 staging: x, y, z in fm, w unused.
 // MIXED staging: x, y, z as 32-bit fixed point (x/L * 2^32), w = species.
@@ -146,9 +171,11 @@ void launch_bin_count(const double* pos, const uint8_t* species, int64_t n, cons
 // chunk > 0, also writes the nuclear work list.
 void launch_scan(const CellBuf& cb, int C, int chunk, hipStream_t s, Timer* t);
 // Stable scatter: slot order = (bin, particle index).  Writes perm and, when
-// staging pointers are given, the sorted staging coordinates.
+// staging pointers are given, the sorted staging coordinates.  prev_order:
+// visit particles in the order of the previous build (cb.perm must hold it).
 void launch_scatter_rank(const double* pos, const uint8_t* species, int64_t n, const Grid& g,
-                         const CellBuf& cb, double4* stg64, Q4* stgq, hipStream_t s, Timer* t);
+                         const CellBuf& cb, double4* stg64, Q4* stgq, hipStream_t s, Timer* t,
+                         bool prev_order = false);
 
 // ----------------------------------------------------------------- forces
 struct PairParams {

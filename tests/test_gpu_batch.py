@@ -1,0 +1,181 @@
+"""GPU parity of the batched path (several independent systems advanced by
+one persistent launch per step, or one launch per phase, from a captured
+hipGraph) against the FP64 oracle, system by system.  Tolerances as in
+test_gpu_parity.py."""
+import numpy as np
+import pytest
+
+pytestmark = pytest.mark.gpu
+
+TOL_F = {0: 1e-12, 1: 1e-5}
+TOL_E = {0: 1e-12, 1: 1e-6}
+TOL_X = {0: 1e-9, 1: 2e-4}
+
+
+@pytest.fixture(scope="module")
+def env():
+    import torch
+    import oracle
+    from paper_1412_8502_amd import binding as B
+    from paper_1412_8502_amd import inputs
+    assert torch.cuda.is_available()
+    oracle.build()
+    return dict(torch=torch, B=B, O=oracle, I=inputs, dev=torch.device("cuda:0"))
+
+
+def say(*a):
+    print(*a, flush=True)
+
+
+def rel(a, b):
+    nb = np.linalg.norm(b)
+    return np.linalg.norm(a - b) / (nb if nb > 0 else 1.0)
+
+
+SMALL = [  # (N, Y_P, density, T, seed): uneven sizes, densities and charge
+    (700, 0.40, 0.030, 1.0, 1),
+    (2400, 0.20, 0.080, 0.75, 2),
+    (1500, 0.05, 0.050, 0.5, 3),
+    (1000, 0.00, 0.060, 1.0, 4),
+    (1200, 1.00, 0.040, 1.0, 5),
+]
+
+
+def make(env, specs, integs=None, prec=1, mode=0, spg=4, L_max=None):
+    t = env["torch"]
+    states = [env["I"].make_state(N, yp, d, T, seed) for (N, yp, d, T, seed) in specs]
+    pos = t.tensor(np.concatenate([s["pos"] for s in states]), device=env["dev"])
+    vel = t.tensor(np.concatenate([s["vel"] for s in states]), device=env["dev"])
+    sp = t.tensor(np.concatenate([s["species"] for s in states]), device=env["dev"])
+    integs = integs or [dict(dt=2.0, T=s["T"]) for s in states]
+    b = env["B"].Batch(pos, vel, sp, [s["n"] for s in states], [s["L"] for s in states], integs,
+                       precision=prec, mode=mode, steps_per_graph=spg, L_max=L_max)
+    offs = np.concatenate([[0], np.cumsum([s["n"] for s in states])])
+    return b, states, pos, vel, offs
+
+
+@pytest.mark.parametrize("mode", [0, 1])
+@pytest.mark.parametrize("prec", [0, 1])
+def test_batch_initial_forces(env, prec, mode):
+    say("batch initial forces prec", prec, "mode", mode)
+    b, states, pos, vel, offs = make(env, SMALL, prec=prec, mode=mode)
+    f, e = b.forces()
+    f, e = f.cpu().numpy(), e.cpu().numpy()
+    for k, st in enumerate(states):
+        of, oe = env["O"].forces(st["pos"], st["species"], st["L"])
+        sl = slice(offs[k], offs[k + 1])
+        ef, ee = rel(f[sl], of), rel(e[sl], oe)
+        say(f"  system {k}: force {ef:.2e} energy {ee:.2e}")
+        assert ef <= TOL_F[prec] and ee <= TOL_E[prec]
+    b.close()
+
+
+@pytest.mark.parametrize("prec", [0, 1])
+def test_batch_trajectory_vs_oracle(env, prec):
+    specs = SMALL[:3]
+    integs = [dict(dt=2.0, T=1.0, xi_dot=1e-3),           # expanding box
+              dict(dt=2.0, T=0.75, rescale_every=4),      # thermostat every 4 steps
+              dict(dt=1.0, T=0.5, xi_dot=5e-4, scale_positions=1)]
+    states = [env["I"].make_state(*s) for s in specs]
+    nsteps = 10
+    L_max = [st["L"] * (1 + g.get("xi_dot", 0) * g["dt"] * nsteps) for st, g in zip(states, integs)]
+    b, states, pos, vel, offs = make(env, specs, integs, prec=prec, mode=0, spg=4, L_max=L_max)
+    b.step(nsteps)
+    en = b.energies()
+    P, V = pos.cpu().numpy(), vel.cpu().numpy()
+    for k, (st, g) in enumerate(zip(states, integs)):
+        op, ov, oL, oek, oep, of = env["O"].run(
+            st["pos"], st["vel"], st["species"], st["L"], nsteps, dt=g["dt"],
+            xi_dot=g.get("xi_dot", 0.0), T=g["T"], rescale_every=g.get("rescale_every", 0),
+            scale_positions=g.get("scale_positions", 0))
+        sl = slice(offs[k], offs[k + 1])
+        d = P[sl] - op
+        d -= oL * np.round(d / oL)
+        dx = np.abs(d).max()
+        say(f"  system {k}: L {en['L'][k]:.6f} vs {oL:.6f}, max |dx| {dx:.3e}")
+        assert en["L"][k] == oL
+        assert dx <= TOL_X[prec]
+        assert abs(en["ekin"][k] - oek) <= 1e-6 * oek + 10 * TOL_X[prec] * oek
+    assert en["step"] == nsteps
+    b.close()
+
+
+def test_batch_modes_and_graph_replay_agree(env):
+    """Persistent and per-phase forms run the same phase code; graph replays
+    (4 steps per graph) and direct launches must agree with each other."""
+    outs = []
+    for mode, spg in ((0, 4), (1, 4), (0, 1)):
+        b, states, pos, vel, offs = make(env, SMALL[:4], prec=0, mode=mode, spg=spg,
+                                         integs=[dict(dt=2.0, T=1.0, rescale_every=3)] * 4)
+        b.step(10)
+        b.step(3)
+        outs.append((pos.cpu().numpy(), vel.cpu().numpy()))
+        b.close()
+    for p, v in outs[1:]:
+        assert np.abs(p - outs[0][0]).max() <= 1e-12
+        assert np.abs(v - outs[0][1]).max() <= 1e-12
+
+
+def test_batch_matches_single_system_path(env):
+    t, B = env["torch"], env["B"]
+    specs = SMALL[:3]
+    b, states, pos, vel, offs = make(env, specs, prec=1, mode=0,
+                                     integs=[dict(dt=2.0, T=1.0, rescale_every=5)] * 3)
+    b.step(12)
+    P = pos.cpu().numpy()
+    for k, st in enumerate(states):
+        p1 = t.tensor(st["pos"], device=env["dev"])
+        v1 = t.tensor(st["vel"], device=env["dev"])
+        s1 = t.tensor(st["species"], device=env["dev"])
+        sim = B.Sim(p1, v1, s1, st["L"], dt=2.0, T=1.0, rescale_every=5, precision=1)
+        sim.step(12)
+        d = np.abs(p1.cpu().numpy() - P[offs[k]:offs[k + 1]])
+        d = np.minimum(d, st["L"] - d)
+        say(f"  system {k}: batch vs single max |dx| {d.max():.3e}")
+        assert d.max() <= 1e-9
+        sim.close()
+    b.close()
+
+
+def test_batch_thermostat_and_pairs(env):
+    specs = SMALL[:3]
+    b, states, pos, vel, offs = make(env, specs, prec=0, mode=0,
+                                     integs=[dict(dt=2.0, T=s[3], rescale_every=5) for s in specs])
+    b.step(5)
+    en = b.energies()
+    for k, st in enumerate(states):
+        assert en["ekin"][k] == pytest.approx(1.5 * st["n"] * st["T"], rel=1e-13)
+    nn, nc = b.pair_counts()
+    P = pos.cpu().numpy()
+    for k, st in enumerate(states):
+        onn, onc = env["O"].pair_counts(P[offs[k]:offs[k + 1]], st["species"], st["L"])
+        assert (nn[k], nc[k]) == (onn, onc)
+    b.close()
+
+
+def test_batch_paper_grid_sampled(env):
+    """The 15-system grid (Y_P x T, seeded N and density) at full size, mixed
+    precision, persistent form: 5 steps, then sampled forces per system
+    against the oracle on the GPU's own state."""
+    t, B, O = env["torch"], env["B"], env["O"]
+    states = env["I"].batch_grid()
+    pos = t.tensor(np.concatenate([s["pos"] for s in states]), device=env["dev"])
+    vel = t.tensor(np.concatenate([s["vel"] for s in states]), device=env["dev"])
+    sp = t.tensor(np.concatenate([s["species"] for s in states]), device=env["dev"])
+    b = B.Batch(pos, vel, sp, [s["n"] for s in states], [s["L"] for s in states],
+                [dict(dt=2.0, T=s["T"], rescale_every=100) for s in states], precision=1,
+                mode=0, steps_per_graph=5)
+    say("  grid", b.info(), "total N", pos.shape[0])
+    b.step(5)
+    f, _ = b.forces()
+    f = f.cpu().numpy()
+    P = pos.cpu().numpy()
+    offs = np.concatenate([[0], np.cumsum([s["n"] for s in states])])
+    rng = np.random.Generator(np.random.PCG64(7))
+    for k, st in enumerate(states):
+        sl = slice(offs[k], offs[k + 1])
+        tg = rng.choice(st["n"], 40, replace=False)
+        of, _ = O.forces(P[sl], st["species"], st["L"], targets=tg)
+        err = rel(f[sl][tg], of)
+        assert err <= TOL_F[1], (k, err)
+    b.close()
