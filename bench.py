@@ -126,6 +126,13 @@ def main():
     log(f"workload {WORKLOAD}: N={N} Z={Z} L={st['L']:.4f} steps={K} warmup={W}")
     mixed = run_path(B, torch, st, B.PASTA_MIXED, K, W, timing=True)
     log(f"mixed: {mixed['seconds'] / K * 1e3:.4f} ms/step")
+    # the dense cell-tile nuclear kernel, for comparison with the default
+    # screened + compacted one
+    old = B.pasta_set_tuning(nuclear_variant=0)
+    dense = run_path(B, torch, st, B.PASTA_MIXED, max(20, K // 5), min(W, 20), timing=True)
+    B.pasta_set_tuning(**old)
+    kd = max(20, K // 5)
+    log(f"mixed, dense nuclear kernel: {dense['seconds'] / kd * 1e3:.4f} ms/step")
     k64 = args.fp64_steps or max(20, K // 4)
     fp64 = run_path(B, torch, st, B.PASTA_FP64, k64, min(W, 20), timing=True)
     log(f"fp64: {fp64['seconds'] / k64 * 1e3:.4f} ms/step")
@@ -188,6 +195,9 @@ def main():
                  "steps": k64,
                  "per_kernel_ms": {k: round(v[0] / k64, 5) for k, v in fp64["kernel_times"].items() if v[1]}},
         "mixed_over_fp64_speedup": fp64_ms / ms_step,
+        "nuclear_variant": B.pasta_get_tuning()["nuclear_variant"],
+        "dense_nuclear_variant": {"ms_per_step": dense["seconds"] / kd * 1e3,
+                                  "nuclear_ms": dense["kernel_times"]["nuclear+kick"][0] / kd},
         "ms_per_step_with_events": mixed["seconds_with_events"] / K * 1e3,
         "per_kernel": per_kernel,
         "roofline": roof,

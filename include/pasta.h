@@ -94,6 +94,20 @@ typedef struct pasta_integrator {
                                 (the paper); 1: x *= L_{n+1}/L_n (variant) */
 } pasta_integrator;
 
+/* Kernel choices, process-wide; read at every launch.
+ * nuclear_variant: 0 = dense cell tiles (every candidate pair through the
+ *   full pair arithmetic); 1 = screened + compacted (a conservative 16-bit
+ *   screen, survivors listed in LDS, exact arithmetic on listed pairs only;
+ *   the default).  Both give the same forces to rounding.
+ * coulomb_splits: number of source ranges per Coulomb target tile, 1..32;
+ *   0 = automatic (about 2^19 / Z, at most 32). */
+typedef struct pasta_tuning {
+    int32_t nuclear_variant;
+    int32_t coulomb_splits;
+} pasta_tuning;
+int pasta_set_tuning(const pasta_tuning* t);
+int pasta_get_tuning(pasta_tuning* out);
+
 /* Fills *out with the paper's values (Table I, lambda = 10 fm, M = 939 MeV,
  * r_nuc = 11.5 fm, alpha hbar c = 1.4399645 MeV fm). */
 void pasta_potential_paper(pasta_potential* out);

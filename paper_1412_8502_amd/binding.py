@@ -40,6 +40,10 @@ class pasta_potential(ctypes.Structure):
                 ("a", "b", "c", "Lambda", "lambda_s", "alpha_hbarc", "mass", "r_nuc")]
 
 
+class pasta_tuning(ctypes.Structure):
+    _fields_ = [("nuclear_variant", ctypes.c_int32), ("coulomb_splits", ctypes.c_int32)]
+
+
 class pasta_integrator(ctypes.Structure):
     _fields_ = [("dt", ctypes.c_double), ("xi_dot", ctypes.c_double), ("T", ctypes.c_double),
                 ("rescale_every", ctypes.c_int32), ("scale_positions", ctypes.c_int32)]
@@ -57,6 +61,8 @@ def _load():
     pot, integ = P(pasta_potential), P(pasta_integrator)
     sig = {
         "pasta_potential_paper": (None, [pot]),
+        "pasta_set_tuning": (ctypes.c_int, [P(pasta_tuning)]),
+        "pasta_get_tuning": (ctypes.c_int, [P(pasta_tuning)]),
         "pasta_last_error": (ctypes.c_char_p, []),
         "pasta_version": (ctypes.c_char_p, []),
         "pasta_cell_list_workspace": (ctypes.c_int, [i64, d, d, P(sz)]),
@@ -141,6 +147,24 @@ def pasta_potential_paper() -> pasta_potential:
     p = pasta_potential()
     lib.pasta_potential_paper(ctypes.byref(p))
     return p
+
+
+def pasta_set_tuning(nuclear_variant: int | None = None, coulomb_splits: int | None = None):
+    """Process-wide kernel choices (see pasta_tuning in include/pasta.h);
+    returns the previous setting as a dict."""
+    cur = pasta_tuning()
+    _check(lib.pasta_get_tuning(ctypes.byref(cur)))
+    old = dict(nuclear_variant=cur.nuclear_variant, coulomb_splits=cur.coulomb_splits)
+    new = pasta_tuning(old["nuclear_variant"] if nuclear_variant is None else nuclear_variant,
+                       old["coulomb_splits"] if coulomb_splits is None else coulomb_splits)
+    _check(lib.pasta_set_tuning(ctypes.byref(new)))
+    return old
+
+
+def pasta_get_tuning() -> dict:
+    cur = pasta_tuning()
+    _check(lib.pasta_get_tuning(ctypes.byref(cur)))
+    return dict(nuclear_variant=cur.nuclear_variant, coulomb_splits=cur.coulomb_splits)
 
 
 def pasta_version() -> str:

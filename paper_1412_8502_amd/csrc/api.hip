@@ -237,6 +237,23 @@ extern "C" void pasta_potential_paper(pasta_potential* out)
     out->r_nuc = 11.5;
 }
 
+extern "C" int pasta_set_tuning(const pasta_tuning* t)
+{
+    if (!t || (t->nuclear_variant != 0 && t->nuclear_variant != 1) || t->coulomb_splits < 0 ||
+        t->coulomb_splits > 32)
+        return fail(PASTA_EINVAL, "pasta_set_tuning: bad argument");
+    g_tuning = *t;
+    return PASTA_OK;
+}
+
+extern "C" int pasta_get_tuning(pasta_tuning* out)
+{
+    if (!out)
+        return fail(PASTA_EINVAL, "pasta_get_tuning: null");
+    *out = g_tuning;
+    return PASTA_OK;
+}
+
 extern "C" const char* pasta_kernel_class_name(int32_t k)
 {
     static const char* names[PASTA_KERNEL_CLASSES] = {

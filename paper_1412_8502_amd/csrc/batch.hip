@@ -75,6 +75,7 @@ struct BatchDev {
     uint32_t* err;
     unsigned long long* pairs;  // [nsys] diagnostic nuclear pair counts
     double* red;          // [256] host-read reduction partials
+    int nuc_variant;      // 0 dense, 1 screened + compacted
 };
 
 __device__ __forceinline__ int find_sys_chunk(const BatchDev& B, int64_t g)
@@ -393,7 +394,10 @@ __device__ void phase_forces(const BatchDev& B, int64_t step, int mode, char* ld
             A.fnuc = B.fnuc + S.off;  // raw nuclear part; combine adds the rest
             A.pairs = B.pairs + s;
             A.err = B.err;
-            nuclear_item<P, true, COUNT>(stg + S.off, A, k, local, lds);
+            if (B.nuc_variant == 1)
+                nuclear_item_compact<P, true, COUNT>(stg + S.off, A, k, local, lds);
+            else
+                nuclear_item<P, true, COUNT>(stg + S.off, A, k, local, lds);
         }
     }
 }
@@ -477,12 +481,19 @@ __device__ void phase_thermostat(const BatchDev& B, int64_t step, int mode, char
     }
 }
 
-constexpr int BATCH_LDS = 34 * 1024;
+template <class P>
+constexpr int batch_lds()
+{
+    constexpr int a = coulomb_lds_bytes<P>(), b = nuclear_lds_bytes<P>(),
+                  c = nuclear_compact_lds_bytes<P>();
+    constexpr int m = a > b ? a : b;
+    return (m > c ? m : c) + 64;
+}
 
 template <class P>
 __global__ __launch_bounds__(BW) void k_batch_step(BatchDev B, int mode)
 {
-    __shared__ __align__(16) char lds[BATCH_LDS];
+    __shared__ __align__(16) char lds[batch_lds<P>()];
     __shared__ int s_flag, s_item;
     if (__hip_atomic_load(B.err, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) & ERR_BARRIER)
         return;
@@ -530,7 +541,7 @@ __global__ __launch_bounds__(BW) void k_ph_rank(BatchDev B, int mode)
 template <class P, bool COUNT>
 __global__ __launch_bounds__(BW) void k_ph_forces(BatchDev B, int mode)
 {
-    __shared__ __align__(16) char lds[BATCH_LDS];
+    __shared__ __align__(16) char lds[batch_lds<P>()];
     __shared__ int s_item;
     phase_forces<P, COUNT>(B, *B.step, mode, lds, &s_item);
 }
@@ -950,6 +961,7 @@ extern "C" int pasta_batch_create(const pasta_potential* pot, int32_t precision,
     B.pp.lambda_s = pot->lambda_s;
     B.pp.L = 0.0;
     B.mass = pot->mass;
+    B.nuc_variant = g_tuning.nuclear_variant;
     B.pos = d_pos;
     B.vel = d_vel;
     B.species = d_species;

@@ -40,16 +40,33 @@ __global__ __launch_bounds__(WG) void k_nuclear(const typename P::Src* __restric
     nuclear_item<P, NUC, COUNT>(stg, A, k, blockIdx.x, lds);
 }
 
+template <class P, bool NUC, bool COUNT>
+__global__ __launch_bounds__(WG) void k_nuclear_compact(const typename P::Src* __restrict__ stg,
+                                                        NucArgs A,
+                                                        const int32_t* __restrict__ n_items,
+                                                        NucConsts k)
+{
+    __shared__ __align__(16) char lds[nuclear_compact_lds_bytes<P>()];
+    if ((int)blockIdx.x >= *n_items)
+        return;
+    nuclear_item_compact<P, NUC, COUNT>(stg, A, k, blockIdx.x, lds);
+}
+
 template <class P>
 void nuclear_dispatch(const typename P::Src* stg, const NucArgs& a, const int32_t* n_items,
-                      const NucConsts& k, bool nuc, bool count, unsigned grid, hipStream_t s)
+                      const NucConsts& k, bool nuc, bool count, int variant, unsigned grid,
+                      hipStream_t s)
 {
-    if (nuc && count)
-        k_nuclear<P, true, true><<<grid, WG, 0, s>>>(stg, a, n_items, k);
-    else if (nuc)
-        k_nuclear<P, true, false><<<grid, WG, 0, s>>>(stg, a, n_items, k);
-    else
+    if (!nuc)
         k_nuclear<P, false, false><<<grid, WG, 0, s>>>(stg, a, n_items, k);
+    else if (variant == 1 && count)
+        k_nuclear_compact<P, true, true><<<grid, WG, 0, s>>>(stg, a, n_items, k);
+    else if (variant == 1)
+        k_nuclear_compact<P, true, false><<<grid, WG, 0, s>>>(stg, a, n_items, k);
+    else if (count)
+        k_nuclear<P, true, true><<<grid, WG, 0, s>>>(stg, a, n_items, k);
+    else
+        k_nuclear<P, true, false><<<grid, WG, 0, s>>>(stg, a, n_items, k);
 }
 
 }  // namespace
@@ -60,9 +77,16 @@ int coulomb_splits(int64_t Z)
 {
     if (Z <= 0)
         return 0;
-    int64_t s = 524288 / Z;
-    return (int)(s < 1 ? 1 : (s > 32 ? 32 : s));
+    const int req = g_tuning.coulomb_splits;
+    int64_t s = req > 0 ? req : 524288 / Z;
+    s = s < 1 ? 1 : (s > 32 ? 32 : s);
+    // the partial-sum buffer holds max(min(32 n, 2^19), n) entries, n >= Z
+    while (s > 1 && s * Z > 524288)
+        --s;
+    return (int)s;
 }
+
+pasta_tuning g_tuning = {1, 0};
 
 size_t forcebuf_carve(Carver& cv, ForceBuf* out, int64_t n, int64_t item_max, int precision)
 {
@@ -123,13 +147,14 @@ void launch_nuclear(int precision, const ForceBuf& fb, const CellBuf& cb, const 
     a.fnuc = nullptr;
     const unsigned grid = (unsigned)cb.item_max;
     const bool count = pair_counter != nullptr;
+    const int variant = g_tuning.nuclear_variant;
     timer_begin(t, KC_NUCLEAR, s);
     if (precision == PASTA_FP64)
         nuclear_dispatch<Fp64Policy>(fb.stg64, a, cb.n_items, k, with_nuclear_terms, count,
-                                     grid, s);
+                                     variant, grid, s);
     else
         nuclear_dispatch<MixedPolicy>(fb.stgq, a, cb.n_items, k, with_nuclear_terms, count,
-                                      grid, s);
+                                      variant, grid, s);
     timer_end(t, KC_NUCLEAR, s);
 }
 

@@ -200,6 +200,8 @@ struct ForceBuf {
     uint64_t* pairs;    // [2] diagnostic pair counters
 };
 int coulomb_splits(int64_t Z);
+// Process-wide kernel choices (set through pasta_set_tuning).
+extern pasta_tuning g_tuning;
 size_t forcebuf_carve(Carver& cv, ForceBuf* out, int64_t n, int64_t item_max, int precision);
 
 // Coulomb all-pairs over protons (sorted slots [0, Z)).

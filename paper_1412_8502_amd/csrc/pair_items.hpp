@@ -19,6 +19,8 @@
 //                  accumulators.
 #pragma once
 
+#include <climits>
+
 #include "internal.hpp"
 
 namespace pasta {
@@ -38,6 +40,10 @@ struct NucConsts {
     float cgq, A2f, af, Blf_L, Buf_L, Blf, Buf, thr_q;
     double q;       // fm per fixed-point unit
     double self_v;  // V(0) of a like pair = a + b + c, removed from E
+    // screening pass of the compacting kernel
+    double qscale;  // 2^32 / L (fixed-point units per fm)
+    int thr16;      // (r_nuc / (L/2^16) + 2)^2: conservative 16-bit test
+    float thr_stage;  // r_nuc^2 in 32-bit units^2, with a rounding margin
 };
 
 __host__ __device__ inline NucConsts make_nuc_consts(const PairParams& pp)
@@ -64,6 +70,10 @@ __host__ __device__ inline NucConsts make_nuc_consts(const PairParams& pp)
     k.Buf_L = (float)k.Bu_L;
     k.thr_q = (float)(k.rc2 / (k.q * k.q));
     k.self_v = pp.a + pp.b_like;
+    k.qscale = 4294967296.0 / pp.L;
+    const double r16 = pp.r_nuc * 65536.0 / pp.L + 2.0;
+    k.thr16 = (int)(r16 * r16) + 1;
+    k.thr_stage = (float)(k.rc2 / (k.q * k.q) * (1.0 + 1e-5));
     return k;
 }
 
@@ -107,14 +117,14 @@ struct Fp64Policy {
 
     template <bool COUNT>
     __device__ static void pair(const Src& me, const Lds& s, double B_L, double B,
-                                const NucConsts& k, Part& p)
+                                const NucConsts& k, Part& p, bool valid = true)
     {
         double dx = me.x - s.x, dy = me.y - s.y, dz = me.z - s.z;
         dx = fma(-k.L, rint(dx * k.invL), dx);
         dy = fma(-k.L, rint(dy * k.invL), dy);
         dz = fma(-k.L, rint(dz * k.invL), dz);
         double r2 = dx * dx + dy * dy + dz * dz;
-        const bool in = r2 < k.rc2;
+        const bool in = valid && r2 < k.rc2;
         if (COUNT)
             p.np += in ? 1u : 0u;
         double g = in ? exp(r2 * k.cg) : 0.0;
@@ -157,6 +167,13 @@ struct Fp64Policy {
     }
     __device__ static double coul_fscale(const CoulConsts&) { return 1.0; }
     __device__ static double coul_vscale(const CoulConsts&) { return 1.0; }
+    // 32-bit fixed-point coordinates (x/L * 2^32) for the screening pass
+    __device__ static uint3 fixed(const Src& s, const NucConsts& k)
+    {
+        return make_uint3((uint32_t)(uint64_t)(s.x * k.qscale), (uint32_t)(uint64_t)(s.y * k.qscale),
+                          (uint32_t)(uint64_t)(s.z * k.qscale));
+    }
+    static constexpr int CTILE = 512;  // sources per tile in the compacting kernel
 };
 
 struct MixedPolicy {
@@ -179,13 +196,13 @@ struct MixedPolicy {
 
     template <bool COUNT>
     __device__ static void pair(const Src& me, const Lds& s, float B_L, float B,
-                                const NucConsts& k, Part& p)
+                                const NucConsts& k, Part& p, bool valid = true)
     {
         float dx = (float)(int32_t)(me.x - s.x);
         float dy = (float)(int32_t)(me.y - s.y);
         float dz = (float)(int32_t)(me.z - s.z);
         float r2 = dx * dx + dy * dy + dz * dz;
-        const bool in = r2 < k.thr_q;
+        const bool in = valid && r2 < k.thr_q;
         if (COUNT)
             p.np += in ? 1u : 0u;
         r2 = in ? r2 : 3.0e38f;  // exp2 underflows to exactly 0 outside the cutoff
@@ -228,6 +245,11 @@ struct MixedPolicy {
     }
     __device__ static double coul_fscale(const CoulConsts& k) { return k.f_scale; }
     __device__ static double coul_vscale(const CoulConsts& k) { return k.v_scale; }
+    __device__ static uint3 fixed(const Src& s, const NucConsts&)
+    {
+        return make_uint3(s.x, s.y, s.z);
+    }
+    static constexpr int CTILE = 768;
 };
 
 // LDS bytes a work item needs (the caller provides at least this much,
@@ -238,6 +260,14 @@ template <class P>
 constexpr int nuclear_lds_bytes()
 {
     return P::TILE * (int)sizeof(typename P::Lds) + 54 * 4 + 55 * 4 + 4 + 4 * 8 + 4 * 8;
+}
+constexpr int NUC_CAP = 24;  // per-lane pair-list capacity (compacting kernel)
+constexpr int NUC_U = 4;     // candidates per lane between list-fill checks
+template <class P>
+constexpr int nuclear_compact_lds_bytes()
+{
+    return P::CTILE * ((int)sizeof(typename P::Lds) + 8) + NUC_CAP * WG * 2 + 54 * 4 +
+           55 * 4 + 16 * 4 + 4 * 8 + 4 * 8 + 64;
 }
 
 // ============================================================ Coulomb ==
@@ -442,6 +472,301 @@ __device__ void nuclear_item(const typename P::Src* __restrict__ stg, const NucA
         if ((tid & 63) == 0) {
             ke_red[tid >> 6] = ke;
             np_red[tid >> 6] = npairs;
+        }
+        __syncthreads();
+        if (tid == 0) {
+            double s = 0.0;
+            unsigned long long sn = 0;
+            for (int w = 0; w < WG / 64; ++w) {
+                s += ke_red[w];
+                sn += np_red[w];
+            }
+            if (A.ke_part && !A.fnuc)
+                A.ke_part[item] = s;
+            if (COUNT)
+                atomicAdd(A.pairs, sn);
+        }
+        __syncthreads();
+    }
+}
+
+
+// ================================================ nuclear, compacting ==
+// Same contract as nuclear_item, with a two-pass inner loop.  The
+// neighbourhood is staged tile by tile, keeping only sources that can reach
+// the bounding box of the chunk's targets.  Each lane then screens its share
+// of the tile with a cheap conservative test on 16-bit truncated coordinates
+// (packed 16-bit subtraction, which wraps to the nearest image, and a 2-wide
+// integer dot product), appends the survivors to a private list in LDS, and
+// evaluates the exact pair arithmetic only on listed pairs.  The screen never
+// drops a pair inside the cutoff (|d_true| < |d_16| + 1 per axis), and the
+// exact cutoff test of the pair arithmetic removes the false positives.
+__device__ __forceinline__ int screen16(uint32_t me_xy16, uint32_t me_z, uint2 t)
+{
+    typedef short v2s __attribute__((ext_vector_type(2)));
+    const v2s a = __builtin_bit_cast(v2s, me_xy16);
+    const v2s b = __builtin_bit_cast(v2s, t.x);
+    const v2s d = a - b;
+    const int dz = ((int32_t)(me_z - t.y)) >> 16;
+    return __builtin_amdgcn_sdot2(d, d, dz * dz, false);
+}
+
+template <class P, bool NUC, bool COUNT>
+__device__ void nuclear_item_compact(const typename P::Src* __restrict__ stg, const NucArgs& A,
+                                     const NucConsts& k, int item, char* lds)
+{
+    using Lds = typename P::Lds;
+    constexpr int T = P::CTILE;
+    Lds* src = reinterpret_cast<Lds*>(lds);
+    uint2* tst = reinterpret_cast<uint2*>(src + T);
+    uint16_t* lists = reinterpret_cast<uint16_t*>(tst + T);
+    int* seg_beg = reinterpret_cast<int*>(lists + NUC_CAP * WG);
+    int* seg_off = seg_beg + 54;
+    int* misc = seg_off + 55;  // [0..5] bbox lo/hi, [6..9] wave counts, [10..13] wave protons
+    double* ke_red = reinterpret_cast<double*>(
+        (reinterpret_cast<uintptr_t>(misc + 16) + 7) & ~uintptr_t(7));
+    unsigned long long* np_red = reinterpret_cast<unsigned long long*>(ke_red + WG / 64);
+
+    const int c = A.items[2 * item + 0];
+    const int chunk = A.items[2 * item + 1];
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    const int nc = A.nc, C = A.C;
+    const int cx = c % nc, cy = (c / nc) % nc, cz = c / (nc * nc);
+
+    if (tid < 54) {
+        const int kk = tid % 27, sp = tid / 27;  // sp 0: protons, 1: neutrons
+        const int ox = kk % 3 - 1, oy = (kk / 3) % 3 - 1, oz = kk / 9 - 1;
+        const int lo = axis_lo(nc), hi = axis_hi(nc);
+        int beg = 0, len = 0;
+        if (NUC && ox >= lo && ox <= hi && oy >= lo && oy <= hi && oz >= lo && oz <= hi) {
+            const int nx = (cx + ox + nc) % nc, ny = (cy + oy + nc) % nc,
+                      nz = (cz + oz + nc) % nc;
+            const int b = sp * C + (nz * nc + ny) * nc + nx;
+            beg = A.start[b];
+            len = A.start[b + 1] - beg;
+        }
+        seg_beg[tid] = beg;
+        seg_off[tid + 1] = len;
+    }
+    if (tid < 6)
+        misc[tid] = tid < 3 ? -1 : 0;  // lo = UINT_MAX, hi = 0 (as unsigned)
+    __syncthreads();
+    if (tid == 0) {
+        seg_off[0] = 0;
+        for (int s = 1; s <= 54; ++s)
+            seg_off[s] += seg_off[s - 1];
+    }
+
+    const int ps = A.start[c], npc = A.start[c + 1] - ps;
+    const int ns = A.start[C + c], mc = npc + (A.start[C + c + 1] - ns);
+    const int tl = tid / NUC_TPT, q = tid % NUC_TPT;
+    const int tidx = chunk * NUC_CHUNK + tl;
+    const bool active = tidx < mc;
+    const int slot = active ? (tidx < npc ? ps + tidx : ns + (tidx - npc)) : 0;
+    const bool tprot = tidx < npc;
+    const typename P::Src me = stg[slot];
+    const uint3 mef = P::fixed(me, k);
+    const uint32_t me_xy16 = (mef.x >> 16) | (mef.y & 0xffff0000u);
+
+    // bounding box of the chunk's targets (they lie inside one cell: no wrap)
+    if (active && q == 0) {
+        atomicMin(reinterpret_cast<unsigned*>(&misc[0]), mef.x);
+        atomicMin(reinterpret_cast<unsigned*>(&misc[1]), mef.y);
+        atomicMin(reinterpret_cast<unsigned*>(&misc[2]), mef.z);
+        atomicMax(reinterpret_cast<unsigned*>(&misc[3]), mef.x);
+        atomicMax(reinterpret_cast<unsigned*>(&misc[4]), mef.y);
+        atomicMax(reinterpret_cast<unsigned*>(&misc[5]), mef.z);
+    }
+    __syncthreads();
+    // box centre and half extent (rounded up): the nearest-image offset of a
+    // source from the centre, less the half extent, is its periodic gap
+    uint32_t bc[3], bh[3];
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+        const uint32_t lo = (uint32_t)misc[a], ext = (uint32_t)misc[3 + a] - lo;
+        bc[a] = lo + (ext >> 1);
+        bh[a] = ext - (ext >> 1);
+    }
+
+    typename P::Acc acc;
+    if (NUC) {
+        const int total = seg_off[54], np_tot = seg_off[27];
+        const auto BLp = P::bl(k, tprot), Bp = P::bv(k, tprot);    // proton sources
+        const auto BLn = P::bl(k, !tprot), Bn = P::bv(k, !tprot);  // neutron sources
+        typename P::Part part;
+        int tile_n = 0, tile_np = 0;  // wave-uniform copies of the tile fill
+
+        // evaluate the listed pairs of every lane, then empty the lists
+        auto drain = [&](int cnt, int kb) {
+            for (int kk = 0; __ballot(kk < cnt); kk += 2) {
+                const bool v0 = kk < cnt, v1 = kk + 1 < cnt;
+                const int j0 = v0 ? lists[kk * WG + tid] : 0;
+                const int j1 = v1 ? lists[(kk + 1) * WG + tid] : 0;
+                const Lds s0 = src[j0], s1 = src[j1];
+                const bool p0 = j0 < kb, p1 = j1 < kb;  // protons first in the tile
+                P::template pair<COUNT>(me, s0, p0 ? BLp : BLn, p0 ? Bp : Bn, k, part, v0);
+                P::template pair<COUNT>(me, s1, p1 ? BLp : BLn, p1 ? Bp : Bn, k, part, v1);
+            }
+        };
+        // Screen the tile's sources against this lane's target.  The append
+        // is branch-free: every candidate is written at position cnt and cnt
+        // advances only for survivors (slot cnt < NUC_CAP always exists).
+        // Lanes without a target get a threshold nothing passes.
+        const int thr = active ? k.thr16 : INT_MIN;
+        const bool wave_live = __ballot(active) != 0ull;
+        auto process = [&](int n, int kb) {
+            if (!wave_live)
+                return;
+            int cnt = 0;
+            constexpr int STEP = NUC_TPT * NUC_U;
+            const int nfull = (n / STEP) * STEP;
+            for (int j0 = 0; j0 < nfull; j0 += STEP) {
+                uint2 tv[NUC_U];
+#pragma unroll
+                for (int u = 0; u < NUC_U; ++u)
+                    tv[u] = tst[j0 + u * NUC_TPT + q];
+#pragma unroll
+                for (int u = 0; u < NUC_U; ++u) {
+                    const int j = j0 + u * NUC_TPT + q;
+                    lists[cnt * WG + tid] = (uint16_t)j;
+                    cnt += screen16(me_xy16, mef.z, tv[u]) < thr ? 1 : 0;
+                }
+                if (__ballot(cnt > NUC_CAP - NUC_U)) {
+                    drain(cnt, kb);
+                    cnt = 0;
+                }
+            }
+#pragma unroll
+            for (int u = 0; u < NUC_U; ++u) {
+                const int j = nfull + u * NUC_TPT + q;
+                if (j < n) {
+                    lists[cnt * WG + tid] = (uint16_t)j;
+                    cnt += screen16(me_xy16, mef.z, tst[j]) < thr ? 1 : 0;
+                }
+            }
+            drain(cnt, kb);
+            P::fold(acc, part);
+        };
+
+        for (int base = 0; base < total; base += WG) {
+            // one candidate per thread: locate, load, screen against the box
+            const int gidx = base + tid;
+            bool keep = false;
+            Lds e{};
+            uint3 f{};
+            if (gidx < total) {
+                int lo = 0, hi = 54;
+                while (hi - lo > 1) {
+                    const int mid = (lo + hi) >> 1;
+                    if (seg_off[mid] <= gidx)
+                        lo = mid;
+                    else
+                        hi = mid;
+                }
+                const typename P::Src sv = stg[seg_beg[lo] + (gidx - seg_off[lo])];
+                e = *reinterpret_cast<const Lds*>(&sv);
+                f = P::fixed(sv, k);
+                float g2 = 0.f;
+                const uint32_t fv[3] = {f.x, f.y, f.z};
+#pragma unroll
+                for (int a = 0; a < 3; ++a) {
+                    const int32_t rel = (int32_t)(fv[a] - bc[a]);
+                    const uint32_t mag = rel < 0 ? (uint32_t)(-(int64_t)rel) : (uint32_t)rel;
+                    const float gf = (float)(mag > bh[a] ? mag - bh[a] : 0u);
+                    g2 += gf * gf;
+                }
+                keep = g2 < k.thr_stage;
+            }
+            // block compaction in candidate order (protons stay first)
+            const unsigned long long m = __ballot(keep);
+            const unsigned long long mp = __ballot(keep && gidx < np_tot);
+            if (lane == 0) {
+                misc[6 + wave] = __popcll(m);
+                misc[10 + wave] = __popcll(mp);
+            }
+            __syncthreads();
+            int woff = 0, blk = 0, blkp = 0;
+            for (int w = 0; w < WG / 64; ++w) {
+                woff += w < wave ? misc[6 + w] : 0;
+                blk += misc[6 + w];
+                blkp += misc[10 + w];
+            }
+            if (tile_n + blk > T) {  // no room: use the tile as it is first
+                process(tile_n, tile_np);
+                tile_n = 0;
+                tile_np = 0;
+                __syncthreads();
+            }
+            if (keep) {
+                const int pos = tile_n + woff + __popcll(m & ((1ull << lane) - 1ull));
+                src[pos] = e;
+                tst[pos] = make_uint2((f.x >> 16) | (f.y & 0xffff0000u), f.z);
+            }
+            tile_n += blk;
+            tile_np += blkp;
+            __syncthreads();
+        }
+        if (tile_n > 0)
+            process(tile_n, tile_np);
+#pragma unroll
+        for (int m = 1; m < NUC_TPT; m <<= 1) {
+            acc.fx += __shfl_xor(acc.fx, m, NUC_TPT);
+            acc.fy += __shfl_xor(acc.fy, m, NUC_TPT);
+            acc.fz += __shfl_xor(acc.fz, m, NUC_TPT);
+            acc.e += __shfl_xor(acc.e, m, NUC_TPT);
+            if (COUNT)
+                acc.np += __shfl_xor(acc.np, m, NUC_TPT);
+        }
+    }
+
+    const double fsc = P::f_scale(k);
+    double ke = 0.0;
+    unsigned long long npairs = 0;
+    if (active && q == 0) {
+        if (COUNT)
+            npairs = acc.np - 1u;
+        double V = NUC ? acc.e - k.self_v : 0.0;
+        double Fx = acc.fx * fsc, Fy = acc.fy * fsc, Fz = acc.fz * fsc;
+        if (A.fnuc) {
+            A.fnuc[slot] = make_double4(Fx, Fy, Fz, V);
+        } else {
+            if (A.S > 0 && tprot) {
+                for (int s = 0; s < A.S; ++s) {
+                    const double4 cp = A.coul_part[(int64_t)s * A.Z + slot];
+                    Fx += cp.x;
+                    Fy += cp.y;
+                    Fz += cp.z;
+                    V += cp.w;
+                }
+            }
+            const int64_t id = A.perm[slot];
+            A.force[3 * id + 0] = Fx;
+            A.force[3 * id + 1] = Fy;
+            A.force[3 * id + 2] = Fz;
+            if (A.epot)
+                A.epot[id] = 0.5 * V;
+            if (!(isfinite(Fx) && isfinite(Fy) && isfinite(Fz)))
+                atomicOr(A.err, ERR_NONFINITE_FORCE);
+            if (A.vel) {
+                double vx = A.vel[3 * id + 0] + A.hdtm * Fx;
+                double vy = A.vel[3 * id + 1] + A.hdtm * Fy;
+                double vz = A.vel[3 * id + 2] + A.hdtm * Fz;
+                A.vel[3 * id + 0] = vx;
+                A.vel[3 * id + 1] = vy;
+                A.vel[3 * id + 2] = vz;
+                ke = 0.5 * A.mass * (vx * vx + vy * vy + vz * vz);
+            }
+        }
+    }
+    if (A.ke_part || COUNT) {
+        for (int m = 32; m >= 1; m >>= 1) {
+            ke += __shfl_xor(ke, m, 64);
+            if (COUNT)
+                npairs += __shfl_xor(npairs, m, 64);
+        }
+        if (lane == 0) {
+            ke_red[wave] = ke;
+            np_red[wave] = npairs;
         }
         __syncthreads();
         if (tid == 0) {

@@ -122,6 +122,43 @@ def test_forces_full_size_sampled(env, name, prec):
     assert np.all(np.isfinite(f.cpu().numpy()))
 
 
+@pytest.mark.parametrize("prec", [0, 1])
+def test_nuclear_variants_agree(env, prec):
+    """The dense cell-tile kernel and the screened + compacted kernel give the
+    same forces to rounding, and both match the oracle."""
+    B = env["B"]
+    st = env["I"].make_state(9000, 0.3, 0.06, 1.0, seed=61)
+    pos, sp = to_dev(env, st)
+    out = []
+    old = B.pasta_set_tuning(nuclear_variant=0)
+    try:
+        for v in (0, 1):
+            B.pasta_set_tuning(nuclear_variant=v)
+            out.append(B.pasta_forces(pos, sp, st["L"], precision=prec))
+    finally:
+        B.pasta_set_tuning(**old)
+    of, oe = env["O"].forces(st["pos"], st["species"], st["L"])
+    for f, e in out:
+        assert rel(f.cpu().numpy(), of) <= TOL_F[prec]
+        assert rel(e.cpu().numpy(), oe) <= TOL_E[prec]
+    d = rel(out[0][0].cpu().numpy(), out[1][0].cpu().numpy())
+    say(f"  variants differ by {d:.2e} (prec {prec})")
+    assert d <= (1e-14 if prec == 0 else 1e-6)
+
+
+def test_coulomb_split_override(env):
+    B = env["B"]
+    st = env["I"].workload("n3200_yp040_n0.040")
+    pos, sp = to_dev(env, st)
+    of, _ = env["O"].forces(st["pos"], st["species"], st["L"])
+    old = B.pasta_set_tuning(coulomb_splits=3)
+    try:
+        f, _ = B.pasta_forces(pos, sp, st["L"], precision=0)
+    finally:
+        B.pasta_set_tuning(**old)
+    assert rel(f.cpu().numpy(), of) <= TOL_F[0]
+
+
 def test_many_per_cell_multiple_tiles(env):
     """A dense small box: each cell's neighbourhood holds more sources than
     one LDS tile, exercising the multi-tile path."""
