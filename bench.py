@@ -77,6 +77,91 @@ def run_path(B, torch, st, precision, steps, warmup, timing):
                 coul_pairs=coul, kernel_times=kt, energies=en)
 
 
+def run_batch(B, torch, states, precision, mode, steps, warmup, spg=10):
+    """The 15-system grid advanced together (one persistent launch per step
+    for mode 0, one launch per phase for mode 1), from a captured hipGraph."""
+    import numpy as np
+    dev = torch.device("cuda:0")
+    pos = torch.tensor(np.concatenate([s["pos"] for s in states]), device=dev)
+    vel = torch.tensor(np.concatenate([s["vel"] for s in states]), device=dev)
+    sp = torch.tensor(np.concatenate([s["species"] for s in states]), device=dev)
+    b = B.Batch(pos, vel, sp, [s["n"] for s in states], [s["L"] for s in states],
+                [dict(dt=2.0, T=s["T"], rescale_every=100) for s in states],
+                precision=precision, mode=mode, steps_per_graph=spg)
+    b.step(warmup)
+    torch.cuda.synchronize()
+    nn, nc = b.pair_counts()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    b.step(steps)
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    info = b.info()
+    b.close()
+    return dict(seconds=dt, pairs_per_step=float(sum(nn) + sum(nc)), grid=info["grid"])
+
+
+def run_sequential(B, torch, states, precision, steps, warmup):
+    """The same systems one after another on the single-system path."""
+    dev = torch.device("cuda:0")
+    total, pairs = 0.0, 0.0
+    for st in states:
+        pos = torch.tensor(st["pos"], device=dev)
+        vel = torch.tensor(st["vel"], device=dev)
+        sp = torch.tensor(st["species"], device=dev)
+        sim = B.Sim(pos, vel, sp, st["L"], dt=2.0, T=st["T"], rescale_every=100,
+                    precision=precision)
+        sim.step(warmup)
+        torch.cuda.synchronize()
+        nn, nc = sim.pair_counts()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        sim.step(steps)
+        torch.cuda.synchronize()
+        total += time.perf_counter() - t0
+        pairs += nn + nc
+        sim.close()
+    return dict(seconds=total, pairs_per_step=pairs)
+
+
+def batched_section(B, torch, steps, warmup):
+    from paper_1412_8502_amd.inputs import batch_grid
+    states = batch_grid()
+    nsys = len(states)
+    out = {"systems": nsys, "N_total": int(sum(s["n"] for s in states)),
+           "N_per_system": [s["n"] for s in states],
+           "density_per_system": [round(s["density"], 5) for s in states],
+           "steps": steps,
+           "workload": "15 systems: Y_P in {0.05,0.10,0.20,0.30,0.40} x T in {0.5,0.75,1.0} MeV, "
+                       "N from {6400,12800,25600,51200} and n in [0.02,0.08] fm^-3 by seed 2000, "
+                       "dt=2 fm/c, rescale every 100 steps"}
+
+    def entry(r):
+        return {"ms_per_step": r["seconds"] / steps * 1e3,
+                "system_steps_per_s": nsys * steps / r["seconds"],
+                "pair_interactions_per_s": r["pairs_per_step"] * steps / r["seconds"]}
+    pers = run_batch(B, torch, states, B.PASTA_MIXED, 0, steps, warmup)
+    log(f"batched persistent: {pers['seconds'] / steps * 1e3:.4f} ms/step")
+    out["persistent_mixed"] = dict(entry(pers), grid=pers["grid"])
+    multi = run_batch(B, torch, states, B.PASTA_MIXED, 1, steps, warmup)
+    log(f"batched multi-kernel: {multi['seconds'] / steps * 1e3:.4f} ms/step")
+    out["multi_kernel_mixed"] = entry(multi)
+    seqm = run_sequential(B, torch, states, B.PASTA_MIXED, steps, warmup)
+    log(f"sequential mixed: {seqm['seconds'] / steps * 1e3:.4f} ms/step")
+    out["sequential_mixed"] = entry(seqm)
+    seq64 = run_sequential(B, torch, states, B.PASTA_FP64, max(50, steps // 5), warmup)
+    log(f"sequential fp64: {seq64['seconds'] / max(50, steps // 5) * 1e3:.4f} ms/step")
+    k64 = max(50, steps // 5)
+    out["sequential_fp64"] = {"ms_per_step": seq64["seconds"] / k64 * 1e3,
+                              "system_steps_per_s": nsys * k64 / seq64["seconds"],
+                              "pair_interactions_per_s": seq64["pairs_per_step"] * k64 / seq64["seconds"],
+                              "steps": k64}
+    best = min(out["persistent_mixed"]["ms_per_step"], out["multi_kernel_mixed"]["ms_per_step"])
+    out["speedup_vs_sequential_mixed"] = out["sequential_mixed"]["ms_per_step"] / best
+    out["speedup_vs_sequential_fp64"] = out["sequential_fp64"]["ms_per_step"] / best
+    return out
+
+
 def cpu_baseline(st, pairs_per_target_fn, budget_s=15.0):
     """The FP64 oracle (brute force over all sources, OpenMP over targets) on a
     bounded sample of targets of the same state."""
@@ -109,6 +194,8 @@ def main():
     ap.add_argument("--warmup", type=int, default=50)
     ap.add_argument("--fp64-steps", type=int, default=None)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--batch-steps", type=int, default=500)
+    ap.add_argument("--no-batch", action="store_true")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}); the multi-GPU "
@@ -124,17 +211,28 @@ def main():
     N, Z = st["n"], st["Z"]
     K, W = args.steps, args.warmup
     log(f"workload {WORKLOAD}: N={N} Z={Z} L={st['L']:.4f} steps={K} warmup={W}")
+    # autotune the pair kernels on this workload (not cached: measured here)
+    from paper_1412_8502_amd.autotune import tune
+    dev = torch.device("cuda:0")
+    tpos = torch.tensor(st["pos"], device=dev)
+    tsp = torch.tensor(st["species"], device=dev)
+    tuned64, _, table64 = tune(tpos, tsp, st["L"], B.PASTA_FP64, use_cache=False, apply=False)
+    tuned, _, table = tune(tpos, tsp, st["L"], B.PASTA_MIXED, use_cache=False, apply=True)
+    log(f"autotuned mixed: {tuned}  fp64: {tuned64}")
+    del tpos, tsp
     mixed = run_path(B, torch, st, B.PASTA_MIXED, K, W, timing=True)
     log(f"mixed: {mixed['seconds'] / K * 1e3:.4f} ms/step")
     # the dense cell-tile nuclear kernel, for comparison with the default
     # screened + compacted one
-    old = B.pasta_set_tuning(nuclear_variant=0)
+    old = B.pasta_set_tuning(nuclear_variant=0, coulomb_splits=0)
     dense = run_path(B, torch, st, B.PASTA_MIXED, max(20, K // 5), min(W, 20), timing=True)
     B.pasta_set_tuning(**old)
     kd = max(20, K // 5)
     log(f"mixed, dense nuclear kernel: {dense['seconds'] / kd * 1e3:.4f} ms/step")
     k64 = args.fp64_steps or max(20, K // 4)
+    B.pasta_set_tuning(**tuned64)
     fp64 = run_path(B, torch, st, B.PASTA_FP64, k64, min(W, 20), timing=True)
+    B.pasta_set_tuning(**tuned)
     log(f"fp64: {fp64['seconds'] / k64 * 1e3:.4f} ms/step")
 
     useful = mixed["nuc_pairs"] + mixed["coul_pairs"]
@@ -159,6 +257,10 @@ def main():
     else:
         roof = {"kernel": dom, "bound": "hbm", "achieved": None, "peak": 8000.0,
                 "unit": "GB/s", "frac": None, "traffic": None, "avg_launch_ms": round(avg_ms, 5)}
+
+    batched = None
+    if not args.no_batch:
+        batched = batched_section(B, torch, args.batch_steps, min(W, 20))
 
     cpu = None
     if not args.no_cpu_baseline:
@@ -195,12 +297,17 @@ def main():
                  "steps": k64,
                  "per_kernel_ms": {k: round(v[0] / k64, 5) for k, v in fp64["kernel_times"].items() if v[1]}},
         "mixed_over_fp64_speedup": fp64_ms / ms_step,
-        "nuclear_variant": B.pasta_get_tuning()["nuclear_variant"],
+        "autotuned": {"mixed": tuned, "fp64": tuned64,
+                      "mixed_candidates_ms": [[c["nuclear_variant"], c["coulomb_splits"], round(ms, 5)]
+                                              for c, ms in table],
+                      "fp64_candidates_ms": [[c["nuclear_variant"], c["coulomb_splits"], round(ms, 5)]
+                                             for c, ms in table64]},
         "dense_nuclear_variant": {"ms_per_step": dense["seconds"] / kd * 1e3,
                                   "nuclear_ms": dense["kernel_times"]["nuclear+kick"][0] / kd},
         "ms_per_step_with_events": mixed["seconds_with_events"] / K * 1e3,
         "per_kernel": per_kernel,
         "roofline": roof,
+        "batched": batched,
         "cpu_baseline": cpu,
     }
     print(json.dumps(out))

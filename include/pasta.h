@@ -107,6 +107,18 @@ typedef struct pasta_tuning {
 } pasta_tuning;
 int pasta_set_tuning(const pasta_tuning* t);
 int pasta_get_tuning(pasta_tuning* out);
+/* Autotuner: builds the cell list of the given state once, then times the
+ * Coulomb + nuclear kernels (reps evaluations each, HIP events) for every
+ * candidate setting -- nuclear variant {0, 1} x Coulomb splits {S/2, S, 2S}
+ * around the automatic S -- and returns the fastest in *h_best.  Optional
+ * outputs: h_cands[] / h_ms[] (capacity *h_ncand on entry, count on exit).
+ * Does not change the process-wide setting.  Synchronises. */
+int pasta_autotune_workspace(const pasta_potential* pot, int32_t precision, int64_t n, double L,
+                             size_t* h_bytes);
+int pasta_autotune(const pasta_potential* pot, int32_t precision, int64_t n, double L,
+                   const double* d_pos, const uint8_t* d_species, void* d_work,
+                   size_t work_bytes, void* stream, int32_t reps, pasta_tuning* h_best,
+                   double* h_ms, pasta_tuning* h_cands, int32_t* h_ncand);
 
 /* Fills *out with the paper's values (Table I, lambda = 10 fm, M = 939 MeV,
  * r_nuc = 11.5 fm, alpha hbar c = 1.4399645 MeV fm). */

@@ -9,7 +9,7 @@ synthetic initial states.
 """
 import importlib
 
-__all__ = ["binding", "inputs"]
+__all__ = ["binding", "inputs", "autotune"]
 
 
 def __getattr__(name):

@@ -1,0 +1,96 @@
+"""Autotuner front end: runs the library's pasta_autotune on a state, caches
+the choice per workload shape in a JSON file, and applies it with
+pasta_set_tuning.
+
+Shape key: precision, N rounded to a power of two, density to 0.01 fm^-3
+and proton fraction to 0.05 -- the quantities the pair-kernel costs depend on
+(Coulomb work ~ Z^2, nuclear candidates ~ N n).  The cache lives in
+$PASTA_TUNING_CACHE, else ~/.cache/pasta_md/tuning.json.
+"""
+from __future__ import annotations
+
+import ctypes
+import json
+import math
+import os
+
+import torch
+
+from . import binding as B
+
+
+def cache_path() -> str:
+    p = os.environ.get("PASTA_TUNING_CACHE")
+    if p:
+        return p
+    return os.path.join(os.path.expanduser("~"), ".cache", "pasta_md", "tuning.json")
+
+
+def shape_key(n: int, z: int, L: float, precision: int) -> str:
+    dens = n / L ** 3
+    yp = z / max(n, 1)
+    nb = 2 ** int(round(math.log2(max(n, 1))))
+    return f"p{precision}_n{nb}_d{round(dens, 2):.2f}_y{round(yp * 20) / 20:.2f}"
+
+
+def _load_cache(path):
+    try:
+        with open(path) as f:
+            return json.load(f)
+    except (OSError, ValueError):
+        return {}
+
+
+def _store_cache(path, data):
+    os.makedirs(os.path.dirname(path), exist_ok=True)
+    tmp = path + ".tmp%d" % os.getpid()
+    with open(tmp, "w") as f:
+        json.dump(data, f, indent=1, sort_keys=True)
+    os.replace(tmp, path)
+
+
+def pasta_autotune(pos, species, L: float, precision: int, reps: int = 3, pot=None,
+                   stream=None):
+    """Times every candidate setting on this state (see include/pasta.h).
+    Returns (best dict, [(candidate dict, ms), ...])."""
+    B._check_state(pos, species)
+    pot = pot or B.pasta_potential_paper()
+    n = pos.shape[0]
+    nb = ctypes.c_size_t()
+    B._check(B.lib.pasta_autotune_workspace(ctypes.byref(pot), precision, n, L,
+                                            ctypes.byref(nb)))
+    work = B._workspace(nb.value, pos.device)
+    best = B.pasta_tuning()
+    cap = 16
+    ms = (ctypes.c_double * cap)()
+    cands = (B.pasta_tuning * cap)()
+    ncand = ctypes.c_int32(cap)
+    B._check(B.lib.pasta_autotune(ctypes.byref(pot), precision, n, L, B._p(pos), B._p(species),
+                                  B._p(work), work.numel(), B._stream(stream), reps,
+                                  ctypes.byref(best), ms, cands, ctypes.byref(ncand)))
+    table = [(dict(nuclear_variant=cands[k].nuclear_variant,
+                   coulomb_splits=cands[k].coulomb_splits), ms[k])
+             for k in range(min(ncand.value, cap))]
+    return dict(nuclear_variant=best.nuclear_variant, coulomb_splits=best.coulomb_splits), table
+
+
+def tune(pos, species, L: float, precision: int, use_cache: bool = True, apply: bool = True):
+    """Cached autotune for this workload shape; applies the result
+    process-wide when `apply`.  Returns (setting, source, table)."""
+    n = pos.shape[0]
+    z = int((species == 1).sum().item())
+    key = shape_key(n, z, L, precision)
+    path = cache_path()
+    data = _load_cache(path) if use_cache else {}
+    table = None
+    if key in data:
+        best, source = data[key]["best"], "cache"
+    else:
+        best, table = pasta_autotune(pos, species, L, precision)
+        source = "measured"
+        if use_cache:
+            data[key] = {"best": best, "table": table}
+            _store_cache(path, data)
+    if apply:
+        B.pasta_set_tuning(**best)
+    return best, source, table

@@ -62,6 +62,9 @@ def _load():
     sig = {
         "pasta_potential_paper": (None, [pot]),
         "pasta_set_tuning": (ctypes.c_int, [P(pasta_tuning)]),
+        "pasta_autotune_workspace": (ctypes.c_int, [pot, i32, i64, d, P(sz)]),
+        "pasta_autotune": (ctypes.c_int, [pot, i32, i64, d, vp, vp, vp, sz, vp, i32,
+                                          P(pasta_tuning), vp, vp, P(i32)]),
         "pasta_get_tuning": (ctypes.c_int, [P(pasta_tuning)]),
         "pasta_last_error": (ctypes.c_char_p, []),
         "pasta_version": (ctypes.c_char_p, []),

@@ -358,6 +358,121 @@ extern "C" int pasta_forces(const pasta_potential* pot, int32_t precision, int32
     return read_err(w.err, s, "pasta_forces");
 }
 
+// -------------------------------------------------------------- tuning
+// Times the two pair kernels (Coulomb + nuclear with its epilogue) on the
+// given state for every candidate setting and keeps the fastest.  Candidates:
+// nuclear variant {dense, compacted} x Coulomb source splits {S/2, S, 2S}
+// around the automatic S (clamped to 1..32).  The cell list is built once.
+extern "C" int pasta_autotune(const pasta_potential* pot, int32_t precision, int64_t n, double L,
+                              const double* d_pos, const uint8_t* d_species, void* d_work,
+                              size_t work_bytes, void* stream, int32_t reps, pasta_tuning* h_best,
+                              double* h_ms, pasta_tuning* h_cands, int32_t* h_ncand)
+{
+    PASTA_TRY(check_pot(pot));
+    if (n <= 0 || n > INT32_MAX - 1 || !d_pos || !d_species || !h_best || reps < 1 ||
+        !(L > 0.0) || !std::isfinite(L) || (precision != PASTA_FP64 && precision != PASTA_MIXED))
+        return fail(PASTA_EINVAL, "pasta_autotune: bad argument");
+    if (L < 2.0 * pot->r_nuc)
+        return fail(PASTA_EBOX, "pasta_autotune: L < 2 r_nuc");
+    size_t need = 0;
+    PASTA_TRY(pasta_forces_workspace(pot, precision, n, L, &need));
+    Carver cvn(nullptr);
+    const Grid g = make_grid(L, pot->r_nuc);
+    force_carve(cvn, nullptr, n, g.C, precision);
+    cvn.take<double>(4 * (size_t)n);  // scratch force + energy outputs
+    need = cvn.size();
+    PASTA_TRY(check_work(d_work, work_bytes, need, "pasta_autotune"));
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    ForceWork w;
+    Carver cv(d_work);
+    force_carve(cv, &w, n, g.C, precision);
+    double* f = cv.take<double>(3 * (size_t)n);
+    double* e = cv.take<double>((size_t)n);
+    PASTA_HIP(hipMemsetAsync(w.err, 0, sizeof(uint32_t), s));
+    cellbuf_zero(w.cb, g.C, s);
+    build_cells(d_pos, d_species, n, g, w, precision, s, nullptr);
+    int32_t Z = 0;
+    PASTA_HIP(hipMemcpyAsync(&Z, w.cb.start + g.C, sizeof(int32_t), hipMemcpyDeviceToHost, s));
+    PASTA_HIP(hipStreamSynchronize(s));
+
+    const pasta_tuning saved = g_tuning;
+    pasta_tuning auto_t = {1, 0};
+    g_tuning = auto_t;
+    const int S0 = Z > 0 ? coulomb_splits(Z) : 1;
+    std::vector<pasta_tuning> cands;
+    for (int v = 0; v <= 1; ++v) {
+        int last = -1;
+        for (int sc : {S0 / 2, S0, 2 * S0}) {
+            int sv = sc < 1 ? 1 : (sc > 32 ? 32 : sc);
+            if (sv == last)
+                continue;
+            last = sv;
+            cands.push_back({v, sv});
+        }
+    }
+    hipEvent_t e0, e1;
+    PASTA_HIP(hipEventCreate(&e0));
+    PASTA_HIP(hipEventCreate(&e1));
+    double best = 1e300;
+    int best_k = 0;
+    const PairParams pp = pair_params(pot, L);
+    KickArgs kick{nullptr, 0.0, pot->mass, nullptr};
+    int rc = PASTA_OK;
+    for (size_t c = 0; c < cands.size() && rc == PASTA_OK; ++c) {
+        g_tuning = cands[c];
+        // one untimed warm-up, then reps timed evaluations
+        eval_forces(precision, PASTA_TERM_ALL, w, g, n, Z, pp, f, e, kick, nullptr, s, nullptr);
+        if (hipEventRecord(e0, s) != hipSuccess) {
+            rc = fail(PASTA_EHIP, "hipEventRecord failed");
+            break;
+        }
+        for (int r = 0; r < reps; ++r)
+            eval_forces(precision, PASTA_TERM_ALL, w, g, n, Z, pp, f, e, kick, nullptr, s,
+                        nullptr);
+        float ms = 0.f;
+        if (hipEventRecord(e1, s) != hipSuccess || hipEventSynchronize(e1) != hipSuccess ||
+            hipEventElapsedTime(&ms, e0, e1) != hipSuccess) {
+            rc = fail(PASTA_EHIP, "event timing failed");
+            break;
+        }
+        const double per = ms / reps;
+        if (h_ms && h_ncand && (int)c < *h_ncand)
+            h_ms[c] = per;
+        if (h_cands && h_ncand && (int)c < *h_ncand)
+            h_cands[c] = cands[c];
+        if (per < best) {
+            best = per;
+            best_k = (int)c;
+        }
+    }
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    g_tuning = saved;
+    if (rc != PASTA_OK)
+        return rc;
+    if (h_ncand)
+        *h_ncand = (int32_t)cands.size();
+    *h_best = cands[best_k];
+    PASTA_HIP(hipGetLastError());
+    return read_err(w.err, s, "pasta_autotune");
+}
+
+extern "C" int pasta_autotune_workspace(const pasta_potential* pot, int32_t precision, int64_t n,
+                                        double L, size_t* h_bytes)
+{
+    PASTA_TRY(check_pot(pot));
+    if (!h_bytes || n < 0 || !(L > 0.0) || !std::isfinite(L) ||
+        (precision != PASTA_FP64 && precision != PASTA_MIXED))
+        return fail(PASTA_EINVAL, "pasta_autotune_workspace: bad argument");
+    const Grid g = make_grid(L, pot->r_nuc);
+    Carver cv(nullptr);
+    force_carve(cv, nullptr, n, g.C, precision);
+    cv.take<double>(3 * (size_t)n);
+    cv.take<double>((size_t)n);
+    *h_bytes = cv.size();
+    return PASTA_OK;
+}
+
 // ------------------------------------------------------------------- a4
 struct pasta_sim {
     pasta_potential pot;

@@ -110,7 +110,12 @@ __device__ __forceinline__ Grid grid_at(double L, double r_cut)
 }
 
 // Bounded grid-wide barrier.  Returns false (and every later barrier returns
-// false at once) when the wait limit is hit.
+// false at once) when the wait limit is hit.  Memory ordering: one
+// agent-scope release fence per arriving workgroup before its (relaxed)
+// arrival, an acquire + release fence by the last arriver before it bumps the
+// generation, and one agent-scope acquire fence per workgroup after the
+// generation changed.  The spin itself uses relaxed loads, so waiting
+// workgroups do not keep invalidating caches that the laggards are using.
 __device__ bool grid_sync(const BatchDev& B, int* s_flag)
 {
     __syncthreads();
@@ -123,17 +128,18 @@ __device__ bool grid_sync(const BatchDev& B, int* s_flag)
             const unsigned gen =
                 __hip_atomic_load(&B.barrier[1], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
             __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
-            const unsigned arrived = __hip_atomic_fetch_add(&B.barrier[0], 1u, __ATOMIC_ACQ_REL,
+            const unsigned arrived = __hip_atomic_fetch_add(&B.barrier[0], 1u, __ATOMIC_RELAXED,
                                                             __HIP_MEMORY_SCOPE_AGENT) + 1u;
             if (arrived == nb) {
+                __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "agent");
                 __hip_atomic_store(&B.barrier[0], 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-                __hip_atomic_store(&B.barrier[1], gen + 1u, __ATOMIC_RELEASE,
+                __hip_atomic_store(&B.barrier[1], gen + 1u, __ATOMIC_RELAXED,
                                    __HIP_MEMORY_SCOPE_AGENT);
             } else {
                 long spins = 0;
-                while (__hip_atomic_load(&B.barrier[1], __ATOMIC_ACQUIRE,
+                while (__hip_atomic_load(&B.barrier[1], __ATOMIC_RELAXED,
                                          __HIP_MEMORY_SCOPE_AGENT) == gen) {
-                    __builtin_amdgcn_s_sleep(2);
+                    __builtin_amdgcn_s_sleep(1);
                     if (++spins > BARRIER_SPIN_LIMIT) {
                         atomicOr(B.err, ERR_BARRIER);
                         ok = 0;
@@ -146,8 +152,8 @@ __device__ bool grid_sync(const BatchDev& B, int* s_flag)
                         break;
                     }
                 }
+                __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
             }
-            __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
         }
         *s_flag = ok;
     }
@@ -834,8 +840,9 @@ int persistent_grid(unsigned* out)
     PASTA_HIP(hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ, k_batch_step<P>, BW, 0));
     if (occ < 1)
         return fail(PASTA_EHIP, "persistent batch kernel cannot be resident");
-    // at most two workgroups per CU: every workgroup must be resident at once
-    *out = (unsigned)ncu * (unsigned)(occ < 2 ? occ : 2);
+    // every workgroup must be resident at once: the occupancy the runtime
+    // reports, at most four per CU
+    *out = (unsigned)ncu * (unsigned)(occ < 4 ? occ : 4);
     return PASTA_OK;
 }
 

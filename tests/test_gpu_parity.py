@@ -399,3 +399,27 @@ def test_clusters_after_dynamics(env):
     sim.step(200)
     ref = check_clusters(env, pos.cpu().numpy(), st["species"], st["L"])
     say("  K", ref["nclusters"], "largest A", int(np.nonzero(ref["hist_A"])[0].max()))
+
+
+def test_autotuner(env, tmp_path, monkeypatch):
+    """The tuner times every candidate, returns the fastest, leaves the
+    process-wide setting alone, and its choice still matches the oracle."""
+    from paper_1412_8502_amd import autotune
+    monkeypatch.setenv("PASTA_TUNING_CACHE", str(tmp_path / "t.json"))
+    B = env["B"]
+    st = env["I"].workload("n3200_yp040_n0.040")
+    pos, sp = to_dev(env, st)
+    before = B.pasta_get_tuning()
+    best, table = autotune.pasta_autotune(pos, sp, st["L"], B.PASTA_MIXED)
+    assert B.pasta_get_tuning() == before
+    assert len(table) >= 4 and {0, 1} == {c["nuclear_variant"] for c, _ in table}
+    assert min(table, key=lambda r: r[1])[0] == best
+    got, source, _ = autotune.tune(pos, sp, st["L"], B.PASTA_MIXED, apply=True)
+    again, source2, _ = autotune.tune(pos, sp, st["L"], B.PASTA_MIXED, apply=True)
+    assert source == "measured" and source2 == "cache" and again == got
+    try:
+        f, _ = B.pasta_forces(pos, sp, st["L"], precision=B.PASTA_MIXED)
+    finally:
+        B.pasta_set_tuning(**before)
+    of, _ = env["O"].forces(st["pos"], st["species"], st["L"])
+    assert rel(f.cpu().numpy(), of) <= TOL_F[1]

@@ -1,0 +1,50 @@
+"""Host-side logic that needs no GPU: the seeded input generator, the
+autotuner's shape key and cache, and the batch grid recipe."""
+import json
+import os
+
+import numpy as np
+import pytest
+
+
+def test_make_state_recipe():
+    from paper_1412_8502_amd.inputs import make_state, box_side
+    st = make_state(3200, 0.40, 0.040, 1.0, seed=1000)
+    assert st["L"] == pytest.approx((3200 / 0.04) ** (1 / 3), rel=1e-15)
+    assert st["pos"].shape == (3200, 3) and st["pos"].dtype == np.float64
+    assert np.all((st["pos"] >= 0) & (st["pos"] < st["L"]))
+    assert st["Z"] == 1280 and st["species"][:1280].all() and not st["species"][1280:].any()
+    # Maxwell-Boltzmann: each component has variance T/M
+    assert st["vel"].var() == pytest.approx(1.0 / 939.0, rel=0.05)
+    again = make_state(3200, 0.40, 0.040, 1.0, seed=1000)
+    assert np.array_equal(st["pos"], again["pos"]) and np.array_equal(st["vel"], again["vel"])
+    assert box_side(51200, 0.08) == pytest.approx(86.17738760127535, rel=1e-14)
+
+
+def test_batch_grid_recipe():
+    from paper_1412_8502_amd.inputs import batch_grid
+    g = batch_grid()
+    assert len(g) == 15
+    assert sorted({(s["y_p"], s["T"]) for s in g}) == sorted(
+        (yp, T) for yp in (0.05, 0.10, 0.20, 0.30, 0.40) for T in (0.5, 0.75, 1.0))
+    for s in g:
+        assert s["n"] in (6400, 12800, 25600, 51200)
+        assert 0.02 <= s["density"] <= 0.08
+        assert s["L"] >= 2 * 11.5
+
+
+def test_autotune_shape_key_and_cache(tmp_path, monkeypatch):
+    pytest.importorskip("torch")
+    from paper_1412_8502_amd import build
+    if not os.path.exists(build.LIB):
+        build.build()
+    from paper_1412_8502_amd import autotune
+    monkeypatch.setenv("PASTA_TUNING_CACHE", str(tmp_path / "c" / "t.json"))
+    k1 = autotune.shape_key(51200, 10240, 86.17738760127535, 1)
+    k2 = autotune.shape_key(51000, 10200, 86.1, 1)
+    assert k1 == k2 == "p1_n65536_d0.08_y0.20"
+    assert autotune.shape_key(51200, 10240, 86.17738760127535, 0) != k1
+    path = autotune.cache_path()
+    autotune._store_cache(path, {k1: {"best": {"nuclear_variant": 1, "coulomb_splits": 8}}})
+    with open(path) as f:
+        assert json.load(f)[k1]["best"]["coulomb_splits"] == 8
