@@ -196,6 +196,9 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--batch-steps", type=int, default=500)
     ap.add_argument("--no-batch", action="store_true")
+    ap.add_argument("--copy-calibration-mib", type=int, default=0,
+                    help="run one plain device-to-device copy of this size first (a "
+                         "known-size kernel for scaling hardware byte counters)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}); the multi-GPU "
@@ -207,6 +210,14 @@ def main():
     from paper_1412_8502_amd import binding as B
     from paper_1412_8502_amd.inputs import workload
 
+    if args.copy_calibration_mib > 0:
+        nb = args.copy_calibration_mib << 20
+        a = torch.empty(nb, dtype=torch.uint8, device="cuda:0").fill_(1)
+        b = torch.empty_like(a)
+        torch.cuda.synchronize()
+        b.copy_(a)
+        torch.cuda.synchronize()
+        del a, b
     st = workload(WORKLOAD)
     N, Z = st["n"], st["Z"]
     K, W = args.steps, args.warmup
@@ -259,8 +270,16 @@ def main():
                 "unit": "GB/s", "frac": None, "traffic": None, "avg_launch_ms": round(avg_ms, 5)}
 
     batched = None
+    via_batch = None
     if not args.no_batch:
         batched = batched_section(B, torch, args.batch_steps, min(W, 20))
+        # the same N = 51 200 system through the batched machinery (one
+        # system, per-phase kernels, graph replay) for comparison
+        vb = run_batch(B, torch, [st], B.PASTA_MIXED, 1, K, W)
+        vb0 = run_batch(B, torch, [st], B.PASTA_MIXED, 0, K, W)
+        via_batch = {"multi_kernel_ms_per_step": vb["seconds"] / K * 1e3,
+                     "persistent_ms_per_step": vb0["seconds"] / K * 1e3}
+        log(f"single system via batch: {via_batch}")
 
     cpu = None
     if not args.no_cpu_baseline:
@@ -308,6 +327,7 @@ def main():
         "per_kernel": per_kernel,
         "roofline": roof,
         "batched": batched,
+        "single_system_via_batch_path": via_batch,
         "cpu_baseline": cpu,
     }
     print(json.dumps(out))

@@ -9,8 +9,8 @@
 // scheduling.
 //
 // Precision policies:
-//   Fp64Policy  -- double coordinates, nearest image d - L*rint(d/L), ROCm
-//                  device exp and rsqrt, double accumulation.
+//   Fp64Policy  -- double coordinates, nearest image d - L*rint(d/L), the
+//                  FP64 exp and rsqrt of fp64math.hpp, double accumulation.
 //   MixedPolicy -- 32-bit fixed-point coordinates (q = L/2^32 fm per unit):
 //                  the int32 difference of two coordinates is the
 //                  nearest-image separation in units of q, exactly; FP32 pair
@@ -21,6 +21,7 @@
 
 #include <climits>
 
+#include "fp64math.hpp"
 #include "internal.hpp"
 
 namespace pasta {
@@ -127,7 +128,7 @@ struct Fp64Policy {
         const bool in = valid && r2 < k.rc2;
         if (COUNT)
             p.np += in ? 1u : 0u;
-        double g = in ? exp(r2 * k.cg) : 0.0;
+        double g = in ? exp_nonpos(r2 * k.cg) : 0.0;
         double fs = g * fma(k.A2, g, B_L);
         p.fx = fma(fs, dx, p.fx);
         p.fy = fma(fs, dy, p.fy);
@@ -156,9 +157,9 @@ struct Fp64Policy {
         dz = fma(-k.L, rint(dz * k.invL), dz);
         double r2 = dx * dx + dy * dy + dz * dz;
         r2 = self ? 1e300 : r2;
-        double ir = rsqrt(r2);
+        double ir = rsqrt_fast(r2);
         double r = r2 * ir;
-        double v = k.ahc * exp(-r * k.inv_lambda) * ir;
+        double v = k.ahc * exp_nonpos(-r * k.inv_lambda) * ir;
         double fs = v * (ir + k.inv_lambda) * ir;
         fx = fma(fs, dx, fx);
         fy = fma(fs, dy, fy);
@@ -174,6 +175,7 @@ struct Fp64Policy {
                           (uint32_t)(uint64_t)(s.z * k.qscale));
     }
     static constexpr int CTILE = 512;  // sources per tile in the compacting kernel
+    static constexpr int STAGE_PER_THREAD = 1;  // candidates per thread per staging round
 };
 
 struct MixedPolicy {
@@ -250,6 +252,7 @@ struct MixedPolicy {
         return make_uint3(s.x, s.y, s.z);
     }
     static constexpr int CTILE = 768;
+    static constexpr int STAGE_PER_THREAD = 2;
 };
 
 // LDS bytes a work item needs (the caller provides at least this much,
@@ -267,7 +270,7 @@ template <class P>
 constexpr int nuclear_compact_lds_bytes()
 {
     return P::CTILE * ((int)sizeof(typename P::Lds) + 8) + NUC_CAP * WG * 2 + 54 * 4 +
-           55 * 4 + 16 * 4 + 4 * 8 + 4 * 8 + 64;
+           55 * 4 + 24 * 4 + 4 * 8 + 4 * 8 + 64;
 }
 
 // ============================================================ Coulomb ==
@@ -522,9 +525,9 @@ __device__ void nuclear_item_compact(const typename P::Src* __restrict__ stg, co
     uint16_t* lists = reinterpret_cast<uint16_t*>(tst + T);
     int* seg_beg = reinterpret_cast<int*>(lists + NUC_CAP * WG);
     int* seg_off = seg_beg + 54;
-    int* misc = seg_off + 55;  // [0..5] bbox lo/hi, [6..9] wave counts, [10..13] wave protons
+    int* misc = seg_off + 55;  // [0..5] box lo/hi, [6..13] kept counts, [14..21] kept protons
     double* ke_red = reinterpret_cast<double*>(
-        (reinterpret_cast<uintptr_t>(misc + 16) + 7) & ~uintptr_t(7));
+        (reinterpret_cast<uintptr_t>(misc + 24) + 7) & ~uintptr_t(7));
     unsigned long long* np_red = reinterpret_cast<unsigned long long*>(ke_red + WG / 64);
 
     const int c = A.items[2 * item + 0];
@@ -648,26 +651,48 @@ __device__ void nuclear_item_compact(const typename P::Src* __restrict__ stg, co
             P::fold(acc, part);
         };
 
-        for (int base = 0; base < total; base += WG) {
-            // one candidate per thread: locate, load, screen against the box
-            const int gidx = base + tid;
-            bool keep = false;
-            Lds e{};
-            uint3 f{};
-            if (gidx < total) {
-                int lo = 0, hi = 54;
-                while (hi - lo > 1) {
-                    const int mid = (lo + hi) >> 1;
-                    if (seg_off[mid] <= gidx)
-                        lo = mid;
-                    else
-                        hi = mid;
+        // Staging rounds of SP candidates per thread: locate (a binary search
+        // for the first, a short forward walk for the next), load, and keep
+        // the sources that can reach the targets' box, compacted in candidate
+        // order so protons stay first.
+        constexpr int SP = P::STAGE_PER_THREAD;
+        for (int base = 0; base < total; base += SP * WG) {
+            bool keep[SP];
+            Lds e[SP];
+            uint3 f[SP];
+            int gidx[SP], src_idx[SP];
+            int seg = 0;
+#pragma unroll
+            for (int u = 0; u < SP; ++u) {
+                gidx[u] = base + u * WG + tid;
+                src_idx[u] = -1;
+                if (gidx[u] < total) {
+                    if (u == 0) {
+                        int hi = 54;
+                        while (hi - seg > 1) {
+                            const int mid = (seg + hi) >> 1;
+                            if (seg_off[mid] <= gidx[u])
+                                seg = mid;
+                            else
+                                hi = mid;
+                        }
+                    } else {
+                        while (seg_off[seg + 1] <= gidx[u])
+                            ++seg;
+                    }
+                    src_idx[u] = seg_beg[seg] + (gidx[u] - seg_off[seg]);
                 }
-                const typename P::Src sv = stg[seg_beg[lo] + (gidx - seg_off[lo])];
-                e = *reinterpret_cast<const Lds*>(&sv);
-                f = P::fixed(sv, k);
+            }
+            typename P::Src sv[SP];
+#pragma unroll
+            for (int u = 0; u < SP; ++u)
+                sv[u] = stg[src_idx[u] >= 0 ? src_idx[u] : 0];
+#pragma unroll
+            for (int u = 0; u < SP; ++u) {
+                e[u] = *reinterpret_cast<const Lds*>(&sv[u]);
+                f[u] = P::fixed(sv[u], k);
                 float g2 = 0.f;
-                const uint32_t fv[3] = {f.x, f.y, f.z};
+                const uint32_t fv[3] = {f[u].x, f[u].y, f[u].z};
 #pragma unroll
                 for (int a = 0; a < 3; ++a) {
                     const int32_t rel = (int32_t)(fv[a] - bc[a]);
@@ -675,21 +700,32 @@ __device__ void nuclear_item_compact(const typename P::Src* __restrict__ stg, co
                     const float gf = (float)(mag > bh[a] ? mag - bh[a] : 0u);
                     g2 += gf * gf;
                 }
-                keep = g2 < k.thr_stage;
+                keep[u] = src_idx[u] >= 0 && g2 < k.thr_stage;
             }
-            // block compaction in candidate order (protons stay first)
-            const unsigned long long m = __ballot(keep);
-            const unsigned long long mp = __ballot(keep && gidx < np_tot);
-            if (lane == 0) {
-                misc[6 + wave] = __popcll(m);
-                misc[10 + wave] = __popcll(mp);
+            // block compaction in candidate order (u, thread)
+            unsigned long long m[SP];
+#pragma unroll
+            for (int u = 0; u < SP; ++u) {
+                m[u] = __ballot(keep[u]);
+                const unsigned long long mp = __ballot(keep[u] && gidx[u] < np_tot);
+                if (lane == 0) {
+                    misc[6 + u * 4 + wave] = __popcll(m[u]);
+                    misc[14 + u * 4 + wave] = __popcll(mp);
+                }
             }
             __syncthreads();
-            int woff = 0, blk = 0, blkp = 0;
-            for (int w = 0; w < WG / 64; ++w) {
-                woff += w < wave ? misc[6 + w] : 0;
-                blk += misc[6 + w];
-                blkp += misc[10 + w];
+            int blk = 0, blkp = 0;
+            int off[SP];
+#pragma unroll
+            for (int u = 0; u < SP; ++u) {
+                off[u] = blk;
+                for (int w = 0; w < WG / 64; ++w) {
+                    off[u] += w < wave ? misc[6 + u * 4 + w] : 0;
+                }
+                for (int w = 0; w < WG / 64; ++w) {
+                    blk += misc[6 + u * 4 + w];
+                    blkp += misc[14 + u * 4 + w];
+                }
             }
             if (tile_n + blk > T) {  // no room: use the tile as it is first
                 process(tile_n, tile_np);
@@ -697,10 +733,13 @@ __device__ void nuclear_item_compact(const typename P::Src* __restrict__ stg, co
                 tile_np = 0;
                 __syncthreads();
             }
-            if (keep) {
-                const int pos = tile_n + woff + __popcll(m & ((1ull << lane) - 1ull));
-                src[pos] = e;
-                tst[pos] = make_uint2((f.x >> 16) | (f.y & 0xffff0000u), f.z);
+#pragma unroll
+            for (int u = 0; u < SP; ++u) {
+                if (keep[u]) {
+                    const int pos = tile_n + off[u] + __popcll(m[u] & ((1ull << lane) - 1ull));
+                    src[pos] = e[u];
+                    tst[pos] = make_uint2((f[u].x >> 16) | (f[u].y & 0xffff0000u), f[u].z);
+                }
             }
             tile_n += blk;
             tile_np += blkp;

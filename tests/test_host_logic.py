@@ -48,3 +48,50 @@ def test_autotune_shape_key_and_cache(tmp_path, monkeypatch):
     autotune._store_cache(path, {k1: {"best": {"nuclear_variant": 1, "coulomb_splits": 8}}})
     with open(path) as f:
         assert json.load(f)[k1]["best"]["coulomb_splits"] == 8
+
+
+def _fp64math(tmp_path_factory):
+    import ctypes
+    import subprocess
+    here = os.path.dirname(os.path.abspath(__file__))
+    out = str(tmp_path_factory.mktemp("fp64math") / "libfp64math.so")
+    subprocess.check_call(["g++", "-O2", "-ffp-contract=off", "-shared", "-fPIC", "-o", out,
+                           os.path.join(here, "fp64math_host.cpp")])
+    lib = ctypes.CDLL(out)
+    lib.host_exp_nonpos.restype = ctypes.c_double
+    lib.host_exp_nonpos.argtypes = [ctypes.c_double]
+    lib.host_rsqrt_refine.restype = ctypes.c_double
+    lib.host_rsqrt_refine.argtypes = [ctypes.c_double, ctypes.c_double]
+    return lib
+
+
+def test_fp64_exp_accuracy(tmp_path_factory):
+    """The kernels' FP64 exp (Cody-Waite + Taylor) within 2 ulp of libm on
+    the range the potentials use, and exact at 0."""
+    import math
+    lib = _fp64math(tmp_path_factory)
+    rng = np.random.Generator(np.random.PCG64(5))
+    xs = np.concatenate([-rng.random(20000) * 60.0, -rng.random(2000) * 700.0,
+                         [0.0, -1e-300, -0.5 * math.log(2), -math.log(2), -52.9, -700.0]])
+    worst = 0.0
+    for x in xs:
+        got, ref = lib.host_exp_nonpos(float(x)), math.exp(float(x))
+        worst = max(worst, abs(got - ref) / math.ulp(ref))
+    assert worst <= 2.0, worst
+    assert lib.host_exp_nonpos(0.0) == 1.0
+
+
+def test_fp64_rsqrt_refinement(tmp_path_factory):
+    """Two Newton steps take a single-precision-quality estimate to full
+    double precision (within 2 ulp of 1/sqrt)."""
+    import math
+    lib = _fp64math(tmp_path_factory)
+    rng = np.random.Generator(np.random.PCG64(6))
+    xs = np.exp(rng.uniform(-20, 20, 20000))
+    worst = 0.0
+    for x in xs:
+        y0 = float(np.float32(1.0 / math.sqrt(x)))  # a coarse estimate
+        got = lib.host_rsqrt_refine(float(x), y0)
+        ref = 1.0 / math.sqrt(x)
+        worst = max(worst, abs(got - ref) / math.ulp(ref))
+    assert worst <= 2.0, worst
