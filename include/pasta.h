@@ -100,17 +100,23 @@ typedef struct pasta_integrator {
  *   screen, survivors listed in LDS, exact arithmetic on listed pairs only;
  *   the default).  Both give the same forces to rounding.
  * coulomb_splits: number of source ranges per Coulomb target tile, 1..32;
- *   0 = automatic (about 2^19 / Z, at most 32). */
+ *   0 = automatic (about 2^19 / Z, at most 32).
+ * fused_forces: 0 = the Coulomb kernel, then the nuclear kernel whose
+ *   epilogue adds the Coulomb partials and applies the half kick; 1 = one
+ *   launch holding both kinds of work items (they share the GPU) followed by
+ *   a small combine + kick kernel. */
 typedef struct pasta_tuning {
     int32_t nuclear_variant;
     int32_t coulomb_splits;
+    int32_t fused_forces;
 } pasta_tuning;
 int pasta_set_tuning(const pasta_tuning* t);
 int pasta_get_tuning(pasta_tuning* out);
 /* Autotuner: builds the cell list of the given state once, then times the
  * Coulomb + nuclear kernels (reps evaluations each, HIP events) for every
  * candidate setting -- nuclear variant {0, 1} x Coulomb splits {S/2, S, 2S}
- * around the automatic S -- and returns the fastest in *h_best.  Optional
+ * around the automatic S x fused_forces {0, 1} -- and returns the fastest
+ * in *h_best.  Optional
  * outputs: h_cands[] / h_ms[] (capacity *h_ncand on entry, count on exit).
  * Does not change the process-wide setting.  Synchronises. */
 int pasta_autotune_workspace(const pasta_potential* pot, int32_t precision, int64_t n, double L,

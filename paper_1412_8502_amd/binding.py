@@ -41,7 +41,8 @@ class pasta_potential(ctypes.Structure):
 
 
 class pasta_tuning(ctypes.Structure):
-    _fields_ = [("nuclear_variant", ctypes.c_int32), ("coulomb_splits", ctypes.c_int32)]
+    _fields_ = [("nuclear_variant", ctypes.c_int32), ("coulomb_splits", ctypes.c_int32),
+                ("fused_forces", ctypes.c_int32)]
 
 
 class pasta_integrator(ctypes.Structure):
@@ -152,22 +153,23 @@ def pasta_potential_paper() -> pasta_potential:
     return p
 
 
-def pasta_set_tuning(nuclear_variant: int | None = None, coulomb_splits: int | None = None):
-    """Process-wide kernel choices (see pasta_tuning in include/pasta.h);
-    returns the previous setting as a dict."""
-    cur = pasta_tuning()
-    _check(lib.pasta_get_tuning(ctypes.byref(cur)))
-    old = dict(nuclear_variant=cur.nuclear_variant, coulomb_splits=cur.coulomb_splits)
-    new = pasta_tuning(old["nuclear_variant"] if nuclear_variant is None else nuclear_variant,
-                       old["coulomb_splits"] if coulomb_splits is None else coulomb_splits)
-    _check(lib.pasta_set_tuning(ctypes.byref(new)))
-    return old
-
-
 def pasta_get_tuning() -> dict:
     cur = pasta_tuning()
     _check(lib.pasta_get_tuning(ctypes.byref(cur)))
-    return dict(nuclear_variant=cur.nuclear_variant, coulomb_splits=cur.coulomb_splits)
+    return dict(nuclear_variant=cur.nuclear_variant, coulomb_splits=cur.coulomb_splits,
+                fused_forces=cur.fused_forces)
+
+
+def pasta_set_tuning(nuclear_variant: int | None = None, coulomb_splits: int | None = None,
+                     fused_forces: int | None = None):
+    """Process-wide kernel choices (see pasta_tuning in include/pasta.h);
+    returns the previous setting as a dict."""
+    old = pasta_get_tuning()
+    new = pasta_tuning(old["nuclear_variant"] if nuclear_variant is None else nuclear_variant,
+                       old["coulomb_splits"] if coulomb_splits is None else coulomb_splits,
+                       old["fused_forces"] if fused_forces is None else fused_forces)
+    _check(lib.pasta_set_tuning(ctypes.byref(new)))
+    return old
 
 
 def pasta_version() -> str:

@@ -204,6 +204,12 @@ static void eval_forces(int precision, int terms, const ForceWork& w, const Grid
                         int64_t Z, const PairParams& pp, double* force, double* epot,
                         const KickArgs& kick, uint64_t* pair_counter, hipStream_t s, Timer* t)
 {
+    if (g_tuning.fused_forces && (terms & PASTA_TERM_NUCLEAR)) {
+        launch_forces_fused(precision, w.fb, w.cb, g, n, Z, pp, true,
+                            (terms & PASTA_TERM_COULOMB) != 0, force, epot, kick, pair_counter,
+                            w.err, s, t);
+        return;
+    }
     int S = 0;
     if ((terms & PASTA_TERM_COULOMB) && Z > 0) {
         launch_coulomb(precision, w.fb, Z, pp, nullptr, s, t);
@@ -240,7 +246,7 @@ extern "C" void pasta_potential_paper(pasta_potential* out)
 extern "C" int pasta_set_tuning(const pasta_tuning* t)
 {
     if (!t || (t->nuclear_variant != 0 && t->nuclear_variant != 1) || t->coulomb_splits < 0 ||
-        t->coulomb_splits > 32)
+        t->coulomb_splits > 32 || (t->fused_forces != 0 && t->fused_forces != 1))
         return fail(PASTA_EINVAL, "pasta_set_tuning: bad argument");
     g_tuning = *t;
     return PASTA_OK;
@@ -258,7 +264,7 @@ extern "C" const char* pasta_kernel_class_name(int32_t k)
 {
     static const char* names[PASTA_KERNEL_CLASSES] = {
         "drift+bin", "scan", "scatter", "rank+stage", "coulomb", "nuclear+kick", "thermostat",
-        "other"};
+        "combine+kick"};
     return (k >= 0 && k < PASTA_KERNEL_CLASSES) ? names[k] : "?";
 }
 
@@ -396,20 +402,21 @@ extern "C" int pasta_autotune(const pasta_potential* pot, int32_t precision, int
     PASTA_HIP(hipStreamSynchronize(s));
 
     const pasta_tuning saved = g_tuning;
-    pasta_tuning auto_t = {1, 0};
+    pasta_tuning auto_t = {1, 0, 0};
     g_tuning = auto_t;
     const int S0 = Z > 0 ? coulomb_splits(Z) : 1;
     std::vector<pasta_tuning> cands;
-    for (int v = 0; v <= 1; ++v) {
-        int last = -1;
-        for (int sc : {S0 / 2, S0, 2 * S0}) {
-            int sv = sc < 1 ? 1 : (sc > 32 ? 32 : sc);
-            if (sv == last)
-                continue;
-            last = sv;
-            cands.push_back({v, sv});
+    for (int fused = 0; fused <= 1; ++fused)
+        for (int v = 0; v <= 1; ++v) {
+            int last = -1;
+            for (int sc : {S0 / 2, S0, 2 * S0}) {
+                int sv = sc < 1 ? 1 : (sc > 32 ? 32 : sc);
+                if (sv == last)
+                    continue;
+                last = sv;
+                cands.push_back({v, sv, fused});
+            }
         }
-    }
     hipEvent_t e0, e1;
     PASTA_HIP(hipEventCreate(&e0));
     PASTA_HIP(hipEventCreate(&e1));
@@ -646,7 +653,8 @@ extern "C" int pasta_sim_step(pasta_sim* sim, int64_t nsteps)
                     pair_params(&sim->pot, L_new), sim->force, sim->epot, kick, nullptr, s,
                     &sim->timer);
         if (thermo)
-            launch_thermostat(sim->vel, sim->n, sim->w.fb.ke_part, sim->w.cb.n_items,
+            launch_thermostat(sim->vel, sim->n, sim->w.fb.ke_part,
+                              g_tuning.fused_forces ? sim->w.fb.n_ke : sim->w.cb.n_items,
                               1.5 * (double)sim->n * gi.T, sim->w.scale, s, &sim->timer);
         sim->step = n0 + 1;
     }

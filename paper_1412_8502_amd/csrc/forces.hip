@@ -52,6 +52,89 @@ __global__ __launch_bounds__(WG) void k_nuclear_compact(const typename P::Src* _
     nuclear_item_compact<P, NUC, COUNT>(stg, A, k, blockIdx.x, lds);
 }
 
+// Fused form: blocks [0, item_max) are nuclear cell tiles (raw nuclear
+// force and energy per sorted slot), blocks after them Coulomb tiles.
+template <class P, bool COUNT>
+__global__ __launch_bounds__(WG) void k_forces_fused(const typename P::Src* __restrict__ stg,
+                                                     NucArgs A, const int32_t* __restrict__ n_items,
+                                                     int item_max, int nuc_variant, NucConsts k,
+                                                     int Z, int per_split, int coul_blocks,
+                                                     CoulConsts kc, double4* __restrict__ part)
+{
+    constexpr int a = coulomb_lds_bytes<P>(), b = nuclear_lds_bytes<P>(),
+                  c = nuclear_compact_lds_bytes<P>();
+    constexpr int m0 = a > b ? a : b;
+    __shared__ __align__(16) char lds[m0 > c ? m0 : c];
+    const int g = blockIdx.x;
+    if (g < item_max) {
+        if (g >= *n_items)
+            return;
+        if (nuc_variant == 1)
+            nuclear_item_compact<P, true, COUNT>(stg, A, k, g, lds);
+        else
+            nuclear_item<P, true, COUNT>(stg, A, k, g, lds);
+    } else {
+        const int h = g - item_max;
+        coulomb_item<P>(stg, Z, per_split, kc, part, h % coul_blocks, h / coul_blocks, lds);
+    }
+}
+
+// F = nuclear + Coulomb partials per sorted slot, written in caller order,
+// with the optional second half kick and per-block kinetic energy.
+__global__ __launch_bounds__(WG) void k_combine(const double4* __restrict__ fnuc,
+                                                const double4* __restrict__ part, int S, int Z,
+                                                const int32_t* __restrict__ perm, int64_t n,
+                                                double* __restrict__ force,
+                                                double* __restrict__ epot, double* vel, double hdtm,
+                                                double mass, double* __restrict__ ke_part,
+                                                int32_t* __restrict__ n_ke, uint32_t* err)
+{
+    __shared__ double red[WG / 64];
+    const int64_t sl = (int64_t)blockIdx.x * WG + threadIdx.x;
+    double ke = 0.0;
+    if (sl < n) {
+        const double4 fn = fnuc[sl];
+        double Fx = fn.x, Fy = fn.y, Fz = fn.z, V = fn.w;
+        if (sl < Z) {
+            for (int k = 0; k < S; ++k) {
+                const double4 cp = part[(int64_t)k * Z + sl];
+                Fx += cp.x;
+                Fy += cp.y;
+                Fz += cp.z;
+                V += cp.w;
+            }
+        }
+        const int64_t id = perm[sl];
+        force[3 * id + 0] = Fx;
+        force[3 * id + 1] = Fy;
+        force[3 * id + 2] = Fz;
+        if (epot)
+            epot[id] = 0.5 * V;
+        if (!(isfinite(Fx) && isfinite(Fy) && isfinite(Fz)))
+            atomicOr(err, ERR_NONFINITE_FORCE);
+        if (vel) {
+            const double vx = vel[3 * id + 0] + hdtm * Fx, vy = vel[3 * id + 1] + hdtm * Fy,
+                         vz = vel[3 * id + 2] + hdtm * Fz;
+            vel[3 * id + 0] = vx;
+            vel[3 * id + 1] = vy;
+            vel[3 * id + 2] = vz;
+            ke = 0.5 * mass * (vx * vx + vy * vy + vz * vz);
+        }
+    }
+    if (ke_part) {
+        for (int m = 32; m >= 1; m >>= 1)
+            ke += __shfl_xor(ke, m, 64);
+        if ((threadIdx.x & 63) == 0)
+            red[threadIdx.x >> 6] = ke;
+        __syncthreads();
+        if (threadIdx.x == 0) {
+            ke_part[blockIdx.x] = ((red[0] + red[1]) + red[2]) + red[3];
+            if (blockIdx.x == 0)
+                *n_ke = (int32_t)gridDim.x;
+        }
+    }
+}
+
 template <class P>
 void nuclear_dispatch(const typename P::Src* stg, const NucArgs& a, const int32_t* n_items,
                       const NucConsts& k, bool nuc, bool count, int variant, unsigned grid,
@@ -86,7 +169,62 @@ int coulomb_splits(int64_t Z)
     return (int)s;
 }
 
-pasta_tuning g_tuning = {1, 0};
+pasta_tuning g_tuning = {1, 0, 1};
+
+void launch_forces_fused(int precision, const ForceBuf& fb, const CellBuf& cb, const Grid& g,
+                         int64_t n, int64_t Z, const PairParams& pp, bool with_nuclear_terms,
+                         bool with_coulomb, double* force, double* epot, const KickArgs& kick,
+                         uint64_t* pair_counter, uint32_t* err, hipStream_t s, Timer* t)
+{
+    const NucConsts k = make_nuc_consts(pp);
+    const CoulConsts kc = make_coul_consts(pp);
+    const int S = (with_coulomb && Z > 0) ? coulomb_splits(Z) : 0;
+    const int per = S ? (int)((Z + S - 1) / S) : 0;
+    const int coul_blocks = S ? (int)((Z + WG - 1) / WG) : 0;
+    NucArgs a{};
+    a.start = cb.start;
+    a.items = cb.items;
+    a.perm = cb.perm;
+    a.nc = g.nc;
+    a.C = g.C;
+    a.Z = (int)Z;
+    a.pairs = reinterpret_cast<unsigned long long*>(pair_counter);
+    a.err = err;
+    a.fnuc = fb.fnuc;
+    (void)with_nuclear_terms;  // the fused form always carries the nuclear terms
+    const int item_max = (int)cb.item_max;
+    const unsigned grid = (unsigned)(item_max + coul_blocks * S);
+    const bool count = pair_counter != nullptr;
+    const int variant = g_tuning.nuclear_variant;
+    timer_begin(t, KC_NUCLEAR, s);
+    if (grid > 0) {
+        if (precision == PASTA_FP64) {
+            if (count)
+                k_forces_fused<Fp64Policy, true><<<grid, WG, 0, s>>>(
+                    fb.stg64, a, cb.n_items, item_max, variant, k, (int)Z, per, coul_blocks, kc,
+                    fb.coul_part);
+            else
+                k_forces_fused<Fp64Policy, false><<<grid, WG, 0, s>>>(
+                    fb.stg64, a, cb.n_items, item_max, variant, k, (int)Z, per, coul_blocks, kc,
+                    fb.coul_part);
+        } else {
+            if (count)
+                k_forces_fused<MixedPolicy, true><<<grid, WG, 0, s>>>(
+                    fb.stgq, a, cb.n_items, item_max, variant, k, (int)Z, per, coul_blocks, kc,
+                    fb.coul_part);
+            else
+                k_forces_fused<MixedPolicy, false><<<grid, WG, 0, s>>>(
+                    fb.stgq, a, cb.n_items, item_max, variant, k, (int)Z, per, coul_blocks, kc,
+                    fb.coul_part);
+        }
+    }
+    timer_end(t, KC_NUCLEAR, s);
+    timer_begin(t, KC_COMBINE, s);
+    k_combine<<<(unsigned)((n + WG - 1) / WG), WG, 0, s>>>(
+        fb.fnuc, fb.coul_part, S, (int)Z, cb.perm, n, force, epot, kick.vel, kick.hdtm,
+        kick.mass, kick.ke_part, fb.n_ke, err);
+    timer_end(t, KC_COMBINE, s);
+}
 
 size_t forcebuf_carve(Carver& cv, ForceBuf* out, int64_t n, int64_t item_max, int precision)
 {
@@ -96,7 +234,9 @@ size_t forcebuf_carve(Carver& cv, ForceBuf* out, int64_t n, int64_t item_max, in
     int64_t cm = 32 * n < 524288 ? 32 * n : 524288;
     fb.coul_max = cm > n ? cm : n;
     fb.coul_part = cv.take<double4>(fb.coul_max);
-    fb.ke_part = cv.take<double>(item_max);
+    fb.ke_part = cv.take<double>(item_max > (n + WG - 1) / WG ? item_max : (n + WG - 1) / WG);
+    fb.n_ke = cv.take<int32_t>(1);
+    fb.fnuc = cv.take<double4>(n);
     fb.pairs = cv.take<uint64_t>(2);
     if (out)
         *out = fb;

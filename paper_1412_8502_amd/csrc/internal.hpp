@@ -140,7 +140,7 @@ enum KernelClass : int {
     KC_COULOMB = 4,
     KC_NUCLEAR = 5,
     KC_THERMO = 6,
-    KC_OTHER = 7,
+    KC_COMBINE = 7,
 };
 
 // Launch timing hook: when non-null, brackets a launch with HIP events.
@@ -196,7 +196,9 @@ struct ForceBuf {
     Q4* stgq;           // [n] fixed-point staging (sorted)
     double4* coul_part; // [coul_max] partial Coulomb sums (fx, fy, fz, V)
     int64_t coul_max;
-    double* ke_part;    // [item_max]
+    double* ke_part;    // [item_max] kinetic-energy partials of the last kick
+    int32_t* n_ke;      // [1] number of valid ke_part entries (fused form)
+    double4* fnuc;      // [n] nuclear (F, V) per sorted slot (fused form)
     uint64_t* pairs;    // [2] diagnostic pair counters
 };
 int coulomb_splits(int64_t Z);
@@ -229,6 +231,14 @@ struct DriftArgs {
 };
 void launch_drift(const DriftArgs& a, const Grid& g, const CellBuf& cb, uint32_t* err,
                   hipStream_t s, Timer* t);
+// Fused form: one launch with every Coulomb tile and nuclear cell tile (the
+// nuclear items write fb.fnuc), then the combine kernel: F = nuclear +
+// Coulomb partials, E, the optional half kick and kinetic-energy partials
+// (count in *fb.n_ke).
+void launch_forces_fused(int precision, const ForceBuf& fb, const CellBuf& cb, const Grid& g,
+                         int64_t n, int64_t Z, const PairParams& pp, bool with_nuclear_terms,
+                         bool with_coulomb, double* force, double* epot, const KickArgs& kick,
+                         uint64_t* pair_counter, uint32_t* err, hipStream_t s, Timer* t);
 // Thermostat: reduce ke_part[0 .. *n_items) and scale velocities to
 // KE = 1.5 N T.  scale_out receives the factor.
 void launch_thermostat(double* vel, int64_t n, const double* ke_part, const int32_t* n_items,

@@ -130,20 +130,40 @@ def test_nuclear_variants_agree(env, prec):
     st = env["I"].make_state(9000, 0.3, 0.06, 1.0, seed=61)
     pos, sp = to_dev(env, st)
     out = []
-    old = B.pasta_set_tuning(nuclear_variant=0)
+    old = B.pasta_get_tuning()
     try:
-        for v in (0, 1):
-            B.pasta_set_tuning(nuclear_variant=v)
-            out.append(B.pasta_forces(pos, sp, st["L"], precision=prec))
+        for fused in (0, 1):
+            for v in (0, 1):
+                B.pasta_set_tuning(nuclear_variant=v, fused_forces=fused)
+                out.append(B.pasta_forces(pos, sp, st["L"], precision=prec))
     finally:
         B.pasta_set_tuning(**old)
     of, oe = env["O"].forces(st["pos"], st["species"], st["L"])
     for f, e in out:
         assert rel(f.cpu().numpy(), of) <= TOL_F[prec]
         assert rel(e.cpu().numpy(), oe) <= TOL_E[prec]
-    d = rel(out[0][0].cpu().numpy(), out[1][0].cpu().numpy())
-    say(f"  variants differ by {d:.2e} (prec {prec})")
-    assert d <= (1e-14 if prec == 0 else 1e-6)
+    for f, e in out[1:]:
+        d = rel(out[0][0].cpu().numpy(), f.cpu().numpy())
+        say(f"  forms differ by {d:.2e} (prec {prec})")
+        assert d <= (1e-14 if prec == 0 else 1e-6)
+
+
+@pytest.mark.parametrize("fused", [0, 1])
+def test_trajectory_both_forms(env, fused):
+    """The unfused (kick in the nuclear epilogue) and fused (combine kernel)
+    step forms both follow the oracle."""
+    B = env["B"]
+    st = env["I"].make_state(2500, 0.3, 0.05, 1.0, seed=71)
+    old = B.pasta_set_tuning(fused_forces=fused)
+    try:
+        sim, pos, vel = make_sim(env, st, dt=2.0, T=1.0, rescale_every=4, precision=0)
+        sim.step(9)
+    finally:
+        B.pasta_set_tuning(**old)
+    op, ov, oL, *_ = env["O"].run(st["pos"], st["vel"], st["species"], st["L"], 9, dt=2.0,
+                                  T=1.0, rescale_every=4)
+    assert np.abs(wrapped_diff(pos.cpu().numpy(), op, oL)).max() <= 1e-9
+    assert np.abs(vel.cpu().numpy() - ov).max() <= 1e-9
 
 
 def test_coulomb_split_override(env):
