@@ -228,16 +228,8 @@ __device__ int64_t block_exscan(const int32_t* v, int32_t* out, int64_t m, int64
     int64_t s = 0;
     for (int64_t k = b; k < e; ++k)
         s += v[k];
-    lds[tid] = s;
-    __syncthreads();
-    for (int off = 1; off < BW; off <<= 1) {
-        const int64_t t = tid >= off ? lds[tid - off] : 0;
-        __syncthreads();
-        lds[tid] += t;
-        __syncthreads();
-    }
-    int64_t run = lds[tid] - s;
-    const int64_t total = lds[BW - 1];
+    int64_t total = 0;
+    int64_t run = block_exclusive_scan(s, lds, &total);
     for (int64_t k = b; k < e; ++k) {
         const int32_t c = v[k];
         out[k] = (int32_t)run;

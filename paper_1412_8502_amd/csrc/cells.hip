@@ -41,9 +41,10 @@ __global__ __launch_bounds__(256) void k_bin_count(const double* __restrict__ po
 }
 
 constexpr int SCAN_THREADS = 1024;
+static_assert(SCAN_THREADS <= 64 * 63, "wave totals must fit the LDS scratch");
 
-// Exclusive scan of v[0..m) (per-thread contiguous runs + LDS scan of the
-// run totals).  Returns the grand total to every thread.
+// Exclusive scan of v[0..m) (per-thread contiguous runs + the workgroup scan
+// of the run totals).  Returns the grand total to every thread.
 __device__ int64_t block_scan_runs(const int32_t* v, int32_t* out, int64_t m,
                                    int64_t* lds)
 {
@@ -53,18 +54,10 @@ __device__ int64_t block_scan_runs(const int32_t* v, int32_t* out, int64_t m,
     int64_t s = 0;
     for (int64_t k = b; k < e; ++k)
         s += v[k];
-    lds[tid] = s;
-    __syncthreads();
-    for (int off = 1; off < SCAN_THREADS; off <<= 1) {
-        int64_t t = tid >= off ? lds[tid - off] : 0;
-        __syncthreads();
-        lds[tid] += t;
-        __syncthreads();
-    }
-    int64_t run = lds[tid] - s;  // exclusive prefix of this thread's run
-    int64_t total = lds[SCAN_THREADS - 1];
+    int64_t total = 0;
+    int64_t run = block_exclusive_scan(s, lds, &total);
     for (int64_t k = b; k < e; ++k) {
-        int32_t c = v[k];
+        const int32_t c = v[k];
         out[k] = (int32_t)run;
         run += c;
     }

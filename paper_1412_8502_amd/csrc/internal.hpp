@@ -124,6 +124,45 @@ __device__ inline int wave_aggregated_add(int32_t* counters, int bin)
     return result;
 }
 
+// Exclusive prefix of one int64 per thread over the workgroup: a shuffle
+// scan inside each wavefront, the wavefront totals scanned by the first
+// wavefront through LDS (three barriers).  lds needs 64 entries.  Returns
+// the prefix; *total gets the workgroup sum.
+__device__ inline int64_t block_exclusive_scan(int64_t x, int64_t* lds, int64_t* total)
+{
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    const int nw = (blockDim.x + 63) >> 6;
+    int64_t inc = x;
+#pragma unroll
+    for (int off = 1; off < 64; off <<= 1) {
+        const int64_t y = __shfl_up(inc, off, 64);
+        if (lane >= off)
+            inc += y;
+    }
+    if (lane == 63)
+        lds[wave] = inc;
+    __syncthreads();
+    if (wave == 0) {
+        int64_t t = lane < nw ? lds[lane] : 0;
+        int64_t ti = t;
+#pragma unroll
+        for (int off = 1; off < 64; off <<= 1) {
+            const int64_t y = __shfl_up(ti, off, 64);
+            if (lane >= off)
+                ti += y;
+        }
+        if (lane < nw)
+            lds[lane] = ti - t;  // exclusive prefix of the wave totals
+        if (lane == nw - 1)
+            lds[63] = ti;
+    }
+    __syncthreads();
+    const int64_t pre = lds[wave] + inc - x;
+    *total = lds[63];
+    __syncthreads();
+    return pre;
+}
+
 // ------------------------------------------------------ staging formats
 // FP64 staging: x, y, z in fm, w unused.
 // MIXED staging: x, y, z as 32-bit fixed point (x/L * 2^32), w = species.
