@@ -94,21 +94,41 @@ typedef struct pasta_integrator {
                                 (the paper); 1: x *= L_{n+1}/L_n (variant) */
 } pasta_integrator;
 
-/* Kernel choices, process-wide; read at every launch.
+/* Kernel choices, process-wide; read at every launch (the list settings:
+ * when a workspace is sized and when a simulation is created).
  * nuclear_variant: 0 = dense cell tiles (every candidate pair through the
  *   full pair arithmetic); 1 = screened + compacted (a conservative 16-bit
  *   screen, survivors listed in LDS, exact arithmetic on listed pairs only;
- *   the default).  Both give the same forces to rounding.
+ *   the default); 2 = neighbour lists with a halo (Sec. II.B.1): each target
+ *   lists the sources within r_nuc + list_skin, built from cells at least
+ *   that wide; the forces read only the lists; a simulation rebuilds cells
+ *   and lists, all at once, only in steps where
+ *       2 max_i |u_i| + sqrt(3) |L - L_build| >= list_skin
+ *   (u_i = nearest-image displacement since the last build), the condition
+ *   under which a pair now inside r_nuc may have been outside r_nuc +
+ *   list_skin at the build.  The decision is taken on the device.  If the
+ *   list memory runs out, the forces fall back to the screened cell sweep
+ *   over the cells of the last build until the next build.  One-shot
+ *   pasta_forces builds and uses the lists once.  The batched path treats
+ *   2 as 1.  All variants give the same forces to rounding.
  * coulomb_splits: number of source ranges per Coulomb target tile, 1..32;
  *   0 = automatic (about 2^19 / Z, at most 32).
  * fused_forces: 0 = the Coulomb kernel, then the nuclear kernel whose
  *   epilogue adds the Coulomb partials and applies the half kick; 1 = one
  *   launch holding both kinds of work items (they share the GPU) followed by
- *   a small combine + kick kernel. */
+ *   a small combine + kick kernel.
+ * reserved: must be 0.
+ * list_skin: the halo delta_r of variant 2, fm, in (0, 64] (default 2).
+ * list_pool_scale: list memory relative to the default sizing, in (0, 1000]
+ *   (default 1; the default holds 1.5 x the expected entries per lane at the
+ *   starting density plus a Poisson margin). */
 typedef struct pasta_tuning {
     int32_t nuclear_variant;
     int32_t coulomb_splits;
     int32_t fused_forces;
+    int32_t reserved;
+    double list_skin;
+    double list_pool_scale;
 } pasta_tuning;
 int pasta_set_tuning(const pasta_tuning* t);
 int pasta_get_tuning(pasta_tuning* out);
@@ -116,7 +136,9 @@ int pasta_get_tuning(pasta_tuning* out);
  * Coulomb + nuclear kernels (reps evaluations each, HIP events) for every
  * candidate setting -- nuclear variant {0, 1} x Coulomb splits {S/2, S, 2S}
  * around the automatic S x fused_forces {0, 1} -- and returns the fastest
- * in *h_best.  Optional
+ * in *h_best (the list fields copied from the current setting; the list
+ * form's cost depends on how often the lists are rebuilt, which a single
+ * state does not tell, so it is not a candidate).  Optional
  * outputs: h_cands[] / h_ms[] (capacity *h_ncand on entry, count on exit).
  * Does not change the process-wide setting.  Synchronises. */
 int pasta_autotune_workspace(const pasta_potential* pot, int32_t precision, int64_t n, double L,
@@ -156,8 +178,10 @@ int pasta_cell_list(int64_t n, double L, double r_cut, const double* d_pos,
  *   E_i = (1/2) sum_{j != i} V_ij               (sum_i E_i = total energy).
  * `terms` selects the nuclear and/or Coulomb parts.  d_force is [n][3]
  * MeV/fm, d_epot is [n] MeV (may be NULL).  Requires L >= 2 r_nuc.
- * Internally: a1 cell list with r_cut = r_nuc, the nuclear cell-tile
- * kernel, and the all-pairs screened-Coulomb tile kernel. */
+ * Internally: a1 cell list with r_cut = r_nuc (r_nuc + list_skin and the
+ * neighbour lists in the list form), the nuclear kernel, and the all-pairs
+ * screened-Coulomb tile kernel.  The workspace query and the call must see
+ * the same process-wide setting. */
 int pasta_forces_workspace(const pasta_potential* pot, int32_t precision, int64_t n,
                            double L, size_t* h_bytes);
 int pasta_forces(const pasta_potential* pot, int32_t precision, int32_t terms, int64_t n,
@@ -178,10 +202,15 @@ int pasta_forces(const pasta_potential* pot, int32_t precision, int32_t terms, i
  * always hold the state at the current step (caller order).  d_species
  * must stay valid and unchanged.  L_max bounds the largest box the run will
  * reach (it sizes the cell grid); a step that would exceed it fails with
- * PASTA_EBOX.  pasta_sim_create evaluates F at the starting state. */
+ * PASTA_EBOX.  L_start (workspace query) is the box side at the starting
+ * step: with the list form it sets the density the list memory is sized for
+ * (a simulation gives the list memory whatever the workspace holds beyond
+ * the rest, so a larger workspace means more list memory).
+ * pasta_sim_create evaluates F at the starting state. */
 typedef struct pasta_sim pasta_sim;
 int pasta_sim_workspace(const pasta_potential* pot, const pasta_integrator* integ,
-                        int32_t precision, int64_t n, double L_max, size_t* h_bytes);
+                        int32_t precision, int64_t n, double L_start, double L_max,
+                        size_t* h_bytes);
 int pasta_sim_create(const pasta_potential* pot, const pasta_integrator* integ,
                      int32_t precision, int64_t n, double L0, int64_t step0, double L_max,
                      double* d_pos, double* d_vel, const uint8_t* d_species, void* d_work,
@@ -207,10 +236,17 @@ int pasta_sim_set_state(pasta_sim* sim, const double* d_pos, const double* d_vel
  * every launch is bracketed by events; pasta_sim_kernel_times synchronises
  * and returns, per kernel class, the summed milliseconds and launch counts
  * since timing was switched on (arrays of PASTA_KERNEL_CLASSES entries). */
-#define PASTA_KERNEL_CLASSES 8
+#define PASTA_KERNEL_CLASSES 9
 int pasta_sim_set_timing(pasta_sim* sim, int32_t on);
 int pasta_sim_kernel_times(pasta_sim* sim, double* h_ms, int64_t* h_launches);
 const char* pasta_kernel_class_name(int32_t k);
+/* Neighbour-list statistics (zeros unless the simulation uses the list
+ * form).  Synchronises.  builds: list builds so far (the initial one
+ * included); overflows: builds that ran out of list memory; max_disp: max
+ * |u| (fm) at the last rebuild decision; rows_used / rows_capacity: list
+ * memory rows (256 entries each) taken by the last build / available. */
+int pasta_sim_list_stats(pasta_sim* sim, int64_t* h_builds, int64_t* h_overflows,
+                         double* h_max_disp, int64_t* h_rows_used, int64_t* h_rows_capacity);
 void pasta_sim_destroy(pasta_sim* sim);
 
 /* ------------------------------------------------------------------ a5 --

@@ -68,12 +68,10 @@ def pasta_autotune(pos, species, L: float, precision: int, reps: int = 3, pot=No
     B._check(B.lib.pasta_autotune(ctypes.byref(pot), precision, n, L, B._p(pos), B._p(species),
                                   B._p(work), work.numel(), B._stream(stream), reps,
                                   ctypes.byref(best), ms, cands, ctypes.byref(ncand)))
-    table = [(dict(nuclear_variant=cands[k].nuclear_variant,
-                   coulomb_splits=cands[k].coulomb_splits,
-                   fused_forces=cands[k].fused_forces), ms[k])
+    keys = ("nuclear_variant", "coulomb_splits", "fused_forces")
+    table = [({f: getattr(cands[k], f) for f in keys}, ms[k])
              for k in range(min(ncand.value, cap))]
-    return dict(nuclear_variant=best.nuclear_variant, coulomb_splits=best.coulomb_splits,
-                fused_forces=best.fused_forces), table
+    return {f: getattr(best, f) for f in keys}, table
 
 
 def tune(pos, species, L: float, precision: int, use_cache: bool = True, apply: bool = True):

@@ -24,7 +24,7 @@ PASTA_MIXED = 1
 PASTA_TERM_NUCLEAR = 1
 PASTA_TERM_COULOMB = 2
 PASTA_TERM_ALL = 3
-PASTA_KERNEL_CLASSES = 8
+PASTA_KERNEL_CLASSES = 9
 ERRORS = {-1: "PASTA_EINVAL", -2: "PASTA_EBOX", -3: "PASTA_EWORKSPACE", -4: "PASTA_EHIP",
           -5: "PASTA_EDEVICE", -6: "PASTA_ENOMEM"}
 
@@ -42,7 +42,12 @@ class pasta_potential(ctypes.Structure):
 
 class pasta_tuning(ctypes.Structure):
     _fields_ = [("nuclear_variant", ctypes.c_int32), ("coulomb_splits", ctypes.c_int32),
-                ("fused_forces", ctypes.c_int32)]
+                ("fused_forces", ctypes.c_int32), ("reserved", ctypes.c_int32),
+                ("list_skin", ctypes.c_double), ("list_pool_scale", ctypes.c_double)]
+
+
+TUNING_FIELDS = ("nuclear_variant", "coulomb_splits", "fused_forces", "list_skin",
+                 "list_pool_scale")
 
 
 class pasta_integrator(ctypes.Structure):
@@ -73,7 +78,7 @@ def _load():
         "pasta_cell_list": (ctypes.c_int, [i64, d, d, vp, vp, vp, vp, P(i32), vp, sz, vp]),
         "pasta_forces_workspace": (ctypes.c_int, [pot, i32, i64, d, P(sz)]),
         "pasta_forces": (ctypes.c_int, [pot, i32, i32, i64, d, vp, vp, vp, vp, vp, sz, vp]),
-        "pasta_sim_workspace": (ctypes.c_int, [pot, integ, i32, i64, d, P(sz)]),
+        "pasta_sim_workspace": (ctypes.c_int, [pot, integ, i32, i64, d, d, P(sz)]),
         "pasta_sim_create": (ctypes.c_int, [pot, integ, i32, i64, d, i64, d, vp, vp, vp, vp,
                                             sz, vp, P(vp)]),
         "pasta_sim_step": (ctypes.c_int, [vp, i64]),
@@ -85,6 +90,7 @@ def _load():
         "pasta_sim_set_timing": (ctypes.c_int, [vp, i32]),
         "pasta_sim_kernel_times": (ctypes.c_int, [vp, vp, vp]),
         "pasta_kernel_class_name": (ctypes.c_char_p, [i32]),
+        "pasta_sim_list_stats": (ctypes.c_int, [vp, P(i64), P(i64), P(d), P(i64), P(i64)]),
         "pasta_sim_destroy": (None, [vp]),
         "pasta_cluster_workspace": (ctypes.c_int, [i64, d, d, d, P(sz)]),
         "pasta_batch_workspace": (ctypes.c_int, [pot, i32, i32, vp, vp, P(sz)]),
@@ -153,21 +159,30 @@ def pasta_potential_paper() -> pasta_potential:
     return p
 
 
+def tuning_dict(t: pasta_tuning) -> dict:
+    return {f: getattr(t, f) for f in TUNING_FIELDS}
+
+
 def pasta_get_tuning() -> dict:
     cur = pasta_tuning()
     _check(lib.pasta_get_tuning(ctypes.byref(cur)))
-    return dict(nuclear_variant=cur.nuclear_variant, coulomb_splits=cur.coulomb_splits,
-                fused_forces=cur.fused_forces)
+    return tuning_dict(cur)
 
 
-def pasta_set_tuning(nuclear_variant: int | None = None, coulomb_splits: int | None = None,
-                     fused_forces: int | None = None):
-    """Process-wide kernel choices (see pasta_tuning in include/pasta.h);
-    returns the previous setting as a dict."""
+def pasta_set_tuning(**kw):
+    """Process-wide kernel choices (see pasta_tuning in include/pasta.h):
+    any of nuclear_variant, coulomb_splits, fused_forces, list_skin,
+    list_pool_scale; the others keep their values.  Returns the previous
+    setting as a dict."""
+    bad = set(kw) - set(TUNING_FIELDS)
+    if bad:
+        raise TypeError(f"unknown tuning fields {sorted(bad)}")
     old = pasta_get_tuning()
-    new = pasta_tuning(old["nuclear_variant"] if nuclear_variant is None else nuclear_variant,
-                       old["coulomb_splits"] if coulomb_splits is None else coulomb_splits,
-                       old["fused_forces"] if fused_forces is None else fused_forces)
+    merged = dict(old)
+    merged.update({k: v for k, v in kw.items() if v is not None})
+    new = pasta_tuning()
+    for f in TUNING_FIELDS:
+        setattr(new, f, merged[f])
     _check(lib.pasta_set_tuning(ctypes.byref(new)))
     return old
 
@@ -239,9 +254,11 @@ class Sim:
         self.stream = stream
         if L_max is None:
             L_max = L0
+        L_start = L0 * (1.0 + xi_dot * step0 * dt)
         nb = ctypes.c_size_t()
         _check(lib.pasta_sim_workspace(ctypes.byref(self.pot), ctypes.byref(self.integ),
-                                       precision, self.n, L_max, ctypes.byref(nb)))
+                                       precision, self.n, L_start, max(L_max, L_start),
+                                       ctypes.byref(nb)))
         self.work = _workspace(nb.value, pos.device)
         self.handle = ctypes.c_void_p()
         _check(lib.pasta_sim_create(ctypes.byref(self.pot), ctypes.byref(self.integ), precision,
@@ -280,6 +297,15 @@ class Sim:
 
     def set_timing(self, on: bool):
         _check(lib.pasta_sim_set_timing(self.handle, int(bool(on))))
+
+    def list_stats(self) -> dict:
+        """Neighbour-list counters (all zero unless the list form is on)."""
+        b, o, r, c = ctypes.c_int64(), ctypes.c_int64(), ctypes.c_int64(), ctypes.c_int64()
+        d = ctypes.c_double()
+        _check(lib.pasta_sim_list_stats(self.handle, ctypes.byref(b), ctypes.byref(o),
+                                        ctypes.byref(d), ctypes.byref(r), ctypes.byref(c)))
+        return dict(builds=b.value, overflows=o.value, max_disp=d.value, rows_used=r.value,
+                    rows_capacity=c.value)
 
     def kernel_times(self):
         ms = (ctypes.c_double * PASTA_KERNEL_CLASSES)()

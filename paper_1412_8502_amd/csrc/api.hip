@@ -148,23 +148,59 @@ static PairParams pair_params(const pasta_potential* p, double L)
     return pp;
 }
 
-// Shared layout of the force workspace (a1 + a2 + a3).
+// Neighbour-list settings of a workspace: off, or on with halo `skin` and
+// pool sized for box sides down to L_min.
+struct ListCfg {
+    bool on = false;
+    double skin = 0.0;
+    double L_min = 0.0;
+    double pool_scale = 1.0;
+};
+static ListCfg list_cfg(int terms, double L_min)
+{
+    ListCfg c;
+    c.on = g_tuning.nuclear_variant == 2 && (terms & PASTA_TERM_NUCLEAR);
+    c.skin = g_tuning.list_skin;
+    c.L_min = L_min;
+    c.pool_scale = g_tuning.list_pool_scale;
+    return c;
+}
+// cell width of the grid: r_nuc, or r_nuc + skin for the list form
+static double cell_cut(const pasta_potential* p, const ListCfg& lc)
+{
+    return lc.on ? p->r_nuc + lc.skin : p->r_nuc;
+}
+
+// Shared layout of the force workspace (a1 + a2 + a3 [+ lists]).
 struct ForceWork {
     CellBuf cb;
     ForceBuf fb;
+    ListBuf lb;
+    bool lists;
     uint32_t* err;
     double* red;  // [256] reduction partials
     double* scale;  // [2]
 };
-static size_t force_carve(Carver& cv, ForceWork* w, int64_t n, int C_max, int precision)
+static size_t force_carve(Carver& cv, ForceWork* w, int64_t n, int C_max, int precision,
+                          const pasta_potential* pot, const ListCfg& lc, int64_t pool_rows = -1)
 {
     ForceWork fw;
-    const int chunk = nuclear_chunk(precision);
+    const int chunk = nuclear_chunk(precision, lc.on);
     cellbuf_carve(cv, &fw.cb, n, C_max, chunk);
     forcebuf_carve(cv, &fw.fb, n, fw.cb.item_max, precision);
     fw.err = cv.take<uint32_t>(1);
     fw.red = cv.take<double>(256);
     fw.scale = cv.take<double>(2);
+    fw.lists = lc.on;
+    fw.lb = ListBuf{};
+    if (lc.on) {
+        const int64_t rows =
+            pool_rows > 0 ? pool_rows
+                          : list_pool_rows(n, lc.L_min, pot->r_nuc + lc.skin, fw.cb.item_max,
+                                           lc.pool_scale);
+        listbuf_carve(cv, &fw.lb, n, fw.cb.item_max, rows);
+        fw.lb.skin = lc.skin;
+    }
     if (w)
         *w = fw;
     return cv.size();
@@ -190,13 +226,20 @@ static int read_err(uint32_t* d_err, hipStream_t s, const char* who)
     return PASTA_OK;
 }
 
-// Build the cell list (+ staging) for positions at box side L and return Z.
+// Build the cell list (+ staging) for positions at box side L (grid g); in
+// the list form also the lists (a forced build: positions recorded in xb).
 static int build_cells(const double* pos, const uint8_t* species, int64_t n, const Grid& g,
-                       ForceWork& w, int precision, hipStream_t s, Timer* t)
+                       ForceWork& w, int precision, const PairParams& pp, hipStream_t s,
+                       Timer* t)
 {
     launch_bin_count(pos, species, n, g, w.cb, w.err, s, t);
-    launch_scan(w.cb, g.C, nuclear_chunk(precision), s, t);
-    launch_scatter_rank(pos, species, n, g, w.cb, w.fb.stg64, w.fb.stgq, s, t);
+    launch_scan(w.cb, g.C, nuclear_chunk(precision, w.lists), s, t);
+    launch_scatter_rank(pos, species, n, g, w.cb, w.fb.stg64, w.fb.stgq, s, t, false, nullptr,
+                        w.lists ? w.lb.xb : nullptr);
+    if (w.lists) {
+        launch_list_force_rebuild(w.lb, g, s);
+        launch_list_build(precision, w.fb, w.cb, g, w.lb, pp, s, t);
+    }
     return PASTA_OK;
 }
 
@@ -204,10 +247,11 @@ static void eval_forces(int precision, int terms, const ForceWork& w, const Grid
                         int64_t Z, const PairParams& pp, double* force, double* epot,
                         const KickArgs& kick, uint64_t* pair_counter, hipStream_t s, Timer* t)
 {
+    const ListBuf* lb = (w.lists && (terms & PASTA_TERM_NUCLEAR)) ? &w.lb : nullptr;
     if (g_tuning.fused_forces && (terms & PASTA_TERM_NUCLEAR)) {
         launch_forces_fused(precision, w.fb, w.cb, g, n, Z, pp, true,
                             (terms & PASTA_TERM_COULOMB) != 0, force, epot, kick, pair_counter,
-                            w.err, s, t);
+                            w.err, s, t, lb);
         return;
     }
     int S = 0;
@@ -216,7 +260,7 @@ static void eval_forces(int precision, int terms, const ForceWork& w, const Grid
         S = coulomb_splits(Z);
     }
     launch_nuclear(precision, w.fb, w.cb, g, n, Z, pp, (terms & PASTA_TERM_NUCLEAR) != 0, S,
-                   force, epot, kick, pair_counter, w.err, s, t);
+                   force, epot, kick, pair_counter, w.err, s, t, lb);
 }
 
 }  // namespace pasta
@@ -245,8 +289,10 @@ extern "C" void pasta_potential_paper(pasta_potential* out)
 
 extern "C" int pasta_set_tuning(const pasta_tuning* t)
 {
-    if (!t || (t->nuclear_variant != 0 && t->nuclear_variant != 1) || t->coulomb_splits < 0 ||
-        t->coulomb_splits > 32 || (t->fused_forces != 0 && t->fused_forces != 1))
+    if (!t || t->nuclear_variant < 0 || t->nuclear_variant > 2 || t->coulomb_splits < 0 ||
+        t->coulomb_splits > 32 || (t->fused_forces != 0 && t->fused_forces != 1) ||
+        t->reserved != 0 || !(t->list_skin > 0.0 && t->list_skin <= 64.0) ||
+        !(t->list_pool_scale > 0.0 && t->list_pool_scale <= 1e3))
         return fail(PASTA_EINVAL, "pasta_set_tuning: bad argument");
     g_tuning = *t;
     return PASTA_OK;
@@ -264,7 +310,7 @@ extern "C" const char* pasta_kernel_class_name(int32_t k)
 {
     static const char* names[PASTA_KERNEL_CLASSES] = {
         "drift+bin", "scan", "scatter", "rank+stage", "coulomb", "nuclear+kick", "thermostat",
-        "combine+kick"};
+        "combine+kick", "list build"};
     return (k >= 0 && k < PASTA_KERNEL_CLASSES) ? names[k] : "?";
 }
 
@@ -323,9 +369,10 @@ extern "C" int pasta_forces_workspace(const pasta_potential* pot, int32_t precis
     if (!h_bytes || n < 0 || !(L > 0.0) || !std::isfinite(L) ||
         (precision != PASTA_FP64 && precision != PASTA_MIXED))
         return fail(PASTA_EINVAL, "pasta_forces_workspace: bad argument");
-    const Grid g = make_grid(L, pot->r_nuc);
+    const ListCfg lc = list_cfg(PASTA_TERM_ALL, L);
+    const Grid g = make_grid(L, cell_cut(pot, lc));
     Carver cv(nullptr);
-    *h_bytes = force_carve(cv, nullptr, n, g.C, precision);
+    *h_bytes = force_carve(cv, nullptr, n, g.C, precision, pot, lc);
     return PASTA_OK;
 }
 
@@ -347,19 +394,27 @@ extern "C" int pasta_forces(const pasta_potential* pot, int32_t precision, int32
     if (n == 0)
         return PASTA_OK;
     hipStream_t s = static_cast<hipStream_t>(stream);
-    const Grid g = make_grid(L, pot->r_nuc);
+    // a call without the nuclear terms uses the cell-sweep layout, which is
+    // smaller than the list layout the workspace query may have sized
+    const ListCfg lc = list_cfg(terms, L);
+    const Grid g = make_grid(L, cell_cut(pot, lc));
+    Carver cv0(nullptr);
+    PASTA_TRY(check_work(d_work, work_bytes, force_carve(cv0, nullptr, n, g.C, precision, pot, lc),
+                         "pasta_forces"));
     ForceWork w;
     Carver cv(d_work);
-    force_carve(cv, &w, n, g.C, precision);
+    force_carve(cv, &w, n, g.C, precision, pot, lc);
+    const PairParams pp = pair_params(pot, L);
     PASTA_HIP(hipMemsetAsync(w.err, 0, sizeof(uint32_t), s));
+    if (w.lists)
+        PASTA_HIP(hipMemsetAsync(w.lb.ctl, 0, sizeof(ListCtl), s));
     cellbuf_zero(w.cb, g.C, s);
-    build_cells(d_pos, d_species, n, g, w, precision, s, nullptr);
+    build_cells(d_pos, d_species, n, g, w, precision, pp, s, nullptr);
     int32_t Z = 0;
     PASTA_HIP(hipMemcpyAsync(&Z, w.cb.start + g.C, sizeof(int32_t), hipMemcpyDeviceToHost, s));
     PASTA_HIP(hipStreamSynchronize(s));
     KickArgs kick{nullptr, 0.0, pot->mass, nullptr};
-    eval_forces(precision, terms, w, g, n, Z, pair_params(pot, L), d_force, d_epot, kick,
-                nullptr, s, nullptr);
+    eval_forces(precision, terms, w, g, n, Z, pp, d_force, d_epot, kick, nullptr, s, nullptr);
     PASTA_HIP(hipGetLastError());
     return read_err(w.err, s, "pasta_forces");
 }
@@ -380,29 +435,31 @@ extern "C" int pasta_autotune(const pasta_potential* pot, int32_t precision, int
         return fail(PASTA_EINVAL, "pasta_autotune: bad argument");
     if (L < 2.0 * pot->r_nuc)
         return fail(PASTA_EBOX, "pasta_autotune: L < 2 r_nuc");
-    size_t need = 0;
-    PASTA_TRY(pasta_forces_workspace(pot, precision, n, L, &need));
+    const ListCfg no_lists;
     Carver cvn(nullptr);
     const Grid g = make_grid(L, pot->r_nuc);
-    force_carve(cvn, nullptr, n, g.C, precision);
+    force_carve(cvn, nullptr, n, g.C, precision, pot, no_lists);
     cvn.take<double>(4 * (size_t)n);  // scratch force + energy outputs
-    need = cvn.size();
-    PASTA_TRY(check_work(d_work, work_bytes, need, "pasta_autotune"));
+    PASTA_TRY(check_work(d_work, work_bytes, cvn.size(), "pasta_autotune"));
     hipStream_t s = static_cast<hipStream_t>(stream);
     ForceWork w;
     Carver cv(d_work);
-    force_carve(cv, &w, n, g.C, precision);
+    force_carve(cv, &w, n, g.C, precision, pot, no_lists);
     double* f = cv.take<double>(3 * (size_t)n);
     double* e = cv.take<double>((size_t)n);
+    const PairParams pp = pair_params(pot, L);
     PASTA_HIP(hipMemsetAsync(w.err, 0, sizeof(uint32_t), s));
     cellbuf_zero(w.cb, g.C, s);
-    build_cells(d_pos, d_species, n, g, w, precision, s, nullptr);
+    build_cells(d_pos, d_species, n, g, w, precision, pp, s, nullptr);
     int32_t Z = 0;
     PASTA_HIP(hipMemcpyAsync(&Z, w.cb.start + g.C, sizeof(int32_t), hipMemcpyDeviceToHost, s));
     PASTA_HIP(hipStreamSynchronize(s));
 
     const pasta_tuning saved = g_tuning;
-    pasta_tuning auto_t = {1, 0, 0};
+    pasta_tuning auto_t = saved;
+    auto_t.nuclear_variant = 1;
+    auto_t.coulomb_splits = 0;
+    auto_t.fused_forces = 0;
     g_tuning = auto_t;
     const int S0 = Z > 0 ? coulomb_splits(Z) : 1;
     std::vector<pasta_tuning> cands;
@@ -414,7 +471,11 @@ extern "C" int pasta_autotune(const pasta_potential* pot, int32_t precision, int
                 if (sv == last)
                     continue;
                 last = sv;
-                cands.push_back({v, sv, fused});
+                pasta_tuning c = saved;
+                c.nuclear_variant = v;
+                c.coulomb_splits = sv;
+                c.fused_forces = fused;
+                cands.push_back(c);
             }
         }
     hipEvent_t e0, e1;
@@ -422,7 +483,6 @@ extern "C" int pasta_autotune(const pasta_potential* pot, int32_t precision, int
     PASTA_HIP(hipEventCreate(&e1));
     double best = 1e300;
     int best_k = 0;
-    const PairParams pp = pair_params(pot, L);
     KickArgs kick{nullptr, 0.0, pot->mass, nullptr};
     int rc = PASTA_OK;
     for (size_t c = 0; c < cands.size() && rc == PASTA_OK; ++c) {
@@ -473,7 +533,7 @@ extern "C" int pasta_autotune_workspace(const pasta_potential* pot, int32_t prec
         return fail(PASTA_EINVAL, "pasta_autotune_workspace: bad argument");
     const Grid g = make_grid(L, pot->r_nuc);
     Carver cv(nullptr);
-    force_carve(cv, nullptr, n, g.C, precision);
+    force_carve(cv, nullptr, n, g.C, precision, pot, ListCfg());
     cv.take<double>(3 * (size_t)n);
     cv.take<double>((size_t)n);
     *h_bytes = cv.size();
@@ -493,6 +553,7 @@ struct pasta_sim {
     const uint8_t* species;
     hipStream_t stream;
     int C_max;
+    double r_cell;  // cell width: r_nuc, or r_nuc + list halo
     ForceWork w;
     double* force;
     double* epot;
@@ -506,9 +567,10 @@ static double box_side(const pasta_sim* sim, int64_t step)
 }
 
 static size_t sim_carve(Carver& cv, ForceWork* w, double** force, double** epot, int64_t n,
-                        int C_max, int precision)
+                        int C_max, int precision, const pasta_potential* pot, const ListCfg& lc,
+                        int64_t pool_rows = -1)
 {
-    force_carve(cv, w, n, C_max, precision);
+    force_carve(cv, w, n, C_max, precision, pot, lc, pool_rows);
     double* f = cv.take<double>(3 * (size_t)n);
     double* e = cv.take<double>((size_t)n);
     if (force)
@@ -529,16 +591,18 @@ static int check_integ(const pasta_integrator* g)
 }
 
 extern "C" int pasta_sim_workspace(const pasta_potential* pot, const pasta_integrator* integ,
-                                   int32_t precision, int64_t n, double L_max, size_t* h_bytes)
+                                   int32_t precision, int64_t n, double L_start, double L_max,
+                                   size_t* h_bytes)
 {
     PASTA_TRY(check_pot(pot));
     PASTA_TRY(check_integ(integ));
-    if (!h_bytes || n < 0 || !(L_max > 0.0) || !std::isfinite(L_max) ||
-        (precision != PASTA_FP64 && precision != PASTA_MIXED))
+    if (!h_bytes || n < 0 || !(L_max > 0.0) || !std::isfinite(L_max) || !(L_start > 0.0) ||
+        !std::isfinite(L_start) || (precision != PASTA_FP64 && precision != PASTA_MIXED))
         return fail(PASTA_EINVAL, "pasta_sim_workspace: bad argument");
-    const Grid g = make_grid(L_max, pot->r_nuc);
+    const ListCfg lc = list_cfg(PASTA_TERM_ALL, L_start);
+    const Grid g = make_grid(L_max > L_start ? L_max : L_start, cell_cut(pot, lc));
     Carver cv(nullptr);
-    *h_bytes = sim_carve(cv, nullptr, nullptr, nullptr, n, g.C, precision);
+    *h_bytes = sim_carve(cv, nullptr, nullptr, nullptr, n, g.C, precision, pot, lc);
     return PASTA_OK;
 }
 
@@ -546,15 +610,16 @@ static int sim_eval_initial(pasta_sim* sim)
 {
     hipStream_t s = sim->stream;
     const double L = box_side(sim, sim->step);
-    const Grid g = make_grid(L, sim->pot.r_nuc);
-    build_cells(sim->pos, sim->species, sim->n, g, sim->w, sim->precision, s, &sim->timer);
+    const Grid g = make_grid(L, sim->r_cell);
+    const PairParams pp = pair_params(&sim->pot, L);
+    build_cells(sim->pos, sim->species, sim->n, g, sim->w, sim->precision, pp, s, &sim->timer);
     int32_t Z = 0;
     PASTA_HIP(hipMemcpyAsync(&Z, sim->w.cb.start + g.C, sizeof(int32_t), hipMemcpyDeviceToHost, s));
     PASTA_HIP(hipStreamSynchronize(s));
     sim->Z = Z;
     KickArgs kick{nullptr, 0.0, sim->pot.mass, nullptr};
-    eval_forces(sim->precision, PASTA_TERM_ALL, sim->w, g, sim->n, sim->Z,
-                pair_params(&sim->pot, L), sim->force, sim->epot, kick, nullptr, s, &sim->timer);
+    eval_forces(sim->precision, PASTA_TERM_ALL, sim->w, g, sim->n, sim->Z, pp, sim->force,
+                sim->epot, kick, nullptr, s, &sim->timer);
     PASTA_HIP(hipGetLastError());
     return read_err(sim->w.err, s, "pasta_sim");
 }
@@ -591,16 +656,33 @@ extern "C" int pasta_sim_create(const pasta_potential* pot, const pasta_integrat
         delete sim;
         return fail(PASTA_EBOX, "pasta_sim_create: L = %g < 2 r_nuc", Lstart);
     }
-    sim->C_max = make_grid(sim->L_max, pot->r_nuc).C;
+    // the list form (nuclear_variant 2 when the simulation is created) keeps
+    // its setting for the life of the simulation; the list memory takes the
+    // rest of the workspace
+    const ListCfg lc = list_cfg(PASTA_TERM_ALL, Lstart);
+    sim->r_cell = cell_cut(pot, lc);
+    sim->C_max = make_grid(sim->L_max, sim->r_cell).C;
     Carver cv0(nullptr);
-    const size_t need = sim_carve(cv0, nullptr, nullptr, nullptr, n, sim->C_max, precision);
+    const size_t need =
+        sim_carve(cv0, nullptr, nullptr, nullptr, n, sim->C_max, precision, pot, lc, 1);
     int rc = check_work(d_work, work_bytes, need, "pasta_sim_create");
     if (rc != PASTA_OK) {
         delete sim;
         return rc;
     }
+    int64_t rows = -1;
+    if (lc.on) {
+        rows = 1 + (int64_t)((work_bytes - need) / LIST_ROW_BYTES);
+        for (;;) {
+            Carver cvr(nullptr);
+            if (sim_carve(cvr, nullptr, nullptr, nullptr, n, sim->C_max, precision, pot, lc,
+                          rows) <= work_bytes || rows == 1)
+                break;
+            --rows;
+        }
+    }
     Carver cv(d_work);
-    sim_carve(cv, &sim->w, &sim->force, &sim->epot, n, sim->C_max, precision);
+    sim_carve(cv, &sim->w, &sim->force, &sim->epot, n, sim->C_max, precision, pot, lc, rows);
     for (int k = 0; k < PASTA_KERNEL_CLASSES; ++k)
         sim->timer.open[k] = -1;
     hipStream_t s = sim->stream;
@@ -609,6 +691,10 @@ extern "C" int pasta_sim_create(const pasta_potential* pot, const pasta_integrat
         return fail(PASTA_EHIP, "hipMemsetAsync failed");
     }
     cellbuf_zero(sim->w.cb, sim->C_max, s);
+    if (sim->w.lists && hipMemsetAsync(sim->w.lb.ctl, 0, sizeof(ListCtl), s) != hipSuccess) {
+        delete sim;
+        return fail(PASTA_EHIP, "hipMemsetAsync failed");
+    }
     rc = sim_eval_initial(sim);
     if (rc != PASTA_OK) {
         delete sim;
@@ -631,7 +717,7 @@ extern "C" int pasta_sim_step(pasta_sim* sim, int64_t nsteps)
         if (L_new > sim->L_max * (1.0 + 1e-12) || L_new < 2.0 * sim->pot.r_nuc)
             return fail(PASTA_EBOX, "pasta_sim_step: box side %g at step %lld is outside "
                         "[2 r_nuc, L_max = %g]", L_new, (long long)(n0 + 1), sim->L_max);
-        const Grid g = make_grid(L_new, sim->pot.r_nuc);
+        const Grid g = make_grid(L_new, sim->r_cell);
         DriftArgs da;
         da.pos = sim->pos;
         da.vel = sim->vel;
@@ -643,15 +729,31 @@ extern "C" int pasta_sim_step(pasta_sim* sim, int64_t nsteps)
         da.L_new = L_new;
         da.ratio = L_new / L_old;
         da.scale_positions = gi.scale_positions;
-        launch_drift(da, g, sim->w.cb, sim->w.err, s, &sim->timer);
-        launch_scan(sim->w.cb, g.C, nuclear_chunk(sim->precision), s, &sim->timer);
-        launch_scatter_rank(sim->pos, sim->species, sim->n, g, sim->w.cb, sim->w.fb.stg64,
-                            sim->w.fb.stgq, s, &sim->timer, true);
+        const PairParams pp = pair_params(&sim->pot, L_new);
+        if (sim->w.lists) {
+            // drift + staging + rebuild decision, then the build kernels,
+            // each of which returns at once unless this step rebuilds
+            const ListBuf& lb = sim->w.lb;
+            const int32_t* gate = &lb.ctl->rebuild;
+            launch_drift_list(da, g, sim->w.cb, lb, sim->w.fb.stg64, sim->w.fb.stgq, n0,
+                              sim->w.err, s, &sim->timer);
+            launch_bin_count(sim->pos, sim->species, sim->n, g, sim->w.cb, sim->w.err, s,
+                             &sim->timer, gate);
+            launch_scan(sim->w.cb, g.C, nuclear_chunk(sim->precision, true), s, &sim->timer,
+                        gate);
+            launch_scatter_rank(sim->pos, sim->species, sim->n, g, sim->w.cb, sim->w.fb.stg64,
+                                sim->w.fb.stgq, s, &sim->timer, true, gate, lb.xb);
+            launch_list_build(sim->precision, sim->w.fb, sim->w.cb, g, lb, pp, s, &sim->timer);
+        } else {
+            launch_drift(da, g, sim->w.cb, sim->w.err, s, &sim->timer);
+            launch_scan(sim->w.cb, g.C, nuclear_chunk(sim->precision), s, &sim->timer);
+            launch_scatter_rank(sim->pos, sim->species, sim->n, g, sim->w.cb, sim->w.fb.stg64,
+                                sim->w.fb.stgq, s, &sim->timer, true);
+        }
         const bool thermo = gi.rescale_every > 0 && (n0 + 1) % gi.rescale_every == 0;
         KickArgs kick{sim->vel, hdtm, sim->pot.mass, thermo ? sim->w.fb.ke_part : nullptr};
-        eval_forces(sim->precision, PASTA_TERM_ALL, sim->w, g, sim->n, sim->Z,
-                    pair_params(&sim->pot, L_new), sim->force, sim->epot, kick, nullptr, s,
-                    &sim->timer);
+        eval_forces(sim->precision, PASTA_TERM_ALL, sim->w, g, sim->n, sim->Z, pp, sim->force,
+                    sim->epot, kick, nullptr, s, &sim->timer);
         if (thermo)
             launch_thermostat(sim->vel, sim->n, sim->w.fb.ke_part,
                               g_tuning.fused_forces ? sim->w.fb.n_ke : sim->w.cb.n_items,
@@ -712,7 +814,7 @@ extern "C" int pasta_sim_pair_counts(pasta_sim* sim, int64_t* h_nuclear, int64_t
         return fail(PASTA_EINVAL, "pasta_sim_pair_counts: null sim");
     hipStream_t s = sim->stream;
     const double L = box_side(sim, sim->step);
-    const Grid g = make_grid(L, sim->pot.r_nuc);
+    const Grid g = make_grid(L, sim->r_cell);
     uint64_t* ctr = sim->w.fb.pairs;
     PASTA_HIP(hipMemsetAsync(ctr, 0, 2 * sizeof(uint64_t), s));
     KickArgs kick{nullptr, 0.0, sim->pot.mass, nullptr};
@@ -726,6 +828,31 @@ extern "C" int pasta_sim_pair_counts(pasta_sim* sim, int64_t* h_nuclear, int64_t
         *h_nuclear = (int64_t)(h[0] / 2);  // ordered -> unordered
     if (h_coulomb)
         *h_coulomb = sim->Z * (sim->Z - 1) / 2;
+    return PASTA_OK;
+}
+
+extern "C" int pasta_sim_list_stats(pasta_sim* sim, int64_t* h_builds, int64_t* h_overflows,
+                                    double* h_max_disp, int64_t* h_rows_used,
+                                    int64_t* h_rows_capacity)
+{
+    if (!sim)
+        return fail(PASTA_EINVAL, "pasta_sim_list_stats: null sim");
+    ListCtl c{};
+    if (sim->w.lists) {
+        PASTA_HIP(hipMemcpyAsync(&c, sim->w.lb.ctl, sizeof(c), hipMemcpyDeviceToHost,
+                                 sim->stream));
+        PASTA_HIP(hipStreamSynchronize(sim->stream));
+    }
+    if (h_builds)
+        *h_builds = (int64_t)c.n_builds;
+    if (h_overflows)
+        *h_overflows = (int64_t)c.n_overflow + (c.overflow ? 1 : 0);
+    if (h_max_disp)
+        *h_max_disp = c.max_disp;
+    if (h_rows_used)
+        *h_rows_used = (int64_t)c.pool_used;
+    if (h_rows_capacity)
+        *h_rows_capacity = sim->w.lists ? sim->w.lb.pool_rows : 0;
     return PASTA_OK;
 }
 

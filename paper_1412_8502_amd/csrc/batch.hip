@@ -960,7 +960,7 @@ extern "C" int pasta_batch_create(const pasta_potential* pot, int32_t precision,
     B.pp.lambda_s = pot->lambda_s;
     B.pp.L = 0.0;
     B.mass = pot->mass;
-    B.nuc_variant = g_tuning.nuclear_variant;
+    B.nuc_variant = g_tuning.nuclear_variant == 0 ? 0 : 1;  // lists: single systems only
     B.pos = d_pos;
     B.vel = d_vel;
     B.species = d_species;

@@ -1,6 +1,8 @@
 // Cell-list build: a stable counting sort of particles into cubic cells no
 // narrower than the interaction range (the binning of Sec. II.B.2), rebuilt
-// from scratch every step.  Memory-bound; four launches:
+// from scratch every step (cell sweeps) or whenever the neighbour lists are
+// rebuilt (the kernels then take a device gate word).  Memory-bound; four
+// launches:
 //   bin/count   one thread per particle: bin = (proton ? 0 : C) + cell,
 //               integer atomic count per bin (order-independent);
 //   scan        one workgroup: exclusive scan of the 2C counts, the nuclear
@@ -22,10 +24,11 @@ __global__ __launch_bounds__(256) void k_bin_count(const double* __restrict__ po
                                                    int64_t n, int nc, int C, double inv_w,
                                                    double L, int32_t* __restrict__ key,
                                                    int32_t* __restrict__ count,
-                                                   uint32_t* __restrict__ err)
+                                                   uint32_t* __restrict__ err,
+                                                   const int32_t* __restrict__ gate)
 {
     int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= n)
+    if (i >= n || (gate && *gate == 0))
         return;
     double x = pos[3 * i + 0], y = pos[3 * i + 1], z = pos[3 * i + 2];
     const uint8_t sp = species[i];
@@ -70,9 +73,12 @@ __global__ __launch_bounds__(SCAN_THREADS) void k_scan(int32_t* __restrict__ cou
                                                        int32_t* __restrict__ start, int C,
                                                        int chunk, int32_t* __restrict__ items,
                                                        int32_t* __restrict__ n_items,
-                                                       int32_t* __restrict__ tmpc)
+                                                       int32_t* __restrict__ tmpc,
+                                                       const int32_t* __restrict__ gate)
 {
     __shared__ int64_t lds[SCAN_THREADS];
+    if (gate && *gate == 0)
+        return;
     const int tid = threadIdx.x;
     const int64_t nb = 2 * (int64_t)C;
     int64_t total = block_scan_runs(count, start, nb, lds);
@@ -111,10 +117,11 @@ __global__ __launch_bounds__(256) void k_scatter(const int32_t* __restrict__ key
                                                  const int32_t* __restrict__ order,
                                                  const int32_t* __restrict__ start,
                                                  int32_t* __restrict__ fill,
-                                                 int32_t* __restrict__ tmp)
+                                                 int32_t* __restrict__ tmp,
+                                                 const int32_t* __restrict__ gate)
 {
     int64_t s = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (s >= n)
+    if (s >= n || (gate && *gate == 0))
         return;
     const int32_t i = order ? order[s] : (int32_t)s;
     const int b = key[i];
@@ -129,10 +136,12 @@ __global__ __launch_bounds__(256) void k_rank(const int32_t* __restrict__ key,
                                               const double* __restrict__ pos,
                                               const uint8_t* __restrict__ species,
                                               double4* __restrict__ stg64,
-                                              Q4* __restrict__ stgq, double qscale)
+                                              Q4* __restrict__ stgq, double qscale,
+                                              const int32_t* __restrict__ gate,
+                                              double* __restrict__ xb)
 {
     int64_t s = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (s >= n)
+    if (s >= n || (gate && *gate == 0))
         return;
     const int32_t id = tmp[s];
     const int b = key[id];
@@ -155,6 +164,11 @@ __global__ __launch_bounds__(256) void k_rank(const int32_t* __restrict__ key,
     perm[dst] = id;
     double x = pos[3 * (int64_t)id + 0], y = pos[3 * (int64_t)id + 1],
            z = pos[3 * (int64_t)id + 2];
+    if (xb) {
+        xb[3 * (int64_t)dst + 0] = x;
+        xb[3 * (int64_t)dst + 1] = y;
+        xb[3 * (int64_t)dst + 2] = z;
+    }
     if (stg64)
         stg64[dst] = make_double4(x, y, z, (double)species[id]);
     if (stgq) {
@@ -204,37 +218,40 @@ void cellbuf_zero(const CellBuf& cb, int C_max, hipStream_t s)
 }
 
 void launch_bin_count(const double* pos, const uint8_t* species, int64_t n, const Grid& g,
-                      const CellBuf& cb, uint32_t* err, hipStream_t s, Timer* t)
+                      const CellBuf& cb, uint32_t* err, hipStream_t s, Timer* t,
+                      const int32_t* gate)
 {
     timer_begin(t, KC_DRIFT, s);
     if (n > 0)
         k_bin_count<<<blocks_for(n, 256), 256, 0, s>>>(pos, species, n, g.nc, g.C, g.inv_w,
-                                                       g.L, cb.key, cb.count, err);
+                                                       g.L, cb.key, cb.count, err, gate);
     timer_end(t, KC_DRIFT, s);
 }
 
-void launch_scan(const CellBuf& cb, int C, int chunk, hipStream_t s, Timer* t)
+void launch_scan(const CellBuf& cb, int C, int chunk, hipStream_t s, Timer* t,
+                 const int32_t* gate)
 {
     timer_begin(t, KC_SCAN, s);
     // cb.tmp doubles as the per-cell chunk-count scratch (2C entries)
     k_scan<<<1, SCAN_THREADS, 0, s>>>(cb.count, cb.fill, cb.start, C, chunk, cb.items,
-                                      cb.n_items, cb.tmp);
+                                      cb.n_items, cb.tmp, gate);
     timer_end(t, KC_SCAN, s);
 }
 
 void launch_scatter_rank(const double* pos, const uint8_t* species, int64_t n, const Grid& g,
                          const CellBuf& cb, double4* stg64, Q4* stgq, hipStream_t s, Timer* t,
-                         bool prev_order)
+                         bool prev_order, const int32_t* gate, double* xb)
 {
     if (n <= 0)
         return;
     timer_begin(t, KC_SCATTER, s);
     k_scatter<<<blocks_for(n, 256), 256, 0, s>>>(cb.key, n, prev_order ? cb.perm : nullptr,
-                                                 cb.start, cb.fill, cb.tmp);
+                                                 cb.start, cb.fill, cb.tmp, gate);
     timer_end(t, KC_SCATTER, s);
     timer_begin(t, KC_RANK, s);
     k_rank<<<blocks_for(n, 256), 256, 0, s>>>(cb.key, cb.tmp, n, cb.start, cb.perm, pos,
-                                              species, stg64, stgq, 4294967296.0 / g.L);
+                                              species, stg64, stgq, 4294967296.0 / g.L, gate,
+                                              xb);
     timer_end(t, KC_RANK, s);
 }
 

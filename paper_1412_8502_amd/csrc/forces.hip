@@ -14,7 +14,7 @@
 // sources, then combine by wavefront shuffles.  The epilogue adds the Coulomb
 // partials, writes F and E in the caller's particle order and can apply the
 // velocity-Verlet second half kick (fused integrate).
-#include "pair_items.hpp"
+#include "list_items.hpp"
 
 namespace pasta {
 
@@ -52,6 +52,46 @@ __global__ __launch_bounds__(WG) void k_nuclear_compact(const typename P::Src* _
     nuclear_item_compact<P, NUC, COUNT>(stg, A, k, blockIdx.x, lds);
 }
 
+// List form of a nuclear item: the lists of the last build, or, when that
+// build ran out of list memory, the screened cell sweep over its cells (the
+// grid of the last build is read from the control block).
+template <class P, bool COUNT>
+__device__ void nuclear_item_listed(const typename P::Src* __restrict__ stg, const NucArgs& A,
+                                    const NucConsts& k, const ListArgs& LA, int item, char* lds)
+{
+    NucArgs B = A;
+    B.nc = LA.ctl->nc;
+    B.C = LA.ctl->C;
+    if (LA.ctl->overflow)
+        nuclear_item_compact_t<P, LIST_TPT, true, COUNT>(stg, B, k, item, lds);
+    else
+        list_force_item<P, COUNT>(stg, B, k, LA, item, lds);
+}
+
+template <class P, bool COUNT>
+__global__ __launch_bounds__(WG) void k_nuclear_list(const typename P::Src* __restrict__ stg,
+                                                     NucArgs A,
+                                                     const int32_t* __restrict__ n_items,
+                                                     NucConsts k, ListArgs LA)
+{
+    __shared__ __align__(16) char lds[nuclear_compact_lds_bytes<P>()];
+    if ((int)blockIdx.x >= *n_items)
+        return;
+    nuclear_item_listed<P, COUNT>(stg, A, k, LA, blockIdx.x, lds);
+}
+
+// Gated on the rebuild decision of this step.
+template <class P>
+__global__ __launch_bounds__(WG) void k_list_build(const typename P::Src* __restrict__ stg,
+                                                   NucArgs A, const int32_t* __restrict__ n_items,
+                                                   NucConsts kl, ListArgs LA)
+{
+    __shared__ __align__(16) char lds[list_build_lds_bytes()];
+    if ((int)blockIdx.x >= *n_items || LA.ctl->rebuild == 0)
+        return;
+    list_build_item<P>(stg, A, kl, LA, blockIdx.x, lds);
+}
+
 // Fused form: blocks [0, item_max) are nuclear cell tiles (raw nuclear
 // force and energy per sorted slot), blocks after them Coulomb tiles.
 template <class P, bool COUNT>
@@ -59,7 +99,8 @@ __global__ __launch_bounds__(WG) void k_forces_fused(const typename P::Src* __re
                                                      NucArgs A, const int32_t* __restrict__ n_items,
                                                      int item_max, int nuc_variant, NucConsts k,
                                                      int Z, int per_split, int coul_blocks,
-                                                     CoulConsts kc, double4* __restrict__ part)
+                                                     CoulConsts kc, double4* __restrict__ part,
+                                                     ListArgs LA)
 {
     constexpr int a = coulomb_lds_bytes<P>(), b = nuclear_lds_bytes<P>(),
                   c = nuclear_compact_lds_bytes<P>();
@@ -69,7 +110,9 @@ __global__ __launch_bounds__(WG) void k_forces_fused(const typename P::Src* __re
     if (g < item_max) {
         if (g >= *n_items)
             return;
-        if (nuc_variant == 1)
+        if (nuc_variant == 2)
+            nuclear_item_listed<P, COUNT>(stg, A, k, LA, g, lds);
+        else if (nuc_variant == 1)
             nuclear_item_compact<P, true, COUNT>(stg, A, k, g, lds);
         else
             nuclear_item<P, true, COUNT>(stg, A, k, g, lds);
@@ -154,7 +197,68 @@ void nuclear_dispatch(const typename P::Src* stg, const NucArgs& a, const int32_
 
 }  // namespace
 
-int nuclear_chunk(int /*precision*/) { return NUC_CHUNK; }
+int nuclear_chunk(int /*precision*/, bool lists) { return lists ? LIST_CHUNK : NUC_CHUNK; }
+
+static ListArgs list_args(const ListBuf* lb)
+{
+    ListArgs la{};
+    if (lb) {
+        la.ctl = lb->ctl;
+        la.hdr = lb->hdr;
+        la.cnt = lb->cnt;
+        la.pool = lb->pool;
+        la.pool_rows = lb->pool_rows;
+    }
+    return la;
+}
+
+int64_t list_pool_rows(int64_t n, double L_min, double r_list, int64_t item_max, double scale)
+{
+    // expected list entries per lane at the densest box, plus a Poisson
+    // margin for the largest lane of an item, times the safety scale
+    const double rho = (double)n / (L_min * L_min * L_min);
+    const double per_lane = rho * (4.0 / 3.0) * M_PI * r_list * r_list * r_list / LIST_TPT;
+    const double rows_item = 1.5 * per_lane + 4.0 * std::sqrt(per_lane) + 8.0;
+    double rows = std::ceil((double)item_max * rows_item * (scale > 0.0 ? scale : 1.0));
+    return rows < 1.0 ? 1 : (int64_t)rows;
+}
+
+size_t listbuf_carve(Carver& cv, ListBuf* out, int64_t n, int64_t item_max, int64_t pool_rows)
+{
+    ListBuf lb{};
+    lb.ctl = cv.take<ListCtl>(1);
+    lb.xb = cv.take<double>(3 * (size_t)n);
+    lb.hdr = cv.take<int2>((size_t)item_max);
+    lb.cnt = cv.take<int32_t>((size_t)item_max * WG);
+    lb.pool = cv.take<int32_t>((size_t)pool_rows * WG);
+    lb.pool_rows = pool_rows;
+    if (out)
+        *out = lb;
+    return cv.size();
+}
+
+void launch_list_build(int precision, const ForceBuf& fb, const CellBuf& cb, const Grid& g,
+                       const ListBuf& lb, const PairParams& pp, hipStream_t s, Timer* t)
+{
+    PairParams pl = pp;
+    pl.r_nuc = (pp.r_nuc + lb.skin) * (1.0 + 1e-5);  // a superset: rounding margin
+    const NucConsts kl = make_nuc_consts(pl);
+    NucArgs a{};
+    a.start = cb.start;
+    a.items = cb.items;
+    a.perm = cb.perm;
+    a.nc = g.nc;
+    a.C = g.C;
+    const ListArgs la = list_args(&lb);
+    timer_begin(t, KC_LIST, s);
+    if (precision == PASTA_FP64)
+        k_list_build<Fp64Policy><<<(unsigned)cb.item_max, WG, 0, s>>>(fb.stg64, a, cb.n_items,
+                                                                       kl, la);
+    else
+        k_list_build<MixedPolicy><<<(unsigned)cb.item_max, WG, 0, s>>>(fb.stgq, a, cb.n_items,
+                                                                       kl, la);
+    timer_end(t, KC_LIST, s);
+}
 
 int coulomb_splits(int64_t Z)
 {
@@ -169,12 +273,13 @@ int coulomb_splits(int64_t Z)
     return (int)s;
 }
 
-pasta_tuning g_tuning = {1, 0, 1};
+pasta_tuning g_tuning = {1, 0, 1, 0, 2.0, 1.0};
 
 void launch_forces_fused(int precision, const ForceBuf& fb, const CellBuf& cb, const Grid& g,
                          int64_t n, int64_t Z, const PairParams& pp, bool with_nuclear_terms,
                          bool with_coulomb, double* force, double* epot, const KickArgs& kick,
-                         uint64_t* pair_counter, uint32_t* err, hipStream_t s, Timer* t)
+                         uint64_t* pair_counter, uint32_t* err, hipStream_t s, Timer* t,
+                         const ListBuf* lb)
 {
     const NucConsts k = make_nuc_consts(pp);
     const CoulConsts kc = make_coul_consts(pp);
@@ -195,27 +300,28 @@ void launch_forces_fused(int precision, const ForceBuf& fb, const CellBuf& cb, c
     const int item_max = (int)cb.item_max;
     const unsigned grid = (unsigned)(item_max + coul_blocks * S);
     const bool count = pair_counter != nullptr;
-    const int variant = g_tuning.nuclear_variant;
+    const int variant = lb ? 2 : (g_tuning.nuclear_variant == 0 ? 0 : 1);
+    const ListArgs la = list_args(lb);
     timer_begin(t, KC_NUCLEAR, s);
     if (grid > 0) {
         if (precision == PASTA_FP64) {
             if (count)
                 k_forces_fused<Fp64Policy, true><<<grid, WG, 0, s>>>(
                     fb.stg64, a, cb.n_items, item_max, variant, k, (int)Z, per, coul_blocks, kc,
-                    fb.coul_part);
+                    fb.coul_part, la);
             else
                 k_forces_fused<Fp64Policy, false><<<grid, WG, 0, s>>>(
                     fb.stg64, a, cb.n_items, item_max, variant, k, (int)Z, per, coul_blocks, kc,
-                    fb.coul_part);
+                    fb.coul_part, la);
         } else {
             if (count)
                 k_forces_fused<MixedPolicy, true><<<grid, WG, 0, s>>>(
                     fb.stgq, a, cb.n_items, item_max, variant, k, (int)Z, per, coul_blocks, kc,
-                    fb.coul_part);
+                    fb.coul_part, la);
             else
                 k_forces_fused<MixedPolicy, false><<<grid, WG, 0, s>>>(
                     fb.stgq, a, cb.n_items, item_max, variant, k, (int)Z, per, coul_blocks, kc,
-                    fb.coul_part);
+                    fb.coul_part, la);
         }
     }
     timer_end(t, KC_NUCLEAR, s);
@@ -263,7 +369,8 @@ void launch_coulomb(int precision, const ForceBuf& fb, int64_t Z, const PairPara
 void launch_nuclear(int precision, const ForceBuf& fb, const CellBuf& cb, const Grid& g,
                     int64_t n, int64_t Z, const PairParams& pp, bool with_nuclear_terms,
                     int coul_S, double* force, double* epot, const KickArgs& kick,
-                    uint64_t* pair_counter, uint32_t* err, hipStream_t s, Timer* t)
+                    uint64_t* pair_counter, uint32_t* err, hipStream_t s, Timer* t,
+                    const ListBuf* lb)
 {
     (void)n;
     const NucConsts k = make_nuc_consts(pp);
@@ -287,14 +394,28 @@ void launch_nuclear(int precision, const ForceBuf& fb, const CellBuf& cb, const 
     a.fnuc = nullptr;
     const unsigned grid = (unsigned)cb.item_max;
     const bool count = pair_counter != nullptr;
-    const int variant = g_tuning.nuclear_variant;
+    const int variant = g_tuning.nuclear_variant == 0 ? 0 : 1;
     timer_begin(t, KC_NUCLEAR, s);
-    if (precision == PASTA_FP64)
+    if (lb && with_nuclear_terms) {
+        const ListArgs la = list_args(lb);
+        if (precision == PASTA_FP64) {
+            if (count)
+                k_nuclear_list<Fp64Policy, true><<<grid, WG, 0, s>>>(fb.stg64, a, cb.n_items, k, la);
+            else
+                k_nuclear_list<Fp64Policy, false><<<grid, WG, 0, s>>>(fb.stg64, a, cb.n_items, k, la);
+        } else {
+            if (count)
+                k_nuclear_list<MixedPolicy, true><<<grid, WG, 0, s>>>(fb.stgq, a, cb.n_items, k, la);
+            else
+                k_nuclear_list<MixedPolicy, false><<<grid, WG, 0, s>>>(fb.stgq, a, cb.n_items, k, la);
+        }
+    } else if (precision == PASTA_FP64) {
         nuclear_dispatch<Fp64Policy>(fb.stg64, a, cb.n_items, k, with_nuclear_terms, count,
                                      variant, grid, s);
-    else
+    } else {
         nuclear_dispatch<MixedPolicy>(fb.stgq, a, cb.n_items, k, with_nuclear_terms, count,
                                       variant, grid, s);
+    }
     timer_end(t, KC_NUCLEAR, s);
 }
 

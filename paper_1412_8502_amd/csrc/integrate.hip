@@ -60,6 +60,125 @@ __global__ __launch_bounds__(256) void k_drift(DriftArgs a, int nc, int C, doubl
     wave_aggregated_add(count, bin);
 }
 
+// List form.  Thread s owns sorted slot s of the last build.  The rebuild
+// decision is taken by the last workgroup to finish (a device-scope counter
+// after a release fence), so it sees every workgroup's maximum; the other
+// workgroups never wait.
+__global__ __launch_bounds__(256) void k_drift_list(DriftArgs a, ListCtl* __restrict__ ctl,
+                                                    const double* __restrict__ xb,
+                                                    const int32_t* __restrict__ order,
+                                                    double4* __restrict__ stg64,
+                                                    Q4* __restrict__ stgq, double qscale,
+                                                    int parity, double skin, int nc_new,
+                                                    int C_new, uint32_t* __restrict__ err)
+{
+    __shared__ float wmax[4];
+    __shared__ int last;
+    const int64_t s = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const double L = a.L_new;
+    float d2 = 0.f;
+    if (s < a.n) {
+        const int64_t i = order[s];
+        uint32_t bad = 0;
+        double xn[3];
+#pragma unroll
+        for (int d = 0; d < 3; ++d) {
+            double v = a.vel[3 * i + d] + a.hdtm * a.force[3 * i + d];
+            double x = a.pos[3 * i + d] + a.dt * v;
+            if (a.scale_positions)
+                x *= a.ratio;
+            if (x < 0.0)
+                x += L;
+            if (x >= L)
+                x -= L;
+            if (!(x >= 0.0 && x < L)) {
+                bad |= isfinite(x) ? ERR_WRAP : ERR_NONFINITE_POS;
+                x = isfinite(x) ? x - L * floor(x / L) : 0.0;
+                if (!(x >= 0.0 && x < L))
+                    x = 0.0;
+            }
+            if (!isfinite(v))
+                bad |= ERR_NONFINITE_VEL;
+            a.vel[3 * i + d] = v;
+            a.pos[3 * i + d] = x;
+            xn[d] = x;
+        }
+        if (bad)
+            atomicOr(err, bad);
+        double u2 = 0.0;
+#pragma unroll
+        for (int d = 0; d < 3; ++d) {
+            double u = xn[d] - xb[3 * s + d];
+            u -= L * rint(u / L);
+            u2 += u * u;
+        }
+        d2 = (float)u2 * 1.000001f;  // rounded up: the test stays conservative
+        const uint8_t sp = a.species[i];
+        if (stg64)
+            stg64[s] = make_double4(xn[0], xn[1], xn[2], (double)sp);
+        if (stgq) {
+            Q4 q;
+            q.x = (uint32_t)(uint64_t)(xn[0] * qscale);
+            q.y = (uint32_t)(uint64_t)(xn[1] * qscale);
+            q.z = (uint32_t)(uint64_t)(xn[2] * qscale);
+            q.w = sp;
+            stgq[s] = q;
+        }
+    }
+    for (int m = 32; m >= 1; m >>= 1)
+        d2 = fmaxf(d2, __shfl_xor(d2, m, 64));
+    if ((threadIdx.x & 63) == 0)
+        wmax[threadIdx.x >> 6] = d2;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        const float bm = fmaxf(fmaxf(wmax[0], wmax[1]), fmaxf(wmax[2], wmax[3]));
+        // non-negative floats order like their bit patterns
+        atomicMax(&ctl->maxd2[parity], __float_as_uint(bm));
+        __threadfence();
+        last = atomicAdd(&ctl->done, 1u) == gridDim.x - 1;
+    }
+    __syncthreads();
+    if (last && threadIdx.x == 0) {
+        __threadfence();
+        const float m2 = __uint_as_float(atomicAdd(&ctl->maxd2[parity], 0u));
+        const double dmax = sqrt((double)m2);
+        const double growth = 1.7320508075688772 * fabs(L - ctl->L_build);
+        const int need = !(2.0 * dmax + growth < skin);
+        ctl->max_disp = dmax;
+        if (need) {
+            ctl->n_overflow += ctl->overflow ? 1u : 0u;
+            ctl->L_build = L;
+            ctl->nc = nc_new;
+            ctl->C = C_new;
+            ctl->pool_used = 0;
+            ctl->max_rows = 0;
+            ctl->overflow = 0;
+            ctl->n_builds += 1;
+        }
+        ctl->rebuild = need;
+        ctl->maxd2[parity ^ 1] = 0u;
+        ctl->done = 0u;
+    }
+}
+
+// Forces a build at the next gated launch sequence (rebuild = 1) for grid
+// nc/C at box side L.
+__global__ void k_list_force_rebuild(ListCtl* ctl, double L, int nc, int C)
+{
+    ctl->n_overflow += ctl->overflow ? 1u : 0u;
+    ctl->L_build = L;
+    ctl->nc = nc;
+    ctl->C = C;
+    ctl->pool_used = 0;
+    ctl->max_rows = 0;
+    ctl->overflow = 0;
+    ctl->n_builds += 1;
+    ctl->rebuild = 1;
+    ctl->maxd2[0] = 0u;
+    ctl->maxd2[1] = 0u;
+    ctl->done = 0u;
+}
+
 constexpr int RED = 1024;
 
 __global__ __launch_bounds__(RED) void k_thermostat_reduce(const double* __restrict__ ke_part,
@@ -134,6 +253,24 @@ void launch_drift(const DriftArgs& a, const Grid& g, const CellBuf& cb, uint32_t
     k_drift<<<(unsigned)((a.n + 255) / 256), 256, 0, s>>>(a, g.nc, g.C, g.inv_w, cb.perm,
                                                           cb.key, cb.count, err);
     timer_end(t, KC_DRIFT, s);
+}
+
+void launch_drift_list(const DriftArgs& a, const Grid& g, const CellBuf& cb, const ListBuf& lb,
+                       double4* stg64, Q4* stgq, int64_t step, uint32_t* err, hipStream_t s,
+                       Timer* t)
+{
+    if (a.n <= 0)
+        return;
+    timer_begin(t, KC_DRIFT, s);
+    k_drift_list<<<(unsigned)((a.n + 255) / 256), 256, 0, s>>>(
+        a, lb.ctl, lb.xb, cb.perm, stg64, stgq, 4294967296.0 / a.L_new, (int)(step & 1),
+        lb.skin, g.nc, g.C, err);
+    timer_end(t, KC_DRIFT, s);
+}
+
+void launch_list_force_rebuild(const ListBuf& lb, const Grid& g, hipStream_t s)
+{
+    k_list_force_rebuild<<<1, 1, 0, s>>>(lb.ctl, g.L, g.nc, g.C);
 }
 
 void launch_thermostat(double* vel, int64_t n, const double* ke_part, const int32_t* n_items,

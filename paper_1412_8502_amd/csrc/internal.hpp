@@ -180,12 +180,43 @@ enum KernelClass : int {
     KC_NUCLEAR = 5,
     KC_THERMO = 6,
     KC_COMBINE = 7,
+    KC_LIST = 8,
 };
 
 // Launch timing hook: when non-null, brackets a launch with HIP events.
 struct Timer;
 void timer_begin(Timer* t, int kc, hipStream_t s);
 void timer_end(Timer* t, int kc, hipStream_t s);
+
+// -------------------------------------------------------- neighbour lists
+// Device control block of the neighbour lists of one system.  The drift
+// kernel's last workgroup decides, once per step, whether this step
+// rebuilds (rebuild), and the gated build kernels read that word.
+struct ListCtl {
+    double L_build;                  // box side at the last build
+    unsigned long long pool_used;    // pool rows taken by the last build
+    unsigned long long n_builds;     // builds so far
+    unsigned long long n_overflow;   // builds that ran out of list memory
+    uint32_t maxd2[2];               // FP32 bits of max |u|^2, by step parity
+    uint32_t done;                   // drift workgroups finished this step
+    int32_t rebuild;                 // 1: this step rebuilds cells + lists
+    int32_t overflow;                // 1: the last build ran out of memory
+    int32_t nc, C;                   // cell grid of the last build
+    uint32_t max_rows;               // largest item row count of the last build
+    double max_disp;                 // max |u| seen at the last decision (fm)
+};
+struct ListBuf {
+    ListCtl* ctl;
+    double* xb;        // [3n] positions at the last build, sorted-slot order
+    int2* hdr;         // [item_max]
+    int32_t* cnt;      // [item_max * 256]
+    int32_t* pool;     // [pool_rows * 256]
+    int64_t pool_rows;
+    double skin;       // delta_r (fm)
+};
+constexpr size_t LIST_ROW_BYTES = 256 * sizeof(int32_t);  // one pool row (a workgroup's entries)
+int64_t list_pool_rows(int64_t n, double L_min, double r_list, int64_t item_max, double scale);
+size_t listbuf_carve(Carver& cv, ListBuf* out, int64_t n, int64_t item_max, int64_t pool_rows);
 
 // -------------------------------------------------------- cell-list build
 struct CellBuf {
@@ -204,17 +235,22 @@ void cellbuf_zero(const CellBuf& cb, int C_max, hipStream_t s);
 
 // Bins + counts from positions (caller order); the drift kernel does the
 // same inside the integrator.
+// gate (optional, device): when non-null the kernels of the build return at
+// once unless *gate is non-zero (the neighbour-list rebuild decision).
 void launch_bin_count(const double* pos, const uint8_t* species, int64_t n, const Grid& g,
-                      const CellBuf& cb, uint32_t* err, hipStream_t s, Timer* t);
+                      const CellBuf& cb, uint32_t* err, hipStream_t s, Timer* t,
+                      const int32_t* gate = nullptr);
 // Exclusive scan of the 2C counts into start[]; zeroes count and fill; when
 // chunk > 0, also writes the nuclear work list.
-void launch_scan(const CellBuf& cb, int C, int chunk, hipStream_t s, Timer* t);
+void launch_scan(const CellBuf& cb, int C, int chunk, hipStream_t s, Timer* t,
+                 const int32_t* gate = nullptr);
 // Stable scatter: slot order = (bin, particle index).  Writes perm and, when
 // staging pointers are given, the sorted staging coordinates.  prev_order:
 // visit particles in the order of the previous build (cb.perm must hold it).
 void launch_scatter_rank(const double* pos, const uint8_t* species, int64_t n, const Grid& g,
                          const CellBuf& cb, double4* stg64, Q4* stgq, hipStream_t s, Timer* t,
-                         bool prev_order = false);
+                         bool prev_order = false, const int32_t* gate = nullptr,
+                         double* xb = nullptr);
 
 // ----------------------------------------------------------------- forces
 struct PairParams {
@@ -254,8 +290,14 @@ void launch_coulomb(int precision, const ForceBuf& fb, int64_t Z, const PairPara
 void launch_nuclear(int precision, const ForceBuf& fb, const CellBuf& cb, const Grid& g,
                     int64_t n, int64_t Z, const PairParams& pp, bool with_nuclear_terms,
                     int coul_S, double* force, double* epot, const KickArgs& kick,
-                    uint64_t* pair_counter, uint32_t* err, hipStream_t s, Timer* t);
-int nuclear_chunk(int precision);
+                    uint64_t* pair_counter, uint32_t* err, hipStream_t s, Timer* t,
+                    const ListBuf* lb = nullptr);
+// Targets per nuclear work item (the scan's chunk): 64 for cell sweeps, 32
+// for the list form (8 lanes per target).
+int nuclear_chunk(int precision, bool lists = false);
+// Neighbour-list build (gated on lb.ctl->rebuild) for the cells of grid g.
+void launch_list_build(int precision, const ForceBuf& fb, const CellBuf& cb, const Grid& g,
+                       const ListBuf& lb, const PairParams& pp, hipStream_t s, Timer* t);
 
 // ------------------------------------------------------------- integrate
 struct DriftArgs {
@@ -270,6 +312,16 @@ struct DriftArgs {
 };
 void launch_drift(const DriftArgs& a, const Grid& g, const CellBuf& cb, uint32_t* err,
                   hipStream_t s, Timer* t);
+// Neighbour-list form of the drift: the same update, visiting the sorted
+// slots of the last build; writes the slot's staging coordinates for the new
+// box, reduces max |u|^2 (nearest-image displacement since the build) and,
+// in its last workgroup, decides whether this step rebuilds (ListCtl).
+// g is the cell grid a rebuild at this step would use.
+void launch_drift_list(const DriftArgs& a, const Grid& g, const CellBuf& cb, const ListBuf& lb,
+                       double4* stg64, Q4* stgq, int64_t step, uint32_t* err, hipStream_t s,
+                       Timer* t);
+// Marks the next build as due (initial state, set_state) for grid g.
+void launch_list_force_rebuild(const ListBuf& lb, const Grid& g, hipStream_t s);
 // Fused form: one launch with every Coulomb tile and nuclear cell tile (the
 // nuclear items write fb.fnuc), then the combine kernel: F = nuclear +
 // Coulomb partials, E, the optional half kick and kinetic-energy partials
@@ -277,7 +329,8 @@ void launch_drift(const DriftArgs& a, const Grid& g, const CellBuf& cb, uint32_t
 void launch_forces_fused(int precision, const ForceBuf& fb, const CellBuf& cb, const Grid& g,
                          int64_t n, int64_t Z, const PairParams& pp, bool with_nuclear_terms,
                          bool with_coulomb, double* force, double* epot, const KickArgs& kick,
-                         uint64_t* pair_counter, uint32_t* err, hipStream_t s, Timer* t);
+                         uint64_t* pair_counter, uint32_t* err, hipStream_t s, Timer* t,
+                         const ListBuf* lb = nullptr);
 // Thermostat: reduce ke_part[0 .. *n_items) and scale velocities to
 // KE = 1.5 N T.  scale_out receives the factor.
 void launch_thermostat(double* vel, int64_t n, const double* ke_part, const int32_t* n_items,

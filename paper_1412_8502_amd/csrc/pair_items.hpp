@@ -144,6 +144,7 @@ struct Fp64Policy {
         a.np += p.np;
         p = Part();
     }
+    __device__ static bool is_proton(const double4& s) { return s.w != 0.0; }
     __device__ static double f_scale(const NucConsts&) { return 1.0; }
     __device__ static double bl(const NucConsts& k, bool like) { return like ? k.Bl_L : k.Bu_L; }
     __device__ static double bv(const NucConsts& k, bool like) { return like ? k.Bl : k.Bu; }
@@ -224,6 +225,8 @@ struct MixedPolicy {
         a.np += p.np;
         p = Part();
     }
+    __device__ static bool is_proton(const Q4& s) { return s.w != 0u; }
+    __device__ static bool is_proton(const uint4& s) { return s.w != 0u; }
     __device__ static double f_scale(const NucConsts& k) { return k.q; }
     __device__ static float bl(const NucConsts& k, bool like) { return like ? k.Blf_L : k.Buf_L; }
     __device__ static float bv(const NucConsts& k, bool like) { return like ? k.Blf : k.Buf; }
@@ -266,12 +269,6 @@ constexpr int nuclear_lds_bytes()
 }
 constexpr int NUC_CAP = 24;  // per-lane pair-list capacity (compacting kernel)
 constexpr int NUC_U = 4;     // candidates per lane between list-fill checks
-template <class P>
-constexpr int nuclear_compact_lds_bytes()
-{
-    return P::CTILE * ((int)sizeof(typename P::Lds) + 8) + NUC_CAP * WG * 2 + 54 * 4 +
-           55 * 4 + 24 * 4 + 4 * 8 + 4 * 8 + 64;
-}
 
 // ============================================================ Coulomb ==
 // Targets are the proton slots [tb, tb + WG) ∩ [0, Z); sources the slots
@@ -514,271 +511,251 @@ __device__ __forceinline__ int screen16(uint32_t me_xy16, uint32_t me_z, uint2 t
     return __builtin_amdgcn_sdot2(d, d, dz * dz, false);
 }
 
-template <class P, bool NUC, bool COUNT>
-__device__ void nuclear_item_compact(const typename P::Src* __restrict__ stg, const NucArgs& A,
-                                     const NucConsts& k, int item, char* lds)
+// LDS scratch shared by the cell-item helpers below (after the tiles).
+struct ItemLds {
+    int* seg_beg;   // [54] first sorted slot of each neighbour bin
+    int* seg_off;   // [55] exclusive prefix of the bin lengths
+    int* misc;      // [24] box lo/hi, per-wave kept counts
+    double* ke_red;  // [WG/64]
+    unsigned long long* np_red;  // [WG/64]
+};
+constexpr int ITEM_LDS_BYTES = 54 * 4 + 55 * 4 + 24 * 4 + 4 * 8 + 4 * 8 + 16;
+__device__ inline ItemLds item_lds(char* p)
 {
-    using Lds = typename P::Lds;
-    constexpr int T = P::CTILE;
-    Lds* src = reinterpret_cast<Lds*>(lds);
-    uint2* tst = reinterpret_cast<uint2*>(src + T);
-    uint16_t* lists = reinterpret_cast<uint16_t*>(tst + T);
-    int* seg_beg = reinterpret_cast<int*>(lists + NUC_CAP * WG);
-    int* seg_off = seg_beg + 54;
-    int* misc = seg_off + 55;  // [0..5] box lo/hi, [6..13] kept counts, [14..21] kept protons
-    double* ke_red = reinterpret_cast<double*>(
-        (reinterpret_cast<uintptr_t>(misc + 24) + 7) & ~uintptr_t(7));
-    unsigned long long* np_red = reinterpret_cast<unsigned long long*>(ke_red + WG / 64);
+    ItemLds s;
+    s.seg_beg = reinterpret_cast<int*>(p);
+    s.seg_off = s.seg_beg + 54;
+    s.misc = s.seg_off + 55;
+    s.ke_red = reinterpret_cast<double*>(
+        (reinterpret_cast<uintptr_t>(s.misc + 24) + 7) & ~uintptr_t(7));
+    s.np_red = reinterpret_cast<unsigned long long*>(s.ke_red + WG / 64);
+    return s;
+}
 
-    const int c = A.items[2 * item + 0];
+// The item's target: chunk `chunk` of cell c holds targets chunk*(WG/TPT) +
+// tid/TPT of the cell's protons-then-neutrons; TPT lanes share a target.
+struct ItemTarget {
+    int c, tl, q, slot;
+    bool active, tprot;
+};
+template <int TPT>
+__device__ inline ItemTarget item_target(const NucArgs& A, int item)
+{
+    ItemTarget t;
+    t.c = A.items[2 * item + 0];
     const int chunk = A.items[2 * item + 1];
-    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-    const int nc = A.nc, C = A.C;
-    const int cx = c % nc, cy = (c / nc) % nc, cz = c / (nc * nc);
+    const int ps = A.start[t.c], npc = A.start[t.c + 1] - ps;
+    const int ns = A.start[A.C + t.c], mc = npc + (A.start[A.C + t.c + 1] - ns);
+    t.tl = threadIdx.x / TPT;
+    t.q = threadIdx.x % TPT;
+    const int tidx = chunk * (WG / TPT) + t.tl;
+    t.active = tidx < mc;
+    t.slot = t.active ? (tidx < npc ? ps + tidx : ns + (tidx - npc)) : 0;
+    t.tprot = tidx < npc;
+    return t;
+}
 
+// Neighbour bins of cell c (protons of the 27 cells, then their neutrons,
+// duplicates removed for small grids) and the bounding box of the item's
+// targets (fixed-point; a chunk lies inside one cell, so no wrap).  Ends
+// with a barrier; afterwards seg_off[54] is the candidate count.
+__device__ inline void item_setup(const NucArgs& A, const ItemLds& L, int c, bool nuc,
+                                  bool in_box, uint3 mef)
+{
+    const int tid = threadIdx.x, nc = A.nc, C = A.C;
+    const int cx = c % nc, cy = (c / nc) % nc, cz = c / (nc * nc);
     if (tid < 54) {
         const int kk = tid % 27, sp = tid / 27;  // sp 0: protons, 1: neutrons
         const int ox = kk % 3 - 1, oy = (kk / 3) % 3 - 1, oz = kk / 9 - 1;
         const int lo = axis_lo(nc), hi = axis_hi(nc);
         int beg = 0, len = 0;
-        if (NUC && ox >= lo && ox <= hi && oy >= lo && oy <= hi && oz >= lo && oz <= hi) {
+        if (nuc && ox >= lo && ox <= hi && oy >= lo && oy <= hi && oz >= lo && oz <= hi) {
             const int nx = (cx + ox + nc) % nc, ny = (cy + oy + nc) % nc,
                       nz = (cz + oz + nc) % nc;
             const int b = sp * C + (nz * nc + ny) * nc + nx;
             beg = A.start[b];
             len = A.start[b + 1] - beg;
         }
-        seg_beg[tid] = beg;
-        seg_off[tid + 1] = len;
+        L.seg_beg[tid] = beg;
+        L.seg_off[tid + 1] = len;
     }
     if (tid < 6)
-        misc[tid] = tid < 3 ? -1 : 0;  // lo = UINT_MAX, hi = 0 (as unsigned)
+        L.misc[tid] = tid < 3 ? -1 : 0;  // lo = UINT_MAX, hi = 0 (as unsigned)
     __syncthreads();
     if (tid == 0) {
-        seg_off[0] = 0;
+        L.seg_off[0] = 0;
         for (int s = 1; s <= 54; ++s)
-            seg_off[s] += seg_off[s - 1];
+            L.seg_off[s] += L.seg_off[s - 1];
     }
-
-    const int ps = A.start[c], npc = A.start[c + 1] - ps;
-    const int ns = A.start[C + c], mc = npc + (A.start[C + c + 1] - ns);
-    const int tl = tid / NUC_TPT, q = tid % NUC_TPT;
-    const int tidx = chunk * NUC_CHUNK + tl;
-    const bool active = tidx < mc;
-    const int slot = active ? (tidx < npc ? ps + tidx : ns + (tidx - npc)) : 0;
-    const bool tprot = tidx < npc;
-    const typename P::Src me = stg[slot];
-    const uint3 mef = P::fixed(me, k);
-    const uint32_t me_xy16 = (mef.x >> 16) | (mef.y & 0xffff0000u);
-
-    // bounding box of the chunk's targets (they lie inside one cell: no wrap)
-    if (active && q == 0) {
-        atomicMin(reinterpret_cast<unsigned*>(&misc[0]), mef.x);
-        atomicMin(reinterpret_cast<unsigned*>(&misc[1]), mef.y);
-        atomicMin(reinterpret_cast<unsigned*>(&misc[2]), mef.z);
-        atomicMax(reinterpret_cast<unsigned*>(&misc[3]), mef.x);
-        atomicMax(reinterpret_cast<unsigned*>(&misc[4]), mef.y);
-        atomicMax(reinterpret_cast<unsigned*>(&misc[5]), mef.z);
+    if (in_box) {
+        atomicMin(reinterpret_cast<unsigned*>(&L.misc[0]), mef.x);
+        atomicMin(reinterpret_cast<unsigned*>(&L.misc[1]), mef.y);
+        atomicMin(reinterpret_cast<unsigned*>(&L.misc[2]), mef.z);
+        atomicMax(reinterpret_cast<unsigned*>(&L.misc[3]), mef.x);
+        atomicMax(reinterpret_cast<unsigned*>(&L.misc[4]), mef.y);
+        atomicMax(reinterpret_cast<unsigned*>(&L.misc[5]), mef.z);
     }
     __syncthreads();
-    // box centre and half extent (rounded up): the nearest-image offset of a
-    // source from the centre, less the half extent, is its periodic gap
+}
+
+// Stages the neighbourhood in rounds of SP candidates per thread: locate (a
+// binary search for the first, a short forward walk for the next), load,
+// keep the sources whose periodic gap to the targets' box (centre and half
+// extent, rounded up) is below sqrt(thr_stage) fixed-point units, and
+// compact them in candidate order (so protons stay first).  put(pos, src,
+// fixed, slot) stores a kept source at tile position pos; flush(n, np) is
+// called, by the whole workgroup, when the next round might not fit in a
+// tile of T entries and at the end (np = protons among the n).
+template <class P, int T, class Put, class Flush>
+__device__ __forceinline__ void stage_neighbourhood(const typename P::Src* __restrict__ stg,
+                                                    const NucConsts& k, const ItemLds& L,
+                                                    float thr_stage, Put put, Flush flush)
+{
+    using Lds = typename P::Lds;
+    constexpr int SP = P::STAGE_PER_THREAD;
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    const int total = L.seg_off[54], np_tot = L.seg_off[27];
     uint32_t bc[3], bh[3];
 #pragma unroll
     for (int a = 0; a < 3; ++a) {
-        const uint32_t lo = (uint32_t)misc[a], ext = (uint32_t)misc[3 + a] - lo;
+        const uint32_t lo = (uint32_t)L.misc[a], ext = (uint32_t)L.misc[3 + a] - lo;
         bc[a] = lo + (ext >> 1);
         bh[a] = ext - (ext >> 1);
     }
-
-    typename P::Acc acc;
-    if (NUC) {
-        const int total = seg_off[54], np_tot = seg_off[27];
-        const auto BLp = P::bl(k, tprot), Bp = P::bv(k, tprot);    // proton sources
-        const auto BLn = P::bl(k, !tprot), Bn = P::bv(k, !tprot);  // neutron sources
-        typename P::Part part;
-        int tile_n = 0, tile_np = 0;  // wave-uniform copies of the tile fill
-
-        // evaluate the listed pairs of every lane, then empty the lists
-        auto drain = [&](int cnt, int kb) {
-            for (int kk = 0; __ballot(kk < cnt); kk += 2) {
-                const bool v0 = kk < cnt, v1 = kk + 1 < cnt;
-                const int j0 = v0 ? lists[kk * WG + tid] : 0;
-                const int j1 = v1 ? lists[(kk + 1) * WG + tid] : 0;
-                const Lds s0 = src[j0], s1 = src[j1];
-                const bool p0 = j0 < kb, p1 = j1 < kb;  // protons first in the tile
-                P::template pair<COUNT>(me, s0, p0 ? BLp : BLn, p0 ? Bp : Bn, k, part, v0);
-                P::template pair<COUNT>(me, s1, p1 ? BLp : BLn, p1 ? Bp : Bn, k, part, v1);
-            }
-        };
-        // Screen the tile's sources against this lane's target.  The append
-        // is branch-free: every candidate is written at position cnt and cnt
-        // advances only for survivors (slot cnt < NUC_CAP always exists).
-        // Lanes without a target get a threshold nothing passes.
-        const int thr = active ? k.thr16 : INT_MIN;
-        const bool wave_live = __ballot(active) != 0ull;
-        auto process = [&](int n, int kb) {
-            if (!wave_live)
-                return;
-            int cnt = 0;
-            constexpr int STEP = NUC_TPT * NUC_U;
-            const int nfull = (n / STEP) * STEP;
-            for (int j0 = 0; j0 < nfull; j0 += STEP) {
-                uint2 tv[NUC_U];
+    int tile_n = 0, tile_np = 0;  // workgroup-uniform tile fill
+    for (int base = 0; base < total; base += SP * WG) {
+        bool keep[SP];
+        uint3 f[SP];
+        int gidx[SP], src_idx[SP];
+        int seg = 0;
 #pragma unroll
-                for (int u = 0; u < NUC_U; ++u)
-                    tv[u] = tst[j0 + u * NUC_TPT + q];
-#pragma unroll
-                for (int u = 0; u < NUC_U; ++u) {
-                    const int j = j0 + u * NUC_TPT + q;
-                    lists[cnt * WG + tid] = (uint16_t)j;
-                    cnt += screen16(me_xy16, mef.z, tv[u]) < thr ? 1 : 0;
-                }
-                if (__ballot(cnt > NUC_CAP - NUC_U)) {
-                    drain(cnt, kb);
-                    cnt = 0;
-                }
-            }
-#pragma unroll
-            for (int u = 0; u < NUC_U; ++u) {
-                const int j = nfull + u * NUC_TPT + q;
-                if (j < n) {
-                    lists[cnt * WG + tid] = (uint16_t)j;
-                    cnt += screen16(me_xy16, mef.z, tst[j]) < thr ? 1 : 0;
-                }
-            }
-            drain(cnt, kb);
-            P::fold(acc, part);
-        };
-
-        // Staging rounds of SP candidates per thread: locate (a binary search
-        // for the first, a short forward walk for the next), load, and keep
-        // the sources that can reach the targets' box, compacted in candidate
-        // order so protons stay first.
-        constexpr int SP = P::STAGE_PER_THREAD;
-        for (int base = 0; base < total; base += SP * WG) {
-            bool keep[SP];
-            Lds e[SP];
-            uint3 f[SP];
-            int gidx[SP], src_idx[SP];
-            int seg = 0;
-#pragma unroll
-            for (int u = 0; u < SP; ++u) {
-                gidx[u] = base + u * WG + tid;
-                src_idx[u] = -1;
-                if (gidx[u] < total) {
-                    if (u == 0) {
-                        int hi = 54;
-                        while (hi - seg > 1) {
-                            const int mid = (seg + hi) >> 1;
-                            if (seg_off[mid] <= gidx[u])
-                                seg = mid;
-                            else
-                                hi = mid;
-                        }
-                    } else {
-                        while (seg_off[seg + 1] <= gidx[u])
-                            ++seg;
+        for (int u = 0; u < SP; ++u) {
+            gidx[u] = base + u * WG + tid;
+            src_idx[u] = -1;
+            if (gidx[u] < total) {
+                if (u == 0) {
+                    int hi = 54;
+                    while (hi - seg > 1) {
+                        const int mid = (seg + hi) >> 1;
+                        if (L.seg_off[mid] <= gidx[u])
+                            seg = mid;
+                        else
+                            hi = mid;
                     }
-                    src_idx[u] = seg_beg[seg] + (gidx[u] - seg_off[seg]);
+                } else {
+                    while (L.seg_off[seg + 1] <= gidx[u])
+                        ++seg;
                 }
+                src_idx[u] = L.seg_beg[seg] + (gidx[u] - L.seg_off[seg]);
             }
-            typename P::Src sv[SP];
+        }
+        typename P::Src sv[SP];
 #pragma unroll
-            for (int u = 0; u < SP; ++u)
-                sv[u] = stg[src_idx[u] >= 0 ? src_idx[u] : 0];
+        for (int u = 0; u < SP; ++u)
+            sv[u] = stg[src_idx[u] >= 0 ? src_idx[u] : 0];
 #pragma unroll
-            for (int u = 0; u < SP; ++u) {
-                e[u] = *reinterpret_cast<const Lds*>(&sv[u]);
-                f[u] = P::fixed(sv[u], k);
-                float g2 = 0.f;
-                const uint32_t fv[3] = {f[u].x, f[u].y, f[u].z};
+        for (int u = 0; u < SP; ++u) {
+            f[u] = P::fixed(sv[u], k);
+            float g2 = 0.f;
+            const uint32_t fv[3] = {f[u].x, f[u].y, f[u].z};
 #pragma unroll
-                for (int a = 0; a < 3; ++a) {
-                    const int32_t rel = (int32_t)(fv[a] - bc[a]);
-                    const uint32_t mag = rel < 0 ? (uint32_t)(-(int64_t)rel) : (uint32_t)rel;
-                    const float gf = (float)(mag > bh[a] ? mag - bh[a] : 0u);
-                    g2 += gf * gf;
-                }
-                keep[u] = src_idx[u] >= 0 && g2 < k.thr_stage;
+            for (int a = 0; a < 3; ++a) {
+                const int32_t rel = (int32_t)(fv[a] - bc[a]);
+                const uint32_t mag = rel < 0 ? (uint32_t)(-(int64_t)rel) : (uint32_t)rel;
+                const float gf = (float)(mag > bh[a] ? mag - bh[a] : 0u);
+                g2 += gf * gf;
             }
-            // block compaction in candidate order (u, thread)
-            unsigned long long m[SP];
+            keep[u] = src_idx[u] >= 0 && g2 < thr_stage;
+        }
+        // block compaction in candidate order (u, thread)
+        unsigned long long m[SP];
 #pragma unroll
-            for (int u = 0; u < SP; ++u) {
-                m[u] = __ballot(keep[u]);
-                const unsigned long long mp = __ballot(keep[u] && gidx[u] < np_tot);
-                if (lane == 0) {
-                    misc[6 + u * 4 + wave] = __popcll(m[u]);
-                    misc[14 + u * 4 + wave] = __popcll(mp);
-                }
+        for (int u = 0; u < SP; ++u) {
+            m[u] = __ballot(keep[u]);
+            const unsigned long long mp = __ballot(keep[u] && gidx[u] < np_tot);
+            if (lane == 0) {
+                L.misc[6 + u * 4 + wave] = __popcll(m[u]);
+                L.misc[14 + u * 4 + wave] = __popcll(mp);
             }
-            __syncthreads();
-            int blk = 0, blkp = 0;
-            int off[SP];
+        }
+        __syncthreads();
+        int blk = 0, blkp = 0;
+        int off[SP];
 #pragma unroll
-            for (int u = 0; u < SP; ++u) {
-                off[u] = blk;
-                for (int w = 0; w < WG / 64; ++w) {
-                    off[u] += w < wave ? misc[6 + u * 4 + w] : 0;
-                }
-                for (int w = 0; w < WG / 64; ++w) {
-                    blk += misc[6 + u * 4 + w];
-                    blkp += misc[14 + u * 4 + w];
-                }
+        for (int u = 0; u < SP; ++u) {
+            off[u] = blk;
+            for (int w = 0; w < WG / 64; ++w)
+                off[u] += w < wave ? L.misc[6 + u * 4 + w] : 0;
+            for (int w = 0; w < WG / 64; ++w) {
+                blk += L.misc[6 + u * 4 + w];
+                blkp += L.misc[14 + u * 4 + w];
             }
-            if (tile_n + blk > T) {  // no room: use the tile as it is first
-                process(tile_n, tile_np);
-                tile_n = 0;
-                tile_np = 0;
-                __syncthreads();
-            }
-#pragma unroll
-            for (int u = 0; u < SP; ++u) {
-                if (keep[u]) {
-                    const int pos = tile_n + off[u] + __popcll(m[u] & ((1ull << lane) - 1ull));
-                    src[pos] = e[u];
-                    tst[pos] = make_uint2((f[u].x >> 16) | (f[u].y & 0xffff0000u), f[u].z);
-                }
-            }
-            tile_n += blk;
-            tile_np += blkp;
+        }
+        if (tile_n + blk > T) {  // no room: use the tile as it is first
+            flush(tile_n, tile_np);
+            tile_n = 0;
+            tile_np = 0;
             __syncthreads();
         }
-        if (tile_n > 0)
-            process(tile_n, tile_np);
 #pragma unroll
-        for (int m = 1; m < NUC_TPT; m <<= 1) {
-            acc.fx += __shfl_xor(acc.fx, m, NUC_TPT);
-            acc.fy += __shfl_xor(acc.fy, m, NUC_TPT);
-            acc.fz += __shfl_xor(acc.fz, m, NUC_TPT);
-            acc.e += __shfl_xor(acc.e, m, NUC_TPT);
+        for (int u = 0; u < SP; ++u) {
+            if (keep[u]) {
+                const int pos = tile_n + off[u] + __popcll(m[u] & ((1ull << lane) - 1ull));
+                put(pos, *reinterpret_cast<const Lds*>(&sv[u]), f[u], src_idx[u]);
+            }
+        }
+        tile_n += blk;
+        tile_np += blkp;
+        __syncthreads();
+    }
+    if (tile_n > 0)
+        flush(tile_n, tile_np);
+}
+
+// Epilogue of a nuclear cell item: combine the TPT lanes of each target,
+// then either store the raw nuclear (F, V) per sorted slot (fnuc form) or
+// add the Coulomb partials, write F and E in caller order and apply the
+// optional half kick; finally the fixed-order per-item kinetic-energy and
+// pair-count reductions.  self_in_sum: the target's own r = 0 term (a like
+// pair, V(0) = a + b + c) was summed and is removed here.
+template <class P, int TPT, bool NUC, bool COUNT>
+__device__ void nuclear_finish(const NucArgs& A, const NucConsts& k, typename P::Acc acc,
+                               const ItemTarget& t, int item, bool self_in_sum,
+                               const ItemLds& L)
+{
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    if (NUC) {
+#pragma unroll
+        for (int m = 1; m < TPT; m <<= 1) {
+            acc.fx += __shfl_xor(acc.fx, m, TPT);
+            acc.fy += __shfl_xor(acc.fy, m, TPT);
+            acc.fz += __shfl_xor(acc.fz, m, TPT);
+            acc.e += __shfl_xor(acc.e, m, TPT);
             if (COUNT)
-                acc.np += __shfl_xor(acc.np, m, NUC_TPT);
+                acc.np += __shfl_xor(acc.np, m, TPT);
         }
     }
-
     const double fsc = P::f_scale(k);
     double ke = 0.0;
     unsigned long long npairs = 0;
-    if (active && q == 0) {
+    if (t.active && t.q == 0) {
         if (COUNT)
-            npairs = acc.np - 1u;
-        double V = NUC ? acc.e - k.self_v : 0.0;
+            npairs = acc.np - (self_in_sum ? 1u : 0u);
+        double V = NUC ? acc.e - (self_in_sum ? k.self_v : 0.0) : 0.0;
         double Fx = acc.fx * fsc, Fy = acc.fy * fsc, Fz = acc.fz * fsc;
         if (A.fnuc) {
-            A.fnuc[slot] = make_double4(Fx, Fy, Fz, V);
+            A.fnuc[t.slot] = make_double4(Fx, Fy, Fz, V);
         } else {
-            if (A.S > 0 && tprot) {
+            if (A.S > 0 && t.tprot) {
                 for (int s = 0; s < A.S; ++s) {
-                    const double4 cp = A.coul_part[(int64_t)s * A.Z + slot];
+                    const double4 cp = A.coul_part[(int64_t)s * A.Z + t.slot];
                     Fx += cp.x;
                     Fy += cp.y;
                     Fz += cp.z;
                     V += cp.w;
                 }
             }
-            const int64_t id = A.perm[slot];
+            const int64_t id = A.perm[t.slot];
             A.force[3 * id + 0] = Fx;
             A.force[3 * id + 1] = Fy;
             A.force[3 * id + 2] = Fz;
@@ -804,16 +781,16 @@ __device__ void nuclear_item_compact(const typename P::Src* __restrict__ stg, co
                 npairs += __shfl_xor(npairs, m, 64);
         }
         if (lane == 0) {
-            ke_red[wave] = ke;
-            np_red[wave] = npairs;
+            L.ke_red[wave] = ke;
+            L.np_red[wave] = npairs;
         }
         __syncthreads();
         if (tid == 0) {
             double s = 0.0;
             unsigned long long sn = 0;
             for (int w = 0; w < WG / 64; ++w) {
-                s += ke_red[w];
-                sn += np_red[w];
+                s += L.ke_red[w];
+                sn += L.np_red[w];
             }
             if (A.ke_part && !A.fnuc)
                 A.ke_part[item] = s;
@@ -822,6 +799,106 @@ __device__ void nuclear_item_compact(const typename P::Src* __restrict__ stg, co
         }
         __syncthreads();
     }
+}
+
+template <class P>
+constexpr int nuclear_compact_lds_bytes()
+{
+    return P::CTILE * ((int)sizeof(typename P::Lds) + 8) + NUC_CAP * WG * 2 + ITEM_LDS_BYTES;
+}
+
+template <class P, int TPT, bool NUC, bool COUNT>
+__device__ void nuclear_item_compact_t(const typename P::Src* __restrict__ stg,
+                                       const NucArgs& A, const NucConsts& k, int item, char* lds)
+{
+    using Lds = typename P::Lds;
+    constexpr int T = P::CTILE;
+    Lds* src = reinterpret_cast<Lds*>(lds);
+    uint2* tst = reinterpret_cast<uint2*>(src + T);
+    uint16_t* lists = reinterpret_cast<uint16_t*>(tst + T);
+    const ItemLds L = item_lds(reinterpret_cast<char*>(lists + NUC_CAP * WG));
+    const int tid = threadIdx.x;
+
+    const ItemTarget t = item_target<TPT>(A, item);
+    const typename P::Src me = stg[t.slot];
+    const uint3 mef = P::fixed(me, k);
+    const uint32_t me_xy16 = (mef.x >> 16) | (mef.y & 0xffff0000u);
+    item_setup(A, L, t.c, NUC, t.active && t.q == 0, mef);
+
+    typename P::Acc acc;
+    if (NUC) {
+        const auto BLp = P::bl(k, t.tprot), Bp = P::bv(k, t.tprot);    // proton sources
+        const auto BLn = P::bl(k, !t.tprot), Bn = P::bv(k, !t.tprot);  // neutron sources
+        typename P::Part part;
+        const int q = t.q;
+
+        // evaluate the listed pairs of every lane, then empty the lists
+        auto drain = [&](int cnt, int kb) {
+            for (int kk = 0; __ballot(kk < cnt); kk += 2) {
+                const bool v0 = kk < cnt, v1 = kk + 1 < cnt;
+                const int j0 = v0 ? lists[kk * WG + tid] : 0;
+                const int j1 = v1 ? lists[(kk + 1) * WG + tid] : 0;
+                const Lds s0 = src[j0], s1 = src[j1];
+                const bool p0 = j0 < kb, p1 = j1 < kb;  // protons first in the tile
+                P::template pair<COUNT>(me, s0, p0 ? BLp : BLn, p0 ? Bp : Bn, k, part, v0);
+                P::template pair<COUNT>(me, s1, p1 ? BLp : BLn, p1 ? Bp : Bn, k, part, v1);
+            }
+        };
+        // Screen the tile's sources against this lane's target.  The append
+        // is branch-free: every candidate is written at position cnt and cnt
+        // advances only for survivors (slot cnt < NUC_CAP always exists).
+        // Lanes without a target get a threshold nothing passes.
+        const int thr = t.active ? k.thr16 : INT_MIN;
+        const bool wave_live = __ballot(t.active) != 0ull;
+        auto process = [&](int n, int kb) {
+            if (!wave_live)
+                return;
+            int cnt = 0;
+            constexpr int STEP = TPT * NUC_U;
+            const int nfull = (n / STEP) * STEP;
+            for (int j0 = 0; j0 < nfull; j0 += STEP) {
+                uint2 tv[NUC_U];
+#pragma unroll
+                for (int u = 0; u < NUC_U; ++u)
+                    tv[u] = tst[j0 + u * TPT + q];
+#pragma unroll
+                for (int u = 0; u < NUC_U; ++u) {
+                    const int j = j0 + u * TPT + q;
+                    lists[cnt * WG + tid] = (uint16_t)j;
+                    cnt += screen16(me_xy16, mef.z, tv[u]) < thr ? 1 : 0;
+                }
+                if (__ballot(cnt > NUC_CAP - NUC_U)) {
+                    drain(cnt, kb);
+                    cnt = 0;
+                }
+            }
+#pragma unroll
+            for (int u = 0; u < NUC_U; ++u) {
+                const int j = nfull + u * TPT + q;
+                if (j < n) {
+                    lists[cnt * WG + tid] = (uint16_t)j;
+                    cnt += screen16(me_xy16, mef.z, tst[j]) < thr ? 1 : 0;
+                }
+            }
+            drain(cnt, kb);
+            P::fold(acc, part);
+        };
+        stage_neighbourhood<P, T>(
+            stg, k, L, k.thr_stage,
+            [&](int pos, const Lds& e, const uint3& f, int) {
+                src[pos] = e;
+                tst[pos] = make_uint2((f.x >> 16) | (f.y & 0xffff0000u), f.z);
+            },
+            process);
+    }
+    nuclear_finish<P, TPT, NUC, COUNT>(A, k, acc, t, item, true, L);
+}
+
+template <class P, bool NUC, bool COUNT>
+__device__ void nuclear_item_compact(const typename P::Src* __restrict__ stg, const NucArgs& A,
+                                     const NucConsts& k, int item, char* lds)
+{
+    nuclear_item_compact_t<P, NUC_TPT, NUC, COUNT>(stg, A, k, item, lds);
 }
 
 }  // namespace pasta

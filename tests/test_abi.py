@@ -40,11 +40,23 @@ def test_workspace_queries(B):
         assert nb.value > 51200 * 16 and nb.value % 256 == 0
     g = B.pasta_integrator(2.0, 7.5e-5, 0.5, 100, 0)
     small, big = ctypes.c_size_t(), ctypes.c_size_t()
-    assert B.lib.pasta_sim_workspace(ctypes.byref(p), ctypes.byref(g), 1, 51200, 86.18,
+    assert B.lib.pasta_sim_workspace(ctypes.byref(p), ctypes.byref(g), 1, 51200, 86.18, 86.18,
                                      ctypes.byref(small)) == 0
-    assert B.lib.pasta_sim_workspace(ctypes.byref(p), ctypes.byref(g), 1, 51200, 344.71,
+    assert B.lib.pasta_sim_workspace(ctypes.byref(p), ctypes.byref(g), 1, 51200, 86.18, 344.71,
                                      ctypes.byref(big)) == 0
     assert big.value > small.value  # the cell grid grows with L_max
+    # the list form adds the list memory, sized by the starting density
+    old = B.pasta_set_tuning(nuclear_variant=2, list_skin=2.0)
+    try:
+        dense, dilute = ctypes.c_size_t(), ctypes.c_size_t()
+        assert B.lib.pasta_sim_workspace(ctypes.byref(p), ctypes.byref(g), 1, 51200, 86.18,
+                                         344.71, ctypes.byref(dense)) == 0
+        assert B.lib.pasta_sim_workspace(ctypes.byref(p), ctypes.byref(g), 1, 51200, 172.4,
+                                         344.71, ctypes.byref(dilute)) == 0
+        assert dense.value > dilute.value > 0
+        assert dense.value > big.value
+    finally:
+        B.pasta_set_tuning(**old)
     assert B.lib.pasta_cluster_workspace(3200, 43.09, 4.5, 3.0, ctypes.byref(nb)) == 0
     assert B.lib.pasta_cell_list_workspace(3200, 43.09, 11.5, ctypes.byref(nb)) == 0
 
@@ -81,10 +93,22 @@ def test_argument_errors(B):
     K = ctypes.c_int32()
     assert B.lib.pasta_cluster(10, 8.0, fake, fake, 4.5, 3.0, fake, fake, fake,
                                ctypes.byref(K), None, fake, 1 << 30, None) == -2
+    # tuning: unknown variant, non-positive halo, reserved field set
+    t = B.pasta_tuning()
+    assert B.lib.pasta_get_tuning(ctypes.byref(t)) == 0
+    for field, value in (("nuclear_variant", 3), ("list_skin", 0.0), ("list_skin", -1.0),
+                         ("list_pool_scale", 0.0), ("reserved", 1), ("fused_forces", 2)):
+        bad_t = B.pasta_tuning()
+        ctypes.pointer(bad_t)[0] = t
+        setattr(bad_t, field, value)
+        assert B.lib.pasta_set_tuning(ctypes.byref(bad_t)) == -1, field
+    cur = B.pasta_tuning()
+    assert B.lib.pasta_get_tuning(ctypes.byref(cur)) == 0
+    assert B.tuning_dict(cur) == B.tuning_dict(t)
     # bad integrator
     g = B.pasta_integrator(-1.0, 0.0, 1.0, 0, 0)
     nb = ctypes.c_size_t()
-    assert B.lib.pasta_sim_workspace(ctypes.byref(p), ctypes.byref(g), 0, 10, 30.0,
+    assert B.lib.pasta_sim_workspace(ctypes.byref(p), ctypes.byref(g), 0, 10, 30.0, 30.0,
                                      ctypes.byref(nb)) == -1
 
 

@@ -95,3 +95,49 @@ def test_fp64_rsqrt_refinement(tmp_path_factory):
         ref = 1.0 / math.sqrt(x)
         worst = max(worst, abs(got - ref) / math.ulp(ref))
     assert worst <= 2.0, worst
+
+
+def _min_image(d, L):
+    return d - L * np.round(d / L)
+
+
+@pytest.mark.parametrize("scale_positions", [False, True])
+def test_list_rebuild_bound(scale_positions):
+    """The rebuild rule of the neighbour-list form: if every nearest-image
+    displacement u_i since the build (measured in the current box) satisfies
+    2 max|u| + sqrt(3) |L - L_b| < delta_r, then every pair inside r_nuc now
+    was inside r_nuc + delta_r at the build.  Brute force over random
+    configurations with particles near the faces, random moves of bounded
+    length, wraps, and box growth or shrinkage (with and without the affine
+    variant)."""
+    rng = np.random.Generator(np.random.PCG64(2024))
+    r_nuc = 11.5
+    worst = -np.inf
+    for trial in range(60):
+        n = 300
+        Lb = rng.uniform(23.5, 40.0)
+        yb = rng.uniform(0, Lb, (n, 3))
+        yb[: n // 4] = np.mod(rng.normal(0, 0.3, (n // 4, 3)), Lb)  # crowd a corner
+        dL = rng.uniform(-0.4, 0.6)
+        L = Lb + dL
+        dmax = rng.uniform(0.05, 1.5)
+        step = rng.normal(size=(n, 3))
+        step *= (rng.uniform(0, 1, (n, 1)) * dmax) / np.linalg.norm(step, axis=1, keepdims=True)
+        y = yb + step
+        if scale_positions:
+            y *= L / Lb
+        y = np.mod(y, L)
+        # displacement as the drift kernel measures it, in the current box
+        u = _min_image(y - yb, L)
+        umax = np.sqrt((u * u).sum(axis=1)).max()
+        bound = 2 * umax + np.sqrt(3.0) * abs(L - Lb)
+        d_now = _min_image(y[:, None, :] - y[None, :, :], L)
+        r_now = np.sqrt((d_now ** 2).sum(-1))
+        d_b = _min_image(yb[:, None, :] - yb[None, :, :], Lb)
+        r_b = np.sqrt((d_b ** 2).sum(-1))
+        close = r_now < r_nuc
+        # the claim: r_b <= r_now + bound for every pair (in particular those
+        # inside r_nuc now are inside r_nuc + delta_r once bound < delta_r)
+        excess = (r_b - r_now - bound)[close]
+        worst = max(worst, excess.max())
+    assert worst <= 1e-9, worst
