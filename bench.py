@@ -72,9 +72,11 @@ def run_path(B, torch, st, precision, steps, warmup, timing):
         kt = sim.kernel_times()
         sim.set_timing(False)
     en = sim.energies()
+    ls = sim.list_stats()
     sim.close()
     return dict(seconds=dt_plain, seconds_with_events=dt_timed, nuc_pairs=(nuc0 + nuc1) / 2,
-                coul_pairs=coul, kernel_times=kt, energies=en)
+                coul_pairs=coul, kernel_times=kt, energies=en, list_stats=ls,
+                steps=steps + (steps if timing else 0) + warmup)
 
 
 def run_batch(B, torch, states, precision, mode, steps, warmup, spg=10):
@@ -231,8 +233,24 @@ def main():
     tuned, _, table = tune(tpos, tsp, st["L"], B.PASTA_MIXED, use_cache=False, apply=True)
     log(f"autotuned mixed: {tuned}  fp64: {tuned64}")
     del tpos, tsp
-    mixed = run_path(B, torch, st, B.PASTA_MIXED, K, W, timing=True)
-    log(f"mixed: {mixed['seconds'] / K * 1e3:.4f} ms/step")
+    mixed_cells = run_path(B, torch, st, B.PASTA_MIXED, K, W, timing=True)
+    log(f"mixed, cell sweeps: {mixed_cells['seconds'] / K * 1e3:.4f} ms/step")
+    # the neighbour-list form: halo chosen by short timed runs, then the same
+    # timed protocol; the faster form is the headline
+    from paper_1412_8502_amd.autotune import tune_list_skin
+    tpos = torch.tensor(st["pos"], device=dev)
+    tvel = torch.tensor(st["vel"], device=dev)
+    tsp = torch.tensor(st["species"], device=dev)
+    skin, skin_table = tune_list_skin(tpos, tvel, tsp, st["L"], B.PASTA_MIXED, st["T"])
+    del tpos, tvel, tsp
+    log(f"list halo trials (halo, ms/step, builds in 200 steps): {skin_table} -> {skin}")
+    old = B.pasta_set_tuning(nuclear_variant=2, list_skin=skin)
+    mixed_lists = run_path(B, torch, st, B.PASTA_MIXED, K, W, timing=True)
+    B.pasta_set_tuning(**old)
+    log(f"mixed, neighbour lists: {mixed_lists['seconds'] / K * 1e3:.4f} ms/step, "
+        f"{mixed_lists['list_stats']}")
+    use_lists = mixed_lists["seconds"] < mixed_cells["seconds"]
+    mixed = mixed_lists if use_lists else mixed_cells
     # the dense cell-tile nuclear kernel, for comparison with the default
     # screened + compacted one
     old = B.pasta_set_tuning(nuclear_variant=0, coulomb_splits=0, fused_forces=0)
@@ -242,6 +260,8 @@ def main():
     log(f"mixed, dense nuclear kernel: {dense['seconds'] / kd * 1e3:.4f} ms/step")
     k64 = args.fp64_steps or max(20, K // 4)
     B.pasta_set_tuning(**tuned64)
+    if use_lists:
+        B.pasta_set_tuning(nuclear_variant=2, list_skin=skin)
     fp64 = run_path(B, torch, st, B.PASTA_FP64, k64, min(W, 20), timing=True)
     B.pasta_set_tuning(**tuned)
     log(f"fp64: {fp64['seconds'] / k64 * 1e3:.4f} ms/step")
@@ -260,9 +280,10 @@ def main():
     nuc_fl = 2 * mixed["nuc_pairs"] * FLOPS_NUC_PAIR
     coul_fl = 2 * mixed["coul_pairs"] * FLOPS_COUL_PAIR
     if tuned.get("fused_forces"):
-        # one launch carries both the nuclear cell tiles and the Coulomb tiles
+        # one launch carries both the nuclear items and the Coulomb tiles
         flops = {"nuclear+kick": nuc_fl + coul_fl}
-        kname = {"nuclear+kick": "pair forces (nuclear + Coulomb tiles, one launch)"}
+        kname = {"nuclear+kick": "pair forces (nuclear %s + Coulomb tiles, one launch)"
+                 % ("list items" if use_lists else "cell tiles")}
     else:
         flops = {"coulomb": coul_fl, "nuclear+kick": nuc_fl}
         kname = {}
@@ -333,6 +354,18 @@ def main():
                                              for c, ms in table64]},
         "dense_nuclear_variant": {"ms_per_step": dense["seconds"] / kd * 1e3,
                                   "nuclear_ms": dense["kernel_times"]["nuclear+kick"][0] / kd},
+        "nuclear_form": "neighbour lists" if use_lists else "cell sweeps",
+        "cell_sweeps": {"ms_per_step": mixed_cells["seconds"] / K * 1e3,
+                        "per_kernel_ms": {k: round(v[0] / K, 5)
+                                          for k, v in mixed_cells["kernel_times"].items() if v[1]}},
+        "neighbour_lists": {"ms_per_step": mixed_lists["seconds"] / K * 1e3, "halo_fm": skin,
+                            "halo_trials_ms": [[h, round(ms, 5), nb] for h, ms, nb in skin_table],
+                            "builds": mixed_lists["list_stats"]["builds"],
+                            "steps_run": mixed_lists["steps"],
+                            "overflows": mixed_lists["list_stats"]["overflows"],
+                            "per_kernel_ms": {k: round(v[0] / K, 5)
+                                              for k, v in mixed_lists["kernel_times"].items()
+                                              if v[1]}},
         "ms_per_step_with_events": mixed["seconds_with_events"] / K * 1e3,
         "per_kernel": per_kernel,
         "roofline": roof,

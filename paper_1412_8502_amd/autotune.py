@@ -94,3 +94,36 @@ def tune(pos, species, L: float, precision: int, use_cache: bool = True, apply: 
     if apply:
         B.pasta_set_tuning(**best)
     return best, source, table
+
+
+def tune_list_skin(pos, vel, species, L: float, precision: int, T: float, skins=(1.0, 1.5, 2.0, 3.0),
+                   warmup: int = 50, steps: int = 200, dt: float = 2.0, rescale_every: int = 100):
+    """Chooses the halo of the neighbour-list form by running the simulation:
+    the list form's cost is (force on the lists) + (build) / (steps between
+    builds), and the rebuild interval depends on the dynamics, so each
+    candidate halo advances a copy of the state `warmup` + `steps` steps and
+    the steps are timed.  Leaves the process-wide setting unchanged.
+    Returns (best halo, [(halo, ms per step, builds during the timed steps)])."""
+    table = []
+    old = B.pasta_get_tuning()
+    try:
+        for skin in skins:
+            B.pasta_set_tuning(nuclear_variant=2, list_skin=float(skin))
+            p, v = pos.clone(), vel.clone()
+            sim = B.Sim(p, v, species, L, dt=dt, T=T, rescale_every=rescale_every,
+                        precision=precision)
+            sim.step(warmup)
+            b0 = sim.list_stats()["builds"]
+            torch.cuda.synchronize()
+            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            e0.record()
+            sim.step(steps)
+            e1.record()
+            e1.synchronize()
+            table.append((float(skin), e0.elapsed_time(e1) / steps,
+                          sim.list_stats()["builds"] - b0))
+            sim.close()
+    finally:
+        B.pasta_set_tuning(**old)
+    best = min(table, key=lambda r: r[1])[0]
+    return best, table
