@@ -109,8 +109,12 @@ typedef struct pasta_integrator {
  *   list_skin at the build.  The decision is taken on the device.  If the
  *   list memory runs out, the forces fall back to the screened cell sweep
  *   over the cells of the last build until the next build.  One-shot
- *   pasta_forces builds and uses the lists once.  The batched path treats
- *   2 as 1.  All variants give the same forces to rounding.
+ *   pasta_forces builds and uses the lists once; 3 = as 1 with 8 lanes per
+ *   target and 32 targets per work item (smaller target boxes, so fewer
+ *   staged sources).  Cells are binned by octant inside, so the targets of
+ *   a work item are spatially compact.  The batched path treats 2 and 3 as
+ *   1.  A simulation keeps the variant it was created with.  All variants
+ *   give the same forces to rounding.
  * coulomb_splits: number of source ranges per Coulomb target tile, 1..32;
  *   0 = automatic (about 2^19 / Z, at most 32).
  * fused_forces: 0 = the Coulomb kernel, then the nuclear kernel whose
@@ -134,7 +138,7 @@ int pasta_set_tuning(const pasta_tuning* t);
 int pasta_get_tuning(pasta_tuning* out);
 /* Autotuner: builds the cell list of the given state once, then times the
  * Coulomb + nuclear kernels (reps evaluations each, HIP events) for every
- * candidate setting -- nuclear variant {0, 1} x Coulomb splits {S/2, S, 2S}
+ * candidate setting -- nuclear variant {0, 1, 3} x Coulomb splits {S/2, S, 2S}
  * around the automatic S x fused_forces {0, 1} -- and returns the fastest
  * in *h_best (the list fields copied from the current setting; the list
  * form's cost depends on how often the lists are rebuilt, which a single

@@ -61,7 +61,7 @@ def pasta_autotune(pos, species, L: float, precision: int, reps: int = 3, pot=No
                                             ctypes.byref(nb)))
     work = B._workspace(nb.value, pos.device)
     best = B.pasta_tuning()
-    cap = 16
+    cap = 32
     ms = (ctypes.c_double * cap)()
     cands = (B.pasta_tuning * cap)()
     ncand = ctypes.c_int32(cap)

@@ -148,9 +148,13 @@ static PairParams pair_params(const pasta_potential* p, double L)
     return pp;
 }
 
-// Neighbour-list settings of a workspace: off, or on with halo `skin` and
-// pool sized for box sides down to L_min.
+// Nuclear-kernel settings of a workspace: the variant (0 dense, 1 compact,
+// 2 lists, 3 compact with 8 lanes per target), and for the list form the
+// halo and the pool sized for box sides down to L_min.  Calls without the
+// nuclear terms use variant 1's layout.
+constexpr int CELL_SUB = 8;  // octant bins inside each cell (compact chunks)
 struct ListCfg {
+    int variant = 1;
     bool on = false;
     double skin = 0.0;
     double L_min = 0.0;
@@ -159,10 +163,17 @@ struct ListCfg {
 static ListCfg list_cfg(int terms, double L_min)
 {
     ListCfg c;
-    c.on = g_tuning.nuclear_variant == 2 && (terms & PASTA_TERM_NUCLEAR);
+    c.variant = (terms & PASTA_TERM_NUCLEAR) ? g_tuning.nuclear_variant : 1;
+    c.on = c.variant == 2;
     c.skin = g_tuning.list_skin;
     c.L_min = L_min;
     c.pool_scale = g_tuning.list_pool_scale;
+    return c;
+}
+static ListCfg cfg_variant(int v)
+{
+    ListCfg c;
+    c.variant = v;
     return c;
 }
 // cell width of the grid: r_nuc, or r_nuc + skin for the list form
@@ -177,6 +188,8 @@ struct ForceWork {
     ForceBuf fb;
     ListBuf lb;
     bool lists;
+    int variant;
+    int chunk;
     uint32_t* err;
     double* red;  // [256] reduction partials
     double* scale;  // [2]
@@ -185,8 +198,9 @@ static size_t force_carve(Carver& cv, ForceWork* w, int64_t n, int C_max, int pr
                           const pasta_potential* pot, const ListCfg& lc, int64_t pool_rows = -1)
 {
     ForceWork fw;
-    const int chunk = nuclear_chunk(precision, lc.on);
-    cellbuf_carve(cv, &fw.cb, n, C_max, chunk);
+    fw.variant = lc.variant;
+    fw.chunk = nuclear_chunk_for(lc.variant);
+    cellbuf_carve(cv, &fw.cb, n, C_max, fw.chunk, CELL_SUB);
     forcebuf_carve(cv, &fw.fb, n, fw.cb.item_max, precision);
     fw.err = cv.take<uint32_t>(1);
     fw.red = cv.take<double>(256);
@@ -233,7 +247,7 @@ static int build_cells(const double* pos, const uint8_t* species, int64_t n, con
                        Timer* t)
 {
     launch_bin_count(pos, species, n, g, w.cb, w.err, s, t);
-    launch_scan(w.cb, g.C, nuclear_chunk(precision, w.lists), s, t);
+    launch_scan(w.cb, g, w.chunk, s, t);
     launch_scatter_rank(pos, species, n, g, w.cb, w.fb.stg64, w.fb.stgq, s, t, false, nullptr,
                         w.lists ? w.lb.xb : nullptr);
     if (w.lists) {
@@ -251,7 +265,7 @@ static void eval_forces(int precision, int terms, const ForceWork& w, const Grid
     if (g_tuning.fused_forces && (terms & PASTA_TERM_NUCLEAR)) {
         launch_forces_fused(precision, w.fb, w.cb, g, n, Z, pp, true,
                             (terms & PASTA_TERM_COULOMB) != 0, force, epot, kick, pair_counter,
-                            w.err, s, t, lb);
+                            w.err, s, t, w.variant, lb);
         return;
     }
     int S = 0;
@@ -260,7 +274,7 @@ static void eval_forces(int precision, int terms, const ForceWork& w, const Grid
         S = coulomb_splits(Z);
     }
     launch_nuclear(precision, w.fb, w.cb, g, n, Z, pp, (terms & PASTA_TERM_NUCLEAR) != 0, S,
-                   force, epot, kick, pair_counter, w.err, s, t, lb);
+                   force, epot, kick, pair_counter, w.err, s, t, w.variant, lb);
 }
 
 }  // namespace pasta
@@ -289,7 +303,7 @@ extern "C" void pasta_potential_paper(pasta_potential* out)
 
 extern "C" int pasta_set_tuning(const pasta_tuning* t)
 {
-    if (!t || t->nuclear_variant < 0 || t->nuclear_variant > 2 || t->coulomb_splits < 0 ||
+    if (!t || t->nuclear_variant < 0 || t->nuclear_variant > 3 || t->coulomb_splits < 0 ||
         t->coulomb_splits > 32 || (t->fused_forces != 0 && t->fused_forces != 1) ||
         t->reserved != 0 || !(t->list_skin > 0.0 && t->list_skin <= 64.0) ||
         !(t->list_pool_scale > 0.0 && t->list_pool_scale <= 1e3))
@@ -349,7 +363,7 @@ extern "C" int pasta_cell_list(int64_t n, double L, double r_cut, const double* 
     PASTA_HIP(hipMemsetAsync(err, 0, sizeof(uint32_t), s));
     cellbuf_zero(cb, g.C, s);
     launch_bin_count(d_pos, d_species, n, g, cb, err, s, nullptr);
-    launch_scan(cb, g.C, 0, s, nullptr);
+    launch_scan(cb, g, 0, s, nullptr);
     launch_scatter_rank(d_pos, d_species, n, g, cb, nullptr, nullptr, s, nullptr);
     PASTA_HIP(hipMemcpyAsync(d_cell_start, cb.start, sizeof(int32_t) * (2 * (size_t)g.C + 1),
                              hipMemcpyDeviceToDevice, s));
@@ -370,7 +384,7 @@ extern "C" int pasta_forces_workspace(const pasta_potential* pot, int32_t precis
         (precision != PASTA_FP64 && precision != PASTA_MIXED))
         return fail(PASTA_EINVAL, "pasta_forces_workspace: bad argument");
     const ListCfg lc = list_cfg(PASTA_TERM_ALL, L);
-    const Grid g = make_grid(L, cell_cut(pot, lc));
+    const Grid g = make_grid(L, cell_cut(pot, lc), CELL_SUB);
     Carver cv(nullptr);
     *h_bytes = force_carve(cv, nullptr, n, g.C, precision, pot, lc);
     return PASTA_OK;
@@ -397,7 +411,7 @@ extern "C" int pasta_forces(const pasta_potential* pot, int32_t precision, int32
     // a call without the nuclear terms uses the cell-sweep layout, which is
     // smaller than the list layout the workspace query may have sized
     const ListCfg lc = list_cfg(terms, L);
-    const Grid g = make_grid(L, cell_cut(pot, lc));
+    const Grid g = make_grid(L, cell_cut(pot, lc), CELL_SUB);
     Carver cv0(nullptr);
     PASTA_TRY(check_work(d_work, work_bytes, force_carve(cv0, nullptr, n, g.C, precision, pot, lc),
                          "pasta_forces"));
@@ -408,10 +422,11 @@ extern "C" int pasta_forces(const pasta_potential* pot, int32_t precision, int32
     PASTA_HIP(hipMemsetAsync(w.err, 0, sizeof(uint32_t), s));
     if (w.lists)
         PASTA_HIP(hipMemsetAsync(w.lb.ctl, 0, sizeof(ListCtl), s));
-    cellbuf_zero(w.cb, g.C, s);
+    cellbuf_zero(w.cb, g.C, s, g.sub);
     build_cells(d_pos, d_species, n, g, w, precision, pp, s, nullptr);
     int32_t Z = 0;
-    PASTA_HIP(hipMemcpyAsync(&Z, w.cb.start + g.C, sizeof(int32_t), hipMemcpyDeviceToHost, s));
+    PASTA_HIP(hipMemcpyAsync(&Z, w.cb.start + (int64_t)g.C * g.sub, sizeof(int32_t),
+                             hipMemcpyDeviceToHost, s));
     PASTA_HIP(hipStreamSynchronize(s));
     KickArgs kick{nullptr, 0.0, pot->mass, nullptr};
     eval_forces(precision, terms, w, g, n, Z, pp, d_force, d_epot, kick, nullptr, s, nullptr);
@@ -422,8 +437,9 @@ extern "C" int pasta_forces(const pasta_potential* pot, int32_t precision, int32
 // -------------------------------------------------------------- tuning
 // Times the two pair kernels (Coulomb + nuclear with its epilogue) on the
 // given state for every candidate setting and keeps the fastest.  Candidates:
-// nuclear variant {dense, compacted} x Coulomb source splits {S/2, S, 2S}
-// around the automatic S (clamped to 1..32).  The cell list is built once.
+// nuclear variant {dense, compacted, compacted with 8 lanes per target} x
+// Coulomb source splits {S/2, S, 2S} around the automatic S (clamped to
+// 1..32) x fused {0, 1}.  The cell list is built once per item size.
 extern "C" int pasta_autotune(const pasta_potential* pot, int32_t precision, int64_t n, double L,
                               const double* d_pos, const uint8_t* d_species, void* d_work,
                               size_t work_bytes, void* stream, int32_t reps, pasta_tuning* h_best,
@@ -435,24 +451,40 @@ extern "C" int pasta_autotune(const pasta_potential* pot, int32_t precision, int
         return fail(PASTA_EINVAL, "pasta_autotune: bad argument");
     if (L < 2.0 * pot->r_nuc)
         return fail(PASTA_EBOX, "pasta_autotune: L < 2 r_nuc");
-    const ListCfg no_lists;
+    // laid out for the 32-target items (the larger item list); 64-target
+    // candidates use a prefix of it
+    const ListCfg lay = cfg_variant(3);
     Carver cvn(nullptr);
-    const Grid g = make_grid(L, pot->r_nuc);
-    force_carve(cvn, nullptr, n, g.C, precision, pot, no_lists);
+    const Grid g = make_grid(L, pot->r_nuc, CELL_SUB);
+    force_carve(cvn, nullptr, n, g.C, precision, pot, lay);
     cvn.take<double>(4 * (size_t)n);  // scratch force + energy outputs
     PASTA_TRY(check_work(d_work, work_bytes, cvn.size(), "pasta_autotune"));
     hipStream_t s = static_cast<hipStream_t>(stream);
     ForceWork w;
     Carver cv(d_work);
-    force_carve(cv, &w, n, g.C, precision, pot, no_lists);
+    force_carve(cv, &w, n, g.C, precision, pot, lay);
+    const int64_t items32 = w.cb.item_max;
+    const int64_t items64 = n / nuclear_chunk_for(1) + g.C + 1;
     double* f = cv.take<double>(3 * (size_t)n);
     double* e = cv.take<double>((size_t)n);
     const PairParams pp = pair_params(pot, L);
     PASTA_HIP(hipMemsetAsync(w.err, 0, sizeof(uint32_t), s));
-    cellbuf_zero(w.cb, g.C, s);
-    build_cells(d_pos, d_species, n, g, w, precision, pp, s, nullptr);
+    cellbuf_zero(w.cb, g.C, s, g.sub);
     int32_t Z = 0;
-    PASTA_HIP(hipMemcpyAsync(&Z, w.cb.start + g.C, sizeof(int32_t), hipMemcpyDeviceToHost, s));
+    int built_chunk = 0;
+    // (re)builds the cell list for a candidate's item size
+    auto cells_for = [&](int variant) {
+        w.variant = variant;
+        w.chunk = nuclear_chunk_for(variant);
+        w.cb.item_max = w.chunk == nuclear_chunk_for(1) ? items64 : items32;
+        if (w.chunk != built_chunk) {
+            build_cells(d_pos, d_species, n, g, w, precision, pp, s, nullptr);
+            built_chunk = w.chunk;
+        }
+    };
+    cells_for(1);
+    PASTA_HIP(hipMemcpyAsync(&Z, w.cb.start + (int64_t)g.C * g.sub, sizeof(int32_t),
+                             hipMemcpyDeviceToHost, s));
     PASTA_HIP(hipStreamSynchronize(s));
 
     const pasta_tuning saved = g_tuning;
@@ -464,7 +496,7 @@ extern "C" int pasta_autotune(const pasta_potential* pot, int32_t precision, int
     const int S0 = Z > 0 ? coulomb_splits(Z) : 1;
     std::vector<pasta_tuning> cands;
     for (int fused = 0; fused <= 1; ++fused)
-        for (int v = 0; v <= 1; ++v) {
+        for (int v : {0, 1, 3}) {
             int last = -1;
             for (int sc : {S0 / 2, S0, 2 * S0}) {
                 int sv = sc < 1 ? 1 : (sc > 32 ? 32 : sc);
@@ -487,6 +519,7 @@ extern "C" int pasta_autotune(const pasta_potential* pot, int32_t precision, int
     int rc = PASTA_OK;
     for (size_t c = 0; c < cands.size() && rc == PASTA_OK; ++c) {
         g_tuning = cands[c];
+        cells_for(cands[c].nuclear_variant);
         // one untimed warm-up, then reps timed evaluations
         eval_forces(precision, PASTA_TERM_ALL, w, g, n, Z, pp, f, e, kick, nullptr, s, nullptr);
         if (hipEventRecord(e0, s) != hipSuccess) {
@@ -531,9 +564,9 @@ extern "C" int pasta_autotune_workspace(const pasta_potential* pot, int32_t prec
     if (!h_bytes || n < 0 || !(L > 0.0) || !std::isfinite(L) ||
         (precision != PASTA_FP64 && precision != PASTA_MIXED))
         return fail(PASTA_EINVAL, "pasta_autotune_workspace: bad argument");
-    const Grid g = make_grid(L, pot->r_nuc);
+    const Grid g = make_grid(L, pot->r_nuc, CELL_SUB);
     Carver cv(nullptr);
-    force_carve(cv, nullptr, n, g.C, precision, pot, ListCfg());
+    force_carve(cv, nullptr, n, g.C, precision, pot, cfg_variant(3));
     cv.take<double>(3 * (size_t)n);
     cv.take<double>((size_t)n);
     *h_bytes = cv.size();
@@ -600,7 +633,7 @@ extern "C" int pasta_sim_workspace(const pasta_potential* pot, const pasta_integ
         !std::isfinite(L_start) || (precision != PASTA_FP64 && precision != PASTA_MIXED))
         return fail(PASTA_EINVAL, "pasta_sim_workspace: bad argument");
     const ListCfg lc = list_cfg(PASTA_TERM_ALL, L_start);
-    const Grid g = make_grid(L_max > L_start ? L_max : L_start, cell_cut(pot, lc));
+    const Grid g = make_grid(L_max > L_start ? L_max : L_start, cell_cut(pot, lc), CELL_SUB);
     Carver cv(nullptr);
     *h_bytes = sim_carve(cv, nullptr, nullptr, nullptr, n, g.C, precision, pot, lc);
     return PASTA_OK;
@@ -610,11 +643,12 @@ static int sim_eval_initial(pasta_sim* sim)
 {
     hipStream_t s = sim->stream;
     const double L = box_side(sim, sim->step);
-    const Grid g = make_grid(L, sim->r_cell);
+    const Grid g = make_grid(L, sim->r_cell, CELL_SUB);
     const PairParams pp = pair_params(&sim->pot, L);
     build_cells(sim->pos, sim->species, sim->n, g, sim->w, sim->precision, pp, s, &sim->timer);
     int32_t Z = 0;
-    PASTA_HIP(hipMemcpyAsync(&Z, sim->w.cb.start + g.C, sizeof(int32_t), hipMemcpyDeviceToHost, s));
+    PASTA_HIP(hipMemcpyAsync(&Z, sim->w.cb.start + (int64_t)g.C * g.sub, sizeof(int32_t),
+                             hipMemcpyDeviceToHost, s));
     PASTA_HIP(hipStreamSynchronize(s));
     sim->Z = Z;
     KickArgs kick{nullptr, 0.0, sim->pot.mass, nullptr};
@@ -656,12 +690,12 @@ extern "C" int pasta_sim_create(const pasta_potential* pot, const pasta_integrat
         delete sim;
         return fail(PASTA_EBOX, "pasta_sim_create: L = %g < 2 r_nuc", Lstart);
     }
-    // the list form (nuclear_variant 2 when the simulation is created) keeps
-    // its setting for the life of the simulation; the list memory takes the
-    // rest of the workspace
+    // the nuclear variant (and the list settings) in force when the
+    // simulation is created stay with it; the list memory takes the rest of
+    // the workspace
     const ListCfg lc = list_cfg(PASTA_TERM_ALL, Lstart);
     sim->r_cell = cell_cut(pot, lc);
-    sim->C_max = make_grid(sim->L_max, sim->r_cell).C;
+    sim->C_max = make_grid(sim->L_max, sim->r_cell, CELL_SUB).C;
     Carver cv0(nullptr);
     const size_t need =
         sim_carve(cv0, nullptr, nullptr, nullptr, n, sim->C_max, precision, pot, lc, 1);
@@ -690,7 +724,7 @@ extern "C" int pasta_sim_create(const pasta_potential* pot, const pasta_integrat
         delete sim;
         return fail(PASTA_EHIP, "hipMemsetAsync failed");
     }
-    cellbuf_zero(sim->w.cb, sim->C_max, s);
+    cellbuf_zero(sim->w.cb, sim->C_max, s, CELL_SUB);
     if (sim->w.lists && hipMemsetAsync(sim->w.lb.ctl, 0, sizeof(ListCtl), s) != hipSuccess) {
         delete sim;
         return fail(PASTA_EHIP, "hipMemsetAsync failed");
@@ -717,7 +751,7 @@ extern "C" int pasta_sim_step(pasta_sim* sim, int64_t nsteps)
         if (L_new > sim->L_max * (1.0 + 1e-12) || L_new < 2.0 * sim->pot.r_nuc)
             return fail(PASTA_EBOX, "pasta_sim_step: box side %g at step %lld is outside "
                         "[2 r_nuc, L_max = %g]", L_new, (long long)(n0 + 1), sim->L_max);
-        const Grid g = make_grid(L_new, sim->r_cell);
+        const Grid g = make_grid(L_new, sim->r_cell, CELL_SUB);
         DriftArgs da;
         da.pos = sim->pos;
         da.vel = sim->vel;
@@ -739,14 +773,13 @@ extern "C" int pasta_sim_step(pasta_sim* sim, int64_t nsteps)
                               sim->w.err, s, &sim->timer);
             launch_bin_count(sim->pos, sim->species, sim->n, g, sim->w.cb, sim->w.err, s,
                              &sim->timer, gate);
-            launch_scan(sim->w.cb, g.C, nuclear_chunk(sim->precision, true), s, &sim->timer,
-                        gate);
+            launch_scan(sim->w.cb, g, sim->w.chunk, s, &sim->timer, gate);
             launch_scatter_rank(sim->pos, sim->species, sim->n, g, sim->w.cb, sim->w.fb.stg64,
                                 sim->w.fb.stgq, s, &sim->timer, true, gate, lb.xb);
             launch_list_build(sim->precision, sim->w.fb, sim->w.cb, g, lb, pp, s, &sim->timer);
         } else {
             launch_drift(da, g, sim->w.cb, sim->w.err, s, &sim->timer);
-            launch_scan(sim->w.cb, g.C, nuclear_chunk(sim->precision), s, &sim->timer);
+            launch_scan(sim->w.cb, g, sim->w.chunk, s, &sim->timer);
             launch_scatter_rank(sim->pos, sim->species, sim->n, g, sim->w.cb, sim->w.fb.stg64,
                                 sim->w.fb.stgq, s, &sim->timer, true);
         }
@@ -814,7 +847,7 @@ extern "C" int pasta_sim_pair_counts(pasta_sim* sim, int64_t* h_nuclear, int64_t
         return fail(PASTA_EINVAL, "pasta_sim_pair_counts: null sim");
     hipStream_t s = sim->stream;
     const double L = box_side(sim, sim->step);
-    const Grid g = make_grid(L, sim->r_cell);
+    const Grid g = make_grid(L, sim->r_cell, CELL_SUB);
     uint64_t* ctr = sim->w.fb.pairs;
     PASTA_HIP(hipMemsetAsync(ctr, 0, 2 * sizeof(uint64_t), s));
     KickArgs kick{nullptr, 0.0, sim->pot.mass, nullptr};

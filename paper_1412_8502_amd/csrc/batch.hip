@@ -388,6 +388,7 @@ __device__ void phase_forces(const BatchDev& B, int64_t step, int mode, char* ld
             A.perm = B.perm + S.off;
             A.nc = gr.nc;
             A.C = gr.C;
+            A.sub = 1;
             A.Z = S.Z;
             A.fnuc = B.fnuc + S.off;  // raw nuclear part; combine adds the rest
             A.pairs = B.pairs + s;
@@ -960,7 +961,8 @@ extern "C" int pasta_batch_create(const pasta_potential* pot, int32_t precision,
     B.pp.lambda_s = pot->lambda_s;
     B.pp.L = 0.0;
     B.mass = pot->mass;
-    B.nuc_variant = g_tuning.nuclear_variant == 0 ? 0 : 1;  // lists: single systems only
+    // the batch's items hold 64 targets: variants 2 and 3 run as 1
+    B.nuc_variant = g_tuning.nuclear_variant == 0 ? 0 : 1;
     B.pos = d_pos;
     B.vel = d_vel;
     B.species = d_species;

@@ -21,8 +21,9 @@ namespace {
 
 __global__ __launch_bounds__(256) void k_bin_count(const double* __restrict__ pos,
                                                    const uint8_t* __restrict__ species,
-                                                   int64_t n, int nc, int C, double inv_w,
-                                                   double L, int32_t* __restrict__ key,
+                                                   int64_t n, int nc, int C, int sub,
+                                                   double inv_w, double L,
+                                                   int32_t* __restrict__ key,
                                                    int32_t* __restrict__ count,
                                                    uint32_t* __restrict__ err,
                                                    const int32_t* __restrict__ gate)
@@ -36,9 +37,7 @@ __global__ __launch_bounds__(256) void k_bin_count(const double* __restrict__ po
         atomicOr(err, (isfinite(x) && isfinite(y) && isfinite(z)) ? ERR_RANGE : ERR_NONFINITE_POS);
     if (sp > 1)
         atomicOr(err, ERR_SPECIES);
-    int cx = cell_coord(x, inv_w, nc), cy = cell_coord(y, inv_w, nc),
-        cz = cell_coord(z, inv_w, nc);
-    int bin = (sp == 1 ? 0 : C) + (cz * nc + cy) * nc + cx;
+    const int bin = particle_bin(x, y, z, sp == 1, inv_w, nc, C, sub);
     key[i] = bin;
     wave_aggregated_add(count, bin);
 }
@@ -71,7 +70,8 @@ __device__ int64_t block_scan_runs(const int32_t* v, int32_t* out, int64_t m,
 __global__ __launch_bounds__(SCAN_THREADS) void k_scan(int32_t* __restrict__ count,
                                                        int32_t* __restrict__ fill,
                                                        int32_t* __restrict__ start, int C,
-                                                       int chunk, int32_t* __restrict__ items,
+                                                       int sub, int chunk,
+                                                       int32_t* __restrict__ items,
                                                        int32_t* __restrict__ n_items,
                                                        int32_t* __restrict__ tmpc,
                                                        const int32_t* __restrict__ gate)
@@ -80,15 +80,18 @@ __global__ __launch_bounds__(SCAN_THREADS) void k_scan(int32_t* __restrict__ cou
     if (gate && *gate == 0)
         return;
     const int tid = threadIdx.x;
-    const int64_t nb = 2 * (int64_t)C;
+    const int64_t nb = 2 * (int64_t)C * sub;
     int64_t total = block_scan_runs(count, start, nb, lds);
     if (tid == 0)
         start[nb] = (int32_t)total;
     __syncthreads();
     if (chunk > 0) {
         // chunks per cell (protons + neutrons of the cell)
+        const int64_t CS = (int64_t)C * sub;
         for (int64_t c = tid; c < C; c += SCAN_THREADS) {
-            int32_t m = count[c] + count[C + c];
+            int32_t m = 0;
+            for (int o = 0; o < sub; ++o)
+                m += count[c * sub + o] + count[CS + c * sub + o];
             tmpc[c] = (m + chunk - 1) / chunk;
         }
         __syncthreads();
@@ -194,14 +197,15 @@ inline unsigned blocks_for(int64_t n, int bs) { return (unsigned)((n + bs - 1) /
 
 }  // namespace
 
-size_t cellbuf_carve(Carver& cv, CellBuf* out, int64_t n, int C_max, int chunk)
+size_t cellbuf_carve(Carver& cv, CellBuf* out, int64_t n, int C_max, int chunk, int sub)
 {
     CellBuf cb;
+    const int64_t nb = 2 * (int64_t)C_max * sub;
     cb.key = cv.take<int32_t>(n);
-    cb.count = cv.take<int32_t>(2 * (size_t)C_max);
-    cb.fill = cv.take<int32_t>(2 * (size_t)C_max);
-    cb.start = cv.take<int32_t>(2 * (size_t)C_max + 1);
-    cb.tmp = cv.take<int32_t>(n > 2 * (int64_t)C_max ? n : 2 * (int64_t)C_max);
+    cb.count = cv.take<int32_t>((size_t)nb);
+    cb.fill = cv.take<int32_t>((size_t)nb);
+    cb.start = cv.take<int32_t>((size_t)nb + 1);
+    cb.tmp = cv.take<int32_t>(n > nb ? n : nb);
     cb.perm = cv.take<int32_t>(n);
     cb.item_max = chunk > 0 ? n / chunk + C_max + 1 : 1;
     cb.items = cv.take<int32_t>(2 * (size_t)cb.item_max);
@@ -211,9 +215,9 @@ size_t cellbuf_carve(Carver& cv, CellBuf* out, int64_t n, int C_max, int chunk)
     return cv.size();
 }
 
-void cellbuf_zero(const CellBuf& cb, int C_max, hipStream_t s)
+void cellbuf_zero(const CellBuf& cb, int C_max, hipStream_t s, int sub)
 {
-    int64_t m = 2 * (int64_t)C_max;
+    int64_t m = 2 * (int64_t)C_max * sub;
     k_zero2<<<blocks_for(m, 256), 256, 0, s>>>(cb.count, cb.fill, m);
 }
 
@@ -223,17 +227,18 @@ void launch_bin_count(const double* pos, const uint8_t* species, int64_t n, cons
 {
     timer_begin(t, KC_DRIFT, s);
     if (n > 0)
-        k_bin_count<<<blocks_for(n, 256), 256, 0, s>>>(pos, species, n, g.nc, g.C, g.inv_w,
-                                                       g.L, cb.key, cb.count, err, gate);
+        k_bin_count<<<blocks_for(n, 256), 256, 0, s>>>(pos, species, n, g.nc, g.C, g.sub,
+                                                       g.inv_w, g.L, cb.key, cb.count, err,
+                                                       gate);
     timer_end(t, KC_DRIFT, s);
 }
 
-void launch_scan(const CellBuf& cb, int C, int chunk, hipStream_t s, Timer* t,
+void launch_scan(const CellBuf& cb, const Grid& g, int chunk, hipStream_t s, Timer* t,
                  const int32_t* gate)
 {
     timer_begin(t, KC_SCAN, s);
     // cb.tmp doubles as the per-cell chunk-count scratch (2C entries)
-    k_scan<<<1, SCAN_THREADS, 0, s>>>(cb.count, cb.fill, cb.start, C, chunk, cb.items,
+    k_scan<<<1, SCAN_THREADS, 0, s>>>(cb.count, cb.fill, cb.start, g.C, g.sub, chunk, cb.items,
                                       cb.n_items, cb.tmp, gate);
     timer_end(t, KC_SCAN, s);
 }

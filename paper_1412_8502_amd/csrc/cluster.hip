@@ -341,7 +341,7 @@ extern "C" int pasta_cluster(int64_t n, double L, const double* d_pos, const uin
     PASTA_HIP(hipMemsetAsync(b.err, 0, sizeof(uint32_t), s));
     cellbuf_zero(b.cb, g.C, s);
     launch_bin_count(d_pos, d_species, n, g, b.cb, b.err, s, nullptr);
-    launch_scan(b.cb, g.C, 0, s, nullptr);
+    launch_scan(b.cb, g, 0, s, nullptr);
     launch_scatter_rank(d_pos, d_species, n, g, b.cb, nullptr, nullptr, s, nullptr);
 
     ClusterArgs a{};

@@ -40,7 +40,7 @@ __global__ __launch_bounds__(WG) void k_nuclear(const typename P::Src* __restric
     nuclear_item<P, NUC, COUNT>(stg, A, k, blockIdx.x, lds);
 }
 
-template <class P, bool NUC, bool COUNT>
+template <class P, int TPT, bool NUC, bool COUNT>
 __global__ __launch_bounds__(WG) void k_nuclear_compact(const typename P::Src* __restrict__ stg,
                                                         NucArgs A,
                                                         const int32_t* __restrict__ n_items,
@@ -49,7 +49,7 @@ __global__ __launch_bounds__(WG) void k_nuclear_compact(const typename P::Src* _
     __shared__ __align__(16) char lds[nuclear_compact_lds_bytes<P>()];
     if ((int)blockIdx.x >= *n_items)
         return;
-    nuclear_item_compact<P, NUC, COUNT>(stg, A, k, blockIdx.x, lds);
+    nuclear_item_compact_t<P, TPT, NUC, COUNT>(stg, A, k, blockIdx.x, lds);
 }
 
 // List form of a nuclear item: the lists of the last build, or, when that
@@ -112,6 +112,8 @@ __global__ __launch_bounds__(WG) void k_forces_fused(const typename P::Src* __re
             return;
         if (nuc_variant == 2)
             nuclear_item_listed<P, COUNT>(stg, A, k, LA, g, lds);
+        else if (nuc_variant == 3)
+            nuclear_item_compact_t<P, 8, true, COUNT>(stg, A, k, g, lds);
         else if (nuc_variant == 1)
             nuclear_item_compact<P, true, COUNT>(stg, A, k, g, lds);
         else
@@ -185,10 +187,14 @@ void nuclear_dispatch(const typename P::Src* stg, const NucArgs& a, const int32_
 {
     if (!nuc)
         k_nuclear<P, false, false><<<grid, WG, 0, s>>>(stg, a, n_items, k);
+    else if (variant == 3 && count)
+        k_nuclear_compact<P, 8, true, true><<<grid, WG, 0, s>>>(stg, a, n_items, k);
+    else if (variant == 3)
+        k_nuclear_compact<P, 8, true, false><<<grid, WG, 0, s>>>(stg, a, n_items, k);
     else if (variant == 1 && count)
-        k_nuclear_compact<P, true, true><<<grid, WG, 0, s>>>(stg, a, n_items, k);
+        k_nuclear_compact<P, NUC_TPT, true, true><<<grid, WG, 0, s>>>(stg, a, n_items, k);
     else if (variant == 1)
-        k_nuclear_compact<P, true, false><<<grid, WG, 0, s>>>(stg, a, n_items, k);
+        k_nuclear_compact<P, NUC_TPT, true, false><<<grid, WG, 0, s>>>(stg, a, n_items, k);
     else if (count)
         k_nuclear<P, true, true><<<grid, WG, 0, s>>>(stg, a, n_items, k);
     else
@@ -197,7 +203,7 @@ void nuclear_dispatch(const typename P::Src* stg, const NucArgs& a, const int32_
 
 }  // namespace
 
-int nuclear_chunk(int /*precision*/, bool lists) { return lists ? LIST_CHUNK : NUC_CHUNK; }
+int nuclear_chunk_for(int variant) { return (variant == 2 || variant == 3) ? LIST_CHUNK : NUC_CHUNK; }
 
 static ListArgs list_args(const ListBuf* lb)
 {
@@ -249,6 +255,7 @@ void launch_list_build(int precision, const ForceBuf& fb, const CellBuf& cb, con
     a.perm = cb.perm;
     a.nc = g.nc;
     a.C = g.C;
+    a.sub = g.sub;
     const ListArgs la = list_args(&lb);
     timer_begin(t, KC_LIST, s);
     if (precision == PASTA_FP64)
@@ -279,7 +286,7 @@ void launch_forces_fused(int precision, const ForceBuf& fb, const CellBuf& cb, c
                          int64_t n, int64_t Z, const PairParams& pp, bool with_nuclear_terms,
                          bool with_coulomb, double* force, double* epot, const KickArgs& kick,
                          uint64_t* pair_counter, uint32_t* err, hipStream_t s, Timer* t,
-                         const ListBuf* lb)
+                         int variant, const ListBuf* lb)
 {
     const NucConsts k = make_nuc_consts(pp);
     const CoulConsts kc = make_coul_consts(pp);
@@ -292,6 +299,7 @@ void launch_forces_fused(int precision, const ForceBuf& fb, const CellBuf& cb, c
     a.perm = cb.perm;
     a.nc = g.nc;
     a.C = g.C;
+    a.sub = g.sub;
     a.Z = (int)Z;
     a.pairs = reinterpret_cast<unsigned long long*>(pair_counter);
     a.err = err;
@@ -300,7 +308,8 @@ void launch_forces_fused(int precision, const ForceBuf& fb, const CellBuf& cb, c
     const int item_max = (int)cb.item_max;
     const unsigned grid = (unsigned)(item_max + coul_blocks * S);
     const bool count = pair_counter != nullptr;
-    const int variant = lb ? 2 : (g_tuning.nuclear_variant == 0 ? 0 : 1);
+    if (variant == 2 && !lb)
+        variant = 1;
     const ListArgs la = list_args(lb);
     timer_begin(t, KC_NUCLEAR, s);
     if (grid > 0) {
@@ -370,7 +379,7 @@ void launch_nuclear(int precision, const ForceBuf& fb, const CellBuf& cb, const 
                     int64_t n, int64_t Z, const PairParams& pp, bool with_nuclear_terms,
                     int coul_S, double* force, double* epot, const KickArgs& kick,
                     uint64_t* pair_counter, uint32_t* err, hipStream_t s, Timer* t,
-                    const ListBuf* lb)
+                    int variant, const ListBuf* lb)
 {
     (void)n;
     const NucConsts k = make_nuc_consts(pp);
@@ -380,6 +389,7 @@ void launch_nuclear(int precision, const ForceBuf& fb, const CellBuf& cb, const 
     a.perm = cb.perm;
     a.nc = g.nc;
     a.C = g.C;
+    a.sub = g.sub;
     a.Z = (int)Z;
     a.coul_part = fb.coul_part;
     a.S = coul_S;
@@ -394,9 +404,8 @@ void launch_nuclear(int precision, const ForceBuf& fb, const CellBuf& cb, const 
     a.fnuc = nullptr;
     const unsigned grid = (unsigned)cb.item_max;
     const bool count = pair_counter != nullptr;
-    const int variant = g_tuning.nuclear_variant == 0 ? 0 : 1;
     timer_begin(t, KC_NUCLEAR, s);
-    if (lb && with_nuclear_terms) {
+    if (variant == 2 && lb && with_nuclear_terms) {
         const ListArgs la = list_args(lb);
         if (precision == PASTA_FP64) {
             if (count)

@@ -18,7 +18,7 @@ namespace {
 
 // Particles are visited in the order of the previous cell build (perm), so
 // the lanes of a wave mostly fall in one bin and the count atomics aggregate.
-__global__ __launch_bounds__(256) void k_drift(DriftArgs a, int nc, int C, double inv_w,
+__global__ __launch_bounds__(256) void k_drift(DriftArgs a, int nc, int C, int sub, double inv_w,
                                                const int32_t* __restrict__ order,
                                                int32_t* __restrict__ key,
                                                int32_t* __restrict__ count,
@@ -29,7 +29,7 @@ __global__ __launch_bounds__(256) void k_drift(DriftArgs a, int nc, int C, doubl
         return;
     const int64_t i = order[s];
     const double L = a.L_new;
-    int cc[3];
+    double xn[3];
     uint32_t bad = 0;
 #pragma unroll
     for (int d = 0; d < 3; ++d) {
@@ -51,11 +51,11 @@ __global__ __launch_bounds__(256) void k_drift(DriftArgs a, int nc, int C, doubl
             bad |= ERR_NONFINITE_VEL;
         a.vel[3 * i + d] = v;
         a.pos[3 * i + d] = x;
-        cc[d] = cell_coord(x, inv_w, nc);
+        xn[d] = x;
     }
     if (bad)
         atomicOr(err, bad);
-    const int bin = (a.species[i] == 1 ? 0 : C) + (cc[2] * nc + cc[1]) * nc + cc[0];
+    const int bin = particle_bin(xn[0], xn[1], xn[2], a.species[i] == 1, inv_w, nc, C, sub);
     key[i] = bin;
     wave_aggregated_add(count, bin);
 }
@@ -250,7 +250,7 @@ void launch_drift(const DriftArgs& a, const Grid& g, const CellBuf& cb, uint32_t
     if (a.n <= 0)
         return;
     timer_begin(t, KC_DRIFT, s);
-    k_drift<<<(unsigned)((a.n + 255) / 256), 256, 0, s>>>(a, g.nc, g.C, g.inv_w, cb.perm,
+    k_drift<<<(unsigned)((a.n + 255) / 256), 256, 0, s>>>(a, g.nc, g.C, g.sub, g.inv_w, cb.perm,
                                                           cb.key, cb.count, err);
     timer_end(t, KC_DRIFT, s);
 }

@@ -71,17 +71,24 @@ inline int cell_dims(double L, double r_cut)
     return nc < 1 ? 1 : nc;
 }
 
+// sub = bins per cell and species: 1, or 8 (the cell's octants, so that a
+// run of consecutive slots inside a cell is spatially compact).  Bin of a
+// particle = (proton ? 0 : C*sub) + cell*sub + octant; a cell's protons are
+// the bins [cell*sub, cell*sub + sub), its neutrons the same range + C*sub.
 struct Grid {
     int nc;        // cells per side
     int C;         // nc^3
+    int sub;       // bins per cell and species (1 or 8)
     double inv_w;  // nc / L  (cell coordinate = floor(x * inv_w))
     double L;
+    int64_t nbins() const { return 2 * (int64_t)C * sub; }
 };
-inline Grid make_grid(double L, double r_cut)
+inline Grid make_grid(double L, double r_cut, int sub = 1)
 {
     Grid g;
     g.nc = cell_dims(L, r_cut);
     g.C = g.nc * g.nc * g.nc;
+    g.sub = sub;
     g.inv_w = (double)g.nc / L;
     g.L = L;
     return g;
@@ -97,6 +104,35 @@ __device__ inline int cell_coord(double x, double inv_w, int nc)
     int k = (int)(x * inv_w);
     k = k > nc - 1 ? nc - 1 : k;
     return k < 0 ? 0 : k;
+}
+
+// Bin of a particle (see Grid).  The octant bit along an axis is whether
+// the fractional cell coordinate a = x * inv_w is at least 1/2; floor(2a)
+// is exact in binary, so the cell is floor(2a) / 2 and agrees with
+// cell_coord.
+__device__ inline int particle_bin(double x, double y, double z, bool proton, double inv_w,
+                                   int nc, int C, int sub)
+{
+    const double a[3] = {x * inv_w, y * inv_w, z * inv_w};
+    int k[3], o = 0;
+#pragma unroll
+    for (int d = 0; d < 3; ++d) {
+        int h = (int)(2.0 * a[d]);
+        int c = h >> 1;
+        h &= 1;
+        if (c > nc - 1) {
+            c = nc - 1;
+            h = 1;
+        }
+        if (c < 0) {
+            c = 0;
+            h = 0;
+        }
+        k[d] = c;
+        o |= h << d;
+    }
+    const int cell = (k[2] * nc + k[1]) * nc + k[0];
+    return (proton ? 0 : C * sub) + cell * sub + (sub == 8 ? o : 0);
 }
 
 // Wave-aggregated atomic add of 1 per lane on counters[bin]: lanes of a
@@ -221,17 +257,18 @@ size_t listbuf_carve(Carver& cv, ListBuf* out, int64_t n, int64_t item_max, int6
 // -------------------------------------------------------- cell-list build
 struct CellBuf {
     int32_t* key;     // [n] bin of each particle (caller order)
-    int32_t* count;   // [2C_max] per-bin counts (zero between builds)
-    int32_t* fill;    // [2C_max] per-bin scatter cursors (zero between builds)
-    int32_t* start;   // [2C_max + 1]
+    int32_t* count;   // [2 C_max sub] per-bin counts (zero between builds)
+    int32_t* fill;    // [2 C_max sub] per-bin scatter cursors (zero between builds)
+    int32_t* start;   // [2 C_max sub + 1]
     int32_t* tmp;     // [n] unsorted slots
     int32_t* perm;    // [n] slot -> particle index
     int32_t* items;   // [2 * item_max] nuclear work items (cell, chunk)
     int32_t* n_items; // [1]
     int64_t item_max;
 };
-size_t cellbuf_carve(Carver& cv, CellBuf* out, int64_t n, int C_max, int chunk);
-void cellbuf_zero(const CellBuf& cb, int C_max, hipStream_t s);
+// C_max: the largest cell count; sub: bins per cell and species.
+size_t cellbuf_carve(Carver& cv, CellBuf* out, int64_t n, int C_max, int chunk, int sub = 1);
+void cellbuf_zero(const CellBuf& cb, int C_max, hipStream_t s, int sub = 1);
 
 // Bins + counts from positions (caller order); the drift kernel does the
 // same inside the integrator.
@@ -242,7 +279,7 @@ void launch_bin_count(const double* pos, const uint8_t* species, int64_t n, cons
                       const int32_t* gate = nullptr);
 // Exclusive scan of the 2C counts into start[]; zeroes count and fill; when
 // chunk > 0, also writes the nuclear work list.
-void launch_scan(const CellBuf& cb, int C, int chunk, hipStream_t s, Timer* t,
+void launch_scan(const CellBuf& cb, const Grid& g, int chunk, hipStream_t s, Timer* t,
                  const int32_t* gate = nullptr);
 // Stable scatter: slot order = (bin, particle index).  Writes perm and, when
 // staging pointers are given, the sorted staging coordinates.  prev_order:
@@ -291,10 +328,10 @@ void launch_nuclear(int precision, const ForceBuf& fb, const CellBuf& cb, const 
                     int64_t n, int64_t Z, const PairParams& pp, bool with_nuclear_terms,
                     int coul_S, double* force, double* epot, const KickArgs& kick,
                     uint64_t* pair_counter, uint32_t* err, hipStream_t s, Timer* t,
-                    const ListBuf* lb = nullptr);
-// Targets per nuclear work item (the scan's chunk): 64 for cell sweeps, 32
-// for the list form (8 lanes per target).
-int nuclear_chunk(int precision, bool lists = false);
+                    int variant, const ListBuf* lb = nullptr);
+// Targets per nuclear work item (the scan's chunk) for a nuclear variant:
+// 64 for variants 0 and 1 (4 lanes per target), 32 for 2 and 3 (8 lanes).
+int nuclear_chunk_for(int variant);
 // Neighbour-list build (gated on lb.ctl->rebuild) for the cells of grid g.
 void launch_list_build(int precision, const ForceBuf& fb, const CellBuf& cb, const Grid& g,
                        const ListBuf& lb, const PairParams& pp, hipStream_t s, Timer* t);
@@ -330,7 +367,7 @@ void launch_forces_fused(int precision, const ForceBuf& fb, const CellBuf& cb, c
                          int64_t n, int64_t Z, const PairParams& pp, bool with_nuclear_terms,
                          bool with_coulomb, double* force, double* epot, const KickArgs& kick,
                          uint64_t* pair_counter, uint32_t* err, hipStream_t s, Timer* t,
-                         const ListBuf* lb = nullptr);
+                         int variant, const ListBuf* lb = nullptr);
 // Thermostat: reduce ke_part[0 .. *n_items) and scale velocities to
 // KE = 1.5 N T.  scale_out receives the factor.
 void launch_thermostat(double* vel, int64_t n, const double* ke_part, const int32_t* n_items,

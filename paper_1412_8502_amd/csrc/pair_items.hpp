@@ -314,10 +314,11 @@ __device__ void coulomb_item(const typename P::Src* __restrict__ stg, int Z, int
 
 // ============================================================ nuclear ==
 struct NucArgs {
-    const int32_t* start;    // [2C+1]
+    const int32_t* start;    // [2 C sub + 1]
     const int32_t* items;    // [2*item_max]
     const int32_t* perm;     // [n]
     int nc, C;
+    int sub;                 // bins per cell and species (1 or 8)
     int Z;
     const double4* coul_part;
     int S;                   // Coulomb splits to add (0 = none)
@@ -357,9 +358,9 @@ __device__ void nuclear_item(const typename P::Src* __restrict__ stg, const NucA
         if (ox >= lo && ox <= hi && oy >= lo && oy <= hi && oz >= lo && oz <= hi) {
             const int nx = (cx + ox + nc) % nc, ny = (cy + oy + nc) % nc,
                       nz = (cz + oz + nc) % nc;
-            const int b = sp * C + (nz * nc + ny) * nc + nx;
+            const int b = (sp * C + (nz * nc + ny) * nc + nx) * A.sub;
             beg = A.start[b];
-            len = A.start[b + 1] - beg;
+            len = A.start[b + A.sub] - beg;
         }
         seg_beg[tid] = beg;
         seg_off[tid + 1] = len;
@@ -372,8 +373,8 @@ __device__ void nuclear_item(const typename P::Src* __restrict__ stg, const NucA
     }
     __syncthreads();
 
-    const int ps = A.start[c], npc = A.start[c + 1] - ps;
-    const int ns = A.start[C + c], mc = npc + (A.start[C + c + 1] - ns);
+    const int ps = A.start[c * A.sub], npc = A.start[(c + 1) * A.sub] - ps;
+    const int ns = A.start[(C + c) * A.sub], mc = npc + (A.start[(C + c + 1) * A.sub] - ns);
     const int tl = tid / NUC_TPT, q = tid % NUC_TPT;
     const int tidx = chunk * NUC_CHUNK + tl;
     const bool active = tidx < mc;
@@ -544,8 +545,9 @@ __device__ inline ItemTarget item_target(const NucArgs& A, int item)
     ItemTarget t;
     t.c = A.items[2 * item + 0];
     const int chunk = A.items[2 * item + 1];
-    const int ps = A.start[t.c], npc = A.start[t.c + 1] - ps;
-    const int ns = A.start[A.C + t.c], mc = npc + (A.start[A.C + t.c + 1] - ns);
+    const int S = A.sub;
+    const int ps = A.start[t.c * S], npc = A.start[(t.c + 1) * S] - ps;
+    const int ns = A.start[(A.C + t.c) * S], mc = npc + (A.start[(A.C + t.c + 1) * S] - ns);
     t.tl = threadIdx.x / TPT;
     t.q = threadIdx.x % TPT;
     const int tidx = chunk * (WG / TPT) + t.tl;
@@ -572,9 +574,9 @@ __device__ inline void item_setup(const NucArgs& A, const ItemLds& L, int c, boo
         if (nuc && ox >= lo && ox <= hi && oy >= lo && oy <= hi && oz >= lo && oz <= hi) {
             const int nx = (cx + ox + nc) % nc, ny = (cy + oy + nc) % nc,
                       nz = (cz + oz + nc) % nc;
-            const int b = sp * C + (nz * nc + ny) * nc + nx;
+            const int b = (sp * C + (nz * nc + ny) * nc + nx) * A.sub;
             beg = A.start[b];
-            len = A.start[b + 1] - beg;
+            len = A.start[b + A.sub] - beg;
         }
         L.seg_beg[tid] = beg;
         L.seg_off[tid + 1] = len;

@@ -96,7 +96,7 @@ def test_argument_errors(B):
     # tuning: unknown variant, non-positive halo, reserved field set
     t = B.pasta_tuning()
     assert B.lib.pasta_get_tuning(ctypes.byref(t)) == 0
-    for field, value in (("nuclear_variant", 3), ("list_skin", 0.0), ("list_skin", -1.0),
+    for field, value in (("nuclear_variant", 4), ("list_skin", 0.0), ("list_skin", -1.0),
                          ("list_pool_scale", 0.0), ("reserved", 1), ("fused_forces", 2)):
         bad_t = B.pasta_tuning()
         ctypes.pointer(bad_t)[0] = t

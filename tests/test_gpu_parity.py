@@ -124,8 +124,9 @@ def test_forces_full_size_sampled(env, name, prec):
 
 @pytest.mark.parametrize("prec", [0, 1])
 def test_nuclear_variants_agree(env, prec):
-    """The dense cell-tile kernel and the screened + compacted kernel give the
-    same forces to rounding, and both match the oracle."""
+    """The dense cell-tile kernel and the screened + compacted kernel (4 or 8
+    lanes per target) give the same forces to rounding, and all match the
+    oracle."""
     B = env["B"]
     st = env["I"].make_state(9000, 0.3, 0.06, 1.0, seed=61)
     pos, sp = to_dev(env, st)
@@ -133,7 +134,7 @@ def test_nuclear_variants_agree(env, prec):
     old = B.pasta_get_tuning()
     try:
         for fused in (0, 1):
-            for v in (0, 1):
+            for v in (0, 1, 3):
                 B.pasta_set_tuning(nuclear_variant=v, fused_forces=fused)
                 out.append(B.pasta_forces(pos, sp, st["L"], precision=prec))
     finally:
@@ -148,13 +149,14 @@ def test_nuclear_variants_agree(env, prec):
         assert d <= (1e-14 if prec == 0 else 1e-6)
 
 
+@pytest.mark.parametrize("variant", [1, 3])
 @pytest.mark.parametrize("fused", [0, 1])
-def test_trajectory_both_forms(env, fused):
+def test_trajectory_both_forms(env, fused, variant):
     """The unfused (kick in the nuclear epilogue) and fused (combine kernel)
-    step forms both follow the oracle."""
+    step forms both follow the oracle, with 4 or 8 lanes per target."""
     B = env["B"]
     st = env["I"].make_state(2500, 0.3, 0.05, 1.0, seed=71)
-    old = B.pasta_set_tuning(fused_forces=fused)
+    old = B.pasta_set_tuning(fused_forces=fused, nuclear_variant=variant)
     try:
         sim, pos, vel = make_sim(env, st, dt=2.0, T=1.0, rescale_every=4, precision=0)
         sim.step(9)
