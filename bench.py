@@ -198,6 +198,11 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--batch-steps", type=int, default=500)
     ap.add_argument("--no-batch", action="store_true")
+    ap.add_argument("--tuning", default=None,
+                    help="variant,splits,fused: use this kernel setting instead of autotuning")
+    ap.add_argument("--headline-only", action="store_true",
+                    help="time only the headline path (no dense, list, FP64 or batched runs); "
+                         "for profiler runs")
     ap.add_argument("--copy-calibration-mib", type=int, default=0,
                     help="run one plain device-to-device copy of this size first (a "
                          "known-size kernel for scaling hardware byte counters)")
@@ -229,12 +234,32 @@ def main():
     dev = torch.device("cuda:0")
     tpos = torch.tensor(st["pos"], device=dev)
     tsp = torch.tensor(st["species"], device=dev)
-    tuned64, _, table64 = tune(tpos, tsp, st["L"], B.PASTA_FP64, use_cache=False, apply=False)
-    tuned, _, table = tune(tpos, tsp, st["L"], B.PASTA_MIXED, use_cache=False, apply=True)
-    log(f"autotuned mixed: {tuned}  fp64: {tuned64}")
+    if args.tuning:
+        v, sp_, fu = (int(x) for x in args.tuning.split(","))
+        tuned = dict(nuclear_variant=v, coulomb_splits=sp_, fused_forces=fu)
+        tuned64, table, table64 = dict(tuned), [], []
+        B.pasta_set_tuning(**tuned)
+    else:
+        tuned64, _, table64 = tune(tpos, tsp, st["L"], B.PASTA_FP64, use_cache=False,
+                                   apply=False)
+        tuned, _, table = tune(tpos, tsp, st["L"], B.PASTA_MIXED, use_cache=False, apply=True)
+    log(f"kernel setting mixed: {tuned}  fp64: {tuned64}")
     del tpos, tsp
     mixed_cells = run_path(B, torch, st, B.PASTA_MIXED, K, W, timing=True)
     log(f"mixed, cell sweeps: {mixed_cells['seconds'] / K * 1e3:.4f} ms/step")
+    if args.headline_only:
+        useful = mixed_cells["nuc_pairs"] + mixed_cells["coul_pairs"]
+        kt = mixed_cells["kernel_times"]
+        fl = 2 * mixed_cells["nuc_pairs"] * FLOPS_NUC_PAIR + 2 * mixed_cells["coul_pairs"] * FLOPS_COUL_PAIR
+        ms_f, nl = kt["nuclear+kick"]
+        print(json.dumps({"metric": "headline path only (profiler run)", "steps": K, "warmup": W,
+                          "ms_per_step": mixed_cells["seconds"] / K * 1e3,
+                          "value": useful * K / mixed_cells["seconds"],
+                          "unit": "pair interactions/s", "tuning": tuned,
+                          "pair_forces_avg_launch_ms": ms_f / max(nl, 1),
+                          "pair_forces_tflops": fl / (ms_f / max(nl, 1) * 1e-3) / 1e12,
+                          "per_kernel_ms": {k: round(v[0] / K, 5) for k, v in kt.items() if v[1]}}))
+        return
     # the neighbour-list form: halo chosen by short timed runs, then the same
     # timed protocol; the faster form is the headline
     from paper_1412_8502_amd.autotune import tune_list_skin

@@ -31,8 +31,8 @@ struct SysDev {
     int32_t n, Z;
     double L0, xi_dot, dt, T, hdtm;
     int32_t rescale_every, scale_positions;
-    int64_t bin_off;      // count/fill: 2*C_max entries
-    int64_t start_off;    // start: 2*C_max + 1 entries
+    int64_t bin_off;      // count/fill: 2*C_max*BSUB entries
+    int64_t start_off;    // start: 2*C_max*BSUB + 1 entries
     int64_t item_off;     // nuclear items: item_max pairs
     int32_t item_max;
     int64_t coul_off;     // Coulomb partials: S*Z entries
@@ -96,9 +96,13 @@ __device__ __forceinline__ double box_at(const SysDev& S, int64_t step)
     return S.L0 * (1.0 + S.xi_dot * ((double)step * S.dt));
 }
 
+// octant bins inside each cell, as in the single-system path
+constexpr int BSUB = 8;
+
 __device__ __forceinline__ Grid grid_at(double L, double r_cut)
 {
     Grid g;
+    g.sub = BSUB;
     int nc = (int)floor(L / r_cut);
     while (nc > 1 && L / (double)nc < r_cut)
         nc--;
@@ -180,7 +184,7 @@ __device__ void phase_drift(const BatchDev& B, int64_t step, int mode)
         const int64_t i = S.off + (mode ? B.perm[S.off + sl] : sl);
         double* x = B.pos + 3 * i;
         double* v = B.vel + 3 * i;
-        int cc[3];
+        double xn[3];
         if (mode) {
             const double sc = B.pending[s];
             const double ratio = L_new / L_old;
@@ -201,7 +205,7 @@ __device__ void phase_drift(const BatchDev& B, int64_t step, int mode)
                 }
                 v[d] = vv;
                 x[d] = xx;
-                cc[d] = cell_coord(xx, gr.inv_w, gr.nc);
+                xn[d] = xx;
             }
             if (bad)
                 atomicOr(B.err, bad);
@@ -211,10 +215,11 @@ __device__ void phase_drift(const BatchDev& B, int64_t step, int mode)
                 const double xx = x[d];
                 if (!(xx >= 0.0 && xx < L_new))
                     atomicOr(B.err, ERR_RANGE);
-                cc[d] = cell_coord(xx, gr.inv_w, gr.nc);
+                xn[d] = xx;
             }
         }
-        const int bin = (B.species[i] == 1 ? 0 : gr.C) + (cc[2] * gr.nc + cc[1]) * gr.nc + cc[0];
+        const int bin = particle_bin(xn[0], xn[1], xn[2], B.species[i] == 1, gr.inv_w, gr.nc, gr.C,
+                                     gr.sub);
         B.key[i] = bin;
         wave_aggregated_add(B.count + S.bin_off, bin);
     }
@@ -249,15 +254,18 @@ __device__ void phase_scan(const BatchDev& B, int64_t step, int mode, char* lds_
         int32_t* count = B.count + S.bin_off;
         int32_t* fill = B.fill + S.bin_off;
         int32_t* start = B.start + S.start_off;
-        const int64_t nb = 2 * (int64_t)gr.C;
+        const int64_t nb = gr.nbins();
         const int64_t total = block_exscan(count, start, nb, lds);
         if (threadIdx.x == 0)
             start[nb] = (int32_t)total;
         __syncthreads();
         // nuclear work list: ceil(members / NUC_CHUNK) items per cell; fill
         // doubles as scratch for the per-cell item counts
+        const int64_t CS = (int64_t)gr.C * gr.sub;
         for (int64_t c = threadIdx.x; c < gr.C; c += BW) {
-            const int32_t m = count[c] + count[gr.C + c];
+            int32_t m = 0;
+            for (int o = 0; o < gr.sub; ++o)
+                m += count[c * gr.sub + o] + count[CS + c * gr.sub + o];
             fill[c] = (m + NUC_CHUNK - 1) / NUC_CHUNK;
         }
         __syncthreads();
@@ -388,7 +396,7 @@ __device__ void phase_forces(const BatchDev& B, int64_t step, int mode, char* ld
             A.perm = B.perm + S.off;
             A.nc = gr.nc;
             A.C = gr.C;
-            A.sub = 1;
+            A.sub = gr.sub;
             A.Z = S.Z;
             A.fnuc = B.fnuc + S.off;  // raw nuclear part; combine adds the rest
             A.pairs = B.pairs + s;
@@ -737,8 +745,8 @@ int batch_layout(const pasta_potential* pot, int nsys, const int64_t* n, const i
         S.coul_item_off = lay.coul_items;
         S.nuc_item_off = lay.nuc_items;
         lay.n_total += n[s];
-        lay.bins += 2 * (int64_t)C_max;
-        lay.starts += 2 * (int64_t)C_max + 1;
+        lay.bins += 2 * (int64_t)C_max * BSUB;
+        lay.starts += 2 * (int64_t)C_max * BSUB + 1;
         lay.items += S.item_max;
         // capacity for any proton count Z <= n: S(Z) Z <= max(min(32 n, 2^19), n)
         const int64_t cap32 = 32 * n[s] < 524288 ? 32 * n[s] : 524288;

@@ -14,6 +14,8 @@
 // sources, then combine by wavefront shuffles.  The epilogue adds the Coulomb
 // partials, writes F and E in the caller's particle order and can apply the
 // velocity-Verlet second half kick (fused integrate).
+#include <type_traits>
+
 #include "list_items.hpp"
 
 namespace pasta {
@@ -94,27 +96,34 @@ __global__ __launch_bounds__(WG) void k_list_build(const typename P::Src* __rest
 
 // Fused form: blocks [0, item_max) are nuclear cell tiles (raw nuclear
 // force and energy per sorted slot), blocks after them Coulomb tiles.
-template <class P, bool COUNT>
+// One instantiation per nuclear variant (V), so each kernel carries only
+// its own item code (registers and LDS sized for it).
+template <class P, int V>
+constexpr int fused_lds_bytes()
+{
+    constexpr int a = coulomb_lds_bytes<P>();
+    constexpr int b = V == 0 ? nuclear_lds_bytes<P>() : nuclear_compact_lds_bytes<P>();
+    return a > b ? a : b;
+}
+
+template <class P, bool COUNT, int V>
 __global__ __launch_bounds__(WG) void k_forces_fused(const typename P::Src* __restrict__ stg,
                                                      NucArgs A, const int32_t* __restrict__ n_items,
-                                                     int item_max, int nuc_variant, NucConsts k,
-                                                     int Z, int per_split, int coul_blocks,
+                                                     int item_max, NucConsts k, int Z,
+                                                     int per_split, int coul_blocks,
                                                      CoulConsts kc, double4* __restrict__ part,
                                                      ListArgs LA)
 {
-    constexpr int a = coulomb_lds_bytes<P>(), b = nuclear_lds_bytes<P>(),
-                  c = nuclear_compact_lds_bytes<P>();
-    constexpr int m0 = a > b ? a : b;
-    __shared__ __align__(16) char lds[m0 > c ? m0 : c];
+    __shared__ __align__(16) char lds[fused_lds_bytes<P, V>()];
     const int g = blockIdx.x;
     if (g < item_max) {
         if (g >= *n_items)
             return;
-        if (nuc_variant == 2)
+        if constexpr (V == 2)
             nuclear_item_listed<P, COUNT>(stg, A, k, LA, g, lds);
-        else if (nuc_variant == 3)
+        else if constexpr (V == 3)
             nuclear_item_compact_t<P, 8, true, COUNT>(stg, A, k, g, lds);
-        else if (nuc_variant == 1)
+        else if constexpr (V == 1)
             nuclear_item_compact<P, true, COUNT>(stg, A, k, g, lds);
         else
             nuclear_item<P, true, COUNT>(stg, A, k, g, lds);
@@ -313,24 +322,33 @@ void launch_forces_fused(int precision, const ForceBuf& fb, const CellBuf& cb, c
     const ListArgs la = list_args(lb);
     timer_begin(t, KC_NUCLEAR, s);
     if (grid > 0) {
-        if (precision == PASTA_FP64) {
-            if (count)
-                k_forces_fused<Fp64Policy, true><<<grid, WG, 0, s>>>(
-                    fb.stg64, a, cb.n_items, item_max, variant, k, (int)Z, per, coul_blocks, kc,
-                    fb.coul_part, la);
-            else
-                k_forces_fused<Fp64Policy, false><<<grid, WG, 0, s>>>(
-                    fb.stg64, a, cb.n_items, item_max, variant, k, (int)Z, per, coul_blocks, kc,
-                    fb.coul_part, la);
-        } else {
-            if (count)
-                k_forces_fused<MixedPolicy, true><<<grid, WG, 0, s>>>(
-                    fb.stgq, a, cb.n_items, item_max, variant, k, (int)Z, per, coul_blocks, kc,
-                    fb.coul_part, la);
-            else
-                k_forces_fused<MixedPolicy, false><<<grid, WG, 0, s>>>(
-                    fb.stgq, a, cb.n_items, item_max, variant, k, (int)Z, per, coul_blocks, kc,
-                    fb.coul_part, la);
+        auto go = [&](auto vtag) {
+            constexpr int V = decltype(vtag)::value;
+            if (precision == PASTA_FP64) {
+                if (count)
+                    k_forces_fused<Fp64Policy, true, V><<<grid, WG, 0, s>>>(
+                        fb.stg64, a, cb.n_items, item_max, k, (int)Z, per, coul_blocks, kc,
+                        fb.coul_part, la);
+                else
+                    k_forces_fused<Fp64Policy, false, V><<<grid, WG, 0, s>>>(
+                        fb.stg64, a, cb.n_items, item_max, k, (int)Z, per, coul_blocks, kc,
+                        fb.coul_part, la);
+            } else {
+                if (count)
+                    k_forces_fused<MixedPolicy, true, V><<<grid, WG, 0, s>>>(
+                        fb.stgq, a, cb.n_items, item_max, k, (int)Z, per, coul_blocks, kc,
+                        fb.coul_part, la);
+                else
+                    k_forces_fused<MixedPolicy, false, V><<<grid, WG, 0, s>>>(
+                        fb.stgq, a, cb.n_items, item_max, k, (int)Z, per, coul_blocks, kc,
+                        fb.coul_part, la);
+            }
+        };
+        switch (variant) {
+        case 0: go(std::integral_constant<int, 0>()); break;
+        case 2: go(std::integral_constant<int, 2>()); break;
+        case 3: go(std::integral_constant<int, 3>()); break;
+        default: go(std::integral_constant<int, 1>()); break;
         }
     }
     timer_end(t, KC_NUCLEAR, s);

@@ -81,7 +81,7 @@ struct Grid {
     int sub;       // bins per cell and species (1 or 8)
     double inv_w;  // nc / L  (cell coordinate = floor(x * inv_w))
     double L;
-    int64_t nbins() const { return 2 * (int64_t)C * sub; }
+    __host__ __device__ int64_t nbins() const { return 2 * (int64_t)C * sub; }
 };
 inline Grid make_grid(double L, double r_cut, int sub = 1)
 {

@@ -434,7 +434,7 @@ def test_autotuner(env, tmp_path, monkeypatch):
     before = B.pasta_get_tuning()
     best, table = autotune.pasta_autotune(pos, sp, st["L"], B.PASTA_MIXED)
     assert B.pasta_get_tuning() == before
-    assert len(table) >= 4 and {0, 1} == {c["nuclear_variant"] for c, _ in table}
+    assert len(table) >= 6 and {0, 1, 3} == {c["nuclear_variant"] for c, _ in table}
     assert min(table, key=lambda r: r[1])[0] == best
     got, source, _ = autotune.tune(pos, sp, st["L"], B.PASTA_MIXED, apply=True)
     again, source2, _ = autotune.tune(pos, sp, st["L"], B.PASTA_MIXED, apply=True)
