@@ -41,6 +41,34 @@ def log(*a):
     print(*a, file=sys.stderr, flush=True)
 
 
+def measured_traffic(kernel_name, tuning):
+    """HBM bytes per launch of the pair-force kernel from the counter runs
+    recorded under profiles/ (FETCH_SIZE and WRITE_SIZE, each scaled by what
+    the counter reads for a copy of known size), or None when the kernel
+    sources or setting differ from the ones the counters were taken on."""
+    import hashlib
+    path = os.path.join(ROOT, "profiles", "traffic_pair_forces_n51200.json")
+    try:
+        with open(path) as f:
+            rec = json.load(f)
+    except (OSError, ValueError):
+        return None
+    h = hashlib.sha256()
+    for src in rec.get("sources", []):
+        try:
+            with open(os.path.join(ROOT, src), "rb") as f:
+                data = f.read()
+        except OSError:
+            return None
+        h.update(src.encode())
+        h.update(data)
+    want = [tuning.get("nuclear_variant"), tuning.get("coulomb_splits"), tuning.get("fused_forces")]
+    if h.hexdigest() != rec.get("sources_sha256") or rec.get("tuning") != want \
+            or rec.get("kernel") != kernel_name:
+        return None
+    return rec["bytes_per_launch"]
+
+
 def run_path(B, torch, st, precision, steps, warmup, timing):
     dev = torch.device("cuda:0")
     pos = torch.tensor(st["pos"], device=dev)
@@ -314,9 +342,14 @@ def main():
         kname = {}
     if dom in flops:
         ach = flops[dom] / (avg_ms * 1e-3) / 1e12
+        traffic = None
+        if dom == "nuclear+kick" and tuned.get("fused_forces") and not use_lists:
+            traffic = measured_traffic("k_forces_fused<MixedPolicy, false, %d>"
+                                       % tuned["nuclear_variant"], tuned)
         roof = {"kernel": kname.get(dom, dom), "bound": "alu", "achieved": round(ach, 3),
                 "peak": PEAK_FP32_TFLOPS, "unit": "TFLOP/s",
-                "frac": round(ach / PEAK_FP32_TFLOPS, 4), "traffic": None,
+                "frac": round(ach / PEAK_FP32_TFLOPS, 4), "traffic": traffic,
+                "traffic_unit": "bytes per launch (HBM, counter runs in profiles/)",
                 "avg_launch_ms": round(avg_ms, 5)}
     else:
         roof = {"kernel": dom, "bound": "hbm", "achieved": None, "peak": 8000.0,
