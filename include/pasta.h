@@ -222,7 +222,10 @@ int pasta_sim_create(const pasta_potential* pot, const pasta_integrator* integ,
 /* Advances nsteps steps (asynchronous). */
 int pasta_sim_step(pasta_sim* sim, int64_t nsteps);
 /* Synchronises; returns kinetic and potential energy (MeV), the box side and
- * the global step index of the current state.  Any pointer may be NULL. */
+ * the global step index of the current state.  Any pointer may be NULL.
+ * Steps evaluate forces only; the potential energy (and the energy shares of
+ * pasta_sim_forces) of the current state is evaluated when first asked for,
+ * with one more force evaluation that rewrites the same forces. */
 int pasta_sim_energies(pasta_sim* sim, double* h_ekin, double* h_epot, double* h_L,
                        int64_t* h_step);
 /* Copies the current forces ([n][3], caller order) and energy shares ([n])

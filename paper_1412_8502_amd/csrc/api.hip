@@ -270,7 +270,7 @@ static void eval_forces(int precision, int terms, const ForceWork& w, const Grid
     }
     int S = 0;
     if ((terms & PASTA_TERM_COULOMB) && Z > 0) {
-        launch_coulomb(precision, w.fb, Z, pp, nullptr, s, t);
+        launch_coulomb(precision, w.fb, Z, pp, epot != nullptr || pair_counter != nullptr, s, t);
         S = coulomb_splits(Z);
     }
     launch_nuclear(precision, w.fb, w.cb, g, n, Z, pp, (terms & PASTA_TERM_NUCLEAR) != 0, S,
@@ -590,6 +590,7 @@ struct pasta_sim {
     ForceWork w;
     double* force;
     double* epot;
+    bool epot_valid;  // steps compute forces only; energies are evaluated on demand
     Timer timer;
 };
 
@@ -654,8 +655,27 @@ static int sim_eval_initial(pasta_sim* sim)
     KickArgs kick{nullptr, 0.0, sim->pot.mass, nullptr};
     eval_forces(sim->precision, PASTA_TERM_ALL, sim->w, g, sim->n, sim->Z, pp, sim->force,
                 sim->epot, kick, nullptr, s, &sim->timer);
+    sim->epot_valid = true;
     PASTA_HIP(hipGetLastError());
     return read_err(sim->w.err, s, "pasta_sim");
+}
+
+// Energy shares of the current state (the steps skip them): one force
+// evaluation with energies on the cell list / neighbour lists in place.
+// The forces it writes are the same bits the step wrote.
+static int sim_refresh_energies(pasta_sim* sim)
+{
+    if (sim->epot_valid)
+        return PASTA_OK;
+    const double L = box_side(sim, sim->step);
+    const Grid g = make_grid(L, sim->r_cell, CELL_SUB);
+    KickArgs kick{nullptr, 0.0, sim->pot.mass, nullptr};
+    eval_forces(sim->precision, PASTA_TERM_ALL, sim->w, g, sim->n, sim->Z,
+                pair_params(&sim->pot, L), sim->force, sim->epot, kick, nullptr, sim->stream,
+                nullptr);
+    PASTA_HIP(hipGetLastError());
+    sim->epot_valid = true;
+    return PASTA_OK;
 }
 
 extern "C" int pasta_sim_create(const pasta_potential* pot, const pasta_integrator* integ,
@@ -786,7 +806,8 @@ extern "C" int pasta_sim_step(pasta_sim* sim, int64_t nsteps)
         const bool thermo = gi.rescale_every > 0 && (n0 + 1) % gi.rescale_every == 0;
         KickArgs kick{sim->vel, hdtm, sim->pot.mass, thermo ? sim->w.fb.ke_part : nullptr};
         eval_forces(sim->precision, PASTA_TERM_ALL, sim->w, g, sim->n, sim->Z, pp, sim->force,
-                    sim->epot, kick, nullptr, s, &sim->timer);
+                    nullptr, kick, nullptr, s, &sim->timer);
+        sim->epot_valid = false;
         if (thermo)
             launch_thermostat(sim->vel, sim->n, sim->w.fb.ke_part,
                               g_tuning.fused_forces ? sim->w.fb.n_ke : sim->w.cb.n_items,
@@ -819,8 +840,10 @@ extern "C" int pasta_sim_energies(pasta_sim* sim, double* h_ekin, double* h_epot
     PASTA_TRY(read_err(sim->w.err, sim->stream, "pasta_sim"));
     if (h_ekin)
         PASTA_TRY(sum_on_device(sim, sim->vel, sim->n, 1, h_ekin));
-    if (h_epot)
+    if (h_epot) {
+        PASTA_TRY(sim_refresh_energies(sim));
         PASTA_TRY(sum_on_device(sim, sim->epot, sim->n, 0, h_epot));
+    }
     if (h_L)
         *h_L = box_side(sim, sim->step);
     if (h_step)
@@ -832,6 +855,8 @@ extern "C" int pasta_sim_forces(pasta_sim* sim, double* d_force, double* d_epot)
 {
     if (!sim)
         return fail(PASTA_EINVAL, "pasta_sim_forces: null sim");
+    if (d_epot)
+        PASTA_TRY(sim_refresh_energies(sim));
     if (d_force)
         PASTA_HIP(hipMemcpyAsync(d_force, sim->force, sizeof(double) * 3 * sim->n,
                                  hipMemcpyDeviceToDevice, sim->stream));
@@ -854,6 +879,7 @@ extern "C" int pasta_sim_pair_counts(pasta_sim* sim, int64_t* h_nuclear, int64_t
     // the cell list and staging of the current state are in place
     eval_forces(sim->precision, PASTA_TERM_ALL, sim->w, g, sim->n, sim->Z,
                 pair_params(&sim->pot, L), sim->force, sim->epot, kick, ctr, s, nullptr);
+    sim->epot_valid = true;
     uint64_t h[2] = {0, 0};
     PASTA_HIP(hipMemcpyAsync(h, ctr, sizeof(h), hipMemcpyDeviceToHost, s));
     PASTA_HIP(hipStreamSynchronize(s));

@@ -225,20 +225,36 @@ __device__ void phase_drift(const BatchDev& B, int64_t step, int mode)
     }
 }
 
+// Exclusive scan of v[0..m) by one workgroup: contiguous runs per thread
+// (the first 8 values of a run held in registers) and the workgroup scan of
+// the run totals.
 __device__ int64_t block_exscan(const int32_t* v, int32_t* out, int64_t m, int64_t* lds)
 {
+    constexpr int CACHE = 8;
     const int tid = threadIdx.x;
     const int64_t per = (m + BW - 1) / BW;
     const int64_t b = tid * per, e = b + per < m ? b + per : m;
+    int32_t c[CACHE];
     int64_t s = 0;
-    for (int64_t k = b; k < e; ++k)
+#pragma unroll
+    for (int u = 0; u < CACHE; ++u) {
+        c[u] = b + u < e ? v[b + u] : 0;
+        s += c[u];
+    }
+    for (int64_t k = b + CACHE; k < e; ++k)
         s += v[k];
     int64_t total = 0;
     int64_t run = block_exclusive_scan(s, lds, &total);
-    for (int64_t k = b; k < e; ++k) {
-        const int32_t c = v[k];
+#pragma unroll
+    for (int u = 0; u < CACHE; ++u) {
+        if (b + u < e)
+            out[b + u] = (int32_t)run;
+        run += c[u];
+    }
+    for (int64_t k = b + CACHE; k < e; ++k) {
+        const int32_t x = v[k];
         out[k] = (int32_t)run;
-        run += c;
+        run += x;
     }
     __syncthreads();
     return total;
@@ -263,9 +279,8 @@ __device__ void phase_scan(const BatchDev& B, int64_t step, int mode, char* lds_
         // doubles as scratch for the per-cell item counts
         const int64_t CS = (int64_t)gr.C * gr.sub;
         for (int64_t c = threadIdx.x; c < gr.C; c += BW) {
-            int32_t m = 0;
-            for (int o = 0; o < gr.sub; ++o)
-                m += count[c * gr.sub + o] + count[CS + c * gr.sub + o];
+            const int32_t m = (start[(c + 1) * gr.sub] - start[c * gr.sub]) +
+                              (start[CS + (c + 1) * gr.sub] - start[CS + c * gr.sub]);
             fill[c] = (m + NUC_CHUNK - 1) / NUC_CHUNK;
         }
         __syncthreads();
@@ -354,6 +369,7 @@ __device__ void phase_forces(const BatchDev& B, int64_t step, int mode, char* ld
 {
     const auto* stg = reinterpret_cast<const typename P::Src*>(B.stg);
     const int64_t total = B.coul_items + B.nuc_items;
+    constexpr int M = COUNT ? MODE_COUNT : MODE_ENERGY;  // the batch keeps energies
     unsigned* ctr = B.queue;
     while (true) {
         if (threadIdx.x == 0)
@@ -402,9 +418,9 @@ __device__ void phase_forces(const BatchDev& B, int64_t step, int mode, char* ld
             A.pairs = B.pairs + s;
             A.err = B.err;
             if (B.nuc_variant == 1)
-                nuclear_item_compact<P, true, COUNT>(stg + S.off, A, k, local, lds);
+                nuclear_item_compact<P, true, M>(stg + S.off, A, k, local, lds);
             else
-                nuclear_item<P, true, COUNT>(stg + S.off, A, k, local, lds);
+                nuclear_item<P, true, M>(stg + S.off, A, k, local, lds);
         }
     }
 }

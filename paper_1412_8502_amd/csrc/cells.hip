@@ -47,21 +47,36 @@ static_assert(SCAN_THREADS <= 64 * 63, "wave totals must fit the LDS scratch");
 
 // Exclusive scan of v[0..m) (per-thread contiguous runs + the workgroup scan
 // of the run totals).  Returns the grand total to every thread.
+// Runs of up to RUN_CACHE values are held in registers (loaded with
+// independent loads), longer runs are re-read.
+constexpr int RUN_CACHE = 8;
 __device__ int64_t block_scan_runs(const int32_t* v, int32_t* out, int64_t m,
                                    int64_t* lds)
 {
     const int tid = threadIdx.x;
     const int64_t per = (m + SCAN_THREADS - 1) / SCAN_THREADS;
     const int64_t b = tid * per, e = b + per < m ? b + per : m;
+    int32_t c[RUN_CACHE];
     int64_t s = 0;
-    for (int64_t k = b; k < e; ++k)
+#pragma unroll
+    for (int u = 0; u < RUN_CACHE; ++u) {
+        c[u] = b + u < e ? v[b + u] : 0;
+        s += c[u];
+    }
+    for (int64_t k = b + RUN_CACHE; k < e; ++k)
         s += v[k];
     int64_t total = 0;
     int64_t run = block_exclusive_scan(s, lds, &total);
-    for (int64_t k = b; k < e; ++k) {
-        const int32_t c = v[k];
+#pragma unroll
+    for (int u = 0; u < RUN_CACHE; ++u) {
+        if (b + u < e)
+            out[b + u] = (int32_t)run;
+        run += c[u];
+    }
+    for (int64_t k = b + RUN_CACHE; k < e; ++k) {
+        const int32_t x = v[k];
         out[k] = (int32_t)run;
-        run += c;
+        run += x;
     }
     __syncthreads();
     return total;
@@ -87,11 +102,11 @@ __global__ __launch_bounds__(SCAN_THREADS) void k_scan(int32_t* __restrict__ cou
     __syncthreads();
     if (chunk > 0) {
         // chunks per cell (protons + neutrons of the cell)
+        // members of cell c from the starts just written (four loads)
         const int64_t CS = (int64_t)C * sub;
         for (int64_t c = tid; c < C; c += SCAN_THREADS) {
-            int32_t m = 0;
-            for (int o = 0; o < sub; ++o)
-                m += count[c * sub + o] + count[CS + c * sub + o];
+            const int32_t m = (start[(c + 1) * sub] - start[c * sub]) +
+                              (start[CS + (c + 1) * sub] - start[CS + c * sub]);
             tmpc[c] = (m + chunk - 1) / chunk;
         }
         __syncthreads();

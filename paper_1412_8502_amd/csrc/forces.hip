@@ -22,16 +22,16 @@ namespace pasta {
 
 namespace {
 
-template <class P>
+template <class P, bool E>
 __global__ __launch_bounds__(WG) void k_coulomb(const typename P::Src* __restrict__ stg, int Z,
                                                 int per_split, CoulConsts k,
                                                 double4* __restrict__ part)
 {
     __shared__ __align__(16) char lds[coulomb_lds_bytes<P>()];
-    coulomb_item<P>(stg, Z, per_split, k, part, blockIdx.x, blockIdx.y, lds);
+    coulomb_item<P, E>(stg, Z, per_split, k, part, blockIdx.x, blockIdx.y, lds);
 }
 
-template <class P, bool NUC, bool COUNT>
+template <class P, bool NUC, int MODE>
 __global__ __launch_bounds__(WG) void k_nuclear(const typename P::Src* __restrict__ stg,
                                                 NucArgs A, const int32_t* __restrict__ n_items,
                                                 NucConsts k)
@@ -39,10 +39,10 @@ __global__ __launch_bounds__(WG) void k_nuclear(const typename P::Src* __restric
     __shared__ __align__(16) char lds[nuclear_lds_bytes<P>()];
     if ((int)blockIdx.x >= *n_items)
         return;
-    nuclear_item<P, NUC, COUNT>(stg, A, k, blockIdx.x, lds);
+    nuclear_item<P, NUC, MODE>(stg, A, k, blockIdx.x, lds);
 }
 
-template <class P, int TPT, bool NUC, bool COUNT>
+template <class P, int TPT, bool NUC, int MODE>
 __global__ __launch_bounds__(WG) void k_nuclear_compact(const typename P::Src* __restrict__ stg,
                                                         NucArgs A,
                                                         const int32_t* __restrict__ n_items,
@@ -51,13 +51,13 @@ __global__ __launch_bounds__(WG) void k_nuclear_compact(const typename P::Src* _
     __shared__ __align__(16) char lds[nuclear_compact_lds_bytes<P>()];
     if ((int)blockIdx.x >= *n_items)
         return;
-    nuclear_item_compact_t<P, TPT, NUC, COUNT>(stg, A, k, blockIdx.x, lds);
+    nuclear_item_compact_t<P, TPT, NUC, MODE>(stg, A, k, blockIdx.x, lds);
 }
 
 // List form of a nuclear item: the lists of the last build, or, when that
 // build ran out of list memory, the screened cell sweep over its cells (the
 // grid of the last build is read from the control block).
-template <class P, bool COUNT>
+template <class P, int MODE>
 __device__ void nuclear_item_listed(const typename P::Src* __restrict__ stg, const NucArgs& A,
                                     const NucConsts& k, const ListArgs& LA, int item, char* lds)
 {
@@ -65,12 +65,12 @@ __device__ void nuclear_item_listed(const typename P::Src* __restrict__ stg, con
     B.nc = LA.ctl->nc;
     B.C = LA.ctl->C;
     if (LA.ctl->overflow)
-        nuclear_item_compact_t<P, LIST_TPT, true, COUNT>(stg, B, k, item, lds);
+        nuclear_item_compact_t<P, LIST_TPT, true, MODE>(stg, B, k, item, lds);
     else
-        list_force_item<P, COUNT>(stg, B, k, LA, item, lds);
+        list_force_item<P, MODE>(stg, B, k, LA, item, lds);
 }
 
-template <class P, bool COUNT>
+template <class P, int MODE>
 __global__ __launch_bounds__(WG) void k_nuclear_list(const typename P::Src* __restrict__ stg,
                                                      NucArgs A,
                                                      const int32_t* __restrict__ n_items,
@@ -79,7 +79,7 @@ __global__ __launch_bounds__(WG) void k_nuclear_list(const typename P::Src* __re
     __shared__ __align__(16) char lds[nuclear_compact_lds_bytes<P>()];
     if ((int)blockIdx.x >= *n_items)
         return;
-    nuclear_item_listed<P, COUNT>(stg, A, k, LA, blockIdx.x, lds);
+    nuclear_item_listed<P, MODE>(stg, A, k, LA, blockIdx.x, lds);
 }
 
 // Gated on the rebuild decision of this step.
@@ -106,7 +106,7 @@ constexpr int fused_lds_bytes()
     return a > b ? a : b;
 }
 
-template <class P, bool COUNT, int V>
+template <class P, int MODE, int V>
 __global__ __launch_bounds__(WG) void k_forces_fused(const typename P::Src* __restrict__ stg,
                                                      NucArgs A, const int32_t* __restrict__ n_items,
                                                      int item_max, NucConsts k, int Z,
@@ -120,16 +120,17 @@ __global__ __launch_bounds__(WG) void k_forces_fused(const typename P::Src* __re
         if (g >= *n_items)
             return;
         if constexpr (V == 2)
-            nuclear_item_listed<P, COUNT>(stg, A, k, LA, g, lds);
+            nuclear_item_listed<P, MODE>(stg, A, k, LA, g, lds);
         else if constexpr (V == 3)
-            nuclear_item_compact_t<P, 8, true, COUNT>(stg, A, k, g, lds);
+            nuclear_item_compact_t<P, 8, true, MODE>(stg, A, k, g, lds);
         else if constexpr (V == 1)
-            nuclear_item_compact<P, true, COUNT>(stg, A, k, g, lds);
+            nuclear_item_compact<P, true, MODE>(stg, A, k, g, lds);
         else
-            nuclear_item<P, true, COUNT>(stg, A, k, g, lds);
+            nuclear_item<P, true, MODE>(stg, A, k, g, lds);
     } else {
         const int h = g - item_max;
-        coulomb_item<P>(stg, Z, per_split, kc, part, h % coul_blocks, h / coul_blocks, lds);
+        coulomb_item<P, MODE != MODE_FORCE>(stg, Z, per_split, kc, part, h % coul_blocks,
+                                            h / coul_blocks, lds);
     }
 }
 
@@ -150,7 +151,22 @@ __global__ __launch_bounds__(WG) void k_combine(const double4* __restrict__ fnuc
         const double4 fn = fnuc[sl];
         double Fx = fn.x, Fy = fn.y, Fz = fn.z, V = fn.w;
         if (sl < Z) {
-            for (int k = 0; k < S; ++k) {
+            // eight partials in flight; summed in split order
+            int k = 0;
+            for (; k + 8 <= S; k += 8) {
+                double4 cp[8];
+#pragma unroll
+                for (int u = 0; u < 8; ++u)
+                    cp[u] = part[(int64_t)(k + u) * Z + sl];
+#pragma unroll
+                for (int u = 0; u < 8; ++u) {
+                    Fx += cp[u].x;
+                    Fy += cp[u].y;
+                    Fz += cp[u].z;
+                    V += cp[u].w;
+                }
+            }
+            for (; k < S; ++k) {
                 const double4 cp = part[(int64_t)k * Z + sl];
                 Fx += cp.x;
                 Fy += cp.y;
@@ -189,25 +205,35 @@ __global__ __launch_bounds__(WG) void k_combine(const double4* __restrict__ fnuc
     }
 }
 
+template <class F>
+void with_mode(int mode, F f)
+{
+    if (mode == MODE_COUNT)
+        f(std::integral_constant<int, MODE_COUNT>());
+    else if (mode == MODE_ENERGY)
+        f(std::integral_constant<int, MODE_ENERGY>());
+    else
+        f(std::integral_constant<int, MODE_FORCE>());
+}
+
 template <class P>
 void nuclear_dispatch(const typename P::Src* stg, const NucArgs& a, const int32_t* n_items,
-                      const NucConsts& k, bool nuc, bool count, int variant, unsigned grid,
+                      const NucConsts& k, bool nuc, int mode, int variant, unsigned grid,
                       hipStream_t s)
 {
-    if (!nuc)
-        k_nuclear<P, false, false><<<grid, WG, 0, s>>>(stg, a, n_items, k);
-    else if (variant == 3 && count)
-        k_nuclear_compact<P, 8, true, true><<<grid, WG, 0, s>>>(stg, a, n_items, k);
-    else if (variant == 3)
-        k_nuclear_compact<P, 8, true, false><<<grid, WG, 0, s>>>(stg, a, n_items, k);
-    else if (variant == 1 && count)
-        k_nuclear_compact<P, NUC_TPT, true, true><<<grid, WG, 0, s>>>(stg, a, n_items, k);
-    else if (variant == 1)
-        k_nuclear_compact<P, NUC_TPT, true, false><<<grid, WG, 0, s>>>(stg, a, n_items, k);
-    else if (count)
-        k_nuclear<P, true, true><<<grid, WG, 0, s>>>(stg, a, n_items, k);
-    else
-        k_nuclear<P, true, false><<<grid, WG, 0, s>>>(stg, a, n_items, k);
+    if (!nuc) {
+        k_nuclear<P, false, MODE_ENERGY><<<grid, WG, 0, s>>>(stg, a, n_items, k);
+        return;
+    }
+    with_mode(mode, [&](auto mt) {
+        constexpr int M = decltype(mt)::value;
+        if (variant == 3)
+            k_nuclear_compact<P, 8, true, M><<<grid, WG, 0, s>>>(stg, a, n_items, k);
+        else if (variant == 1)
+            k_nuclear_compact<P, NUC_TPT, true, M><<<grid, WG, 0, s>>>(stg, a, n_items, k);
+        else
+            k_nuclear<P, true, M><<<grid, WG, 0, s>>>(stg, a, n_items, k);
+    });
 }
 
 }  // namespace
@@ -316,40 +342,32 @@ void launch_forces_fused(int precision, const ForceBuf& fb, const CellBuf& cb, c
     (void)with_nuclear_terms;  // the fused form always carries the nuclear terms
     const int item_max = (int)cb.item_max;
     const unsigned grid = (unsigned)(item_max + coul_blocks * S);
-    const bool count = pair_counter != nullptr;
+    const int mode = pair_counter ? MODE_COUNT : (epot ? MODE_ENERGY : MODE_FORCE);
     if (variant == 2 && !lb)
         variant = 1;
     const ListArgs la = list_args(lb);
     timer_begin(t, KC_NUCLEAR, s);
     if (grid > 0) {
-        auto go = [&](auto vtag) {
+        auto go = [&](auto vtag, auto mtag) {
             constexpr int V = decltype(vtag)::value;
-            if (precision == PASTA_FP64) {
-                if (count)
-                    k_forces_fused<Fp64Policy, true, V><<<grid, WG, 0, s>>>(
-                        fb.stg64, a, cb.n_items, item_max, k, (int)Z, per, coul_blocks, kc,
-                        fb.coul_part, la);
-                else
-                    k_forces_fused<Fp64Policy, false, V><<<grid, WG, 0, s>>>(
-                        fb.stg64, a, cb.n_items, item_max, k, (int)Z, per, coul_blocks, kc,
-                        fb.coul_part, la);
-            } else {
-                if (count)
-                    k_forces_fused<MixedPolicy, true, V><<<grid, WG, 0, s>>>(
-                        fb.stgq, a, cb.n_items, item_max, k, (int)Z, per, coul_blocks, kc,
-                        fb.coul_part, la);
-                else
-                    k_forces_fused<MixedPolicy, false, V><<<grid, WG, 0, s>>>(
-                        fb.stgq, a, cb.n_items, item_max, k, (int)Z, per, coul_blocks, kc,
-                        fb.coul_part, la);
-            }
+            constexpr int M = decltype(mtag)::value;
+            if (precision == PASTA_FP64)
+                k_forces_fused<Fp64Policy, M, V><<<grid, WG, 0, s>>>(
+                    fb.stg64, a, cb.n_items, item_max, k, (int)Z, per, coul_blocks, kc,
+                    fb.coul_part, la);
+            else
+                k_forces_fused<MixedPolicy, M, V><<<grid, WG, 0, s>>>(
+                    fb.stgq, a, cb.n_items, item_max, k, (int)Z, per, coul_blocks, kc,
+                    fb.coul_part, la);
         };
-        switch (variant) {
-        case 0: go(std::integral_constant<int, 0>()); break;
-        case 2: go(std::integral_constant<int, 2>()); break;
-        case 3: go(std::integral_constant<int, 3>()); break;
-        default: go(std::integral_constant<int, 1>()); break;
-        }
+        with_mode(mode, [&](auto mt) {
+            switch (variant) {
+            case 0: go(std::integral_constant<int, 0>(), mt); break;
+            case 2: go(std::integral_constant<int, 2>(), mt); break;
+            case 3: go(std::integral_constant<int, 3>(), mt); break;
+            default: go(std::integral_constant<int, 1>(), mt); break;
+            }
+        });
     }
     timer_end(t, KC_NUCLEAR, s);
     timer_begin(t, KC_COMBINE, s);
@@ -377,7 +395,7 @@ size_t forcebuf_carve(Carver& cv, ForceBuf* out, int64_t n, int64_t item_max, in
 }
 
 void launch_coulomb(int precision, const ForceBuf& fb, int64_t Z, const PairParams& pp,
-                    uint64_t* /*pair_counter*/, hipStream_t s, Timer* t)
+                    bool energy, hipStream_t s, Timer* t)
 {
     if (Z <= 0)
         return;
@@ -386,10 +404,17 @@ void launch_coulomb(int precision, const ForceBuf& fb, int64_t Z, const PairPara
     const CoulConsts k = make_coul_consts(pp);
     dim3 grid((unsigned)((Z + WG - 1) / WG), (unsigned)S);
     timer_begin(t, KC_COULOMB, s);
-    if (precision == PASTA_FP64)
-        k_coulomb<Fp64Policy><<<grid, WG, 0, s>>>(fb.stg64, (int)Z, per, k, fb.coul_part);
-    else
-        k_coulomb<MixedPolicy><<<grid, WG, 0, s>>>(fb.stgq, (int)Z, per, k, fb.coul_part);
+    if (precision == PASTA_FP64) {
+        if (energy)
+            k_coulomb<Fp64Policy, true><<<grid, WG, 0, s>>>(fb.stg64, (int)Z, per, k, fb.coul_part);
+        else
+            k_coulomb<Fp64Policy, false><<<grid, WG, 0, s>>>(fb.stg64, (int)Z, per, k, fb.coul_part);
+    } else {
+        if (energy)
+            k_coulomb<MixedPolicy, true><<<grid, WG, 0, s>>>(fb.stgq, (int)Z, per, k, fb.coul_part);
+        else
+            k_coulomb<MixedPolicy, false><<<grid, WG, 0, s>>>(fb.stgq, (int)Z, per, k, fb.coul_part);
+    }
     timer_end(t, KC_COULOMB, s);
 }
 
@@ -421,26 +446,22 @@ void launch_nuclear(int precision, const ForceBuf& fb, const CellBuf& cb, const 
     a.err = err;
     a.fnuc = nullptr;
     const unsigned grid = (unsigned)cb.item_max;
-    const bool count = pair_counter != nullptr;
+    const int mode = pair_counter ? MODE_COUNT : (epot ? MODE_ENERGY : MODE_FORCE);
     timer_begin(t, KC_NUCLEAR, s);
     if (variant == 2 && lb && with_nuclear_terms) {
         const ListArgs la = list_args(lb);
-        if (precision == PASTA_FP64) {
-            if (count)
-                k_nuclear_list<Fp64Policy, true><<<grid, WG, 0, s>>>(fb.stg64, a, cb.n_items, k, la);
+        with_mode(mode, [&](auto mt) {
+            constexpr int M = decltype(mt)::value;
+            if (precision == PASTA_FP64)
+                k_nuclear_list<Fp64Policy, M><<<grid, WG, 0, s>>>(fb.stg64, a, cb.n_items, k, la);
             else
-                k_nuclear_list<Fp64Policy, false><<<grid, WG, 0, s>>>(fb.stg64, a, cb.n_items, k, la);
-        } else {
-            if (count)
-                k_nuclear_list<MixedPolicy, true><<<grid, WG, 0, s>>>(fb.stgq, a, cb.n_items, k, la);
-            else
-                k_nuclear_list<MixedPolicy, false><<<grid, WG, 0, s>>>(fb.stgq, a, cb.n_items, k, la);
-        }
+                k_nuclear_list<MixedPolicy, M><<<grid, WG, 0, s>>>(fb.stgq, a, cb.n_items, k, la);
+        });
     } else if (precision == PASTA_FP64) {
-        nuclear_dispatch<Fp64Policy>(fb.stg64, a, cb.n_items, k, with_nuclear_terms, count,
+        nuclear_dispatch<Fp64Policy>(fb.stg64, a, cb.n_items, k, with_nuclear_terms, mode,
                                      variant, grid, s);
     } else {
-        nuclear_dispatch<MixedPolicy>(fb.stgq, a, cb.n_items, k, with_nuclear_terms, count,
+        nuclear_dispatch<MixedPolicy>(fb.stgq, a, cb.n_items, k, with_nuclear_terms, mode,
                                       variant, grid, s);
     }
     timer_end(t, KC_NUCLEAR, s);

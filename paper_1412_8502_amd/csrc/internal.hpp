@@ -135,29 +135,33 @@ __device__ inline int particle_bin(double x, double y, double z, bool proton, do
     return (proton ? 0 : C * sub) + cell * sub + (sub == 8 ? o : 0);
 }
 
-// Wave-aggregated atomic add of 1 per lane on counters[bin]: lanes of a
-// wavefront that share a bin issue one atomic between them.  Returns the
-// counter value seen by this lane's share (old value + rank among the
-// wave's lanes with the same bin, in lane order).  Must be called by every
-// active lane of the wave (the loop below is wave-uniform).
+// Wave-aggregated atomic add of 1 per lane on counters[bin]: the lanes of a
+// wavefront that share a bin are grouped (ballots only), then every group's
+// leader lane adds its group size in one vector atomic instruction, so the
+// wave makes a single round trip to memory however many bins it touches.
+// Returns the counter value seen by this lane's share (old value + rank
+// among the wave's lanes with the same bin, in lane order).  Must be called
+// by every active lane of the wave (the loop below is wave-uniform).
 __device__ inline int wave_aggregated_add(int32_t* counters, int bin)
 {
     unsigned long long todo = __ballot(1);
     const int lane = __lane_id();
-    int result = 0;
+    int leader = lane, rank = 0, size = 0;
     while (todo) {
-        const int leader = __ffsll((unsigned long long)todo) - 1;
-        const int b = __shfl(bin, leader);
+        const int l = __ffsll((unsigned long long)todo) - 1;
+        const int b = __shfl(bin, l);
         const unsigned long long mask = __ballot(bin == b) & todo;
-        int base = 0;
-        if (lane == leader)
-            base = atomicAdd(&counters[b], __popcll(mask));
-        base = __shfl(base, leader);
-        if (bin == b)
-            result = base + __popcll(mask & ((1ull << lane) - 1ull));
+        if (bin == b) {
+            leader = l;
+            rank = __popcll(mask & ((1ull << lane) - 1ull));
+            size = __popcll(mask);
+        }
         todo &= ~mask;
     }
-    return result;
+    int base = 0;
+    if (lane == leader)
+        base = atomicAdd(&counters[bin], size);
+    return __shfl(base, leader) + rank;
 }
 
 // Exclusive prefix of one int64 per thread over the workgroup: a shuffle
@@ -319,8 +323,9 @@ extern pasta_tuning g_tuning;
 size_t forcebuf_carve(Carver& cv, ForceBuf* out, int64_t n, int64_t item_max, int precision);
 
 // Coulomb all-pairs over protons (sorted slots [0, Z)).
+// energy: also accumulate the energy shares (else the partials' w is 0).
 void launch_coulomb(int precision, const ForceBuf& fb, int64_t Z, const PairParams& pp,
-                    uint64_t* pair_counter, hipStream_t s, Timer* t);
+                    bool energy, hipStream_t s, Timer* t);
 // Nuclear cell-tile kernel; adds the coul_S Coulomb partials of proton
 // targets (coul_S = 0: none),
 // writes F and E in caller order, optionally applies the second half kick.

@@ -118,7 +118,7 @@ __device__ void list_build_item(const typename P::Src* __restrict__ stg, const N
 
 // Nuclear force on the item's targets from their lists (the same contract
 // as nuclear_item_compact; the target itself is not in its list).
-template <class P, bool COUNT>
+template <class P, int MODE>
 __device__ void list_force_item(const typename P::Src* __restrict__ stg, const NucArgs& A,
                                 const NucConsts& k, const ListArgs& LA, int item, char* lds)
 {
@@ -153,14 +153,14 @@ __device__ void list_force_item(const typename P::Src* __restrict__ stg, const N
 #pragma unroll
         for (int u = 0; u < LIST_U; ++u) {
             const bool like = P::is_proton(s[u]) == mp;
-            P::template pair<COUNT>(me, s[u], like ? BLlike : BLun, like ? Blike : Bun, k, part,
+            P::template pair<MODE>(me, s[u], like ? BLlike : BLun, like ? Blike : Bun, k, part,
                                     j0 + u < m);
         }
         if ((j0 & 127) == 128 - LIST_U)  // FP32 partial sums over at most 128 pairs
             P::fold(acc, part);
     }
     P::fold(acc, part);
-    nuclear_finish<P, LIST_TPT, true, COUNT>(A, k, acc, t, item, false, L);
+    nuclear_finish<P, LIST_TPT, true, MODE>(A, k, acc, t, item, false, L);
 }
 
 }  // namespace pasta

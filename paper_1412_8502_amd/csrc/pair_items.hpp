@@ -26,6 +26,12 @@
 
 namespace pasta {
 
+// What a pair kernel accumulates: forces only, forces and energy shares,
+// or forces, energies and the count of pairs inside the cutoff.
+constexpr int MODE_FORCE = 0;
+constexpr int MODE_ENERGY = 1;
+constexpr int MODE_COUNT = 2;
+
 constexpr int WG = 256;
 constexpr int NUC_TPT = 4;               // lanes per target (nuclear)
 constexpr int NUC_CHUNK = WG / NUC_TPT;  // targets per work item
@@ -116,7 +122,7 @@ struct Fp64Policy {
     using CAcc = double;  // Coulomb per-tile accumulator
     __device__ static Lds load(const Src* s, int j) { return s[j]; }
 
-    template <bool COUNT>
+    template <int MODE>
     __device__ static void pair(const Src& me, const Lds& s, double B_L, double B,
                                 const NucConsts& k, Part& p, bool valid = true)
     {
@@ -126,14 +132,15 @@ struct Fp64Policy {
         dz = fma(-k.L, rint(dz * k.invL), dz);
         double r2 = dx * dx + dy * dy + dz * dz;
         const bool in = valid && r2 < k.rc2;
-        if (COUNT)
+        if (MODE == MODE_COUNT)
             p.np += in ? 1u : 0u;
         double g = in ? exp_nonpos(r2 * k.cg) : 0.0;
         double fs = g * fma(k.A2, g, B_L);
         p.fx = fma(fs, dx, p.fx);
         p.fy = fma(fs, dy, p.fy);
         p.fz = fma(fs, dz, p.fz);
-        p.e = fma(g, fma(k.a, g, B), p.e);
+        if (MODE != MODE_FORCE)
+            p.e = fma(g, fma(k.a, g, B), p.e);
     }
     __device__ static void fold(Acc& a, Part& p)
     {
@@ -149,6 +156,7 @@ struct Fp64Policy {
     __device__ static double bl(const NucConsts& k, bool like) { return like ? k.Bl_L : k.Bu_L; }
     __device__ static double bv(const NucConsts& k, bool like) { return like ? k.Bl : k.Bu; }
 
+    template <bool E>
     __device__ static void coul(const Src& me, const Lds& s, bool self, const CoulConsts& k,
                                 CAcc& fx, CAcc& fy, CAcc& fz, CAcc& e)
     {
@@ -165,7 +173,8 @@ struct Fp64Policy {
         fx = fma(fs, dx, fx);
         fy = fma(fs, dy, fy);
         fz = fma(fs, dz, fz);
-        e += v;
+        if (E)
+            e += v;
     }
     __device__ static double coul_fscale(const CoulConsts&) { return 1.0; }
     __device__ static double coul_vscale(const CoulConsts&) { return 1.0; }
@@ -197,7 +206,7 @@ struct MixedPolicy {
         return reinterpret_cast<const uint4*>(s)[j];
     }
 
-    template <bool COUNT>
+    template <int MODE>
     __device__ static void pair(const Src& me, const Lds& s, float B_L, float B,
                                 const NucConsts& k, Part& p, bool valid = true)
     {
@@ -206,7 +215,7 @@ struct MixedPolicy {
         float dz = (float)(int32_t)(me.z - s.z);
         float r2 = dx * dx + dy * dy + dz * dz;
         const bool in = valid && r2 < k.thr_q;
-        if (COUNT)
+        if (MODE == MODE_COUNT)
             p.np += in ? 1u : 0u;
         r2 = in ? r2 : 3.0e38f;  // exp2 underflows to exactly 0 outside the cutoff
         float g = __builtin_amdgcn_exp2f(r2 * k.cgq);
@@ -214,7 +223,8 @@ struct MixedPolicy {
         p.fx = fmaf(fs, dx, p.fx);
         p.fy = fmaf(fs, dy, p.fy);
         p.fz = fmaf(fs, dz, p.fz);
-        p.e = fmaf(g, fmaf(k.af, g, B), p.e);
+        if (MODE != MODE_FORCE)
+            p.e = fmaf(g, fmaf(k.af, g, B), p.e);
     }
     __device__ static void fold(Acc& a, Part& p)
     {
@@ -231,6 +241,7 @@ struct MixedPolicy {
     __device__ static float bl(const NucConsts& k, bool like) { return like ? k.Blf_L : k.Buf_L; }
     __device__ static float bv(const NucConsts& k, bool like) { return like ? k.Blf : k.Buf; }
 
+    template <bool E>
     __device__ static void coul(const Src& me, const Lds& s, bool self, const CoulConsts& k,
                                 CAcc& fx, CAcc& fy, CAcc& fz, CAcc& e)
     {
@@ -246,7 +257,8 @@ struct MixedPolicy {
         fx = fmaf(fs, dx, fx);
         fy = fmaf(fs, dy, fy);
         fz = fmaf(fs, dz, fz);
-        e += w;
+        if (E)
+            e += w;
     }
     __device__ static double coul_fscale(const CoulConsts& k) { return k.f_scale; }
     __device__ static double coul_vscale(const CoulConsts& k) { return k.v_scale; }
@@ -273,7 +285,7 @@ constexpr int NUC_U = 4;     // candidates per lane between list-fill checks
 // ============================================================ Coulomb ==
 // Targets are the proton slots [tb, tb + WG) ∩ [0, Z); sources the slots
 // [split * per_split, ...).  Writes part[split * Z + t] = (Fx, Fy, Fz, sum V).
-template <class P>
+template <class P, bool E = true>
 __device__ void coulomb_item(const typename P::Src* __restrict__ stg, int Z, int per_split,
                              const CoulConsts& k, double4* __restrict__ part, int tblock,
                              int split, char* lds)
@@ -294,11 +306,11 @@ __device__ void coulomb_item(const typename P::Src* __restrict__ stg, int Z, int
         typename P::CAcc ax = 0, ay = 0, az = 0, ae = 0;
         if (base < tb1 && base + cnt > tb0) {
             for (int q = 0; q < cnt; ++q)
-                P::coul(me, tile[q], base + q == t, k, ax, ay, az, ae);
+                P::template coul<E>(me, tile[q], base + q == t, k, ax, ay, az, ae);
         } else {
 #pragma unroll 4
             for (int q = 0; q < cnt; ++q)
-                P::coul(me, tile[q], false, k, ax, ay, az, ae);
+                P::template coul<E>(me, tile[q], false, k, ax, ay, az, ae);
         }
         fx += (double)ax;
         fy += (double)ay;
@@ -332,7 +344,7 @@ struct NucArgs {
     double4* fnuc;           // batch form: raw nuclear (F, V) per sorted slot, no epilogue
 };
 
-template <class P, bool NUC, bool COUNT>
+template <class P, bool NUC, int MODE>
 __device__ void nuclear_item(const typename P::Src* __restrict__ stg, const NucArgs& A,
                              const NucConsts& k, int item, char* lds)
 {
@@ -405,9 +417,9 @@ __device__ void nuclear_item(const typename P::Src* __restrict__ stg, const NucA
             __syncthreads();
             const int kb = min(max(np_tot - w0, 0), cnt);
             for (int j = q; j < kb; j += NUC_TPT)
-                P::template pair<COUNT>(me, tile[j], BLp, Bp, k, part);
+                P::template pair<MODE>(me, tile[j], BLp, Bp, k, part);
             for (int j = kb + q; j < cnt; j += NUC_TPT)
-                P::template pair<COUNT>(me, tile[j], BLn, Bn, k, part);
+                P::template pair<MODE>(me, tile[j], BLn, Bn, k, part);
             P::fold(acc, part);
             __syncthreads();
         }
@@ -417,7 +429,7 @@ __device__ void nuclear_item(const typename P::Src* __restrict__ stg, const NucA
             acc.fy += __shfl_xor(acc.fy, m, NUC_TPT);
             acc.fz += __shfl_xor(acc.fz, m, NUC_TPT);
             acc.e += __shfl_xor(acc.e, m, NUC_TPT);
-            if (COUNT)
+            if (MODE == MODE_COUNT)
                 acc.np += __shfl_xor(acc.np, m, NUC_TPT);
         }
     }
@@ -426,7 +438,7 @@ __device__ void nuclear_item(const typename P::Src* __restrict__ stg, const NucA
     double ke = 0.0;
     unsigned long long npairs = 0;
     if (active && q == 0) {
-        if (COUNT)
+        if (MODE == MODE_COUNT)
             npairs = acc.np - 1u;  // minus the self pair
         // the self pair (r = 0) entered the sum with V(0) = a + b + c
         double V = NUC ? acc.e - k.self_v : 0.0;
@@ -463,11 +475,11 @@ __device__ void nuclear_item(const typename P::Src* __restrict__ stg, const NucA
             }
         }
     }
-    if (A.ke_part || COUNT) {
+    if (A.ke_part || MODE == MODE_COUNT) {
         // fixed-order block reduction (deterministic)
         for (int m = 32; m >= 1; m >>= 1) {
             ke += __shfl_xor(ke, m, 64);
-            if (COUNT)
+            if (MODE == MODE_COUNT)
                 npairs += __shfl_xor(npairs, m, 64);
         }
         if ((tid & 63) == 0) {
@@ -484,7 +496,7 @@ __device__ void nuclear_item(const typename P::Src* __restrict__ stg, const NucA
             }
             if (A.ke_part && !A.fnuc)
                 A.ke_part[item] = s;
-            if (COUNT)
+            if (MODE == MODE_COUNT)
                 atomicAdd(A.pairs, sn);
         }
         __syncthreads();
@@ -720,7 +732,7 @@ __device__ __forceinline__ void stage_neighbourhood(const typename P::Src* __res
 // optional half kick; finally the fixed-order per-item kinetic-energy and
 // pair-count reductions.  self_in_sum: the target's own r = 0 term (a like
 // pair, V(0) = a + b + c) was summed and is removed here.
-template <class P, int TPT, bool NUC, bool COUNT>
+template <class P, int TPT, bool NUC, int MODE>
 __device__ void nuclear_finish(const NucArgs& A, const NucConsts& k, typename P::Acc acc,
                                const ItemTarget& t, int item, bool self_in_sum,
                                const ItemLds& L)
@@ -733,7 +745,7 @@ __device__ void nuclear_finish(const NucArgs& A, const NucConsts& k, typename P:
             acc.fy += __shfl_xor(acc.fy, m, TPT);
             acc.fz += __shfl_xor(acc.fz, m, TPT);
             acc.e += __shfl_xor(acc.e, m, TPT);
-            if (COUNT)
+            if (MODE == MODE_COUNT)
                 acc.np += __shfl_xor(acc.np, m, TPT);
         }
     }
@@ -741,7 +753,7 @@ __device__ void nuclear_finish(const NucArgs& A, const NucConsts& k, typename P:
     double ke = 0.0;
     unsigned long long npairs = 0;
     if (t.active && t.q == 0) {
-        if (COUNT)
+        if (MODE == MODE_COUNT)
             npairs = acc.np - (self_in_sum ? 1u : 0u);
         double V = NUC ? acc.e - (self_in_sum ? k.self_v : 0.0) : 0.0;
         double Fx = acc.fx * fsc, Fy = acc.fy * fsc, Fz = acc.fz * fsc;
@@ -776,10 +788,10 @@ __device__ void nuclear_finish(const NucArgs& A, const NucConsts& k, typename P:
             }
         }
     }
-    if (A.ke_part || COUNT) {
+    if (A.ke_part || MODE == MODE_COUNT) {
         for (int m = 32; m >= 1; m >>= 1) {
             ke += __shfl_xor(ke, m, 64);
-            if (COUNT)
+            if (MODE == MODE_COUNT)
                 npairs += __shfl_xor(npairs, m, 64);
         }
         if (lane == 0) {
@@ -796,7 +808,7 @@ __device__ void nuclear_finish(const NucArgs& A, const NucConsts& k, typename P:
             }
             if (A.ke_part && !A.fnuc)
                 A.ke_part[item] = s;
-            if (COUNT)
+            if (MODE == MODE_COUNT)
                 atomicAdd(A.pairs, sn);
         }
         __syncthreads();
@@ -809,7 +821,7 @@ constexpr int nuclear_compact_lds_bytes()
     return P::CTILE * ((int)sizeof(typename P::Lds) + 8) + NUC_CAP * WG * 2 + ITEM_LDS_BYTES;
 }
 
-template <class P, int TPT, bool NUC, bool COUNT>
+template <class P, int TPT, bool NUC, int MODE>
 __device__ void nuclear_item_compact_t(const typename P::Src* __restrict__ stg,
                                        const NucArgs& A, const NucConsts& k, int item, char* lds)
 {
@@ -842,8 +854,8 @@ __device__ void nuclear_item_compact_t(const typename P::Src* __restrict__ stg,
                 const int j1 = v1 ? lists[(kk + 1) * WG + tid] : 0;
                 const Lds s0 = src[j0], s1 = src[j1];
                 const bool p0 = j0 < kb, p1 = j1 < kb;  // protons first in the tile
-                P::template pair<COUNT>(me, s0, p0 ? BLp : BLn, p0 ? Bp : Bn, k, part, v0);
-                P::template pair<COUNT>(me, s1, p1 ? BLp : BLn, p1 ? Bp : Bn, k, part, v1);
+                P::template pair<MODE>(me, s0, p0 ? BLp : BLn, p0 ? Bp : Bn, k, part, v0);
+                P::template pair<MODE>(me, s1, p1 ? BLp : BLn, p1 ? Bp : Bn, k, part, v1);
             }
         };
         // Screen the tile's sources against this lane's target.  The append
@@ -893,14 +905,14 @@ __device__ void nuclear_item_compact_t(const typename P::Src* __restrict__ stg,
             },
             process);
     }
-    nuclear_finish<P, TPT, NUC, COUNT>(A, k, acc, t, item, true, L);
+    nuclear_finish<P, TPT, NUC, MODE>(A, k, acc, t, item, true, L);
 }
 
-template <class P, bool NUC, bool COUNT>
+template <class P, bool NUC, int MODE>
 __device__ void nuclear_item_compact(const typename P::Src* __restrict__ stg, const NucArgs& A,
                                      const NucConsts& k, int item, char* lds)
 {
-    nuclear_item_compact_t<P, NUC_TPT, NUC, COUNT>(stg, A, k, item, lds);
+    nuclear_item_compact_t<P, NUC_TPT, NUC, MODE>(stg, A, k, item, lds);
 }
 
 }  // namespace pasta

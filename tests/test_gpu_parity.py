@@ -275,6 +275,8 @@ def test_trajectory_20_steps(env, prec, tol):
     assert dx <= tol
     assert en["step"] == 20 and en["L"] == oL
     assert abs(en["ekin"] - oek) <= 10 * tol * abs(oek) + 1e-9
+    # the potential energy is evaluated on demand at the current state
+    assert abs(en["epot"] - oep) <= 10 * tol * abs(oep) + 1e-9
     f, _ = sim.forces()
     # forces at the final GPU state, against the oracle on the same bits
     of2, _ = env["O"].forces(pos.cpu().numpy(), st["species"], st["L"])
@@ -307,6 +309,26 @@ def test_integrator_variants(env, variant):
         sim2, pos2, vel2 = make_sim(env, rng_state, **kw)
         sim2.step(10)
         assert sim2.energies()["ekin"] == pytest.approx(1.5 * 1500 * 0.8, rel=1e-13)
+
+
+@pytest.mark.parametrize("prec", [0, 1])
+def test_energy_refresh_keeps_trajectory(env, prec):
+    """Steps compute forces only; asking for energies re-evaluates the forces
+    with energies on.  That evaluation must rewrite the same force bits, so
+    asking for energies mid-run does not change the trajectory."""
+    t = env["torch"]
+    st = env["I"].make_state(2000, 0.3, 0.05, 1.0, seed=43)
+    runs = []
+    for ask in (False, True):
+        sim, pos, vel = make_sim(env, st, dt=2.0, T=1.0, rescale_every=7, precision=prec)
+        for _ in range(4):
+            sim.step(5)
+            if ask:
+                sim.energies()
+                sim.forces()
+        runs.append((pos.clone(), vel.clone()))
+        sim.close()
+    assert t.equal(runs[0][0], runs[1][0]) and t.equal(runs[0][1], runs[1][1])
 
 
 def test_checkpoint_restart_bitwise(env):
