@@ -112,9 +112,10 @@ typedef struct pasta_integrator {
  *   pasta_forces builds and uses the lists once; 3 = as 1 with 8 lanes per
  *   target and 32 targets per work item (smaller target boxes, so fewer
  *   staged sources).  Cells are binned by octant inside, so the targets of
- *   a work item are spatially compact.  The batched path treats 2 and 3 as
- *   1.  A simulation keeps the variant it was created with.  All variants
- *   give the same forces to rounding.
+ *   a work item are spatially compact.  The batched path runs 2 as 3 (it
+ *   rebuilds its cells every step) and reads the variant at creation.  A
+ *   simulation keeps the variant it was created with.  All variants give
+ *   the same forces to rounding.
  * coulomb_splits: number of source ranges per Coulomb target tile, 1..32;
  *   0 = automatic (about 2^19 / Z, at most 32).
  * fused_forces: 0 = the Coulomb kernel, then the nuclear kernel whose
@@ -300,7 +301,10 @@ int pasta_batch_create(const pasta_potential* pot, int32_t precision, int32_t ns
                        int32_t steps_per_graph, void* stream, pasta_batch** out);
 int pasta_batch_step(pasta_batch* b, int64_t nsteps);
 /* Synchronises; per-system kinetic and potential energies and box sides
- * (arrays of nsys; any may be NULL) and the global step index. */
+ * (arrays of nsys; any may be NULL) and the global step index.  As for a
+ * simulation, steps compute forces only and the energy shares of the
+ * current state are evaluated when first asked for (here or by
+ * pasta_batch_forces). */
 int pasta_batch_energies(pasta_batch* b, double* h_ekin, double* h_epot, double* h_L,
                          int64_t* h_step);
 /* Copies forces ([sum n][3]) and energy shares ([sum n]) of the current state. */

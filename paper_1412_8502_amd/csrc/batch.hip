@@ -75,7 +75,8 @@ struct BatchDev {
     uint32_t* err;
     unsigned long long* pairs;  // [nsys] diagnostic nuclear pair counts
     double* red;          // [256] host-read reduction partials
-    int nuc_variant;      // 0 dense, 1 screened + compacted
+    int nuc_variant;      // 0 dense, 1 screened + compacted, 3 the same with 8 lanes/target
+    int chunk;            // targets per nuclear work item (64, or 32 for variant 3)
 };
 
 __device__ __forceinline__ int find_sys_chunk(const BatchDev& B, int64_t g)
@@ -275,13 +276,13 @@ __device__ void phase_scan(const BatchDev& B, int64_t step, int mode, char* lds_
         if (threadIdx.x == 0)
             start[nb] = (int32_t)total;
         __syncthreads();
-        // nuclear work list: ceil(members / NUC_CHUNK) items per cell; fill
+        // nuclear work list: ceil(members / chunk) items per cell; fill
         // doubles as scratch for the per-cell item counts
         const int64_t CS = (int64_t)gr.C * gr.sub;
         for (int64_t c = threadIdx.x; c < gr.C; c += BW) {
             const int32_t m = (start[(c + 1) * gr.sub] - start[c * gr.sub]) +
                               (start[CS + (c + 1) * gr.sub] - start[CS + c * gr.sub]);
-            fill[c] = (m + NUC_CHUNK - 1) / NUC_CHUNK;
+            fill[c] = (m + B.chunk - 1) / B.chunk;
         }
         __syncthreads();
         const int64_t nit = block_exscan(fill, fill + gr.C, gr.C, lds);
@@ -364,12 +365,13 @@ __device__ void phase_rank(const BatchDev& B, int64_t step, int mode)
     }
 }
 
-template <class P, bool COUNT>
+// M: what the pair items accumulate (MODE_FORCE in steps, MODE_ENERGY when
+// the energies are asked for, MODE_COUNT for the pair counts).
+template <class P, int M>
 __device__ void phase_forces(const BatchDev& B, int64_t step, int mode, char* lds, int* s_item)
 {
     const auto* stg = reinterpret_cast<const typename P::Src*>(B.stg);
     const int64_t total = B.coul_items + B.nuc_items;
-    constexpr int M = COUNT ? MODE_COUNT : MODE_ENERGY;  // the batch keeps energies
     unsigned* ctr = B.queue;
     while (true) {
         if (threadIdx.x == 0)
@@ -380,7 +382,7 @@ __device__ void phase_forces(const BatchDev& B, int64_t step, int mode, char* ld
         if (it >= total)
             break;
         if (it < B.coul_items) {
-            if (COUNT)
+            if (M == MODE_COUNT)
                 continue;
             int s = 0;
             while (s + 1 < B.nsys && B.sys[s + 1].coul_item_off <= it)
@@ -391,8 +393,8 @@ __device__ void phase_forces(const BatchDev& B, int64_t step, int mode, char* ld
             PairParams pp = B.pp;
             pp.L = box_at(S, mode ? step + 1 : step);
             const CoulConsts k = make_coul_consts(pp);
-            coulomb_item<P>(stg + S.off, S.Z, S.per_split, k, B.coul_part + S.coul_off, tblock,
-                            split, lds);
+            coulomb_item<P, M != MODE_FORCE>(stg + S.off, S.Z, S.per_split, k,
+                                             B.coul_part + S.coul_off, tblock, split, lds);
         } else {
             const int64_t jt = it - B.coul_items;
             int s = 0;
@@ -417,7 +419,9 @@ __device__ void phase_forces(const BatchDev& B, int64_t step, int mode, char* ld
             A.fnuc = B.fnuc + S.off;  // raw nuclear part; combine adds the rest
             A.pairs = B.pairs + s;
             A.err = B.err;
-            if (B.nuc_variant == 1)
+            if (B.nuc_variant == 3)
+                nuclear_item_compact_t<P, 8, true, M>(stg + S.off, A, k, local, lds);
+            else if (B.nuc_variant == 1)
                 nuclear_item_compact<P, true, M>(stg + S.off, A, k, local, lds);
             else
                 nuclear_item<P, true, M>(stg + S.off, A, k, local, lds);
@@ -425,7 +429,8 @@ __device__ void phase_forces(const BatchDev& B, int64_t step, int mode, char* ld
     }
 }
 
-__device__ void phase_combine(const BatchDev& B, int mode, char* lds_raw)
+// energy: the pair phase accumulated energies; write the shares.
+__device__ void phase_combine(const BatchDev& B, int mode, bool energy, char* lds_raw)
 {
     double* red = reinterpret_cast<double*>(lds_raw);
     for (int64_t g = blockIdx.x; g < B.total_chunks; g += gridDim.x) {
@@ -449,7 +454,8 @@ __device__ void phase_combine(const BatchDev& B, int mode, char* lds_raw)
             B.force[3 * i + 0] = Fx;
             B.force[3 * i + 1] = Fy;
             B.force[3 * i + 2] = Fz;
-            B.epot[i] = 0.5 * V;
+            if (energy)
+                B.epot[i] = 0.5 * V;
             if (!(isfinite(Fx) && isfinite(Fy) && isfinite(Fz)))
                 atomicOr(B.err, ERR_NONFINITE_FORCE);
             if (mode) {
@@ -513,7 +519,7 @@ constexpr int batch_lds()
     return (m > c ? m : c) + 64;
 }
 
-template <class P>
+template <class P, int M>
 __global__ __launch_bounds__(BW) void k_batch_step(BatchDev B, int mode)
 {
     __shared__ __align__(16) char lds[batch_lds<P>()];
@@ -533,10 +539,10 @@ __global__ __launch_bounds__(BW) void k_batch_step(BatchDev B, int mode)
     phase_rank<P>(B, step, mode);
     if (!grid_sync(B, &s_flag))
         return;
-    phase_forces<P, false>(B, step, mode, lds, &s_item);
+    phase_forces<P, M>(B, step, mode, lds, &s_item);
     if (!grid_sync(B, &s_flag))
         return;
-    phase_combine(B, mode, lds);
+    phase_combine(B, mode, M != MODE_FORCE, lds);
     if (!grid_sync(B, &s_flag))
         return;
     phase_thermostat(B, step, mode, lds);
@@ -561,17 +567,17 @@ __global__ __launch_bounds__(BW) void k_ph_rank(BatchDev B, int mode)
 {
     phase_rank<P>(B, *B.step, mode);
 }
-template <class P, bool COUNT>
+template <class P, int M>
 __global__ __launch_bounds__(BW) void k_ph_forces(BatchDev B, int mode)
 {
     __shared__ __align__(16) char lds[batch_lds<P>()];
     __shared__ int s_item;
-    phase_forces<P, COUNT>(B, *B.step, mode, lds, &s_item);
+    phase_forces<P, M>(B, *B.step, mode, lds, &s_item);
 }
-__global__ __launch_bounds__(BW) void k_ph_combine(BatchDev B, int mode)
+__global__ __launch_bounds__(BW) void k_ph_combine(BatchDev B, int mode, int energy)
 {
     __shared__ __align__(16) char lds[64];
-    phase_combine(B, mode, lds);
+    phase_combine(B, mode, energy != 0, lds);
 }
 __global__ __launch_bounds__(BW) void k_ph_thermostat(BatchDev B, int mode)
 {
@@ -692,6 +698,7 @@ struct pasta_batch {
     hipGraph_t graph = nullptr;
     hipGraphExec_t exec = nullptr;
     double* red;         // [256]
+    bool epot_valid = false;  // steps compute forces only
     ~pasta_batch()
     {
         if (stream)
@@ -734,6 +741,15 @@ struct BatchLayout {
     int64_t bins = 0, starts = 0, items = 0, coul = 0;
 };
 
+// Nuclear variant of the batch (the lists run as 3: the batch rebuilds its
+// cells every step) and its work-item size.
+int batch_variant()
+{
+    const int v = g_tuning.nuclear_variant;
+    return v == 0 ? 0 : (v == 1 ? 1 : 3);
+}
+int batch_chunk() { return nuclear_chunk_for(batch_variant()); }
+
 int batch_layout(const pasta_potential* pot, int nsys, const int64_t* n, const int64_t* Z,
                  const double* L_max, BatchLayout* out)
 {
@@ -750,7 +766,7 @@ int batch_layout(const pasta_potential* pot, int nsys, const int64_t* n, const i
         S.Z = Z ? (int32_t)Z[s] : (int32_t)n[s];
         S.bin_off = lay.bins;
         S.start_off = lay.starts;
-        S.item_max = (int32_t)(n[s] / NUC_CHUNK + C_max + 1);
+        S.item_max = (int32_t)(n[s] / batch_chunk() + C_max + 1);
         S.item_off = lay.items;
         S.S = coulomb_splits(S.Z);
         S.per_split = S.S ? (int32_t)((S.Z + S.S - 1) / S.S) : 0;
@@ -806,20 +822,28 @@ size_t batch_carve(Carver& cv, const BatchLayout& lay, int nsys, int precision, 
     return cv.size();
 }
 
+// Steps (mode 1) accumulate forces only; the initial evaluation (mode 0)
+// also the energies.
 template <class P>
 int launch_step(pasta_batch* bt, int mode)
 {
     hipStream_t s = bt->stream;
     if (bt->mode == 0) {
-        k_batch_step<P><<<bt->grid, BW, 0, s>>>(bt->dev, mode);
+        if (mode)
+            k_batch_step<P, MODE_FORCE><<<bt->grid, BW, 0, s>>>(bt->dev, mode);
+        else
+            k_batch_step<P, MODE_ENERGY><<<bt->grid, BW, 0, s>>>(bt->dev, mode);
     } else {
         const unsigned g = bt->phase_grid;
         k_ph_drift<P><<<g, BW, 0, s>>>(bt->dev, mode);
         k_ph_scan<<<(unsigned)bt->nsys, BW, 0, s>>>(bt->dev, mode);
         k_ph_scatter<<<g, BW, 0, s>>>(bt->dev, mode);
         k_ph_rank<P><<<g, BW, 0, s>>>(bt->dev, mode);
-        k_ph_forces<P, false><<<g, BW, 0, s>>>(bt->dev, mode);
-        k_ph_combine<<<g, BW, 0, s>>>(bt->dev, mode);
+        if (mode)
+            k_ph_forces<P, MODE_FORCE><<<g, BW, 0, s>>>(bt->dev, mode);
+        else
+            k_ph_forces<P, MODE_ENERGY><<<g, BW, 0, s>>>(bt->dev, mode);
+        k_ph_combine<<<g, BW, 0, s>>>(bt->dev, mode, mode ? 0 : 1);
         k_ph_thermostat<<<(unsigned)bt->nsys, BW, 0, s>>>(bt->dev, mode);
         if (mode)
             k_ph_advance<<<1, 64, 0, s>>>(bt->dev);
@@ -854,7 +878,13 @@ int persistent_grid(unsigned* out)
     int dev = 0, ncu = 0, occ = 0;
     PASTA_HIP(hipGetDevice(&dev));
     PASTA_HIP(hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev));
-    PASTA_HIP(hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ, k_batch_step<P>, BW, 0));
+    // both instantiations run on the same grid
+    int occ2 = 0;
+    PASTA_HIP(hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ, k_batch_step<P, MODE_FORCE>,
+                                                           BW, 0));
+    PASTA_HIP(hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ2, k_batch_step<P, MODE_ENERGY>,
+                                                           BW, 0));
+    occ = occ < occ2 ? occ : occ2;
     if (occ < 1)
         return fail(PASTA_EHIP, "persistent batch kernel cannot be resident");
     // every workgroup must be resident at once: the occupancy the runtime
@@ -985,8 +1015,8 @@ extern "C" int pasta_batch_create(const pasta_potential* pot, int32_t precision,
     B.pp.lambda_s = pot->lambda_s;
     B.pp.L = 0.0;
     B.mass = pot->mass;
-    // the batch's items hold 64 targets: variants 2 and 3 run as 1
-    B.nuc_variant = g_tuning.nuclear_variant == 0 ? 0 : 1;
+    B.nuc_variant = batch_variant();
+    B.chunk = batch_chunk();
     B.pos = d_pos;
     B.vel = d_vel;
     B.species = d_species;
@@ -1007,6 +1037,7 @@ extern "C" int pasta_batch_create(const pasta_potential* pot, int32_t precision,
         rc = check_batch_err(bt, "pasta_batch_create");
     if (rc != PASTA_OK)
         return fail_free(rc);
+    bt->epot_valid = true;
     rc = join_out(bt);
     if (rc != PASTA_OK)
         return fail_free(rc);
@@ -1044,7 +1075,7 @@ extern "C" int pasta_batch_step(pasta_batch* bt, int64_t nsteps)
         const Grid gr = make_grid(L, bt->pot.r_nuc);
         const double Lm = bt->sys[s].L0 * (1.0 + g.xi_dot * ((double)bt->step * g.dt));
         const Grid g0 = make_grid(Lm, bt->pot.r_nuc);
-        const int64_t cap = (int64_t)bt->sys[s].item_max - bt->sys[s].n / NUC_CHUNK - 1;
+        const int64_t cap = (int64_t)bt->sys[s].item_max - bt->sys[s].n / bt->dev.chunk - 1;
         if (L < 2.0 * bt->pot.r_nuc || gr.C > cap || g0.C > cap)
             return fail(PASTA_EBOX, "pasta_batch_step: system %d leaves [2 r_nuc, L_max]", s);
     }
@@ -1062,7 +1093,30 @@ extern "C" int pasta_batch_step(pasta_batch* bt, int64_t nsteps)
     k_reset_pending<<<1, 1024, 0, st>>>(bt->dev);
     PASTA_HIP(hipGetLastError());
     bt->step += nsteps;
+    if (nsteps > 0)
+        bt->epot_valid = false;
     return join_out(bt);
+}
+
+// Energy shares of the current state, evaluated when asked for (the steps
+// skip them): the pair phase with energies and the combine without a kick,
+// on the cell lists and staging already in place; the forces are rewritten
+// with the same bits.
+static int batch_refresh_energies(pasta_batch* bt)
+{
+    if (bt->epot_valid)
+        return PASTA_OK;
+    hipStream_t s = bt->stream;
+    k_batch_zero_pairs<<<1, 1024, 0, s>>>(bt->dev);
+    const unsigned g = bt->phase_grid;
+    if (bt->precision == PASTA_FP64)
+        k_ph_forces<Fp64Policy, MODE_ENERGY><<<g, BW, 0, s>>>(bt->dev, 0);
+    else
+        k_ph_forces<MixedPolicy, MODE_ENERGY><<<g, BW, 0, s>>>(bt->dev, 0);
+    k_ph_combine<<<g, BW, 0, s>>>(bt->dev, 0, 1);
+    PASTA_HIP(hipGetLastError());
+    bt->epot_valid = true;
+    return PASTA_OK;
 }
 
 extern "C" int pasta_batch_energies(pasta_batch* bt, double* h_ekin, double* h_epot, double* h_L,
@@ -1071,6 +1125,8 @@ extern "C" int pasta_batch_energies(pasta_batch* bt, double* h_ekin, double* h_e
     if (!bt)
         return fail(PASTA_EINVAL, "pasta_batch_energies: null batch");
     PASTA_TRY(join_in(bt));
+    if (h_epot)
+        PASTA_TRY(batch_refresh_energies(bt));
     PASTA_TRY(check_batch_err(bt, "pasta_batch"));
     hipStream_t s = bt->stream;
     std::vector<double> h(256);
@@ -1105,6 +1161,8 @@ extern "C" int pasta_batch_forces(pasta_batch* bt, double* d_force, double* d_ep
     if (!bt)
         return fail(PASTA_EINVAL, "pasta_batch_forces: null batch");
     PASTA_TRY(join_in(bt));
+    if (d_epot)
+        PASTA_TRY(batch_refresh_energies(bt));
     if (d_force)
         PASTA_HIP(hipMemcpyAsync(d_force, bt->dev.force, sizeof(double) * 3 * bt->n_total,
                                  hipMemcpyDeviceToDevice, bt->stream));
@@ -1125,9 +1183,9 @@ extern "C" int pasta_batch_pair_counts(pasta_batch* bt, int64_t* h_nuclear, int6
     // count pass rewrites F (same values) without a kick
     const unsigned g = bt->phase_grid;
     if (bt->precision == PASTA_FP64)
-        k_ph_forces<Fp64Policy, true><<<g, BW, 0, s>>>(bt->dev, 0);
+        k_ph_forces<Fp64Policy, MODE_COUNT><<<g, BW, 0, s>>>(bt->dev, 0);
     else
-        k_ph_forces<MixedPolicy, true><<<g, BW, 0, s>>>(bt->dev, 0);
+        k_ph_forces<MixedPolicy, MODE_COUNT><<<g, BW, 0, s>>>(bt->dev, 0);
     PASTA_HIP(hipGetLastError());
     std::vector<unsigned long long> h(bt->nsys);
     PASTA_HIP(hipMemcpyAsync(h.data(), bt->dev.pairs, sizeof(unsigned long long) * bt->nsys,

@@ -116,25 +116,57 @@ def test_batch_modes_and_graph_replay_agree(env):
         assert np.abs(v - outs[0][1]).max() <= 1e-12
 
 
-def test_batch_matches_single_system_path(env):
+@pytest.mark.parametrize("variant", [1, 3])
+def test_batch_matches_single_system_path(env, variant):
+    """With the same nuclear variant, the batched and single-system paths run
+    the same items in the same order."""
     t, B = env["torch"], env["B"]
     specs = SMALL[:3]
-    b, states, pos, vel, offs = make(env, specs, prec=1, mode=0,
-                                     integs=[dict(dt=2.0, T=1.0, rescale_every=5)] * 3)
-    b.step(12)
-    P = pos.cpu().numpy()
-    for k, st in enumerate(states):
-        p1 = t.tensor(st["pos"], device=env["dev"])
-        v1 = t.tensor(st["vel"], device=env["dev"])
-        s1 = t.tensor(st["species"], device=env["dev"])
-        sim = B.Sim(p1, v1, s1, st["L"], dt=2.0, T=1.0, rescale_every=5, precision=1)
-        sim.step(12)
-        d = np.abs(p1.cpu().numpy() - P[offs[k]:offs[k + 1]])
-        d = np.minimum(d, st["L"] - d)
-        say(f"  system {k}: batch vs single max |dx| {d.max():.3e}")
-        assert d.max() <= 1e-9
-        sim.close()
-    b.close()
+    old = B.pasta_set_tuning(nuclear_variant=variant)
+    try:
+        b, states, pos, vel, offs = make(env, specs, prec=1, mode=0,
+                                         integs=[dict(dt=2.0, T=1.0, rescale_every=5)] * 3)
+        b.step(12)
+        P = pos.cpu().numpy()
+        for k, st in enumerate(states):
+            p1 = t.tensor(st["pos"], device=env["dev"])
+            v1 = t.tensor(st["vel"], device=env["dev"])
+            s1 = t.tensor(st["species"], device=env["dev"])
+            sim = B.Sim(p1, v1, s1, st["L"], dt=2.0, T=1.0, rescale_every=5, precision=1)
+            sim.step(12)
+            d = np.abs(p1.cpu().numpy() - P[offs[k]:offs[k + 1]])
+            d = np.minimum(d, st["L"] - d)
+            say(f"  variant {variant} system {k}: batch vs single max |dx| {d.max():.3e}")
+            assert d.max() <= 1e-9
+            sim.close()
+        b.close()
+    finally:
+        B.pasta_set_tuning(**old)
+
+
+@pytest.mark.parametrize("mode", [0, 1])
+def test_batch_energy_refresh_keeps_trajectory(env, mode):
+    """Steps compute forces only; asking for energies mid-run re-evaluates the
+    forces with energies on and must not change the trajectory."""
+    t = env["torch"]
+    runs = []
+    for ask in (False, True):
+        b, states, pos, vel, offs = make(env, SMALL[:3], prec=1, mode=mode, spg=3,
+                                         integs=[dict(dt=2.0, T=1.0, rescale_every=4)] * 3)
+        for _ in range(3):
+            b.step(3)
+            if ask:
+                en = b.energies()
+                b.forces()
+        runs.append((pos.clone(), vel.clone()))
+        if ask:
+            # the energies asked for are those of the current state
+            P = pos.cpu().numpy()
+            for k, st in enumerate(states):
+                _, oe = env["O"].forces(P[offs[k]:offs[k + 1]], st["species"], st["L"])
+                assert en["epot"][k] == pytest.approx(oe.sum(), rel=1e-6, abs=1e-6)
+        b.close()
+    assert t.equal(runs[0][0], runs[1][0]) and t.equal(runs[0][1], runs[1][1])
 
 
 def test_batch_thermostat_and_pairs(env):
