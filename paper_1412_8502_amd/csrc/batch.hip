@@ -16,6 +16,8 @@
 // The same phase functions also run as one kernel per phase ("multi-kernel"
 // form) for comparison.  Barrier waits are bounded: a grid that is not fully
 // resident sets an error bit and every workgroup leaves.
+#include <type_traits>
+
 #include "pair_items.hpp"
 
 namespace pasta {
@@ -77,6 +79,11 @@ struct BatchDev {
     double* red;          // [256] host-read reduction partials
     int nuc_variant;      // 0 dense, 1 screened + compacted, 3 the same with 8 lanes/target
     int chunk;            // targets per nuclear work item (64, or 32 for variant 3)
+    // per-system pair constants and cell grid of the current box, written
+    // once per step by the drift phase (read as uniform loads by the items)
+    NucConsts* nk;
+    CoulConsts* ck;
+    int2* grid_nc;        // (nc, C)
 };
 
 __device__ __forceinline__ int find_sys_chunk(const BatchDev& B, int64_t g)
@@ -173,6 +180,18 @@ __device__ void phase_drift(const BatchDev& B, int64_t step, int mode)
 {
     if (blockIdx.x == 0 && threadIdx.x == 0)
         B.queue[0] = 0u;  // work counter of this step's force phase
+    // the pair constants of every system's new box
+    if (blockIdx.x == 0) {
+        for (int s = threadIdx.x; s < B.nsys; s += blockDim.x) {
+            const SysDev& S = B.sys[s];
+            PairParams pp = B.pp;
+            pp.L = box_at(S, mode ? step + 1 : step);
+            B.nk[s] = make_nuc_consts(pp);
+            B.ck[s] = make_coul_consts(pp);
+            const Grid gr = grid_at(pp.L, pp.r_nuc);
+            B.grid_nc[s] = make_int2(gr.nc, gr.C);
+        }
+    }
     for (int64_t g = blockIdx.x; g < B.total_chunks; g += gridDim.x) {
         const int s = find_sys_chunk(B, g);
         const SysDev& S = B.sys[s];
@@ -367,7 +386,7 @@ __device__ void phase_rank(const BatchDev& B, int64_t step, int mode)
 
 // M: what the pair items accumulate (MODE_FORCE in steps, MODE_ENERGY when
 // the energies are asked for, MODE_COUNT for the pair counts).
-template <class P, int M>
+template <class P, int M, int V>
 __device__ void phase_forces(const BatchDev& B, int64_t step, int mode, char* lds, int* s_item)
 {
     const auto* stg = reinterpret_cast<const typename P::Src*>(B.stg);
@@ -387,12 +406,11 @@ __device__ void phase_forces(const BatchDev& B, int64_t step, int mode, char* ld
             int s = 0;
             while (s + 1 < B.nsys && B.sys[s + 1].coul_item_off <= it)
                 ++s;
+            s = __builtin_amdgcn_readfirstlane(s);  // uniform: the constants load as scalars
             const SysDev& S = B.sys[s];
             const int64_t local = it - S.coul_item_off;
             const int tblock = (int)(local % S.coul_blocks), split = (int)(local / S.coul_blocks);
-            PairParams pp = B.pp;
-            pp.L = box_at(S, mode ? step + 1 : step);
-            const CoulConsts k = make_coul_consts(pp);
+            const CoulConsts k = B.ck[s];
             coulomb_item<P, M != MODE_FORCE>(stg + S.off, S.Z, S.per_split, k,
                                              B.coul_part + S.coul_off, tblock, split, lds);
         } else {
@@ -400,28 +418,27 @@ __device__ void phase_forces(const BatchDev& B, int64_t step, int mode, char* ld
             int s = 0;
             while (s + 1 < B.nsys && B.sys[s + 1].nuc_item_off <= jt)
                 ++s;
+            s = __builtin_amdgcn_readfirstlane(s);
             const SysDev& S = B.sys[s];
             const int local = (int)(jt - S.nuc_item_off);
             if (local >= B.n_items[s])
                 continue;
-            PairParams pp = B.pp;
-            pp.L = box_at(S, mode ? step + 1 : step);
-            const Grid gr = grid_at(pp.L, pp.r_nuc);
-            const NucConsts k = make_nuc_consts(pp);
+            const NucConsts k = B.nk[s];
+            const int2 gnc = B.grid_nc[s];
             NucArgs A{};
             A.start = B.start + S.start_off;
             A.items = B.items + 2 * S.item_off;
             A.perm = B.perm + S.off;
-            A.nc = gr.nc;
-            A.C = gr.C;
-            A.sub = gr.sub;
+            A.nc = gnc.x;
+            A.C = gnc.y;
+            A.sub = BSUB;
             A.Z = S.Z;
             A.fnuc = B.fnuc + S.off;  // raw nuclear part; combine adds the rest
             A.pairs = B.pairs + s;
             A.err = B.err;
-            if (B.nuc_variant == 3)
+            if constexpr (V == 3)
                 nuclear_item_compact_t<P, 8, true, M>(stg + S.off, A, k, local, lds);
-            else if (B.nuc_variant == 1)
+            else if constexpr (V == 1)
                 nuclear_item_compact<P, true, M>(stg + S.off, A, k, local, lds);
             else
                 nuclear_item<P, true, M>(stg + S.off, A, k, local, lds);
@@ -510,19 +527,19 @@ __device__ void phase_thermostat(const BatchDev& B, int64_t step, int mode, char
     }
 }
 
-template <class P>
+// One instantiation per nuclear variant V (registers and LDS sized for it).
+template <class P, int V>
 constexpr int batch_lds()
 {
-    constexpr int a = coulomb_lds_bytes<P>(), b = nuclear_lds_bytes<P>(),
-                  c = nuclear_compact_lds_bytes<P>();
-    constexpr int m = a > b ? a : b;
-    return (m > c ? m : c) + 64;
+    constexpr int a = coulomb_lds_bytes<P>();
+    constexpr int b = V == 0 ? nuclear_lds_bytes<P>() : nuclear_compact_lds_bytes<P>();
+    return (a > b ? a : b) + 64;
 }
 
-template <class P, int M>
+template <class P, int M, int V>
 __global__ __launch_bounds__(BW) void k_batch_step(BatchDev B, int mode)
 {
-    __shared__ __align__(16) char lds[batch_lds<P>()];
+    __shared__ __align__(16) char lds[batch_lds<P, V>()];
     __shared__ int s_flag, s_item;
     if (__hip_atomic_load(B.err, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) & ERR_BARRIER)
         return;
@@ -539,7 +556,7 @@ __global__ __launch_bounds__(BW) void k_batch_step(BatchDev B, int mode)
     phase_rank<P>(B, step, mode);
     if (!grid_sync(B, &s_flag))
         return;
-    phase_forces<P, M>(B, step, mode, lds, &s_item);
+    phase_forces<P, M, V>(B, step, mode, lds, &s_item);
     if (!grid_sync(B, &s_flag))
         return;
     phase_combine(B, mode, M != MODE_FORCE, lds);
@@ -567,12 +584,36 @@ __global__ __launch_bounds__(BW) void k_ph_rank(BatchDev B, int mode)
 {
     phase_rank<P>(B, *B.step, mode);
 }
-template <class P, int M>
+template <class P, int M, int V>
 __global__ __launch_bounds__(BW) void k_ph_forces(BatchDev B, int mode)
 {
-    __shared__ __align__(16) char lds[batch_lds<P>()];
+    __shared__ __align__(16) char lds[batch_lds<P, V>()];
     __shared__ int s_item;
-    phase_forces<P, M>(B, *B.step, mode, lds, &s_item);
+    phase_forces<P, M, V>(B, *B.step, mode, lds, &s_item);
+}
+
+template <class F>
+void with_batch_variant(int v, F f)
+{
+    if (v == 0)
+        f(std::integral_constant<int, 0>());
+    else if (v == 3)
+        f(std::integral_constant<int, 3>());
+    else
+        f(std::integral_constant<int, 1>());
+}
+
+// The pair phase alone (mode 0: the state in place, no kick).
+template <int M>
+void launch_pair_phase(const BatchDev& dev, int precision, unsigned g, hipStream_t s)
+{
+    with_batch_variant(dev.nuc_variant, [&](auto vt) {
+        constexpr int V = decltype(vt)::value;
+        if (precision == PASTA_FP64)
+            k_ph_forces<Fp64Policy, M, V><<<g, BW, 0, s>>>(dev, 0);
+        else
+            k_ph_forces<MixedPolicy, M, V><<<g, BW, 0, s>>>(dev, 0);
+    });
 }
 __global__ __launch_bounds__(BW) void k_ph_combine(BatchDev B, int mode, int energy)
 {
@@ -817,6 +858,9 @@ size_t batch_carve(Carver& cv, const BatchLayout& lay, int nsys, int precision, 
     b.err = cv.take<uint32_t>(1);
     b.pairs = cv.take<unsigned long long>(nsys);
     b.red = cv.take<double>(256);
+    b.nk = cv.take<NucConsts>(nsys);
+    b.ck = cv.take<CoulConsts>(nsys);
+    b.grid_nc = cv.take<int2>(nsys);
     if (d)
         *d = b;
     return cv.size();
@@ -829,20 +873,26 @@ int launch_step(pasta_batch* bt, int mode)
 {
     hipStream_t s = bt->stream;
     if (bt->mode == 0) {
-        if (mode)
-            k_batch_step<P, MODE_FORCE><<<bt->grid, BW, 0, s>>>(bt->dev, mode);
-        else
-            k_batch_step<P, MODE_ENERGY><<<bt->grid, BW, 0, s>>>(bt->dev, mode);
+        with_batch_variant(bt->dev.nuc_variant, [&](auto vt) {
+            constexpr int V = decltype(vt)::value;
+            if (mode)
+                k_batch_step<P, MODE_FORCE, V><<<bt->grid, BW, 0, s>>>(bt->dev, mode);
+            else
+                k_batch_step<P, MODE_ENERGY, V><<<bt->grid, BW, 0, s>>>(bt->dev, mode);
+        });
     } else {
         const unsigned g = bt->phase_grid;
         k_ph_drift<P><<<g, BW, 0, s>>>(bt->dev, mode);
         k_ph_scan<<<(unsigned)bt->nsys, BW, 0, s>>>(bt->dev, mode);
         k_ph_scatter<<<g, BW, 0, s>>>(bt->dev, mode);
         k_ph_rank<P><<<g, BW, 0, s>>>(bt->dev, mode);
-        if (mode)
-            k_ph_forces<P, MODE_FORCE><<<g, BW, 0, s>>>(bt->dev, mode);
-        else
-            k_ph_forces<P, MODE_ENERGY><<<g, BW, 0, s>>>(bt->dev, mode);
+        with_batch_variant(bt->dev.nuc_variant, [&](auto vt) {
+            constexpr int V = decltype(vt)::value;
+            if (mode)
+                k_ph_forces<P, MODE_FORCE, V><<<g, BW, 0, s>>>(bt->dev, mode);
+            else
+                k_ph_forces<P, MODE_ENERGY, V><<<g, BW, 0, s>>>(bt->dev, mode);
+        });
         k_ph_combine<<<g, BW, 0, s>>>(bt->dev, mode, mode ? 0 : 1);
         k_ph_thermostat<<<(unsigned)bt->nsys, BW, 0, s>>>(bt->dev, mode);
         if (mode)
@@ -873,17 +923,23 @@ int check_batch_err(pasta_batch* bt, const char* who)
 }
 
 template <class P>
-int persistent_grid(unsigned* out)
+int persistent_grid(int variant, unsigned* out)
 {
     int dev = 0, ncu = 0, occ = 0;
     PASTA_HIP(hipGetDevice(&dev));
     PASTA_HIP(hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev));
     // both instantiations run on the same grid
     int occ2 = 0;
-    PASTA_HIP(hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ, k_batch_step<P, MODE_FORCE>,
-                                                           BW, 0));
-    PASTA_HIP(hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ2, k_batch_step<P, MODE_ENERGY>,
-                                                           BW, 0));
+    hipError_t e1 = hipSuccess, e2 = hipSuccess;
+    with_batch_variant(variant, [&](auto vt) {
+        constexpr int V = decltype(vt)::value;
+        e1 = hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ, k_batch_step<P, MODE_FORCE, V>,
+                                                          BW, 0);
+        e2 = hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ2, k_batch_step<P, MODE_ENERGY, V>,
+                                                          BW, 0);
+    });
+    PASTA_HIP(e1);
+    PASTA_HIP(e2);
     occ = occ < occ2 ? occ : occ2;
     if (occ < 1)
         return fail(PASTA_EHIP, "persistent batch kernel cannot be resident");
@@ -1026,8 +1082,8 @@ extern "C" int pasta_batch_create(const pasta_potential* pot, int32_t precision,
         return fail_free(fail(PASTA_EHIP, "pasta_batch_create: descriptor copy failed"));
     k_batch_init_scalars<<<1, 1024, 0, s>>>(B, step0);
     k_batch_zero<<<256, BW, 0, s>>>(B.count, B.fill, lay.bins);
-    rc = precision == PASTA_FP64 ? persistent_grid<Fp64Policy>(&bt->grid)
-                                 : persistent_grid<MixedPolicy>(&bt->grid);
+    rc = precision == PASTA_FP64 ? persistent_grid<Fp64Policy>(B.nuc_variant, &bt->grid)
+                                 : persistent_grid<MixedPolicy>(B.nuc_variant, &bt->grid);
     if (rc != PASTA_OK)
         return fail_free(rc);
     bt->phase_grid = bt->grid * 2;
@@ -1109,10 +1165,7 @@ static int batch_refresh_energies(pasta_batch* bt)
     hipStream_t s = bt->stream;
     k_batch_zero_pairs<<<1, 1024, 0, s>>>(bt->dev);
     const unsigned g = bt->phase_grid;
-    if (bt->precision == PASTA_FP64)
-        k_ph_forces<Fp64Policy, MODE_ENERGY><<<g, BW, 0, s>>>(bt->dev, 0);
-    else
-        k_ph_forces<MixedPolicy, MODE_ENERGY><<<g, BW, 0, s>>>(bt->dev, 0);
+    launch_pair_phase<MODE_ENERGY>(bt->dev, bt->precision, g, s);
     k_ph_combine<<<g, BW, 0, s>>>(bt->dev, 0, 1);
     PASTA_HIP(hipGetLastError());
     bt->epot_valid = true;
@@ -1182,10 +1235,7 @@ extern "C" int pasta_batch_pair_counts(pasta_batch* bt, int64_t* h_nuclear, int6
     // the cell lists and staging of the current state are in place; the
     // count pass rewrites F (same values) without a kick
     const unsigned g = bt->phase_grid;
-    if (bt->precision == PASTA_FP64)
-        k_ph_forces<Fp64Policy, MODE_COUNT><<<g, BW, 0, s>>>(bt->dev, 0);
-    else
-        k_ph_forces<MixedPolicy, MODE_COUNT><<<g, BW, 0, s>>>(bt->dev, 0);
+    launch_pair_phase<MODE_COUNT>(bt->dev, bt->precision, g, s);
     PASTA_HIP(hipGetLastError());
     std::vector<unsigned long long> h(bt->nsys);
     PASTA_HIP(hipMemcpyAsync(h.data(), bt->dev.pairs, sizeof(unsigned long long) * bt->nsys,
