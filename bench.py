@@ -62,7 +62,8 @@ def measured_traffic(kernel_name, tuning):
             return None
         h.update(src.encode())
         h.update(data)
-    want = [tuning.get("nuclear_variant"), tuning.get("coulomb_splits"), tuning.get("fused_forces")]
+    want = [tuning.get("nuclear_variant"), tuning.get("coulomb_splits"), tuning.get("fused_forces"),
+            tuning.get("coulomb_form", 0)]
     if h.hexdigest() != rec.get("sources_sha256") or rec.get("tuning") != want \
             or rec.get("kernel") != kernel_name:
         return None
@@ -227,7 +228,8 @@ def main():
     ap.add_argument("--batch-steps", type=int, default=500)
     ap.add_argument("--no-batch", action="store_true")
     ap.add_argument("--tuning", default=None,
-                    help="variant,splits,fused: use this kernel setting instead of autotuning")
+                    help="variant,splits,fused[,coulomb_form]: use this kernel setting instead "
+                         "of autotuning")
     ap.add_argument("--headline-only", action="store_true",
                     help="time only the headline path (no dense, list, FP64 or batched runs); "
                          "for profiler runs")
@@ -263,8 +265,10 @@ def main():
     tpos = torch.tensor(st["pos"], device=dev)
     tsp = torch.tensor(st["species"], device=dev)
     if args.tuning:
-        v, sp_, fu = (int(x) for x in args.tuning.split(","))
-        tuned = dict(nuclear_variant=v, coulomb_splits=sp_, fused_forces=fu)
+        vals = [int(x) for x in args.tuning.split(",")]
+        v, sp_, fu = vals[:3]
+        cf = vals[3] if len(vals) > 3 else 0
+        tuned = dict(nuclear_variant=v, coulomb_splits=sp_, fused_forces=fu, coulomb_form=cf)
         tuned64, table, table64 = dict(tuned), [], []
         B.pasta_set_tuning(**tuned)
     else:
@@ -344,8 +348,9 @@ def main():
         ach = flops[dom] / (avg_ms * 1e-3) / 1e12
         traffic = None
         if dom == "nuclear+kick" and tuned.get("fused_forces") and not use_lists:
-            traffic = measured_traffic("k_forces_fused<MixedPolicy, false, %d>"
-                                       % tuned["nuclear_variant"], tuned)
+            traffic = measured_traffic("k_forces_fused<MixedPolicy, 0, %d, %d>"
+                                       % (tuned["nuclear_variant"], tuned.get("coulomb_form", 0)),
+                                       tuned)
         roof = {"kernel": kname.get(dom, dom), "bound": "alu", "achieved": round(ach, 3),
                 "peak": PEAK_FP32_TFLOPS, "unit": "TFLOP/s",
                 "frac": round(ach / PEAK_FP32_TFLOPS, 4), "traffic": traffic,
@@ -403,13 +408,14 @@ def main():
                  "per_kernel_ms": {k: round(v[0] / k64, 5) for k, v in fp64["kernel_times"].items() if v[1]}},
         "mixed_over_fp64_speedup": fp64_ms / ms_step,
         "autotuned": {"mixed": tuned, "fp64": tuned64,
-                      "candidates": "[fused_forces, nuclear_variant, coulomb_splits, ms]",
+                      "candidates": "[fused_forces, nuclear_variant, coulomb_form, "
+                                    "coulomb_splits, ms]",
                       "mixed_candidates_ms": [[c["fused_forces"], c["nuclear_variant"],
-                                               c["coulomb_splits"], round(ms, 5)]
-                                              for c, ms in table],
+                                               c.get("coulomb_form", 0), c["coulomb_splits"],
+                                               round(ms, 5)] for c, ms in table],
                       "fp64_candidates_ms": [[c["fused_forces"], c["nuclear_variant"],
-                                              c["coulomb_splits"], round(ms, 5)]
-                                             for c, ms in table64]},
+                                              c.get("coulomb_form", 0), c["coulomb_splits"],
+                                              round(ms, 5)] for c, ms in table64]},
         "dense_nuclear_variant": {"ms_per_step": dense["seconds"] / kd * 1e3,
                                   "nuclear_ms": dense["kernel_times"]["nuclear+kick"][0] / kd},
         "nuclear_form": "neighbour lists" if use_lists else "cell sweeps",

@@ -122,7 +122,12 @@ typedef struct pasta_integrator {
  *   epilogue adds the Coulomb partials and applies the half kick; 1 = one
  *   launch holding both kinds of work items (they share the GPU) followed by
  *   a small combine + kick kernel.
- * reserved: must be 0.
+ * coulomb_form: 0 = gather tiles (every ordered proton pair, summed per
+ *   target; coulomb_splits applies); 1 = pairwise: every unordered pair once
+ *   (Newton's third law), the reaction carried along the wavefront by a
+ *   lane rotation; 256-proton super-blocks, one partial per super-block and
+ *   proton (used when those partials fit the workspace's partial buffer,
+ *   else the gather form).  The batched path always uses the gather form.
  * list_skin: the halo delta_r of variant 2, fm, in (0, 64] (default 2).
  * list_pool_scale: list memory relative to the default sizing, in (0, 1000]
  *   (default 1; the default holds 1.5 x the expected entries per lane at the
@@ -131,7 +136,7 @@ typedef struct pasta_tuning {
     int32_t nuclear_variant;
     int32_t coulomb_splits;
     int32_t fused_forces;
-    int32_t reserved;
+    int32_t coulomb_form;
     double list_skin;
     double list_pool_scale;
 } pasta_tuning;
@@ -139,8 +144,9 @@ int pasta_set_tuning(const pasta_tuning* t);
 int pasta_get_tuning(pasta_tuning* out);
 /* Autotuner: builds the cell list of the given state once, then times the
  * Coulomb + nuclear kernels (reps evaluations each, HIP events) for every
- * candidate setting -- nuclear variant {0, 1, 3} x Coulomb splits {S/2, S, 2S}
- * around the automatic S x fused_forces {0, 1} -- and returns the fastest
+ * candidate setting -- nuclear variant {0, 1, 3} x Coulomb {gather with
+ * splits S/2, S, 2S around the automatic S, pairwise} x fused_forces {0, 1}
+ * -- and returns the fastest
  * in *h_best (the list fields copied from the current setting; the list
  * form's cost depends on how often the lists are rebuilt, which a single
  * state does not tell, so it is not a candidate).  Optional

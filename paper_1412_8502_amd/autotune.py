@@ -68,7 +68,7 @@ def pasta_autotune(pos, species, L: float, precision: int, reps: int = 3, pot=No
     B._check(B.lib.pasta_autotune(ctypes.byref(pot), precision, n, L, B._p(pos), B._p(species),
                                   B._p(work), work.numel(), B._stream(stream), reps,
                                   ctypes.byref(best), ms, cands, ctypes.byref(ncand)))
-    keys = ("nuclear_variant", "coulomb_splits", "fused_forces")
+    keys = ("nuclear_variant", "coulomb_splits", "fused_forces", "coulomb_form")
     table = [({f: getattr(cands[k], f) for f in keys}, ms[k])
              for k in range(min(ncand.value, cap))]
     return {f: getattr(best, f) for f in keys}, table

@@ -42,12 +42,12 @@ class pasta_potential(ctypes.Structure):
 
 class pasta_tuning(ctypes.Structure):
     _fields_ = [("nuclear_variant", ctypes.c_int32), ("coulomb_splits", ctypes.c_int32),
-                ("fused_forces", ctypes.c_int32), ("reserved", ctypes.c_int32),
+                ("fused_forces", ctypes.c_int32), ("coulomb_form", ctypes.c_int32),
                 ("list_skin", ctypes.c_double), ("list_pool_scale", ctypes.c_double)]
 
 
-TUNING_FIELDS = ("nuclear_variant", "coulomb_splits", "fused_forces", "list_skin",
-                 "list_pool_scale")
+TUNING_FIELDS = ("nuclear_variant", "coulomb_splits", "fused_forces", "coulomb_form",
+                 "list_skin", "list_pool_scale")
 
 
 class pasta_integrator(ctypes.Structure):
@@ -171,8 +171,8 @@ def pasta_get_tuning() -> dict:
 
 def pasta_set_tuning(**kw):
     """Process-wide kernel choices (see pasta_tuning in include/pasta.h):
-    any of nuclear_variant, coulomb_splits, fused_forces, list_skin,
-    list_pool_scale; the others keep their values.  Returns the previous
+    any of nuclear_variant, coulomb_splits, fused_forces, coulomb_form,
+    list_skin, list_pool_scale; the others keep their values.  Returns the previous
     setting as a dict."""
     bad = set(kw) - set(TUNING_FIELDS)
     if bad:

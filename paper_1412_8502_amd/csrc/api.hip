@@ -269,10 +269,9 @@ static void eval_forces(int precision, int terms, const ForceWork& w, const Grid
         return;
     }
     int S = 0;
-    if ((terms & PASTA_TERM_COULOMB) && Z > 0) {
-        launch_coulomb(precision, w.fb, Z, pp, epot != nullptr || pair_counter != nullptr, s, t);
-        S = coulomb_splits(Z);
-    }
+    if ((terms & PASTA_TERM_COULOMB) && Z > 0)
+        S = launch_coulomb(precision, w.fb, Z, pp, epot != nullptr || pair_counter != nullptr, s,
+                           t);
     launch_nuclear(precision, w.fb, w.cb, g, n, Z, pp, (terms & PASTA_TERM_NUCLEAR) != 0, S,
                    force, epot, kick, pair_counter, w.err, s, t, w.variant, lb);
 }
@@ -305,7 +304,7 @@ extern "C" int pasta_set_tuning(const pasta_tuning* t)
 {
     if (!t || t->nuclear_variant < 0 || t->nuclear_variant > 3 || t->coulomb_splits < 0 ||
         t->coulomb_splits > 32 || (t->fused_forces != 0 && t->fused_forces != 1) ||
-        t->reserved != 0 || !(t->list_skin > 0.0 && t->list_skin <= 64.0) ||
+        (t->coulomb_form != 0 && t->coulomb_form != 1) || !(t->list_skin > 0.0 && t->list_skin <= 64.0) ||
         !(t->list_pool_scale > 0.0 && t->list_pool_scale <= 1e3))
         return fail(PASTA_EINVAL, "pasta_set_tuning: bad argument");
     g_tuning = *t;
@@ -438,8 +437,9 @@ extern "C" int pasta_forces(const pasta_potential* pot, int32_t precision, int32
 // Times the two pair kernels (Coulomb + nuclear with its epilogue) on the
 // given state for every candidate setting and keeps the fastest.  Candidates:
 // nuclear variant {dense, compacted, compacted with 8 lanes per target} x
-// Coulomb source splits {S/2, S, 2S} around the automatic S (clamped to
-// 1..32) x fused {0, 1}.  The cell list is built once per item size.
+// Coulomb {gather with source splits S/2, S, 2S around the automatic S
+// (clamped to 1..32), pairwise} x fused {0, 1}.  The cell list is built
+// once per item size.
 extern "C" int pasta_autotune(const pasta_potential* pot, int32_t precision, int64_t n, double L,
                               const double* d_pos, const uint8_t* d_species, void* d_work,
                               size_t work_bytes, void* stream, int32_t reps, pasta_tuning* h_best,
@@ -492,9 +492,11 @@ extern "C" int pasta_autotune(const pasta_potential* pot, int32_t precision, int
     auto_t.nuclear_variant = 1;
     auto_t.coulomb_splits = 0;
     auto_t.fused_forces = 0;
+    auto_t.coulomb_form = 0;
     g_tuning = auto_t;
     const int S0 = Z > 0 ? coulomb_splits(Z) : 1;
     std::vector<pasta_tuning> cands;
+    const bool pair_fits = Z > 0 && (int64_t)coulomb_pair_plan_supers(Z) * Z <= w.fb.coul_max;
     for (int fused = 0; fused <= 1; ++fused)
         for (int v : {0, 1, 3}) {
             int last = -1;
@@ -507,6 +509,15 @@ extern "C" int pasta_autotune(const pasta_potential* pot, int32_t precision, int
                 c.nuclear_variant = v;
                 c.coulomb_splits = sv;
                 c.fused_forces = fused;
+                c.coulomb_form = 0;
+                cands.push_back(c);
+            }
+            if (pair_fits) {
+                pasta_tuning c = saved;
+                c.nuclear_variant = v;
+                c.coulomb_splits = 0;
+                c.fused_forces = fused;
+                c.coulomb_form = 1;
                 cands.push_back(c);
             }
         }

@@ -31,6 +31,15 @@ __global__ __launch_bounds__(WG) void k_coulomb(const typename P::Src* __restric
     coulomb_item<P, E>(stg, Z, per_split, k, part, blockIdx.x, blockIdx.y, lds);
 }
 
+template <class P, bool E>
+__global__ __launch_bounds__(WG) void k_coulomb_pair(const typename P::Src* __restrict__ stg,
+                                                     int Z, CoulConsts k,
+                                                     double4* __restrict__ part)
+{
+    __shared__ __align__(16) char lds[coulomb_pair_lds_bytes<P>()];
+    coulomb_pair_item<P, E>(stg, Z, k, part, blockIdx.x, lds);
+}
+
 template <class P, bool NUC, int MODE>
 __global__ __launch_bounds__(WG) void k_nuclear(const typename P::Src* __restrict__ stg,
                                                 NucArgs A, const int32_t* __restrict__ n_items,
@@ -101,12 +110,15 @@ __global__ __launch_bounds__(WG) void k_list_build(const typename P::Src* __rest
 template <class P, int V>
 constexpr int fused_lds_bytes()
 {
+    static_assert(coulomb_pair_lds_bytes<P>() <= coulomb_lds_bytes<P>(), "LDS of the pair form");
     constexpr int a = coulomb_lds_bytes<P>();
     constexpr int b = V == 0 ? nuclear_lds_bytes<P>() : nuclear_compact_lds_bytes<P>();
     return a > b ? a : b;
 }
 
-template <class P, int MODE, int V>
+// CF: Coulomb form, 0 = gather tiles (coul_blocks x splits items), 1 =
+// pairwise super-block items.
+template <class P, int MODE, int V, int CF>
 __global__ __launch_bounds__(WG) void k_forces_fused(const typename P::Src* __restrict__ stg,
                                                      NucArgs A, const int32_t* __restrict__ n_items,
                                                      int item_max, NucConsts k, int Z,
@@ -129,8 +141,11 @@ __global__ __launch_bounds__(WG) void k_forces_fused(const typename P::Src* __re
             nuclear_item<P, true, MODE>(stg, A, k, g, lds);
     } else {
         const int h = g - item_max;
-        coulomb_item<P, MODE != MODE_FORCE>(stg, Z, per_split, kc, part, h % coul_blocks,
-                                            h / coul_blocks, lds);
+        if constexpr (CF == 1)
+            coulomb_pair_item<P, MODE != MODE_FORCE>(stg, Z, kc, part, h, lds);
+        else
+            coulomb_item<P, MODE != MODE_FORCE>(stg, Z, per_split, kc, part, h % coul_blocks,
+                                                h / coul_blocks, lds);
     }
 }
 
@@ -315,7 +330,23 @@ int coulomb_splits(int64_t Z)
     return (int)s;
 }
 
-pasta_tuning g_tuning = {1, 0, 1, 0, 2.0, 1.0};
+int coulomb_pair_plan_supers(int64_t Z) { return coulomb_pair_supers(Z); }
+
+CoulPlan coulomb_plan(int64_t Z, int64_t coul_max)
+{
+    CoulPlan p{0, 0};
+    if (Z <= 0)
+        return p;
+    if (g_tuning.coulomb_form == 1 && (int64_t)coulomb_pair_supers(Z) * Z <= coul_max) {
+        p.form = 1;
+        p.S = coulomb_pair_supers(Z);
+    } else {
+        p.S = coulomb_splits(Z);
+    }
+    return p;
+}
+
+pasta_tuning g_tuning = {1, 0, 1, 0, 2.0, 1.0};  // coulomb_form 0: gather
 
 void launch_forces_fused(int precision, const ForceBuf& fb, const CellBuf& cb, const Grid& g,
                          int64_t n, int64_t Z, const PairParams& pp, bool with_nuclear_terms,
@@ -325,9 +356,12 @@ void launch_forces_fused(int precision, const ForceBuf& fb, const CellBuf& cb, c
 {
     const NucConsts k = make_nuc_consts(pp);
     const CoulConsts kc = make_coul_consts(pp);
-    const int S = (with_coulomb && Z > 0) ? coulomb_splits(Z) : 0;
+    const CoulPlan plan = (with_coulomb && Z > 0) ? coulomb_plan(Z, fb.coul_max) : CoulPlan{0, 0};
+    const int S = plan.S;
     const int per = S ? (int)((Z + S - 1) / S) : 0;
     const int coul_blocks = S ? (int)((Z + WG - 1) / WG) : 0;
+    const int64_t coul_items = S == 0 ? 0 : (plan.form == 1 ? coulomb_pair_items(Z)
+                                                            : (int64_t)coul_blocks * S);
     NucArgs a{};
     a.start = cb.start;
     a.items = cb.items;
@@ -341,7 +375,7 @@ void launch_forces_fused(int precision, const ForceBuf& fb, const CellBuf& cb, c
     a.fnuc = fb.fnuc;
     (void)with_nuclear_terms;  // the fused form always carries the nuclear terms
     const int item_max = (int)cb.item_max;
-    const unsigned grid = (unsigned)(item_max + coul_blocks * S);
+    const unsigned grid = (unsigned)(item_max + coul_items);
     const int mode = pair_counter ? MODE_COUNT : (epot ? MODE_ENERGY : MODE_FORCE);
     if (variant == 2 && !lb)
         variant = 1;
@@ -351,14 +385,21 @@ void launch_forces_fused(int precision, const ForceBuf& fb, const CellBuf& cb, c
         auto go = [&](auto vtag, auto mtag) {
             constexpr int V = decltype(vtag)::value;
             constexpr int M = decltype(mtag)::value;
-            if (precision == PASTA_FP64)
-                k_forces_fused<Fp64Policy, M, V><<<grid, WG, 0, s>>>(
-                    fb.stg64, a, cb.n_items, item_max, k, (int)Z, per, coul_blocks, kc,
-                    fb.coul_part, la);
+            auto launch = [&](auto ctag) {
+                constexpr int CF = decltype(ctag)::value;
+                if (precision == PASTA_FP64)
+                    k_forces_fused<Fp64Policy, M, V, CF><<<grid, WG, 0, s>>>(
+                        fb.stg64, a, cb.n_items, item_max, k, (int)Z, per, coul_blocks, kc,
+                        fb.coul_part, la);
+                else
+                    k_forces_fused<MixedPolicy, M, V, CF><<<grid, WG, 0, s>>>(
+                        fb.stgq, a, cb.n_items, item_max, k, (int)Z, per, coul_blocks, kc,
+                        fb.coul_part, la);
+            };
+            if (plan.form == 1)
+                launch(std::integral_constant<int, 1>());
             else
-                k_forces_fused<MixedPolicy, M, V><<<grid, WG, 0, s>>>(
-                    fb.stgq, a, cb.n_items, item_max, k, (int)Z, per, coul_blocks, kc,
-                    fb.coul_part, la);
+                launch(std::integral_constant<int, 0>());
         };
         with_mode(mode, [&](auto mt) {
             switch (variant) {
@@ -394,16 +435,33 @@ size_t forcebuf_carve(Carver& cv, ForceBuf* out, int64_t n, int64_t item_max, in
     return cv.size();
 }
 
-void launch_coulomb(int precision, const ForceBuf& fb, int64_t Z, const PairParams& pp,
-                    bool energy, hipStream_t s, Timer* t)
+int launch_coulomb(int precision, const ForceBuf& fb, int64_t Z, const PairParams& pp,
+                   bool energy, hipStream_t s, Timer* t)
 {
     if (Z <= 0)
-        return;
-    const int S = coulomb_splits(Z);
+        return 0;
+    const CoulPlan plan = coulomb_plan(Z, fb.coul_max);
+    const int S = plan.S;
     const int per = (int)((Z + S - 1) / S);
     const CoulConsts k = make_coul_consts(pp);
-    dim3 grid((unsigned)((Z + WG - 1) / WG), (unsigned)S);
     timer_begin(t, KC_COULOMB, s);
+    if (plan.form == 1) {
+        const unsigned g1 = (unsigned)coulomb_pair_items(Z);
+        if (precision == PASTA_FP64) {
+            if (energy)
+                k_coulomb_pair<Fp64Policy, true><<<g1, WG, 0, s>>>(fb.stg64, (int)Z, k, fb.coul_part);
+            else
+                k_coulomb_pair<Fp64Policy, false><<<g1, WG, 0, s>>>(fb.stg64, (int)Z, k, fb.coul_part);
+        } else {
+            if (energy)
+                k_coulomb_pair<MixedPolicy, true><<<g1, WG, 0, s>>>(fb.stgq, (int)Z, k, fb.coul_part);
+            else
+                k_coulomb_pair<MixedPolicy, false><<<g1, WG, 0, s>>>(fb.stgq, (int)Z, k, fb.coul_part);
+        }
+        timer_end(t, KC_COULOMB, s);
+        return S;
+    }
+    dim3 grid((unsigned)((Z + WG - 1) / WG), (unsigned)S);
     if (precision == PASTA_FP64) {
         if (energy)
             k_coulomb<Fp64Policy, true><<<grid, WG, 0, s>>>(fb.stg64, (int)Z, per, k, fb.coul_part);
@@ -416,6 +474,7 @@ void launch_coulomb(int precision, const ForceBuf& fb, int64_t Z, const PairPara
             k_coulomb<MixedPolicy, false><<<grid, WG, 0, s>>>(fb.stgq, (int)Z, per, k, fb.coul_part);
     }
     timer_end(t, KC_COULOMB, s);
+    return S;
 }
 
 void launch_nuclear(int precision, const ForceBuf& fb, const CellBuf& cb, const Grid& g,

@@ -318,14 +318,26 @@ struct ForceBuf {
     uint64_t* pairs;    // [2] diagnostic pair counters
 };
 int coulomb_splits(int64_t Z);
+// How the Coulomb partials of Z protons are produced: form 0 = gather tiles
+// with S source splits, 1 = pairwise super-block items (S = super-blocks of
+// 256 protons; used when S Z partials fit coul_max).  Every proton gets S
+// partials.
+struct CoulPlan {
+    int form;
+    int S;
+};
+CoulPlan coulomb_plan(int64_t Z, int64_t coul_max);
+// Super-blocks (partials per proton) of the pairwise form for Z protons.
+int coulomb_pair_plan_supers(int64_t Z);
 // Process-wide kernel choices (set through pasta_set_tuning).
 extern pasta_tuning g_tuning;
 size_t forcebuf_carve(Carver& cv, ForceBuf* out, int64_t n, int64_t item_max, int precision);
 
 // Coulomb all-pairs over protons (sorted slots [0, Z)).
 // energy: also accumulate the energy shares (else the partials' w is 0).
-void launch_coulomb(int precision, const ForceBuf& fb, int64_t Z, const PairParams& pp,
-                    bool energy, hipStream_t s, Timer* t);
+// Returns the number of partials per proton written (the S to add).
+int launch_coulomb(int precision, const ForceBuf& fb, int64_t Z, const PairParams& pp,
+                   bool energy, hipStream_t s, Timer* t);
 // Nuclear cell-tile kernel; adds the coul_S Coulomb partials of proton
 // targets (coul_S = 0: none),
 // writes F and E in caller order, optionally applies the second half kick.

@@ -176,6 +176,23 @@ struct Fp64Policy {
         if (E)
             e += v;
     }
+    // Pairwise form: the difference vector, the force factor fs (force on
+    // the first particle = fs d, on the second -fs d) and the pair energy w.
+    __device__ static void coul_pair(const Src& me, const Src& s, const CoulConsts& k, CAcc& dx,
+                                     CAcc& dy, CAcc& dz, CAcc& fs, CAcc& w)
+    {
+        dx = me.x - s.x;
+        dy = me.y - s.y;
+        dz = me.z - s.z;
+        dx = fma(-k.L, rint(dx * k.invL), dx);
+        dy = fma(-k.L, rint(dy * k.invL), dy);
+        dz = fma(-k.L, rint(dz * k.invL), dz);
+        const double r2 = dx * dx + dy * dy + dz * dz;
+        const double ir = rsqrt_fast(r2);
+        const double r = r2 * ir;
+        w = k.ahc * exp_nonpos(-r * k.inv_lambda) * ir;
+        fs = w * (ir + k.inv_lambda) * ir;
+    }
     __device__ static double coul_fscale(const CoulConsts&) { return 1.0; }
     __device__ static double coul_vscale(const CoulConsts&) { return 1.0; }
     // 32-bit fixed-point coordinates (x/L * 2^32) for the screening pass
@@ -260,6 +277,18 @@ struct MixedPolicy {
         if (E)
             e += w;
     }
+    __device__ static void coul_pair(const Src& me, const Src& s, const CoulConsts& k, CAcc& dx,
+                                     CAcc& dy, CAcc& dz, CAcc& fs, CAcc& w)
+    {
+        dx = (float)(int32_t)(me.x - s.x);
+        dy = (float)(int32_t)(me.y - s.y);
+        dz = (float)(int32_t)(me.z - s.z);
+        const float r2 = dx * dx + dy * dy + dz * dz;
+        const float ir = __builtin_amdgcn_rsqf(r2);
+        const float ru = r2 * ir;
+        w = __builtin_amdgcn_exp2f(ru * k.c_exp) * ir;
+        fs = w * ir * fmaf(ir, k.cA, k.cB);
+    }
     __device__ static double coul_fscale(const CoulConsts& k) { return k.f_scale; }
     __device__ static double coul_vscale(const CoulConsts& k) { return k.v_scale; }
     __device__ static uint3 fixed(const Src& s, const NucConsts&)
@@ -322,6 +351,197 @@ __device__ void coulomb_item(const typename P::Src* __restrict__ stg, int Z, int
         const double fs = P::coul_fscale(k), vs = P::coul_vscale(k);
         part[(int64_t)split * Z + t] = make_double4(fx * fs, fy * fs, fz * fs, e * vs);
     }
+}
+
+// ============================================== Coulomb, pairwise form ==
+// Each unordered proton pair is evaluated once (Newton's third law).
+// Protons (sorted slots [0, Z)) are taken in blocks of 64, one per lane of
+// a wavefront, and super-blocks of CP_SUPER blocks.  A work item is a
+// super-block pair (A, B), A <= B, and one workgroup: wavefront w owns the
+// target block I = CP_SUPER A + w and visits every source block J of B
+// (J >= I when A == B).  For an off-diagonal block pair each lane evaluates
+// 64 pairs: (its target, the source it holds), adding the force to its
+// target and the reaction to the source's accumulator; then the source
+// coordinates and accumulators move one lane along the wavefront (a
+// wave-wide rotate), so after 64 steps every source has met every target
+// and its accumulator is back at its own lane.  A diagonal block (J = I)
+// needs the rotations 1..32 only, the 32nd on half of the lanes (lanes l
+// and l + 32 then hold the same pair), and a final move by 32 lanes.
+// Partials: proton p of super-block X receives from item (A, B) the sum of
+// its contributions as part[Y][p], Y the other super-block of the item
+// (Y = X when A == B), i.e. exactly one partial per super-block, which the
+// combine adds in super-block order.
+constexpr int CP_SUPER = 4;  // blocks per super-block (= wavefronts per workgroup)
+static_assert(CP_SUPER * 64 == WG, "one wavefront per block of a super-block");
+
+__host__ __device__ inline int coulomb_pair_supers(int64_t Z) { return (int)((Z + 255) / 256); }
+__host__ __device__ inline int64_t coulomb_pair_items(int64_t Z)
+{
+    const int64_t S = coulomb_pair_supers(Z);
+    return S * (S + 1) / 2;
+}
+
+__device__ __forceinline__ uint32_t wave_rotate(uint32_t v)
+{
+    // DPP wave_rol:1 -- one lane along the whole wavefront (a rotation: every
+    // lane has a source lane, so no old value is needed)
+    return (uint32_t)__builtin_amdgcn_mov_dpp((int)v, 0x134, 0xF, 0xF, true);
+}
+__device__ __forceinline__ float wave_rotate(float v)
+{
+    return __builtin_bit_cast(float, wave_rotate(__builtin_bit_cast(uint32_t, v)));
+}
+__device__ __forceinline__ double wave_rotate(double v)
+{
+    uint2 u = __builtin_bit_cast(uint2, v);
+    u.x = wave_rotate(u.x);
+    u.y = wave_rotate(u.y);
+    return __builtin_bit_cast(double, u);
+}
+__device__ __forceinline__ Q4 wave_rotate(const Q4& s)
+{
+    Q4 r;
+    r.x = wave_rotate(s.x);
+    r.y = wave_rotate(s.y);
+    r.z = wave_rotate(s.z);
+    r.w = s.w;
+    return r;
+}
+__device__ __forceinline__ double4 wave_rotate(const double4& s)
+{
+    return make_double4(wave_rotate(s.x), wave_rotate(s.y), wave_rotate(s.z), s.w);
+}
+
+template <class P>
+constexpr int coulomb_pair_lds_bytes()
+{
+    return CP_SUPER * CP_SUPER * 64 * 4 * (int)sizeof(typename P::CAcc);
+}
+
+template <class P, bool E>
+__device__ void coulomb_pair_item(const typename P::Src* __restrict__ stg, int Z,
+                                  const CoulConsts& k, double4* __restrict__ part, int item,
+                                  char* lds)
+{
+    using Src = typename P::Src;
+    using CA = typename P::CAcc;
+    CA* acc = reinterpret_cast<CA*>(lds);  // [wave][block of B][lane][4]
+    const int S = coulomb_pair_supers(Z);
+    int A = 0, r = item;
+    while (r >= S - A) {
+        r -= S - A;
+        ++A;
+    }
+    const int Bs = A + r;
+    const int tid = threadIdx.x, w = tid >> 6, lane = tid & 63;
+    const int nb = (Z + 63) / 64;
+    for (int i = tid; i < CP_SUPER * CP_SUPER * 64 * 4; i += WG)
+        acc[i] = CA(0);
+    __syncthreads();
+    const int I = CP_SUPER * A + w;  // wave-uniform
+    if (I < nb) {
+        const int t = I * 64 + lane;
+        const bool tv = t < Z;
+        const Src me = stg[tv ? t : Z - 1];
+        CA tx = 0, ty = 0, tz = 0, te = 0;
+        const int J0 = A == Bs ? I : CP_SUPER * Bs;
+        const int J1 = min(CP_SUPER * Bs + CP_SUPER, nb);
+        for (int J = J0; J < J1; ++J) {
+            const int s0 = J * 64 + lane;
+            Src src = stg[s0 < Z ? s0 : Z - 1];
+            CA sx = 0, sy = 0, sz = 0, se = 0;
+            const bool full = I * 64 + 64 <= Z && J * 64 + 64 <= Z;  // wave-uniform
+            auto one = [&](bool valid) {
+                CA dx, dy, dz, fs, wv;
+                P::coul_pair(me, src, k, dx, dy, dz, fs, wv);
+                fs = valid ? fs : CA(0);
+                tx += fs * dx;
+                ty += fs * dy;
+                tz += fs * dz;
+                sx -= fs * dx;
+                sy -= fs * dy;
+                sz -= fs * dz;
+                if (E) {
+                    wv = valid ? wv : CA(0);
+                    te += wv;
+                    se += wv;
+                }
+            };
+            auto rotate = [&]() {
+                src = wave_rotate(src);
+                sx = wave_rotate(sx);
+                sy = wave_rotate(sy);
+                sz = wave_rotate(sz);
+                if (E)
+                    se = wave_rotate(se);
+            };
+            if (J != I) {
+                if (full) {
+                    for (int kk = 0; kk < 64; ++kk) {
+                        one(true);
+                        rotate();
+                    }
+                } else {
+                    int sidx = s0;  // travels with the source
+                    for (int kk = 0; kk < 64; ++kk) {
+                        one(tv && sidx < Z);
+                        rotate();
+                        sidx = (int)wave_rotate((uint32_t)sidx);
+                    }
+                }
+            } else {
+                int sidx = s0;
+                for (int kk = 1; kk <= 32; ++kk) {
+                    rotate();
+                    sidx = (int)wave_rotate((uint32_t)sidx);
+                    one(tv && sidx < Z && (kk < 32 || lane < 32));
+                }
+                // 32 rotations moved every source by 32 lanes (either way)
+                sx = __shfl(sx, (lane + 32) & 63);
+                sy = __shfl(sy, (lane + 32) & 63);
+                sz = __shfl(sz, (lane + 32) & 63);
+                if (E)
+                    se = __shfl(se, (lane + 32) & 63);
+            }
+            CA* a = acc + ((w * CP_SUPER + (J - CP_SUPER * Bs)) * 64 + lane) * 4;
+            a[0] += sx;
+            a[1] += sy;
+            a[2] += sz;
+            a[3] += se;
+        }
+        const double fsc = P::coul_fscale(k), vsc = P::coul_vscale(k);
+        if (A != Bs) {
+            if (tv)
+                part[(int64_t)Bs * Z + t] = make_double4((double)tx * fsc, (double)ty * fsc,
+                                                         (double)tz * fsc, (double)te * vsc);
+        } else {
+            CA* a = acc + ((w * CP_SUPER + (I - CP_SUPER * A)) * 64 + lane) * 4;
+            a[0] += tx;
+            a[1] += ty;
+            a[2] += tz;
+            a[3] += te;
+        }
+    }
+    __syncthreads();
+    // the source side (and, for A == B, everything) of block b of B, summed
+    // over the wavefronts in fixed order
+    {
+        const int b = tid >> 6;
+        const int p = (CP_SUPER * Bs + b) * 64 + lane;
+        if (p < Z) {
+            double fx = 0, fy = 0, fz = 0, e = 0;
+            for (int v = 0; v < CP_SUPER; ++v) {
+                const CA* a = acc + ((v * CP_SUPER + b) * 64 + lane) * 4;
+                fx += (double)a[0];
+                fy += (double)a[1];
+                fz += (double)a[2];
+                e += (double)a[3];
+            }
+            const double fsc = P::coul_fscale(k), vsc = P::coul_vscale(k);
+            part[(int64_t)A * Z + p] = make_double4(fx * fsc, fy * fsc, fz * fsc, e * vsc);
+        }
+    }
+    __syncthreads();
 }
 
 // ============================================================ nuclear ==

@@ -93,11 +93,11 @@ def test_argument_errors(B):
     K = ctypes.c_int32()
     assert B.lib.pasta_cluster(10, 8.0, fake, fake, 4.5, 3.0, fake, fake, fake,
                                ctypes.byref(K), None, fake, 1 << 30, None) == -2
-    # tuning: unknown variant, non-positive halo, reserved field set
+    # tuning: unknown variant, non-positive halo, unknown Coulomb form
     t = B.pasta_tuning()
     assert B.lib.pasta_get_tuning(ctypes.byref(t)) == 0
     for field, value in (("nuclear_variant", 4), ("list_skin", 0.0), ("list_skin", -1.0),
-                         ("list_pool_scale", 0.0), ("reserved", 1), ("fused_forces", 2)):
+                         ("list_pool_scale", 0.0), ("coulomb_form", 2), ("fused_forces", 2)):
         bad_t = B.pasta_tuning()
         ctypes.pointer(bad_t)[0] = t
         setattr(bad_t, field, value)

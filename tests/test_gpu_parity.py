@@ -102,14 +102,21 @@ def test_forces_terms(env, prec, terms):
 
 
 @pytest.mark.parametrize("prec", [0, 1])
-@pytest.mark.parametrize("name", ["n51200_yp020_n0.080", "n409600_yp040_n0.080"])
-def test_forces_full_size_sampled(env, name, prec):
+@pytest.mark.parametrize("name,cf", [("n51200_yp020_n0.080", 0), ("n51200_yp020_n0.080", 1),
+                                     ("n409600_yp040_n0.080", 0), ("n409600_yp040_n0.080", 1)])
+def test_forces_full_size_sampled(env, name, cf, prec):
     """Full-size workloads: every force on the GPU, the oracle on a seeded
-    sample of targets (each an exact O(N) sum)."""
-    say("forces sampled", name, "prec", prec)
+    sample of targets (each an exact O(N) sum); both Coulomb forms (the
+    pairwise form falls back to the gather form where its partials do not
+    fit, as at N = 409 600)."""
+    say("forces sampled", name, "prec", prec, "coulomb form", cf)
     st = env["I"].workload(name)
     pos, sp = to_dev(env, st)
-    f, e = env["B"].pasta_forces(pos, sp, st["L"], precision=prec)
+    old = env["B"].pasta_set_tuning(coulomb_form=cf)
+    try:
+        f, e = env["B"].pasta_forces(pos, sp, st["L"], precision=prec)
+    finally:
+        env["B"].pasta_set_tuning(**old)
     rng = np.random.Generator(np.random.PCG64(99))
     N = st["n"]
     tg = np.concatenate([rng.choice(st["Z"], 150, replace=False),
@@ -135,8 +142,9 @@ def test_nuclear_variants_agree(env, prec):
     try:
         for fused in (0, 1):
             for v in (0, 1, 3):
-                B.pasta_set_tuning(nuclear_variant=v, fused_forces=fused)
-                out.append(B.pasta_forces(pos, sp, st["L"], precision=prec))
+                for cf in (0, 1):
+                    B.pasta_set_tuning(nuclear_variant=v, fused_forces=fused, coulomb_form=cf)
+                    out.append(B.pasta_forces(pos, sp, st["L"], precision=prec))
     finally:
         B.pasta_set_tuning(**old)
     of, oe = env["O"].forces(st["pos"], st["species"], st["L"])
@@ -149,14 +157,16 @@ def test_nuclear_variants_agree(env, prec):
         assert d <= (1e-14 if prec == 0 else 1e-6)
 
 
+@pytest.mark.parametrize("cf", [0, 1])
 @pytest.mark.parametrize("variant", [1, 3])
 @pytest.mark.parametrize("fused", [0, 1])
-def test_trajectory_both_forms(env, fused, variant):
+def test_trajectory_both_forms(env, fused, variant, cf):
     """The unfused (kick in the nuclear epilogue) and fused (combine kernel)
-    step forms both follow the oracle, with 4 or 8 lanes per target."""
+    step forms both follow the oracle, with 4 or 8 lanes per target and
+    either Coulomb form."""
     B = env["B"]
     st = env["I"].make_state(2500, 0.3, 0.05, 1.0, seed=71)
-    old = B.pasta_set_tuning(fused_forces=fused, nuclear_variant=variant)
+    old = B.pasta_set_tuning(fused_forces=fused, nuclear_variant=variant, coulomb_form=cf)
     try:
         sim, pos, vel = make_sim(env, st, dt=2.0, T=1.0, rescale_every=4, precision=0)
         sim.step(9)
@@ -166,6 +176,31 @@ def test_trajectory_both_forms(env, fused, variant):
                                   T=1.0, rescale_every=4)
     assert np.abs(wrapped_diff(pos.cpu().numpy(), op, oL)).max() <= 1e-9
     assert np.abs(vel.cpu().numpy() - ov).max() <= 1e-9
+
+
+@pytest.mark.parametrize("prec", [0, 1])
+@pytest.mark.parametrize("case", [
+    (3200, 0.40, 0.040, 1000), (1000, 0.30, 0.060, 5), (4097, 0.20, 0.080, 6),
+    (6000, 1.00, 0.050, 8), (130, 0.5, 0.008, 12), (700, 0.0915, 0.03, 13)])
+@pytest.mark.parametrize("fused", [0, 1])
+def test_coulomb_pairwise_form(env, case, prec, fused):
+    """The pairwise Coulomb form (each unordered pair once, reactions carried
+    by a lane rotation) against the oracle: full and ragged proton blocks
+    (Z = 1280, 300, 819, 6000, 65, 64), alone and with the nuclear terms."""
+    B = env["B"]
+    N, yp, dens, seed = case
+    st = env["I"].make_state(N, yp, dens, 1.0, seed=seed)
+    pos, sp = to_dev(env, st)
+    old = B.pasta_set_tuning(coulomb_form=1, fused_forces=fused)
+    try:
+        for terms in (2, 3):
+            f, e = B.pasta_forces(pos, sp, st["L"], precision=prec, terms=terms)
+            of, oe = env["O"].forces(st["pos"], st["species"], st["L"], terms=terms)
+            ef, ee = rel(f.cpu().numpy(), of), rel(e.cpu().numpy(), oe)
+            say(f"  Z {st['Z']} terms {terms}: force {ef:.2e} energy {ee:.2e}")
+            assert ef <= TOL_F[prec] and ee <= TOL_E[prec]
+    finally:
+        B.pasta_set_tuning(**old)
 
 
 def test_coulomb_split_override(env):
