@@ -17,7 +17,13 @@ ARCH = "gfx950"
 
 SOURCES = ["api.hip", "cells.hip", "forces.hip", "integrate.hip", "cluster.hip", "batch.hip"]
 # Per-file extra flags: the cluster distances must not be contracted into FMA.
-EXTRA = {"cluster.hip": ["-ffp-contract=off"]}
+# cluster.hip: distances without FMA contraction (the same bits as the
+# definition the labels are checked against).  forces.hip: the wave-wide DPP
+# rotations of the pairwise Coulomb form stay plain v_mov_b32_dpp moves; the
+# DPP combiner would fold them into VOP2 arithmetic, where the wave-rotate
+# control did not give the rotated operand on gfx950.
+EXTRA = {"cluster.hip": ["-ffp-contract=off"],
+         "forces.hip": ["-mllvm", "-amdgpu-dpp-combine=false"]}
 
 COMMON = [
     "--offload-arch=" + ARCH, "-O3", "-fPIC", "-std=c++17",
