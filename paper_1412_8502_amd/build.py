@@ -18,10 +18,10 @@ ARCH = "gfx950"
 SOURCES = ["api.hip", "cells.hip", "forces.hip", "integrate.hip", "cluster.hip", "batch.hip"]
 # Per-file extra flags: the cluster distances must not be contracted into FMA.
 # cluster.hip: distances without FMA contraction (the same bits as the
-# definition the labels are checked against).  forces.hip: the wave-wide DPP
-# rotations of the pairwise Coulomb form stay plain v_mov_b32_dpp moves; the
-# DPP combiner would fold them into VOP2 arithmetic, where the wave-rotate
-# control did not give the rotated operand on gfx950.
+# definition the labels are checked against).  forces.hip: the DPP lane
+# rotations of the pairwise Coulomb form stay plain v_mov_b32_dpp moves.  The
+# DPP combiner folds such moves into VOP2 arithmetic; with a wave-rotate
+# control that gave wrong operands on gfx950, so it stays off for this file.
 EXTRA = {"cluster.hip": ["-ffp-contract=off"],
          "forces.hip": ["-mllvm", "-amdgpu-dpp-combine=false"]}
 

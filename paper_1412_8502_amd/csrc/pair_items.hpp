@@ -359,14 +359,19 @@ __device__ void coulomb_item(const typename P::Src* __restrict__ stg, int Z, int
 // a wavefront, and super-blocks of CP_SUPER blocks.  A work item is a
 // super-block pair (A, B), A <= B, and one workgroup: wavefront w owns the
 // target block I = CP_SUPER A + w and visits every source block J of B
-// (J >= I when A == B).  For an off-diagonal block pair each lane evaluates
-// 64 pairs: (its target, the source it holds), adding the force to its
-// target and the reaction to the source's accumulator; then the source
-// coordinates and accumulators move one lane along the wavefront (a
-// wave-wide rotate), so after 64 steps every source has met every target
-// and its accumulator is back at its own lane.  A diagonal block (J = I)
-// needs the rotations 1..32 only, the 32nd on half of the lanes (lanes l
-// and l + 32 then hold the same pair), and a final move by 32 lanes.
+// (J >= I when A == B).  Each lane holds its target and one source; it
+// evaluates the pair, adds the force to its target and the reaction to the
+// source's accumulator, then the sources and their accumulators move: one
+// column along the lane's row of 16 (a row rotation), and after every 16
+// rotations one row down (a 16-lane shift), so an off-diagonal block pair
+// takes 4 x 16 steps and leaves every source accumulator at its own lane.
+// Write a held source's offset from its lane as (row, column) offsets
+// (rho, c).  For a diagonal block (J = I) each unordered pair appears at
+// two opposite offsets, so one of each is visited: (0, 1..8), (1, all 16),
+// (2, 8..15 and 0), where the self-opposite offsets (0, 8), (2, 8) and
+// (2, 0) are evaluated by half of the lanes; the accumulators then sit two
+// rows away from home and move back with one 32-lane shift.  The schedule
+// does not depend on which way the hardware rotates.
 // Partials: proton p of super-block X receives from item (A, B) the sum of
 // its contributions as part[Y][p], Y the other super-block of the item
 // (Y = X when A == B), i.e. exactly one partial per super-block, which the
@@ -381,35 +386,47 @@ __host__ __device__ inline int64_t coulomb_pair_items(int64_t Z)
     return S * (S + 1) / 2;
 }
 
-__device__ __forceinline__ uint32_t wave_rotate(uint32_t v)
+// Row rotation: DPP row_ror:1 (each row of 16 lanes rotates by one; every
+// lane has a source lane, so no old value is needed).
+__device__ __forceinline__ uint32_t row_rotate(uint32_t v)
 {
-    // DPP wave_rol:1 -- one lane along the whole wavefront (a rotation: every
-    // lane has a source lane, so no old value is needed)
-    return (uint32_t)__builtin_amdgcn_mov_dpp((int)v, 0x134, 0xF, 0xF, true);
+    return (uint32_t)__builtin_amdgcn_mov_dpp((int)v, 0x121, 0xF, 0xF, true);
 }
-__device__ __forceinline__ float wave_rotate(float v)
+__device__ __forceinline__ float row_rotate(float v)
 {
-    return __builtin_bit_cast(float, wave_rotate(__builtin_bit_cast(uint32_t, v)));
+    return __builtin_bit_cast(float, row_rotate(__builtin_bit_cast(uint32_t, v)));
 }
-__device__ __forceinline__ double wave_rotate(double v)
+__device__ __forceinline__ double row_rotate(double v)
 {
     uint2 u = __builtin_bit_cast(uint2, v);
-    u.x = wave_rotate(u.x);
-    u.y = wave_rotate(u.y);
+    u.x = row_rotate(u.x);
+    u.y = row_rotate(u.y);
     return __builtin_bit_cast(double, u);
 }
-__device__ __forceinline__ Q4 wave_rotate(const Q4& s)
+// Row shift: lane l takes the value of lane l + 16 (mod 64).
+__device__ __forceinline__ uint32_t row_shift(uint32_t v)
+{
+    return (uint32_t)__shfl((int)v, (__lane_id() + 16) & 63);
+}
+__device__ __forceinline__ float row_shift(float v) { return __shfl(v, (__lane_id() + 16) & 63); }
+__device__ __forceinline__ double row_shift(double v)
+{
+    return __shfl(v, (__lane_id() + 16) & 63);
+}
+template <class T>
+__device__ __forceinline__ Q4 move_src(const Q4& s, T op)
 {
     Q4 r;
-    r.x = wave_rotate(s.x);
-    r.y = wave_rotate(s.y);
-    r.z = wave_rotate(s.z);
+    r.x = op(s.x);
+    r.y = op(s.y);
+    r.z = op(s.z);
     r.w = s.w;
     return r;
 }
-__device__ __forceinline__ double4 wave_rotate(const double4& s)
+template <class T>
+__device__ __forceinline__ double4 move_src(const double4& s, T op)
 {
-    return make_double4(wave_rotate(s.x), wave_rotate(s.y), wave_rotate(s.z), s.w);
+    return make_double4(op(s.x), op(s.y), op(s.z), s.w);
 }
 
 template <class P>
@@ -446,9 +463,11 @@ __device__ void coulomb_pair_item(const typename P::Src* __restrict__ stg, int Z
         CA tx = 0, ty = 0, tz = 0, te = 0;
         const int J0 = A == Bs ? I : CP_SUPER * Bs;
         const int J1 = min(CP_SUPER * Bs + CP_SUPER, nb);
+        const bool low_col = (lane & 15) < 8, low_row = lane < 32;
         for (int J = J0; J < J1; ++J) {
             const int s0 = J * 64 + lane;
             Src src = stg[s0 < Z ? s0 : Z - 1];
+            int sidx = s0;  // travels with the source (validity of partial blocks)
             CA sx = 0, sy = 0, sz = 0, se = 0;
             const bool full = I * 64 + 64 <= Z && J * 64 + 64 <= Z;  // wave-uniform
             auto one = [&](bool valid) {
@@ -467,36 +486,66 @@ __device__ void coulomb_pair_item(const typename P::Src* __restrict__ stg, int Z
                     se += wv;
                 }
             };
-            auto rotate = [&]() {
-                src = wave_rotate(src);
-                sx = wave_rotate(sx);
-                sy = wave_rotate(sy);
-                sz = wave_rotate(sz);
+            auto rot = [&]() {
+                src = move_src(src, [](auto v) { return row_rotate(v); });
+                sx = row_rotate(sx);
+                sy = row_rotate(sy);
+                sz = row_rotate(sz);
                 if (E)
-                    se = wave_rotate(se);
+                    se = row_rotate(se);
+                if (!full)
+                    sidx = (int)row_rotate((uint32_t)sidx);
             };
+            auto down = [&]() {
+                src = move_src(src, [](auto v) { return row_shift(v); });
+                sx = row_shift(sx);
+                sy = row_shift(sy);
+                sz = row_shift(sz);
+                if (E)
+                    se = row_shift(se);
+                if (!full)
+                    sidx = (int)row_shift((uint32_t)sidx);
+            };
+            auto ok = [&](bool half_ok) { return full ? half_ok : (tv && sidx < Z && half_ok); };
             if (J != I) {
-                if (full) {
-                    for (int kk = 0; kk < 64; ++kk) {
-                        one(true);
-                        rotate();
+                for (int rho = 0; rho < 4; ++rho) {
+                    if (full) {
+                        for (int c = 0; c < 16; ++c) {
+                            one(true);
+                            rot();
+                        }
+                    } else {
+                        for (int c = 0; c < 16; ++c) {
+                            one(tv && sidx < Z);
+                            rot();
+                        }
                     }
-                } else {
-                    int sidx = s0;  // travels with the source
-                    for (int kk = 0; kk < 64; ++kk) {
-                        one(tv && sidx < Z);
-                        rotate();
-                        sidx = (int)wave_rotate((uint32_t)sidx);
-                    }
+                    down();
                 }
             } else {
-                int sidx = s0;
-                for (int kk = 1; kk <= 32; ++kk) {
-                    rotate();
-                    sidx = (int)wave_rotate((uint32_t)sidx);
-                    one(tv && sidx < Z && (kk < 32 || lane < 32));
+                // (0, 1..8)
+                for (int c = 1; c <= 8; ++c) {
+                    rot();
+                    one(ok(c < 8 || low_col));
                 }
-                // 32 rotations moved every source by 32 lanes (either way)
+                // (1, 8..15, 0..7)
+                down();
+                one(ok(true));
+                for (int c = 1; c < 16; ++c) {
+                    rot();
+                    one(ok(true));
+                }
+                // (2, 8), (2, 9..15), (2, 0)
+                rot();
+                down();
+                one(ok(low_col));
+                for (int c = 1; c < 8; ++c) {
+                    rot();
+                    one(ok(true));
+                }
+                rot();
+                one(ok(low_row));
+                // two rows from home: one 32-lane shift brings them back
                 sx = __shfl(sx, (lane + 32) & 63);
                 sy = __shfl(sy, (lane + 32) & 63);
                 sz = __shfl(sz, (lane + 32) & 63);
