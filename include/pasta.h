@@ -209,9 +209,12 @@ int pasta_forces(const pasta_potential* pot, int32_t precision, int32_t terms, i
  *   F_{n+1} = F(x, L_{n+1});  v += (dt/2M) F_{n+1};
  *   if rescale_every > 0 and (n+1) % rescale_every == 0:
  *       v *= sqrt(1.5 N T / KE),  KE = sum (1/2) M v^2.
- * The simulation works in place on the caller's d_pos and d_vel, which
- * always hold the state at the current step (caller order).  d_species
- * must stay valid and unchanged.  L_max bounds the largest box the run will
+ * The simulation keeps its own copy of the state, in the sorted order of
+ * its cell list.  It reads the caller's d_pos and d_vel (caller order) in
+ * pasta_sim_create and pasta_sim_set_state, and writes the current state
+ * back into them at the end of every pasta_sim_step call (in stream order);
+ * changing them in between has no effect on the run.  d_species must stay
+ * valid and unchanged.  L_max bounds the largest box the run will
  * reach (it sizes the cell grid); a step that would exceed it fails with
  * PASTA_EBOX.  L_start (workspace query) is the box side at the starting
  * step: with the list form it sets the density the list memory is sized for

@@ -236,8 +236,10 @@ def pasta_forces(pos, species, L: float, precision: int = PASTA_FP64,
 
 # ------------------------------------------------------------------- a4
 class Sim:
-    """Owner of a pasta_sim handle and of its workspace tensor.  The state
-    lives in the caller's `pos` and `vel` tensors, advanced in place."""
+    """Owner of a pasta_sim handle and of its workspace tensor.  The library
+    keeps the state in sorted order; `pos` and `vel` receive the current
+    state after every `step` call (stream order) and are read again only by
+    `set_state`."""
 
     def __init__(self, pos, vel, species, L0: float, dt: float = 2.0, xi_dot: float = 0.0,
                  T: float = 1.0, rescale_every: int = 0, scale_positions: bool = False,

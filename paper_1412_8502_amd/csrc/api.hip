@@ -242,14 +242,15 @@ static int read_err(uint32_t* d_err, hipStream_t s, const char* who)
 
 // Build the cell list (+ staging) for positions at box side L (grid g); in
 // the list form also the lists (a forced build: positions recorded in xb).
+// mv (optional): also move the particle state into sorted order.
 static int build_cells(const double* pos, const uint8_t* species, int64_t n, const Grid& g,
                        ForceWork& w, int precision, const PairParams& pp, hipStream_t s,
-                       Timer* t)
+                       Timer* t, const StateMove* mv = nullptr)
 {
     launch_bin_count(pos, species, n, g, w.cb, w.err, s, t);
     launch_scan(w.cb, g, w.chunk, s, t);
     launch_scatter_rank(pos, species, n, g, w.cb, w.fb.stg64, w.fb.stgq, s, t, false, nullptr,
-                        w.lists ? w.lb.xb : nullptr);
+                        w.lists ? w.lb.xb : nullptr, mv);
     if (w.lists) {
         launch_list_force_rebuild(w.lb, g, s);
         launch_list_build(precision, w.fb, w.cb, g, w.lb, pp, s, t);
@@ -427,7 +428,7 @@ extern "C" int pasta_forces(const pasta_potential* pot, int32_t precision, int32
     PASTA_HIP(hipMemcpyAsync(&Z, w.cb.start + (int64_t)g.C * g.sub, sizeof(int32_t),
                              hipMemcpyDeviceToHost, s));
     PASTA_HIP(hipStreamSynchronize(s));
-    KickArgs kick{nullptr, 0.0, pot->mass, nullptr};
+    KickArgs kick{nullptr, 0.0, pot->mass, nullptr, false};
     eval_forces(precision, terms, w, g, n, Z, pp, d_force, d_epot, kick, nullptr, s, nullptr);
     PASTA_HIP(hipGetLastError());
     return read_err(w.err, s, "pasta_forces");
@@ -526,7 +527,7 @@ extern "C" int pasta_autotune(const pasta_potential* pot, int32_t precision, int
     PASTA_HIP(hipEventCreate(&e1));
     double best = 1e300;
     int best_k = 0;
-    KickArgs kick{nullptr, 0.0, pot->mass, nullptr};
+    KickArgs kick{nullptr, 0.0, pot->mass, nullptr, true};  // sorted order, as in a simulation
     int rc = PASTA_OK;
     for (size_t c = 0; c < cands.size() && rc == PASTA_OK; ++c) {
         g_tuning = cands[c];
@@ -592,15 +593,24 @@ struct pasta_sim {
     int64_t n, Z;
     double L0, L_max;
     int64_t step;
-    double* pos;
+    double* pos;  // caller's arrays (caller order): read on import, written on export
     double* vel;
     const uint8_t* species;
     hipStream_t stream;
     int C_max;
     double r_cell;  // cell width: r_nuc, or r_nuc + list halo
     ForceWork w;
-    double* force;
-    double* epot;
+    // The state lives in the sorted order of the last cell build, so every
+    // per-particle kernel of a step reads and writes contiguous memory.  Two
+    // copies: the rank kernel of a build moves the state from one into the
+    // other (cur names the live one).  ids[k] is the caller index of slot k.
+    double* xs[2];
+    double* vs[2];
+    int32_t* ids[2];
+    uint8_t* sps[2];
+    int cur;
+    double* force;  // [n][3] F of the current state, sorted order
+    double* epot;   // [n] energy shares, sorted order
     bool epot_valid;  // steps compute forces only; energies are evaluated on demand
     Timer timer;
 };
@@ -611,18 +621,48 @@ static double box_side(const pasta_sim* sim, int64_t step)
     return sim->L0 * (1.0 + sim->integ.xi_dot * ((double)step * sim->integ.dt));
 }
 
-static size_t sim_carve(Carver& cv, ForceWork* w, double** force, double** epot, int64_t n,
-                        int C_max, int precision, const pasta_potential* pot, const ListCfg& lc,
-                        int64_t pool_rows = -1)
+static size_t sim_carve(Carver& cv, pasta_sim* sim, int64_t n, int C_max, int precision,
+                        const pasta_potential* pot, const ListCfg& lc, int64_t pool_rows = -1)
 {
-    force_carve(cv, w, n, C_max, precision, pot, lc, pool_rows);
+    force_carve(cv, sim ? &sim->w : nullptr, n, C_max, precision, pot, lc, pool_rows);
     double* f = cv.take<double>(3 * (size_t)n);
     double* e = cv.take<double>((size_t)n);
-    if (force)
-        *force = f;
-    if (epot)
-        *epot = e;
+    double* xs[2];
+    double* vs[2];
+    int32_t* ids[2];
+    uint8_t* sps[2];
+    for (int b = 0; b < 2; ++b) {
+        xs[b] = cv.take<double>(3 * (size_t)n);
+        vs[b] = cv.take<double>(3 * (size_t)n);
+        ids[b] = cv.take<int32_t>((size_t)n);
+        sps[b] = cv.take<uint8_t>((size_t)n);
+    }
+    if (sim) {
+        sim->force = f;
+        sim->epot = e;
+        for (int b = 0; b < 2; ++b) {
+            sim->xs[b] = xs[b];
+            sim->vs[b] = vs[b];
+            sim->ids[b] = ids[b];
+            sim->sps[b] = sps[b];
+        }
+    }
     return cv.size();
+}
+
+// The spare copy of the sorted state as the destination of a state move
+// from the live one.
+static StateMove sim_move(const pasta_sim* sim)
+{
+    const int a = sim->cur, b = 1 - sim->cur;
+    return StateMove{sim->vs[a], sim->ids[a], sim->xs[b], sim->vs[b], sim->ids[b], sim->sps[b]};
+}
+
+// Writes the live sorted state to the caller's arrays (caller order).
+static void sim_export(pasta_sim* sim)
+{
+    launch_export(sim->ids[sim->cur], sim->n, sim->xs[sim->cur], sim->pos, sim->vs[sim->cur],
+                  sim->vel, nullptr, nullptr, sim->stream);
 }
 
 static int check_integ(const pasta_integrator* g)
@@ -647,23 +687,27 @@ extern "C" int pasta_sim_workspace(const pasta_potential* pot, const pasta_integ
     const ListCfg lc = list_cfg(PASTA_TERM_ALL, L_start);
     const Grid g = make_grid(L_max > L_start ? L_max : L_start, cell_cut(pot, lc), CELL_SUB);
     Carver cv(nullptr);
-    *h_bytes = sim_carve(cv, nullptr, nullptr, nullptr, n, g.C, precision, pot, lc);
+    *h_bytes = sim_carve(cv, nullptr, n, g.C, precision, pot, lc);
     return PASTA_OK;
 }
 
+// Imports the caller's state: the cell build sorts it into the live copy.
 static int sim_eval_initial(pasta_sim* sim)
 {
     hipStream_t s = sim->stream;
     const double L = box_side(sim, sim->step);
     const Grid g = make_grid(L, sim->r_cell, CELL_SUB);
     const PairParams pp = pair_params(&sim->pot, L);
-    build_cells(sim->pos, sim->species, sim->n, g, sim->w, sim->precision, pp, s, &sim->timer);
+    sim->cur = 0;
+    const StateMove mv{sim->vel, nullptr, sim->xs[0], sim->vs[0], sim->ids[0], sim->sps[0]};
+    build_cells(sim->pos, sim->species, sim->n, g, sim->w, sim->precision, pp, s, &sim->timer,
+                &mv);
     int32_t Z = 0;
     PASTA_HIP(hipMemcpyAsync(&Z, sim->w.cb.start + (int64_t)g.C * g.sub, sizeof(int32_t),
                              hipMemcpyDeviceToHost, s));
     PASTA_HIP(hipStreamSynchronize(s));
     sim->Z = Z;
-    KickArgs kick{nullptr, 0.0, sim->pot.mass, nullptr};
+    KickArgs kick{nullptr, 0.0, sim->pot.mass, nullptr, true};
     eval_forces(sim->precision, PASTA_TERM_ALL, sim->w, g, sim->n, sim->Z, pp, sim->force,
                 sim->epot, kick, nullptr, s, &sim->timer);
     sim->epot_valid = true;
@@ -680,7 +724,7 @@ static int sim_refresh_energies(pasta_sim* sim)
         return PASTA_OK;
     const double L = box_side(sim, sim->step);
     const Grid g = make_grid(L, sim->r_cell, CELL_SUB);
-    KickArgs kick{nullptr, 0.0, sim->pot.mass, nullptr};
+    KickArgs kick{nullptr, 0.0, sim->pot.mass, nullptr, true};
     eval_forces(sim->precision, PASTA_TERM_ALL, sim->w, g, sim->n, sim->Z,
                 pair_params(&sim->pot, L), sim->force, sim->epot, kick, nullptr, sim->stream,
                 nullptr);
@@ -728,8 +772,7 @@ extern "C" int pasta_sim_create(const pasta_potential* pot, const pasta_integrat
     sim->r_cell = cell_cut(pot, lc);
     sim->C_max = make_grid(sim->L_max, sim->r_cell, CELL_SUB).C;
     Carver cv0(nullptr);
-    const size_t need =
-        sim_carve(cv0, nullptr, nullptr, nullptr, n, sim->C_max, precision, pot, lc, 1);
+    const size_t need = sim_carve(cv0, nullptr, n, sim->C_max, precision, pot, lc, 1);
     int rc = check_work(d_work, work_bytes, need, "pasta_sim_create");
     if (rc != PASTA_OK) {
         delete sim;
@@ -740,14 +783,14 @@ extern "C" int pasta_sim_create(const pasta_potential* pot, const pasta_integrat
         rows = 1 + (int64_t)((work_bytes - need) / LIST_ROW_BYTES);
         for (;;) {
             Carver cvr(nullptr);
-            if (sim_carve(cvr, nullptr, nullptr, nullptr, n, sim->C_max, precision, pot, lc,
-                          rows) <= work_bytes || rows == 1)
+            if (sim_carve(cvr, nullptr, n, sim->C_max, precision, pot, lc, rows) <= work_bytes ||
+                rows == 1)
                 break;
             --rows;
         }
     }
     Carver cv(d_work);
-    sim_carve(cv, &sim->w, &sim->force, &sim->epot, n, sim->C_max, precision, pot, lc, rows);
+    sim_carve(cv, sim, n, sim->C_max, precision, pot, lc, rows);
     for (int k = 0; k < PASTA_KERNEL_CLASSES; ++k)
         sim->timer.open[k] = -1;
     hipStream_t s = sim->stream;
@@ -783,11 +826,12 @@ extern "C" int pasta_sim_step(pasta_sim* sim, int64_t nsteps)
             return fail(PASTA_EBOX, "pasta_sim_step: box side %g at step %lld is outside "
                         "[2 r_nuc, L_max = %g]", L_new, (long long)(n0 + 1), sim->L_max);
         const Grid g = make_grid(L_new, sim->r_cell, CELL_SUB);
+        const int c = sim->cur;
         DriftArgs da;
-        da.pos = sim->pos;
-        da.vel = sim->vel;
+        da.pos = sim->xs[c];
+        da.vel = sim->vs[c];
         da.force = sim->force;
-        da.species = sim->species;
+        da.species = sim->sps[c];
         da.n = sim->n;
         da.hdtm = hdtm;
         da.dt = gi.dt;
@@ -798,33 +842,43 @@ extern "C" int pasta_sim_step(pasta_sim* sim, int64_t nsteps)
         if (sim->w.lists) {
             // drift + staging + rebuild decision, then the build kernels,
             // each of which returns at once unless this step rebuilds
+            // (a rebuild sorts the state into the spare copy and copies it
+            // back, so the live copy stays the same on the host side)
             const ListBuf& lb = sim->w.lb;
             const int32_t* gate = &lb.ctl->rebuild;
+            const StateMove mv = sim_move(sim);
             launch_drift_list(da, g, sim->w.cb, lb, sim->w.fb.stg64, sim->w.fb.stgq, n0,
                               sim->w.err, s, &sim->timer);
-            launch_bin_count(sim->pos, sim->species, sim->n, g, sim->w.cb, sim->w.err, s,
+            launch_bin_count(sim->xs[c], sim->sps[c], sim->n, g, sim->w.cb, sim->w.err, s,
                              &sim->timer, gate);
             launch_scan(sim->w.cb, g, sim->w.chunk, s, &sim->timer, gate);
-            launch_scatter_rank(sim->pos, sim->species, sim->n, g, sim->w.cb, sim->w.fb.stg64,
-                                sim->w.fb.stgq, s, &sim->timer, true, gate, lb.xb);
+            launch_scatter_rank(sim->xs[c], sim->sps[c], sim->n, g, sim->w.cb, sim->w.fb.stg64,
+                                sim->w.fb.stgq, s, &sim->timer, false, gate, lb.xb, &mv);
+            launch_state_copy(mv, sim->xs[c], sim->vs[c], sim->ids[c], sim->sps[c], sim->n, gate,
+                              s);
             launch_list_build(sim->precision, sim->w.fb, sim->w.cb, g, lb, pp, s, &sim->timer);
         } else {
+            const StateMove mv = sim_move(sim);
             launch_drift(da, g, sim->w.cb, sim->w.err, s, &sim->timer);
             launch_scan(sim->w.cb, g, sim->w.chunk, s, &sim->timer);
-            launch_scatter_rank(sim->pos, sim->species, sim->n, g, sim->w.cb, sim->w.fb.stg64,
-                                sim->w.fb.stgq, s, &sim->timer, true);
+            launch_scatter_rank(sim->xs[c], sim->sps[c], sim->n, g, sim->w.cb, sim->w.fb.stg64,
+                                sim->w.fb.stgq, s, &sim->timer, false, nullptr, nullptr, &mv);
+            sim->cur = 1 - c;
         }
         const bool thermo = gi.rescale_every > 0 && (n0 + 1) % gi.rescale_every == 0;
-        KickArgs kick{sim->vel, hdtm, sim->pot.mass, thermo ? sim->w.fb.ke_part : nullptr};
+        double* v = sim->vs[sim->cur];
+        KickArgs kick{v, hdtm, sim->pot.mass, thermo ? sim->w.fb.ke_part : nullptr, true};
         eval_forces(sim->precision, PASTA_TERM_ALL, sim->w, g, sim->n, sim->Z, pp, sim->force,
                     nullptr, kick, nullptr, s, &sim->timer);
         sim->epot_valid = false;
         if (thermo)
-            launch_thermostat(sim->vel, sim->n, sim->w.fb.ke_part,
+            launch_thermostat(v, sim->n, sim->w.fb.ke_part,
                               g_tuning.fused_forces ? sim->w.fb.n_ke : sim->w.cb.n_items,
                               1.5 * (double)sim->n * gi.T, sim->w.scale, s, &sim->timer);
         sim->step = n0 + 1;
     }
+    if (nsteps > 0)
+        sim_export(sim);
     PASTA_HIP(hipGetLastError());
     return PASTA_OK;
 }
@@ -868,12 +922,9 @@ extern "C" int pasta_sim_forces(pasta_sim* sim, double* d_force, double* d_epot)
         return fail(PASTA_EINVAL, "pasta_sim_forces: null sim");
     if (d_epot)
         PASTA_TRY(sim_refresh_energies(sim));
-    if (d_force)
-        PASTA_HIP(hipMemcpyAsync(d_force, sim->force, sizeof(double) * 3 * sim->n,
-                                 hipMemcpyDeviceToDevice, sim->stream));
-    if (d_epot)
-        PASTA_HIP(hipMemcpyAsync(d_epot, sim->epot, sizeof(double) * sim->n,
-                                 hipMemcpyDeviceToDevice, sim->stream));
+    launch_export(sim->ids[sim->cur], sim->n, sim->force, d_force, nullptr, nullptr, sim->epot,
+                  d_epot, sim->stream);
+    PASTA_HIP(hipGetLastError());
     return PASTA_OK;
 }
 
@@ -886,7 +937,7 @@ extern "C" int pasta_sim_pair_counts(pasta_sim* sim, int64_t* h_nuclear, int64_t
     const Grid g = make_grid(L, sim->r_cell, CELL_SUB);
     uint64_t* ctr = sim->w.fb.pairs;
     PASTA_HIP(hipMemsetAsync(ctr, 0, 2 * sizeof(uint64_t), s));
-    KickArgs kick{nullptr, 0.0, sim->pot.mass, nullptr};
+    KickArgs kick{nullptr, 0.0, sim->pot.mass, nullptr, true};
     // the cell list and staging of the current state are in place
     eval_forces(sim->precision, PASTA_TERM_ALL, sim->w, g, sim->n, sim->Z,
                 pair_params(&sim->pot, L), sim->force, sim->epot, kick, ctr, s, nullptr);

@@ -11,8 +11,13 @@
 //               (arrival order, not yet stable);
 //   rank        one thread per slot: the stable rank inside the bin is the
 //               number of bin members with a smaller particle index, so the
-//               final order is (bin, index) whatever order the atomics took;
-//               the same thread gathers the particle's staging coordinates.
+//               final order is (bin, particle index) whatever order the
+//               atomics took; the same thread gathers the particle's staging
+//               coordinates and, for a simulation, moves its state.
+// The source index is the particle's position in the arrays the build reads:
+// the caller's order for a standalone build (source index = particle index),
+// the previous sorted order for a simulation step (whose state is kept in
+// sorted order, with the particle index of every slot beside it).
 #include "internal.hpp"
 
 namespace pasta {
@@ -131,12 +136,16 @@ __global__ __launch_bounds__(SCAN_THREADS) void k_scan(int32_t* __restrict__ cou
 // order: the previous sorted order (perm of the last build) or null for the
 // caller's order.  Visiting particles in the previous cell order keeps the
 // lanes of a wave in one or two bins, so the cursor atomics aggregate.
+// ids (optional): particle index of each source; then tmp receives the
+// particle index and src the source index of each unsorted slot.
 __global__ __launch_bounds__(256) void k_scatter(const int32_t* __restrict__ key, int64_t n,
                                                  const int32_t* __restrict__ order,
                                                  const int32_t* __restrict__ start,
                                                  int32_t* __restrict__ fill,
                                                  int32_t* __restrict__ tmp,
-                                                 const int32_t* __restrict__ gate)
+                                                 const int32_t* __restrict__ gate,
+                                                 const int32_t* __restrict__ ids,
+                                                 int32_t* __restrict__ src)
 {
     int64_t s = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (s >= n || (gate && *gate == 0))
@@ -144,7 +153,12 @@ __global__ __launch_bounds__(256) void k_scatter(const int32_t* __restrict__ key
     const int32_t i = order ? order[s] : (int32_t)s;
     const int b = key[i];
     const int slot = start[b] + wave_aggregated_add(fill, b);
-    tmp[slot] = i;
+    if (ids) {
+        tmp[slot] = ids[i];
+        src[slot] = i;
+    } else {
+        tmp[slot] = i;
+    }
 }
 
 __global__ __launch_bounds__(256) void k_rank(const int32_t* __restrict__ key,
@@ -156,13 +170,15 @@ __global__ __launch_bounds__(256) void k_rank(const int32_t* __restrict__ key,
                                               double4* __restrict__ stg64,
                                               Q4* __restrict__ stgq, double qscale,
                                               const int32_t* __restrict__ gate,
-                                              double* __restrict__ xb)
+                                              double* __restrict__ xb,
+                                              const int32_t* __restrict__ srcix, StateMove mv)
 {
     int64_t s = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (s >= n || (gate && *gate == 0))
         return;
-    const int32_t id = tmp[s];
-    const int b = key[id];
+    const int32_t id = tmp[s];                  // particle index: the rank key
+    const int32_t src = srcix ? srcix[s] : id;  // where its data is
+    const int b = key[src];
     const int beg = start[b], end = start[b + 1];
     // rank = members of the bin with a smaller index; eight independent
     // loads per iteration keep the loop from being latency-bound
@@ -179,24 +195,78 @@ __global__ __launch_bounds__(256) void k_rank(const int32_t* __restrict__ key,
     for (; k < end; ++k)
         r += tmp[k] < id;
     const int dst = beg + r;
-    perm[dst] = id;
-    double x = pos[3 * (int64_t)id + 0], y = pos[3 * (int64_t)id + 1],
-           z = pos[3 * (int64_t)id + 2];
+    perm[dst] = src;
+    double x = pos[3 * (int64_t)src + 0], y = pos[3 * (int64_t)src + 1],
+           z = pos[3 * (int64_t)src + 2];
     if (xb) {
         xb[3 * (int64_t)dst + 0] = x;
         xb[3 * (int64_t)dst + 1] = y;
         xb[3 * (int64_t)dst + 2] = z;
     }
+    const uint8_t sp = species[src];
     if (stg64)
-        stg64[dst] = make_double4(x, y, z, (double)species[id]);
+        stg64[dst] = make_double4(x, y, z, (double)sp);
     if (stgq) {
         Q4 q;
         q.x = (uint32_t)(uint64_t)(x * qscale);
         q.y = (uint32_t)(uint64_t)(y * qscale);
         q.z = (uint32_t)(uint64_t)(z * qscale);
-        q.w = species[id];
+        q.w = sp;
         stgq[dst] = q;
     }
+    if (mv.pos_dst) {
+        const double* v = mv.vel_src + 3 * (int64_t)src;
+        const double vx = v[0], vy = v[1], vz = v[2];
+        mv.pos_dst[3 * (int64_t)dst + 0] = x;
+        mv.pos_dst[3 * (int64_t)dst + 1] = y;
+        mv.pos_dst[3 * (int64_t)dst + 2] = z;
+        mv.vel_dst[3 * (int64_t)dst + 0] = vx;
+        mv.vel_dst[3 * (int64_t)dst + 1] = vy;
+        mv.vel_dst[3 * (int64_t)dst + 2] = vz;
+        mv.id_dst[dst] = id;
+        mv.sp_dst[dst] = sp;
+    }
+}
+
+__global__ __launch_bounds__(256) void k_state_copy(StateMove m, double* __restrict__ pos,
+                                                    double* __restrict__ vel,
+                                                    int32_t* __restrict__ id,
+                                                    uint8_t* __restrict__ sp, int64_t n,
+                                                    const int32_t* __restrict__ gate)
+{
+    const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (k >= n || (gate && *gate == 0))
+        return;
+#pragma unroll
+    for (int d = 0; d < 3; ++d) {
+        pos[3 * k + d] = m.pos_dst[3 * k + d];
+        vel[3 * k + d] = m.vel_dst[3 * k + d];
+    }
+    id[k] = m.id_dst[k];
+    sp[k] = m.sp_dst[k];
+}
+
+__global__ __launch_bounds__(256) void k_export(const int32_t* __restrict__ id, int64_t n,
+                                                const double* __restrict__ src3a,
+                                                double* __restrict__ dst3a,
+                                                const double* __restrict__ src3b,
+                                                double* __restrict__ dst3b,
+                                                const double* __restrict__ src1,
+                                                double* __restrict__ dst1)
+{
+    const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (k >= n)
+        return;
+    const int64_t i = id[k];
+#pragma unroll
+    for (int d = 0; d < 3; ++d) {
+        if (dst3a)
+            dst3a[3 * i + d] = src3a[3 * k + d];
+        if (dst3b)
+            dst3b[3 * i + d] = src3b[3 * k + d];
+    }
+    if (dst1)
+        dst1[i] = src1[k];
 }
 
 __global__ void k_zero2(int32_t* a, int32_t* b, int64_t m)
@@ -222,6 +292,7 @@ size_t cellbuf_carve(Carver& cv, CellBuf* out, int64_t n, int C_max, int chunk, 
     cb.start = cv.take<int32_t>((size_t)nb + 1);
     cb.tmp = cv.take<int32_t>(n > nb ? n : nb);
     cb.perm = cv.take<int32_t>(n);
+    cb.src = cv.take<int32_t>(n);
     cb.item_max = chunk > 0 ? n / chunk + C_max + 1 : 1;
     cb.items = cv.take<int32_t>(2 * (size_t)cb.item_max);
     cb.n_items = cv.take<int32_t>(1);
@@ -260,19 +331,41 @@ void launch_scan(const CellBuf& cb, const Grid& g, int chunk, hipStream_t s, Tim
 
 void launch_scatter_rank(const double* pos, const uint8_t* species, int64_t n, const Grid& g,
                          const CellBuf& cb, double4* stg64, Q4* stgq, hipStream_t s, Timer* t,
-                         bool prev_order, const int32_t* gate, double* xb)
+                         bool prev_order, const int32_t* gate, double* xb,
+                         const StateMove* mv)
 {
     if (n <= 0)
         return;
+    const StateMove none{};
     timer_begin(t, KC_SCATTER, s);
+    // a state move ranks by particle index: the scatter records it (the
+    // source's id, or the source index itself when there are no ids)
+    const bool ids = mv && mv->id_src;
     k_scatter<<<blocks_for(n, 256), 256, 0, s>>>(cb.key, n, prev_order ? cb.perm : nullptr,
-                                                 cb.start, cb.fill, cb.tmp, gate);
+                                                 cb.start, cb.fill, cb.tmp, gate,
+                                                 ids ? mv->id_src : nullptr, cb.src);
     timer_end(t, KC_SCATTER, s);
     timer_begin(t, KC_RANK, s);
     k_rank<<<blocks_for(n, 256), 256, 0, s>>>(cb.key, cb.tmp, n, cb.start, cb.perm, pos,
                                               species, stg64, stgq, 4294967296.0 / g.L, gate,
-                                              xb);
+                                              xb, ids ? cb.src : nullptr, mv ? *mv : none);
     timer_end(t, KC_RANK, s);
+}
+
+void launch_state_copy(const StateMove& m, double* pos, double* vel, int32_t* id, uint8_t* sp,
+                       int64_t n, const int32_t* gate, hipStream_t s)
+{
+    if (n > 0)
+        k_state_copy<<<blocks_for(n, 256), 256, 0, s>>>(m, pos, vel, id, sp, n, gate);
+}
+
+void launch_export(const int32_t* id, int64_t n, const double* src3a, double* dst3a,
+                   const double* src3b, double* dst3b, const double* src1, double* dst1,
+                   hipStream_t s)
+{
+    if (n > 0)
+        k_export<<<blocks_for(n, 256), 256, 0, s>>>(id, n, src3a, dst3a, src3b, dst3b, src1,
+                                                    dst1);
 }
 
 }  // namespace pasta

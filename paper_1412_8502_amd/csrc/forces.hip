@@ -189,7 +189,7 @@ __global__ __launch_bounds__(WG) void k_combine(const double4* __restrict__ fnuc
                 V += cp.w;
             }
         }
-        const int64_t id = perm[sl];
+        const int64_t id = perm ? perm[sl] : sl;
         force[3 * id + 0] = Fx;
         force[3 * id + 1] = Fy;
         force[3 * id + 2] = Fz;
@@ -365,7 +365,7 @@ void launch_forces_fused(int precision, const ForceBuf& fb, const CellBuf& cb, c
     NucArgs a{};
     a.start = cb.start;
     a.items = cb.items;
-    a.perm = cb.perm;
+    a.perm = kick.slot_order ? nullptr : cb.perm;
     a.nc = g.nc;
     a.C = g.C;
     a.sub = g.sub;
@@ -413,8 +413,8 @@ void launch_forces_fused(int precision, const ForceBuf& fb, const CellBuf& cb, c
     timer_end(t, KC_NUCLEAR, s);
     timer_begin(t, KC_COMBINE, s);
     k_combine<<<(unsigned)((n + WG - 1) / WG), WG, 0, s>>>(
-        fb.fnuc, fb.coul_part, S, (int)Z, cb.perm, n, force, epot, kick.vel, kick.hdtm,
-        kick.mass, kick.ke_part, fb.n_ke, err);
+        fb.fnuc, fb.coul_part, S, (int)Z, kick.slot_order ? nullptr : cb.perm, n, force, epot,
+        kick.vel, kick.hdtm, kick.mass, kick.ke_part, fb.n_ke, err);
     timer_end(t, KC_COMBINE, s);
 }
 
@@ -488,7 +488,7 @@ void launch_nuclear(int precision, const ForceBuf& fb, const CellBuf& cb, const 
     NucArgs a{};
     a.start = cb.start;
     a.items = cb.items;
-    a.perm = cb.perm;
+    a.perm = kick.slot_order ? nullptr : cb.perm;
     a.nc = g.nc;
     a.C = g.C;
     a.sub = g.sub;

@@ -1,7 +1,7 @@
 // Velocity-Verlet integration in the expanding periodic box (Sec. II.A and
 // Eq. 3).  FP64 throughout.
 //
-// The drift kernel fuses, per particle (caller order): the first half kick
+// The drift kernel fuses, per particle (sorted slot): the first half kick
 // v += (dt/2M) F_n, the drift x += dt v, the optional affine scaling of the
 // variant, the wrap into [0, L_{n+1}), and the cell binning of the new
 // position with its integer atomic count (the first pass of the cell-list
@@ -16,10 +16,9 @@ namespace pasta {
 
 namespace {
 
-// Particles are visited in the order of the previous cell build (perm), so
-// the lanes of a wave mostly fall in one bin and the count atomics aggregate.
+// The state is in the sorted order of the previous cell build, so the lanes
+// of a wave mostly fall in one bin and the count atomics aggregate.
 __global__ __launch_bounds__(256) void k_drift(DriftArgs a, int nc, int C, int sub, double inv_w,
-                                               const int32_t* __restrict__ order,
                                                int32_t* __restrict__ key,
                                                int32_t* __restrict__ count,
                                                uint32_t* __restrict__ err)
@@ -27,7 +26,7 @@ __global__ __launch_bounds__(256) void k_drift(DriftArgs a, int nc, int C, int s
     const int64_t s = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (s >= a.n)
         return;
-    const int64_t i = order[s];
+    const int64_t i = s;
     const double L = a.L_new;
     double xn[3];
     uint32_t bad = 0;
@@ -66,7 +65,6 @@ __global__ __launch_bounds__(256) void k_drift(DriftArgs a, int nc, int C, int s
 // workgroups never wait.
 __global__ __launch_bounds__(256) void k_drift_list(DriftArgs a, ListCtl* __restrict__ ctl,
                                                     const double* __restrict__ xb,
-                                                    const int32_t* __restrict__ order,
                                                     double4* __restrict__ stg64,
                                                     Q4* __restrict__ stgq, double qscale,
                                                     int parity, double skin, int nc_new,
@@ -78,7 +76,7 @@ __global__ __launch_bounds__(256) void k_drift_list(DriftArgs a, ListCtl* __rest
     const double L = a.L_new;
     float d2 = 0.f;
     if (s < a.n) {
-        const int64_t i = order[s];
+        const int64_t i = s;
         uint32_t bad = 0;
         double xn[3];
 #pragma unroll
@@ -250,8 +248,8 @@ void launch_drift(const DriftArgs& a, const Grid& g, const CellBuf& cb, uint32_t
     if (a.n <= 0)
         return;
     timer_begin(t, KC_DRIFT, s);
-    k_drift<<<(unsigned)((a.n + 255) / 256), 256, 0, s>>>(a, g.nc, g.C, g.sub, g.inv_w, cb.perm,
-                                                          cb.key, cb.count, err);
+    k_drift<<<(unsigned)((a.n + 255) / 256), 256, 0, s>>>(a, g.nc, g.C, g.sub, g.inv_w, cb.key,
+                                                          cb.count, err);
     timer_end(t, KC_DRIFT, s);
 }
 
@@ -263,7 +261,7 @@ void launch_drift_list(const DriftArgs& a, const Grid& g, const CellBuf& cb, con
         return;
     timer_begin(t, KC_DRIFT, s);
     k_drift_list<<<(unsigned)((a.n + 255) / 256), 256, 0, s>>>(
-        a, lb.ctl, lb.xb, cb.perm, stg64, stgq, 4294967296.0 / a.L_new, (int)(step & 1),
+        a, lb.ctl, lb.xb, stg64, stgq, 4294967296.0 / a.L_new, (int)(step & 1),
         lb.skin, g.nc, g.C, err);
     timer_end(t, KC_DRIFT, s);
 }

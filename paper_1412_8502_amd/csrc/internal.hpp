@@ -260,12 +260,14 @@ size_t listbuf_carve(Carver& cv, ListBuf* out, int64_t n, int64_t item_max, int6
 
 // -------------------------------------------------------- cell-list build
 struct CellBuf {
-    int32_t* key;     // [n] bin of each particle (caller order)
+    int32_t* key;     // [n] bin of each particle (indexed like the build's positions)
     int32_t* count;   // [2 C_max sub] per-bin counts (zero between builds)
     int32_t* fill;    // [2 C_max sub] per-bin scatter cursors (zero between builds)
     int32_t* start;   // [2 C_max sub + 1]
-    int32_t* tmp;     // [n] unsorted slots
-    int32_t* perm;    // [n] slot -> particle index
+    int32_t* tmp;     // [n] unsorted slots: particle index
+    int32_t* src;     // [n] unsorted slots: source index (state moves)
+    int32_t* perm;    // [n] slot -> source index (the particle index unless the
+                      //     build moves a state kept in sorted order)
     int32_t* items;   // [2 * item_max] nuclear work items (cell, chunk)
     int32_t* n_items; // [1]
     int64_t item_max;
@@ -285,13 +287,38 @@ void launch_bin_count(const double* pos, const uint8_t* species, int64_t n, cons
 // chunk > 0, also writes the nuclear work list.
 void launch_scan(const CellBuf& cb, const Grid& g, int chunk, hipStream_t s, Timer* t,
                  const int32_t* gate = nullptr);
-// Stable scatter: slot order = (bin, particle index).  Writes perm and, when
-// staging pointers are given, the sorted staging coordinates.  prev_order:
-// visit particles in the order of the previous build (cb.perm must hold it).
+// Particle state carried into sorted order by the rank kernel (all or
+// nothing): destination slot d receives the position, velocity, species and
+// particle index of source index perm[d].  Sources are indexed like the pos
+// and species arrays of the build; id_src gives their particle indices (null:
+// the source index is the particle index).  The sorted order is (bin,
+// particle index) either way.
+struct StateMove {
+    const double* vel_src;  // [n][3]
+    const int32_t* id_src;  // [n] or null
+    double* pos_dst;        // [n][3]
+    double* vel_dst;        // [n][3]
+    int32_t* id_dst;        // [n]
+    uint8_t* sp_dst;        // [n]
+};
+// Stable scatter: slot order = (bin, particle index); the source index is
+// the position in pos/species.  Writes perm (slot -> source index) and, when
+// given, the sorted staging coordinates, the build positions xb and the
+// moved state.  prev_order: visit particles in the order of the previous
+// build (cb.perm must hold it).
 void launch_scatter_rank(const double* pos, const uint8_t* species, int64_t n, const Grid& g,
                          const CellBuf& cb, double4* stg64, Q4* stgq, hipStream_t s, Timer* t,
                          bool prev_order = false, const int32_t* gate = nullptr,
-                         double* xb = nullptr);
+                         double* xb = nullptr, const StateMove* mv = nullptr);
+// Gated copy of a moved state back into the primary arrays (list form: a
+// rebuild moves the state to the spare arrays, this brings it back).
+void launch_state_copy(const StateMove& from_spare, double* pos, double* vel, int32_t* id,
+                       uint8_t* sp, int64_t n, const int32_t* gate, hipStream_t s);
+// Caller-order copies of sorted-slot arrays: dst3[id[k]] = src3[k] (3
+// doubles) and dst1[id[k]] = src1[k]; any pair may be null.
+void launch_export(const int32_t* id, int64_t n, const double* src3a, double* dst3a,
+                   const double* src3b, double* dst3b, const double* src1, double* dst1,
+                   hipStream_t s);
 
 // ----------------------------------------------------------------- forces
 struct PairParams {
@@ -306,6 +333,9 @@ struct KickArgs {
     double hdtm;       // dt / (2 M)
     double mass;
     double* ke_part;   // [item_max] per-work-item kinetic energy, or nullptr
+    // Where F, E and the kicked velocity of sorted slot k live: index k
+    // (true: the arrays are in sorted order) or perm[k] (false: caller order).
+    bool slot_order;
 };
 struct ForceBuf {
     double4* stg64;     // [n] FP64 staging (sorted)
@@ -364,10 +394,13 @@ struct DriftArgs {
     double L_new, ratio;  // ratio = L_new / L_old (affine variant only)
     int scale_positions;
 };
+// The state arrays of DriftArgs are in the sorted order of the last build:
+// thread k updates slot k and bins it (key[k]), so the lanes of a wave
+// mostly fall in one bin and the count atomics aggregate.
 void launch_drift(const DriftArgs& a, const Grid& g, const CellBuf& cb, uint32_t* err,
                   hipStream_t s, Timer* t);
-// Neighbour-list form of the drift: the same update, visiting the sorted
-// slots of the last build; writes the slot's staging coordinates for the new
+// Neighbour-list form of the drift: the same update of the sorted slots of
+// the last build; writes the slot's staging coordinates for the new
 // box, reduces max |u|^2 (nearest-image displacement since the build) and,
 // in its last workgroup, decides whether this step rebuilds (ListCtl).
 // g is the cell grid a rebuild at this step would use.

@@ -597,7 +597,7 @@ __device__ void coulomb_pair_item(const typename P::Src* __restrict__ stg, int Z
 struct NucArgs {
     const int32_t* start;    // [2 C sub + 1]
     const int32_t* items;    // [2*item_max]
-    const int32_t* perm;     // [n]
+    const int32_t* perm;     // [n] slot -> output index of F and E, or null (slot)
     int nc, C;
     int sub;                 // bins per cell and species (1 or 8)
     int Z;
@@ -725,7 +725,7 @@ __device__ void nuclear_item(const typename P::Src* __restrict__ stg, const NucA
                     V += cp.w;
                 }
             }
-            const int64_t id = A.perm[slot];
+            const int64_t id = A.perm ? A.perm[slot] : slot;
             A.force[3 * id + 0] = Fx;
             A.force[3 * id + 1] = Fy;
             A.force[3 * id + 2] = Fz;
@@ -1038,7 +1038,7 @@ __device__ void nuclear_finish(const NucArgs& A, const NucConsts& k, typename P:
                     V += cp.w;
                 }
             }
-            const int64_t id = A.perm[t.slot];
+            const int64_t id = A.perm ? A.perm[t.slot] : t.slot;
             A.force[3 * id + 0] = Fx;
             A.force[3 * id + 1] = Fy;
             A.force[3 * id + 2] = Fz;
