@@ -819,10 +819,17 @@ extern "C" int pasta_sim_step(pasta_sim* sim, int64_t nsteps)
     hipStream_t s = sim->stream;
     const pasta_integrator& gi = sim->integ;
     const double hdtm = gi.dt / (2.0 * sim->pot.mass);
+    auto box_ok = [&](double L) {
+        return !(L > sim->L_max * (1.0 + 1e-12) || L < 2.0 * sim->pot.r_nuc);
+    };
+    // drifted: this step's first part (half kick, drift, binning) was done by
+    // the previous step's combine kernel (cell form, fused forces: every step
+    // but the last of the call and the thermostat steps)
+    bool drifted = false;
     for (int64_t k = 0; k < nsteps; ++k) {
         const int64_t n0 = sim->step;
         const double L_old = box_side(sim, n0), L_new = box_side(sim, n0 + 1);
-        if (L_new > sim->L_max * (1.0 + 1e-12) || L_new < 2.0 * sim->pot.r_nuc)
+        if (!box_ok(L_new))
             return fail(PASTA_EBOX, "pasta_sim_step: box side %g at step %lld is outside "
                         "[2 r_nuc, L_max = %g]", L_new, (long long)(n0 + 1), sim->L_max);
         const Grid g = make_grid(L_new, sim->r_cell, CELL_SUB);
@@ -859,7 +866,8 @@ extern "C" int pasta_sim_step(pasta_sim* sim, int64_t nsteps)
             launch_list_build(sim->precision, sim->w.fb, sim->w.cb, g, lb, pp, s, &sim->timer);
         } else {
             const StateMove mv = sim_move(sim);
-            launch_drift(da, g, sim->w.cb, sim->w.err, s, &sim->timer);
+            if (!drifted)
+                launch_drift(da, g, sim->w.cb, sim->w.err, s, &sim->timer);
             launch_scan(sim->w.cb, g, sim->w.chunk, s, &sim->timer);
             launch_scatter_rank(sim->xs[c], sim->sps[c], sim->n, g, sim->w.cb, sim->w.fb.stg64,
                                 sim->w.fb.stgq, s, &sim->timer, false, nullptr, nullptr, &mv);
@@ -868,8 +876,26 @@ extern "C" int pasta_sim_step(pasta_sim* sim, int64_t nsteps)
         const bool thermo = gi.rescale_every > 0 && (n0 + 1) % gi.rescale_every == 0;
         double* v = sim->vs[sim->cur];
         KickArgs kick{v, hdtm, sim->pot.mass, thermo ? sim->w.fb.ke_part : nullptr, true};
+        const double L_next = box_side(sim, n0 + 2);
+        const bool fuse = !sim->w.lists && g_tuning.fused_forces && !thermo && k + 1 < nsteps &&
+                          box_ok(L_next);
+        NextDrift nd{};
+        if (fuse) {
+            const Grid g2 = make_grid(L_next, sim->r_cell, CELL_SUB);
+            nd.pos = sim->xs[sim->cur];
+            nd.species = sim->sps[sim->cur];
+            nd.key = sim->w.cb.key;
+            nd.count = sim->w.cb.count;
+            nd.step = DriftStep{hdtm, gi.dt, L_next, L_next / L_new, gi.scale_positions};
+            nd.nc = g2.nc;
+            nd.C = g2.C;
+            nd.sub = g2.sub;
+            nd.inv_w = g2.inv_w;
+            kick.next = &nd;
+        }
         eval_forces(sim->precision, PASTA_TERM_ALL, sim->w, g, sim->n, sim->Z, pp, sim->force,
                     nullptr, kick, nullptr, s, &sim->timer);
+        drifted = fuse;
         sim->epot_valid = false;
         if (thermo)
             launch_thermostat(v, sim->n, sim->w.fb.ke_part,

@@ -149,15 +149,19 @@ __global__ __launch_bounds__(WG) void k_forces_fused(const typename P::Src* __re
     }
 }
 
-// F = nuclear + Coulomb partials per sorted slot, written in caller order,
-// with the optional second half kick and per-block kinetic energy.
+// F = nuclear + Coulomb partials per sorted slot, written at perm[slot] (or
+// the slot), with the optional second half kick and per-block kinetic
+// energy.  With has_next (sorted order): then also the next step's half
+// kick, drift and binning of the slot (nd), which the drift kernel would
+// otherwise do at the start of the next step.
 __global__ __launch_bounds__(WG) void k_combine(const double4* __restrict__ fnuc,
                                                 const double4* __restrict__ part, int S, int Z,
                                                 const int32_t* __restrict__ perm, int64_t n,
                                                 double* __restrict__ force,
                                                 double* __restrict__ epot, double* vel, double hdtm,
                                                 double mass, double* __restrict__ ke_part,
-                                                int32_t* __restrict__ n_ke, uint32_t* err)
+                                                int32_t* __restrict__ n_ke, uint32_t* err,
+                                                NextDrift nd, int has_next)
 {
     __shared__ double red[WG / 64];
     const int64_t sl = (int64_t)blockIdx.x * WG + threadIdx.x;
@@ -200,10 +204,28 @@ __global__ __launch_bounds__(WG) void k_combine(const double4* __restrict__ fnuc
         if (vel) {
             const double vx = vel[3 * id + 0] + hdtm * Fx, vy = vel[3 * id + 1] + hdtm * Fy,
                          vz = vel[3 * id + 2] + hdtm * Fz;
-            vel[3 * id + 0] = vx;
-            vel[3 * id + 1] = vy;
-            vel[3 * id + 2] = vz;
             ke = 0.5 * mass * (vx * vx + vy * vy + vz * vz);
+            if (has_next) {
+                double x[3] = {nd.pos[3 * sl + 0], nd.pos[3 * sl + 1], nd.pos[3 * sl + 2]};
+                double v[3] = {vx, vy, vz};
+                const double f[3] = {Fx, Fy, Fz};
+                const uint32_t bad = drift_update(x, v, f, nd.step);
+                if (bad)
+                    atomicOr(err, bad);
+#pragma unroll
+                for (int d = 0; d < 3; ++d) {
+                    vel[3 * sl + d] = v[d];
+                    nd.pos[3 * sl + d] = x[d];
+                }
+                const int bin = particle_bin(x[0], x[1], x[2], nd.species[sl] == 1, nd.inv_w,
+                                             nd.nc, nd.C, nd.sub);
+                nd.key[sl] = bin;
+                wave_aggregated_add(nd.count, bin);
+            } else {
+                vel[3 * id + 0] = vx;
+                vel[3 * id + 1] = vy;
+                vel[3 * id + 2] = vz;
+            }
         }
     }
     if (ke_part) {
@@ -414,7 +436,8 @@ void launch_forces_fused(int precision, const ForceBuf& fb, const CellBuf& cb, c
     timer_begin(t, KC_COMBINE, s);
     k_combine<<<(unsigned)((n + WG - 1) / WG), WG, 0, s>>>(
         fb.fnuc, fb.coul_part, S, (int)Z, kick.slot_order ? nullptr : cb.perm, n, force, epot,
-        kick.vel, kick.hdtm, kick.mass, kick.ke_part, fb.n_ke, err);
+        kick.vel, kick.hdtm, kick.mass, kick.ke_part, fb.n_ke, err,
+        kick.next ? *kick.next : NextDrift{}, kick.next ? 1 : 0);
     timer_end(t, KC_COMBINE, s);
 }
 

@@ -16,6 +16,11 @@ namespace pasta {
 
 namespace {
 
+__device__ inline DriftStep drift_step(const DriftArgs& a)
+{
+    return DriftStep{a.hdtm, a.dt, a.L_new, a.ratio, a.scale_positions};
+}
+
 // The state is in the sorted order of the previous cell build, so the lanes
 // of a wave mostly fall in one bin and the count atomics aggregate.
 __global__ __launch_bounds__(256) void k_drift(DriftArgs a, int nc, int C, int sub, double inv_w,
@@ -26,36 +31,23 @@ __global__ __launch_bounds__(256) void k_drift(DriftArgs a, int nc, int C, int s
     const int64_t s = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (s >= a.n)
         return;
-    const int64_t i = s;
-    const double L = a.L_new;
-    double xn[3];
-    uint32_t bad = 0;
+    double x[3], v[3], f[3];
 #pragma unroll
     for (int d = 0; d < 3; ++d) {
-        double v = a.vel[3 * i + d] + a.hdtm * a.force[3 * i + d];
-        double x = a.pos[3 * i + d] + a.dt * v;
-        if (a.scale_positions)
-            x *= a.ratio;
-        if (x < 0.0)
-            x += L;
-        if (x >= L)
-            x -= L;
-        if (!(x >= 0.0 && x < L)) {
-            bad |= isfinite(x) ? ERR_WRAP : ERR_NONFINITE_POS;
-            x = isfinite(x) ? x - L * floor(x / L) : 0.0;
-            if (!(x >= 0.0 && x < L))
-                x = 0.0;
-        }
-        if (!isfinite(v))
-            bad |= ERR_NONFINITE_VEL;
-        a.vel[3 * i + d] = v;
-        a.pos[3 * i + d] = x;
-        xn[d] = x;
+        x[d] = a.pos[3 * s + d];
+        v[d] = a.vel[3 * s + d];
+        f[d] = a.force[3 * s + d];
+    }
+    const uint32_t bad = drift_update(x, v, f, drift_step(a));
+#pragma unroll
+    for (int d = 0; d < 3; ++d) {
+        a.vel[3 * s + d] = v[d];
+        a.pos[3 * s + d] = x[d];
     }
     if (bad)
         atomicOr(err, bad);
-    const int bin = particle_bin(xn[0], xn[1], xn[2], a.species[i] == 1, inv_w, nc, C, sub);
-    key[i] = bin;
+    const int bin = particle_bin(x[0], x[1], x[2], a.species[s] == 1, inv_w, nc, C, sub);
+    key[s] = bin;
     wave_aggregated_add(count, bin);
 }
 
@@ -76,30 +68,18 @@ __global__ __launch_bounds__(256) void k_drift_list(DriftArgs a, ListCtl* __rest
     const double L = a.L_new;
     float d2 = 0.f;
     if (s < a.n) {
-        const int64_t i = s;
-        uint32_t bad = 0;
-        double xn[3];
+        double xn[3], v[3], f[3];
 #pragma unroll
         for (int d = 0; d < 3; ++d) {
-            double v = a.vel[3 * i + d] + a.hdtm * a.force[3 * i + d];
-            double x = a.pos[3 * i + d] + a.dt * v;
-            if (a.scale_positions)
-                x *= a.ratio;
-            if (x < 0.0)
-                x += L;
-            if (x >= L)
-                x -= L;
-            if (!(x >= 0.0 && x < L)) {
-                bad |= isfinite(x) ? ERR_WRAP : ERR_NONFINITE_POS;
-                x = isfinite(x) ? x - L * floor(x / L) : 0.0;
-                if (!(x >= 0.0 && x < L))
-                    x = 0.0;
-            }
-            if (!isfinite(v))
-                bad |= ERR_NONFINITE_VEL;
-            a.vel[3 * i + d] = v;
-            a.pos[3 * i + d] = x;
-            xn[d] = x;
+            xn[d] = a.pos[3 * s + d];
+            v[d] = a.vel[3 * s + d];
+            f[d] = a.force[3 * s + d];
+        }
+        const uint32_t bad = drift_update(xn, v, f, drift_step(a));
+#pragma unroll
+        for (int d = 0; d < 3; ++d) {
+            a.vel[3 * s + d] = v[d];
+            a.pos[3 * s + d] = xn[d];
         }
         if (bad)
             atomicOr(err, bad);
@@ -111,7 +91,7 @@ __global__ __launch_bounds__(256) void k_drift_list(DriftArgs a, ListCtl* __rest
             u2 += u * u;
         }
         d2 = (float)u2 * 1.000001f;  // rounded up: the test stays conservative
-        const uint8_t sp = a.species[i];
+        const uint8_t sp = a.species[s];
         if (stg64)
             stg64[s] = make_double4(xn[0], xn[1], xn[2], (double)sp);
         if (stgq) {

@@ -135,6 +135,45 @@ __device__ inline int particle_bin(double x, double y, double z, bool proton, do
     return (proton ? 0 : C * sub) + cell * sub + (sub == 8 ? o : 0);
 }
 
+// One particle's share of a step's first part (Sec. II.A, Eq. 3): the half
+// kick v += (dt/2M) F, the drift x += dt v, the optional affine scaling by
+// L_new / L_old and the wrap into [0, L_new).  x and v are updated in place;
+// returns ERR_* bits.  Every kernel that drifts uses this one function, so
+// the arithmetic is the same code wherever the drift runs.
+struct DriftStep {
+    double hdtm, dt;
+    double L_new, ratio;
+    int scale_positions;
+};
+__device__ inline uint32_t drift_update(double (&x)[3], double (&v)[3], const double (&f)[3],
+                                        const DriftStep& c)
+{
+    uint32_t bad = 0;
+    const double L = c.L_new;
+#pragma unroll
+    for (int d = 0; d < 3; ++d) {
+        const double vd = v[d] + c.hdtm * f[d];
+        double xd = x[d] + c.dt * vd;
+        if (c.scale_positions)
+            xd *= c.ratio;
+        if (xd < 0.0)
+            xd += L;
+        if (xd >= L)
+            xd -= L;
+        if (!(xd >= 0.0 && xd < L)) {
+            bad |= isfinite(xd) ? ERR_WRAP : ERR_NONFINITE_POS;
+            xd = isfinite(xd) ? xd - L * floor(xd / L) : 0.0;
+            if (!(xd >= 0.0 && xd < L))
+                xd = 0.0;
+        }
+        if (!isfinite(vd))
+            bad |= ERR_NONFINITE_VEL;
+        v[d] = vd;
+        x[d] = xd;
+    }
+    return bad;
+}
+
 // Wave-aggregated atomic add of 1 per lane on counters[bin]: the lanes of a
 // wavefront that share a bin are grouped (ballots only), then every group's
 // leader lane adds its group size in one vector atomic instruction, so the
@@ -336,6 +375,19 @@ struct KickArgs {
     // Where F, E and the kicked velocity of sorted slot k live: index k
     // (true: the arrays are in sorted order) or perm[k] (false: caller order).
     bool slot_order;
+    // Optional (fused form, sorted order, no kinetic energy): after the
+    // second half kick of this step, the first part of the next step (half
+    // kick, drift, wrap) and its cell binning, as the drift kernel does it.
+    const struct NextDrift* next = nullptr;
+};
+struct NextDrift {
+    double* pos;             // [n][3] sorted order
+    const uint8_t* species;  // [n] sorted order
+    int32_t* key;            // [n] bin of each slot
+    int32_t* count;          // [2 C sub] bin counters (zero on entry)
+    DriftStep step;          // hdtm, dt, L_{n+2}, L_{n+2} / L_{n+1}
+    int nc, C, sub;          // the cell grid at L_{n+2}
+    double inv_w;
 };
 struct ForceBuf {
     double4* stg64;     // [n] FP64 staging (sorted)
