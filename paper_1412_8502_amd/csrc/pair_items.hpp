@@ -202,6 +202,7 @@ struct Fp64Policy {
                           (uint32_t)(uint64_t)(s.z * k.qscale));
     }
     static constexpr int CTILE = 512;  // sources per tile in the compacting kernel
+    static constexpr int DRAIN_U = 2;  // listed pairs per drain round
     static constexpr int STAGE_PER_THREAD = 1;  // candidates per thread per staging round
 };
 
@@ -296,6 +297,7 @@ struct MixedPolicy {
         return make_uint3(s.x, s.y, s.z);
     }
     static constexpr int CTILE = 768;
+    static constexpr int DRAIN_U = 4;
     static constexpr int STAGE_PER_THREAD = 2;
 };
 
@@ -308,7 +310,11 @@ constexpr int nuclear_lds_bytes()
 {
     return P::TILE * (int)sizeof(typename P::Lds) + 54 * 4 + 55 * 4 + 4 + 4 * 8 + 4 * 8;
 }
-constexpr int NUC_CAP = 24;  // per-lane pair-list capacity (compacting kernel)
+// Per-lane pair-list capacity of the compacting kernel.  Each lane's list is
+// one LDS row of NUC_CAP 16-bit entries; the row stride is an odd number of
+// 32-bit words, so the lanes of a wavefront write and read in distinct banks.
+constexpr int NUC_CAP = 26;
+static_assert(NUC_CAP % 2 == 0 && (NUC_CAP / 2) % 2 == 1, "odd word stride per lane");
 constexpr int NUC_U = 4;     // candidates per lane between list-fill checks
 
 // ============================================================ Coulomb ==
@@ -1115,16 +1121,36 @@ __device__ void nuclear_item_compact_t(const typename P::Src* __restrict__ stg,
         typename P::Part part;
         const int q = t.q;
 
-        // evaluate the listed pairs of every lane, then empty the lists
+        // evaluate the listed pairs of every lane, DU per round (DU / 2 list
+        // words of two entries), then empty the lists.  Entries at or past
+        // cnt are read but masked; a round may read up to DU / 2 - 1 words
+        // past the lane's row, which is the next lane's row or, for the last
+        // lane, the item scratch that follows the lists in LDS.
+        constexpr int DU = P::DRAIN_U;
+        static_assert(DU % 2 == 0 && ITEM_LDS_BYTES >= 2 * DU, "list over-read stays in LDS");
+        const uint32_t* row = reinterpret_cast<const uint32_t*>(lists + tid * NUC_CAP);
         auto drain = [&](int cnt, int kb) {
-            for (int kk = 0; __ballot(kk < cnt); kk += 2) {
-                const bool v0 = kk < cnt, v1 = kk + 1 < cnt;
-                const int j0 = v0 ? lists[kk * WG + tid] : 0;
-                const int j1 = v1 ? lists[(kk + 1) * WG + tid] : 0;
-                const Lds s0 = src[j0], s1 = src[j1];
-                const bool p0 = j0 < kb, p1 = j1 < kb;  // protons first in the tile
-                P::template pair<MODE>(me, s0, p0 ? BLp : BLn, p0 ? Bp : Bn, k, part, v0);
-                P::template pair<MODE>(me, s1, p1 ? BLp : BLn, p1 ? Bp : Bn, k, part, v1);
+            for (int kk = 0; __ballot(kk < cnt); kk += DU) {
+                int j[DU];
+#pragma unroll
+                for (int h = 0; h < DU / 2; ++h) {
+                    const uint32_t w = row[(kk >> 1) + h];
+                    j[2 * h] = (int)(w & 0xffffu);
+                    j[2 * h + 1] = (int)(w >> 16);
+                }
+                bool v[DU];
+                Lds sv[DU];
+#pragma unroll
+                for (int u = 0; u < DU; ++u) {
+                    v[u] = kk + u < cnt;
+                    j[u] = v[u] ? j[u] : 0;
+                    sv[u] = src[j[u]];
+                }
+#pragma unroll
+                for (int u = 0; u < DU; ++u) {
+                    const bool pu = j[u] < kb;  // protons first in the tile
+                    P::template pair<MODE>(me, sv[u], pu ? BLp : BLn, pu ? Bp : Bn, k, part, v[u]);
+                }
             }
         };
         // Screen the tile's sources against this lane's target.  The append
@@ -1147,7 +1173,7 @@ __device__ void nuclear_item_compact_t(const typename P::Src* __restrict__ stg,
 #pragma unroll
                 for (int u = 0; u < NUC_U; ++u) {
                     const int j = j0 + u * TPT + q;
-                    lists[cnt * WG + tid] = (uint16_t)j;
+                    lists[tid * NUC_CAP + cnt] = (uint16_t)j;
                     cnt += screen16(me_xy16, mef.z, tv[u]) < thr ? 1 : 0;
                 }
                 if (__ballot(cnt > NUC_CAP - NUC_U)) {
@@ -1159,7 +1185,7 @@ __device__ void nuclear_item_compact_t(const typename P::Src* __restrict__ stg,
             for (int u = 0; u < NUC_U; ++u) {
                 const int j = nfull + u * TPT + q;
                 if (j < n) {
-                    lists[cnt * WG + tid] = (uint16_t)j;
+                    lists[tid * NUC_CAP + cnt] = (uint16_t)j;
                     cnt += screen16(me_xy16, mef.z, tst[j]) < thr ? 1 : 0;
                 }
             }
