@@ -310,11 +310,11 @@ constexpr int nuclear_lds_bytes()
 {
     return P::TILE * (int)sizeof(typename P::Lds) + 54 * 4 + 55 * 4 + 4 + 4 * 8 + 4 * 8;
 }
-// Per-lane pair-list capacity of the compacting kernel.  Each lane's list is
-// one LDS row of NUC_CAP 16-bit entries; the row stride is an odd number of
-// 32-bit words, so the lanes of a wavefront write and read in distinct banks.
+// Per-lane pair-list capacity of the compacting kernel.  Entry c of thread
+// t is the 16-bit word c * WG + t: whatever the lanes' counts, a wavefront's
+// appends then fall in one bank per pair of lanes, and a drain round reads
+// one row.
 constexpr int NUC_CAP = 26;
-static_assert(NUC_CAP % 2 == 0 && (NUC_CAP / 2) % 2 == 1, "odd word stride per lane");
 constexpr int NUC_U = 4;     // candidates per lane between list-fill checks
 
 // ============================================================ Coulomb ==
@@ -1121,29 +1121,20 @@ __device__ void nuclear_item_compact_t(const typename P::Src* __restrict__ stg,
         typename P::Part part;
         const int q = t.q;
 
-        // evaluate the listed pairs of every lane, DU per round (DU / 2 list
-        // words of two entries), then empty the lists.  Entries at or past
-        // cnt are read but masked; a round may read up to DU / 2 - 1 words
-        // past the lane's row, which is the next lane's row or, for the last
-        // lane, the item scratch that follows the lists in LDS.
+        // evaluate the listed pairs of every lane, DU per round, then empty
+        // the lists.  Every lane reads DU entries per round (rows clamped to
+        // the capacity) and masks those at or past its count.
         constexpr int DU = P::DRAIN_U;
-        static_assert(DU % 2 == 0 && ITEM_LDS_BYTES >= 2 * DU, "list over-read stays in LDS");
-        const uint32_t* row = reinterpret_cast<const uint32_t*>(lists + tid * NUC_CAP);
         auto drain = [&](int cnt, int kb) {
             for (int kk = 0; __ballot(kk < cnt); kk += DU) {
                 int j[DU];
-#pragma unroll
-                for (int h = 0; h < DU / 2; ++h) {
-                    const uint32_t w = row[(kk >> 1) + h];
-                    j[2 * h] = (int)(w & 0xffffu);
-                    j[2 * h + 1] = (int)(w >> 16);
-                }
                 bool v[DU];
                 Lds sv[DU];
 #pragma unroll
                 for (int u = 0; u < DU; ++u) {
+                    const int raw = lists[min(kk + u, NUC_CAP - 1) * WG + tid];
                     v[u] = kk + u < cnt;
-                    j[u] = v[u] ? j[u] : 0;
+                    j[u] = v[u] ? raw : 0;
                     sv[u] = src[j[u]];
                 }
 #pragma unroll
@@ -1173,7 +1164,7 @@ __device__ void nuclear_item_compact_t(const typename P::Src* __restrict__ stg,
 #pragma unroll
                 for (int u = 0; u < NUC_U; ++u) {
                     const int j = j0 + u * TPT + q;
-                    lists[tid * NUC_CAP + cnt] = (uint16_t)j;
+                    lists[cnt * WG + tid] = (uint16_t)j;
                     cnt += screen16(me_xy16, mef.z, tv[u]) < thr ? 1 : 0;
                 }
                 if (__ballot(cnt > NUC_CAP - NUC_U)) {
@@ -1185,7 +1176,7 @@ __device__ void nuclear_item_compact_t(const typename P::Src* __restrict__ stg,
             for (int u = 0; u < NUC_U; ++u) {
                 const int j = nfull + u * TPT + q;
                 if (j < n) {
-                    lists[tid * NUC_CAP + cnt] = (uint16_t)j;
+                    lists[cnt * WG + tid] = (uint16_t)j;
                     cnt += screen16(me_xy16, mef.z, tst[j]) < thr ? 1 : 0;
                 }
             }
