@@ -45,7 +45,8 @@ def measured_traffic(kernel_name, tuning):
     """HBM bytes per launch of the pair-force kernel from the counter runs
     recorded under profiles/ (FETCH_SIZE and WRITE_SIZE, each scaled by what
     the counter reads for a copy of known size), or None when the kernel
-    sources or setting differ from the ones the counters were taken on."""
+    sources differ from the ones the counters were taken on or no record
+    matches this kernel and setting."""
     import hashlib
     path = os.path.join(ROOT, "profiles", "traffic_pair_forces_n51200.json")
     try:
@@ -62,12 +63,14 @@ def measured_traffic(kernel_name, tuning):
             return None
         h.update(src.encode())
         h.update(data)
+    if h.hexdigest() != rec.get("sources_sha256"):
+        return None
     want = [tuning.get("nuclear_variant"), tuning.get("coulomb_splits"), tuning.get("fused_forces"),
             tuning.get("coulomb_form", 0)]
-    if h.hexdigest() != rec.get("sources_sha256") or rec.get("tuning") != want \
-            or rec.get("kernel") != kernel_name:
-        return None
-    return rec["bytes_per_launch"]
+    for e in rec.get("entries", []):
+        if e.get("kernel") == kernel_name and e.get("tuning") == want:
+            return e["bytes_per_launch"]
+    return None
 
 
 def run_path(B, torch, st, precision, steps, warmup, timing):
