@@ -821,7 +821,10 @@ __device__ inline ItemLds item_lds(char* p)
 }
 
 // The item's target: chunk `chunk` of cell c holds targets chunk*(WG/TPT) +
-// tid/TPT of the cell's protons-then-neutrons; TPT lanes share a target.
+// tid/TPT of the cell's members taken octant by octant (within an octant the
+// protons, then the neutrons); TPT lanes share a target.  Octant order keeps
+// a chunk's targets close together, so the sources within range of their
+// bounding box are fewer than for a chunk that spans the whole cell.
 struct ItemTarget {
     int c, tl, q, slot;
     bool active, tprot;
@@ -833,14 +836,27 @@ __device__ inline ItemTarget item_target(const NucArgs& A, int item)
     t.c = A.items[2 * item + 0];
     const int chunk = A.items[2 * item + 1];
     const int S = A.sub;
-    const int ps = A.start[t.c * S], npc = A.start[(t.c + 1) * S] - ps;
-    const int ns = A.start[(A.C + t.c) * S], mc = npc + (A.start[(A.C + t.c + 1) * S] - ns);
+    const int pb = t.c * S, nb = (A.C + t.c) * S;  // the cell's first proton / neutron bin
     t.tl = threadIdx.x / TPT;
     t.q = threadIdx.x % TPT;
     const int tidx = chunk * (WG / TPT) + t.tl;
-    t.active = tidx < mc;
-    t.slot = t.active ? (tidx < npc ? ps + tidx : ns + (tidx - npc)) : 0;
-    t.tprot = tidx < npc;
+    int before = 0, slot = -1;
+    bool prot = false;
+    for (int o = 0; o < S; ++o) {
+        const int p0 = A.start[pb + o], np = A.start[pb + o + 1] - p0;
+        const int n0 = A.start[nb + o], nn = A.start[nb + o + 1] - n0;
+        const int r = tidx - before;
+        if (slot < 0 && r >= 0 && r < np) {
+            slot = p0 + r;
+            prot = true;
+        } else if (slot < 0 && r >= np && r < np + nn) {
+            slot = n0 + (r - np);
+        }
+        before += np + nn;
+    }
+    t.active = slot >= 0;
+    t.slot = t.active ? slot : 0;
+    t.tprot = prot;
     return t;
 }
 
