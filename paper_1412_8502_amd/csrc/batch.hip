@@ -396,7 +396,7 @@ __device__ void phase_forces(const BatchDev& B, int64_t step, int mode, char* ld
         if (threadIdx.x == 0)
             *s_item = (int)atomicAdd(ctr, 1u);
         __syncthreads();
-        const int64_t it = *s_item;
+        const int64_t it = __builtin_amdgcn_readfirstlane(*s_item);  // uniform: the item
         __syncthreads();
         if (it >= total)
             break;

@@ -141,3 +141,23 @@ def test_list_rebuild_bound(scale_positions):
         excess = (r_b - r_now - bound)[close]
         worst = max(worst, excess.max())
     assert worst <= 1e-9, worst
+
+
+def test_expansion_cluster_stats():
+    """Table II statistics from labels: free-neutron mass fraction, mean and
+    population SD of A and Z over clusters with A >= 12, light clusters."""
+    from paper_1412_8502_amd.expansion import cluster_stats
+    # cluster 0: 12 nucleons (4 protons); cluster 1: 20 (8 protons);
+    # cluster 2: 3 (1 proton, light); 5 free neutrons
+    label = np.array([0] * 12 + [1] * 20 + [2] * 3 + [-1] * 5)
+    species = np.zeros(40, np.uint8)
+    species[[0, 1, 2, 3]] = 1
+    species[12:20] = 1
+    species[32] = 1
+    s = cluster_stats(label, species)
+    assert s["clusters"] == 3 and s["clusters_A_ge_12"] == 2
+    assert s["mass_fraction_free_neutrons"] == 5 / 40
+    assert s["mass_fraction_light_clusters"] == 3 / 40
+    assert s["largest_A"] == 20
+    assert s["mean_A"] == 16.0 and s["sd_A"] == 4.0
+    assert s["mean_Z"] == 6.0 and s["sd_Z"] == 2.0
