@@ -36,7 +36,7 @@ constexpr int WG = 256;
 constexpr int NUC_TPT = 4;               // lanes per target (nuclear)
 constexpr int NUC_CHUNK = WG / NUC_TPT;  // targets per work item
 constexpr int TILE64 = 1024;             // FP64 sources per LDS tile (32 KB)
-constexpr int TILEQ = 2048;              // fixed-point sources per tile (32 KB)
+constexpr int TILEQ = 1024;              // fixed-point sources per tile (16 KB)
 
 // ----------------------------------------------------------- constants
 struct NucConsts {
@@ -296,7 +296,10 @@ struct MixedPolicy {
     {
         return make_uint3(s.x, s.y, s.z);
     }
-    static constexpr int CTILE = 768;
+    // 512 sources per tile keep the compacting item's LDS (tile, screen
+    // coordinates, pair lists, scratch) under 160 KB / 6: with <= 80 VGPRs,
+    // six workgroups per CU
+    static constexpr int CTILE = 512;
     static constexpr int DRAIN_U = 4;
     static constexpr int STAGE_PER_THREAD = 2;
 };
@@ -1111,6 +1114,9 @@ constexpr int nuclear_compact_lds_bytes()
 {
     return P::CTILE * ((int)sizeof(typename P::Lds) + 8) + NUC_CAP * WG * 2 + ITEM_LDS_BYTES;
 }
+
+static_assert(nuclear_compact_lds_bytes<MixedPolicy>() <= 26 * 1024 + 512,
+              "mixed compacting item: six workgroups per CU");
 
 template <class P, int TPT, bool NUC, int MODE>
 __device__ void nuclear_item_compact_t(const typename P::Src* __restrict__ stg,
