@@ -585,7 +585,10 @@ __global__ __launch_bounds__(BW) void k_ph_rank(BatchDev B, int mode)
     phase_rank<P>(B, *B.step, mode);
 }
 template <class P, int M, int V>
-__global__ __launch_bounds__(BW) void k_ph_forces(BatchDev B, int mode)
+// At least five waves per SIMD: the compiler keeps the force phase within 96
+// VGPRs (without the bound it takes up to 138 for the compacting items, and
+// the phase runs with three).
+__global__ __launch_bounds__(BW) __attribute__((amdgpu_waves_per_eu(5))) void k_ph_forces(BatchDev B, int mode)
 {
     __shared__ __align__(16) char lds[batch_lds<P, V>()];
     __shared__ int s_item;
