@@ -48,7 +48,9 @@ def cluster_stats(label: np.ndarray, species: np.ndarray, a_min: int = 12) -> di
 
 def run(n: int, yp: float, T: float, xi_log10: float, equil_steps: int, seed: int,
         n0: float = 0.08, n_end: float = 0.01, dt: float = 2.0, report_every: int = 50000,
-        log=print) -> dict:
+        log=print, return_state: bool = False):
+    """One run; returns the result dict (and, with return_state, also the
+    final positions [n][3] and box side as numpy / float)."""
     import torch
     from . import binding as B
     from .inputs import make_state
@@ -91,10 +93,13 @@ def run(n: int, yp: float, T: float, xi_log10: float, equil_steps: int, seed: in
     del sim
     cl = B.pasta_cluster(pos, sp, L_end)
     stats = cluster_stats(cl["label"].cpu().numpy(), st["species"])
-    return {"N": n, "Y_P": yp, "T_MeV": T, "log10_xi_dot": xi_log10, "dt_fm_c": dt,
-            "equilibration_steps": equil_steps, "expansion_steps": steps,
-            "n_final": n / L_end ** 3, "seed": seed, "seconds": time.perf_counter() - t0,
-            **stats}
+    res = {"N": n, "Y_P": yp, "T_MeV": T, "log10_xi_dot": xi_log10, "dt_fm_c": dt,
+           "equilibration_steps": equil_steps, "expansion_steps": steps,
+           "n_final": n / L_end ** 3, "seed": seed, "seconds": time.perf_counter() - t0,
+           **stats}
+    if return_state:
+        return res, pos.cpu().numpy(), L_end
+    return res
 
 
 def main(argv=None):

@@ -121,3 +121,26 @@ def test_large_system(env):
     assert (np.arange(len(hA)) * hA).sum() + cl["nfree"] == st["n"]
     assert (np.arange(len(hZ)) * hZ).sum() == st["Z"]
     say(f"  large: K = {ncomp}, free = {cl['nfree']}")
+
+
+def test_expansion_run_statistics(env):
+    """A short decompression run through expansion.run (equilibration, then
+    the box law at xi_dot = 1e-3 c/fm down to 0.01 fm^-3): the reported
+    density and Table II statistics must equal the oracle's cluster algorithm
+    and statistics on the run's final state."""
+    from paper_1412_8502_amd import expansion
+    O = env["O"]
+    res, P, L = expansion.run(3200, 0.3, 1.0, -3.0, 1000, seed=77, report_every=500,
+                              log=say, return_state=True)
+    st = env["I"].make_state(3200, 0.3, 0.08, 1.0, 77)
+    assert res["expansion_steps"] == 500
+    assert res["n_final"] == pytest.approx(0.01, rel=1e-9)
+    assert L == O.box_length(st["L"], 1e-3, 2.0, 500)
+    ref = O.cluster_stats(O.cluster(P, st["species"], L), st["species"])
+    say(f"  run: {res}")
+    assert res["clusters"] == ref["nclusters"]
+    assert res["clusters_A_ge_12"] == ref["n_heavy"]
+    assert res["mass_fraction_free_neutrons"] == ref["x_free"]
+    if ref["n_heavy"]:
+        assert res["mean_A"] == ref["A_mean"] and res["sd_A"] == ref["A_std"]
+        assert res["mean_Z"] == ref["Z_mean"] and res["sd_Z"] == ref["Z_std"]
