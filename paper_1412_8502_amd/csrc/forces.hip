@@ -1,19 +1,27 @@
 // Pair-force kernels (a2 nuclear, a3 Coulomb) for one system.  The work
-// items themselves live in pair_items.hpp, shared with the batched
-// persistent kernel.
+// items themselves live in pair_items.hpp and list_items.hpp, shared with
+// the batched kernels.
 //
-// Coulomb: all proton pairs.  Protons occupy sorted slots [0, Z).  A
-// workgroup owns 256 targets (one per thread) and one of S source ranges;
-// sources stream through an LDS tile and are read as wave-wide broadcasts.
-// The S partial sums per target are added in fixed order by the nuclear
-// kernel's epilogue.
+// Coulomb: all proton pairs; protons occupy sorted slots [0, Z).  Gather
+// form: a workgroup owns 256 targets (one per thread) and one of S source
+// ranges, the sources streaming through an LDS tile as wave-wide broadcasts.
+// Pairwise form: a workgroup owns a pair of 256-proton super-blocks and
+// evaluates each proton pair once, moving sources and their reactions along
+// the lanes.  Either way every proton gets S partial sums, added in fixed
+// order afterwards.
 //
-// Nuclear: cell tiles.  A workgroup owns a chunk of the targets of one cell;
-// the neighbour cells' particles (protons first, then neutrons) are staged
-// into an LDS tile; NUC_TPT adjacent lanes share one target and split its
-// sources, then combine by wavefront shuffles.  The epilogue adds the Coulomb
-// partials, writes F and E in the caller's particle order and can apply the
-// velocity-Verlet second half kick (fused integrate).
+// Nuclear: cell items.  A workgroup owns a chunk of the targets of one cell
+// (taken octant by octant); the neighbour cells' particles within range of
+// the chunk are staged in LDS; 4 or 8 adjacent lanes share one target
+// (dense sweep, or screen + per-lane pair lists + drain), and combine by
+// shuffles.  The list form reads per-target neighbour lists instead.
+//
+// Fused form (default): one launch holds every nuclear item and then every
+// Coulomb item; the nuclear items write raw (F, V) per sorted slot and
+// k_combine adds the partials, writes F (and E) at the slot or the caller
+// index, applies the second half kick and, in a simulation, the next step's
+// drift and binning.  Unfused form: k_coulomb / k_coulomb_pair, then the
+// nuclear kernel whose epilogue does the combine.
 #include <type_traits>
 
 #include "list_items.hpp"

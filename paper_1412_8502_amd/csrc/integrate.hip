@@ -5,7 +5,9 @@
 // v += (dt/2M) F_n, the drift x += dt v, the optional affine scaling of the
 // variant, the wrap into [0, L_{n+1}), and the cell binning of the new
 // position with its integer atomic count (the first pass of the cell-list
-// build).  The second half kick is fused into the nuclear kernel's epilogue.
+// build).  The second half kick is fused into the force combine (k_combine,
+// or the nuclear kernel's epilogue in the unfused form), which in a run of
+// several steps also performs the next step's drift and binning.
 //
 // The thermostat (every rescale_every steps) reduces the per-work-item
 // kinetic energies in fixed order in one workgroup and scales v by

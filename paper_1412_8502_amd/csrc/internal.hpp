@@ -422,7 +422,8 @@ int launch_coulomb(int precision, const ForceBuf& fb, int64_t Z, const PairParam
                    bool energy, hipStream_t s, Timer* t);
 // Nuclear cell-tile kernel; adds the coul_S Coulomb partials of proton
 // targets (coul_S = 0: none),
-// writes F and E in caller order, optionally applies the second half kick.
+// writes F and E at the caller index (perm[slot]) or at the sorted slot
+// (kick.slot_order), optionally applies the second half kick.
 void launch_nuclear(int precision, const ForceBuf& fb, const CellBuf& cb, const Grid& g,
                     int64_t n, int64_t Z, const PairParams& pp, bool with_nuclear_terms,
                     int coul_S, double* force, double* epot, const KickArgs& kick,

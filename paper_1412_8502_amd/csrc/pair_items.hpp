@@ -612,7 +612,7 @@ struct NucArgs {
     int Z;
     const double4* coul_part;
     int S;                   // Coulomb splits to add (0 = none)
-    double* force;           // [n][3] caller order
+    double* force;           // [n][3] at perm[slot] (caller order) or the slot
     double* epot;            // [n] or null
     double* vel;             // [n][3] or null: apply the half kick
     double hdtm, mass;
@@ -1022,7 +1022,8 @@ __device__ __forceinline__ void stage_neighbourhood(const typename P::Src* __res
 
 // Epilogue of a nuclear cell item: combine the TPT lanes of each target,
 // then either store the raw nuclear (F, V) per sorted slot (fnuc form) or
-// add the Coulomb partials, write F and E in caller order and apply the
+// add the Coulomb partials, write F and E (at perm[slot], or at the slot when
+// perm is null) and apply the
 // optional half kick; finally the fixed-order per-item kinetic-energy and
 // pair-count reductions.  self_in_sum: the target's own r = 0 term (a like
 // pair, V(0) = a + b + c) was summed and is removed here.
