@@ -144,3 +144,27 @@ def test_expansion_run_statistics(env):
     if ref["n_heavy"]:
         assert res["mean_A"] == ref["A_mean"] and res["sd_A"] == ref["A_std"]
         assert res["mean_Z"] == ref["Z_mean"] and res["sd_Z"] == ref["Z_std"]
+
+
+def test_expansion_checkpoint_resume(env, tmp_path):
+    """A decompression run cut into three segments through checkpoint files
+    (mid-equilibration, then mid-expansion) takes the same steps as the uncut
+    run: the resumed simulation starts at the saved global step, so the box
+    law and the thermostat cadence continue, and the final positions, box
+    side and statistics equal the uncut run's bit for bit."""
+    from paper_1412_8502_amd import expansion
+    args = (3200, 0.3, 1.0, -3.0, 1000)
+    kw = dict(seed=78, report_every=250, log=say)
+    ref, P_ref, L_ref = expansion.run(*args, return_state=True, **kw)
+    ck = tmp_path / "run.npz"
+    r1 = expansion.run(*args, checkpoint=ck, max_steps=750, **kw)
+    assert r1["status"] == "checkpointed" and (r1["phase"], r1["done"]) == (0, 750)
+    r2 = expansion.run(*args, checkpoint=ck, resume=ck, max_steps=500, **kw)
+    assert r2["status"] == "checkpointed" and (r2["phase"], r2["done"]) == (1, 250)
+    r3, P, L = expansion.run(*args, resume=ck, return_state=True, **kw)
+    say(f"  max |dx| = {np.abs(P - P_ref).max():.3e}")
+    assert r3["status"] == "done" and r3["segments"] == 3
+    assert L == L_ref
+    assert np.array_equal(P, P_ref)
+    for k in ("clusters", "clusters_A_ge_12", "mass_fraction_free_neutrons", "largest_A"):
+        assert r3[k] == ref[k]

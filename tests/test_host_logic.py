@@ -161,3 +161,24 @@ def test_expansion_cluster_stats():
     assert s["largest_A"] == 20
     assert s["mean_A"] == 16.0 and s["sd_A"] == 4.0
     assert s["mean_Z"] == 6.0 and s["sd_Z"] == 2.0
+
+
+def test_expansion_checkpoint_roundtrip(tmp_path):
+    """A decompression checkpoint keeps the state bit for bit and refuses to
+    resume a run with other parameters or a malformed state."""
+    from paper_1412_8502_amd.expansion import save_checkpoint, load_checkpoint
+    rng = np.random.default_rng(5)
+    params = {"n": 7, "yp": 0.3, "T": 1.0, "xi_log10": -7.0, "equil_steps": 500000,
+              "seed": 3202, "n0": 0.08, "n_end": 0.01, "dt": 2.0}
+    pos, vel = rng.random((7, 3)) * 40.0, rng.standard_normal((7, 3))
+    path = tmp_path / "ck.npz"
+    save_checkpoint(path, params, 1, 1250000, 612.5, 2, pos, vel)
+    ck = load_checkpoint(path, params)
+    assert (ck["phase"], ck["done"], ck["seconds"], ck["segments"]) == (1, 1250000, 612.5, 2)
+    assert np.array_equal(ck["pos"], pos) and np.array_equal(ck["vel"], vel)
+    for k, v in (("seed", 3203), ("yp", 0.2), ("xi_log10", -6.0), ("n", 8)):
+        with pytest.raises(ValueError):
+            load_checkpoint(path, {**params, k: v})
+    save_checkpoint(path, params, 2, 0, 0.0, 1, pos, vel)
+    with pytest.raises(ValueError):
+        load_checkpoint(path, params)
