@@ -133,6 +133,76 @@ __global__ __launch_bounds__(SCAN_THREADS) void k_scan(int32_t* __restrict__ cou
     }
 }
 
+// The same for octant bins (sub = 8) and at most SCAN_THREADS cells, the
+// simulation's case: thread c owns cell c, holds its 8 proton and 8 neutron
+// counts in registers (four 16-byte loads, all in flight at once) and the
+// workgroup scans their sums (proton and neutron totals packed in one 64-bit
+// word: both are at most n < 2^31, so the low half never carries) and the
+// cell's item count, so nothing is read back that the kernel wrote.  The
+// buffers are 256-byte aligned and 8 c ints sit at a 32-byte boundary.
+__global__ __launch_bounds__(SCAN_THREADS) void k_scan_oct(int32_t* __restrict__ count,
+                                                           int32_t* __restrict__ fill,
+                                                           int32_t* __restrict__ start, int C,
+                                                           int chunk,
+                                                           int32_t* __restrict__ items,
+                                                           int32_t* __restrict__ n_items,
+                                                           const int32_t* __restrict__ gate)
+{
+    __shared__ int64_t lds[64];
+    if (gate && *gate == 0)
+        return;
+    const int c = threadIdx.x;
+    const int64_t CS = (int64_t)C * 8;
+    int4 p0{0, 0, 0, 0}, p1{0, 0, 0, 0}, n0{0, 0, 0, 0}, n1{0, 0, 0, 0};
+    if (c < C) {
+        const int4* cp = reinterpret_cast<const int4*>(count + 8 * (int64_t)c);
+        const int4* cn = reinterpret_cast<const int4*>(count + CS + 8 * (int64_t)c);
+        p0 = cp[0];
+        p1 = cp[1];
+        n0 = cn[0];
+        n1 = cn[1];
+    }
+    const int64_t sp = (int64_t)p0.x + p0.y + p0.z + p0.w + p1.x + p1.y + p1.z + p1.w;
+    const int64_t sn = (int64_t)n0.x + n0.y + n0.z + n0.w + n1.x + n1.y + n1.z + n1.w;
+    const int64_t k = chunk > 0 ? (sp + sn + chunk - 1) / chunk : 0;
+    int64_t tot = 0, tq = 0;
+    const int64_t pre = block_exclusive_scan(sp | (sn << 32), lds, &tot);
+    const int64_t bq = chunk > 0 ? block_exclusive_scan(k, lds, &tq) : 0;
+    const int64_t Zt = tot & 0xffffffffll;  // all protons
+    if (c < C) {
+        int32_t b = (int32_t)(pre & 0xffffffffll);
+        int4 s0, s1;
+        s0.x = b; b += p0.x; s0.y = b; b += p0.y; s0.z = b; b += p0.z; s0.w = b; b += p0.w;
+        s1.x = b; b += p1.x; s1.y = b; b += p1.y; s1.z = b; b += p1.z; s1.w = b;
+        int4* sp4 = reinterpret_cast<int4*>(start + 8 * (int64_t)c);
+        sp4[0] = s0;
+        sp4[1] = s1;
+        b = (int32_t)(Zt + (pre >> 32));
+        s0.x = b; b += n0.x; s0.y = b; b += n0.y; s0.z = b; b += n0.z; s0.w = b; b += n0.w;
+        s1.x = b; b += n1.x; s1.y = b; b += n1.y; s1.z = b; b += n1.z; s1.w = b;
+        int4* sn4 = reinterpret_cast<int4*>(start + CS + 8 * (int64_t)c);
+        sn4[0] = s0;
+        sn4[1] = s1;
+        for (int64_t q = 0; q < k; ++q) {
+            items[2 * (bq + q) + 0] = c;
+            items[2 * (bq + q) + 1] = (int32_t)q;
+        }
+        // this thread alone read these counters
+        const int4 z{0, 0, 0, 0};
+        int4* zc = reinterpret_cast<int4*>(count + 8 * (int64_t)c);
+        int4* zn = reinterpret_cast<int4*>(count + CS + 8 * (int64_t)c);
+        int4* fc = reinterpret_cast<int4*>(fill + 8 * (int64_t)c);
+        int4* fn = reinterpret_cast<int4*>(fill + CS + 8 * (int64_t)c);
+        zc[0] = z; zc[1] = z; zn[0] = z; zn[1] = z;
+        fc[0] = z; fc[1] = z; fn[0] = z; fn[1] = z;
+    }
+    if (c == 0) {
+        start[2 * CS] = (int32_t)(Zt + (tot >> 32));
+        if (chunk > 0)
+            *n_items = (int32_t)tq;
+    }
+}
+
 // order: the previous sorted order (perm of the last build) or null for the
 // caller's order.  Visiting particles in the previous cell order keeps the
 // lanes of a wave in one or two bins, so the cursor atomics aggregate.
@@ -324,8 +394,12 @@ void launch_scan(const CellBuf& cb, const Grid& g, int chunk, hipStream_t s, Tim
 {
     timer_begin(t, KC_SCAN, s);
     // cb.tmp doubles as the per-cell chunk-count scratch (2C entries)
-    k_scan<<<1, SCAN_THREADS, 0, s>>>(cb.count, cb.fill, cb.start, g.C, g.sub, chunk, cb.items,
-                                      cb.n_items, cb.tmp, gate);
+    if (g.sub == 8 && g.C <= SCAN_THREADS)
+        k_scan_oct<<<1, SCAN_THREADS, 0, s>>>(cb.count, cb.fill, cb.start, g.C, chunk, cb.items,
+                                              cb.n_items, gate);
+    else
+        k_scan<<<1, SCAN_THREADS, 0, s>>>(cb.count, cb.fill, cb.start, g.C, g.sub, chunk,
+                                          cb.items, cb.n_items, cb.tmp, gate);
     timer_end(t, KC_SCAN, s);
 }
 
