@@ -245,41 +245,16 @@ __device__ void phase_drift(const BatchDev& B, int64_t step, int mode)
     }
 }
 
-// Exclusive scan of v[0..m) by one workgroup: contiguous runs per thread
-// (the first 8 values of a run held in registers) and the workgroup scan of
-// the run totals.
-__device__ int64_t block_exscan(const int32_t* v, int32_t* out, int64_t m, int64_t* lds)
-{
-    constexpr int CACHE = 8;
-    const int tid = threadIdx.x;
-    const int64_t per = (m + BW - 1) / BW;
-    const int64_t b = tid * per, e = b + per < m ? b + per : m;
-    int32_t c[CACHE];
-    int64_t s = 0;
-#pragma unroll
-    for (int u = 0; u < CACHE; ++u) {
-        c[u] = b + u < e ? v[b + u] : 0;
-        s += c[u];
-    }
-    for (int64_t k = b + CACHE; k < e; ++k)
-        s += v[k];
-    int64_t total = 0;
-    int64_t run = block_exclusive_scan(s, lds, &total);
-#pragma unroll
-    for (int u = 0; u < CACHE; ++u) {
-        if (b + u < e)
-            out[b + u] = (int32_t)run;
-        run += c[u];
-    }
-    for (int64_t k = b + CACHE; k < e; ++k) {
-        const int32_t x = v[k];
-        out[k] = (int32_t)run;
-        run += x;
-    }
-    __syncthreads();
-    return total;
-}
+static_assert(BSUB == 8, "the scan phase reads a cell's bins as two 16-byte words per species");
 
+// Starts, nuclear work list and counter reset of each system in one
+// workgroup.  Thread t owns a contiguous range of cells: their 8 proton and
+// 8 neutron octant bins, read as 16-byte loads (a system's count and fill
+// start 64-byte aligned, a cell's 8 counters at 32 bytes).  One workgroup
+// scan of the per-thread sums (proton and neutron totals packed in one
+// 64-bit word: both are below 2^31, so the low half never carries) gives the
+// bin starts, a second one the items' offsets; nothing is read back that
+// this phase wrote, and each thread clears the counters it alone read.
 __device__ void phase_scan(const BatchDev& B, int64_t step, int mode, char* lds_raw)
 {
     int64_t* lds = reinterpret_cast<int64_t*>(lds_raw);
@@ -290,35 +265,62 @@ __device__ void phase_scan(const BatchDev& B, int64_t step, int mode, char* lds_
         int32_t* count = B.count + S.bin_off;
         int32_t* fill = B.fill + S.bin_off;
         int32_t* start = B.start + S.start_off;
-        const int64_t nb = gr.nbins();
-        const int64_t total = block_exscan(count, start, nb, lds);
-        if (threadIdx.x == 0)
-            start[nb] = (int32_t)total;
-        __syncthreads();
-        // nuclear work list: ceil(members / chunk) items per cell; fill
-        // doubles as scratch for the per-cell item counts
-        const int64_t CS = (int64_t)gr.C * gr.sub;
-        for (int64_t c = threadIdx.x; c < gr.C; c += BW) {
-            const int32_t m = (start[(c + 1) * gr.sub] - start[c * gr.sub]) +
-                              (start[CS + (c + 1) * gr.sub] - start[CS + c * gr.sub]);
-            fill[c] = (m + B.chunk - 1) / B.chunk;
+        const int64_t C = gr.C, CS = C * BSUB;
+        const int64_t per = (C + BW - 1) / BW;
+        const int64_t c0 = min((int64_t)threadIdx.x * per, C), c1 = min(c0 + per, C);
+        int64_t sp = 0, sn = 0, sq = 0;
+        for (int64_t c = c0; c < c1; ++c) {
+            const int4* cp = reinterpret_cast<const int4*>(count + BSUB * c);
+            const int4* cn = reinterpret_cast<const int4*>(count + CS + BSUB * c);
+            const int4 p0 = cp[0], p1 = cp[1], n0 = cn[0], n1 = cn[1];
+            const int32_t mp = p0.x + p0.y + p0.z + p0.w + p1.x + p1.y + p1.z + p1.w;
+            const int32_t mn = n0.x + n0.y + n0.z + n0.w + n1.x + n1.y + n1.z + n1.w;
+            sp += mp;
+            sn += mn;
+            sq += (mp + mn + B.chunk - 1) / B.chunk;
         }
-        __syncthreads();
-        const int64_t nit = block_exscan(fill, fill + gr.C, gr.C, lds);
+        int64_t tot = 0, tq = 0;
+        const int64_t pre = block_exclusive_scan(sp | (sn << 32), lds, &tot);
+        int64_t bq = block_exclusive_scan(sq, lds, &tq);
+        const int64_t Zt = tot & 0xffffffffll;  // all protons of the system
+        int32_t bp = (int32_t)(pre & 0xffffffffll), bn = (int32_t)(Zt + (pre >> 32));
         int32_t* items = B.items + 2 * S.item_off;
-        for (int64_t c = threadIdx.x; c < gr.C; c += BW) {
-            const int32_t base = fill[gr.C + c], k = fill[c];
-            for (int32_t q = 0; q < k; ++q) {
-                items[2 * (base + q) + 0] = (int32_t)c;
-                items[2 * (base + q) + 1] = q;
+        const int4 z{0, 0, 0, 0};
+        for (int64_t c = c0; c < c1; ++c) {
+            int4* cp = reinterpret_cast<int4*>(count + BSUB * c);
+            int4* cn = reinterpret_cast<int4*>(count + CS + BSUB * c);
+            const int4 p0 = cp[0], p1 = cp[1], n0 = cn[0], n1 = cn[1];
+            const int32_t kp[8] = {p0.x, p0.y, p0.z, p0.w, p1.x, p1.y, p1.z, p1.w};
+            const int32_t kn[8] = {n0.x, n0.y, n0.z, n0.w, n1.x, n1.y, n1.z, n1.w};
+            int32_t m = 0;
+#pragma unroll
+            for (int o = 0; o < BSUB; ++o) {
+                start[BSUB * c + o] = bp;
+                start[CS + BSUB * c + o] = bn;
+                bp += kp[o];
+                bn += kn[o];
+                m += kp[o] + kn[o];
             }
+            const int32_t k = (m + B.chunk - 1) / B.chunk;
+            for (int32_t q = 0; q < k; ++q) {
+                items[2 * (bq + q) + 0] = (int32_t)c;
+                items[2 * (bq + q) + 1] = q;
+            }
+            bq += k;
+            int4* fp = reinterpret_cast<int4*>(fill + BSUB * c);
+            int4* fn = reinterpret_cast<int4*>(fill + CS + BSUB * c);
+            cp[0] = z;
+            cp[1] = z;
+            cn[0] = z;
+            cn[1] = z;
+            fp[0] = z;
+            fp[1] = z;
+            fn[0] = z;
+            fn[1] = z;
         }
-        if (threadIdx.x == 0)
-            B.n_items[s] = (int32_t)nit;
-        __syncthreads();
-        for (int64_t k = threadIdx.x; k < nb; k += BW) {
-            count[k] = 0;
-            fill[k] = 0;
+        if (threadIdx.x == 0) {
+            start[2 * CS] = (int32_t)(Zt + (tot >> 32));
+            B.n_items[s] = (int32_t)tq;
         }
         __syncthreads();
     }
