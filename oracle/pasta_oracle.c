@@ -336,23 +336,57 @@ int oracle_cluster(int64_t n, double L, const double* pos, const uint8_t* specie
     }
     for (int64_t i = 0; i < n; ++i)
         parent[i] = i;
+    /* the protons in increasing index: the pair loops below visit only
+     * protons, in the order a loop over every particle would reach them */
+    int64_t Z = 0;
+    for (int64_t i = 0; i < n; ++i)
+        if (species[i] == 1)
+            canon[Z++] = i;
+    int64_t* prot = (int64_t*)malloc(sizeof(int64_t) * (size_t)(Z > 0 ? Z : 1));
+    int64_t* row = (int64_t*)calloc((size_t)Z + 1, sizeof(int64_t));
+    if (!prot || !row) {
+        free(parent); free(canon); free(zc); free(ac); free(prot); free(row);
+        return -1;
+    }
+    memcpy(prot, canon, sizeof(int64_t) * (size_t)Z);
     /* union over every proton pair within r_pp; the smaller root becomes the
-     * root, so each component's root is its smallest proton index */
-    for (int64_t i = 0; i < n; ++i) {
-        if (species[i] != 1)
-            continue;
-        for (int64_t j = i + 1; j < n; ++j) {
-            if (species[j] != 1)
-                continue;
-            if (dist2(pos, i, j, L) <= rpp2) {
-                int64_t ri = uf_find(parent, i), rj = uf_find(parent, j);
-                if (ri < rj)
-                    parent[rj] = ri;
-                else if (rj < ri)
-                    parent[ri] = rj;
-            }
+     * root, so each component's root is its smallest proton index.  The
+     * distance tests run in parallel, one row (proton a, partners b > a) per
+     * iteration, counted and then listed; the unions then take the linked
+     * pairs serially in increasing (a, b), the order of a double loop. */
+#pragma omp parallel for schedule(dynamic, 64) num_threads(nthreads > 0 ? nthreads : 1)
+    for (int64_t a = 0; a < Z; ++a) {
+        int64_t c = 0;
+        for (int64_t b = a + 1; b < Z; ++b)
+            if (dist2(pos, prot[a], prot[b], L) <= rpp2)
+                c++;
+        row[a + 1] = c;
+    }
+    for (int64_t a = 0; a < Z; ++a)
+        row[a + 1] += row[a];
+    int64_t* link = (int64_t*)malloc(sizeof(int64_t) * (size_t)(row[Z] > 0 ? row[Z] : 1));
+    if (!link) {
+        free(parent); free(canon); free(zc); free(ac); free(prot); free(row);
+        return -1;
+    }
+#pragma omp parallel for schedule(dynamic, 64) num_threads(nthreads > 0 ? nthreads : 1)
+    for (int64_t a = 0; a < Z; ++a) {
+        int64_t c = row[a];
+        for (int64_t b = a + 1; b < Z; ++b)
+            if (dist2(pos, prot[a], prot[b], L) <= rpp2)
+                link[c++] = prot[b];
+    }
+    for (int64_t a = 0; a < Z; ++a) {
+        for (int64_t e = row[a]; e < row[a + 1]; ++e) {
+            int64_t ri = uf_find(parent, prot[a]), rj = uf_find(parent, link[e]);
+            if (ri < rj)
+                parent[rj] = ri;
+            else if (rj < ri)
+                parent[ri] = rj;
         }
     }
+    free(link);
+    free(row);
     /* canonical numbering in increasing root index */
     int32_t K = 0;
     for (int64_t i = 0; i < n; ++i)
@@ -371,9 +405,8 @@ int oracle_cluster(int64_t n, double L, const double* pos, const uint8_t* specie
             continue;
         int64_t best = -1;
         double bd = 0.0;
-        for (int64_t j = 0; j < n; ++j) {
-            if (species[j] != 1)
-                continue;
+        for (int64_t b = 0; b < Z; ++b) {
+            const int64_t j = prot[b];
             double d2 = dist2(pos, k, j, L);
             if (d2 <= rnp2 && (best < 0 || d2 < bd)) {
                 best = j;
@@ -407,7 +440,7 @@ int oracle_cluster(int64_t n, double L, const double* pos, const uint8_t* specie
     *nclusters = K;
     if (nfree)
         *nfree = free_count;
-    free(parent); free(canon); free(zc); free(ac);
+    free(parent); free(canon); free(zc); free(ac); free(prot);
     return 0;
 }
 
