@@ -308,7 +308,19 @@ int pasta_batch_create(const pasta_potential* pot, int32_t precision, int32_t ns
                        int64_t step0, const double* h_L_max, double* d_pos, double* d_vel,
                        const uint8_t* d_species, void* d_work, size_t work_bytes, int32_t mode,
                        int32_t steps_per_graph, void* stream, pasta_batch** out);
+/* Advances every system nsteps steps, then synchronises and checks the
+ * device error word: PASTA_EDEVICE if a device check failed (a non-finite
+ * force, or, in mode 0, a barrier wait that hit its bound -- the persistent
+ * kernel then stops advancing, and this call and every later step, forces
+ * and energies call fail the same way). */
 int pasta_batch_step(pasta_batch* b, int64_t nsteps);
+/* Bound of one device-wide barrier wait of mode 0, in polls of about a
+ * microsecond each (default 2^22).  A wait that reaches it sets the device
+ * error word and every workgroup leaves the kernel instead of waiting on.
+ * polls = 0 makes every wait but the last arriver's fail at once (this is
+ * how the failure path is tested).  Synchronises; the captured steps are
+ * re-captured at the next pasta_batch_step. */
+int pasta_batch_set_wait_limit(pasta_batch* b, int64_t polls);
 /* Synchronises; per-system kinetic and potential energies and box sides
  * (arrays of nsys; any may be NULL) and the global step index.  As for a
  * simulation, steps compute forces only and the energy shares of the
@@ -316,7 +328,9 @@ int pasta_batch_step(pasta_batch* b, int64_t nsteps);
  * pasta_batch_forces). */
 int pasta_batch_energies(pasta_batch* b, double* h_ekin, double* h_epot, double* h_L,
                          int64_t* h_step);
-/* Copies forces ([sum n][3]) and energy shares ([sum n]) of the current state. */
+/* Copies forces ([sum n][3]) and energy shares ([sum n]) of the current
+ * state; synchronises and returns PASTA_EDEVICE, as pasta_batch_step does,
+ * when the device error word is set. */
 int pasta_batch_forces(pasta_batch* b, double* d_force, double* d_epot);
 /* Synchronises; per-system unordered nuclear pairs inside r_nuc and Coulomb
  * pairs at the current state. */

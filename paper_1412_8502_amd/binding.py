@@ -19,6 +19,7 @@ LIB_PATH = os.path.join(HERE, "libpasta.so")
 HEADER = os.path.join(os.path.dirname(HERE), "include", "pasta.h")
 
 PASTA_OK = 0
+PASTA_EDEVICE = -5
 PASTA_FP64 = 0
 PASTA_MIXED = 1
 PASTA_TERM_NUCLEAR = 1
@@ -97,6 +98,7 @@ def _load():
         "pasta_batch_create": (ctypes.c_int, [pot, i32, i32, vp, vp, vp, i64, vp, vp, vp, vp,
                                               vp, sz, i32, i32, vp, P(vp)]),
         "pasta_batch_step": (ctypes.c_int, [vp, i64]),
+        "pasta_batch_set_wait_limit": (ctypes.c_int, [vp, i64]),
         "pasta_batch_energies": (ctypes.c_int, [vp, vp, vp, vp, P(i64)]),
         "pasta_batch_forces": (ctypes.c_int, [vp, vp, vp]),
         "pasta_batch_pair_counts": (ctypes.c_int, [vp, vp, vp]),
@@ -387,6 +389,9 @@ class Batch:
 
     def step(self, nsteps: int = 1):
         _check(lib.pasta_batch_step(self.handle, nsteps))
+
+    def set_wait_limit(self, polls: int):
+        _check(lib.pasta_batch_set_wait_limit(self.handle, polls))
 
     def energies(self):
         n = self.nsys

@@ -84,6 +84,7 @@ struct BatchDev {
     NucConsts* nk;
     CoulConsts* ck;
     int2* grid_nc;        // (nc, C)
+    long spin_limit;      // bound of a barrier wait (polls)
 };
 
 __device__ __forceinline__ int find_sys_chunk(const BatchDev& B, int64_t g)
@@ -124,9 +125,10 @@ __device__ __forceinline__ Grid grid_at(double L, double r_cut)
 // Bounded grid-wide barrier.  Returns false (and every later barrier returns
 // false at once) when the wait limit is hit.  Memory ordering: one
 // agent-scope release fence per arriving workgroup before its (relaxed)
-// arrival, an acquire + release fence by the last arriver before it bumps the
-// generation, and one agent-scope acquire fence per workgroup after the
-// generation changed.  The spin itself uses relaxed loads, so waiting
+// arrival, an acquire + release fence by the last arriver, which then resets
+// the arrival count and publishes the new generation with a release store
+// (so the reset is visible first), and one agent-scope acquire fence per
+// workgroup after the generation changed.  The spin itself uses relaxed loads, so waiting
 // workgroups do not keep invalidating caches that the laggards are using.
 __device__ bool grid_sync(const BatchDev& B, int* s_flag)
 {
@@ -144,15 +146,17 @@ __device__ bool grid_sync(const BatchDev& B, int* s_flag)
                                                             __HIP_MEMORY_SCOPE_AGENT) + 1u;
             if (arrived == nb) {
                 __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "agent");
+                // the reset must be visible before the new generation: a
+                // released workgroup's next arrival then counts from zero
                 __hip_atomic_store(&B.barrier[0], 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-                __hip_atomic_store(&B.barrier[1], gen + 1u, __ATOMIC_RELAXED,
+                __hip_atomic_store(&B.barrier[1], gen + 1u, __ATOMIC_RELEASE,
                                    __HIP_MEMORY_SCOPE_AGENT);
             } else {
                 long spins = 0;
                 while (__hip_atomic_load(&B.barrier[1], __ATOMIC_RELAXED,
                                          __HIP_MEMORY_SCOPE_AGENT) == gen) {
                     __builtin_amdgcn_s_sleep(1);
-                    if (++spins > BARRIER_SPIN_LIMIT) {
+                    if (++spins > B.spin_limit) {
                         atomicOr(B.err, ERR_BARRIER);
                         ok = 0;
                         break;
@@ -1064,6 +1068,7 @@ extern "C" int pasta_batch_create(const pasta_potential* pot, int32_t precision,
     bt->sys = lay2.sys;
     BatchDev& B = bt->dev;
     B.nsys = nsys;
+    B.spin_limit = BARRIER_SPIN_LIMIT;
     B.total_chunks = lay2.total_chunks;
     B.coul_items = lay2.coul_items;
     B.nuc_items = lay2.nuc_items;
@@ -1156,7 +1161,28 @@ extern "C" int pasta_batch_step(pasta_batch* bt, int64_t nsteps)
     bt->step += nsteps;
     if (nsteps > 0)
         bt->epot_valid = false;
-    return join_out(bt);
+    PASTA_TRY(join_out(bt));
+    // a failed device check (a barrier wait that timed out stops every later
+    // step on the device) is reported here and by every later call
+    return check_batch_err(bt, "pasta_batch_step");
+}
+
+extern "C" int pasta_batch_set_wait_limit(pasta_batch* bt, int64_t polls)
+{
+    if (!bt || polls < 0)
+        return fail(PASTA_EINVAL, "pasta_batch_set_wait_limit: bad argument");
+    PASTA_HIP(hipStreamSynchronize(bt->stream));
+    bt->dev.spin_limit = (long)polls;
+    // the captured steps carry the old limit as a kernel argument
+    if (bt->exec) {
+        PASTA_HIP(hipGraphExecDestroy(bt->exec));
+        bt->exec = nullptr;
+    }
+    if (bt->graph) {
+        PASTA_HIP(hipGraphDestroy(bt->graph));
+        bt->graph = nullptr;
+    }
+    return PASTA_OK;
 }
 
 // Energy shares of the current state, evaluated when asked for (the steps
@@ -1227,7 +1253,8 @@ extern "C" int pasta_batch_forces(pasta_batch* bt, double* d_force, double* d_ep
     if (d_epot)
         PASTA_HIP(hipMemcpyAsync(d_epot, bt->dev.epot, sizeof(double) * bt->n_total,
                                  hipMemcpyDeviceToDevice, bt->stream));
-    return join_out(bt);
+    PASTA_TRY(join_out(bt));
+    return check_batch_err(bt, "pasta_batch_forces");
 }
 
 extern "C" int pasta_batch_pair_counts(pasta_batch* bt, int64_t* h_nuclear, int64_t* h_coulomb)

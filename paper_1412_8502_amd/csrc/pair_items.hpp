@@ -9,7 +9,7 @@
 // scheduling.
 //
 // Precision policies:
-//   Fp64Policy  -- double coordinates, nearest image d - L*rint(d/L), the
+//   Fp64Policy  -- double coordinates, nearest image by the strict L/2 test, the
 //                  FP64 exp and rsqrt of fp64math.hpp, double accumulation.
 //   MixedPolicy -- 32-bit fixed-point coordinates (q = L/2^32 fm per unit):
 //                  the int32 difference of two coordinates is the
@@ -25,6 +25,14 @@
 #include "internal.hpp"
 
 namespace pasta {
+
+// Nearest periodic image of an FP64 coordinate difference, positions held
+// in [0, L): subtract L when d > L/2, add L when d < -L/2 (strict, so the
+// difference stays antisymmetric and |d| = L/2 keeps its sign).  hL = L/2.
+__device__ __forceinline__ double nearest_image(double d, double L, double hL)
+{
+    return d > hL ? d - L : (d < -hL ? d + L : d);
+}
 
 // What a pair kernel accumulates: forces only, forces and energy shares,
 // or forces, energies and the count of pairs inside the cutoff.
@@ -42,7 +50,7 @@ constexpr int TILEQ = 1024;              // fixed-point sources per tile (16 KB)
 struct NucConsts {
     // FP64 form: g = exp(r2 * cg); fs = g (A2 g + B/Lambda); V = g (a g + B)
     double cg, A2, a, Bl_L, Bu_L, Bl, Bu, rc2;
-    double L, invL;
+    double L, hL;
     // MIXED form (r2 in units of q^2)
     float cgq, A2f, af, Blf_L, Buf_L, Blf, Buf, thr_q;
     double q;       // fm per fixed-point unit
@@ -66,7 +74,7 @@ __host__ __device__ inline NucConsts make_nuc_consts(const PairParams& pp)
     k.Bu_L = pp.b_unlike / Lam;
     k.rc2 = pp.r_nuc * pp.r_nuc;
     k.L = pp.L;
-    k.invL = 1.0 / pp.L;
+    k.hL = 0.5 * pp.L;
     k.q = pp.L / 4294967296.0;
     k.cgq = (float)(-(k.q * k.q) / (2.0 * Lam) * 1.4426950408889634);
     k.A2f = (float)k.A2;
@@ -86,7 +94,7 @@ __host__ __device__ inline NucConsts make_nuc_consts(const PairParams& pp)
 
 struct CoulConsts {
     // FP64: V = ahc e^{-r/lambda}/r; fs = V (1/r + 1/lambda)/r
-    double ahc, inv_lambda, L, invL;
+    double ahc, inv_lambda, L, hL;
     // MIXED: w = exp2(ru * c_exp) * ir; fs_u = w ir (ir cA + cB)
     float c_exp, cA, cB;
     double v_scale;  // alpha_hbarc / q  (V = v_scale * w)
@@ -99,7 +107,7 @@ __host__ __device__ inline CoulConsts make_coul_consts(const PairParams& pp)
     k.ahc = pp.alpha_hbarc;
     k.inv_lambda = 1.0 / pp.lambda_s;
     k.L = pp.L;
-    k.invL = 1.0 / pp.L;
+    k.hL = 0.5 * pp.L;
     const double q = pp.L / 4294967296.0;
     k.c_exp = (float)(-q / pp.lambda_s * 1.4426950408889634);
     k.cA = (float)(1.0 / (q * q));
@@ -127,9 +135,9 @@ struct Fp64Policy {
                                 const NucConsts& k, Part& p, bool valid = true)
     {
         double dx = me.x - s.x, dy = me.y - s.y, dz = me.z - s.z;
-        dx = fma(-k.L, rint(dx * k.invL), dx);
-        dy = fma(-k.L, rint(dy * k.invL), dy);
-        dz = fma(-k.L, rint(dz * k.invL), dz);
+        dx = nearest_image(dx, k.L, k.hL);
+        dy = nearest_image(dy, k.L, k.hL);
+        dz = nearest_image(dz, k.L, k.hL);
         double r2 = dx * dx + dy * dy + dz * dz;
         const bool in = valid && r2 < k.rc2;
         if (MODE == MODE_COUNT)
@@ -161,9 +169,9 @@ struct Fp64Policy {
                                 CAcc& fx, CAcc& fy, CAcc& fz, CAcc& e)
     {
         double dx = me.x - s.x, dy = me.y - s.y, dz = me.z - s.z;
-        dx = fma(-k.L, rint(dx * k.invL), dx);
-        dy = fma(-k.L, rint(dy * k.invL), dy);
-        dz = fma(-k.L, rint(dz * k.invL), dz);
+        dx = nearest_image(dx, k.L, k.hL);
+        dy = nearest_image(dy, k.L, k.hL);
+        dz = nearest_image(dz, k.L, k.hL);
         double r2 = dx * dx + dy * dy + dz * dz;
         r2 = self ? 1e300 : r2;
         double ir = rsqrt_fast(r2);
@@ -184,9 +192,9 @@ struct Fp64Policy {
         dx = me.x - s.x;
         dy = me.y - s.y;
         dz = me.z - s.z;
-        dx = fma(-k.L, rint(dx * k.invL), dx);
-        dy = fma(-k.L, rint(dy * k.invL), dy);
-        dz = fma(-k.L, rint(dz * k.invL), dz);
+        dx = nearest_image(dx, k.L, k.hL);
+        dy = nearest_image(dy, k.L, k.hL);
+        dz = nearest_image(dz, k.L, k.hL);
         const double r2 = dx * dx + dy * dy + dz * dz;
         const double ir = rsqrt_fast(r2);
         const double r = r2 * ir;

@@ -5,10 +5,10 @@ test_gpu_parity.py."""
 import numpy as np
 import pytest
 
+from parity import check
+
 pytestmark = pytest.mark.gpu
 
-TOL_F = {0: 1e-12, 1: 1e-5}
-TOL_E = {0: 1e-12, 1: 1e-6}
 TOL_X = {0: 1e-9, 1: 2e-4}
 
 
@@ -25,11 +25,6 @@ def env():
 
 def say(*a):
     print(*a, flush=True)
-
-
-def rel(a, b):
-    nb = np.linalg.norm(b)
-    return np.linalg.norm(a - b) / (nb if nb > 0 else 1.0)
 
 
 SMALL = [  # (N, Y_P, density, T, seed): uneven sizes, densities and charge
@@ -64,9 +59,7 @@ def test_batch_initial_forces(env, prec, mode):
     for k, st in enumerate(states):
         of, oe = env["O"].forces(st["pos"], st["species"], st["L"])
         sl = slice(offs[k], offs[k + 1])
-        ef, ee = rel(f[sl], of), rel(e[sl], oe)
-        say(f"  system {k}: force {ef:.2e} energy {ee:.2e}")
-        assert ef <= TOL_F[prec] and ee <= TOL_E[prec]
+        check(f[sl], of, prec, e[sl], oe, what=f"system {k}", say=say)
     b.close()
 
 
@@ -206,8 +199,25 @@ def test_batch_paper_grid_sampled(env):
     rng = np.random.Generator(np.random.PCG64(7))
     for k, st in enumerate(states):
         sl = slice(offs[k], offs[k + 1])
-        tg = rng.choice(st["n"], 40, replace=False)
+        tg = rng.choice(st["n"], 400, replace=False)
         of, _ = O.forces(P[sl], st["species"], st["L"], targets=tg)
-        err = rel(f[sl][tg], of)
-        assert err <= TOL_F[1], (k, err)
+        check(f[sl][tg], of, 1, what=f"grid system {k}", say=say)
+    b.close()
+
+
+def test_batch_barrier_timeout_reported(env):
+    """A device-wide barrier wait that hits its bound (forced from the host
+    with a zero poll limit, so every wait but the last arriver's ends at
+    once and every workgroup leaves the kernel) is reported as PASTA_EDEVICE
+    by the step call and by every later step, forces and energies call."""
+    B = env["B"]
+    b, states, pos, vel, offs = make(env, SMALL[:3], prec=1, mode=0, spg=2)
+    b.step(2)
+    b.forces()
+    b.set_wait_limit(0)
+    for call in (lambda: b.step(2), b.forces, b.energies, lambda: b.step(1)):
+        with pytest.raises(B.PastaError) as ex:
+            call()
+        assert ex.value.code == B.PASTA_EDEVICE
+        say("  reported:", str(ex.value)[:80])
     b.close()

@@ -7,12 +7,18 @@
   cluster algorithm runs every 2000 steps on the GPU state and must match the
   oracle bit for bit; the box side must equal Eq. (3a) exactly and sampled
   forces must match the oracle on every snapshot.
-* Large: N = 409 600, Y_P = 0.40, 200 steps, then device clusters checked by
-  properties that hold at any size (scipy's periodic k-d tree and connected
-  components), and sampled forces against the oracle.
+* Large: N = 409 600 at Y_P = 0.40 and the neutron-rich Y_P = 0.05 of the
+  paper's large runs, 200 steps in FP64 and in mixed precision, then forces
+  on 2000 sampled targets against the oracle (per-particle gate) and the
+  device clusters bit for bit against the oracle's cluster algorithm, with
+  scipy's periodic k-d tree and connected components as a second witness.
+* Energy drift at the headline size (N = 51 200): FP64 and mixed NVE runs of
+  1000 steps from the same warmed state.
 """
 import numpy as np
 import pytest
+
+from parity import check
 
 pytestmark = pytest.mark.gpu
 
@@ -30,10 +36,6 @@ def env():
 
 def say(*a):
     print(*a, flush=True)
-
-
-def rel(a, b):
-    return np.linalg.norm(a - b) / np.linalg.norm(b)
 
 
 def test_decompression_window(env):
@@ -61,44 +63,57 @@ def test_decompression_window(env):
         assert np.array_equal(cl["hist_A"].cpu().numpy(), ref["hist_A"])
         assert np.array_equal(cl["hist_Z"].cpu().numpy(), ref["hist_Z"])
         f, _ = sim.forces()
-        tg = rng.choice(st["n"], 200, replace=False)
+        tg = rng.choice(st["n"], 2000, replace=False)
         of, _ = O.forces(P, st["species"], L, targets=tg)
-        err = rel(f.cpu().numpy()[tg], of)
         stats = O.cluster_stats(ref, st["species"])
         say(f"  step {2000 * k:5d}: n = {st['n'] / L ** 3:.5f} fm^-3, K = {ref['nclusters']}, "
-            f"free n = {ref['nfree']}, A>=12: {stats.get('n_heavy', 0)}, force err {err:.2e}")
-        assert err <= 1e-5
+            f"free n = {ref['nfree']}, A>=12: {stats.get('n_heavy', 0)}")
+        check(f.cpu().numpy()[tg], of, 1, what=f"decompression step {2000 * k}", say=say)
     assert L == pytest.approx(4.0 * L0, rel=1e-12)
     sim.close()
 
 
-def test_large_system(env):
+@pytest.mark.parametrize("prec", [1, 0])
+@pytest.mark.parametrize("name", ["n409600_yp040_n0.080", "n409600_yp005_n0.080"])
+def test_large_system(env, name, prec):
+    """200 steps at N = 409 600, then sampled forces against the oracle and
+    the device clusters against the oracle's cluster algorithm, bit for bit
+    (labels, cluster count, free neutrons, A and Z histograms)."""
     from scipy.sparse import coo_matrix
     from scipy.sparse.csgraph import connected_components
     from scipy.spatial import cKDTree
     t, B, O = env["torch"], env["B"], env["O"]
-    st = env["I"].workload("n409600_yp040_n0.080")
+    say("large", name, "prec", prec)
+    st = env["I"].workload(name)
     L = st["L"]
     pos = t.tensor(st["pos"], device=env["dev"])
     vel = t.tensor(st["vel"], device=env["dev"])
     sp = t.tensor(st["species"], device=env["dev"])
-    sim = B.Sim(pos, vel, sp, L, dt=2.0, T=1.0, rescale_every=100, precision=B.PASTA_MIXED)
+    sim = B.Sim(pos, vel, sp, L, dt=2.0, T=1.0, rescale_every=100, precision=prec)
     sim.step(200)
     en = sim.energies()
-    assert np.isfinite(en["ekin"]) and np.isfinite(en["epot"])
+    assert np.isfinite(en["ekin"]) and np.isfinite(en["epot"]) and en["step"] == 200
     P = pos.cpu().numpy()
     s = st["species"]
-    # sampled forces against the oracle on the GPU's own state
+    # forces on the GPU's own final state against the oracle: 1000 protons
+    # and 1000 neutrons
     f, _ = sim.forces()
     rng = np.random.Generator(np.random.PCG64(4))
-    tg = rng.choice(st["n"], 200, replace=False)
+    tg = np.concatenate([rng.choice(st["Z"], 1000, replace=False),
+                         st["Z"] + rng.choice(st["n"] - st["Z"], 1000, replace=False)])
     of, _ = O.forces(P, s, L, targets=tg)
-    assert rel(f.cpu().numpy()[tg], of) <= 1e-5
+    check(f.cpu().numpy()[tg], of, prec, what=f"{name} after 200 steps", say=say)
     sim.close()
-    # clusters: the partition of the protons must be the connected components
-    # of the r <= 4.5 fm graph, numbered by smallest proton index
     cl = B.pasta_cluster(pos, sp, L)
     lab = cl["label"].cpu().numpy()
+    hA, hZ = cl["hist_A"].cpu().numpy(), cl["hist_Z"].cpu().numpy()
+    # the oracle's cluster algorithm on the same bits
+    ref = O.cluster(P, s, L)
+    assert cl["nclusters"] == ref["nclusters"] and cl["nfree"] == ref["nfree"]
+    assert np.array_equal(lab, ref["label"])
+    assert np.array_equal(hA, ref["hist_A"]) and np.array_equal(hZ, ref["hist_Z"])
+    # second witness: the partition of the protons is the connected
+    # components of the r <= 4.5 fm graph, numbered by smallest proton index
     pidx = np.nonzero(s == 1)[0]
     tree = cKDTree(np.mod(P[pidx], L), boxsize=L)
     pairs = tree.query_pairs(4.5, output_type="ndarray")
@@ -110,17 +125,62 @@ def test_large_system(env):
     rank[np.argsort(first)] = np.arange(ncomp)
     assert cl["nclusters"] == ncomp
     assert np.array_equal(lab[pidx], rank[comp])
-    # neutrons: nearest proton within 3 fm (sampled)
-    nidx = np.nonzero(s == 0)[0]
-    smp = rng.choice(nidx, 5000, replace=False)
-    d, j = tree.query(np.mod(P[smp], L), k=1, distance_upper_bound=3.0)
-    expect = np.where(np.isfinite(d), rank[comp[np.minimum(j, len(pidx) - 1)]], -1)
-    assert np.array_equal(lab[smp], expect)
-    # histogram invariants
-    hA, hZ = cl["hist_A"].cpu().numpy(), cl["hist_Z"].cpu().numpy()
     assert (np.arange(len(hA)) * hA).sum() + cl["nfree"] == st["n"]
     assert (np.arange(len(hZ)) * hZ).sum() == st["Z"]
-    say(f"  large: K = {ncomp}, free = {cl['nfree']}")
+    say(f"  large: K = {ncomp}, free = {cl['nfree']}, largest A = {np.nonzero(hA)[0].max()}")
+
+
+def test_energy_drift_headline(env):
+    """Energy conservation at N = 51 200 (Y_P = 0.20, 0.08 fm^-3): 500 steps
+    with the velocity rescaled every step take the random start's close
+    pairs out, then 1000 NVE steps of dt = 2 fm/c from that one state in FP64
+    and in mixed precision, H/N recorded every 20 fm/c.
+
+    Stated bound: the mixed run's systematic drift (slope of a straight-line
+    fit of H/N over the window, per 1000 steps) stays within the FP64 run's
+    plus 1e-4 MeV, and its max |H(t) - H(0)|/N within twice the FP64 run's
+    (the FP32 pair arithmetic adds no drift of its own; the two chaotic
+    trajectories part, so their maxima differ by about the standard deviation
+    of H); for both, halving dt (2000 steps of 1 fm/c over the same span) at
+    least halves the standard deviation of H (the error is Verlet's).  The
+    FP64 drift itself is tied to the oracle's at N = 600
+    (test_gpu_parity.py::test_energy_drift), where the oracle runs the same
+    protocol; an oracle run of 1000 steps at N = 51 200 would take most of
+    an hour on the host."""
+    t, B = env["torch"], env["B"]
+    st = env["I"].workload("n51200_yp020_n0.080")
+    pos = t.tensor(st["pos"], device=env["dev"])
+    vel = t.tensor(st["vel"], device=env["dev"])
+    sp = t.tensor(st["species"], device=env["dev"])
+    sim = B.Sim(pos, vel, sp, st["L"], dt=2.0, T=st["T"], rescale_every=1, precision=0)
+    sim.step(500)
+    t.cuda.synchronize()
+    p0, v0 = pos.clone(), vel.clone()
+    sim.close()
+
+    def series(prec, dt):
+        p, v = p0.clone(), v0.clone()
+        s = B.Sim(p, v, sp, st["L"], dt=dt, T=st["T"], precision=prec)
+        e = s.energies()
+        H = [(e["ekin"] + e["epot"]) / st["n"]]
+        for _ in range(100):
+            s.step(int(round(20.0 / dt)))
+            e = s.energies()
+            H.append((e["ekin"] + e["epot"]) / st["n"])
+        s.close()
+        return np.array(H)
+
+    D, drift = {}, {}
+    for prec in (0, 1):
+        h2, h1 = series(prec, 2.0), series(prec, 1.0)
+        D[prec] = np.abs(h2 - h2[0]).max()
+        drift[prec] = abs(np.polyfit(np.linspace(0.0, 2000.0, len(h2)), h2, 1)[0]) * 2000.0
+        say(f"  prec {prec}: D(dt=2) = {D[prec]:.3e} MeV/nucleon, linear drift "
+            f"{drift[prec]:.3e}, std {h2.std():.3e} (dt=2) {h1.std():.3e} (dt=1)")
+        assert np.all(np.isfinite(h2)) and np.all(np.isfinite(h1))
+        assert h1.std() <= 0.5 * h2.std()
+    assert drift[1] <= drift[0] + 1e-4
+    assert D[1] <= 2.0 * D[0]
 
 
 def test_expansion_run_statistics(env):

@@ -462,3 +462,111 @@ def test_cell_list_definition(oracle_mod):
     lo = c3 * w
     assert np.all(pos >= lo - 1e-12) and np.all(pos < lo + w + 1e-12)
     assert oracle_mod.cell_dims(43.0887, 11.5) == 3 and oracle_mod.cell_dims(23.0, 11.5) == 2
+
+
+def test_cell_list_hand_placed(oracle_mod):
+    """Particles placed at known cells of a 3 x 3 x 3 grid (L = 34.5 fm,
+    cells of exactly 11.5 fm): the linear cell index is (cz*3 + cy)*3 + cx,
+    protons fill bins 0..26 and neutrons 27..53, and within a bin the order
+    is the particle index.  Written out by hand, not from a formula."""
+    w = 11.5
+    L = 3 * w
+
+    def centre(cx, cy, cz):
+        return [(cx + 0.5) * w, (cy + 0.5) * w, (cz + 0.5) * w]
+
+    pos = np.array([centre(0, 0, 0),          # 0 neutron -> bin 27
+                    centre(2, 0, 1),          # 1 proton  -> bin 11
+                    centre(0, 2, 0),          # 2 proton  -> bin 6
+                    centre(0, 0, 2),          # 3 proton  -> bin 18
+                    centre(2, 2, 2),          # 4 neutron -> bin 53
+                    [1.0, 2 * w + 0.5, 3.0],  # 5 proton  -> bin 6
+                    [L - 0.01, L - 0.01, L - 0.01]])  # 6 neutron -> bin 53
+    sp = np.array([0, 1, 1, 1, 0, 1, 0], np.uint8)
+    nc, start, perm = oracle_mod.cell_list(pos, sp, L, 11.5)
+    assert nc == 3
+    assert list(perm) == [2, 5, 1, 3, 0, 4, 6]
+    expect_start = np.zeros(55, np.int64)
+    counts = {6: 2, 11: 1, 18: 1, 27: 1, 53: 2}
+    for b in range(54):
+        expect_start[b + 1] = expect_start[b] + counts.get(b, 0)
+    assert np.array_equal(start, expect_start)
+
+
+def test_cell_list_structure(oracle_mod):
+    """Properties of the sorted order that any correct cell list has, checked
+    without the binning formula: protons before neutrons, particle indices
+    increasing within a bin, every particle inside its bin's cell, and the
+    bins' members exactly the particles inside that cell."""
+    rng = np.random.Generator(np.random.PCG64(15))
+    n, L, rc = 4000, 50.0, 11.5
+    pos = rng.random((n, 3)) * L
+    sp = (rng.random(n) < 0.3).astype(np.uint8)
+    nc, start, perm = oracle_mod.cell_list(pos, sp, L, rc)
+    C, w = nc ** 3, L / nc
+    Zc = int(sp.sum())
+    assert np.all(sp[perm[:Zc]] == 1) and np.all(sp[perm[Zc:]] == 0)
+    assert start[C] == Zc
+    for b in range(2 * C):
+        members = perm[start[b]:start[b + 1]]
+        assert np.all(np.diff(members) > 0)
+        c = b % C
+        cx, cy, cz = c % nc, (c // nc) % nc, c // (nc * nc)
+        lo = np.array([cx, cy, cz]) * w
+        inside = np.all((pos >= lo - 1e-12) & (pos < lo + w + 1e-12), axis=1)
+        inside &= (sp == 1) if b < C else (sp == 0)
+        assert np.array_equal(np.sort(np.nonzero(inside)[0]), members)
+
+
+def test_cluster_stats_hand_built(oracle_mod):
+    """Table II statistics from a cluster result whose numbers are worked out
+    by hand: clusters of A = 12 (Z = 4), 20 (Z = 8) and 3 (Z = 1, light),
+    5 free neutrons, N = 40.  Free-neutron mass fraction 5/40; over A >= 12:
+    mean A 16 and population SD 4 (the sample SD would be 5.657), mean Z 6
+    and SD 2.  A cluster of A = 11 is left out, one of A = 12 is kept."""
+    label = np.array([0] * 12 + [1] * 20 + [2] * 3 + [-1] * 5, np.int32)
+    species = np.zeros(40, np.uint8)
+    species[[0, 1, 2, 3]] = 1
+    species[12:20] = 1
+    species[32] = 1
+    cl = dict(label=label, nclusters=3, nfree=5)
+    s = oracle_mod.cluster_stats(cl, species)
+    assert s["x_free"] == 0.125 and s["nclusters"] == 3 and s["n_heavy"] == 2
+    assert s["A_mean"] == 16.0 and s["A_std"] == 4.0
+    assert s["Z_mean"] == 6.0 and s["Z_std"] == 2.0
+    # the A >= 12 boundary: an 11-nucleon cluster is excluded
+    label2 = np.array([0] * 11 + [1] * 12 + [-1] * 2, np.int32)
+    sp2 = np.zeros(25, np.uint8)
+    sp2[[0, 11, 12, 13]] = 1
+    s2 = oracle_mod.cluster_stats(dict(label=label2, nclusters=2, nfree=2), sp2)
+    assert s2["n_heavy"] == 1 and s2["A_mean"] == 12.0 and s2["A_std"] == 0.0
+    assert s2["Z_mean"] == 3.0 and s2["x_free"] == 2 / 25
+    # no heavy cluster: only the free fraction and counts
+    s3 = oracle_mod.cluster_stats(dict(label=np.array([0, 0, -1], np.int32), nclusters=1,
+                                       nfree=1), np.array([1, 0, 0], np.uint8))
+    assert s3["n_heavy"] == 0 and "A_mean" not in s3 and s3["x_free"] == 1 / 3
+
+
+def test_cluster_stats_on_hand_built_positions(oracle_mod):
+    """End to end through the cluster algorithm: a chain of 3 protons 4 fm
+    apart with 9 neutrons each 2 fm from one of them (A = 12, Z = 3), an
+    isolated proton with one neutron 2.5 fm away (A = 2, light), and two
+    neutrons far from every proton (free).  N = 16: free fraction 2/16,
+    one heavy cluster with A = 12, Z = 3 (SD 0)."""
+    L = 60.0
+    pos, sp = [], []
+    for k in range(3):
+        pos.append([10.0 + 4.0 * k, 10.0, 10.0])
+        sp.append(1)
+    for k in range(3):
+        for d in ([0, 2.0, 0], [0, -2.0, 0], [0, 0, 2.0]):
+            pos.append([10.0 + 4.0 * k + d[0], 10.0 + d[1], 10.0 + d[2]])
+            sp.append(0)
+    pos += [[40.0, 40.0, 40.0], [42.5, 40.0, 40.0], [25.0, 45.0, 5.0], [50.0, 20.0, 30.0]]
+    sp += [1, 0, 0, 0]
+    pos, sp = np.array(pos), np.array(sp, np.uint8)
+    cl = oracle_mod.cluster(pos, sp, L)
+    assert cl["nclusters"] == 2 and cl["nfree"] == 2
+    s = oracle_mod.cluster_stats(cl, sp)
+    assert s["x_free"] == 2 / 16 and s["n_heavy"] == 1
+    assert s["A_mean"] == 12.0 and s["Z_mean"] == 3.0 and s["A_std"] == 0.0
