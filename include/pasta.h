@@ -199,6 +199,26 @@ int pasta_forces(const pasta_potential* pot, int32_t precision, int32_t terms, i
                  double L, const double* d_pos, const uint8_t* d_species, double* d_force,
                  double* d_epot, void* d_work, size_t work_bytes, void* stream);
 
+/* ------------------------------------------- forces without allocation --
+ * For callers that cannot allocate device memory (tight serving loops,
+ * harnesses that forbid hipMalloc, code that must not grow its footprint):
+ * the same force evaluation as pasta_forces, with the same arguments minus
+ * the workspace.  Its scratch memory is a static device array of
+ * PASTA_NOALLOC_SCRATCH_BYTES inside the library, which each device the
+ * library runs on holds until the process ends; the call itself allocates
+ * nothing.  The array's device address is looked up on the first call on
+ * each device.  Returns PASTA_EWORKSPACE, without touching the outputs, when
+ * the workspace pasta_forces_workspace reports for these arguments (under
+ * the current tuning) exceeds PASTA_NOALLOC_SCRATCH_BYTES.  Every call on a
+ * device shares that device's array: calls that overlap in time on one
+ * device (several host threads or streams) race and corrupt each other's
+ * results, so serialise them.  Like pasta_forces, it synchronises the
+ * stream once (to size the Coulomb launch). */
+#define PASTA_NOALLOC_SCRATCH_BYTES ((size_t)32 << 20)
+int pasta_forces_noalloc(const pasta_potential* pot, int32_t precision, int32_t terms,
+                         int64_t n, double L, const double* d_pos, const uint8_t* d_species,
+                         double* d_force, double* d_epot, void* stream);
+
 /* ------------------------------------------------------------------ a4 --
  * Simulation handle: velocity Verlet in an expanding periodic box.
  * Step n -> n+1 (global step index n):

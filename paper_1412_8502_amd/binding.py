@@ -79,6 +79,7 @@ def _load():
         "pasta_cell_list": (ctypes.c_int, [i64, d, d, vp, vp, vp, vp, P(i32), vp, sz, vp]),
         "pasta_forces_workspace": (ctypes.c_int, [pot, i32, i64, d, P(sz)]),
         "pasta_forces": (ctypes.c_int, [pot, i32, i32, i64, d, vp, vp, vp, vp, vp, sz, vp]),
+        "pasta_forces_noalloc": (ctypes.c_int, [pot, i32, i32, i64, d, vp, vp, vp, vp, vp]),
         "pasta_sim_workspace": (ctypes.c_int, [pot, integ, i32, i64, d, d, P(sz)]),
         "pasta_sim_create": (ctypes.c_int, [pot, integ, i32, i64, d, i64, d, vp, vp, vp, vp,
                                             sz, vp, P(vp)]),
@@ -233,6 +234,24 @@ def pasta_forces(pos, species, L: float, precision: int = PASTA_FP64,
     epot = torch.empty(n, dtype=torch.float64, device=pos.device)
     _check(lib.pasta_forces(ctypes.byref(pot), precision, terms, n, L, _p(pos), _p(species),
                             _p(force), _p(epot), _p(work), work.numel(), _stream(stream)))
+    return force, epot
+
+
+def pasta_forces_noalloc(pos, species, L: float, force, epot=None,
+                         precision: int = PASTA_FP64, terms: int = PASTA_TERM_ALL,
+                         pot: pasta_potential | None = None, stream=None):
+    """pasta_forces into caller tensors (force float64 [n, 3], epot float64
+    [n] or None) with the library's static scratch: no workspace."""
+    _check_state(pos, species)
+    pot = pot or pasta_potential_paper()
+    n = pos.shape[0]
+    for t, shape in ((force, (n, 3)), (epot, (n,))):
+        if t is not None and (t.shape != shape or t.dtype != torch.float64 or
+                              not t.is_contiguous() or t.device != pos.device):
+            raise ValueError("force / epot must be contiguous float64 tensors on pos's device")
+    _check(lib.pasta_forces_noalloc(ctypes.byref(pot), precision, terms, n, L, _p(pos),
+                                    _p(species), _p(force), _p(epot),
+                                    _stream(stream)))
     return force, epot
 
 

@@ -4,6 +4,7 @@
 #include <cstdarg>
 #include <cstdio>
 #include <cstring>
+#include <mutex>
 #include <new>
 #include <vector>
 
@@ -390,38 +391,46 @@ extern "C" int pasta_forces_workspace(const pasta_potential* pot, int32_t precis
     return PASTA_OK;
 }
 
-extern "C" int pasta_forces(const pasta_potential* pot, int32_t precision, int32_t terms,
-                            int64_t n, double L, const double* d_pos, const uint8_t* d_species,
-                            double* d_force, double* d_epot, void* d_work, size_t work_bytes,
-                            void* stream)
+namespace pasta {
+
+// Argument checks shared by pasta_forces and pasta_forces_noalloc.
+static int check_force_args(const char* who, const pasta_potential* pot, int32_t precision,
+                            int32_t terms, int64_t n, double L, const double* d_pos,
+                            const uint8_t* d_species, const double* d_force)
 {
     PASTA_TRY(check_pot(pot));
     if (n < 0 || n > INT32_MAX - 1 || (n > 0 && (!d_pos || !d_species || !d_force)) ||
         !(L > 0.0) || !std::isfinite(L) || (terms & ~PASTA_TERM_ALL) ||
         (precision != PASTA_FP64 && precision != PASTA_MIXED))
-        return fail(PASTA_EINVAL, "pasta_forces: bad argument");
+        return fail(PASTA_EINVAL, "%s: bad argument", who);
     if (L < 2.0 * pot->r_nuc)
-        return fail(PASTA_EBOX, "pasta_forces: L = %g < 2 r_nuc = %g", L, 2.0 * pot->r_nuc);
-    size_t need = 0;
-    PASTA_TRY(pasta_forces_workspace(pot, precision, n, L, &need));
-    PASTA_TRY(check_work(d_work, work_bytes, need, "pasta_forces"));
+        return fail(PASTA_EBOX, "%s: L = %g < 2 r_nuc = %g", who, L, 2.0 * pot->r_nuc);
+    return PASTA_OK;
+}
+
+// One force evaluation on a checked workspace: cell list, pair kernels,
+// device error word.  Clears what must start at zero with fill kernels.
+static int forces_run(const char* who, const pasta_potential* pot, int32_t precision,
+                      int32_t terms, int64_t n, double L, const double* d_pos,
+                      const uint8_t* d_species, double* d_force, double* d_epot, void* d_work,
+                      size_t work_bytes, hipStream_t s)
+{
     if (n == 0)
         return PASTA_OK;
-    hipStream_t s = static_cast<hipStream_t>(stream);
     // a call without the nuclear terms uses the cell-sweep layout, which is
     // smaller than the list layout the workspace query may have sized
     const ListCfg lc = list_cfg(terms, L);
     const Grid g = make_grid(L, cell_cut(pot, lc), CELL_SUB);
     Carver cv0(nullptr);
     PASTA_TRY(check_work(d_work, work_bytes, force_carve(cv0, nullptr, n, g.C, precision, pot, lc),
-                         "pasta_forces"));
+                         who));
     ForceWork w;
     Carver cv(d_work);
     force_carve(cv, &w, n, g.C, precision, pot, lc);
     const PairParams pp = pair_params(pot, L);
-    PASTA_HIP(hipMemsetAsync(w.err, 0, sizeof(uint32_t), s));
+    launch_zero_words(w.err, 1, s);
     if (w.lists)
-        PASTA_HIP(hipMemsetAsync(w.lb.ctl, 0, sizeof(ListCtl), s));
+        launch_zero_words(w.lb.ctl, (int64_t)(sizeof(ListCtl) / sizeof(uint32_t)), s);
     cellbuf_zero(w.cb, g.C, s, g.sub);
     build_cells(d_pos, d_species, n, g, w, precision, pp, s, nullptr);
     int32_t Z = 0;
@@ -431,7 +440,80 @@ extern "C" int pasta_forces(const pasta_potential* pot, int32_t precision, int32
     KickArgs kick{nullptr, 0.0, pot->mass, nullptr, false};
     eval_forces(precision, terms, w, g, n, Z, pp, d_force, d_epot, kick, nullptr, s, nullptr);
     PASTA_HIP(hipGetLastError());
-    return read_err(w.err, s, "pasta_forces");
+    return read_err(w.err, s, who);
+}
+
+}  // namespace pasta
+
+extern "C" int pasta_forces(const pasta_potential* pot, int32_t precision, int32_t terms,
+                            int64_t n, double L, const double* d_pos, const uint8_t* d_species,
+                            double* d_force, double* d_epot, void* d_work, size_t work_bytes,
+                            void* stream)
+{
+    PASTA_TRY(check_force_args("pasta_forces", pot, precision, terms, n, L, d_pos, d_species,
+                               d_force));
+    size_t need = 0;
+    PASTA_TRY(pasta_forces_workspace(pot, precision, n, L, &need));
+    PASTA_TRY(check_work(d_work, work_bytes, need, "pasta_forces"));
+    return forces_run("pasta_forces", pot, precision, terms, n, L, d_pos, d_species, d_force,
+                      d_epot, d_work, work_bytes, static_cast<hipStream_t>(stream));
+}
+
+// -------------------------------------------------- forces without allocation
+// The scratch memory of pasta_forces_noalloc: one static device array, which
+// every device the library runs on holds until the process ends.  In host
+// code `scratch` names a host-side stand-in, never the device memory: its
+// device address is taken once per device with hipGetSymbolAddress (with
+// that device current) and only that address is passed to kernels.
+static __device__ __align__(256) unsigned char scratch[PASTA_NOALLOC_SCRATCH_BYTES];
+
+namespace pasta {
+namespace {
+constexpr int SCRATCH_MAX_DEVICES = 64;
+std::mutex g_scratch_mu;
+void* g_scratch_dev[SCRATCH_MAX_DEVICES] = {};
+
+int scratch_address(void** out)
+{
+    int dev = 0;
+    PASTA_HIP(hipGetDevice(&dev));
+    if (dev < 0 || dev >= SCRATCH_MAX_DEVICES)
+        return fail(PASTA_EINVAL, "pasta_forces_noalloc: device %d beyond %d", dev,
+                    SCRATCH_MAX_DEVICES);
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    if (!g_scratch_dev[dev]) {
+        void* p = nullptr;
+        const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+        if (e != hipSuccess || !p)
+            return fail(PASTA_EHIP, "hipGetSymbolAddress(scratch) on device %d: %s", dev,
+                        hipGetErrorString(e));
+        g_scratch_dev[dev] = p;
+    }
+    *out = g_scratch_dev[dev];
+    return PASTA_OK;
+}
+}  // namespace
+}  // namespace pasta
+
+extern "C" int pasta_forces_noalloc(const pasta_potential* pot, int32_t precision,
+                                    int32_t terms, int64_t n, double L, const double* d_pos,
+                                    const uint8_t* d_species, double* d_force, double* d_epot,
+                                    void* stream)
+{
+    PASTA_TRY(check_force_args("pasta_forces_noalloc", pot, precision, terms, n, L, d_pos,
+                               d_species, d_force));
+    size_t need = 0;
+    PASTA_TRY(pasta_forces_workspace(pot, precision, n, L, &need));
+    if (need > PASTA_NOALLOC_SCRATCH_BYTES)
+        return fail(PASTA_EWORKSPACE,
+                    "pasta_forces_noalloc: n = %lld at L = %g needs %zu bytes of scratch, "
+                    "more than the static %zu",
+                    (long long)n, L, need, (size_t)PASTA_NOALLOC_SCRATCH_BYTES);
+    void* work = nullptr;
+    PASTA_TRY(scratch_address(&work));
+    return forces_run("pasta_forces_noalloc", pot, precision, terms, n, L, d_pos, d_species,
+                      d_force, d_epot, work, PASTA_NOALLOC_SCRATCH_BYTES,
+                      static_cast<hipStream_t>(stream));
 }
 
 // -------------------------------------------------------------- tuning

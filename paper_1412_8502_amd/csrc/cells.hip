@@ -339,6 +339,13 @@ __global__ __launch_bounds__(256) void k_export(const int32_t* __restrict__ id, 
         dst1[i] = src1[k];
 }
 
+__global__ void k_zero_words(uint32_t* a, int64_t m)
+{
+    const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (k < m)
+        a[k] = 0u;
+}
+
 __global__ void k_zero2(int32_t* a, int32_t* b, int64_t m)
 {
     int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
@@ -369,6 +376,12 @@ size_t cellbuf_carve(Carver& cv, CellBuf* out, int64_t n, int C_max, int chunk, 
     if (out)
         *out = cb;
     return cv.size();
+}
+
+void launch_zero_words(void* p, int64_t nwords, hipStream_t s)
+{
+    if (nwords > 0)
+        k_zero_words<<<blocks_for(nwords, 256), 256, 0, s>>>(static_cast<uint32_t*>(p), nwords);
 }
 
 void cellbuf_zero(const CellBuf& cb, int C_max, hipStream_t s, int sub)

@@ -314,6 +314,9 @@ struct CellBuf {
 // C_max: the largest cell count; sub: bins per cell and species.
 size_t cellbuf_carve(Carver& cv, CellBuf* out, int64_t n, int C_max, int chunk, int sub = 1);
 void cellbuf_zero(const CellBuf& cb, int C_max, hipStream_t s, int sub = 1);
+// Zero nwords 32-bit words at p with a fill kernel (no memset node, so the
+// call may sit in a captured stream).
+void launch_zero_words(void* p, int64_t nwords, hipStream_t s);
 
 // Bins + counts from positions (caller order); the drift kernel does the
 // same inside the integrator.
