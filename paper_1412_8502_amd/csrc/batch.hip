@@ -67,7 +67,7 @@ struct BatchDev {
     int32_t* items;
     int32_t* n_items;
     void* stg;            // Q4 or double4 per sorted slot
-    double4* coul_part;
+    void* coul_part;      // Coulomb partials, typename P::CPart per entry
     double4* fnuc;
     double* ke_chunk;
     double* pending;      // per-system velocity scale pending from the thermostat
@@ -417,8 +417,10 @@ __device__ void phase_forces(const BatchDev& B, int64_t step, int mode, char* ld
             const int64_t local = it - S.coul_item_off;
             const int tblock = (int)(local % S.coul_blocks), split = (int)(local / S.coul_blocks);
             const CoulConsts k = B.ck[s];
-            coulomb_item<P, M != MODE_FORCE>(stg + S.off, S.Z, S.per_split, k,
-                                             B.coul_part + S.coul_off, tblock, split, lds);
+            using PT = typename P::CPart;
+            coulomb_item<P, M != MODE_FORCE, PT>(stg + S.off, S.Z, S.per_split, k,
+                                                 static_cast<PT*>(B.coul_part) + S.coul_off,
+                                                 tblock, split, lds);
         } else {
             const int64_t jt = it - B.coul_items;
             int s = 0;
@@ -453,8 +455,14 @@ __device__ void phase_forces(const BatchDev& B, int64_t step, int mode, char* ld
 }
 
 // energy: the pair phase accumulated energies; write the shares.
+// The Coulomb partials of a proton are summed in split order from zero and
+// the sum is added to the nuclear part, the association of the
+// single-system path (so a system gets the same bits either way).
+template <class P>
 __device__ void phase_combine(const BatchDev& B, int mode, bool energy, char* lds_raw)
 {
+    using PT = typename P::CPart;
+    const PT* part = static_cast<const PT*>(B.coul_part);
     double* red = reinterpret_cast<double*>(lds_raw);
     for (int64_t g = blockIdx.x; g < B.total_chunks; g += gridDim.x) {
         const int s = find_sys_chunk(B, g);
@@ -465,13 +473,18 @@ __device__ void phase_combine(const BatchDev& B, int mode, bool energy, char* ld
             const double4 fn = B.fnuc[S.off + sl];
             double Fx = fn.x, Fy = fn.y, Fz = fn.z, V = fn.w;
             if (sl < S.Z) {
+                double cx = 0.0, cy = 0.0, cz = 0.0, cw = 0.0;
                 for (int k = 0; k < S.S; ++k) {
-                    const double4 cp = B.coul_part[S.coul_off + (int64_t)k * S.Z + sl];
-                    Fx += cp.x;
-                    Fy += cp.y;
-                    Fz += cp.z;
-                    V += cp.w;
+                    const PT cp = part[S.coul_off + (int64_t)k * S.Z + sl];
+                    cx += (double)cp.x;
+                    cy += (double)cp.y;
+                    cz += (double)cp.z;
+                    cw += (double)cp.w;
                 }
+                Fx += cx;
+                Fy += cy;
+                Fz += cz;
+                V += cw;
             }
             const int64_t i = S.off + B.perm[S.off + sl];
             B.force[3 * i + 0] = Fx;
@@ -565,7 +578,7 @@ __global__ __launch_bounds__(BW) void k_batch_step(BatchDev B, int mode)
     phase_forces<P, M, V>(B, step, mode, lds, &s_item);
     if (!grid_sync(B, &s_flag))
         return;
-    phase_combine(B, mode, M != MODE_FORCE, lds);
+    phase_combine<P>(B, mode, M != MODE_FORCE, lds);
     if (!grid_sync(B, &s_flag))
         return;
     phase_thermostat(B, step, mode, lds);
@@ -624,10 +637,11 @@ void launch_pair_phase(const BatchDev& dev, int precision, unsigned g, hipStream
             k_ph_forces<MixedPolicy, M, V><<<g, BW, 0, s>>>(dev, 0);
     });
 }
+template <class P>
 __global__ __launch_bounds__(BW) void k_ph_combine(BatchDev B, int mode, int energy)
 {
     __shared__ __align__(16) char lds[64];
-    phase_combine(B, mode, energy != 0, lds);
+    phase_combine<P>(B, mode, energy != 0, lds);
 }
 __global__ __launch_bounds__(BW) void k_ph_thermostat(BatchDev B, int mode)
 {
@@ -857,7 +871,10 @@ size_t batch_carve(Carver& cv, const BatchLayout& lay, int nsys, int precision, 
     b.items = cv.take<int32_t>(2 * lay.items);
     b.n_items = cv.take<int32_t>(nsys);
     b.stg = precision == PASTA_FP64 ? (void*)cv.take<double4>(N) : (void*)cv.take<Q4>(N);
-    b.coul_part = cv.take<double4>(lay.coul);
+    if (precision == PASTA_FP64)
+        b.coul_part = cv.take<double4>(lay.coul);
+    else
+        b.coul_part = cv.take<float4>(lay.coul);
     b.fnuc = cv.take<double4>(N);
     b.ke_chunk = cv.take<double>(lay.total_chunks);
     b.pending = cv.take<double>(nsys);
@@ -902,7 +919,7 @@ int launch_step(pasta_batch* bt, int mode)
             else
                 k_ph_forces<P, MODE_ENERGY, V><<<g, BW, 0, s>>>(bt->dev, mode);
         });
-        k_ph_combine<<<g, BW, 0, s>>>(bt->dev, mode, mode ? 0 : 1);
+        k_ph_combine<P><<<g, BW, 0, s>>>(bt->dev, mode, mode ? 0 : 1);
         k_ph_thermostat<<<(unsigned)bt->nsys, BW, 0, s>>>(bt->dev, mode);
         if (mode)
             k_ph_advance<<<1, 64, 0, s>>>(bt->dev);
@@ -1197,7 +1214,10 @@ static int batch_refresh_energies(pasta_batch* bt)
     k_batch_zero_pairs<<<1, 1024, 0, s>>>(bt->dev);
     const unsigned g = bt->phase_grid;
     launch_pair_phase<MODE_ENERGY>(bt->dev, bt->precision, g, s);
-    k_ph_combine<<<g, BW, 0, s>>>(bt->dev, 0, 1);
+    if (bt->precision == PASTA_FP64)
+        k_ph_combine<Fp64Policy><<<g, BW, 0, s>>>(bt->dev, 0, 1);
+    else
+        k_ph_combine<MixedPolicy><<<g, BW, 0, s>>>(bt->dev, 0, 1);
     PASTA_HIP(hipGetLastError());
     bt->epot_valid = true;
     return PASTA_OK;

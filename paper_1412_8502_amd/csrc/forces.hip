@@ -32,20 +32,21 @@ namespace {
 
 template <class P, bool E>
 __global__ __launch_bounds__(WG) void k_coulomb(const typename P::Src* __restrict__ stg, int Z,
-                                                int per_split, CoulConsts k,
-                                                double4* __restrict__ part)
+                                                int per_split, CoulConsts k, void* part)
 {
     __shared__ __align__(16) char lds[coulomb_lds_bytes<P>()];
-    coulomb_item<P, E>(stg, Z, per_split, k, part, blockIdx.x, blockIdx.y, lds);
+    using PT = typename P::CPart;
+    coulomb_item<P, E, PT>(stg, Z, per_split, k, static_cast<PT*>(part), blockIdx.x, blockIdx.y,
+                           lds);
 }
 
 template <class P, bool E>
 __global__ __launch_bounds__(WG) void k_coulomb_pair(const typename P::Src* __restrict__ stg,
-                                                     int Z, CoulConsts k,
-                                                     double4* __restrict__ part)
+                                                     int Z, CoulConsts k, void* part)
 {
     __shared__ __align__(16) char lds[coulomb_pair_lds_bytes<P>()];
-    coulomb_pair_item<P, E>(stg, Z, k, part, blockIdx.x, lds);
+    using PT = typename P::CPart;
+    coulomb_pair_item<P, E, PT>(stg, Z, k, static_cast<PT*>(part), blockIdx.x, lds);
 }
 
 template <class P, bool NUC, int MODE>
@@ -131,10 +132,11 @@ __global__ __launch_bounds__(WG) void k_forces_fused(const typename P::Src* __re
                                                      NucArgs A, const int32_t* __restrict__ n_items,
                                                      int item_max, NucConsts k, int Z,
                                                      int per_split, int coul_blocks,
-                                                     CoulConsts kc, double4* __restrict__ part,
-                                                     ListArgs LA)
+                                                     CoulConsts kc, void* part_raw, ListArgs LA)
 {
     __shared__ __align__(16) char lds[fused_lds_bytes<P, V>()];
+    using PT = typename P::CPart;
+    PT* part = static_cast<PT*>(part_raw);
     const int g = blockIdx.x;
     if (g < item_max) {
         if (g >= *n_items)
@@ -150,10 +152,10 @@ __global__ __launch_bounds__(WG) void k_forces_fused(const typename P::Src* __re
     } else {
         const int h = g - item_max;
         if constexpr (CF == 1)
-            coulomb_pair_item<P, MODE != MODE_FORCE>(stg, Z, kc, part, h, lds);
+            coulomb_pair_item<P, MODE != MODE_FORCE, PT>(stg, Z, kc, part, h, lds);
         else
-            coulomb_item<P, MODE != MODE_FORCE>(stg, Z, per_split, kc, part, h % coul_blocks,
-                                                h / coul_blocks, lds);
+            coulomb_item<P, MODE != MODE_FORCE, PT>(stg, Z, per_split, kc, part, h % coul_blocks,
+                                                    h / coul_blocks, lds);
     }
 }
 
@@ -162,45 +164,74 @@ __global__ __launch_bounds__(WG) void k_forces_fused(const typename P::Src* __re
 // energy.  With has_next (sorted order): then also the next step's half
 // kick, drift and binning of the slot (nd), which the drift kernel would
 // otherwise do at the start of the next step.
+// Blocks [0, zb) take the protons, COMB_LANES lanes per proton: lane q adds
+// the partials s = q, q + COMB_LANES, ... in order, the lanes then combine
+// by a fixed shuffle tree and the first lane does the per-slot work (so a
+// proton's S partial loads are spread over several lanes, all in flight).
+// Blocks [zb, ...) take the neutrons, one lane each.
+constexpr int COMB_LANES = 4;
+__host__ __device__ inline int64_t combine_proton_blocks(int64_t Z)
+{
+    return (Z * COMB_LANES + WG - 1) / WG;
+}
+
+template <class PT>
 __global__ __launch_bounds__(WG) void k_combine(const double4* __restrict__ fnuc,
-                                                const double4* __restrict__ part, int S, int Z,
-                                                const int32_t* __restrict__ perm, int64_t n,
-                                                double* __restrict__ force,
+                                                const PT* __restrict__ part, int S, int Z,
+                                                int zb, const int32_t* __restrict__ perm,
+                                                int64_t n, double* __restrict__ force,
                                                 double* __restrict__ epot, double* vel, double hdtm,
                                                 double mass, double* __restrict__ ke_part,
                                                 int32_t* __restrict__ n_ke, uint32_t* err,
                                                 NextDrift nd, int has_next)
 {
     __shared__ double red[WG / 64];
-    const int64_t sl = (int64_t)blockIdx.x * WG + threadIdx.x;
-    double ke = 0.0;
-    if (sl < n) {
-        const double4 fn = fnuc[sl];
-        double Fx = fn.x, Fy = fn.y, Fz = fn.z, V = fn.w;
+    int64_t sl;
+    bool lead;
+    double cx = 0.0, cy = 0.0, cz = 0.0, cw = 0.0;
+    if ((int)blockIdx.x < zb) {
+        const int64_t t = (int64_t)blockIdx.x * WG + threadIdx.x;
+        sl = t / COMB_LANES;
+        const int q = (int)(t % COMB_LANES);
         if (sl < Z) {
-            // eight partials in flight; summed in split order
-            int k = 0;
-            for (; k + 8 <= S; k += 8) {
-                double4 cp[8];
+            int s = q;
+            for (; s + 3 * COMB_LANES < S; s += 4 * COMB_LANES) {
+                PT v[4];
 #pragma unroll
-                for (int u = 0; u < 8; ++u)
-                    cp[u] = part[(int64_t)(k + u) * Z + sl];
+                for (int u = 0; u < 4; ++u)
+                    v[u] = part[(int64_t)(s + u * COMB_LANES) * Z + sl];
 #pragma unroll
-                for (int u = 0; u < 8; ++u) {
-                    Fx += cp[u].x;
-                    Fy += cp[u].y;
-                    Fz += cp[u].z;
-                    V += cp[u].w;
+                for (int u = 0; u < 4; ++u) {
+                    cx += (double)v[u].x;
+                    cy += (double)v[u].y;
+                    cz += (double)v[u].z;
+                    cw += (double)v[u].w;
                 }
             }
-            for (; k < S; ++k) {
-                const double4 cp = part[(int64_t)k * Z + sl];
-                Fx += cp.x;
-                Fy += cp.y;
-                Fz += cp.z;
-                V += cp.w;
+            for (; s < S; s += COMB_LANES) {
+                const PT v = part[(int64_t)s * Z + sl];
+                cx += (double)v.x;
+                cy += (double)v.y;
+                cz += (double)v.z;
+                cw += (double)v.w;
             }
         }
+#pragma unroll
+        for (int m = 1; m < COMB_LANES; m <<= 1) {
+            cx += __shfl_xor(cx, m, COMB_LANES);
+            cy += __shfl_xor(cy, m, COMB_LANES);
+            cz += __shfl_xor(cz, m, COMB_LANES);
+            cw += __shfl_xor(cw, m, COMB_LANES);
+        }
+        lead = q == 0 && sl < Z;
+    } else {
+        sl = (int64_t)Z + (int64_t)(blockIdx.x - zb) * WG + threadIdx.x;
+        lead = sl < n;
+    }
+    double ke = 0.0;
+    if (lead) {
+        const double4 fn = fnuc[sl];
+        const double Fx = fn.x + cx, Fy = fn.y + cy, Fz = fn.z + cz, V = fn.w + cw;
         const int64_t id = perm ? perm[sl] : sl;
         force[3 * id + 0] = Fx;
         force[3 * id + 1] = Fy;
@@ -347,15 +378,15 @@ void launch_list_build(int precision, const ForceBuf& fb, const CellBuf& cb, con
     timer_end(t, KC_LIST, s);
 }
 
-int coulomb_splits(int64_t Z)
+int coulomb_splits(int64_t Z, int64_t cap)
 {
     if (Z <= 0)
         return 0;
     const int req = g_tuning.coulomb_splits;
     int64_t s = req > 0 ? req : 524288 / Z;
     s = s < 1 ? 1 : (s > 32 ? 32 : s);
-    // the partial-sum buffer holds max(min(32 n, 2^19), n) entries, n >= Z
-    while (s > 1 && s * Z > 524288)
+    // the partial-sum buffer holds cap >= n >= Z entries
+    while (s > 1 && s * Z > cap)
         --s;
     return (int)s;
 }
@@ -371,9 +402,21 @@ CoulPlan coulomb_plan(int64_t Z, int64_t coul_max)
         p.form = 1;
         p.S = coulomb_pair_supers(Z);
     } else {
-        p.S = coulomb_splits(Z);
+        p.S = coulomb_splits(Z, coul_max);
     }
     return p;
+}
+
+int64_t coulomb_partial_capacity(int64_t n)
+{
+    // the gather form's default splits (about 2^19 partials), and the
+    // pairwise form's ceil(Z / 256) partials per proton for Z up to 0.4 n
+    // (the largest proton fraction of the paper's runs)
+    const int64_t zd = (int64_t)std::ceil(0.4 * (double)n);
+    int64_t cap = 32 * n < 524288 ? 32 * n : 524288;
+    const int64_t pair = (int64_t)coulomb_pair_supers(zd) * zd;
+    cap = pair > cap ? pair : cap;
+    return cap > n ? cap : n;
 }
 
 pasta_tuning g_tuning = {1, 0, 1, 0, 2.0, 1.0};  // coulomb_form 0: gather
@@ -442,10 +485,22 @@ void launch_forces_fused(int precision, const ForceBuf& fb, const CellBuf& cb, c
     }
     timer_end(t, KC_NUCLEAR, s);
     timer_begin(t, KC_COMBINE, s);
-    k_combine<<<(unsigned)((n + WG - 1) / WG), WG, 0, s>>>(
-        fb.fnuc, fb.coul_part, S, (int)Z, kick.slot_order ? nullptr : cb.perm, n, force, epot,
-        kick.vel, kick.hdtm, kick.mass, kick.ke_part, fb.n_ke, err,
-        kick.next ? *kick.next : NextDrift{}, kick.next ? 1 : 0);
+    {
+        // protons (COMB_LANES lanes each) then neutrons (one lane each)
+        const int zb = (int)combine_proton_blocks(Z);
+        const unsigned cgrid = (unsigned)(zb + (n - Z + WG - 1) / WG);
+        const NextDrift nd = kick.next ? *kick.next : NextDrift{};
+        auto comb = [&](auto* part) {
+            k_combine<<<cgrid, WG, 0, s>>>(fb.fnuc, part, S, (int)Z, zb,
+                                           kick.slot_order ? nullptr : cb.perm, n, force, epot,
+                                           kick.vel, kick.hdtm, kick.mass, kick.ke_part, fb.n_ke,
+                                           err, nd, kick.next ? 1 : 0);
+        };
+        if (precision == PASTA_FP64)
+            comb(static_cast<const double4*>(fb.coul_part));
+        else
+            comb(static_cast<const float4*>(fb.coul_part));
+    }
     timer_end(t, KC_COMBINE, s);
 }
 
@@ -454,10 +509,16 @@ size_t forcebuf_carve(Carver& cv, ForceBuf* out, int64_t n, int64_t item_max, in
     ForceBuf fb;
     fb.stg64 = precision == PASTA_FP64 ? cv.take<double4>(n) : nullptr;
     fb.stgq = precision == PASTA_MIXED ? cv.take<Q4>(n) : nullptr;
-    int64_t cm = 32 * n < 524288 ? 32 * n : 524288;
-    fb.coul_max = cm > n ? cm : n;
-    fb.coul_part = cv.take<double4>(fb.coul_max);
-    fb.ke_part = cv.take<double>(item_max > (n + WG - 1) / WG ? item_max : (n + WG - 1) / WG);
+    fb.coul_max = coulomb_partial_capacity(n);
+    if (precision == PASTA_FP64)
+        fb.coul_part = cv.take<double4>(fb.coul_max);
+    else
+        fb.coul_part = cv.take<float4>(fb.coul_max);
+
+    // per-block kinetic energies: one per nuclear item (unfused kick) or per
+    // combine block (at most n / 64 + 2 with four lanes per proton)
+    const int64_t comb_blocks = n / 64 + 2;
+    fb.ke_part = cv.take<double>(item_max > comb_blocks ? item_max : comb_blocks);
     fb.n_ke = cv.take<int32_t>(1);
     fb.fnuc = cv.take<double4>(n);
     fb.pairs = cv.take<uint64_t>(2);
@@ -475,19 +536,20 @@ int launch_coulomb(int precision, const ForceBuf& fb, int64_t Z, const PairParam
     const int S = plan.S;
     const int per = (int)((Z + S - 1) / S);
     const CoulConsts k = make_coul_consts(pp);
+    void* co = fb.coul_part;
     timer_begin(t, KC_COULOMB, s);
     if (plan.form == 1) {
         const unsigned g1 = (unsigned)coulomb_pair_items(Z);
         if (precision == PASTA_FP64) {
             if (energy)
-                k_coulomb_pair<Fp64Policy, true><<<g1, WG, 0, s>>>(fb.stg64, (int)Z, k, fb.coul_part);
+                k_coulomb_pair<Fp64Policy, true><<<g1, WG, 0, s>>>(fb.stg64, (int)Z, k, co);
             else
-                k_coulomb_pair<Fp64Policy, false><<<g1, WG, 0, s>>>(fb.stg64, (int)Z, k, fb.coul_part);
+                k_coulomb_pair<Fp64Policy, false><<<g1, WG, 0, s>>>(fb.stg64, (int)Z, k, co);
         } else {
             if (energy)
-                k_coulomb_pair<MixedPolicy, true><<<g1, WG, 0, s>>>(fb.stgq, (int)Z, k, fb.coul_part);
+                k_coulomb_pair<MixedPolicy, true><<<g1, WG, 0, s>>>(fb.stgq, (int)Z, k, co);
             else
-                k_coulomb_pair<MixedPolicy, false><<<g1, WG, 0, s>>>(fb.stgq, (int)Z, k, fb.coul_part);
+                k_coulomb_pair<MixedPolicy, false><<<g1, WG, 0, s>>>(fb.stgq, (int)Z, k, co);
         }
         timer_end(t, KC_COULOMB, s);
         return S;
@@ -495,14 +557,14 @@ int launch_coulomb(int precision, const ForceBuf& fb, int64_t Z, const PairParam
     dim3 grid((unsigned)((Z + WG - 1) / WG), (unsigned)S);
     if (precision == PASTA_FP64) {
         if (energy)
-            k_coulomb<Fp64Policy, true><<<grid, WG, 0, s>>>(fb.stg64, (int)Z, per, k, fb.coul_part);
+            k_coulomb<Fp64Policy, true><<<grid, WG, 0, s>>>(fb.stg64, (int)Z, per, k, co);
         else
-            k_coulomb<Fp64Policy, false><<<grid, WG, 0, s>>>(fb.stg64, (int)Z, per, k, fb.coul_part);
+            k_coulomb<Fp64Policy, false><<<grid, WG, 0, s>>>(fb.stg64, (int)Z, per, k, co);
     } else {
         if (energy)
-            k_coulomb<MixedPolicy, true><<<grid, WG, 0, s>>>(fb.stgq, (int)Z, per, k, fb.coul_part);
+            k_coulomb<MixedPolicy, true><<<grid, WG, 0, s>>>(fb.stgq, (int)Z, per, k, co);
         else
-            k_coulomb<MixedPolicy, false><<<grid, WG, 0, s>>>(fb.stgq, (int)Z, per, k, fb.coul_part);
+            k_coulomb<MixedPolicy, false><<<grid, WG, 0, s>>>(fb.stgq, (int)Z, per, k, co);
     }
     timer_end(t, KC_COULOMB, s);
     return S;

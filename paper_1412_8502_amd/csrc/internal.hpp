@@ -395,14 +395,17 @@ struct NextDrift {
 struct ForceBuf {
     double4* stg64;     // [n] FP64 staging (sorted)
     Q4* stgq;           // [n] fixed-point staging (sorted)
-    double4* coul_part; // [coul_max] partial Coulomb sums (fx, fy, fz, V)
-    int64_t coul_max;
+    void* coul_part;    // [coul_max] partial Coulomb sums (fx, fy, fz, V): double4
+                        // (FP64) or float4 (mixed)
+    int64_t coul_max;   // capacity in partials
     double* ke_part;    // [item_max] kinetic-energy partials of the last kick
     int32_t* n_ke;      // [1] number of valid ke_part entries (fused form)
     double4* fnuc;      // [n] nuclear (F, V) per sorted slot (fused form)
     uint64_t* pairs;    // [2] diagnostic pair counters
 };
-int coulomb_splits(int64_t Z);
+// Automatic source splits of the gather form (about 2^19 / Z, at most 32,
+// at most cap / Z); the tuning's coulomb_splits overrides.
+int coulomb_splits(int64_t Z, int64_t cap = 524288);
 // How the Coulomb partials of Z protons are produced: form 0 = gather tiles
 // with S source splits, 1 = pairwise super-block items (S = super-blocks of
 // 256 protons; used when S Z partials fit coul_max).  Every proton gets S
@@ -412,6 +415,9 @@ struct CoulPlan {
     int S;
 };
 CoulPlan coulomb_plan(int64_t Z, int64_t coul_max);
+// Partials a force workspace holds for n particles: enough for the gather
+// form's default splits and for the pairwise form up to Z = 0.4 n.
+int64_t coulomb_partial_capacity(int64_t n);
 // Super-blocks (partials per proton) of the pairwise form for Z protons.
 int coulomb_pair_plan_supers(int64_t Z);
 // Process-wide kernel choices (set through pasta_set_tuning).

@@ -128,6 +128,7 @@ struct Fp64Policy {
     };
     using Part = Acc;
     using CAcc = double;  // Coulomb per-tile accumulator
+    using CPart = double4;  // stored Coulomb partial sum
     __device__ static Lds load(const Src* s, int j) { return s[j]; }
 
     template <int MODE>
@@ -227,6 +228,9 @@ struct MixedPolicy {
         uint32_t np = 0;
     };
     using CAcc = float;
+    // stored Coulomb partial sum: an item's sums are FP32 accumulators (or
+    // at most a few tiles of them), so FP32 storage keeps their precision
+    using CPart = float4;
     __device__ static Lds load(const Src* s, int j)
     {
         return reinterpret_cast<const uint4*>(s)[j];
@@ -328,12 +332,23 @@ constexpr int nuclear_lds_bytes()
 constexpr int NUC_CAP = 26;
 constexpr int NUC_U = 4;     // candidates per lane between list-fill checks
 
+// A Coulomb partial sum (Fx, Fy, Fz, sum V), already scaled to MeV/fm and
+// MeV, stored as double4 or float4.
+__device__ __forceinline__ void store_part(double4* p, double x, double y, double z, double w)
+{
+    *p = make_double4(x, y, z, w);
+}
+__device__ __forceinline__ void store_part(float4* p, double x, double y, double z, double w)
+{
+    *p = make_float4((float)x, (float)y, (float)z, (float)w);
+}
+
 // ============================================================ Coulomb ==
 // Targets are the proton slots [tb, tb + WG) ∩ [0, Z); sources the slots
 // [split * per_split, ...).  Writes part[split * Z + t] = (Fx, Fy, Fz, sum V).
-template <class P, bool E = true>
+template <class P, bool E = true, class PT = double4>
 __device__ void coulomb_item(const typename P::Src* __restrict__ stg, int Z, int per_split,
-                             const CoulConsts& k, double4* __restrict__ part, int tblock,
+                             const CoulConsts& k, PT* __restrict__ part, int tblock,
                              int split, char* lds)
 {
     using Lds = typename P::Lds;
@@ -366,7 +381,7 @@ __device__ void coulomb_item(const typename P::Src* __restrict__ stg, int Z, int
     }
     if (t < Z) {
         const double fs = P::coul_fscale(k), vs = P::coul_vscale(k);
-        part[(int64_t)split * Z + t] = make_double4(fx * fs, fy * fs, fz * fs, e * vs);
+        store_part(&part[(int64_t)split * Z + t], fx * fs, fy * fs, fz * fs, e * vs);
     }
 }
 
@@ -452,21 +467,29 @@ constexpr int coulomb_pair_lds_bytes()
     return CP_SUPER * CP_SUPER * 64 * 4 * (int)sizeof(typename P::CAcc);
 }
 
-template <class P, bool E>
+// Item index -> super-block pair (A, B), A <= B, row-major over A.
+__host__ __device__ inline void coulomb_pair_ab(int item, int S, int* A_out, int* B_out)
+{
+    int A = 0, r = item;
+    while (r >= S - A) {
+        r -= S - A;
+        ++A;
+    }
+    *A_out = A;
+    *B_out = A + r;
+}
+
+template <class P, bool E, class PT = double4>
 __device__ void coulomb_pair_item(const typename P::Src* __restrict__ stg, int Z,
-                                  const CoulConsts& k, double4* __restrict__ part, int item,
+                                  const CoulConsts& k, PT* __restrict__ part, int item,
                                   char* lds)
 {
     using Src = typename P::Src;
     using CA = typename P::CAcc;
     CA* acc = reinterpret_cast<CA*>(lds);  // [wave][block of B][lane][4]
     const int S = coulomb_pair_supers(Z);
-    int A = 0, r = item;
-    while (r >= S - A) {
-        r -= S - A;
-        ++A;
-    }
-    const int Bs = A + r;
+    int A, Bs;
+    coulomb_pair_ab(item, S, &A, &Bs);
     const int tid = threadIdx.x, w = tid >> 6, lane = tid & 63;
     const int nb = (Z + 63) / 64;
     for (int i = tid; i < CP_SUPER * CP_SUPER * 64 * 4; i += WG)
@@ -578,8 +601,8 @@ __device__ void coulomb_pair_item(const typename P::Src* __restrict__ stg, int Z
         const double fsc = P::coul_fscale(k), vsc = P::coul_vscale(k);
         if (A != Bs) {
             if (tv)
-                part[(int64_t)Bs * Z + t] = make_double4((double)tx * fsc, (double)ty * fsc,
-                                                         (double)tz * fsc, (double)te * vsc);
+                store_part(&part[(int64_t)Bs * Z + t], (double)tx * fsc, (double)ty * fsc,
+                           (double)tz * fsc, (double)te * vsc);
         } else {
             CA* a = acc + ((w * CP_SUPER + (I - CP_SUPER * A)) * 64 + lane) * 4;
             a[0] += tx;
@@ -604,10 +627,28 @@ __device__ void coulomb_pair_item(const typename P::Src* __restrict__ stg, int Z
                 e += (double)a[3];
             }
             const double fsc = P::coul_fscale(k), vsc = P::coul_vscale(k);
-            part[(int64_t)A * Z + p] = make_double4(fx * fsc, fy * fsc, fz * fsc, e * vsc);
+            store_part(&part[(int64_t)A * Z + p], fx * fsc, fy * fsc, fz * fsc, e * vsc);
         }
     }
     __syncthreads();
+}
+
+// ------------------------------------------------- Coulomb partial sums --
+// Every proton p receives S partial sums part[s * Z + p] (s = 0..S-1).
+// Sequential sum from zero in s order (the nuclear epilogue of the unfused
+// form and the batched combine use it).
+template <class PT>
+__device__ inline double4 coul_sum_seq(const PT* __restrict__ part, int S, int Z, int p)
+{
+    double x = 0.0, y = 0.0, z = 0.0, w = 0.0;
+    for (int s = 0; s < S; ++s) {
+        const PT v = part[(int64_t)s * Z + p];
+        x += (double)v.x;
+        y += (double)v.y;
+        z += (double)v.z;
+        w += (double)v.w;
+    }
+    return make_double4(x, y, z, w);
 }
 
 // ============================================================ nuclear ==
@@ -618,8 +659,8 @@ struct NucArgs {
     int nc, C;
     int sub;                 // bins per cell and species (1 or 8)
     int Z;
-    const double4* coul_part;
-    int S;                   // Coulomb splits to add (0 = none)
+    const void* coul_part;   // typename P::CPart [S * Z]: Coulomb partials
+    int S;                   // Coulomb partials per proton to add (0 = none)
     double* force;           // [n][3] at perm[slot] (caller order) or the slot
     double* epot;            // [n] or null
     double* vel;             // [n][3] or null: apply the half kick
@@ -734,13 +775,12 @@ __device__ void nuclear_item(const typename P::Src* __restrict__ stg, const NucA
             A.fnuc[slot] = make_double4(Fx, Fy, Fz, V);
         } else {
             if (A.S > 0 && tprot) {
-                for (int s = 0; s < A.S; ++s) {
-                    const double4 cp = A.coul_part[(int64_t)s * A.Z + slot];
-                    Fx += cp.x;
-                    Fy += cp.y;
-                    Fz += cp.z;
-                    V += cp.w;
-                }
+                const double4 cp = coul_sum_seq(
+                    static_cast<const typename P::CPart*>(A.coul_part), A.S, A.Z, slot);
+                Fx += cp.x;
+                Fy += cp.y;
+                Fz += cp.z;
+                V += cp.w;
             }
             const int64_t id = A.perm ? A.perm[slot] : slot;
             A.force[3 * id + 0] = Fx;
@@ -1064,13 +1104,12 @@ __device__ void nuclear_finish(const NucArgs& A, const NucConsts& k, typename P:
             A.fnuc[t.slot] = make_double4(Fx, Fy, Fz, V);
         } else {
             if (A.S > 0 && t.tprot) {
-                for (int s = 0; s < A.S; ++s) {
-                    const double4 cp = A.coul_part[(int64_t)s * A.Z + t.slot];
-                    Fx += cp.x;
-                    Fy += cp.y;
-                    Fz += cp.z;
-                    V += cp.w;
-                }
+                const double4 cp = coul_sum_seq(
+                    static_cast<const typename P::CPart*>(A.coul_part), A.S, A.Z, t.slot);
+                Fx += cp.x;
+                Fy += cp.y;
+                Fz += cp.z;
+                V += cp.w;
             }
             const int64_t id = A.perm ? A.perm[t.slot] : t.slot;
             A.force[3 * id + 0] = Fx;
