@@ -12,7 +12,10 @@ beside it.
 Prints one JSON line: pair interactions per second (useful pairs: unordered
 nuclear pairs inside 11.5 fm plus all unordered proton pairs of the uncut
 Coulomb term), MD steps per second, the roofline entry of the dominant
-kernel and the CPU oracle baseline.
+kernel and the CPU oracle baseline.  Beside the headline: the FP64 path and
+its roofline, the neighbour-list and dense-kernel forms, N = 409 600 at
+Y_P = 0.40 and 0.05 in both precisions, the 20 000-step decompression
+window (0.080 -> 0.00125 fm^-3), and the batched 15-system grid.
 """
 from __future__ import annotations
 
@@ -27,14 +30,43 @@ if ROOT not in sys.path:
     sys.path.insert(0, ROOT)
 
 WORKLOAD = "n51200_yp020_n0.080"
-PEAK_FP32_TFLOPS = 157.3       # MI355X FP32 vector, published
-# Algorithmic work per ordered pair (FMA = 2 flops, each transcendental = 1):
-#   nuclear: difference 3, r^2 5, scale 1, exp 1, g^2 1, V 3, force scalar 3,
-#            force 6, energy 1                                   -> 24
-#   Coulomb: difference 3, nearest image 6, r^2 5, rsqrt 1, r 1, 1/r 1, exp 1,
-#            V 2, force scalar 3, force 6, energy 1              -> 30
-FLOPS_NUC_PAIR = 24
-FLOPS_COUL_PAIR = 30
+LARGE_WORKLOADS = ("n409600_yp040_n0.080", "n409600_yp005_n0.080")
+DECOMPRESSION_WORKLOAD = "n51200_yp030_n0.080"
+PEAK_FP32_TFLOPS = 157.3       # MI355X FP32 vector (packed FMA), published
+PEAK_FP32_NONPACKED_TFLOPS = 78.6  # the same without packed FP32 (256 CU x 2.4 GHz x 128)
+PEAK_FP64_TFLOPS = 78.6        # MI355X FP64 vector, published
+# Algorithmic work per ordered pair inside the cutoff (what the method must
+# compute, whichever kernel form computes it; FMA = 2 flops, transcendentals
+# counted apart as T):
+#   nuclear: difference 3, r^2 5, scale 1, g^2 1, V 3, force scalar 3,
+#            force 6, energy 1 -> 23 flops + 1 T (one exp)
+#   Coulomb: difference 3, nearest image 6, r^2 5, r 1, 1/r 1, V 2, force
+#            scalar 3, force 6, energy 1 -> 28 flops + 2 T (rsqrt, exp)
+FLOPS_NUC_PAIR, T_NUC_PAIR = 23, 1
+FLOPS_COUL_PAIR, T_COUL_PAIR = 28, 2
+
+
+def pair_work(nuc_pairs, coul_pairs):
+    """(flops, transcendentals) of one force evaluation, from the unordered
+    pair counts (each unordered pair is two ordered ones)."""
+    return (2 * nuc_pairs * FLOPS_NUC_PAIR + 2 * coul_pairs * FLOPS_COUL_PAIR,
+            2 * nuc_pairs * T_NUC_PAIR + 2 * coul_pairs * T_COUL_PAIR)
+
+
+def roofline_entry(kernel, nuc_pairs, coul_pairs, avg_ms, precision):
+    """Roofline of the pair-force launch: algorithmic flops per launch over
+    its average duration (HIP events on the simulation's stream)."""
+    flops, tops = pair_work(nuc_pairs, coul_pairs)
+    ach = flops / (avg_ms * 1e-3) / 1e12
+    peak = PEAK_FP64_TFLOPS if precision == 0 else PEAK_FP32_TFLOPS
+    out = {"kernel": kernel, "bound": "alu", "achieved": round(ach, 3), "peak": peak,
+           "unit": "TFLOP/s", "frac": round(ach / peak, 4),
+           "flops_per_launch": flops, "transcendentals_per_launch": tops,
+           "transcendentals_per_s": round(tops / (avg_ms * 1e-3), 1),
+           "avg_launch_ms": round(avg_ms, 5)}
+    if precision != 0:
+        out["frac_vs_nonpacked_fp32"] = round(ach / PEAK_FP32_NONPACKED_TFLOPS, 4)
+    return out
 
 
 def log(*a):
@@ -158,6 +190,103 @@ def run_sequential(B, torch, states, precision, steps, warmup):
     return dict(seconds=total, pairs_per_step=pairs)
 
 
+def kernel_ms(kt, steps):
+    return {k: round(v[0] / max(steps, 1), 5) for k, v in kt.items() if v[1]}
+
+
+def pair_kernel_name(tuning, use_lists=False):
+    if tuning.get("fused_forces"):
+        return "pair forces (nuclear %s + %s Coulomb tiles, one launch)" % (
+            "list items" if use_lists else "cell tiles",
+            "pairwise" if tuning.get("coulomb_form") else "gather")
+    return "nuclear+kick"
+
+
+def large_section(B, torch, steps=20, warmup=5):
+    """N = 409 600 at Y_P = 0.40 and 0.05 (the paper's large runs,
+    Sec. II.B.2), each precision autotuned on its own state: steps/s, pair
+    interactions/s, per-kernel times and the pair kernel's roofline."""
+    from paper_1412_8502_amd.autotune import tune
+    from paper_1412_8502_amd.inputs import workload
+    dev = torch.device("cuda:0")
+    out = {"steps": steps, "warmup": warmup}
+    saved = B.pasta_get_tuning()
+    for name in LARGE_WORKLOADS:
+        st = workload(name)
+        ent = {"N": st["n"], "Z": st["Z"], "L_fm": st["L"], "Y_P": st["y_p"],
+               "density": st["density"], "T_MeV": st["T"]}
+        tpos = torch.tensor(st["pos"], device=dev)
+        tsp = torch.tensor(st["species"], device=dev)
+        for prec, label in ((B.PASTA_MIXED, "mixed"), (B.PASTA_FP64, "fp64")):
+            best, _, _ = tune(tpos, tsp, st["L"], prec, use_cache=False, apply=True)
+            r = run_path(B, torch, st, prec, steps, warmup, timing=True)
+            kt = r["kernel_times"]
+            ms_f, nl = kt["nuclear+kick"]
+            useful = r["nuc_pairs"] + r["coul_pairs"]
+            ent[label] = {
+                "ms_per_step": r["seconds"] / steps * 1e3,
+                "md_steps_per_s": steps / r["seconds"],
+                "pair_interactions_per_s": useful * steps / r["seconds"],
+                "useful_pairs_per_step": {"nuclear": r["nuc_pairs"], "coulomb": r["coul_pairs"]},
+                "tuning": best,
+                "per_kernel_ms": kernel_ms(kt, steps),
+                "roofline": roofline_entry(pair_kernel_name(best), r["nuc_pairs"],
+                                           r["coul_pairs"], ms_f / max(nl, 1), prec)}
+            log(f"large {name} {label}: {ent[label]['ms_per_step']:.3f} ms/step, "
+                f"tuning {best}")
+        ent["mixed_over_fp64_speedup"] = ent["fp64"]["ms_per_step"] / ent["mixed"]["ms_per_step"]
+        out[name] = ent
+        del tpos, tsp
+    B.pasta_set_tuning(**saved)
+    return out
+
+
+def decompression_section(B, torch, nsteps=20000, segment=2000):
+    """The decompression window: N = 51 200, Y_P = 0.30, T = 0.5 MeV, box
+    grown by Eq. (3a) from 0.080 to 0.00125 fm^-3 (L 86.18 -> 344.7 fm) over
+    20 000 steps of 2 fm/c (xi_dot = 7.5e-5 c/fm), velocity rescale every 100
+    steps, mixed precision, kernel setting tuned on the starting state.
+    Steps/s over the whole window and per segment of 2000 steps (the cell
+    grid goes from 7 to 29 cells per side as the box grows)."""
+    from paper_1412_8502_amd.autotune import tune
+    from paper_1412_8502_amd.inputs import workload
+    dev = torch.device("cuda:0")
+    st = workload(DECOMPRESSION_WORKLOAD)
+    L0, xi, dt = st["L"], 7.5e-5, 2.0
+    saved = B.pasta_get_tuning()
+    pos = torch.tensor(st["pos"], device=dev)
+    vel = torch.tensor(st["vel"], device=dev)
+    sp = torch.tensor(st["species"], device=dev)
+    best, _, _ = tune(pos, sp, L0, B.PASTA_MIXED, use_cache=False, apply=True)
+    sim = B.Sim(pos, vel, sp, L0, dt=dt, xi_dot=xi, T=st["T"], rescale_every=100,
+                precision=B.PASTA_MIXED, L_max=4.0 * L0 * (1 + 1e-12))
+    segs = []
+    total = 0.0
+    done = 0
+    torch.cuda.synchronize()
+    while done < nsteps:
+        k = min(segment, nsteps - done)
+        t0 = time.perf_counter()
+        sim.step(k)
+        torch.cuda.synchronize()
+        dt_s = time.perf_counter() - t0
+        total += dt_s
+        done += k
+        L = L0 * (1.0 + xi * done * dt)
+        segs.append([done, round(st["n"] / L ** 3, 6), round(dt_s / k * 1e3, 5)])
+    en = sim.energies()
+    sim.close()
+    B.pasta_set_tuning(**saved)
+    log(f"decompression: {nsteps} steps in {total:.2f} s")
+    return {"workload": "N=51200 Y_P=0.30 T=0.5 MeV, n 0.080 -> 0.00125 fm^-3 "
+                        "(L 86.18 -> 344.7 fm) over 20000 steps, xi_dot=7.5e-5 c/fm, dt=2 fm/c, "
+                        "rescale every 100 steps, mixed",
+            "steps": nsteps, "seconds": total, "md_steps_per_s": nsteps / total,
+            "ms_per_step": total / nsteps * 1e3, "tuning": best, "final_L_fm": en["L"],
+            "segments": "[last step, density fm^-3, ms per step over the segment]",
+            "per_segment": segs}
+
+
 def batched_section(B, torch, steps, warmup):
     from paper_1412_8502_amd.inputs import batch_grid
     states = batch_grid()
@@ -215,10 +344,24 @@ def cpu_baseline(st, pairs_per_target_fn, budget_s=15.0):
     oracle.forces(st["pos"], st["species"], st["L"], targets=sample, nthreads=threads)
     t = time.perf_counter() - t0
     useful = pairs_per_target_fn(sample)
+    model = None
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    model = line.split(":", 1)[1].strip()
+                    break
+    except OSError:
+        pass
+    try:
+        usable = len(os.sched_getaffinity(0))
+    except (AttributeError, OSError):
+        usable = None
     return dict(value=useful / t, unit="pair interactions/s", cores=threads, kind="oracle",
                 sample=f"{m} of {N} targets of the same state, all {N} sources each "
                        f"(FP64 brute force), {t:.1f} s",
-                md_steps_per_s_equiv=1.0 / (t / m * N))
+                md_steps_per_s_equiv=1.0 / (t / m * N), cpu_model=model,
+                nproc=os.cpu_count(), usable_cpus=usable)
 
 
 def main():
@@ -230,6 +373,12 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--batch-steps", type=int, default=500)
     ap.add_argument("--no-batch", action="store_true")
+    ap.add_argument("--no-large", action="store_true",
+                    help="skip the N = 409 600 section")
+    ap.add_argument("--no-decompression", action="store_true",
+                    help="skip the 20 000-step decompression window")
+    ap.add_argument("--section", choices=("large", "decompression"), default=None,
+                    help="run only this section and print its JSON (for profiler runs)")
     ap.add_argument("--tuning", default=None,
                     help="variant,splits,fused[,coulomb_form]: use this kernel setting instead "
                          "of autotuning")
@@ -249,6 +398,11 @@ def main():
     import torch
     from paper_1412_8502_amd import binding as B
     from paper_1412_8502_amd.inputs import workload
+
+    if args.section:
+        fn = large_section if args.section == "large" else decompression_section
+        print(json.dumps({"section": args.section, "result": fn(B, torch)}))
+        return
 
     if args.copy_calibration_mib > 0:
         nb = args.copy_calibration_mib << 20
@@ -285,15 +439,16 @@ def main():
     if args.headline_only:
         useful = mixed_cells["nuc_pairs"] + mixed_cells["coul_pairs"]
         kt = mixed_cells["kernel_times"]
-        fl = 2 * mixed_cells["nuc_pairs"] * FLOPS_NUC_PAIR + 2 * mixed_cells["coul_pairs"] * FLOPS_COUL_PAIR
         ms_f, nl = kt["nuclear+kick"]
         print(json.dumps({"metric": "headline path only (profiler run)", "steps": K, "warmup": W,
                           "ms_per_step": mixed_cells["seconds"] / K * 1e3,
                           "value": useful * K / mixed_cells["seconds"],
                           "unit": "pair interactions/s", "tuning": tuned,
                           "pair_forces_avg_launch_ms": ms_f / max(nl, 1),
-                          "pair_forces_tflops": fl / (ms_f / max(nl, 1) * 1e-3) / 1e12,
-                          "per_kernel_ms": {k: round(v[0] / K, 5) for k, v in kt.items() if v[1]}}))
+                          "roofline": roofline_entry(pair_kernel_name(tuned), mixed_cells["nuc_pairs"],
+                                                     mixed_cells["coul_pairs"], ms_f / max(nl, 1),
+                                                     B.PASTA_MIXED),
+                          "per_kernel_ms": kernel_ms(kt, K)}))
         return
     # the neighbour-list form: halo chosen by short timed runs, then the same
     # timed protocol; the faster form is the headline
@@ -337,31 +492,35 @@ def main():
     dom = max(kt, key=lambda k: kt[k][0])
     ms_tot, launches = kt[dom]
     avg_ms = ms_tot / max(launches, 1)
-    nuc_fl = 2 * mixed["nuc_pairs"] * FLOPS_NUC_PAIR
-    coul_fl = 2 * mixed["coul_pairs"] * FLOPS_COUL_PAIR
-    if tuned.get("fused_forces"):
+    if dom == "nuclear+kick" and tuned.get("fused_forces"):
         # one launch carries both the nuclear items and the Coulomb tiles
-        flops = {"nuclear+kick": nuc_fl + coul_fl}
-        kname = {"nuclear+kick": "pair forces (nuclear %s + Coulomb tiles, one launch)"
-                 % ("list items" if use_lists else "cell tiles")}
-    else:
-        flops = {"coulomb": coul_fl, "nuclear+kick": nuc_fl}
-        kname = {}
-    if dom in flops:
-        ach = flops[dom] / (avg_ms * 1e-3) / 1e12
-        traffic = None
-        if dom == "nuclear+kick" and tuned.get("fused_forces") and not use_lists:
-            traffic = measured_traffic("k_forces_fused<MixedPolicy, 0, %d, %d>"
-                                       % (tuned["nuclear_variant"], tuned.get("coulomb_form", 0)),
-                                       tuned)
-        roof = {"kernel": kname.get(dom, dom), "bound": "alu", "achieved": round(ach, 3),
-                "peak": PEAK_FP32_TFLOPS, "unit": "TFLOP/s",
-                "frac": round(ach / PEAK_FP32_TFLOPS, 4), "traffic": traffic,
-                "traffic_unit": "bytes per launch (HBM, counter runs in profiles/)",
-                "avg_launch_ms": round(avg_ms, 5)}
+        roof = roofline_entry(pair_kernel_name(tuned, use_lists), mixed["nuc_pairs"],
+                              mixed["coul_pairs"], avg_ms, B.PASTA_MIXED)
+        roof["traffic"] = None if use_lists else measured_traffic(
+            "k_forces_fused<MixedPolicy, 0, %d, %d>" % (tuned["nuclear_variant"],
+                                                       tuned.get("coulomb_form", 0)), tuned)
+        roof["traffic_unit"] = "bytes per launch (HBM, counter runs in profiles/)"
+    elif dom in ("coulomb", "nuclear+kick"):
+        roof = roofline_entry(dom, mixed["nuc_pairs"] if dom == "nuclear+kick" else 0,
+                              mixed["coul_pairs"] if dom == "coulomb" else 0, avg_ms,
+                              B.PASTA_MIXED)
+        roof["traffic"] = None
     else:
         roof = {"kernel": dom, "bound": "hbm", "achieved": None, "peak": 8000.0,
                 "unit": "GB/s", "frac": None, "traffic": None, "avg_launch_ms": round(avg_ms, 5)}
+    # the FP64 path's pair kernel against the FP64 vector peak
+    kt64 = fp64["kernel_times"]
+    ms64, nl64 = kt64.get("nuclear+kick", (0.0, 0))
+    roof64 = roofline_entry(pair_kernel_name(tuned64, use_lists), fp64["nuc_pairs"],
+                            fp64["coul_pairs"], ms64 / max(nl64, 1), B.PASTA_FP64) if nl64 else None
+
+    large = None
+    decomp = None
+    if not args.no_large:
+        large = large_section(B, torch)
+    if not args.no_decompression:
+        decomp = decompression_section(B, torch)
+        B.pasta_set_tuning(**tuned)
 
     batched = None
     via_batch = None
@@ -408,7 +567,7 @@ def main():
         "fp64": {"ms_per_step": fp64_ms, "md_steps_per_s": 1e3 / fp64_ms,
                  "pair_interactions_per_s": (fp64["nuc_pairs"] + fp64["coul_pairs"]) * 1e3 / fp64_ms,
                  "steps": k64,
-                 "per_kernel_ms": {k: round(v[0] / k64, 5) for k, v in fp64["kernel_times"].items() if v[1]}},
+                 "per_kernel_ms": kernel_ms(fp64["kernel_times"], k64)},
         "mixed_over_fp64_speedup": fp64_ms / ms_step,
         "autotuned": {"mixed": tuned, "fp64": tuned64,
                       "candidates": "[fused_forces, nuclear_variant, coulomb_form, "
@@ -436,6 +595,9 @@ def main():
         "ms_per_step_with_events": mixed["seconds_with_events"] / K * 1e3,
         "per_kernel": per_kernel,
         "roofline": roof,
+        "fp64_roofline": roof64,
+        "large": large,
+        "decompression": decomp,
         "batched": batched,
         "single_system_via_batch_path": via_batch,
         "cpu_baseline": cpu,

@@ -5,8 +5,10 @@
 // launches:
 //   bin/count   one thread per particle: bin = (proton ? 0 : C) + cell,
 //               integer atomic count per bin (order-independent);
-//   scan        one workgroup: exclusive scan of the 2C counts, the nuclear
-//               work list (cell, target chunk), and the reset of the counters;
+//   scan        exclusive scan of the 2C counts, the nuclear work list (cell,
+//               target chunk), and the reset of the counters: one workgroup
+//               for grids of up to 1024 cells, else two launches of one
+//               thread per cell;
 //   scatter     one thread per particle: slot = start[bin] + atomic cursor
 //               (arrival order, not yet stable);
 //   rank        one thread per slot: the stable rank inside the bin is the
@@ -200,6 +202,141 @@ __global__ __launch_bounds__(SCAN_THREADS) void k_scan_oct(int32_t* __restrict__
         start[2 * CS] = (int32_t)(Zt + (tot >> 32));
         if (chunk > 0)
             *n_items = (int32_t)tq;
+    }
+}
+
+// Grids of more than SCAN_THREADS cells (large systems, a decompressed box,
+// the cluster grid): the same scan over all cells in two launches of one
+// thread per cell.  k_mscan_sums: each workgroup's totals (protons and
+// neutrons packed in one 64-bit word, and work items) into blk; then
+// k_mscan_apply: every workgroup takes the exclusive prefix of the totals
+// of the workgroups before it (at most MSCAN_MAX_BLOCKS of them), scans its
+// own cells as k_scan_oct does, writes the starts and items and clears the
+// counters.  SUB = bins per cell and species (1 or 8).
+constexpr int MSCAN_THREADS = 1024;
+constexpr int MSCAN_MAX_BLOCKS = MSCAN_THREADS;
+
+template <int SUB>
+__device__ inline void load_cell_counts(const int32_t* __restrict__ count, int64_t CS, int64_t c,
+                                        int32_t (&p)[SUB], int32_t (&q)[SUB])
+{
+    if constexpr (SUB == 8) {
+        const int4* cp = reinterpret_cast<const int4*>(count + 8 * c);
+        const int4* cn = reinterpret_cast<const int4*>(count + CS + 8 * c);
+        const int4 a = cp[0], b = cp[1], d = cn[0], e = cn[1];
+        p[0] = a.x; p[1] = a.y; p[2] = a.z; p[3] = a.w;
+        p[4] = b.x; p[5] = b.y; p[6] = b.z; p[7] = b.w;
+        q[0] = d.x; q[1] = d.y; q[2] = d.z; q[3] = d.w;
+        q[4] = e.x; q[5] = e.y; q[6] = e.z; q[7] = e.w;
+    } else {
+#pragma unroll
+        for (int u = 0; u < SUB; ++u) {
+            p[u] = count[SUB * c + u];
+            q[u] = count[CS + SUB * c + u];
+        }
+    }
+}
+
+template <int SUB>
+__global__ __launch_bounds__(MSCAN_THREADS) void k_mscan_sums(const int32_t* __restrict__ count,
+                                                              int C, int chunk,
+                                                              int64_t* __restrict__ blk,
+                                                              const int32_t* __restrict__ gate)
+{
+    __shared__ int64_t lds[64];
+    if (gate && *gate == 0)
+        return;
+    const int64_t c = (int64_t)blockIdx.x * MSCAN_THREADS + threadIdx.x;
+    const int64_t CS = (int64_t)C * SUB;
+    int64_t sp = 0, sn = 0;
+    if (c < C) {
+        int32_t p[SUB], q[SUB];
+        load_cell_counts<SUB>(count, CS, c, p, q);
+#pragma unroll
+        for (int u = 0; u < SUB; ++u) {
+            sp += p[u];
+            sn += q[u];
+        }
+    }
+    const int64_t k = chunk > 0 ? (sp + sn + chunk - 1) / chunk : 0;
+    int64_t tot = 0, tq = 0;
+    block_exclusive_scan(sp | (sn << 32), lds, &tot);
+    block_exclusive_scan(k, lds, &tq);
+    if (threadIdx.x == 0) {
+        blk[2 * blockIdx.x + 0] = tot;
+        blk[2 * blockIdx.x + 1] = tq;
+    }
+}
+
+template <int SUB>
+__global__ __launch_bounds__(MSCAN_THREADS) void k_mscan_apply(
+    int32_t* __restrict__ count, int32_t* __restrict__ fill, int32_t* __restrict__ start, int C,
+    int chunk, int32_t* __restrict__ items, int32_t* __restrict__ n_items,
+    const int64_t* __restrict__ blk, int nblk, const int32_t* __restrict__ gate)
+{
+    __shared__ int64_t lds[64];
+    __shared__ int64_t s_off[2];
+    if (gate && *gate == 0)
+        return;
+    const int t = threadIdx.x;
+    // exclusive prefix of the workgroup totals, and the grand totals
+    const int64_t bt = t < nblk ? blk[2 * t + 0] : 0, bq = t < nblk ? blk[2 * t + 1] : 0;
+    int64_t all_t = 0, all_q = 0;
+    const int64_t pt = block_exclusive_scan(bt, lds, &all_t);
+    const int64_t pq = block_exclusive_scan(bq, lds, &all_q);
+    if (t == (int)blockIdx.x) {
+        s_off[0] = pt;
+        s_off[1] = pq;
+    }
+    __syncthreads();
+    const int64_t off_t = s_off[0], off_q = s_off[1];
+    const int64_t Zt = all_t & 0xffffffffll;  // all protons
+    const int64_t c = (int64_t)blockIdx.x * MSCAN_THREADS + t;
+    const int64_t CS = (int64_t)C * SUB;
+    int32_t p[SUB], q[SUB];
+    int64_t sp = 0, sn = 0;
+    if (c < C) {
+        load_cell_counts<SUB>(count, CS, c, p, q);
+#pragma unroll
+        for (int u = 0; u < SUB; ++u) {
+            sp += p[u];
+            sn += q[u];
+        }
+    }
+    const int64_t k = chunk > 0 ? (sp + sn + chunk - 1) / chunk : 0;
+    int64_t tot = 0, tq = 0;
+    const int64_t pre = off_t + block_exclusive_scan(sp | (sn << 32), lds, &tot);
+    const int64_t bqi = off_q + block_exclusive_scan(k, lds, &tq);
+    if (c < C) {
+        int32_t b = (int32_t)(pre & 0xffffffffll);
+#pragma unroll
+        for (int u = 0; u < SUB; ++u) {
+            start[SUB * c + u] = b;
+            b += p[u];
+        }
+        b = (int32_t)(Zt + (pre >> 32));
+#pragma unroll
+        for (int u = 0; u < SUB; ++u) {
+            start[CS + SUB * c + u] = b;
+            b += q[u];
+        }
+        for (int64_t r = 0; r < k; ++r) {
+            items[2 * (bqi + r) + 0] = (int32_t)c;
+            items[2 * (bqi + r) + 1] = (int32_t)r;
+        }
+        // this thread alone read these counters (in both launches)
+#pragma unroll
+        for (int u = 0; u < SUB; ++u) {
+            count[SUB * c + u] = 0;
+            count[CS + SUB * c + u] = 0;
+            fill[SUB * c + u] = 0;
+            fill[CS + SUB * c + u] = 0;
+        }
+    }
+    if (blockIdx.x == 0 && t == 0) {
+        start[2 * CS] = (int32_t)(Zt + (all_t >> 32));
+        if (chunk > 0)
+            *n_items = (int32_t)all_q;
     }
 }
 
@@ -406,13 +543,32 @@ void launch_scan(const CellBuf& cb, const Grid& g, int chunk, hipStream_t s, Tim
                  const int32_t* gate)
 {
     timer_begin(t, KC_SCAN, s);
-    // cb.tmp doubles as the per-cell chunk-count scratch (2C entries)
-    if (g.sub == 8 && g.C <= SCAN_THREADS)
+    // cb.tmp doubles as scratch: the per-cell chunk counts of k_scan (2C
+    // entries), the workgroup totals of k_mscan_* (4 per workgroup); the
+    // scatter only writes it after the scan
+    const int64_t nblk = ((int64_t)g.C + MSCAN_THREADS - 1) / MSCAN_THREADS;
+    if (g.sub == 8 && g.C <= SCAN_THREADS) {
         k_scan_oct<<<1, SCAN_THREADS, 0, s>>>(cb.count, cb.fill, cb.start, g.C, chunk, cb.items,
                                               cb.n_items, gate);
-    else
+    } else if (g.C > SCAN_THREADS && nblk <= MSCAN_MAX_BLOCKS && (g.sub == 8 || g.sub == 1)) {
+        int64_t* blk = reinterpret_cast<int64_t*>(cb.tmp);
+        if (g.sub == 8) {
+            k_mscan_sums<8><<<(unsigned)nblk, MSCAN_THREADS, 0, s>>>(cb.count, g.C, chunk, blk,
+                                                                     gate);
+            k_mscan_apply<8><<<(unsigned)nblk, MSCAN_THREADS, 0, s>>>(
+                cb.count, cb.fill, cb.start, g.C, chunk, cb.items, cb.n_items, blk, (int)nblk,
+                gate);
+        } else {
+            k_mscan_sums<1><<<(unsigned)nblk, MSCAN_THREADS, 0, s>>>(cb.count, g.C, chunk, blk,
+                                                                     gate);
+            k_mscan_apply<1><<<(unsigned)nblk, MSCAN_THREADS, 0, s>>>(
+                cb.count, cb.fill, cb.start, g.C, chunk, cb.items, cb.n_items, blk, (int)nblk,
+                gate);
+        }
+    } else {
         k_scan<<<1, SCAN_THREADS, 0, s>>>(cb.count, cb.fill, cb.start, g.C, g.sub, chunk,
                                           cb.items, cb.n_items, cb.tmp, gate);
+    }
     timer_end(t, KC_SCAN, s);
 }
 

@@ -45,6 +45,9 @@ def say(*a):
     ("ncell2", 700, 0.30, 0.05, 11.5),
     ("cluster-grid", 3200, 0.40, 0.040, 4.5),
     ("n51200", 51200, 0.20, 0.080, 11.5),
+    # more cells than one scan workgroup (22^3 = 10 648), many of them empty
+    ("big-grid", 20000, 0.30, 0.02, 4.5),
+    ("bigger-grid", 30000, 0.40, 0.002, 4.5),
 ])
 def test_cell_list_bitexact(env, case):
     name, N, yp, dens, rc = case
