@@ -105,13 +105,13 @@ def measured_traffic(kernel_name, tuning):
     return None
 
 
-def run_path(B, torch, st, precision, steps, warmup, timing):
+def run_path(B, torch, st, precision, steps, warmup, timing, pot=None):
     dev = torch.device("cuda:0")
     pos = torch.tensor(st["pos"], device=dev)
     vel = torch.tensor(st["vel"], device=dev)
     sp = torch.tensor(st["species"], device=dev)
     sim = B.Sim(pos, vel, sp, st["L"], dt=2.0, T=st["T"], rescale_every=100,
-                precision=precision)
+                precision=precision, pot=pot)
     sim.step(warmup)
     torch.cuda.synchronize()
     nuc0, coul = sim.pair_counts()
@@ -514,6 +514,20 @@ def main():
     roof64 = roofline_entry(pair_kernel_name(tuned64, use_lists), fp64["nuc_pairs"],
                             fp64["coul_pairs"], ms64 / max(nl64, 1), B.PASTA_FP64) if nl64 else None
 
+    # the same workload with the Coulomb term cut at 20 fm (an option; the
+    # paper's Coulomb term is uncut): gather form with the FP64 cutoff test
+    pot20 = B.pasta_potential_paper()
+    pot20.r_coul = 20.0
+    cut20 = run_path(B, torch, st, B.PASTA_MIXED, K, W, timing=False, pot=pot20)
+    cut20_entry = {"ms_per_step": cut20["seconds"] / K * 1e3,
+                   "md_steps_per_s": K / cut20["seconds"],
+                   "pair_interactions_per_s": (cut20["nuc_pairs"] + cut20["coul_pairs"]) * K /
+                   cut20["seconds"],
+                   "useful_pairs_per_step": {"nuclear": cut20["nuc_pairs"],
+                                             "coulomb_inside_20fm": cut20["coul_pairs"]},
+                   "precision": "mixed"}
+    log(f"mixed, Coulomb cut at 20 fm: {cut20_entry['ms_per_step']:.4f} ms/step")
+
     large = None
     decomp = None
     if not args.no_large:
@@ -596,6 +610,7 @@ def main():
         "per_kernel": per_kernel,
         "roofline": roof,
         "fp64_roofline": roof64,
+        "coulomb_cut_20fm": cut20_entry,
         "large": large,
         "decompression": decomp,
         "batched": batched,

@@ -66,7 +66,7 @@ extern "C" {
 
 /* Which terms a force call evaluates (bit mask). */
 #define PASTA_TERM_NUCLEAR 1 /* Eq. (1a,b), cut at r_nuc           */
-#define PASTA_TERM_COULOMB 2 /* Eq. (1c) screened Coulomb, uncut    */
+#define PASTA_TERM_COULOMB 2 /* Eq. (1c) screened Coulomb (r_coul)  */
 #define PASTA_TERM_ALL 3
 
 /* Interaction parameters (Eq. 1, Table I, Sec. II.A). */
@@ -80,6 +80,13 @@ typedef struct pasta_potential {
     double alpha_hbarc; /* MeV fm, alpha hbar c = 1.4399645                 */
     double mass;        /* MeV, nucleon mass (939)                          */
     double r_nuc;       /* fm, nuclear cutoff (11.5)                        */
+    double r_coul;      /* fm, Coulomb cutoff: INFINITY = uncut, the paper's
+                           model (Sec. II.A cuts only the nuclear part); a
+                           finite value keeps the proton pairs with
+                           r^2 < r_coul^2 (the include test is decided on the
+                           FP64 r^2 in both precisions) and requires
+                           L >= 2 r_coul.  The batched path takes INFINITY
+                           only.                                           */
 } pasta_potential;
 
 /* Integration parameters (Sec. II.A: velocity Verlet, Eq. 3 box growth,
@@ -160,7 +167,7 @@ int pasta_autotune(const pasta_potential* pot, int32_t precision, int64_t n, dou
                    double* h_ms, pasta_tuning* h_cands, int32_t* h_ncand);
 
 /* Fills *out with the paper's values (Table I, lambda = 10 fm, M = 939 MeV,
- * r_nuc = 11.5 fm, alpha hbar c = 1.4399645 MeV fm). */
+ * r_nuc = 11.5 fm, alpha hbar c = 1.4399645 MeV fm, r_coul = INFINITY). */
 void pasta_potential_paper(pasta_potential* out);
 
 /* Thread-local description of the last error (never NULL). */
@@ -179,6 +186,9 @@ const char* pasta_version(void);
  * d_cell_start[2*ncell^3 + 1] = first position of each bin in d_perm (the
  * last entry is n); *h_ncell = ncell.  Requires L >= 2 r_cut. */
 int pasta_cell_list_workspace(int64_t n, double L, double r_cut, size_t* h_bytes);
+/* Sizing query: *h_ncell = the ncell a cell list of box side L and cutoff
+ * r_cut uses (so d_cell_start needs 2 ncell^3 + 1 entries). */
+int pasta_cell_dims(double L, double r_cut, int32_t* h_ncell);
 int pasta_cell_list(int64_t n, double L, double r_cut, const double* d_pos,
                     const uint8_t* d_species, int32_t* d_cell_start, int32_t* d_perm,
                     int32_t* h_ncell, void* d_work, size_t work_bytes, void* stream);
@@ -188,7 +198,8 @@ int pasta_cell_list(int64_t n, double L, double r_cut, const double* d_pos,
  *   F_i = sum_{j != i} -dV_ij/dr (x_i - x_j)/r   (nearest image),
  *   E_i = (1/2) sum_{j != i} V_ij               (sum_i E_i = total energy).
  * `terms` selects the nuclear and/or Coulomb parts.  d_force is [n][3]
- * MeV/fm, d_epot is [n] MeV (may be NULL).  Requires L >= 2 r_nuc.
+ * MeV/fm, d_epot is [n] MeV (may be NULL).  Requires L >= 2 r_nuc (and
+ * L >= 2 r_coul for a finite Coulomb cutoff, which uses the gather form).
  * Internally: a1 cell list with r_cut = r_nuc (r_nuc + list_skin and the
  * neighbour lists in the list form), the nuclear kernel, and the all-pairs
  * screened-Coulomb tile kernel.  The workspace query and the call must see
@@ -267,6 +278,10 @@ int pasta_sim_pair_counts(pasta_sim* sim, int64_t* h_nuclear, int64_t* h_coulomb
 /* Checkpoint/restart: the state is (d_pos, d_vel, step); L follows from the
  * step index.  set_state re-evaluates the forces. */
 int pasta_sim_get_step(pasta_sim* sim, int64_t* h_step);
+/* Copies the current state into caller buffers (d_pos, d_vel: [n][3],
+ * caller order; either may be NULL) and returns its global step index in
+ * *h_step (may be NULL).  Asynchronous for the copies. */
+int pasta_sim_get_state(pasta_sim* sim, double* d_pos, double* d_vel, int64_t* h_step);
 int pasta_sim_set_state(pasta_sim* sim, const double* d_pos, const double* d_vel,
                         int64_t step);
 /* Per-kernel timing with HIP events on the simulation's stream.  When on,

@@ -38,7 +38,8 @@ class PastaError(RuntimeError):
 
 class pasta_potential(ctypes.Structure):
     _fields_ = [(k, ctypes.c_double) for k in
-                ("a", "b", "c", "Lambda", "lambda_s", "alpha_hbarc", "mass", "r_nuc")]
+                ("a", "b", "c", "Lambda", "lambda_s", "alpha_hbarc", "mass", "r_nuc",
+                 "r_coul")]
 
 
 class pasta_tuning(ctypes.Structure):
@@ -76,6 +77,7 @@ def _load():
         "pasta_last_error": (ctypes.c_char_p, []),
         "pasta_version": (ctypes.c_char_p, []),
         "pasta_cell_list_workspace": (ctypes.c_int, [i64, d, d, P(sz)]),
+        "pasta_cell_dims": (ctypes.c_int, [d, d, P(i32)]),
         "pasta_cell_list": (ctypes.c_int, [i64, d, d, vp, vp, vp, vp, P(i32), vp, sz, vp]),
         "pasta_forces_workspace": (ctypes.c_int, [pot, i32, i64, d, P(sz)]),
         "pasta_forces": (ctypes.c_int, [pot, i32, i32, i64, d, vp, vp, vp, vp, vp, sz, vp]),
@@ -88,6 +90,7 @@ def _load():
         "pasta_sim_forces": (ctypes.c_int, [vp, vp, vp]),
         "pasta_sim_pair_counts": (ctypes.c_int, [vp, P(i64), P(i64)]),
         "pasta_sim_get_step": (ctypes.c_int, [vp, P(i64)]),
+        "pasta_sim_get_state": (ctypes.c_int, [vp, vp, vp, P(i64)]),
         "pasta_sim_set_state": (ctypes.c_int, [vp, vp, vp, i64]),
         "pasta_sim_set_timing": (ctypes.c_int, [vp, i32]),
         "pasta_sim_kernel_times": (ctypes.c_int, [vp, vp, vp]),
@@ -206,10 +209,9 @@ def pasta_cell_list(pos, species, L: float, r_cut: float, stream=None):
     nb = ctypes.c_size_t()
     _check(lib.pasta_cell_list_workspace(n, L, r_cut, ctypes.byref(nb)))
     work = _workspace(nb.value, pos.device)
-    from math import floor
-    nc = max(1, int(floor(L / r_cut)))
-    while nc > 1 and L / nc < r_cut:
-        nc -= 1
+    dims = ctypes.c_int32()
+    _check(lib.pasta_cell_dims(L, r_cut, ctypes.byref(dims)))
+    nc = dims.value
     start = torch.empty(2 * nc ** 3 + 1, dtype=torch.int32, device=pos.device)
     perm = torch.empty(n, dtype=torch.int32, device=pos.device)
     ncell = ctypes.c_int32()
@@ -314,6 +316,18 @@ class Sim:
         st = ctypes.c_int64()
         _check(lib.pasta_sim_get_step(self.handle, ctypes.byref(st)))
         return st.value
+
+    def get_state(self, pos=None, vel=None):
+        """Copies the current state into `pos` / `vel` (new tensors when not
+        given); returns (pos, vel, step)."""
+        n = self.pos.shape[0]
+        pos = pos if pos is not None else torch.empty((n, 3), dtype=torch.float64,
+                                                       device=self.pos.device)
+        vel = vel if vel is not None else torch.empty((n, 3), dtype=torch.float64,
+                                                       device=self.pos.device)
+        st = ctypes.c_int64()
+        _check(lib.pasta_sim_get_state(self.handle, _p(pos), _p(vel), ctypes.byref(st)))
+        return pos, vel, st.value
 
     def set_state(self, pos, vel, step: int):
         _check(lib.pasta_sim_set_state(self.handle, _p(pos), _p(vel), step))

@@ -121,6 +121,15 @@ static int timer_collect(Timer* t, hipStream_t s)
     return PASTA_OK;
 }
 
+// A finite Coulomb cutoff (r_coul = +inf: uncut).
+static bool coulomb_cut_finite(const pasta_potential* p) { return std::isfinite(p->r_coul); }
+
+// Largest interaction range: r_nuc, or a finite r_coul beyond it.
+static double max_range(const pasta_potential* p)
+{
+    return coulomb_cut_finite(p) && p->r_coul > p->r_nuc ? p->r_coul : p->r_nuc;
+}
+
 static int check_pot(const pasta_potential* p)
 {
     if (!p)
@@ -132,6 +141,8 @@ static int check_pot(const pasta_potential* p)
             return fail(PASTA_EINVAL, "non-finite potential parameter");
     if (!(p->Lambda > 0) || !(p->lambda_s > 0) || !(p->mass > 0) || !(p->r_nuc > 0))
         return fail(PASTA_EINVAL, "Lambda, lambda_s, mass and r_nuc must be positive");
+    if (!(p->r_coul > 0))  // also NaN; +inf is the uncut model
+        return fail(PASTA_EINVAL, "r_coul must be positive (INFINITY: uncut)");
     return PASTA_OK;
 }
 
@@ -144,6 +155,7 @@ static PairParams pair_params(const pasta_potential* p, double L)
     pp.Lambda = p->Lambda;
     pp.r_nuc = p->r_nuc;
     pp.alpha_hbarc = p->alpha_hbarc;
+    pp.r_coul = coulomb_cut_finite(p) ? p->r_coul : INFINITY;
     pp.lambda_s = p->lambda_s;
     pp.L = L;
     return pp;
@@ -259,22 +271,29 @@ static int build_cells(const double* pos, const uint8_t* species, int64_t n, con
     return PASTA_OK;
 }
 
+// pos / pos_perm: the FP64 positions the staging was built from (row
+// pos_perm[slot], or the slot when pos_perm is null), read only by the
+// finite-cutoff Coulomb test.
 static void eval_forces(int precision, int terms, const ForceWork& w, const Grid& g, int64_t n,
                         int64_t Z, const PairParams& pp, double* force, double* epot,
-                        const KickArgs& kick, uint64_t* pair_counter, hipStream_t s, Timer* t)
+                        const KickArgs& kick, uint64_t* pair_counter, hipStream_t s, Timer* t,
+                        const double* pos, const int32_t* pos_perm)
 {
     const ListBuf* lb = (w.lists && (terms & PASTA_TERM_NUCLEAR)) ? &w.lb : nullptr;
+    ForceBuf fb = w.fb;
+    fb.cut_pos = pos;
+    fb.cut_perm = pos_perm;
     if (g_tuning.fused_forces && (terms & PASTA_TERM_NUCLEAR)) {
-        launch_forces_fused(precision, w.fb, w.cb, g, n, Z, pp, true,
+        launch_forces_fused(precision, fb, w.cb, g, n, Z, pp, true,
                             (terms & PASTA_TERM_COULOMB) != 0, force, epot, kick, pair_counter,
                             w.err, s, t, w.variant, lb);
         return;
     }
     int S = 0;
     if ((terms & PASTA_TERM_COULOMB) && Z > 0)
-        S = launch_coulomb(precision, w.fb, Z, pp, epot != nullptr || pair_counter != nullptr, s,
-                           t);
-    launch_nuclear(precision, w.fb, w.cb, g, n, Z, pp, (terms & PASTA_TERM_NUCLEAR) != 0, S,
+        S = launch_coulomb(precision, fb, Z, pp, epot != nullptr || pair_counter != nullptr, s,
+                           t, pair_counter ? pair_counter + 1 : nullptr);
+    launch_nuclear(precision, fb, w.cb, g, n, Z, pp, (terms & PASTA_TERM_NUCLEAR) != 0, S,
                    force, epot, kick, pair_counter, w.err, s, t, w.variant, lb);
 }
 
@@ -300,6 +319,7 @@ extern "C" void pasta_potential_paper(pasta_potential* out)
     out->alpha_hbarc = 7.2973525693e-3 * 197.3269804;
     out->mass = 939.0;
     out->r_nuc = 11.5;
+    out->r_coul = INFINITY;
 }
 
 extern "C" int pasta_set_tuning(const pasta_tuning* t)
@@ -330,6 +350,14 @@ extern "C" const char* pasta_kernel_class_name(int32_t k)
 }
 
 // ------------------------------------------------------------------- a1
+extern "C" int pasta_cell_dims(double L, double r_cut, int32_t* h_ncell)
+{
+    if (!h_ncell || !(L > 0.0) || !std::isfinite(L) || !(r_cut > 0.0))
+        return fail(PASTA_EINVAL, "pasta_cell_dims: bad argument");
+    *h_ncell = cell_dims(L, r_cut);
+    return PASTA_OK;
+}
+
 extern "C" int pasta_cell_list_workspace(int64_t n, double L, double r_cut, size_t* h_bytes)
 {
     if (!h_bytes || n < 0 || !(L > 0.0) || !(r_cut > 0.0) || !std::isfinite(L))
@@ -403,8 +431,9 @@ static int check_force_args(const char* who, const pasta_potential* pot, int32_t
         !(L > 0.0) || !std::isfinite(L) || (terms & ~PASTA_TERM_ALL) ||
         (precision != PASTA_FP64 && precision != PASTA_MIXED))
         return fail(PASTA_EINVAL, "%s: bad argument", who);
-    if (L < 2.0 * pot->r_nuc)
-        return fail(PASTA_EBOX, "%s: L = %g < 2 r_nuc = %g", who, L, 2.0 * pot->r_nuc);
+    if (L < 2.0 * max_range(pot))
+        return fail(PASTA_EBOX, "%s: L = %g < 2 max(r_nuc, r_coul) = %g", who, L,
+                    2.0 * max_range(pot));
     return PASTA_OK;
 }
 
@@ -438,7 +467,8 @@ static int forces_run(const char* who, const pasta_potential* pot, int32_t preci
                              hipMemcpyDeviceToHost, s));
     PASTA_HIP(hipStreamSynchronize(s));
     KickArgs kick{nullptr, 0.0, pot->mass, nullptr, false};
-    eval_forces(precision, terms, w, g, n, Z, pp, d_force, d_epot, kick, nullptr, s, nullptr);
+    eval_forces(precision, terms, w, g, n, Z, pp, d_force, d_epot, kick, nullptr, s, nullptr,
+                d_pos, w.cb.perm);
     PASTA_HIP(hipGetLastError());
     return read_err(w.err, s, who);
 }
@@ -532,8 +562,8 @@ extern "C" int pasta_autotune(const pasta_potential* pot, int32_t precision, int
     if (n <= 0 || n > INT32_MAX - 1 || !d_pos || !d_species || !h_best || reps < 1 ||
         !(L > 0.0) || !std::isfinite(L) || (precision != PASTA_FP64 && precision != PASTA_MIXED))
         return fail(PASTA_EINVAL, "pasta_autotune: bad argument");
-    if (L < 2.0 * pot->r_nuc)
-        return fail(PASTA_EBOX, "pasta_autotune: L < 2 r_nuc");
+    if (L < 2.0 * max_range(pot))
+        return fail(PASTA_EBOX, "pasta_autotune: L < 2 max(r_nuc, r_coul)");
     // laid out for the 32-target items (the larger item list); 64-target
     // candidates use a prefix of it
     const ListCfg lay = cfg_variant(3);
@@ -615,14 +645,15 @@ extern "C" int pasta_autotune(const pasta_potential* pot, int32_t precision, int
         g_tuning = cands[c];
         cells_for(cands[c].nuclear_variant);
         // one untimed warm-up, then reps timed evaluations
-        eval_forces(precision, PASTA_TERM_ALL, w, g, n, Z, pp, f, e, kick, nullptr, s, nullptr);
+        eval_forces(precision, PASTA_TERM_ALL, w, g, n, Z, pp, f, e, kick, nullptr, s, nullptr,
+                    d_pos, w.cb.perm);
         if (hipEventRecord(e0, s) != hipSuccess) {
             rc = fail(PASTA_EHIP, "hipEventRecord failed");
             break;
         }
         for (int r = 0; r < reps; ++r)
             eval_forces(precision, PASTA_TERM_ALL, w, g, n, Z, pp, f, e, kick, nullptr, s,
-                        nullptr);
+                        nullptr, d_pos, w.cb.perm);
         float ms = 0.f;
         if (hipEventRecord(e1, s) != hipSuccess || hipEventSynchronize(e1) != hipSuccess ||
             hipEventElapsedTime(&ms, e0, e1) != hipSuccess) {
@@ -791,7 +822,7 @@ static int sim_eval_initial(pasta_sim* sim)
     sim->Z = Z;
     KickArgs kick{nullptr, 0.0, sim->pot.mass, nullptr, true};
     eval_forces(sim->precision, PASTA_TERM_ALL, sim->w, g, sim->n, sim->Z, pp, sim->force,
-                sim->epot, kick, nullptr, s, &sim->timer);
+                sim->epot, kick, nullptr, s, &sim->timer, sim->xs[sim->cur], nullptr);
     sim->epot_valid = true;
     PASTA_HIP(hipGetLastError());
     return read_err(sim->w.err, s, "pasta_sim");
@@ -809,7 +840,7 @@ static int sim_refresh_energies(pasta_sim* sim)
     KickArgs kick{nullptr, 0.0, sim->pot.mass, nullptr, true};
     eval_forces(sim->precision, PASTA_TERM_ALL, sim->w, g, sim->n, sim->Z,
                 pair_params(&sim->pot, L), sim->force, sim->epot, kick, nullptr, sim->stream,
-                nullptr);
+                nullptr, sim->xs[sim->cur], nullptr);
     PASTA_HIP(hipGetLastError());
     sim->epot_valid = true;
     return PASTA_OK;
@@ -843,9 +874,9 @@ extern "C" int pasta_sim_create(const pasta_potential* pot, const pasta_integrat
     sim->stream = static_cast<hipStream_t>(stream);
     const double Lstart = box_side(sim, step0);
     sim->L_max = L_max > Lstart ? L_max : Lstart;
-    if (Lstart < 2.0 * pot->r_nuc) {
+    if (Lstart < 2.0 * max_range(pot)) {
         delete sim;
-        return fail(PASTA_EBOX, "pasta_sim_create: L = %g < 2 r_nuc", Lstart);
+        return fail(PASTA_EBOX, "pasta_sim_create: L = %g < 2 max(r_nuc, r_coul)", Lstart);
     }
     // the nuclear variant (and the list settings) in force when the
     // simulation is created stay with it; the list memory takes the rest of
@@ -902,7 +933,7 @@ extern "C" int pasta_sim_step(pasta_sim* sim, int64_t nsteps)
     const pasta_integrator& gi = sim->integ;
     const double hdtm = gi.dt / (2.0 * sim->pot.mass);
     auto box_ok = [&](double L) {
-        return !(L > sim->L_max * (1.0 + 1e-12) || L < 2.0 * sim->pot.r_nuc);
+        return !(L > sim->L_max * (1.0 + 1e-12) || L < 2.0 * max_range(&sim->pot));
     };
     // drifted: this step's first part (half kick, drift, binning) was done by
     // the previous step's combine kernel (cell form, fused forces: every step
@@ -976,7 +1007,7 @@ extern "C" int pasta_sim_step(pasta_sim* sim, int64_t nsteps)
             kick.next = &nd;
         }
         eval_forces(sim->precision, PASTA_TERM_ALL, sim->w, g, sim->n, sim->Z, pp, sim->force,
-                    nullptr, kick, nullptr, s, &sim->timer);
+                    nullptr, kick, nullptr, s, &sim->timer, sim->xs[sim->cur], nullptr);
         drifted = fuse;
         sim->epot_valid = false;
         if (thermo)
@@ -1048,7 +1079,8 @@ extern "C" int pasta_sim_pair_counts(pasta_sim* sim, int64_t* h_nuclear, int64_t
     KickArgs kick{nullptr, 0.0, sim->pot.mass, nullptr, true};
     // the cell list and staging of the current state are in place
     eval_forces(sim->precision, PASTA_TERM_ALL, sim->w, g, sim->n, sim->Z,
-                pair_params(&sim->pot, L), sim->force, sim->epot, kick, ctr, s, nullptr);
+                pair_params(&sim->pot, L), sim->force, sim->epot, kick, ctr, s, nullptr,
+                sim->xs[sim->cur], nullptr);
     sim->epot_valid = true;
     uint64_t h[2] = {0, 0};
     PASTA_HIP(hipMemcpyAsync(h, ctr, sizeof(h), hipMemcpyDeviceToHost, s));
@@ -1056,7 +1088,8 @@ extern "C" int pasta_sim_pair_counts(pasta_sim* sim, int64_t* h_nuclear, int64_t
     if (h_nuclear)
         *h_nuclear = (int64_t)(h[0] / 2);  // ordered -> unordered
     if (h_coulomb)
-        *h_coulomb = sim->Z * (sim->Z - 1) / 2;
+        *h_coulomb = coulomb_cut_finite(&sim->pot) ? (int64_t)(h[1] / 2)  // ordered -> unordered
+                                                   : sim->Z * (sim->Z - 1) / 2;
     return PASTA_OK;
 }
 
@@ -1093,13 +1126,26 @@ extern "C" int pasta_sim_get_step(pasta_sim* sim, int64_t* h_step)
     return PASTA_OK;
 }
 
+extern "C" int pasta_sim_get_state(pasta_sim* sim, double* d_pos, double* d_vel, int64_t* h_step)
+{
+    if (!sim)
+        return fail(PASTA_EINVAL, "pasta_sim_get_state: null sim");
+    if (d_pos || d_vel)
+        launch_export(sim->ids[sim->cur], sim->n, sim->xs[sim->cur], d_pos, sim->vs[sim->cur],
+                      d_vel, nullptr, nullptr, sim->stream);
+    PASTA_HIP(hipGetLastError());
+    if (h_step)
+        *h_step = sim->step;
+    return PASTA_OK;
+}
+
 extern "C" int pasta_sim_set_state(pasta_sim* sim, const double* d_pos, const double* d_vel,
                                    int64_t step)
 {
     if (!sim || step < 0)
         return fail(PASTA_EINVAL, "pasta_sim_set_state: bad argument");
     const double L = box_side(sim, step);
-    if (L > sim->L_max * (1.0 + 1e-12) || L < 2.0 * sim->pot.r_nuc)
+    if (L > sim->L_max * (1.0 + 1e-12) || L < 2.0 * max_range(&sim->pot))
         return fail(PASTA_EBOX, "pasta_sim_set_state: box side %g out of range", L);
     hipStream_t s = sim->stream;
     if (d_pos && d_pos != sim->pos)

@@ -817,6 +817,9 @@ int batch_chunk() { return nuclear_chunk_for(batch_variant()); }
 int batch_layout(const pasta_potential* pot, int nsys, const int64_t* n, const int64_t* Z,
                  const double* L_max, BatchLayout* out)
 {
+    if (!(pot->r_coul > 0) || std::isfinite(pot->r_coul))
+        return fail(PASTA_EINVAL, "pasta_batch: the batched path takes the uncut Coulomb term "
+                                  "only (r_coul = INFINITY)");
     BatchLayout lay;
     lay.sys.resize(nsys);
     for (int s = 0; s < nsys; ++s) {
@@ -1094,6 +1097,7 @@ extern "C" int pasta_batch_create(const pasta_potential* pot, int32_t precision,
     B.pp.b_unlike = pot->b - pot->c;
     B.pp.Lambda = pot->Lambda;
     B.pp.r_nuc = pot->r_nuc;
+    B.pp.r_coul = INFINITY;
     B.pp.alpha_hbarc = pot->alpha_hbarc;
     B.pp.lambda_s = pot->lambda_s;
     B.pp.L = 0.0;

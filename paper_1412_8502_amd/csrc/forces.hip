@@ -30,14 +30,15 @@ namespace pasta {
 
 namespace {
 
-template <class P, bool E>
+template <class P, bool E, bool CUT>
 __global__ __launch_bounds__(WG) void k_coulomb(const typename P::Src* __restrict__ stg, int Z,
-                                                int per_split, CoulConsts k, void* part)
+                                                int per_split, CoulConsts k, void* part,
+                                                CoulCut cc)
 {
     __shared__ __align__(16) char lds[coulomb_lds_bytes<P>()];
     using PT = typename P::CPart;
-    coulomb_item<P, E, PT>(stg, Z, per_split, k, static_cast<PT*>(part), blockIdx.x, blockIdx.y,
-                           lds);
+    coulomb_item<P, E, PT, CUT>(stg, Z, per_split, k, static_cast<PT*>(part), blockIdx.x,
+                                blockIdx.y, lds, cc);
 }
 
 template <class P, bool E>
@@ -126,13 +127,14 @@ constexpr int fused_lds_bytes()
 }
 
 // CF: Coulomb form, 0 = gather tiles (coul_blocks x splits items), 1 =
-// pairwise super-block items.
+// pairwise super-block items, 2 = gather tiles with a finite cutoff.
 template <class P, int MODE, int V, int CF>
 __global__ __launch_bounds__(WG) void k_forces_fused(const typename P::Src* __restrict__ stg,
                                                      NucArgs A, const int32_t* __restrict__ n_items,
                                                      int item_max, NucConsts k, int Z,
                                                      int per_split, int coul_blocks,
-                                                     CoulConsts kc, void* part_raw, ListArgs LA)
+                                                     CoulConsts kc, void* part_raw, ListArgs LA,
+                                                     CoulCut cc)
 {
     __shared__ __align__(16) char lds[fused_lds_bytes<P, V>()];
     using PT = typename P::CPart;
@@ -154,8 +156,9 @@ __global__ __launch_bounds__(WG) void k_forces_fused(const typename P::Src* __re
         if constexpr (CF == 1)
             coulomb_pair_item<P, MODE != MODE_FORCE, PT>(stg, Z, kc, part, h, lds);
         else
-            coulomb_item<P, MODE != MODE_FORCE, PT>(stg, Z, per_split, kc, part, h % coul_blocks,
-                                                    h / coul_blocks, lds);
+            coulomb_item<P, MODE != MODE_FORCE, PT, CF == 2>(stg, Z, per_split, kc, part,
+                                                             h % coul_blocks, h / coul_blocks, lds,
+                                                             cc);
     }
 }
 
@@ -393,12 +396,15 @@ int coulomb_splits(int64_t Z, int64_t cap)
 
 int coulomb_pair_plan_supers(int64_t Z) { return coulomb_pair_supers(Z); }
 
-CoulPlan coulomb_plan(int64_t Z, int64_t coul_max)
+CoulPlan coulomb_plan(int64_t Z, int64_t coul_max, bool cut)
 {
     CoulPlan p{0, 0};
     if (Z <= 0)
         return p;
-    if (g_tuning.coulomb_form == 1 && (int64_t)coulomb_pair_supers(Z) * Z <= coul_max) {
+    if (cut) {
+        p.form = 2;
+        p.S = coulomb_splits(Z, coul_max);
+    } else if (g_tuning.coulomb_form == 1 && (int64_t)coulomb_pair_supers(Z) * Z <= coul_max) {
         p.form = 1;
         p.S = coulomb_pair_supers(Z);
     } else {
@@ -429,7 +435,12 @@ void launch_forces_fused(int precision, const ForceBuf& fb, const CellBuf& cb, c
 {
     const NucConsts k = make_nuc_consts(pp);
     const CoulConsts kc = make_coul_consts(pp);
-    const CoulPlan plan = (with_coulomb && Z > 0) ? coulomb_plan(Z, fb.coul_max) : CoulPlan{0, 0};
+    const bool cut = std::isfinite(pp.r_coul);
+    const CoulPlan plan = (with_coulomb && Z > 0) ? coulomb_plan(Z, fb.coul_max, cut)
+                                                  : CoulPlan{0, 0};
+    const CoulCut cc{fb.cut_pos, fb.cut_perm,
+                     pair_counter ? reinterpret_cast<unsigned long long*>(pair_counter + 1)
+                                  : nullptr};
     const int S = plan.S;
     const int per = S ? (int)((Z + S - 1) / S) : 0;
     const int coul_blocks = S ? (int)((Z + WG - 1) / WG) : 0;
@@ -463,14 +474,16 @@ void launch_forces_fused(int precision, const ForceBuf& fb, const CellBuf& cb, c
                 if (precision == PASTA_FP64)
                     k_forces_fused<Fp64Policy, M, V, CF><<<grid, WG, 0, s>>>(
                         fb.stg64, a, cb.n_items, item_max, k, (int)Z, per, coul_blocks, kc,
-                        fb.coul_part, la);
+                        fb.coul_part, la, cc);
                 else
                     k_forces_fused<MixedPolicy, M, V, CF><<<grid, WG, 0, s>>>(
                         fb.stgq, a, cb.n_items, item_max, k, (int)Z, per, coul_blocks, kc,
-                        fb.coul_part, la);
+                        fb.coul_part, la, cc);
             };
             if (plan.form == 1)
                 launch(std::integral_constant<int, 1>());
+            else if (plan.form == 2)
+                launch(std::integral_constant<int, 2>());
             else
                 launch(std::integral_constant<int, 0>());
         };
@@ -528,13 +541,16 @@ size_t forcebuf_carve(Carver& cv, ForceBuf* out, int64_t n, int64_t item_max, in
 }
 
 int launch_coulomb(int precision, const ForceBuf& fb, int64_t Z, const PairParams& pp,
-                   bool energy, hipStream_t s, Timer* t)
+                   bool energy, hipStream_t s, Timer* t, uint64_t* count)
 {
     if (Z <= 0)
         return 0;
-    const CoulPlan plan = coulomb_plan(Z, fb.coul_max);
+    const bool cut = std::isfinite(pp.r_coul);
+    const CoulPlan plan = coulomb_plan(Z, fb.coul_max, cut);
     const int S = plan.S;
     const int per = (int)((Z + S - 1) / S);
+    const CoulCut cc{fb.cut_pos, fb.cut_perm,
+                     count ? reinterpret_cast<unsigned long long*>(count) : nullptr};
     const CoulConsts k = make_coul_consts(pp);
     void* co = fb.coul_part;
     timer_begin(t, KC_COULOMB, s);
@@ -555,17 +571,19 @@ int launch_coulomb(int precision, const ForceBuf& fb, int64_t Z, const PairParam
         return S;
     }
     dim3 grid((unsigned)((Z + WG - 1) / WG), (unsigned)S);
-    if (precision == PASTA_FP64) {
-        if (energy)
-            k_coulomb<Fp64Policy, true><<<grid, WG, 0, s>>>(fb.stg64, (int)Z, per, k, co);
+    auto go = [&](auto etag, auto ctag) {
+        constexpr bool E = decltype(etag)::value, C = decltype(ctag)::value;
+        if (precision == PASTA_FP64)
+            k_coulomb<Fp64Policy, E, C><<<grid, WG, 0, s>>>(fb.stg64, (int)Z, per, k, co, cc);
         else
-            k_coulomb<Fp64Policy, false><<<grid, WG, 0, s>>>(fb.stg64, (int)Z, per, k, co);
-    } else {
-        if (energy)
-            k_coulomb<MixedPolicy, true><<<grid, WG, 0, s>>>(fb.stgq, (int)Z, per, k, co);
-        else
-            k_coulomb<MixedPolicy, false><<<grid, WG, 0, s>>>(fb.stgq, (int)Z, per, k, co);
-    }
+            k_coulomb<MixedPolicy, E, C><<<grid, WG, 0, s>>>(fb.stgq, (int)Z, per, k, co, cc);
+    };
+    using T_ = std::true_type;
+    using F_ = std::false_type;
+    if (energy)
+        cut ? go(T_(), T_()) : go(T_(), F_());
+    else
+        cut ? go(F_(), T_()) : go(F_(), F_());
     timer_end(t, KC_COULOMB, s);
     return S;
 }

@@ -366,9 +366,16 @@ void launch_export(const int32_t* id, int64_t n, const double* src3a, double* ds
 struct PairParams {
     // nuclear (Eq. 1a,b)
     double a, b_like, b_unlike, Lambda, r_nuc;
-    // Coulomb (Eq. 1c)
-    double alpha_hbarc, lambda_s;
+    // Coulomb (Eq. 1c); r_coul = +inf: uncut
+    double alpha_hbarc, lambda_s, r_coul;
     double L;
+};
+// A finite Coulomb cutoff is decided on the FP64 r^2 of the positions the
+// staging was built from: pos [n][3], row perm[slot] (perm null: row slot).
+struct CoulCut {
+    const double* pos;
+    const int32_t* perm;
+    unsigned long long* count;  // ordered pairs kept (counting calls), or null
 };
 struct KickArgs {
     double* vel;       // [n][3] or nullptr (no kick)
@@ -401,7 +408,11 @@ struct ForceBuf {
     double* ke_part;    // [item_max] kinetic-energy partials of the last kick
     int32_t* n_ke;      // [1] number of valid ke_part entries (fused form)
     double4* fnuc;      // [n] nuclear (F, V) per sorted slot (fused form)
-    uint64_t* pairs;    // [2] diagnostic pair counters
+    uint64_t* pairs;    // [2] diagnostic pair counters (nuclear, Coulomb; ordered)
+    // FP64 positions the staging was built from, for a finite Coulomb
+    // cutoff (set per evaluation; see CoulCut)
+    const double* cut_pos = nullptr;
+    const int32_t* cut_perm = nullptr;
 };
 // Automatic source splits of the gather form (about 2^19 / Z, at most 32,
 // at most cap / Z); the tuning's coulomb_splits overrides.
@@ -411,10 +422,10 @@ int coulomb_splits(int64_t Z, int64_t cap = 524288);
 // 256 protons; used when S Z partials fit coul_max).  Every proton gets S
 // partials.
 struct CoulPlan {
-    int form;
+    int form;  // 0 gather, 1 pairwise, 2 gather with a finite cutoff
     int S;
 };
-CoulPlan coulomb_plan(int64_t Z, int64_t coul_max);
+CoulPlan coulomb_plan(int64_t Z, int64_t coul_max, bool cut = false);
 // Partials a force workspace holds for n particles: enough for the gather
 // form's default splits and for the pairwise form up to Z = 0.4 n.
 int64_t coulomb_partial_capacity(int64_t n);
@@ -427,8 +438,9 @@ size_t forcebuf_carve(Carver& cv, ForceBuf* out, int64_t n, int64_t item_max, in
 // Coulomb all-pairs over protons (sorted slots [0, Z)).
 // energy: also accumulate the energy shares (else the partials' w is 0).
 // Returns the number of partials per proton written (the S to add).
+// count (optional): ordered Coulomb pairs kept by a finite cutoff.
 int launch_coulomb(int precision, const ForceBuf& fb, int64_t Z, const PairParams& pp,
-                   bool energy, hipStream_t s, Timer* t);
+                   bool energy, hipStream_t s, Timer* t, uint64_t* count = nullptr);
 // Nuclear cell-tile kernel; adds the coul_S Coulomb partials of proton
 // targets (coul_S = 0: none),
 // writes F and E at the caller index (perm[slot]) or at the sorted slot

@@ -34,6 +34,13 @@ __device__ __forceinline__ double nearest_image(double d, double L, double hL)
     return d > hL ? d - L : (d < -hL ? d + L : d);
 }
 
+// r^2 = (dx dx + dy dy) + dz dz with every product and sum rounded on its
+// own (no fused multiply-add), the order of the definition.
+__device__ __forceinline__ double r2_exact(double dx, double dy, double dz)
+{
+    return __dadd_rn(__dadd_rn(__dmul_rn(dx, dx), __dmul_rn(dy, dy)), __dmul_rn(dz, dz));
+}
+
 // What a pair kernel accumulates: forces only, forces and energy shares,
 // or forces, energies and the count of pairs inside the cutoff.
 constexpr int MODE_FORCE = 0;
@@ -99,6 +106,11 @@ struct CoulConsts {
     float c_exp, cA, cB;
     double v_scale;  // alpha_hbarc / q  (V = v_scale * w)
     double f_scale;  // alpha_hbarc      (F = f_scale * fs_u * du)
+    // finite cutoff: keep r^2 < rc2 (FP64, fm^2); the mixed form decides on
+    // its FP32 r^2 (q^2 units) below thr_lo or at/above thr_hi and on the
+    // FP64 r^2 of the positions in between
+    double rc2;
+    float thr_lo, thr_hi;
 };
 
 __host__ __device__ inline CoulConsts make_coul_consts(const PairParams& pp)
@@ -114,6 +126,12 @@ __host__ __device__ inline CoulConsts make_coul_consts(const PairParams& pp)
     k.cB = (float)(1.0 / (pp.lambda_s * q));
     k.v_scale = pp.alpha_hbarc / q;
     k.f_scale = pp.alpha_hbarc;
+    k.rc2 = pp.r_coul * pp.r_coul;  // +inf when uncut
+    // the FP32 r^2 of the fixed-point difference is within 2e-7 (rounding)
+    // + 4 q / r (quantisation) of the FP64 one; the band is far wider
+    const double rc2q = k.rc2 / (q * q);
+    k.thr_lo = (float)(rc2q * (1.0 - 4e-6));
+    k.thr_hi = (float)(rc2q * (1.0 + 4e-6));
     return k;
 }
 
@@ -204,6 +222,18 @@ struct Fp64Policy {
     }
     __device__ static double coul_fscale(const CoulConsts&) { return 1.0; }
     __device__ static double coul_vscale(const CoulConsts&) { return 1.0; }
+    // Finite Coulomb cutoff: r^2 as the definition forms it (strict nearest
+    // image, (dx dx + dy dy) + dz dz, no fused multiply-add), compared with
+    // rc2; never undecided.
+    __device__ static bool coul_cut_in(const Src& me, const Lds& s, const CoulConsts& k,
+                                       bool& undecided)
+    {
+        const double dx = nearest_image(me.x - s.x, k.L, k.hL);
+        const double dy = nearest_image(me.y - s.y, k.L, k.hL);
+        const double dz = nearest_image(me.z - s.z, k.L, k.hL);
+        undecided = false;
+        return r2_exact(dx, dy, dz) < k.rc2;
+    }
     // 32-bit fixed-point coordinates (x/L * 2^32) for the screening pass
     __device__ static uint3 fixed(const Src& s, const NucConsts& k)
     {
@@ -304,6 +334,19 @@ struct MixedPolicy {
     }
     __device__ static double coul_fscale(const CoulConsts& k) { return k.f_scale; }
     __device__ static double coul_vscale(const CoulConsts& k) { return k.v_scale; }
+    // Finite Coulomb cutoff on the FP32 r^2 of the exact fixed-point
+    // difference; pairs in the narrow band around the cutoff are left to the
+    // FP64 test on the positions (coul_cut_exact).
+    __device__ static bool coul_cut_in(const Src& me, const Lds& s, const CoulConsts& k,
+                                       bool& undecided)
+    {
+        const float dx = (float)(int32_t)(me.x - s.x);
+        const float dy = (float)(int32_t)(me.y - s.y);
+        const float dz = (float)(int32_t)(me.z - s.z);
+        const float r2 = dx * dx + dy * dy + dz * dz;
+        undecided = r2 >= k.thr_lo && r2 < k.thr_hi;
+        return r2 < k.thr_lo;
+    }
     __device__ static uint3 fixed(const Src& s, const NucConsts&)
     {
         return make_uint3(s.x, s.y, s.z);
@@ -346,10 +389,24 @@ __device__ __forceinline__ void store_part(float4* p, double x, double y, double
 // ============================================================ Coulomb ==
 // Targets are the proton slots [tb, tb + WG) ∩ [0, Z); sources the slots
 // [split * per_split, ...).  Writes part[split * Z + t] = (Fx, Fy, Fz, sum V).
-template <class P, bool E = true, class PT = double4>
+// The FP64 cutoff test of the definition on the positions of proton slots
+// a and b (the undecided band of the mixed form's test).
+__device__ inline bool coul_cut_exact(const CoulCut& cc, const CoulConsts& k, int a, int b)
+{
+    const int64_t ia = cc.perm ? cc.perm[a] : a, ib = cc.perm ? cc.perm[b] : b;
+    const double dx = nearest_image(cc.pos[3 * ia + 0] - cc.pos[3 * ib + 0], k.L, k.hL);
+    const double dy = nearest_image(cc.pos[3 * ia + 1] - cc.pos[3 * ib + 1], k.L, k.hL);
+    const double dz = nearest_image(cc.pos[3 * ia + 2] - cc.pos[3 * ib + 2], k.L, k.hL);
+    return r2_exact(dx, dy, dz) < k.rc2;
+}
+
+// CUT: a finite Coulomb cutoff (k.rc2): a pair outside enters as the self
+// pair does (exactly zero); cc.count, when set, counts the ordered pairs
+// kept.
+template <class P, bool E = true, class PT = double4, bool CUT = false>
 __device__ void coulomb_item(const typename P::Src* __restrict__ stg, int Z, int per_split,
                              const CoulConsts& k, PT* __restrict__ part, int tblock,
-                             int split, char* lds)
+                             int split, char* lds, const CoulCut& cc = CoulCut{})
 {
     using Lds = typename P::Lds;
     Lds* tile = reinterpret_cast<Lds*>(lds);
@@ -359,13 +416,24 @@ __device__ void coulomb_item(const typename P::Src* __restrict__ stg, int Z, int
     const int tb0 = tblock * WG, tb1 = min(Z, tb0 + WG);
     const typename P::Src me = stg[t < Z ? t : 0];
     double fx = 0, fy = 0, fz = 0, e = 0;
+    unsigned long long kept = 0;
     for (int base = j0; base < j1; base += P::TILE) {
         const int cnt = min(P::TILE, j1 - base);
         for (int q = threadIdx.x; q < cnt; q += WG)
             tile[q] = P::load(stg, base + q);
         __syncthreads();
         typename P::CAcc ax = 0, ay = 0, az = 0, ae = 0;
-        if (base < tb1 && base + cnt > tb0) {
+        if constexpr (CUT) {
+            for (int q = 0; q < cnt; ++q) {
+                bool undecided;
+                bool in = P::coul_cut_in(me, tile[q], k, undecided);
+                if (undecided && t < Z)
+                    in = coul_cut_exact(cc, k, t, base + q);
+                const bool skip = base + q == t || !in;
+                kept += (!skip && t < Z) ? 1ull : 0ull;
+                P::template coul<E>(me, tile[q], skip, k, ax, ay, az, ae);
+            }
+        } else if (base < tb1 && base + cnt > tb0) {
             for (int q = 0; q < cnt; ++q)
                 P::template coul<E>(me, tile[q], base + q == t, k, ax, ay, az, ae);
         } else {
@@ -382,6 +450,14 @@ __device__ void coulomb_item(const typename P::Src* __restrict__ stg, int Z, int
     if (t < Z) {
         const double fs = P::coul_fscale(k), vs = P::coul_vscale(k);
         store_part(&part[(int64_t)split * Z + t], fx * fs, fy * fs, fz * fs, e * vs);
+    }
+    if constexpr (CUT) {
+        if (cc.count) {
+            for (int m = 32; m >= 1; m >>= 1)
+                kept += __shfl_xor(kept, m, 64);
+            if ((threadIdx.x & 63) == 0)
+                atomicAdd(cc.count, kept);
+        }
     }
 }
 

@@ -27,6 +27,7 @@ def test_paper_potential(B):
     p = B.pasta_potential_paper()
     assert (p.a, p.b, p.c, p.Lambda, p.lambda_s, p.mass, p.r_nuc) == \
         (110.0, -26.0, 24.0, 1.25, 10.0, 939.0, 11.5)
+    assert p.r_coul == float("inf")  # the paper's Coulomb term is uncut
     assert abs(p.alpha_hbarc - 1.4399645) < 1e-7
     assert "gfx950" in B.pasta_version()
 
@@ -59,6 +60,13 @@ def test_workspace_queries(B):
         B.pasta_set_tuning(**old)
     assert B.lib.pasta_cluster_workspace(3200, 43.09, 4.5, 3.0, ctypes.byref(nb)) == 0
     assert B.lib.pasta_cell_list_workspace(3200, 43.09, 11.5, ctypes.byref(nb)) == 0
+    # the cell-grid sizing query: the largest ncell with L / ncell >= r_cut
+    nc = ctypes.c_int32()
+    for L, rc, want in ((43.0887, 11.5, 3), (23.0, 11.5, 2), (86.18, 11.5, 7), (344.71, 11.5, 29),
+                        (46.0, 11.5, 4), (45.99, 11.5, 3), (10.0, 11.5, 1)):
+        assert B.lib.pasta_cell_dims(L, rc, ctypes.byref(nc)) == 0
+        assert nc.value == want, (L, rc, nc.value)
+    assert B.lib.pasta_cell_dims(-1.0, 11.5, ctypes.byref(nc)) == -1
 
 
 def test_argument_errors(B):
@@ -75,7 +83,22 @@ def test_argument_errors(B):
     # box below twice the cutoff: nearest image ambiguous
     assert B.lib.pasta_forces(ctypes.byref(p), 0, 3, 10, 22.9, fake, fake, fake, None, fake,
                               1 << 30, None) == -2
-    assert "2 r_nuc" in B.lib.pasta_last_error().decode()
+    assert "2 max(r_nuc, r_coul)" in B.lib.pasta_last_error().decode()
+    # a finite Coulomb cutoff needs L >= 2 r_coul; NaN or non-positive is refused
+    cut = B.pasta_potential_paper()
+    cut.r_coul = 20.0
+    assert B.lib.pasta_forces(ctypes.byref(cut), 0, 3, 10, 39.9, fake, fake, fake, None, fake,
+                              1 << 30, None) == -2
+    for v in (float("nan"), 0.0, -5.0):
+        cut.r_coul = v
+        assert B.lib.pasta_forces(ctypes.byref(cut), 0, 3, 10, 50.0, fake, fake, fake, None,
+                                  fake, 1 << 30, None) == -1
+    # the batched path takes the uncut Coulomb term only
+    cut.r_coul = 20.0
+    ns = (ctypes.c_int64 * 1)(1000)
+    lm = (ctypes.c_double * 1)(50.0)
+    nbb = ctypes.c_size_t()
+    assert B.lib.pasta_batch_workspace(ctypes.byref(cut), 1, 1, ns, lm, ctypes.byref(nbb)) == -1
     # workspace too small / misaligned
     assert B.lib.pasta_forces(ctypes.byref(p), 0, 3, 10, 30.0, fake, fake, fake, None, fake,
                               16, None) == -3

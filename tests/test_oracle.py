@@ -105,6 +105,34 @@ def test_screened_coulomb_constants(oracle_mod, paper):
     assert v_np == 0.0
 
 
+def test_coulomb_cutoff_option(oracle_mod):
+    """The optional Coulomb cutoff r_coul (not in the paper, whose Coulomb term
+    is uncut): a proton pair at r < r_coul carries the full screened Coulomb
+    force and energy (closed form, no shift), one at r = r_coul exactly or
+    beyond carries nothing; pair counts follow."""
+    L, rc = 100.0, 20.0
+    params = dict(r_coul=rc)
+    for r, inside in ((19.5, True), (20.0, False), (20.5, False)):
+        pos = np.full((2, 3), 50.0)
+        pos[0, 0], pos[1, 0] = 30.0, 30.0 + r
+        sp = np.array([1, 1], np.uint8)
+        f, e = oracle_mod.forces(pos, sp, L, params=params)
+        nn, nc = oracle_mod.pair_counts(pos, sp, L, params=params)
+        assert nn == 0 and nc == (1 if inside else 0)
+        if inside:
+            v = 1.4399645 * math.exp(-r / 10.0) / r
+            fmag = v * (1.0 / r + 1.0 / 10.0) / r * r   # |F| = -dV/dr
+            assert e.sum() == pytest.approx(v, rel=1e-7)
+            # the pair repels: particle 0 (lower x) is pushed to -x
+            assert f[0, 0] == pytest.approx(-fmag, rel=1e-7) and f[1, 0] == -f[0, 0]
+        else:
+            assert np.all(f == 0.0) and e.sum() == 0.0
+    # uncut by default: the same pair at 20.5 fm interacts
+    pos = np.array([[30.0, 50.0, 50.0], [50.5, 50.0, 50.0]])
+    f, e = oracle_mod.forces(pos, np.array([1, 1], np.uint8), L)
+    assert e.sum() > 0.0 and f[0, 0] < 0.0
+
+
 def test_periodic_face(oracle_mod):
     """x = 1 and x = L - 1 interact as a pair 2 fm apart (nearest image)."""
     L = 40.0
