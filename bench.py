@@ -143,17 +143,26 @@ def run_path(B, torch, st, precision, steps, warmup, timing, pot=None):
                 steps=steps + (steps if timing else 0) + warmup)
 
 
-def run_batch(B, torch, states, precision, mode, steps, warmup, spg=10):
+def run_batch(B, torch, states, precision, mode, steps, warmup, spg=10, tune=False):
     """The 15-system grid advanced together (one persistent launch per step
-    for mode 0, one launch per phase for mode 1), from a captured hipGraph."""
+    for mode 0, one launch per phase for mode 1), from a captured hipGraph.
+    tune: choose the kernel setting on this workload first (timed runs)."""
     import numpy as np
     dev = torch.device("cuda:0")
     pos = torch.tensor(np.concatenate([s["pos"] for s in states]), device=dev)
     vel = torch.tensor(np.concatenate([s["vel"] for s in states]), device=dev)
     sp = torch.tensor(np.concatenate([s["species"] for s in states]), device=dev)
-    b = B.Batch(pos, vel, sp, [s["n"] for s in states], [s["L"] for s in states],
-                [dict(dt=2.0, T=s["T"], rescale_every=100) for s in states],
-                precision=precision, mode=mode, steps_per_graph=spg)
+    ns, L0s = [s["n"] for s in states], [s["L"] for s in states]
+    integs = [dict(dt=2.0, T=s["T"], rescale_every=100) for s in states]
+    saved = B.pasta_get_tuning()
+    best, table = None, None
+    if tune:
+        from paper_1412_8502_amd.autotune import tune_batch
+        best, table = tune_batch(pos, vel, sp, ns, L0s, integs, precision, mode=mode)
+        B.pasta_set_tuning(**best)
+    b = B.Batch(pos, vel, sp, ns, L0s, integs, precision=precision, mode=mode,
+                steps_per_graph=spg)
+    B.pasta_set_tuning(**saved)
     b.step(warmup)
     torch.cuda.synchronize()
     nn, nc = b.pair_counts()
@@ -164,7 +173,8 @@ def run_batch(B, torch, states, precision, mode, steps, warmup, spg=10):
     dt = time.perf_counter() - t0
     info = b.info()
     b.close()
-    return dict(seconds=dt, pairs_per_step=float(sum(nn) + sum(nc)), grid=info["grid"])
+    return dict(seconds=dt, pairs_per_step=float(sum(nn) + sum(nc)), grid=info["grid"],
+                tuning=best, tuning_table=[[c, round(ms, 5)] for c, ms in table] if table else None)
 
 
 def run_sequential(B, torch, states, precision, steps, warmup):
@@ -303,12 +313,16 @@ def batched_section(B, torch, steps, warmup):
         return {"ms_per_step": r["seconds"] / steps * 1e3,
                 "system_steps_per_s": nsys * steps / r["seconds"],
                 "pair_interactions_per_s": r["pairs_per_step"] * steps / r["seconds"]}
-    pers = run_batch(B, torch, states, B.PASTA_MIXED, 0, steps, warmup)
-    log(f"batched persistent: {pers['seconds'] / steps * 1e3:.4f} ms/step")
-    out["persistent_mixed"] = dict(entry(pers), grid=pers["grid"])
-    multi = run_batch(B, torch, states, B.PASTA_MIXED, 1, steps, warmup)
-    log(f"batched multi-kernel: {multi['seconds'] / steps * 1e3:.4f} ms/step")
-    out["multi_kernel_mixed"] = entry(multi)
+    pers = run_batch(B, torch, states, B.PASTA_MIXED, 0, steps, warmup, tune=True)
+    log(f"batched persistent: {pers['seconds'] / steps * 1e3:.4f} ms/step, tuned "
+        f"{pers['tuning']} from {pers['tuning_table']}")
+    out["persistent_mixed"] = dict(entry(pers), grid=pers["grid"], tuning=pers["tuning"],
+                                   tuning_trials_ms=pers["tuning_table"])
+    multi = run_batch(B, torch, states, B.PASTA_MIXED, 1, steps, warmup, tune=True)
+    log(f"batched multi-kernel: {multi['seconds'] / steps * 1e3:.4f} ms/step, tuned "
+        f"{multi['tuning']}")
+    out["multi_kernel_mixed"] = dict(entry(multi), tuning=multi["tuning"],
+                                     tuning_trials_ms=multi["tuning_table"])
     seqm = run_sequential(B, torch, states, B.PASTA_MIXED, steps, warmup)
     log(f"sequential mixed: {seqm['seconds'] / steps * 1e3:.4f} ms/step")
     out["sequential_mixed"] = entry(seqm)
@@ -377,7 +391,7 @@ def main():
                     help="skip the N = 409 600 section")
     ap.add_argument("--no-decompression", action="store_true",
                     help="skip the 20 000-step decompression window")
-    ap.add_argument("--section", choices=("large", "decompression"), default=None,
+    ap.add_argument("--section", choices=("large", "decompression", "batch"), default=None,
                     help="run only this section and print its JSON (for profiler runs)")
     ap.add_argument("--tuning", default=None,
                     help="variant,splits,fused[,coulomb_form]: use this kernel setting instead "
@@ -399,6 +413,17 @@ def main():
     from paper_1412_8502_amd import binding as B
     from paper_1412_8502_amd.inputs import workload
 
+    if args.section == "batch":
+        res = batched_section(B, torch, args.batch_steps, min(args.warmup, 20))
+        st1 = workload(WORKLOAD)
+        vb = run_batch(B, torch, [st1], B.PASTA_MIXED, 1, args.steps, args.warmup)
+        vb0 = run_batch(B, torch, [st1], B.PASTA_MIXED, 0, args.steps, args.warmup)
+        res["single_system_via_batch_path"] = {
+            "multi_kernel_ms_per_step": vb["seconds"] / args.steps * 1e3,
+            "persistent_ms_per_step": vb0["seconds"] / args.steps * 1e3}
+        log(f"single system via batch: {res['single_system_via_batch_path']}")
+        print(json.dumps({"section": "batch", "result": res}))
+        return
     if args.section:
         fn = large_section if args.section == "large" else decompression_section
         print(json.dumps({"section": args.section, "result": fn(B, torch)}))

@@ -136,6 +136,9 @@ typedef struct pasta_integrator {
  *   proton (used when those partials fit the workspace's partial buffer,
  *   else the gather form).  The batched path always uses the gather form.
  * list_skin: the halo delta_r of variant 2, fm, in (0, 64] (default 2).
+ * batch_wgs_per_cu: workgroups per compute unit of the persistent batched
+ *   kernel (mode 0), 1..8, capped at what fits; 0 = as many as fit.  Read
+ *   when a batch is created.
  * list_pool_scale: list memory relative to the default sizing, in (0, 1000]
  *   (default 1; the default holds 1.5 x the expected entries per lane at the
  *   starting density plus a Poisson margin). */
@@ -146,6 +149,7 @@ typedef struct pasta_tuning {
     int32_t coulomb_form;
     double list_skin;
     double list_pool_scale;
+    int32_t batch_wgs_per_cu;
 } pasta_tuning;
 int pasta_set_tuning(const pasta_tuning* t);
 int pasta_get_tuning(pasta_tuning* out);

@@ -45,11 +45,12 @@ class pasta_potential(ctypes.Structure):
 class pasta_tuning(ctypes.Structure):
     _fields_ = [("nuclear_variant", ctypes.c_int32), ("coulomb_splits", ctypes.c_int32),
                 ("fused_forces", ctypes.c_int32), ("coulomb_form", ctypes.c_int32),
-                ("list_skin", ctypes.c_double), ("list_pool_scale", ctypes.c_double)]
+                ("list_skin", ctypes.c_double), ("list_pool_scale", ctypes.c_double),
+                ("batch_wgs_per_cu", ctypes.c_int32)]
 
 
 TUNING_FIELDS = ("nuclear_variant", "coulomb_splits", "fused_forces", "coulomb_form",
-                 "list_skin", "list_pool_scale")
+                 "list_skin", "list_pool_scale", "batch_wgs_per_cu")
 
 
 class pasta_integrator(ctypes.Structure):

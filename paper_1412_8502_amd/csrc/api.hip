@@ -327,7 +327,8 @@ extern "C" int pasta_set_tuning(const pasta_tuning* t)
     if (!t || t->nuclear_variant < 0 || t->nuclear_variant > 3 || t->coulomb_splits < 0 ||
         t->coulomb_splits > 32 || (t->fused_forces != 0 && t->fused_forces != 1) ||
         (t->coulomb_form != 0 && t->coulomb_form != 1) || !(t->list_skin > 0.0 && t->list_skin <= 64.0) ||
-        !(t->list_pool_scale > 0.0 && t->list_pool_scale <= 1e3))
+        !(t->list_pool_scale > 0.0 && t->list_pool_scale <= 1e3) || t->batch_wgs_per_cu < 0 ||
+        t->batch_wgs_per_cu > 8)
         return fail(PASTA_EINVAL, "pasta_set_tuning: bad argument");
     g_tuning = *t;
     return PASTA_OK;

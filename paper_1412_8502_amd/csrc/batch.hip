@@ -72,7 +72,7 @@ struct BatchDev {
     double* ke_chunk;
     double* pending;      // per-system velocity scale pending from the thermostat
     int64_t* step;
-    unsigned* barrier;    // [0] arrivals, [1] generation
+    unsigned* barrier;    // BAR_WORDS words: generation, root count, group counts
     unsigned* queue;      // [0] force-phase work counter
     uint32_t* err;
     unsigned long long* pairs;  // [nsys] diagnostic nuclear pair counts
@@ -122,14 +122,22 @@ __device__ __forceinline__ Grid grid_at(double L, double r_cut)
     return g;
 }
 
-// Bounded grid-wide barrier.  Returns false (and every later barrier returns
-// false at once) when the wait limit is hit.  Memory ordering: one
-// agent-scope release fence per arriving workgroup before its (relaxed)
-// arrival, an acquire + release fence by the last arriver, which then resets
-// the arrival count and publishes the new generation with a release store
-// (so the reset is visible first), and one agent-scope acquire fence per
-// workgroup after the generation changed.  The spin itself uses relaxed loads, so waiting
-// workgroups do not keep invalidating caches that the laggards are using.
+// Bounded grid-wide barrier, two levels: workgroup g arrives at group
+// counter g % BAR_GROUPS; the last arrival of a group resets that counter
+// and arrives at the root counter; the last root arrival resets the root and
+// publishes a new generation, which the waiting workgroups poll.  Every word
+// has a 256-byte line of its own, so the arrivals of one group, the root and
+// the polling do not contend for one line, and the polls back off (up to
+// about a microsecond apart) so that waiting workgroups leave the memory
+// system to the ones still working.  Returns false (and every later barrier
+// returns false at once) when the wait limit is hit.  Memory ordering: an
+// agent-scope release fence before each arrival, an acquire + release fence
+// by each last arrival before it resets its counter (the reset is ordered
+// before its next arrival or the release store of the generation), and an
+// agent-scope acquire fence after the generation changed.
+constexpr int BAR_GROUPS = 32;
+constexpr int BAR_STRIDE = 64;  // words between counters (256 bytes)
+constexpr int BAR_WORDS = (2 + BAR_GROUPS) * BAR_STRIDE;
 __device__ bool grid_sync(const BatchDev& B, int* s_flag)
 {
     __syncthreads();
@@ -138,30 +146,49 @@ __device__ bool grid_sync(const BatchDev& B, int* s_flag)
         if (__hip_atomic_load(B.err, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) & ERR_BARRIER) {
             ok = 0;
         } else {
+            unsigned* gen_w = B.barrier;
+            unsigned* root_w = B.barrier + BAR_STRIDE;
             const unsigned nb = gridDim.x;
-            const unsigned gen =
-                __hip_atomic_load(&B.barrier[1], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            const unsigned grp = blockIdx.x % BAR_GROUPS;
+            const unsigned ngrp = nb < BAR_GROUPS ? nb : BAR_GROUPS;
+            // members of this group: the workgroups with this residue
+            const unsigned gsize = nb / BAR_GROUPS + (grp < nb % BAR_GROUPS ? 1u : 0u);
+            unsigned* grp_w = B.barrier + (2 + grp) * BAR_STRIDE;
+            const unsigned gen = __hip_atomic_load(gen_w, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
             __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
-            const unsigned arrived = __hip_atomic_fetch_add(&B.barrier[0], 1u, __ATOMIC_RELAXED,
-                                                            __HIP_MEMORY_SCOPE_AGENT) + 1u;
-            if (arrived == nb) {
+            bool last = false;
+            if (__hip_atomic_fetch_add(grp_w, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) + 1u ==
+                gsize) {
+                __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "agent");
+                __hip_atomic_store(grp_w, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
+                last = __hip_atomic_fetch_add(root_w, 1u, __ATOMIC_RELAXED,
+                                              __HIP_MEMORY_SCOPE_AGENT) + 1u == ngrp;
+            }
+            if (last) {
                 __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "agent");
                 // the reset must be visible before the new generation: a
-                // released workgroup's next arrival then counts from zero
-                __hip_atomic_store(&B.barrier[0], 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-                __hip_atomic_store(&B.barrier[1], gen + 1u, __ATOMIC_RELEASE,
-                                   __HIP_MEMORY_SCOPE_AGENT);
+                // released group's next arrival then counts from zero
+                __hip_atomic_store(root_w, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                __hip_atomic_store(gen_w, gen + 1u, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
             } else {
                 long spins = 0;
-                while (__hip_atomic_load(&B.barrier[1], __ATOMIC_RELAXED,
-                                         __HIP_MEMORY_SCOPE_AGENT) == gen) {
-                    __builtin_amdgcn_s_sleep(1);
+                int nap = 1;
+                while (__hip_atomic_load(gen_w, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) ==
+                       gen) {
+                    if (nap >= 32)
+                        __builtin_amdgcn_s_sleep(32);
+                    else if (nap >= 8)
+                        __builtin_amdgcn_s_sleep(8);
+                    else
+                        __builtin_amdgcn_s_sleep(1);
+                    nap = nap < 32 ? 2 * nap : 32;
                     if (++spins > B.spin_limit) {
                         atomicOr(B.err, ERR_BARRIER);
                         ok = 0;
                         break;
                     }
-                    if ((spins & 1023) == 0 &&
+                    if ((spins & 255) == 0 &&
                         (__hip_atomic_load(B.err, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) &
                          ERR_BARRIER)) {
                         ok = 0;
@@ -210,7 +237,9 @@ __device__ void phase_drift(const BatchDev& B, int64_t step, int mode)
         double* v = B.vel + 3 * i;
         double xn[3];
         if (mode) {
-            const double sc = B.pending[s];
+            // the thermostat of the previous step (if any) left its factor
+            const double sc = (S.rescale_every > 0 && step % S.rescale_every == 0)
+                                  ? B.pending[s] : 1.0;
             const double ratio = L_new / L_old;
             uint32_t bad = 0;
 #pragma unroll
@@ -555,8 +584,15 @@ constexpr int batch_lds()
     return (a > b ? a : b) + 64;
 }
 
+// Waves per SIMD the persistent kernel is compiled for: five in mixed
+// precision (96 VGPRs, no spills, five workgroups per CU), the compiler's
+// choice in FP64.
+template <class P>
+constexpr int persist_waves() { return std::is_same<P, MixedPolicy>::value ? 5 : 1; }
+
 template <class P, int M, int V>
-__global__ __launch_bounds__(BW) void k_batch_step(BatchDev B, int mode)
+__global__ __launch_bounds__(BW) __attribute__((amdgpu_waves_per_eu(persist_waves<P>())))
+void k_batch_step(BatchDev B, int mode)
 {
     __shared__ __align__(16) char lds[batch_lds<P, V>()];
     __shared__ int s_flag, s_item;
@@ -579,9 +615,16 @@ __global__ __launch_bounds__(BW) void k_batch_step(BatchDev B, int mode)
     if (!grid_sync(B, &s_flag))
         return;
     phase_combine<P>(B, mode, M != MODE_FORCE, lds);
-    if (!grid_sync(B, &s_flag))
-        return;
-    phase_thermostat(B, step, mode, lds);
+    // the thermostat (and the barrier before it) only in steps where some
+    // system rescales; the next step's drift reads the factor only then
+    bool thermo = false;
+    for (int s = 0; s < B.nsys && mode; ++s)
+        thermo |= B.sys[s].rescale_every > 0 && (step + 1) % B.sys[s].rescale_every == 0;
+    if (thermo) {
+        if (!grid_sync(B, &s_flag))
+            return;
+        phase_thermostat(B, step, mode, lds);
+    }
     if (mode && blockIdx.x == 0 && threadIdx.x == 0)
         *B.step = step + 1;
 }
@@ -661,7 +704,9 @@ __global__ __launch_bounds__(BW) void k_apply_pending(BatchDev B)
         const int s = find_sys_chunk(B, g);
         const SysDev& S = B.sys[s];
         const int64_t sl = (g - S.chunk_off) * BW + threadIdx.x;
-        if (sl < S.n) {
+        // only a thermostat in the last step left a factor to apply
+        const int64_t st = *B.step;
+        if (sl < S.n && S.rescale_every > 0 && st % S.rescale_every == 0) {
             const double sc = B.pending[s];
             double* v = B.vel + 3 * (S.off + sl);
             v[0] *= sc;
@@ -686,10 +731,10 @@ __global__ __launch_bounds__(BW) void k_batch_zero(int32_t* a, int32_t* b, int64
 
 __global__ void k_batch_init_scalars(BatchDev B, int64_t step0)
 {
+    for (int k = threadIdx.x; k < BAR_WORDS; k += blockDim.x)
+        B.barrier[k] = 0u;
     if (threadIdx.x == 0) {
         *B.step = step0;
-        B.barrier[0] = 0u;
-        B.barrier[1] = 0u;
         B.queue[0] = 0u;
         B.queue[1] = 0u;
         *B.err = 0u;
@@ -882,7 +927,7 @@ size_t batch_carve(Carver& cv, const BatchLayout& lay, int nsys, int precision, 
     b.ke_chunk = cv.take<double>(lay.total_chunks);
     b.pending = cv.take<double>(nsys);
     b.step = cv.take<int64_t>(1);
-    b.barrier = cv.take<unsigned>(2);
+    b.barrier = cv.take<unsigned>(BAR_WORDS);
     b.queue = cv.take<unsigned>(2);
     b.err = cv.take<uint32_t>(1);
     b.pairs = cv.take<unsigned long long>(nsys);
@@ -973,8 +1018,11 @@ int persistent_grid(int variant, unsigned* out)
     if (occ < 1)
         return fail(PASTA_EHIP, "persistent batch kernel cannot be resident");
     // every workgroup must be resident at once: the occupancy the runtime
-    // reports, at most four per CU
-    *out = (unsigned)ncu * (unsigned)(occ < 4 ? occ : 4);
+    // reports (at most eight per CU), or fewer when the tuning asks
+    int per = occ < 8 ? occ : 8;
+    if (g_tuning.batch_wgs_per_cu > 0 && g_tuning.batch_wgs_per_cu < per)
+        per = g_tuning.batch_wgs_per_cu;
+    *out = (unsigned)ncu * (unsigned)per;
     return PASTA_OK;
 }
 

@@ -425,7 +425,7 @@ int64_t coulomb_partial_capacity(int64_t n)
     return cap > n ? cap : n;
 }
 
-pasta_tuning g_tuning = {1, 0, 1, 0, 2.0, 1.0};  // coulomb_form 0: gather
+pasta_tuning g_tuning = {1, 0, 1, 0, 2.0, 1.0, 0};  // coulomb_form 0: gather
 
 void launch_forces_fused(int precision, const ForceBuf& fb, const CellBuf& cb, const Grid& g,
                          int64_t n, int64_t Z, const PairParams& pp, bool with_nuclear_terms,
