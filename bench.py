@@ -498,6 +498,13 @@ def main():
     B.pasta_set_tuning(**old)
     kd = max(20, K // 5)
     log(f"mixed, dense nuclear kernel: {dense['seconds'] / kd * 1e3:.4f} ms/step")
+    # the Newton-3 half-stencil nuclear variant (each unordered pair once,
+    # reactions in fixed point), for comparison with the full stencil
+    old = B.pasta_set_tuning(nuclear_variant=4, fused_forces=1)
+    n3 = run_path(B, torch, st, B.PASTA_MIXED, max(20, K // 5), min(W, 20), timing=True)
+    B.pasta_set_tuning(**old)
+    kn3 = max(20, K // 5)
+    log(f"mixed, Newton-3 half stencil: {n3['seconds'] / kn3 * 1e3:.4f} ms/step")
     k64 = args.fp64_steps or max(20, K // 4)
     B.pasta_set_tuning(**tuned64)
     if use_lists:
@@ -619,6 +626,8 @@ def main():
                                               round(ms, 5)] for c, ms in table64]},
         "dense_nuclear_variant": {"ms_per_step": dense["seconds"] / kd * 1e3,
                                   "nuclear_ms": dense["kernel_times"]["nuclear+kick"][0] / kd},
+        "newton3_half_stencil_variant": {"ms_per_step": n3["seconds"] / kn3 * 1e3,
+                                         "per_kernel_ms": kernel_ms(n3["kernel_times"], kn3)},
         "nuclear_form": "neighbour lists" if use_lists else "cell sweeps",
         "cell_sweeps": {"ms_per_step": mixed_cells["seconds"] / K * 1e3,
                         "per_kernel_ms": {k: round(v[0] / K, 5)

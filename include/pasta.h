@@ -119,10 +119,16 @@ typedef struct pasta_integrator {
  *   pasta_forces builds and uses the lists once; 3 = as 1 with 8 lanes per
  *   target and 32 targets per work item (smaller target boxes, so fewer
  *   staged sources).  Cells are binned by octant inside, so the targets of
- *   a work item are spatially compact.  The batched path runs 2 as 3 (it
- *   rebuilds its cells every step) and reads the variant at creation.  A
- *   simulation keeps the variant it was created with.  All variants give
- *   the same forces to rounding.
+ *   a work item are spatially compact; 4 = Newton's third law: each item
+ *   stages the half stencil (its cell and the 13 neighbours with a
+ *   lexicographically positive offset), every unordered pair inside r_nuc
+ *   is evaluated once, the reaction on the source is accumulated in 64-bit
+ *   fixed point (2^-43 MeV/fm; order-independent sums, so results are
+ *   deterministic) and added by the combine kernel; always the fused form;
+ *   grids of fewer than 3 cells per side run as 3.  The batched path runs
+ *   2 and 4 as 3 (it rebuilds its cells every step) and reads the variant
+ *   at creation.  A simulation keeps the variant it was created with.  All
+ *   variants give the same forces to rounding.
  * coulomb_splits: number of source ranges per Coulomb target tile, 1..32;
  *   0 = automatic (about 2^19 / Z, at most 32).
  * fused_forces: 0 = the Coulomb kernel, then the nuclear kernel whose
@@ -155,8 +161,9 @@ int pasta_set_tuning(const pasta_tuning* t);
 int pasta_get_tuning(pasta_tuning* out);
 /* Autotuner: builds the cell list of the given state once, then times the
  * Coulomb + nuclear kernels (reps evaluations each, HIP events) for every
- * candidate setting -- nuclear variant {0, 1, 3} x Coulomb {gather with
- * splits S/2, S, 2S around the automatic S, pairwise} x fused_forces {0, 1}
+ * candidate setting -- nuclear variant {0, 1, 3, 4 (fused only)} x Coulomb
+ * {gather with splits S/2, S, 2S around the automatic S, pairwise} x
+ * fused_forces {0, 1}
  * -- and returns the fastest
  * in *h_best (the list fields copied from the current setting; the list
  * form's cost depends on how often the lists are rebuilt, which a single

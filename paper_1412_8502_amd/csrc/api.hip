@@ -283,7 +283,9 @@ static void eval_forces(int precision, int terms, const ForceWork& w, const Grid
     ForceBuf fb = w.fb;
     fb.cut_pos = pos;
     fb.cut_perm = pos_perm;
-    if (g_tuning.fused_forces && (terms & PASTA_TERM_NUCLEAR)) {
+    // the Newton-3 variant needs the combine kernel (reactions from every
+    // item), so it always takes the fused form
+    if ((g_tuning.fused_forces || w.variant == 4) && (terms & PASTA_TERM_NUCLEAR)) {
         launch_forces_fused(precision, fb, w.cb, g, n, Z, pp, true,
                             (terms & PASTA_TERM_COULOMB) != 0, force, epot, kick, pair_counter,
                             w.err, s, t, w.variant, lb);
@@ -324,7 +326,7 @@ extern "C" void pasta_potential_paper(pasta_potential* out)
 
 extern "C" int pasta_set_tuning(const pasta_tuning* t)
 {
-    if (!t || t->nuclear_variant < 0 || t->nuclear_variant > 3 || t->coulomb_splits < 0 ||
+    if (!t || t->nuclear_variant < 0 || t->nuclear_variant > 4 || t->coulomb_splits < 0 ||
         t->coulomb_splits > 32 || (t->fused_forces != 0 && t->fused_forces != 1) ||
         (t->coulomb_form != 0 && t->coulomb_form != 1) || !(t->list_skin > 0.0 && t->list_skin <= 64.0) ||
         !(t->list_pool_scale > 0.0 && t->list_pool_scale <= 1e3) || t->batch_wgs_per_cu < 0 ||
@@ -462,6 +464,7 @@ static int forces_run(const char* who, const pasta_potential* pot, int32_t preci
     if (w.lists)
         launch_zero_words(w.lb.ctl, (int64_t)(sizeof(ListCtl) / sizeof(uint32_t)), s);
     cellbuf_zero(w.cb, g.C, s, g.sub);
+    launch_zero_words(w.fb.react, 8 * n, s);
     build_cells(d_pos, d_species, n, g, w, precision, pp, s, nullptr);
     int32_t Z = 0;
     PASTA_HIP(hipMemcpyAsync(&Z, w.cb.start + (int64_t)g.C * g.sub, sizeof(int32_t),
@@ -550,10 +553,10 @@ extern "C" int pasta_forces_noalloc(const pasta_potential* pot, int32_t precisio
 // -------------------------------------------------------------- tuning
 // Times the two pair kernels (Coulomb + nuclear with its epilogue) on the
 // given state for every candidate setting and keeps the fastest.  Candidates:
-// nuclear variant {dense, compacted, compacted with 8 lanes per target} x
-// Coulomb {gather with source splits S/2, S, 2S around the automatic S
-// (clamped to 1..32), pairwise} x fused {0, 1}.  The cell list is built
-// once per item size.
+// nuclear variant {dense, compacted, compacted with 8 lanes per target,
+// Newton-3 half stencil (fused only)} x Coulomb {gather with source splits
+// S/2, S, 2S around the automatic S (clamped to 1..32), pairwise} x fused
+// {0, 1}.  The cell list is built once per item size.
 extern "C" int pasta_autotune(const pasta_potential* pot, int32_t precision, int64_t n, double L,
                               const double* d_pos, const uint8_t* d_species, void* d_work,
                               size_t work_bytes, void* stream, int32_t reps, pasta_tuning* h_best,
@@ -584,6 +587,7 @@ extern "C" int pasta_autotune(const pasta_potential* pot, int32_t precision, int
     const PairParams pp = pair_params(pot, L);
     PASTA_HIP(hipMemsetAsync(w.err, 0, sizeof(uint32_t), s));
     cellbuf_zero(w.cb, g.C, s, g.sub);
+    launch_zero_words(w.fb.react, 8 * n, s);
     int32_t Z = 0;
     int built_chunk = 0;
     // (re)builds the cell list for a candidate's item size
@@ -612,7 +616,9 @@ extern "C" int pasta_autotune(const pasta_potential* pot, int32_t precision, int
     std::vector<pasta_tuning> cands;
     const bool pair_fits = Z > 0 && (int64_t)coulomb_pair_plan_supers(Z) * Z <= w.fb.coul_max;
     for (int fused = 0; fused <= 1; ++fused)
-        for (int v : {0, 1, 3}) {
+        for (int v : {0, 1, 3, 4}) {
+            if (v == 4 && !fused)
+                continue;  // the Newton-3 variant runs in the fused form only
             int last = -1;
             for (int sc : {S0 / 2, S0, 2 * S0}) {
                 int sv = sc < 1 ? 1 : (sc > 32 ? 32 : sc);
@@ -913,6 +919,7 @@ extern "C" int pasta_sim_create(const pasta_potential* pot, const pasta_integrat
         return fail(PASTA_EHIP, "hipMemsetAsync failed");
     }
     cellbuf_zero(sim->w.cb, sim->C_max, s, CELL_SUB);
+    launch_zero_words(sim->w.fb.react, 8 * n, s);
     if (sim->w.lists && hipMemsetAsync(sim->w.lb.ctl, 0, sizeof(ListCtl), s) != hipSuccess) {
         delete sim;
         return fail(PASTA_EHIP, "hipMemsetAsync failed");

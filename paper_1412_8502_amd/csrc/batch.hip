@@ -855,7 +855,7 @@ struct BatchLayout {
 int batch_variant()
 {
     const int v = g_tuning.nuclear_variant;
-    return v == 0 ? 0 : (v == 1 ? 1 : 3);
+    return v == 0 ? 0 : (v == 1 ? 1 : 3);  // lists (2) and Newton-3 (4) run as 3
 }
 int batch_chunk() { return nuclear_chunk_for(batch_variant()); }
 

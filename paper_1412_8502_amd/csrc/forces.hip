@@ -24,6 +24,7 @@
 // nuclear kernel whose epilogue does the combine.
 #include <type_traits>
 
+#include "half_items.hpp"
 #include "list_items.hpp"
 
 namespace pasta {
@@ -122,7 +123,8 @@ constexpr int fused_lds_bytes()
 {
     static_assert(coulomb_pair_lds_bytes<P>() <= coulomb_lds_bytes<P>(), "LDS of the pair form");
     constexpr int a = coulomb_lds_bytes<P>();
-    constexpr int b = V == 0 ? nuclear_lds_bytes<P>() : nuclear_compact_lds_bytes<P>();
+    constexpr int b = V == 0 ? nuclear_lds_bytes<P>()
+                             : (V == 4 ? nuclear_half_lds_bytes<P>() : nuclear_compact_lds_bytes<P>());
     return a > b ? a : b;
 }
 
@@ -147,6 +149,8 @@ __global__ __launch_bounds__(WG) void k_forces_fused(const typename P::Src* __re
             nuclear_item_listed<P, MODE>(stg, A, k, LA, g, lds);
         else if constexpr (V == 3)
             nuclear_item_compact_t<P, 8, true, MODE>(stg, A, k, g, lds);
+        else if constexpr (V == 4)
+            nuclear_item_half<P, MODE>(stg, A, k, g, lds, A.react);
         else if constexpr (V == 1)
             nuclear_item_compact<P, true, MODE>(stg, A, k, g, lds);
         else
@@ -186,7 +190,8 @@ __global__ __launch_bounds__(WG) void k_combine(const double4* __restrict__ fnuc
                                                 double* __restrict__ epot, double* vel, double hdtm,
                                                 double mass, double* __restrict__ ke_part,
                                                 int32_t* __restrict__ n_ke, uint32_t* err,
-                                                NextDrift nd, int has_next)
+                                                NextDrift nd, int has_next,
+                                                unsigned long long* __restrict__ react)
 {
     __shared__ double red[WG / 64];
     int64_t sl;
@@ -234,7 +239,21 @@ __global__ __launch_bounds__(WG) void k_combine(const double4* __restrict__ fnuc
     double ke = 0.0;
     if (lead) {
         const double4 fn = fnuc[sl];
-        const double Fx = fn.x + cx, Fy = fn.y + cy, Fz = fn.z + cz, V = fn.w + cw;
+        double rx = 0.0, ry = 0.0, rz = 0.0, rw = 0.0;
+        if (react) {
+            // Newton-3 reactions (fixed point), cleared for the next launch
+            unsigned long long* r = react + 4 * sl;
+            rx = (double)(long long)r[0] * REACT_UNIT;
+            ry = (double)(long long)r[1] * REACT_UNIT;
+            rz = (double)(long long)r[2] * REACT_UNIT;
+            rw = (double)(long long)r[3] * REACT_UNIT;
+            r[0] = 0ull;
+            r[1] = 0ull;
+            r[2] = 0ull;
+            r[3] = 0ull;
+        }
+        const double Fx = (fn.x + rx) + cx, Fy = (fn.y + ry) + cy, Fz = (fn.z + rz) + cz,
+                     V = (fn.w + rw) + cw;
         const int64_t id = perm ? perm[sl] : sl;
         force[3 * id + 0] = Fx;
         force[3 * id + 1] = Fy;
@@ -317,7 +336,10 @@ void nuclear_dispatch(const typename P::Src* stg, const NucArgs& a, const int32_
 
 }  // namespace
 
-int nuclear_chunk_for(int variant) { return (variant == 2 || variant == 3) ? LIST_CHUNK : NUC_CHUNK; }
+int nuclear_chunk_for(int variant)
+{
+    return (variant == 2 || variant == 3 || variant == 4) ? LIST_CHUNK : NUC_CHUNK;
+}
 
 static ListArgs list_args(const ListBuf* lb)
 {
@@ -457,12 +479,16 @@ void launch_forces_fused(int precision, const ForceBuf& fb, const CellBuf& cb, c
     a.pairs = reinterpret_cast<unsigned long long*>(pair_counter);
     a.err = err;
     a.fnuc = fb.fnuc;
+    a.react = fb.react;
     (void)with_nuclear_terms;  // the fused form always carries the nuclear terms
     const int item_max = (int)cb.item_max;
     const unsigned grid = (unsigned)(item_max + coul_items);
     const int mode = pair_counter ? MODE_COUNT : (epot ? MODE_ENERGY : MODE_FORCE);
     if (variant == 2 && !lb)
         variant = 1;
+    // the half stencil needs three cells per side (its 14 cells distinct)
+    if (variant == 4 && g.nc < 3)
+        variant = 3;
     const ListArgs la = list_args(lb);
     timer_begin(t, KC_NUCLEAR, s);
     if (grid > 0) {
@@ -492,6 +518,7 @@ void launch_forces_fused(int precision, const ForceBuf& fb, const CellBuf& cb, c
             case 0: go(std::integral_constant<int, 0>(), mt); break;
             case 2: go(std::integral_constant<int, 2>(), mt); break;
             case 3: go(std::integral_constant<int, 3>(), mt); break;
+            case 4: go(std::integral_constant<int, 4>(), mt); break;
             default: go(std::integral_constant<int, 1>(), mt); break;
             }
         });
@@ -507,7 +534,8 @@ void launch_forces_fused(int precision, const ForceBuf& fb, const CellBuf& cb, c
             k_combine<<<cgrid, WG, 0, s>>>(fb.fnuc, part, S, (int)Z, zb,
                                            kick.slot_order ? nullptr : cb.perm, n, force, epot,
                                            kick.vel, kick.hdtm, kick.mass, kick.ke_part, fb.n_ke,
-                                           err, nd, kick.next ? 1 : 0);
+                                           err, nd, kick.next ? 1 : 0,
+                                           variant == 4 ? fb.react : nullptr);
         };
         if (precision == PASTA_FP64)
             comb(static_cast<const double4*>(fb.coul_part));
@@ -534,6 +562,7 @@ size_t forcebuf_carve(Carver& cv, ForceBuf* out, int64_t n, int64_t item_max, in
     fb.ke_part = cv.take<double>(item_max > comb_blocks ? item_max : comb_blocks);
     fb.n_ke = cv.take<int32_t>(1);
     fb.fnuc = cv.take<double4>(n);
+    fb.react = cv.take<unsigned long long>(4 * (size_t)n);
     fb.pairs = cv.take<uint64_t>(2);
     if (out)
         *out = fb;

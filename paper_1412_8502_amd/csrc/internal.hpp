@@ -73,7 +73,7 @@ inline int cell_dims(double L, double r_cut)
 
 // sub = bins per cell and species: 1, or 8 (the cell's octants, so that a
 // run of consecutive slots inside a cell is spatially compact).  Bin of a
-// particle = (proton ? 0 : C*sub) + cell*sub + octant; a cell's protons are
+// particle = (proton ? 0 : C*sub) + cell*sub + octant rank; a cell's protons are
 // the bins [cell*sub, cell*sub + sub), its neutrons the same range + C*sub.
 struct Grid {
     int nc;        // cells per side
@@ -132,7 +132,12 @@ __device__ inline int particle_bin(double x, double y, double z, bool proton, do
         o |= h << d;
     }
     const int cell = (k[2] * nc + k[1]) * nc + k[0];
-    return (proton ? 0 : C * sub) + cell * sub + (sub == 8 ? o : 0);
+    // octants in reflected-Gray-code order (o = x | y << 1 | z << 2 at rank
+    // r = o ^ (o >> 1) ^ (o >> 2)): consecutive octants share a face, so a
+    // run of consecutive slots spanning two or three octants stays within a
+    // 2 x 1 x 1 or 2 x 2 x 1 block of them
+    const int r = o ^ (o >> 1) ^ (o >> 2);
+    return (proton ? 0 : C * sub) + cell * sub + (sub == 8 ? r : 0);
 }
 
 // One particle's share of a step's first part (Sec. II.A, Eq. 3): the half
@@ -408,6 +413,8 @@ struct ForceBuf {
     double* ke_part;    // [item_max] kinetic-energy partials of the last kick
     int32_t* n_ke;      // [1] number of valid ke_part entries (fused form)
     double4* fnuc;      // [n] nuclear (F, V) per sorted slot (fused form)
+    unsigned long long* react;  // [n][4] Newton-3 reactions of variant 4, fixed point
+                                // (zero between launches)
     uint64_t* pairs;    // [2] diagnostic pair counters (nuclear, Coulomb; ordered)
     // FP64 positions the staging was built from, for a finite Coulomb
     // cutoff (set per evaluation; see CoulCut)

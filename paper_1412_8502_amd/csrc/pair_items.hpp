@@ -745,6 +745,7 @@ struct NucArgs {
     unsigned long long* pairs;
     uint32_t* err;
     double4* fnuc;           // batch form: raw nuclear (F, V) per sorted slot, no epilogue
+    unsigned long long* react;  // [n][4] Newton-3 reactions (variant 4), fixed point
 };
 
 template <class P, bool NUC, int MODE>
@@ -987,17 +988,23 @@ __device__ inline ItemTarget item_target(const NucArgs& A, int item)
     return t;
 }
 
-// Neighbour bins of cell c (protons of the 27 cells, then their neutrons,
-// duplicates removed for small grids) and the bounding box of the item's
-// targets (fixed-point; a chunk lies inside one cell, so no wrap).  Ends
-// with a barrier; afterwards seg_off[54] is the candidate count.
+// Neighbour bins of cell c (protons of the NCELL cells, then their
+// neutrons) and the bounding box of the item's targets (fixed-point; a
+// chunk lies inside one cell, so no wrap).  NCELL = 27: the full stencil,
+// duplicates removed for small grids; NCELL = 14: the cell itself and the
+// 13 neighbours whose offset (oz, oy, ox) is lexicographically positive (the
+// half stencil of Newton's third law; needs at least 3 cells per side).
+// Ends with a barrier; afterwards seg_off[2 NCELL] is the candidate count.
+template <int NCELL = 27>
 __device__ inline void item_setup(const NucArgs& A, const ItemLds& L, int c, bool nuc,
                                   bool in_box, uint3 mef)
 {
+    constexpr int NS = 2 * NCELL;
     const int tid = threadIdx.x, nc = A.nc, C = A.C;
     const int cx = c % nc, cy = (c / nc) % nc, cz = c / (nc * nc);
-    if (tid < 54) {
-        const int kk = tid % 27, sp = tid / 27;  // sp 0: protons, 1: neutrons
+    if (tid < NS) {
+        const int kc = tid % NCELL, sp = tid / NCELL;  // sp 0: protons, 1: neutrons
+        const int kk = NCELL == 27 ? kc : (kc == 0 ? 13 : 13 + kc);
         const int ox = kk % 3 - 1, oy = (kk / 3) % 3 - 1, oz = kk / 9 - 1;
         const int lo = axis_lo(nc), hi = axis_hi(nc);
         int beg = 0, len = 0;
@@ -1014,10 +1021,18 @@ __device__ inline void item_setup(const NucArgs& A, const ItemLds& L, int c, boo
     if (tid < 6)
         L.misc[tid] = tid < 3 ? -1 : 0;  // lo = UINT_MAX, hi = 0 (as unsigned)
     __syncthreads();
-    if (tid == 0) {
-        L.seg_off[0] = 0;
-        for (int s = 1; s <= 54; ++s)
-            L.seg_off[s] += L.seg_off[s - 1];
+    if (tid < 64) {
+        // exclusive prefix of the bin lengths by a shuffle scan in the first
+        // wavefront (lane l holds the length of bin l - 1)
+        int v = (tid >= 1 && tid <= NS) ? L.seg_off[tid] : 0;
+#pragma unroll
+        for (int off = 1; off < 64; off <<= 1) {
+            const int y = __shfl_up(v, off, 64);
+            if (tid >= off)
+                v += y;
+        }
+        if (tid <= NS)
+            L.seg_off[tid] = v;
     }
     if (in_box) {
         atomicMin(reinterpret_cast<unsigned*>(&L.misc[0]), mef.x);
@@ -1030,7 +1045,8 @@ __device__ inline void item_setup(const NucArgs& A, const ItemLds& L, int c, boo
     __syncthreads();
 }
 
-// Stages the neighbourhood in rounds of SP candidates per thread: locate (a
+// Stages the neighbourhood in rounds of SP candidates per thread (SP * WG
+// at most the tile size T, so a round fits the tile after a flush): locate (a
 // binary search for the first, a short forward walk for the next), load,
 // keep the sources whose periodic gap to the targets' box (centre and half
 // extent, rounded up) is below sqrt(thr_stage) fixed-point units, and
@@ -1038,15 +1054,17 @@ __device__ inline void item_setup(const NucArgs& A, const ItemLds& L, int c, boo
 // fixed, slot) stores a kept source at tile position pos; flush(n, np) is
 // called, by the whole workgroup, when the next round might not fit in a
 // tile of T entries and at the end (np = protons among the n).
-template <class P, int T, class Put, class Flush>
+template <class P, int T, int NCELL = 27, class Put, class Flush>
 __device__ __forceinline__ void stage_neighbourhood(const typename P::Src* __restrict__ stg,
                                                     const NucConsts& k, const ItemLds& L,
                                                     float thr_stage, Put put, Flush flush)
 {
     using Lds = typename P::Lds;
-    constexpr int SP = P::STAGE_PER_THREAD;
+    // a round keeps at most SP * WG candidates, which must fit an empty tile
+    constexpr int SP = P::STAGE_PER_THREAD * WG <= T ? P::STAGE_PER_THREAD : T / WG;
+    static_assert(SP >= 1 && SP * WG <= T, "a staging round must fit one tile");
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-    const int total = L.seg_off[54], np_tot = L.seg_off[27];
+    const int total = L.seg_off[2 * NCELL], np_tot = L.seg_off[NCELL];
     uint32_t bc[3], bh[3];
 #pragma unroll
     for (int a = 0; a < 3; ++a) {
@@ -1066,7 +1084,7 @@ __device__ __forceinline__ void stage_neighbourhood(const typename P::Src* __res
             src_idx[u] = -1;
             if (gidx[u] < total) {
                 if (u == 0) {
-                    int hi = 54;
+                    int hi = 2 * NCELL;
                     while (hi - seg > 1) {
                         const int mid = (seg + hi) >> 1;
                         if (L.seg_off[mid] <= gidx[u])

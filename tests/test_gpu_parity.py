@@ -543,3 +543,64 @@ def test_autotuner(env, tmp_path, monkeypatch):
         B.pasta_set_tuning(**before)
     of, _ = env["O"].forces(st["pos"], st["species"], st["L"])
     check(f.cpu().numpy(), of, 1, what="tuned", say=say)
+
+
+# ------------------------------------------- Newton-3 half stencil (variant 4)
+@pytest.mark.parametrize("prec", [0, 1])
+@pytest.mark.parametrize("case", [
+    (3200, 0.40, 0.040, 1000),   # the small configuration: 3 cells per side
+    (12345, 0.05, 0.080, 7),     # 4 cells per side, ragged
+    (6000, 1.00, 0.050, 8),      # all protons (like pairs only)
+    (1000, 0.30, 0.060, 5),      # 2 cells per side: runs as variant 3
+    (51200, 0.20, 0.080, 1001),  # the headline state, every target
+])
+def test_newton3_variant(env, case, prec):
+    """Variant 4 evaluates each unordered pair once and carries the reaction
+    in 64-bit fixed point: forces and energy shares against the oracle, the
+    same bits on a repeated call, the pair count, and agreement with the
+    full-stencil variant 3 to rounding."""
+    B = env["B"]
+    N, yp, dens, seed = case
+    st = env["I"].make_state(N, yp, dens, 1.0, seed=seed)
+    pos, sp = to_dev(env, st)
+    old = B.pasta_set_tuning(nuclear_variant=4)
+    try:
+        f, e = B.pasta_forces(pos, sp, st["L"], precision=prec)
+        f2, e2 = B.pasta_forces(pos, sp, st["L"], precision=prec)
+        B.pasta_set_tuning(nuclear_variant=3)
+        f3, _ = B.pasta_forces(pos, sp, st["L"], precision=prec)
+    finally:
+        B.pasta_set_tuning(**old)
+    assert env["torch"].equal(f, f2) and env["torch"].equal(e, e2)
+    of, oe = env["O"].forces(st["pos"], st["species"], st["L"])
+    check(f.cpu().numpy(), of, prec, e.cpu().numpy(), oe, what=f"newton3 {case}", say=say)
+    d = rel(f.cpu().numpy(), f3.cpu().numpy())
+    say(f"  variant 4 vs 3: {d:.2e}")
+    assert d <= (1e-13 if prec == 0 else 1e-6)
+
+
+@pytest.mark.parametrize("prec,tol", [(0, 1e-9), (1, 2e-4)])
+def test_newton3_trajectory_and_counts(env, prec, tol):
+    B = env["B"]
+    st = env["I"].workload("n3200_yp040_n0.040")
+    old = B.pasta_set_tuning(nuclear_variant=4)
+    try:
+        sim, pos, vel = make_sim(env, st, dt=2.0, T=1.0, rescale_every=7, precision=prec)
+        sim.step(20)
+        nn, nc = sim.pair_counts()
+        f, e = sim.forces()
+        en = sim.energies()
+    finally:
+        B.pasta_set_tuning(**old)
+    op, ov, oL, oek, oep, of = env["O"].run(st["pos"], st["vel"], st["species"], st["L"], 20,
+                                            dt=2.0, T=1.0, rescale_every=7)
+    dx = np.abs(wrapped_diff(pos.cpu().numpy(), op, oL)).max()
+    say(f"  newton3 prec {prec}: max |dx| {dx:.3e}")
+    assert dx <= tol
+    P = pos.cpu().numpy()
+    assert (nn, nc) == env["O"].pair_counts(P, st["species"], oL)
+    of2, oe2 = env["O"].forces(P, st["species"], oL)
+    check(f.cpu().numpy(), of2, prec, e.cpu().numpy(), oe2, what="newton3 after 20 steps",
+          say=say)
+    assert abs(en["epot"] - oe2.sum()) <= 1e-6 * abs(oe2).sum()
+    sim.close()
