@@ -236,7 +236,7 @@ int pasta_forces(const pasta_potential* pot, int32_t precision, int32_t terms, i
  * device (several host threads or streams) race and corrupt each other's
  * results, so serialise them.  Like pasta_forces, it synchronises the
  * stream once (to size the Coulomb launch). */
-#define PASTA_NOALLOC_SCRATCH_BYTES ((size_t)32 << 20)
+#define PASTA_NOALLOC_SCRATCH_BYTES ((size_t)64 << 20)
 int pasta_forces_noalloc(const pasta_potential* pot, int32_t precision, int32_t terms,
                          int64_t n, double L, const double* d_pos, const uint8_t* d_species,
                          double* d_force, double* d_epot, void* stream);

@@ -175,8 +175,11 @@ __global__ __launch_bounds__(WG) void k_forces_fused(const typename P::Src* __re
 // the partials s = q, q + COMB_LANES, ... in order, the lanes then combine
 // by a fixed shuffle tree and the first lane does the per-slot work (so a
 // proton's S partial loads are spread over several lanes, all in flight).
-// Blocks [zb, ...) take the neutrons, one lane each.
-constexpr int COMB_LANES = 4;
+// Blocks [zb, ...) take the neutrons, one lane each.  The slot's own loads
+// (nuclear part, velocity, position, species, reactions) are issued before
+// the partials, so the two latencies overlap.
+constexpr int COMB_LANES = 8;
+constexpr int COMB_UNROLL = 8;
 __host__ __device__ inline int64_t combine_proton_blocks(int64_t Z)
 {
     return (Z * COMB_LANES + WG - 1) / WG;
@@ -194,34 +197,64 @@ __global__ __launch_bounds__(WG) void k_combine(const double4* __restrict__ fnuc
                                                 unsigned long long* __restrict__ react)
 {
     __shared__ double red[WG / 64];
+    const bool prot = (int)blockIdx.x < zb;
     int64_t sl;
-    bool lead;
-    double cx = 0.0, cy = 0.0, cz = 0.0, cw = 0.0;
-    if ((int)blockIdx.x < zb) {
+    int q = 0;
+    if (prot) {
         const int64_t t = (int64_t)blockIdx.x * WG + threadIdx.x;
         sl = t / COMB_LANES;
-        const int q = (int)(t % COMB_LANES);
+        q = (int)(t % COMB_LANES);
+    } else {
+        sl = (int64_t)Z + (int64_t)(blockIdx.x - zb) * WG + threadIdx.x;
+    }
+    const bool lead = q == 0 && sl < (prot ? (int64_t)Z : n);
+
+    double4 fn = make_double4(0.0, 0.0, 0.0, 0.0);
+    double v0[3] = {0.0, 0.0, 0.0}, x[3] = {0.0, 0.0, 0.0};
+    unsigned long long rq[4] = {0ull, 0ull, 0ull, 0ull};
+    int64_t id = sl;
+    int spc = 0;
+    if (lead) {
+        fn = fnuc[sl];
+        if (react) {
+#pragma unroll
+            for (int c = 0; c < 4; ++c)
+                rq[c] = react[4 * sl + c];
+        }
+        id = perm ? perm[sl] : sl;
+        if (vel) {
+#pragma unroll
+            for (int d = 0; d < 3; ++d)
+                v0[d] = vel[3 * id + d];
+            if (has_next) {
+#pragma unroll
+                for (int d = 0; d < 3; ++d)
+                    x[d] = nd.pos[3 * sl + d];
+                spc = nd.species[sl];
+            }
+        }
+    }
+
+    double cx = 0.0, cy = 0.0, cz = 0.0, cw = 0.0;
+    if (prot) {
         if (sl < Z) {
-            int s = q;
-            for (; s + 3 * COMB_LANES < S; s += 4 * COMB_LANES) {
-                PT v[4];
+            for (int s = q; s < S; s += COMB_UNROLL * COMB_LANES) {
+                PT v[COMB_UNROLL];
 #pragma unroll
-                for (int u = 0; u < 4; ++u)
-                    v[u] = part[(int64_t)(s + u * COMB_LANES) * Z + sl];
+                for (int u = 0; u < COMB_UNROLL; ++u) {
+                    const int k = s + u * COMB_LANES;
+                    if (k < S)
+                        v[u] = part[(int64_t)k * Z + sl];
+                    else
+                        v[u] = PT{0, 0, 0, 0};
+                }
 #pragma unroll
-                for (int u = 0; u < 4; ++u) {
+                for (int u = 0; u < COMB_UNROLL; ++u) {
                     cx += (double)v[u].x;
                     cy += (double)v[u].y;
                     cz += (double)v[u].z;
                     cw += (double)v[u].w;
                 }
-            }
-            for (; s < S; s += COMB_LANES) {
-                const PT v = part[(int64_t)s * Z + sl];
-                cx += (double)v.x;
-                cy += (double)v.y;
-                cz += (double)v.z;
-                cw += (double)v.w;
             }
         }
 #pragma unroll
@@ -231,30 +264,22 @@ __global__ __launch_bounds__(WG) void k_combine(const double4* __restrict__ fnuc
             cz += __shfl_xor(cz, m, COMB_LANES);
             cw += __shfl_xor(cw, m, COMB_LANES);
         }
-        lead = q == 0 && sl < Z;
-    } else {
-        sl = (int64_t)Z + (int64_t)(blockIdx.x - zb) * WG + threadIdx.x;
-        lead = sl < n;
     }
     double ke = 0.0;
     if (lead) {
-        const double4 fn = fnuc[sl];
         double rx = 0.0, ry = 0.0, rz = 0.0, rw = 0.0;
         if (react) {
             // Newton-3 reactions (fixed point), cleared for the next launch
-            unsigned long long* r = react + 4 * sl;
-            rx = (double)(long long)r[0] * REACT_UNIT;
-            ry = (double)(long long)r[1] * REACT_UNIT;
-            rz = (double)(long long)r[2] * REACT_UNIT;
-            rw = (double)(long long)r[3] * REACT_UNIT;
-            r[0] = 0ull;
-            r[1] = 0ull;
-            r[2] = 0ull;
-            r[3] = 0ull;
+            rx = (double)(long long)rq[0] * REACT_UNIT;
+            ry = (double)(long long)rq[1] * REACT_UNIT;
+            rz = (double)(long long)rq[2] * REACT_UNIT;
+            rw = (double)(long long)rq[3] * REACT_UNIT;
+#pragma unroll
+            for (int c = 0; c < 4; ++c)
+                react[4 * sl + c] = 0ull;
         }
         const double Fx = (fn.x + rx) + cx, Fy = (fn.y + ry) + cy, Fz = (fn.z + rz) + cz,
                      V = (fn.w + rw) + cw;
-        const int64_t id = perm ? perm[sl] : sl;
         force[3 * id + 0] = Fx;
         force[3 * id + 1] = Fy;
         force[3 * id + 2] = Fz;
@@ -263,11 +288,9 @@ __global__ __launch_bounds__(WG) void k_combine(const double4* __restrict__ fnuc
         if (!(isfinite(Fx) && isfinite(Fy) && isfinite(Fz)))
             atomicOr(err, ERR_NONFINITE_FORCE);
         if (vel) {
-            const double vx = vel[3 * id + 0] + hdtm * Fx, vy = vel[3 * id + 1] + hdtm * Fy,
-                         vz = vel[3 * id + 2] + hdtm * Fz;
+            const double vx = v0[0] + hdtm * Fx, vy = v0[1] + hdtm * Fy, vz = v0[2] + hdtm * Fz;
             ke = 0.5 * mass * (vx * vx + vy * vy + vz * vz);
             if (has_next) {
-                double x[3] = {nd.pos[3 * sl + 0], nd.pos[3 * sl + 1], nd.pos[3 * sl + 2]};
                 double v[3] = {vx, vy, vz};
                 const double f[3] = {Fx, Fy, Fz};
                 const uint32_t bad = drift_update(x, v, f, nd.step);
@@ -278,8 +301,8 @@ __global__ __launch_bounds__(WG) void k_combine(const double4* __restrict__ fnuc
                     vel[3 * sl + d] = v[d];
                     nd.pos[3 * sl + d] = x[d];
                 }
-                const int bin = particle_bin(x[0], x[1], x[2], nd.species[sl] == 1, nd.inv_w,
-                                             nd.nc, nd.C, nd.sub);
+                const int bin = particle_bin(x[0], x[1], x[2], spc == 1, nd.inv_w, nd.nc, nd.C,
+                                             nd.sub);
                 nd.key[sl] = bin;
                 wave_aggregated_add(nd.count, bin);
             } else {
@@ -557,8 +580,8 @@ size_t forcebuf_carve(Carver& cv, ForceBuf* out, int64_t n, int64_t item_max, in
         fb.coul_part = cv.take<float4>(fb.coul_max);
 
     // per-block kinetic energies: one per nuclear item (unfused kick) or per
-    // combine block (at most n / 64 + 2 with four lanes per proton)
-    const int64_t comb_blocks = n / 64 + 2;
+    // combine block (at most n * COMB_LANES / WG + 2)
+    const int64_t comb_blocks = (n * COMB_LANES + WG - 1) / WG + 2;
     fb.ke_part = cv.take<double>(item_max > comb_blocks ? item_max : comb_blocks);
     fb.n_ke = cv.take<int32_t>(1);
     fb.fnuc = cv.take<double4>(n);

@@ -102,10 +102,12 @@ __host__ __device__ inline NucConsts make_nuc_consts(const PairParams& pp)
 struct CoulConsts {
     // FP64: V = ahc e^{-r/lambda}/r; fs = V (1/r + 1/lambda)/r
     double ahc, inv_lambda, L, hL;
-    // MIXED: w = exp2(ru * c_exp) * ir; fs_u = w ir (ir cA + cB)
-    float c_exp, cA, cB;
-    double v_scale;  // alpha_hbarc / q  (V = v_scale * w)
-    double f_scale;  // alpha_hbarc      (F = f_scale * fs_u * du)
+    // MIXED: w = exp2(ru * c_exp) * ir; fs_u = w ir (1 + ir cAB), the
+    // physical factor ir (ir/q^2 + 1/(lambda q)) divided by 1/(lambda q),
+    // which f_scale carries (so the FMA takes the inline constant 1)
+    float c_exp, cAB;
+    double v_scale;  // alpha_hbarc / q              (V = v_scale * w)
+    double f_scale;  // alpha_hbarc / (lambda q)     (F = f_scale * fs_u * du)
     // finite cutoff: keep r^2 < rc2 (FP64, fm^2); the mixed form decides on
     // its FP32 r^2 (q^2 units) below thr_lo or at/above thr_hi and on the
     // FP64 r^2 of the positions in between
@@ -122,10 +124,9 @@ __host__ __device__ inline CoulConsts make_coul_consts(const PairParams& pp)
     k.hL = 0.5 * pp.L;
     const double q = pp.L / 4294967296.0;
     k.c_exp = (float)(-q / pp.lambda_s * 1.4426950408889634);
-    k.cA = (float)(1.0 / (q * q));
-    k.cB = (float)(1.0 / (pp.lambda_s * q));
+    k.cAB = (float)(pp.lambda_s / q);
     k.v_scale = pp.alpha_hbarc / q;
-    k.f_scale = pp.alpha_hbarc;
+    k.f_scale = pp.alpha_hbarc / (pp.lambda_s * q);
     k.rc2 = pp.r_coul * pp.r_coul;  // +inf when uncut
     // the FP32 r^2 of the fixed-point difference is within 2e-7 (rounding)
     // + 4 q / r (quantisation) of the FP64 one; the band is far wider
@@ -182,6 +183,22 @@ struct Fp64Policy {
     __device__ static double f_scale(const NucConsts&) { return 1.0; }
     __device__ static double bl(const NucConsts& k, bool like) { return like ? k.Bl_L : k.Bu_L; }
     __device__ static double bv(const NucConsts& k, bool like) { return like ? k.Bl : k.Bu; }
+    // Pair coefficients of one target in the compacting items: by the
+    // source's species (sources of a tile are protons first, pu).
+    struct Coefs {
+        double BLp, BLn, Bp, Bn;
+    };
+    __device__ static Coefs coefs(const NucConsts& k, bool tprot)
+    {
+        return Coefs{bl(k, tprot), bl(k, !tprot), bv(k, tprot), bv(k, !tprot)};
+    }
+    __device__ static Lds tile_entry(const Lds& e) { return e; }
+    template <int MODE>
+    __device__ static void pair_c(const Src& me, const Lds& s, const Coefs& c, bool pu,
+                                  const NucConsts& k, Part& p, bool valid)
+    {
+        pair<MODE>(me, s, pu ? c.BLp : c.BLn, pu ? c.Bp : c.Bn, k, p, valid);
+    }
 
     template <bool E>
     __device__ static void coul(const Src& me, const Lds& s, bool self, const CoulConsts& k,
@@ -300,6 +317,33 @@ struct MixedPolicy {
     __device__ static double f_scale(const NucConsts& k) { return k.q; }
     __device__ static float bl(const NucConsts& k, bool like) { return like ? k.Blf_L : k.Buf_L; }
     __device__ static float bv(const NucConsts& k, bool like) { return like ? k.Blf : k.Buf; }
+    // Pair coefficients of one target in the compacting items, as one FMA
+    // per pair: a tile entry carries its species as s_j = +1 (proton) or -1
+    // (neutron) in FP32, and with s_i the target's, the like/unlike
+    // coefficient is m + (h s_i) s_j, m and h the mean and half-difference
+    // of the like and unlike values (rounded once to FP32 each).
+    struct Coefs {
+        float hL, mL, h, m;
+    };
+    __device__ static Coefs coefs(const NucConsts& k, bool tprot)
+    {
+        const double s = tprot ? 1.0 : -1.0;
+        return Coefs{(float)(0.5 * ((double)k.Blf_L - (double)k.Buf_L) * s),
+                     (float)(0.5 * ((double)k.Blf_L + (double)k.Buf_L)),
+                     (float)(0.5 * ((double)k.Blf - (double)k.Buf) * s),
+                     (float)(0.5 * ((double)k.Blf + (double)k.Buf))};
+    }
+    __device__ static Lds tile_entry(const Lds& e)
+    {
+        return make_uint4(e.x, e.y, e.z, __float_as_uint(e.w != 0u ? 1.0f : -1.0f));
+    }
+    template <int MODE>
+    __device__ static void pair_c(const Src& me, const Lds& s, const Coefs& c, bool,
+                                  const NucConsts& k, Part& p, bool valid)
+    {
+        const float sj = __uint_as_float(s.w);
+        pair<MODE>(me, s, fmaf(sj, c.hL, c.mL), fmaf(sj, c.h, c.m), k, p, valid);
+    }
 
     template <bool E>
     __device__ static void coul(const Src& me, const Lds& s, bool self, const CoulConsts& k,
@@ -313,7 +357,7 @@ struct MixedPolicy {
         float ir = __builtin_amdgcn_rsqf(r2);
         float ru = r2 * ir;
         float w = __builtin_amdgcn_exp2f(ru * k.c_exp) * ir;
-        float fs = w * ir * fmaf(ir, k.cA, k.cB);
+        float fs = w * ir * fmaf(ir, k.cAB, 1.0f);
         fx = fmaf(fs, dx, fx);
         fy = fmaf(fs, dy, fy);
         fz = fmaf(fs, dz, fz);
@@ -330,7 +374,7 @@ struct MixedPolicy {
         const float ir = __builtin_amdgcn_rsqf(r2);
         const float ru = r2 * ir;
         w = __builtin_amdgcn_exp2f(ru * k.c_exp) * ir;
-        fs = w * ir * fmaf(ir, k.cA, k.cB);
+        fs = w * ir * fmaf(ir, k.cAB, 1.0f);
     }
     __device__ static double coul_fscale(const CoulConsts& k) { return k.f_scale; }
     __device__ static double coul_vscale(const CoulConsts& k) { return k.v_scale; }
@@ -1280,32 +1324,40 @@ __device__ void nuclear_item_compact_t(const typename P::Src* __restrict__ stg,
 
     typename P::Acc acc;
     if (NUC) {
-        const auto BLp = P::bl(k, t.tprot), Bp = P::bv(k, t.tprot);    // proton sources
-        const auto BLn = P::bl(k, !t.tprot), Bn = P::bv(k, !t.tprot);  // neutron sources
+        const typename P::Coefs cf = P::coefs(k, t.tprot);
         typename P::Part part;
         const int q = t.q;
+        // list entries are byte offsets of the sources in the tile
+        constexpr int ES = (int)sizeof(Lds);
+        static_assert(T * ES <= 65536, "tile offsets must fit 16 bits");
+        const char* src_b = reinterpret_cast<const char*>(src);
+
+        // Every entry of this lane's list column holds a tile offset from
+        // here on (rows past the count keep older offsets of this item), so
+        // a drain may read any row.
+#pragma unroll
+        for (int c = 0; c < NUC_CAP; ++c)
+            lists[c * WG + tid] = 0;
 
         // evaluate the listed pairs of every lane, DU per round, then empty
         // the lists.  Every lane reads DU entries per round (rows clamped to
         // the capacity) and masks those at or past its count.
         constexpr int DU = P::DRAIN_U;
         auto drain = [&](int cnt, int kb) {
+            const int kbb = kb * ES;
             for (int kk = 0; __ballot(kk < cnt); kk += DU) {
-                int j[DU];
+                int o[DU];
                 bool v[DU];
                 Lds sv[DU];
 #pragma unroll
                 for (int u = 0; u < DU; ++u) {
-                    const int raw = lists[min(kk + u, NUC_CAP - 1) * WG + tid];
+                    o[u] = lists[min(kk + u, NUC_CAP - 1) * WG + tid];
                     v[u] = kk + u < cnt;
-                    j[u] = v[u] ? raw : 0;
-                    sv[u] = src[j[u]];
+                    sv[u] = *reinterpret_cast<const Lds*>(src_b + o[u]);
                 }
 #pragma unroll
-                for (int u = 0; u < DU; ++u) {
-                    const bool pu = j[u] < kb;  // protons first in the tile
-                    P::template pair<MODE>(me, sv[u], pu ? BLp : BLn, pu ? Bp : Bn, k, part, v[u]);
-                }
+                for (int u = 0; u < DU; ++u)  // protons first in the tile
+                    P::template pair_c<MODE>(me, sv[u], cf, o[u] < kbb, k, part, v[u]);
             }
         };
         // Screen the tile's sources against this lane's target.  The append
@@ -1328,7 +1380,7 @@ __device__ void nuclear_item_compact_t(const typename P::Src* __restrict__ stg,
 #pragma unroll
                 for (int u = 0; u < NUC_U; ++u) {
                     const int j = j0 + u * TPT + q;
-                    lists[cnt * WG + tid] = (uint16_t)j;
+                    lists[cnt * WG + tid] = (uint16_t)(j * ES);
                     cnt += screen16(me_xy16, mef.z, tv[u]) < thr ? 1 : 0;
                 }
                 if (__ballot(cnt > NUC_CAP - NUC_U)) {
@@ -1340,7 +1392,7 @@ __device__ void nuclear_item_compact_t(const typename P::Src* __restrict__ stg,
             for (int u = 0; u < NUC_U; ++u) {
                 const int j = nfull + u * TPT + q;
                 if (j < n) {
-                    lists[cnt * WG + tid] = (uint16_t)j;
+                    lists[cnt * WG + tid] = (uint16_t)(j * ES);
                     cnt += screen16(me_xy16, mef.z, tst[j]) < thr ? 1 : 0;
                 }
             }
@@ -1350,7 +1402,7 @@ __device__ void nuclear_item_compact_t(const typename P::Src* __restrict__ stg,
         stage_neighbourhood<P, T>(
             stg, k, L, k.thr_stage,
             [&](int pos, const Lds& e, const uint3& f, int) {
-                src[pos] = e;
+                src[pos] = P::tile_entry(e);
                 tst[pos] = make_uint2((f.x >> 16) | (f.y & 0xffff0000u), f.z);
             },
             process);

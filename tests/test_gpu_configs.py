@@ -12,8 +12,8 @@
   on 2000 sampled targets against the oracle (per-particle gate) and the
   device clusters bit for bit against the oracle's cluster algorithm, with
   scipy's periodic k-d tree and connected components as a second witness.
-* Energy drift at the headline size (N = 51 200): FP64 and mixed NVE runs of
-  1000 steps from the same warmed state.
+* Energy drift at the headline size (N = 51 200): six FP64 and six mixed NVE
+  runs of 1000 steps from the same warmed positions.
 """
 import numpy as np
 import pytest
@@ -133,20 +133,25 @@ def test_large_system(env, name, prec):
 def test_energy_drift_headline(env):
     """Energy conservation at N = 51 200 (Y_P = 0.20, 0.08 fm^-3): 500 steps
     with the velocity rescaled every step take the random start's close
-    pairs out, then 1000 NVE steps of dt = 2 fm/c from that one state in FP64
-    and in mixed precision, H/N recorded every 20 fm/c.
+    pairs out; from those warmed positions, K = 6 NVE runs of 1000 steps of
+    dt = 2 fm/c, each with fresh Maxwell-Boltzmann velocities at T (seeded
+    per run, the same K velocity sets for FP64 and for mixed), H/N recorded
+    every 20 fm/c.
 
-    Stated bound: the mixed run's systematic drift (slope of a straight-line
-    fit of H/N over the window, per 1000 steps) stays within the FP64 run's
-    plus 1e-4 MeV, and its max |H(t) - H(0)|/N within twice the FP64 run's
-    (the FP32 pair arithmetic adds no drift of its own; the two chaotic
-    trajectories part, so their maxima differ by about the standard deviation
-    of H); for both, halving dt (2000 steps of 1 fm/c over the same span) at
-    least halves the standard deviation of H (the error is Verlet's).  The
-    FP64 drift itself is tied to the oracle's at N = 600
-    (test_gpu_parity.py::test_energy_drift), where the oracle runs the same
-    protocol; an oracle run of 1000 steps at N = 51 200 would take most of
-    an hour on the host."""
+    Stated bound (per nucleon, means over the K runs): the mixed runs'
+    max |H(t) - H(0)|/N is within the FP64 runs' plus 1e-4 MeV, and their
+    systematic drift (the mean slope of a straight-line fit of H/N, per 1000
+    steps) within the FP64 runs' plus 1e-4 MeV: the FP32 pair arithmetic
+    adds no drift of its own.  The means are taken because each trajectory
+    is chaotic: one run's max and slope scatter by about the standard
+    deviation of H (~2e-4 MeV here) from run to run, more than the 1e-4
+    margin; over K = 6 runs the scatter of the means is ~2.5x smaller.  For
+    both precisions, halving dt (2000 steps of 1 fm/c over the same span,
+    first velocity set) at least halves the standard deviation of H (the
+    error is Verlet's).  The FP64 drift itself is tied to the oracle's at
+    N = 600 (test_gpu_parity.py::test_energy_drift), where the oracle runs
+    the same protocol; an oracle run of 1000 steps at N = 51 200 would take
+    most of an hour on the host."""
     t, B = env["torch"], env["B"]
     st = env["I"].workload("n51200_yp020_n0.080")
     pos = t.tensor(st["pos"], device=env["dev"])
@@ -155,10 +160,16 @@ def test_energy_drift_headline(env):
     sim = B.Sim(pos, vel, sp, st["L"], dt=2.0, T=st["T"], rescale_every=1, precision=0)
     sim.step(500)
     t.cuda.synchronize()
-    p0, v0 = pos.clone(), vel.clone()
+    p0 = pos.clone()
     sim.close()
+    K = 6
+    vsets = []
+    for k in range(K):
+        rng = np.random.Generator(np.random.PCG64(5000 + k))
+        v = rng.standard_normal((st["n"], 3)) * np.sqrt(st["T"] / env["I"].MASS_MEV)
+        vsets.append(t.tensor(v, device=env["dev"]))
 
-    def series(prec, dt):
+    def series(prec, dt, v0):
         p, v = p0.clone(), v0.clone()
         s = B.Sim(p, v, sp, st["L"], dt=dt, T=st["T"], precision=prec)
         e = s.energies()
@@ -170,17 +181,26 @@ def test_energy_drift_headline(env):
         s.close()
         return np.array(H)
 
+    tt = np.linspace(0.0, 2000.0, 101)
     D, drift = {}, {}
     for prec in (0, 1):
-        h2, h1 = series(prec, 2.0), series(prec, 1.0)
-        D[prec] = np.abs(h2 - h2[0]).max()
-        drift[prec] = abs(np.polyfit(np.linspace(0.0, 2000.0, len(h2)), h2, 1)[0]) * 2000.0
-        say(f"  prec {prec}: D(dt=2) = {D[prec]:.3e} MeV/nucleon, linear drift "
-            f"{drift[prec]:.3e}, std {h2.std():.3e} (dt=2) {h1.std():.3e} (dt=1)")
-        assert np.all(np.isfinite(h2)) and np.all(np.isfinite(h1))
-        assert h1.std() <= 0.5 * h2.std()
+        ds, sl = [], []
+        for k in range(K):
+            h2 = series(prec, 2.0, vsets[k])
+            assert np.all(np.isfinite(h2))
+            ds.append(np.abs(h2 - h2[0]).max())
+            sl.append(np.polyfit(tt, h2, 1)[0] * 2000.0)
+            if k == 0:
+                h1 = series(prec, 1.0, vsets[k])
+                assert np.all(np.isfinite(h1))
+                say(f"  prec {prec}: std of H {h2.std():.3e} (dt=2) {h1.std():.3e} (dt=1)")
+                assert h1.std() <= 0.5 * h2.std()
+        D[prec], drift[prec] = float(np.mean(ds)), abs(float(np.mean(sl)))
+        say(f"  prec {prec}: max|H-H0| per run {' '.join(f'{x:.2e}' for x in ds)}"
+            f" mean {D[prec]:.3e}; slopes per run {' '.join(f'{x:.2e}' for x in sl)}"
+            f" |mean| {drift[prec]:.3e} MeV/nucleon per 1000 steps")
+    assert D[1] <= D[0] + 1e-4
     assert drift[1] <= drift[0] + 1e-4
-    assert D[1] <= 2.0 * D[0]
 
 
 def test_expansion_run_statistics(env):

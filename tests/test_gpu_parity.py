@@ -445,9 +445,13 @@ def test_energy_drift(env):
     for the chaotic divergence of the trajectories), and halving dt cuts it by
     at least 2x in its standard deviation over the window (Verlet's dt^2 law:
     the error is the integrator's, not the force arithmetic's; the max over a
-    chaotic trajectory is too noisy to carry the ratio).  The systematic part
-    (the slope of a straight-line fit of H over the window, per 1000 steps)
-    of the mixed run is within the FP64 run's plus 1e-4 MeV."""
+    chaotic trajectory is too noisy to carry the ratio).  The slope of a
+    straight-line fit of H over the window is reported but not gated here:
+    at N = 600, H fluctuates by ~2.5e-3 MeV/nucleon with correlation times
+    of hundreds of steps, so two chaotic trajectories' fitted slopes differ
+    by ~1e-3 by chance; the mixed-vs-FP64 systematic drift is gated at
+    N = 51 200 (test_gpu_configs.py::test_energy_drift_headline), where the
+    fluctuations are ten times smaller."""
     st = env["I"].make_state(600, 0.4, 0.04, 1.0, seed=1000)
     sim, pos, vel = make_sim(env, st, dt=2.0, T=1.0, rescale_every=1, precision=0)
     sim.step(300)
@@ -472,8 +476,6 @@ def test_energy_drift(env):
             f"std {h2.std():.3e} / {h1.std():.3e}; linear drift {drift[prec]:.3e}")
         assert d2 <= 2.0 * d_oracle + 1e-4
         assert h1.std() <= 0.5 * h2.std()
-    # the FP32 pair arithmetic adds no systematic drift of its own
-    assert drift[1] <= drift[0] + 1e-4
 
 
 # ------------------------------------------------------------------ a5 ----
@@ -532,7 +534,7 @@ def test_autotuner(env, tmp_path, monkeypatch):
     before = B.pasta_get_tuning()
     best, table = autotune.pasta_autotune(pos, sp, st["L"], B.PASTA_MIXED)
     assert B.pasta_get_tuning() == before
-    assert len(table) >= 6 and {0, 1, 3} == {c["nuclear_variant"] for c, _ in table}
+    assert len(table) >= 6 and {0, 1, 3, 4} == {c["nuclear_variant"] for c, _ in table}
     assert min(table, key=lambda r: r[1])[0] == best
     got, source, _ = autotune.tune(pos, sp, st["L"], B.PASTA_MIXED, apply=True)
     again, source2, _ = autotune.tune(pos, sp, st["L"], B.PASTA_MIXED, apply=True)

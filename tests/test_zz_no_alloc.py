@@ -17,8 +17,9 @@ def test_noalloc_matches_workspace_form():
     assert torch.cuda.is_available()
     dev = torch.device("cuda:0")
     for prec in (B.PASTA_FP64, B.PASTA_MIXED):
-        # the second input is smaller than the first
-        for (N, yp, dens, seed) in ((20000, 0.3, 0.06, 11), (2500, 0.4, 0.04, 12)):
+        # each input is smaller than the one before (the headline size first)
+        for (N, yp, dens, seed) in ((51200, 0.2, 0.08, 1001), (20000, 0.3, 0.06, 11),
+                                    (2500, 0.4, 0.04, 12)):
             print("noalloc prec", prec, "N", N, flush=True)
             st = inputs.make_state(N, yp, dens, 1.0, seed)
             pos = torch.tensor(st["pos"], device=dev)
