@@ -177,6 +177,18 @@ def run_batch(B, torch, states, precision, mode, steps, warmup, spg=10, tune=Fal
                 tuning=best, tuning_table=[[c, round(ms, 5)] for c, ms in table] if table else None)
 
 
+def single_via_batch(B, torch, st, steps, warmup):
+    """One system through the batched path in both modes, each tuned on it."""
+    vb = run_batch(B, torch, [st], B.PASTA_MIXED, 1, steps, warmup, tune=True)
+    vb0 = run_batch(B, torch, [st], B.PASTA_MIXED, 0, steps, warmup, tune=True)
+    out = {"multi_kernel_ms_per_step": vb["seconds"] / steps * 1e3,
+           "multi_kernel_tuning": vb["tuning"],
+           "persistent_ms_per_step": vb0["seconds"] / steps * 1e3,
+           "persistent_tuning": vb0["tuning"]}
+    log(f"single system via batch: {out}")
+    return out
+
+
 def run_sequential(B, torch, states, precision, steps, warmup):
     """The same systems one after another on the single-system path."""
     dev = torch.device("cuda:0")
@@ -416,12 +428,8 @@ def main():
     if args.section == "batch":
         res = batched_section(B, torch, args.batch_steps, min(args.warmup, 20))
         st1 = workload(WORKLOAD)
-        vb = run_batch(B, torch, [st1], B.PASTA_MIXED, 1, args.steps, args.warmup)
-        vb0 = run_batch(B, torch, [st1], B.PASTA_MIXED, 0, args.steps, args.warmup)
-        res["single_system_via_batch_path"] = {
-            "multi_kernel_ms_per_step": vb["seconds"] / args.steps * 1e3,
-            "persistent_ms_per_step": vb0["seconds"] / args.steps * 1e3}
-        log(f"single system via batch: {res['single_system_via_batch_path']}")
+        res["single_system_via_batch_path"] = single_via_batch(B, torch, st1, args.steps,
+                                                               args.warmup)
         print(json.dumps({"section": "batch", "result": res}))
         return
     if args.section:
@@ -573,12 +581,8 @@ def main():
     if not args.no_batch:
         batched = batched_section(B, torch, args.batch_steps, min(W, 20))
         # the same N = 51 200 system through the batched machinery (one
-        # system, per-phase kernels, graph replay) for comparison
-        vb = run_batch(B, torch, [st], B.PASTA_MIXED, 1, K, W)
-        vb0 = run_batch(B, torch, [st], B.PASTA_MIXED, 0, K, W)
-        via_batch = {"multi_kernel_ms_per_step": vb["seconds"] / K * 1e3,
-                     "persistent_ms_per_step": vb0["seconds"] / K * 1e3}
-        log(f"single system via batch: {via_batch}")
+        # system, graph replay, each mode tuned on it) for comparison
+        via_batch = single_via_batch(B, torch, st, K, W)
 
     cpu = None
     if not args.no_cpu_baseline:

@@ -130,33 +130,36 @@ def tune_list_skin(pos, vel, species, L: float, precision: int, T: float, skins=
 
 
 def tune_batch(pos, vel, species, ns, L0s, integs, precision: int, mode: int = 0,
-               variants=(1, 3), wgs_per_cu=(2, 3, 4, 5), steps: int = 60, warmup: int = 10,
-               steps_per_graph: int = 10):
+               variants=(1, 3), coulomb_forms=(0, 1), wgs_per_cu=(3, 4, 5), steps: int = 60,
+               warmup: int = 10, steps_per_graph: int = 10):
     """Chooses the batched path's kernel setting on its own workload by timed
-    runs: the nuclear variant and, for the persistent mode, the workgroups
-    per CU of the persistent kernel.  Each candidate advances a copy of the
-    systems `warmup` + `steps` steps.  Leaves the process-wide setting
-    unchanged.  Returns (best dict, [(candidate dict, ms per step)])."""
+    runs: the nuclear variant, the Coulomb form (gather tiles or pairwise
+    super-block items) and, for the persistent mode, the workgroups per CU
+    of the persistent kernel.  Each candidate advances a copy of the systems
+    `warmup` + `steps` steps.  Leaves the process-wide setting unchanged.
+    Returns (best dict, [(candidate dict, ms per step)])."""
     table = []
     old = B.pasta_get_tuning()
     grids = wgs_per_cu if mode == 0 else (0,)
     try:
         for v in variants:
-            for w in grids:
-                B.pasta_set_tuning(nuclear_variant=v, batch_wgs_per_cu=w)
-                p, q = pos.clone(), vel.clone()
-                b = B.Batch(p, q, species, ns, L0s, integs, precision=precision, mode=mode,
-                            steps_per_graph=steps_per_graph)
-                b.step(warmup)
-                torch.cuda.synchronize()
-                e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-                e0.record()
-                b.step(steps)
-                e1.record()
-                e1.synchronize()
-                table.append(({"nuclear_variant": v, "batch_wgs_per_cu": w},
-                              e0.elapsed_time(e1) / steps))
-                b.close()
+            for cf in coulomb_forms:
+                for w in grids:
+                    B.pasta_set_tuning(nuclear_variant=v, coulomb_form=cf, batch_wgs_per_cu=w)
+                    p, q = pos.clone(), vel.clone()
+                    b = B.Batch(p, q, species, ns, L0s, integs, precision=precision, mode=mode,
+                                steps_per_graph=steps_per_graph)
+                    b.step(warmup)
+                    torch.cuda.synchronize()
+                    e0 = torch.cuda.Event(enable_timing=True)
+                    e1 = torch.cuda.Event(enable_timing=True)
+                    e0.record()
+                    b.step(steps)
+                    e1.record()
+                    e1.synchronize()
+                    table.append(({"nuclear_variant": v, "coulomb_form": cf,
+                                   "batch_wgs_per_cu": w}, e0.elapsed_time(e1) / steps))
+                    b.close()
     finally:
         B.pasta_set_tuning(**old)
     best = min(table, key=lambda r: r[1])[0]

@@ -38,7 +38,9 @@ struct SysDev {
     int64_t item_off;     // nuclear items: item_max pairs
     int32_t item_max;
     int64_t coul_off;     // Coulomb partials: S*Z entries
-    int32_t S, per_split, coul_blocks;
+    // Coulomb form: 0 = gather tiles (coul_blocks x S splits of per_split
+    // sources), 1 = pairwise super-block items (S = super-blocks)
+    int32_t S, per_split, coul_blocks, coul_form;
     int64_t chunk_off;    // particle chunks of BW
     int32_t nchunks;
     int64_t coul_item_off;
@@ -444,12 +446,18 @@ __device__ void phase_forces(const BatchDev& B, int64_t step, int mode, char* ld
             s = __builtin_amdgcn_readfirstlane(s);  // uniform: the constants load as scalars
             const SysDev& S = B.sys[s];
             const int64_t local = it - S.coul_item_off;
-            const int tblock = (int)(local % S.coul_blocks), split = (int)(local / S.coul_blocks);
             const CoulConsts k = B.ck[s];
             using PT = typename P::CPart;
-            coulomb_item<P, M != MODE_FORCE, PT>(stg + S.off, S.Z, S.per_split, k,
-                                                 static_cast<PT*>(B.coul_part) + S.coul_off,
-                                                 tblock, split, lds);
+            PT* part = static_cast<PT*>(B.coul_part) + S.coul_off;
+            if (S.coul_form == 1) {
+                coulomb_pair_item<P, M != MODE_FORCE, PT>(stg + S.off, S.Z, k, part, (int)local,
+                                                          lds);
+            } else {
+                const int tblock = (int)(local % S.coul_blocks),
+                          split = (int)(local / S.coul_blocks);
+                coulomb_item<P, M != MODE_FORCE, PT>(stg + S.off, S.Z, S.per_split, k, part,
+                                                     tblock, split, lds);
+            }
         } else {
             const int64_t jt = it - B.coul_items;
             int s = 0;
@@ -484,9 +492,13 @@ __device__ void phase_forces(const BatchDev& B, int64_t step, int mode, char* ld
 }
 
 // energy: the pair phase accumulated energies; write the shares.
-// The Coulomb partials of a proton are summed in split order from zero and
-// the sum is added to the nuclear part, the association of the
-// single-system path (so a system gets the same bits either way).
+// The Coulomb partials of a proton are summed in partial order from zero
+// and the sum is added to the nuclear part, as in the single-system
+// combine.  That combine spreads a proton's partials over lanes and adds the
+// lane sums by a fixed tree; in mixed precision the partials are FP32 values
+// summed in FP64, which is exact unless their exponents span more than 29
+// bits, so the two orders give the same bits in practice (FP64 partials
+// can differ in the last bit).
 template <class P>
 __device__ void phase_combine(const BatchDev& B, int mode, bool energy, char* lds_raw)
 {
@@ -880,8 +892,13 @@ int batch_layout(const pasta_potential* pot, int nsys, const int64_t* n, const i
         S.start_off = lay.starts;
         S.item_max = (int32_t)(n[s] / batch_chunk() + C_max + 1);
         S.item_off = lay.items;
-        S.S = coulomb_splits(S.Z);
-        S.per_split = S.S ? (int32_t)((S.Z + S.S - 1) / S.S) : 0;
+        // the partial capacity depends on n only (the single-system path's
+        // rule), and the plan keeps S * Z within it for the system's Z
+        const int64_t cap = coulomb_partial_capacity(n[s]);
+        const CoulPlan cp = coulomb_plan(S.Z, cap, false);
+        S.coul_form = cp.form;
+        S.S = cp.S;
+        S.per_split = (S.S && cp.form == 0) ? (int32_t)((S.Z + S.S - 1) / S.S) : 0;
         S.coul_blocks = (int32_t)((S.Z + WG - 1) / WG);
         S.coul_off = lay.coul;
         S.nchunks = (int32_t)((n[s] + BW - 1) / BW);
@@ -892,11 +909,9 @@ int batch_layout(const pasta_potential* pot, int nsys, const int64_t* n, const i
         lay.bins += 2 * (int64_t)C_max * BSUB;
         lay.starts += 2 * (int64_t)C_max * BSUB + 1;
         lay.items += S.item_max;
-        // capacity for any proton count Z <= n: S(Z) Z <= max(min(32 n, 2^19), n)
-        const int64_t cap32 = 32 * n[s] < 524288 ? 32 * n[s] : 524288;
-        lay.coul += cap32 > n[s] ? cap32 : n[s];
+        lay.coul += cap;
         lay.total_chunks += S.nchunks;
-        lay.coul_items += (int64_t)S.coul_blocks * S.S;
+        lay.coul_items += cp.form == 1 ? coulomb_pair_items(S.Z) : (int64_t)S.coul_blocks * S.S;
         lay.nuc_items += S.item_max;
     }
     *out = lay;
@@ -1119,8 +1134,8 @@ extern "C" int pasta_batch_create(const pasta_potential* pot, int32_t precision,
     int rc = batch_layout(pot, nsys, h_n, Z.data(), h_L_max, &lay2);
     if (rc != PASTA_OK)
         return fail_free(rc);
-    // the Z-dependent layout must fit the carve made with Z = n (it does: S*Z
-    // and the Coulomb tiles only shrink)
+    // the Z-dependent layout fits the carve made with Z = n: the partial
+    // capacity per system depends on n only
     for (int s = 0; s < nsys; ++s) {
         SysDev& S = lay2.sys[s];
         S.coul_off = lay.sys[s].coul_off;

@@ -49,11 +49,20 @@ def make(env, specs, integs=None, prec=1, mode=0, spg=4, L_max=None):
     return b, states, pos, vel, offs
 
 
+@pytest.mark.parametrize("form", [0, 1])
 @pytest.mark.parametrize("mode", [0, 1])
 @pytest.mark.parametrize("prec", [0, 1])
-def test_batch_initial_forces(env, prec, mode):
-    say("batch initial forces prec", prec, "mode", mode)
-    b, states, pos, vel, offs = make(env, SMALL, prec=prec, mode=mode)
+def test_batch_initial_forces(env, prec, mode, form):
+    """Forces and energy shares of every system against the oracle, with the
+    Coulomb term as gather tiles (form 0) or as pairwise super-block items
+    (form 1; the all-neutron system has none, the all-proton one the most)."""
+    B = env["B"]
+    say("batch initial forces prec", prec, "mode", mode, "coulomb form", form)
+    old = B.pasta_set_tuning(coulomb_form=form)
+    try:
+        b, states, pos, vel, offs = make(env, SMALL, prec=prec, mode=mode)
+    finally:
+        B.pasta_set_tuning(**old)
     f, e = b.forces()
     f, e = f.cpu().numpy(), e.cpu().numpy()
     for k, st in enumerate(states):
@@ -109,13 +118,13 @@ def test_batch_modes_and_graph_replay_agree(env):
         assert np.abs(v - outs[0][1]).max() <= 1e-12
 
 
-@pytest.mark.parametrize("variant", [1, 3])
-def test_batch_matches_single_system_path(env, variant):
-    """With the same nuclear variant, the batched and single-system paths run
-    the same items in the same order."""
+@pytest.mark.parametrize("variant,form", [(1, 0), (3, 0), (3, 1)])
+def test_batch_matches_single_system_path(env, variant, form):
+    """With the same nuclear variant and Coulomb form, the batched and
+    single-system paths run the same items in the same order."""
     t, B = env["torch"], env["B"]
     specs = SMALL[:3]
-    old = B.pasta_set_tuning(nuclear_variant=variant)
+    old = B.pasta_set_tuning(nuclear_variant=variant, coulomb_form=form)
     try:
         b, states, pos, vel, offs = make(env, specs, prec=1, mode=0,
                                          integs=[dict(dt=2.0, T=1.0, rescale_every=5)] * 3)
@@ -129,7 +138,8 @@ def test_batch_matches_single_system_path(env, variant):
             sim.step(12)
             d = np.abs(p1.cpu().numpy() - P[offs[k]:offs[k + 1]])
             d = np.minimum(d, st["L"] - d)
-            say(f"  variant {variant} system {k}: batch vs single max |dx| {d.max():.3e}")
+            say(f"  variant {variant} form {form} system {k}: batch vs single max |dx| "
+                f"{d.max():.3e}")
             assert d.max() <= 1e-9
             sim.close()
         b.close()
