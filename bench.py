@@ -216,10 +216,21 @@ def kernel_ms(kt, steps):
     return {k: round(v[0] / max(steps, 1), 5) for k, v in kt.items() if v[1]}
 
 
+def kernel_variant(tuning):
+    """The fused kernel's variant template argument for a tuning: variant 3
+    with a 256- or 1024-source tile runs as 5 or 6."""
+    v, tile = tuning.get("nuclear_variant"), tuning.get("nuclear_tile", 0)
+    if v == 3 and tile in (256, 1024):
+        return 5 if tile == 256 else 6
+    return v
+
+
 def pair_kernel_name(tuning, use_lists=False):
-    if tuning.get("fused_forces"):
-        return "pair forces (nuclear %s + %s Coulomb tiles, one launch)" % (
+    if tuning.get("fused_forces") or kernel_variant(tuning) >= 4:
+        tile = tuning.get("nuclear_tile", 0)
+        return "pair forces (nuclear %s%s + %s Coulomb tiles, one launch)" % (
             "list items" if use_lists else "cell tiles",
+            " of %d sources" % tile if tile else "",
             "pairwise" if tuning.get("coulomb_form") else "gather")
     return "nuclear+kick"
 
@@ -406,8 +417,8 @@ def main():
     ap.add_argument("--section", choices=("large", "decompression", "batch"), default=None,
                     help="run only this section and print its JSON (for profiler runs)")
     ap.add_argument("--tuning", default=None,
-                    help="variant,splits,fused[,coulomb_form]: use this kernel setting instead "
-                         "of autotuning")
+                    help="variant,splits,fused[,coulomb_form[,nuclear_tile]]: use this kernel "
+                         "setting instead of autotuning")
     ap.add_argument("--headline-only", action="store_true",
                     help="time only the headline path (no dense, list, FP64 or batched runs); "
                          "for profiler runs")
@@ -458,7 +469,9 @@ def main():
         vals = [int(x) for x in args.tuning.split(",")]
         v, sp_, fu = vals[:3]
         cf = vals[3] if len(vals) > 3 else 0
-        tuned = dict(nuclear_variant=v, coulomb_splits=sp_, fused_forces=fu, coulomb_form=cf)
+        tile = vals[4] if len(vals) > 4 else 0
+        tuned = dict(nuclear_variant=v, coulomb_splits=sp_, fused_forces=fu, coulomb_form=cf,
+                     nuclear_tile=tile)
         tuned64, table, table64 = dict(tuned), [], []
         B.pasta_set_tuning(**tuned)
     else:
@@ -532,12 +545,12 @@ def main():
     dom = max(kt, key=lambda k: kt[k][0])
     ms_tot, launches = kt[dom]
     avg_ms = ms_tot / max(launches, 1)
-    if dom == "nuclear+kick" and tuned.get("fused_forces"):
+    if dom == "nuclear+kick" and (tuned.get("fused_forces") or kernel_variant(tuned) >= 4):
         # one launch carries both the nuclear items and the Coulomb tiles
         roof = roofline_entry(pair_kernel_name(tuned, use_lists), mixed["nuc_pairs"],
                               mixed["coul_pairs"], avg_ms, B.PASTA_MIXED)
         roof["traffic"] = None if use_lists else measured_traffic(
-            "k_forces_fused<MixedPolicy, 0, %d, %d>" % (tuned["nuclear_variant"],
+            "k_forces_fused<MixedPolicy, 0, %d, %d>" % (kernel_variant(tuned),
                                                        tuned.get("coulomb_form", 0)), tuned)
         roof["traffic_unit"] = "bytes per launch (HBM, counter runs in profiles/)"
     elif dom in ("coulomb", "nuclear+kick"):

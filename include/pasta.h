@@ -140,14 +140,20 @@ typedef struct pasta_integrator {
  *   (Newton's third law), the reaction carried along the wavefront by a
  *   lane rotation; 256-proton super-blocks, one partial per super-block and
  *   proton (used when those partials fit the workspace's partial buffer,
- *   else the gather form).  The batched path always uses the gather form.
+ *   else the gather form).  The batched path reads it at creation and plans
+ *   each system's Coulomb term the same way.
  * list_skin: the halo delta_r of variant 2, fm, in (0, 64] (default 2).
  * batch_wgs_per_cu: workgroups per compute unit of the persistent batched
  *   kernel (mode 0), 1..8, capped at what fits; 0 = as many as fit.  Read
  *   when a batch is created.
  * list_pool_scale: list memory relative to the default sizing, in (0, 1000]
  *   (default 1; the default holds 1.5 x the expected entries per lane at the
- *   starting density plus a Poisson margin). */
+ *   starting density plus a Poisson margin).
+ * nuclear_tile: sources per LDS tile of variant 3's items: 0 or 512 (the
+ *   default), 256 (more workgroups fit per CU, more end-of-tile drains) or
+ *   1024 (fewer drains, fewer workgroups per CU); a length other than the
+ *   default always runs in the fused form.  The other variants and the
+ *   batched path use their default tiles. */
 typedef struct pasta_tuning {
     int32_t nuclear_variant;
     int32_t coulomb_splits;
@@ -156,12 +162,14 @@ typedef struct pasta_tuning {
     double list_skin;
     double list_pool_scale;
     int32_t batch_wgs_per_cu;
+    int32_t nuclear_tile;
 } pasta_tuning;
 int pasta_set_tuning(const pasta_tuning* t);
 int pasta_get_tuning(pasta_tuning* out);
 /* Autotuner: builds the cell list of the given state once, then times the
  * Coulomb + nuclear kernels (reps evaluations each, HIP events) for every
- * candidate setting -- nuclear variant {0, 1, 3, 4 (fused only)} x Coulomb
+ * candidate setting -- nuclear variant {0, 1, 3, 4 (fused only), 3 with
+ * 256- and 1024-source tiles (fused only)} x Coulomb
  * {gather with splits S/2, S, 2S around the automatic S, pairwise} x
  * fused_forces {0, 1}
  * -- and returns the fastest

@@ -61,14 +61,14 @@ def pasta_autotune(pos, species, L: float, precision: int, reps: int = 3, pot=No
                                             ctypes.byref(nb)))
     work = B._workspace(nb.value, pos.device)
     best = B.pasta_tuning()
-    cap = 32
+    cap = 64
     ms = (ctypes.c_double * cap)()
     cands = (B.pasta_tuning * cap)()
     ncand = ctypes.c_int32(cap)
     B._check(B.lib.pasta_autotune(ctypes.byref(pot), precision, n, L, B._p(pos), B._p(species),
                                   B._p(work), work.numel(), B._stream(stream), reps,
                                   ctypes.byref(best), ms, cands, ctypes.byref(ncand)))
-    keys = ("nuclear_variant", "coulomb_splits", "fused_forces", "coulomb_form")
+    keys = ("nuclear_variant", "coulomb_splits", "fused_forces", "coulomb_form", "nuclear_tile")
     table = [({f: getattr(cands[k], f) for f in keys}, ms[k])
              for k in range(min(ncand.value, cap))]
     return {f: getattr(best, f) for f in keys}, table

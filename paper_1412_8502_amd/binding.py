@@ -46,11 +46,11 @@ class pasta_tuning(ctypes.Structure):
     _fields_ = [("nuclear_variant", ctypes.c_int32), ("coulomb_splits", ctypes.c_int32),
                 ("fused_forces", ctypes.c_int32), ("coulomb_form", ctypes.c_int32),
                 ("list_skin", ctypes.c_double), ("list_pool_scale", ctypes.c_double),
-                ("batch_wgs_per_cu", ctypes.c_int32)]
+                ("batch_wgs_per_cu", ctypes.c_int32), ("nuclear_tile", ctypes.c_int32)]
 
 
 TUNING_FIELDS = ("nuclear_variant", "coulomb_splits", "fused_forces", "coulomb_form",
-                 "list_skin", "list_pool_scale", "batch_wgs_per_cu")
+                 "list_skin", "list_pool_scale", "batch_wgs_per_cu", "nuclear_tile")
 
 
 class pasta_integrator(ctypes.Structure):

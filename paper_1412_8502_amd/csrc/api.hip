@@ -176,7 +176,7 @@ struct ListCfg {
 static ListCfg list_cfg(int terms, double L_min)
 {
     ListCfg c;
-    c.variant = (terms & PASTA_TERM_NUCLEAR) ? g_tuning.nuclear_variant : 1;
+    c.variant = (terms & PASTA_TERM_NUCLEAR) ? internal_variant(g_tuning) : 1;
     c.on = c.variant == 2;
     c.skin = g_tuning.list_skin;
     c.L_min = L_min;
@@ -284,8 +284,9 @@ static void eval_forces(int precision, int terms, const ForceWork& w, const Grid
     fb.cut_pos = pos;
     fb.cut_perm = pos_perm;
     // the Newton-3 variant needs the combine kernel (reactions from every
-    // item), so it always takes the fused form
-    if ((g_tuning.fused_forces || w.variant == 4) && (terms & PASTA_TERM_NUCLEAR)) {
+    // item), so it always takes the fused form, as do the non-default tile
+    // lengths (kernel variants 5 and 6)
+    if ((g_tuning.fused_forces || w.variant >= 4) && (terms & PASTA_TERM_NUCLEAR)) {
         launch_forces_fused(precision, fb, w.cb, g, n, Z, pp, true,
                             (terms & PASTA_TERM_COULOMB) != 0, force, epot, kick, pair_counter,
                             w.err, s, t, w.variant, lb);
@@ -330,7 +331,9 @@ extern "C" int pasta_set_tuning(const pasta_tuning* t)
         t->coulomb_splits > 32 || (t->fused_forces != 0 && t->fused_forces != 1) ||
         (t->coulomb_form != 0 && t->coulomb_form != 1) || !(t->list_skin > 0.0 && t->list_skin <= 64.0) ||
         !(t->list_pool_scale > 0.0 && t->list_pool_scale <= 1e3) || t->batch_wgs_per_cu < 0 ||
-        t->batch_wgs_per_cu > 8)
+        t->batch_wgs_per_cu > 8 ||
+        (t->nuclear_tile != 0 && t->nuclear_tile != NUC_TILE_SHORT && t->nuclear_tile != 512 &&
+         t->nuclear_tile != NUC_TILE_LONG))
         return fail(PASTA_EINVAL, "pasta_set_tuning: bad argument");
     g_tuning = *t;
     return PASTA_OK;
@@ -615,10 +618,14 @@ extern "C" int pasta_autotune(const pasta_potential* pot, int32_t precision, int
     const int S0 = Z > 0 ? coulomb_splits(Z) : 1;
     std::vector<pasta_tuning> cands;
     const bool pair_fits = Z > 0 && (int64_t)coulomb_pair_plan_supers(Z) * Z <= w.fb.coul_max;
+    // (public variant, tile length) pairs; 4 and the non-default tiles run
+    // in the fused form only
+    const int vt[][2] = {{0, 0}, {1, 0}, {3, 0}, {4, 0}, {3, NUC_TILE_SHORT}, {3, NUC_TILE_LONG}};
     for (int fused = 0; fused <= 1; ++fused)
-        for (int v : {0, 1, 3, 4}) {
-            if (v == 4 && !fused)
-                continue;  // the Newton-3 variant runs in the fused form only
+        for (const auto& p : vt) {
+            const int v = p[0], tile = p[1];
+            if ((v == 4 || tile) && !fused)
+                continue;
             int last = -1;
             for (int sc : {S0 / 2, S0, 2 * S0}) {
                 int sv = sc < 1 ? 1 : (sc > 32 ? 32 : sc);
@@ -627,6 +634,7 @@ extern "C" int pasta_autotune(const pasta_potential* pot, int32_t precision, int
                 last = sv;
                 pasta_tuning c = saved;
                 c.nuclear_variant = v;
+                c.nuclear_tile = tile;
                 c.coulomb_splits = sv;
                 c.fused_forces = fused;
                 c.coulomb_form = 0;
@@ -635,6 +643,7 @@ extern "C" int pasta_autotune(const pasta_potential* pot, int32_t precision, int
             if (pair_fits) {
                 pasta_tuning c = saved;
                 c.nuclear_variant = v;
+                c.nuclear_tile = tile;
                 c.coulomb_splits = 0;
                 c.fused_forces = fused;
                 c.coulomb_form = 1;
@@ -650,7 +659,7 @@ extern "C" int pasta_autotune(const pasta_potential* pot, int32_t precision, int
     int rc = PASTA_OK;
     for (size_t c = 0; c < cands.size() && rc == PASTA_OK; ++c) {
         g_tuning = cands[c];
-        cells_for(cands[c].nuclear_variant);
+        cells_for(internal_variant(cands[c]));
         // one untimed warm-up, then reps timed evaluations
         eval_forces(precision, PASTA_TERM_ALL, w, g, n, Z, pp, f, e, kick, nullptr, s, nullptr,
                     d_pos, w.cb.perm);

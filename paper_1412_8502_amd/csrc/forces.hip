@@ -123,8 +123,11 @@ constexpr int fused_lds_bytes()
 {
     static_assert(coulomb_pair_lds_bytes<P>() <= coulomb_lds_bytes<P>(), "LDS of the pair form");
     constexpr int a = coulomb_lds_bytes<P>();
-    constexpr int b = V == 0 ? nuclear_lds_bytes<P>()
-                             : (V == 4 ? nuclear_half_lds_bytes<P>() : nuclear_compact_lds_bytes<P>());
+    constexpr int b = V == 0   ? nuclear_lds_bytes<P>()
+                      : V == 4 ? nuclear_half_lds_bytes<P>()
+                      : V == 5 ? nuclear_compact_lds_bytes<P, NUC_TILE_SHORT>()
+                      : V == 6 ? nuclear_compact_lds_bytes<P, NUC_TILE_LONG>()
+                               : nuclear_compact_lds_bytes<P>();
     return a > b ? a : b;
 }
 
@@ -151,6 +154,10 @@ __global__ __launch_bounds__(WG) void k_forces_fused(const typename P::Src* __re
             nuclear_item_compact_t<P, 8, true, MODE>(stg, A, k, g, lds);
         else if constexpr (V == 4)
             nuclear_item_half<P, MODE>(stg, A, k, g, lds, A.react);
+        else if constexpr (V == 5)
+            nuclear_item_compact_t<P, 8, true, MODE, NUC_TILE_SHORT>(stg, A, k, g, lds);
+        else if constexpr (V == 6)
+            nuclear_item_compact_t<P, 8, true, MODE, NUC_TILE_LONG>(stg, A, k, g, lds);
         else if constexpr (V == 1)
             nuclear_item_compact<P, true, MODE>(stg, A, k, g, lds);
         else
@@ -361,7 +368,7 @@ void nuclear_dispatch(const typename P::Src* stg, const NucArgs& a, const int32_
 
 int nuclear_chunk_for(int variant)
 {
-    return (variant == 2 || variant == 3 || variant == 4) ? LIST_CHUNK : NUC_CHUNK;
+    return (variant >= 2) ? LIST_CHUNK : NUC_CHUNK;
 }
 
 static ListArgs list_args(const ListBuf* lb)
@@ -470,7 +477,7 @@ int64_t coulomb_partial_capacity(int64_t n)
     return cap > n ? cap : n;
 }
 
-pasta_tuning g_tuning = {1, 0, 1, 0, 2.0, 1.0, 0};  // coulomb_form 0: gather
+pasta_tuning g_tuning = {1, 0, 1, 0, 2.0, 1.0, 0, 0};  // coulomb_form 0: gather
 
 void launch_forces_fused(int precision, const ForceBuf& fb, const CellBuf& cb, const Grid& g,
                          int64_t n, int64_t Z, const PairParams& pp, bool with_nuclear_terms,
@@ -542,6 +549,8 @@ void launch_forces_fused(int precision, const ForceBuf& fb, const CellBuf& cb, c
             case 2: go(std::integral_constant<int, 2>(), mt); break;
             case 3: go(std::integral_constant<int, 3>(), mt); break;
             case 4: go(std::integral_constant<int, 4>(), mt); break;
+            case 5: go(std::integral_constant<int, 5>(), mt); break;
+            case 6: go(std::integral_constant<int, 6>(), mt); break;
             default: go(std::integral_constant<int, 1>(), mt); break;
             }
         });

@@ -440,6 +440,21 @@ int64_t coulomb_partial_capacity(int64_t n);
 int coulomb_pair_plan_supers(int64_t Z);
 // Process-wide kernel choices (set through pasta_set_tuning).
 extern pasta_tuning g_tuning;
+// Source-tile lengths of the compacting nuclear items besides the default
+// 512 (pasta_tuning.nuclear_tile; variant 3, fused form).
+constexpr int NUC_TILE_SHORT = 256;
+constexpr int NUC_TILE_LONG = 1024;
+// The kernel variant a tuning runs: the public variant, except variant 3
+// with a non-default tile length, which runs as 5 (256 sources) or 6
+// (1024 sources).
+inline int internal_variant(const pasta_tuning& t)
+{
+    if (t.nuclear_variant == 3 && t.nuclear_tile == NUC_TILE_SHORT)
+        return 5;
+    if (t.nuclear_variant == 3 && t.nuclear_tile == NUC_TILE_LONG)
+        return 6;
+    return t.nuclear_variant;
+}
 size_t forcebuf_carve(Carver& cv, ForceBuf* out, int64_t n, int64_t item_max, int precision);
 
 // Coulomb all-pairs over protons (sorted slots [0, Z)).
@@ -457,8 +472,8 @@ void launch_nuclear(int precision, const ForceBuf& fb, const CellBuf& cb, const 
                     int coul_S, double* force, double* epot, const KickArgs& kick,
                     uint64_t* pair_counter, uint32_t* err, hipStream_t s, Timer* t,
                     int variant, const ListBuf* lb = nullptr);
-// Targets per nuclear work item (the scan's chunk) for a nuclear variant:
-// 64 for variants 0 and 1 (4 lanes per target), 32 for 2 and 3 (8 lanes).
+// Targets per nuclear work item (the scan's chunk) for a kernel variant:
+// 64 for variants 0 and 1 (4 lanes per target), 32 for 2 to 6 (8 lanes).
 int nuclear_chunk_for(int variant);
 // Neighbour-list build (gated on lb.ctl->rebuild) for the cells of grid g.
 void launch_list_build(int precision, const ForceBuf& fb, const CellBuf& cb, const Grid& g,

@@ -599,6 +599,118 @@ __host__ __device__ inline void coulomb_pair_ab(int item, int S, int* A_out, int
     *B_out = A + r;
 }
 
+// Off-diagonal item (A < B) whose eight blocks are all full: two targets
+// per lane.  Wave w holds target blocks I1 = 4A + 2(w & 1) and I1 + 1 (one
+// target of each per lane) and meets source blocks J = 4B + 2(w >> 1) and
+// J + 1, one after the other; each source and its reaction accumulator meet
+// both of the lane's targets before they move, so one set of row rotations
+// serves two pairs.  Every target block is covered by two wavefronts (w and
+// w ^ 2) and every source block by two (w and w ^ 1); their FP32 sums meet
+// in LDS and are added in FP64 in wavefront order.  The pairs evaluated and
+// the partials written are those of the one-target schedule.
+template <class P, bool E, class PT>
+__device__ void coulomb_pair_item_2t(const typename P::Src* __restrict__ stg, int Z,
+                                     const CoulConsts& k, PT* __restrict__ part, int A, int Bs,
+                                     char* lds)
+{
+    using Src = typename P::Src;
+    using CA = typename P::CAcc;
+    // [wave][2 target blocks][lane][4], then [wave][2 source blocks][lane][4]
+    CA* acc_t = reinterpret_cast<CA*>(lds);
+    CA* acc_s = acc_t + CP_SUPER * 2 * 64 * 4;
+    const int tid = threadIdx.x, w = tid >> 6, lane = tid & 63;
+    const int I1 = CP_SUPER * A + 2 * (w & 1), J1 = CP_SUPER * Bs + 2 * (w >> 1);
+    const Src me1 = stg[I1 * 64 + lane], me2 = stg[I1 * 64 + 64 + lane];
+    CA t1x = 0, t1y = 0, t1z = 0, t1e = 0, t2x = 0, t2y = 0, t2z = 0, t2e = 0;
+#pragma unroll 1
+    for (int jj = 0; jj < 2; ++jj) {
+        Src src = stg[(J1 + jj) * 64 + lane];
+        CA sx = 0, sy = 0, sz = 0, se = 0;
+#pragma unroll 1
+        for (int rho = 0; rho < 4; ++rho) {
+            for (int c = 0; c < 16; ++c) {
+                CA dx, dy, dz, fs, wv;
+                P::coul_pair(me1, src, k, dx, dy, dz, fs, wv);
+                t1x += fs * dx;
+                t1y += fs * dy;
+                t1z += fs * dz;
+                sx -= fs * dx;
+                sy -= fs * dy;
+                sz -= fs * dz;
+                if (E) {
+                    t1e += wv;
+                    se += wv;
+                }
+                P::coul_pair(me2, src, k, dx, dy, dz, fs, wv);
+                t2x += fs * dx;
+                t2y += fs * dy;
+                t2z += fs * dz;
+                sx -= fs * dx;
+                sy -= fs * dy;
+                sz -= fs * dz;
+                if (E) {
+                    t2e += wv;
+                    se += wv;
+                }
+                src = move_src(src, [](auto v) { return row_rotate(v); });
+                sx = row_rotate(sx);
+                sy = row_rotate(sy);
+                sz = row_rotate(sz);
+                if (E)
+                    se = row_rotate(se);
+            }
+            src = move_src(src, [](auto v) { return row_shift(v); });
+            sx = row_shift(sx);
+            sy = row_shift(sy);
+            sz = row_shift(sz);
+            if (E)
+                se = row_shift(se);
+        }
+        CA* a = acc_s + ((w * 2 + jj) * 64 + lane) * 4;
+        a[0] = sx;
+        a[1] = sy;
+        a[2] = sz;
+        a[3] = se;
+    }
+    {
+        CA* a = acc_t + ((w * 2 + 0) * 64 + lane) * 4;
+        a[0] = t1x;
+        a[1] = t1y;
+        a[2] = t1z;
+        a[3] = t1e;
+        a += 64 * 4;
+        a[0] = t2x;
+        a[1] = t2y;
+        a[2] = t2z;
+        a[3] = t2e;
+    }
+    __syncthreads();
+    // wavefront b writes block b of A (targets; its partial from B) and
+    // block b of B (sources; its partial from A)
+    const double fsc = P::coul_fscale(k), vsc = P::coul_vscale(k);
+    {
+        const int b = w;
+        const int w0 = b >> 1, slot = b & 1;  // waves w0 and w0 + 2 hold target block b
+        const CA* a0 = acc_t + ((w0 * 2 + slot) * 64 + lane) * 4;
+        const CA* a1 = acc_t + (((w0 + 2) * 2 + slot) * 64 + lane) * 4;
+        const int t = (CP_SUPER * A + b) * 64 + lane;
+        store_part(&part[(int64_t)Bs * Z + t], ((double)a0[0] + (double)a1[0]) * fsc,
+                   ((double)a0[1] + (double)a1[1]) * fsc, ((double)a0[2] + (double)a1[2]) * fsc,
+                   ((double)a0[3] + (double)a1[3]) * vsc);
+    }
+    {
+        const int b = w;
+        const int w0 = 2 * (b >> 1), slot = b & 1;  // waves w0 and w0 + 1 hold source block b
+        const CA* a0 = acc_s + ((w0 * 2 + slot) * 64 + lane) * 4;
+        const CA* a1 = acc_s + (((w0 + 1) * 2 + slot) * 64 + lane) * 4;
+        const int p = (CP_SUPER * Bs + b) * 64 + lane;
+        store_part(&part[(int64_t)A * Z + p], ((double)a0[0] + (double)a1[0]) * fsc,
+                   ((double)a0[1] + (double)a1[1]) * fsc, ((double)a0[2] + (double)a1[2]) * fsc,
+                   ((double)a0[3] + (double)a1[3]) * vsc);
+    }
+    __syncthreads();
+}
+
 template <class P, bool E, class PT = double4>
 __device__ void coulomb_pair_item(const typename P::Src* __restrict__ stg, int Z,
                                   const CoulConsts& k, PT* __restrict__ part, int item,
@@ -610,6 +722,10 @@ __device__ void coulomb_pair_item(const typename P::Src* __restrict__ stg, int Z
     const int S = coulomb_pair_supers(Z);
     int A, Bs;
     coulomb_pair_ab(item, S, &A, &Bs);
+    if (A != Bs && CP_SUPER * Bs + CP_SUPER <= Z / 64) {  // A < B, every block full
+        coulomb_pair_item_2t<P, E, PT>(stg, Z, k, part, A, Bs, lds);
+        return;
+    }
     const int tid = threadIdx.x, w = tid >> 6, lane = tid & 63;
     const int nb = (Z + 63) / 64;
     for (int i = tid; i < CP_SUPER * CP_SUPER * 64 * 4; i += WG)
@@ -1295,21 +1411,21 @@ __device__ void nuclear_finish(const NucArgs& A, const NucConsts& k, typename P:
     }
 }
 
-template <class P>
+// T: sources per LDS tile (the policy's default, or a tuned length)
+template <class P, int T = P::CTILE>
 constexpr int nuclear_compact_lds_bytes()
 {
-    return P::CTILE * ((int)sizeof(typename P::Lds) + 8) + NUC_CAP * WG * 2 + ITEM_LDS_BYTES;
+    return T * ((int)sizeof(typename P::Lds) + 8) + NUC_CAP * WG * 2 + ITEM_LDS_BYTES;
 }
 
 static_assert(nuclear_compact_lds_bytes<MixedPolicy>() <= 26 * 1024 + 512,
               "mixed compacting item: six workgroups per CU");
 
-template <class P, int TPT, bool NUC, int MODE>
+template <class P, int TPT, bool NUC, int MODE, int T = P::CTILE>
 __device__ void nuclear_item_compact_t(const typename P::Src* __restrict__ stg,
                                        const NucArgs& A, const NucConsts& k, int item, char* lds)
 {
     using Lds = typename P::Lds;
-    constexpr int T = P::CTILE;
     Lds* src = reinterpret_cast<Lds*>(lds);
     uint2* tst = reinterpret_cast<uint2*>(src + T);
     uint16_t* lists = reinterpret_cast<uint16_t*>(tst + T);

@@ -121,7 +121,8 @@ def test_argument_errors(B):
     assert B.lib.pasta_get_tuning(ctypes.byref(t)) == 0
     for field, value in (("nuclear_variant", 5), ("list_skin", 0.0), ("list_skin", -1.0),
                          ("batch_wgs_per_cu", 9), ("batch_wgs_per_cu", -1),
-                         ("list_pool_scale", 0.0), ("coulomb_form", 2), ("fused_forces", 2)):
+                         ("list_pool_scale", 0.0), ("coulomb_form", 2), ("fused_forces", 2),
+                         ("nuclear_tile", 128), ("nuclear_tile", 2048), ("nuclear_tile", -1)):
         bad_t = B.pasta_tuning()
         ctypes.pointer(bad_t)[0] = t
         setattr(bad_t, field, value)
@@ -129,6 +130,13 @@ def test_argument_errors(B):
     cur = B.pasta_tuning()
     assert B.lib.pasta_get_tuning(ctypes.byref(cur)) == 0
     assert B.tuning_dict(cur) == B.tuning_dict(t)
+    # the tile lengths the library has kernels for are accepted
+    for tile in (0, 256, 512, 1024):
+        ok_t = B.pasta_tuning()
+        ctypes.pointer(ok_t)[0] = t
+        ok_t.nuclear_tile = tile
+        assert B.lib.pasta_set_tuning(ctypes.byref(ok_t)) == 0, tile
+    assert B.lib.pasta_set_tuning(ctypes.byref(t)) == 0
     # bad integrator
     g = B.pasta_integrator(-1.0, 0.0, 1.0, 0, 0)
     nb = ctypes.c_size_t()

@@ -137,8 +137,8 @@ def test_forces_full_size(env, name, cf, prec):
 @pytest.mark.parametrize("prec", [0, 1])
 def test_nuclear_variants_agree(env, prec):
     """The dense cell-tile kernel and the screened + compacted kernel (4 or 8
-    lanes per target) give the same forces to rounding, and all match the
-    oracle."""
+    lanes per target; 256-, 512- and 1024-source tiles) give the same forces
+    to rounding, and all match the oracle."""
     B = env["B"]
     st = env["I"].make_state(9000, 0.3, 0.06, 1.0, seed=61)
     pos, sp = to_dev(env, st)
@@ -150,6 +150,12 @@ def test_nuclear_variants_agree(env, prec):
                 for cf in (0, 1):
                     B.pasta_set_tuning(nuclear_variant=v, fused_forces=fused, coulomb_form=cf)
                     out.append(B.pasta_forces(pos, sp, st["L"], precision=prec))
+        # variant 3 with 256- and 1024-source tiles (fused form)
+        for tile in (256, 1024):
+            for cf in (0, 1):
+                B.pasta_set_tuning(nuclear_variant=3, fused_forces=1, coulomb_form=cf,
+                                   nuclear_tile=tile)
+                out.append(B.pasta_forces(pos, sp, st["L"], precision=prec))
     finally:
         B.pasta_set_tuning(**old)
     of, oe = env["O"].forces(st["pos"], st["species"], st["L"])
@@ -535,6 +541,7 @@ def test_autotuner(env, tmp_path, monkeypatch):
     best, table = autotune.pasta_autotune(pos, sp, st["L"], B.PASTA_MIXED)
     assert B.pasta_get_tuning() == before
     assert len(table) >= 6 and {0, 1, 3, 4} == {c["nuclear_variant"] for c, _ in table}
+    assert {0, 256, 1024} == {c["nuclear_tile"] for c, _ in table}
     assert min(table, key=lambda r: r[1])[0] == best
     got, source, _ = autotune.tune(pos, sp, st["L"], B.PASTA_MIXED, apply=True)
     again, source2, _ = autotune.tune(pos, sp, st["L"], B.PASTA_MIXED, apply=True)
@@ -546,6 +553,26 @@ def test_autotuner(env, tmp_path, monkeypatch):
     of, _ = env["O"].forces(st["pos"], st["species"], st["L"])
     check(f.cpu().numpy(), of, 1, what="tuned", say=say)
 
+
+
+@pytest.mark.parametrize("prec", [0, 1])
+@pytest.mark.parametrize("tile", [256, 1024])
+def test_tile_lengths_full_size(env, tile, prec):
+    """Variant 3 with a non-default source-tile length on the headline state:
+    every one of the 51 200 targets against the oracle (per-particle gate),
+    and the same bits on a repeated call."""
+    B = env["B"]
+    st = env["I"].workload("n51200_yp020_n0.080")
+    pos, sp = to_dev(env, st)
+    old = B.pasta_set_tuning(nuclear_variant=3, fused_forces=1, coulomb_form=1, nuclear_tile=tile)
+    try:
+        f, e = B.pasta_forces(pos, sp, st["L"], precision=prec)
+        f2, e2 = B.pasta_forces(pos, sp, st["L"], precision=prec)
+    finally:
+        B.pasta_set_tuning(**old)
+    assert env["torch"].equal(f, f2) and env["torch"].equal(e, e2)
+    of, oe = env["O"].forces(st["pos"], st["species"], st["L"])
+    check(f.cpu().numpy(), of, prec, e.cpu().numpy(), oe, what=f"tile {tile}", say=say)
 
 # ------------------------------------------- Newton-3 half stencil (variant 4)
 @pytest.mark.parametrize("prec", [0, 1])
