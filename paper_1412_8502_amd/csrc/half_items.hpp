@@ -205,7 +205,7 @@ __device__ void nuclear_item_half(const typename P::Src* __restrict__ stg, const
             __syncthreads();
         };
         stage_neighbourhood<P, T, 14>(
-            stg, k, L, k.thr_stage,
+            stg, k, L, k.thr_stage16,
             [&](int pos, const Lds& e, const uint3& f, int slot) {
                 src[pos] = e;
                 tst[pos] = make_uint2((f.x >> 16) | (f.y & 0xffff0000u), f.z);

@@ -68,7 +68,7 @@ __device__ void list_build_item(const typename P::Src* __restrict__ stg, const N
         cnt = 0;
         int32_t* out = LA.pool + ((int64_t)row0 * WG + tid);
         stage_neighbourhood<P, LIST_TILE>(
-            stg, kl, L, kl.thr_stage,
+            stg, kl, L, kl.thr_stage16,
             [&](int pos, const typename P::Lds&, const uint3& f, int slot) {
                 cand[pos] = make_uint4(f.x, f.y, f.z, (uint32_t)slot);
             },

@@ -65,7 +65,7 @@ struct NucConsts {
     // screening pass of the compacting kernel
     double qscale;  // 2^32 / L (fixed-point units per fm)
     int thr16;      // (r_nuc / (L/2^16) + 2)^2: conservative 16-bit test
-    float thr_stage;  // r_nuc^2 in 32-bit units^2, with a rounding margin
+    uint32_t thr_stage16;  // (r_nuc / (L/2^16))^2 + 1: the staging gap test
 };
 
 __host__ __device__ inline NucConsts make_nuc_consts(const PairParams& pp)
@@ -95,7 +95,8 @@ __host__ __device__ inline NucConsts make_nuc_consts(const PairParams& pp)
     k.qscale = 4294967296.0 / pp.L;
     const double r16 = pp.r_nuc * 65536.0 / pp.L + 2.0;
     k.thr16 = (int)(r16 * r16) + 1;
-    k.thr_stage = (float)(k.rc2 / (k.q * k.q) * (1.0 + 1e-5));
+    const double rs = pp.r_nuc * 65536.0 / pp.L;
+    k.thr_stage16 = (uint32_t)(rs * rs) + 1u;
     return k;
 }
 
@@ -1088,24 +1089,70 @@ __device__ __forceinline__ int screen16(uint32_t me_xy16, uint32_t me_z, uint2 t
 }
 
 // LDS scratch shared by the cell-item helpers below (after the tiles).
+// Candidate-index buckets: bucket[b] is the neighbour bin holding candidate
+// b * SEG_BUCKET (for the first SEG_BUCKETS * SEG_BUCKET candidates), so a
+// candidate's bin is found from its bucket's bin by a short forward walk.
+constexpr int SEG_BUCKET = 32;
+constexpr int SEG_BUCKETS = WG;
 struct ItemLds {
     int* seg_beg;   // [54] first sorted slot of each neighbour bin
     int* seg_off;   // [55] exclusive prefix of the bin lengths
     int* misc;      // [24] box lo/hi, per-wave kept counts
     double* ke_red;  // [WG/64]
     unsigned long long* np_red;  // [WG/64]
+    uint8_t* bucket;  // [SEG_BUCKETS]
 };
-constexpr int ITEM_LDS_BYTES = 54 * 4 + 55 * 4 + 24 * 4 + 4 * 8 + 4 * 8 + 16;
+constexpr int ITEM_LDS_BYTES = 54 * 4 + 55 * 4 + 24 * 4 + 4 * 8 + 4 * 8 + 16 + SEG_BUCKETS;
 __device__ inline ItemLds item_lds(char* p)
 {
     ItemLds s;
     s.seg_beg = reinterpret_cast<int*>(p);
     s.seg_off = s.seg_beg + 54;
     s.misc = s.seg_off + 55;
+    // the buckets right after misc (a plain offset, so the compiler keeps
+    // them in LDS), then the 8-byte aligned reductions
+    s.bucket = reinterpret_cast<uint8_t*>(s.misc + 24);
     s.ke_red = reinterpret_cast<double*>(
-        (reinterpret_cast<uintptr_t>(s.misc + 24) + 7) & ~uintptr_t(7));
+        (reinterpret_cast<uintptr_t>(s.bucket + SEG_BUCKETS) + 7) & ~uintptr_t(7));
     s.np_red = reinterpret_cast<unsigned long long*>(s.ke_red + WG / 64);
     return s;
+}
+
+// The neighbour bin of candidate g (seg_off ascending, g < seg_off[2 NCELL]):
+// binary search.
+template <int NCELL>
+__device__ inline int seg_search(const ItemLds& L, int g)
+{
+    int seg = 0, hi = 2 * NCELL;
+    while (hi - seg > 1) {
+        const int mid = (seg + hi) >> 1;
+        if (L.seg_off[mid] <= g)
+            seg = mid;
+        else
+            hi = mid;
+    }
+    return seg;
+}
+
+// The bins are at most 54 and the buckets one byte each.
+static_assert(2 * 27 <= 256, "bucket entries are bytes");
+
+// Conservative staging test on 16-bit truncated coordinates, one packed
+// pair of axes: with d = s - c (the wrapped 16-bit difference of source and
+// box centre) and hh = ceil(half extent) + 1 (16-bit units), adds
+// max(|d| - hh, 0)^2 for both halves to acc.  |d| - 1 bounds the true
+// offset from below, so the sum bounds the squared gap to the box from
+// below (in (L / 2^16)^2 units).
+__device__ __forceinline__ uint32_t gap2_16(uint32_t s, uint32_t c, uint32_t hh, uint32_t acc)
+{
+    typedef short v2s __attribute__((ext_vector_type(2)));
+    typedef unsigned short v2u __attribute__((ext_vector_type(2)));
+    const v2s d = __builtin_bit_cast(v2s, s) - __builtin_bit_cast(v2s, c);
+    const v2s nd = (v2s)0 - d;
+    const v2s a = __builtin_elementwise_max(d, nd);  // |d|; -32768 stays 0x8000
+    const v2u au = __builtin_bit_cast(v2u, a), h = __builtin_bit_cast(v2u, hh);
+    const v2u g = __builtin_elementwise_sub_sat(au, h);
+    return __builtin_amdgcn_udot2(g, g, acc, false);
 }
 
 // The item's target: chunk `chunk` of cell c holds targets chunk*(WG/TPT) +
@@ -1203,21 +1250,26 @@ __device__ inline void item_setup(const NucArgs& A, const ItemLds& L, int c, boo
         atomicMax(reinterpret_cast<unsigned*>(&L.misc[5]), mef.z);
     }
     __syncthreads();
+    // the bin of every SEG_BUCKET-th candidate
+    if (tid < SEG_BUCKETS && tid * SEG_BUCKET < L.seg_off[NS])
+        L.bucket[tid] = (uint8_t)seg_search<NCELL>(L, tid * SEG_BUCKET);
+    __syncthreads();
 }
 
 // Stages the neighbourhood in rounds of SP candidates per thread (SP * WG
-// at most the tile size T, so a round fits the tile after a flush): locate (a
-// binary search for the first, a short forward walk for the next), load,
-// keep the sources whose periodic gap to the targets' box (centre and half
-// extent, rounded up) is below sqrt(thr_stage) fixed-point units, and
-// compact them in candidate order (so protons stay first).  put(pos, src,
+// at most the tile size T, so a round fits the tile after a flush): locate
+// (the candidate's bucket, then a short forward walk; a binary search past
+// the buckets), load, keep the sources whose periodic gap to the targets'
+// box may be below r (a conservative test on 16-bit truncated coordinates,
+// gap2_16, against thr_stage16 = (r / (L/2^16))^2 + 1), and compact them in
+// candidate order (so protons stay first).  put(pos, src,
 // fixed, slot) stores a kept source at tile position pos; flush(n, np) is
 // called, by the whole workgroup, when the next round might not fit in a
 // tile of T entries and at the end (np = protons among the n).
 template <class P, int T, int NCELL = 27, class Put, class Flush>
 __device__ __forceinline__ void stage_neighbourhood(const typename P::Src* __restrict__ stg,
                                                     const NucConsts& k, const ItemLds& L,
-                                                    float thr_stage, Put put, Flush flush)
+                                                    uint32_t thr_stage16, Put put, Flush flush)
 {
     using Lds = typename P::Lds;
     // a round keeps at most SP * WG candidates, which must fit an empty tile
@@ -1225,37 +1277,30 @@ __device__ __forceinline__ void stage_neighbourhood(const typename P::Src* __res
     static_assert(SP >= 1 && SP * WG <= T, "a staging round must fit one tile");
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     const int total = L.seg_off[2 * NCELL], np_tot = L.seg_off[NCELL];
-    uint32_t bc[3], bh[3];
+    // box centre (16-bit truncated) and half extent, rounded up, plus the
+    // one unit of truncation (16-bit units)
+    uint32_t bc[3], hh[3];
 #pragma unroll
     for (int a = 0; a < 3; ++a) {
         const uint32_t lo = (uint32_t)L.misc[a], ext = (uint32_t)L.misc[3 + a] - lo;
-        bc[a] = lo + (ext >> 1);
-        bh[a] = ext - (ext >> 1);
+        bc[a] = (lo + (ext >> 1)) >> 16;
+        hh[a] = (uint32_t)(((uint64_t)(ext - (ext >> 1)) + 65535u) >> 16) + 1u;
     }
+    const uint32_t cxy = bc[0] | (bc[1] << 16), hxy = hh[0] | (hh[1] << 16);
     int tile_n = 0, tile_np = 0;  // workgroup-uniform tile fill
     for (int base = 0; base < total; base += SP * WG) {
         bool keep[SP];
         uint3 f[SP];
         int gidx[SP], src_idx[SP];
-        int seg = 0;
 #pragma unroll
         for (int u = 0; u < SP; ++u) {
             gidx[u] = base + u * WG + tid;
             src_idx[u] = -1;
             if (gidx[u] < total) {
-                if (u == 0) {
-                    int hi = 2 * NCELL;
-                    while (hi - seg > 1) {
-                        const int mid = (seg + hi) >> 1;
-                        if (L.seg_off[mid] <= gidx[u])
-                            seg = mid;
-                        else
-                            hi = mid;
-                    }
-                } else {
-                    while (L.seg_off[seg + 1] <= gidx[u])
-                        ++seg;
-                }
+                const int b = gidx[u] / SEG_BUCKET;
+                int seg = b < SEG_BUCKETS ? (int)L.bucket[b] : seg_search<NCELL>(L, gidx[u]);
+                while (L.seg_off[seg + 1] <= gidx[u])
+                    ++seg;
                 src_idx[u] = L.seg_beg[seg] + (gidx[u] - L.seg_off[seg]);
             }
         }
@@ -1266,16 +1311,9 @@ __device__ __forceinline__ void stage_neighbourhood(const typename P::Src* __res
 #pragma unroll
         for (int u = 0; u < SP; ++u) {
             f[u] = P::fixed(sv[u], k);
-            float g2 = 0.f;
-            const uint32_t fv[3] = {f[u].x, f[u].y, f[u].z};
-#pragma unroll
-            for (int a = 0; a < 3; ++a) {
-                const int32_t rel = (int32_t)(fv[a] - bc[a]);
-                const uint32_t mag = rel < 0 ? (uint32_t)(-(int64_t)rel) : (uint32_t)rel;
-                const float gf = (float)(mag > bh[a] ? mag - bh[a] : 0u);
-                g2 += gf * gf;
-            }
-            keep[u] = src_idx[u] >= 0 && g2 < thr_stage;
+            const uint32_t sxy = (f[u].x >> 16) | (f[u].y & 0xffff0000u);
+            const uint32_t g2 = gap2_16(f[u].z >> 16, bc[2], hh[2], gap2_16(sxy, cxy, hxy, 0u));
+            keep[u] = src_idx[u] >= 0 && g2 < thr_stage16;
         }
         // block compaction in candidate order (u, thread)
         unsigned long long m[SP];
@@ -1516,7 +1554,7 @@ __device__ void nuclear_item_compact_t(const typename P::Src* __restrict__ stg,
             P::fold(acc, part);
         };
         stage_neighbourhood<P, T>(
-            stg, k, L, k.thr_stage,
+            stg, k, L, k.thr_stage16,
             [&](int pos, const Lds& e, const uint3& f, int) {
                 src[pos] = P::tile_entry(e);
                 tst[pos] = make_uint2((f.x >> 16) | (f.y & 0xffff0000u), f.z);
