@@ -260,6 +260,9 @@ struct Fp64Policy {
     }
     static constexpr int CTILE = 512;  // sources per tile in the compacting kernel
     static constexpr int DRAIN_U = 2;  // listed pairs per drain round
+    // targets per lane of the off-diagonal pairwise Coulomb items (four
+    // would take the kernel past 128 VGPRs)
+    static constexpr int COUL_NT = 2;
     static constexpr int STAGE_PER_THREAD = 1;  // candidates per thread per staging round
 };
 
@@ -402,6 +405,8 @@ struct MixedPolicy {
     static constexpr int CTILE = 512;
     static constexpr int DRAIN_U = 4;
     static constexpr int STAGE_PER_THREAD = 2;
+    // targets per lane of the off-diagonal pairwise Coulomb items
+    static constexpr int COUL_NT = 4;
 };
 
 // LDS bytes a work item needs (the caller provides at least this much,
@@ -600,58 +605,62 @@ __host__ __device__ inline void coulomb_pair_ab(int item, int S, int* A_out, int
     *B_out = A + r;
 }
 
-// Off-diagonal item (A < B) whose eight blocks are all full: two targets
-// per lane.  Wave w holds target blocks I1 = 4A + 2(w & 1) and I1 + 1 (one
-// target of each per lane) and meets source blocks J = 4B + 2(w >> 1) and
-// J + 1, one after the other; each source and its reaction accumulator meet
-// both of the lane's targets before they move, so one set of row rotations
-// serves two pairs.  Every target block is covered by two wavefronts (w and
-// w ^ 2) and every source block by two (w and w ^ 1); their FP32 sums meet
-// in LDS and are added in FP64 in wavefront order.  The pairs evaluated and
-// the partials written are those of the one-target schedule.
-template <class P, bool E, class PT>
-__device__ void coulomb_pair_item_2t(const typename P::Src* __restrict__ stg, int Z,
+// Off-diagonal item (A < B) whose eight blocks are all full: NT targets per
+// lane (NT = 2 or 4).  The four target blocks of A form 4 / NT groups of NT
+// blocks; wave w holds group w % (4 / NT) (one target of each of its blocks
+// per lane) and meets its share of B's source blocks, 4 / NT of them, one
+// after the other.  Each source and its reaction accumulator meet all of the
+// lane's targets before they move, so one set of row rotations serves NT
+// pairs.  A target block is covered by NT wavefronts, a source block by
+// 4 / NT; where a block has more than one, their FP32 sums meet in LDS and
+// are added in FP64 in wavefront order.  The pairs evaluated and the
+// partials written are those of the one-target schedule.
+template <class P, bool E, class PT, int NT = P::COUL_NT>
+__device__ void coulomb_pair_item_mt(const typename P::Src* __restrict__ stg, int Z,
                                      const CoulConsts& k, PT* __restrict__ part, int A, int Bs,
                                      char* lds)
 {
+    static_assert(NT == 2 || NT == 4, "two or four targets per lane");
+    constexpr int TG = CP_SUPER / NT;   // target groups = source blocks per wave
     using Src = typename P::Src;
     using CA = typename P::CAcc;
-    // [wave][2 target blocks][lane][4], then [wave][2 source blocks][lane][4]
+    // [wave][NT target blocks][lane][4], then (TG > 1) [wave][TG source blocks][lane][4]
     CA* acc_t = reinterpret_cast<CA*>(lds);
-    CA* acc_s = acc_t + CP_SUPER * 2 * 64 * 4;
+    CA* acc_s = acc_t + CP_SUPER * NT * 64 * 4;
     const int tid = threadIdx.x, w = tid >> 6, lane = tid & 63;
-    const int I1 = CP_SUPER * A + 2 * (w & 1), J1 = CP_SUPER * Bs + 2 * (w >> 1);
-    const Src me1 = stg[I1 * 64 + lane], me2 = stg[I1 * 64 + 64 + lane];
-    CA t1x = 0, t1y = 0, t1z = 0, t1e = 0, t2x = 0, t2y = 0, t2z = 0, t2e = 0;
+    const int I0 = CP_SUPER * A + NT * (w % TG), J0 = CP_SUPER * Bs + TG * (w / TG);
+    Src me[NT];
+    CA tx[NT], ty[NT], tz[NT], te[NT];
+#pragma unroll
+    for (int i = 0; i < NT; ++i) {
+        me[i] = stg[(I0 + i) * 64 + lane];
+        tx[i] = ty[i] = tz[i] = te[i] = CA(0);
+    }
+    const double fsc = P::coul_fscale(k), vsc = P::coul_vscale(k);
 #pragma unroll 1
-    for (int jj = 0; jj < 2; ++jj) {
-        Src src = stg[(J1 + jj) * 64 + lane];
+    for (int jj = 0; jj < TG; ++jj) {
+        Src src = stg[(J0 + jj) * 64 + lane];
         CA sx = 0, sy = 0, sz = 0, se = 0;
 #pragma unroll 1
         for (int rho = 0; rho < 4; ++rho) {
+            // a short loop body: the fused kernel's item code shares the
+            // instruction cache
+#pragma unroll 8 / NT
             for (int c = 0; c < 16; ++c) {
-                CA dx, dy, dz, fs, wv;
-                P::coul_pair(me1, src, k, dx, dy, dz, fs, wv);
-                t1x += fs * dx;
-                t1y += fs * dy;
-                t1z += fs * dz;
-                sx -= fs * dx;
-                sy -= fs * dy;
-                sz -= fs * dz;
-                if (E) {
-                    t1e += wv;
-                    se += wv;
-                }
-                P::coul_pair(me2, src, k, dx, dy, dz, fs, wv);
-                t2x += fs * dx;
-                t2y += fs * dy;
-                t2z += fs * dz;
-                sx -= fs * dx;
-                sy -= fs * dy;
-                sz -= fs * dz;
-                if (E) {
-                    t2e += wv;
-                    se += wv;
+#pragma unroll
+                for (int i = 0; i < NT; ++i) {
+                    CA dx, dy, dz, fs, wv;
+                    P::coul_pair(me[i], src, k, dx, dy, dz, fs, wv);
+                    tx[i] += fs * dx;
+                    ty[i] += fs * dy;
+                    tz[i] += fs * dz;
+                    sx -= fs * dx;
+                    sy -= fs * dy;
+                    sz -= fs * dz;
+                    if (E) {
+                        te[i] += wv;
+                        se += wv;
+                    }
                 }
                 src = move_src(src, [](auto v) { return row_rotate(v); });
                 sx = row_rotate(sx);
@@ -667,47 +676,55 @@ __device__ void coulomb_pair_item_2t(const typename P::Src* __restrict__ stg, in
             if (E)
                 se = row_shift(se);
         }
-        CA* a = acc_s + ((w * 2 + jj) * 64 + lane) * 4;
-        a[0] = sx;
-        a[1] = sy;
-        a[2] = sz;
-        a[3] = se;
+        if (TG == 1) {
+            // this wave alone covers the source block: its partial from A
+            const int p = (J0 + jj) * 64 + lane;
+            store_part(&part[(int64_t)A * Z + p], (double)sx * fsc, (double)sy * fsc,
+                       (double)sz * fsc, (double)se * vsc);
+        } else {
+            CA* a = acc_s + ((w * TG + jj) * 64 + lane) * 4;
+            a[0] = sx;
+            a[1] = sy;
+            a[2] = sz;
+            a[3] = se;
+        }
     }
-    {
-        CA* a = acc_t + ((w * 2 + 0) * 64 + lane) * 4;
-        a[0] = t1x;
-        a[1] = t1y;
-        a[2] = t1z;
-        a[3] = t1e;
-        a += 64 * 4;
-        a[0] = t2x;
-        a[1] = t2y;
-        a[2] = t2z;
-        a[3] = t2e;
+#pragma unroll
+    for (int i = 0; i < NT; ++i) {
+        CA* a = acc_t + ((w * NT + i) * 64 + lane) * 4;
+        a[0] = tx[i];
+        a[1] = ty[i];
+        a[2] = tz[i];
+        a[3] = te[i];
     }
     __syncthreads();
-    // wavefront b writes block b of A (targets; its partial from B) and
-    // block b of B (sources; its partial from A)
-    const double fsc = P::coul_fscale(k), vsc = P::coul_vscale(k);
+    // wavefront b writes block b of A (targets; its partial from B) and, when
+    // a source block has several wavefronts, block b of B (its partial from A)
     {
-        const int b = w;
-        const int w0 = b >> 1, slot = b & 1;  // waves w0 and w0 + 2 hold target block b
-        const CA* a0 = acc_t + ((w0 * 2 + slot) * 64 + lane) * 4;
-        const CA* a1 = acc_t + (((w0 + 2) * 2 + slot) * 64 + lane) * 4;
+        const int b = w, g = b / NT, slot = b % NT;  // waves g + TG m hold target block b
+        double fx = 0, fy = 0, fz = 0, fe = 0;
+        for (int m = 0; m < NT; ++m) {
+            const CA* a = acc_t + (((g + TG * m) * NT + slot) * 64 + lane) * 4;
+            fx += (double)a[0];
+            fy += (double)a[1];
+            fz += (double)a[2];
+            fe += (double)a[3];
+        }
         const int t = (CP_SUPER * A + b) * 64 + lane;
-        store_part(&part[(int64_t)Bs * Z + t], ((double)a0[0] + (double)a1[0]) * fsc,
-                   ((double)a0[1] + (double)a1[1]) * fsc, ((double)a0[2] + (double)a1[2]) * fsc,
-                   ((double)a0[3] + (double)a1[3]) * vsc);
+        store_part(&part[(int64_t)Bs * Z + t], fx * fsc, fy * fsc, fz * fsc, fe * vsc);
     }
-    {
-        const int b = w;
-        const int w0 = 2 * (b >> 1), slot = b & 1;  // waves w0 and w0 + 1 hold source block b
-        const CA* a0 = acc_s + ((w0 * 2 + slot) * 64 + lane) * 4;
-        const CA* a1 = acc_s + (((w0 + 1) * 2 + slot) * 64 + lane) * 4;
+    if (TG > 1) {
+        const int b = w, s0 = (b / TG) * TG, slot = b % TG;  // waves s0 .. s0 + TG - 1
+        double fx = 0, fy = 0, fz = 0, fe = 0;
+        for (int i = 0; i < TG; ++i) {
+            const CA* a = acc_s + (((s0 + i) * TG + slot) * 64 + lane) * 4;
+            fx += (double)a[0];
+            fy += (double)a[1];
+            fz += (double)a[2];
+            fe += (double)a[3];
+        }
         const int p = (CP_SUPER * Bs + b) * 64 + lane;
-        store_part(&part[(int64_t)A * Z + p], ((double)a0[0] + (double)a1[0]) * fsc,
-                   ((double)a0[1] + (double)a1[1]) * fsc, ((double)a0[2] + (double)a1[2]) * fsc,
-                   ((double)a0[3] + (double)a1[3]) * vsc);
+        store_part(&part[(int64_t)A * Z + p], fx * fsc, fy * fsc, fz * fsc, fe * vsc);
     }
     __syncthreads();
 }
@@ -724,7 +741,7 @@ __device__ void coulomb_pair_item(const typename P::Src* __restrict__ stg, int Z
     int A, Bs;
     coulomb_pair_ab(item, S, &A, &Bs);
     if (A != Bs && CP_SUPER * Bs + CP_SUPER <= Z / 64) {  // A < B, every block full
-        coulomb_pair_item_2t<P, E, PT>(stg, Z, k, part, A, Bs, lds);
+        coulomb_pair_item_mt<P, E, PT>(stg, Z, k, part, A, Bs, lds);
         return;
     }
     const int tid = threadIdx.x, w = tid >> 6, lane = tid & 63;
