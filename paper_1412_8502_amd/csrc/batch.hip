@@ -12,7 +12,8 @@
 //   P5 forces     one dynamic work queue holding every system's Coulomb tiles
 //                 and nuclear cell tiles (uneven systems balance on it)
 //   P6 combine    nuclear + Coulomb partials, second half kick, kinetic energy
-//   P7 thermostat one workgroup per system on rescale steps
+//   P7 thermostat one workgroup per system on rescale steps (multi-kernel
+//                 form: the combine's last workgroup, every system)
 // The same phase functions also run as one kernel per phase ("multi-kernel"
 // form) for comparison.  Barrier waits are bounded: a grid that is not fully
 // resident sets an error bit and every workgroup leaves.
@@ -75,7 +76,8 @@ struct BatchDev {
     double* pending;      // per-system velocity scale pending from the thermostat
     int64_t* step;
     unsigned* barrier;    // BAR_WORDS words: generation, root count, group counts
-    unsigned* queue;      // [0] force-phase work counter
+    unsigned* queue;      // QUEUE_WORDS words: [0] force-phase work counter, then the
+                          // combine's arrival counters (root, groups; multi-kernel form)
     uint32_t* err;
     unsigned long long* pairs;  // [nsys] diagnostic nuclear pair counts
     double* red;          // [256] host-read reduction partials
@@ -140,6 +142,7 @@ __device__ __forceinline__ Grid grid_at(double L, double r_cut)
 constexpr int BAR_GROUPS = 32;
 constexpr int BAR_STRIDE = 64;  // words between counters (256 bytes)
 constexpr int BAR_WORDS = (2 + BAR_GROUPS) * BAR_STRIDE;
+constexpr int QUEUE_WORDS = (2 + BAR_GROUPS) * BAR_STRIDE;
 __device__ bool grid_sync(const BatchDev& B, int* s_flag)
 {
     __syncthreads();
@@ -514,13 +517,23 @@ __device__ void phase_combine(const BatchDev& B, int mode, bool energy, char* ld
             const double4 fn = B.fnuc[S.off + sl];
             double Fx = fn.x, Fy = fn.y, Fz = fn.z, V = fn.w;
             if (sl < S.Z) {
+                // partials in order k = 0, 1, ..., loaded eight at a time so
+                // that the loads are in flight together
+                constexpr int U = 8;
+                const PT* pp = part + S.coul_off + sl;
                 double cx = 0.0, cy = 0.0, cz = 0.0, cw = 0.0;
-                for (int k = 0; k < S.S; ++k) {
-                    const PT cp = part[S.coul_off + (int64_t)k * S.Z + sl];
-                    cx += (double)cp.x;
-                    cy += (double)cp.y;
-                    cz += (double)cp.z;
-                    cw += (double)cp.w;
+                for (int k0 = 0; k0 < S.S; k0 += U) {
+                    PT cp[U];
+#pragma unroll
+                    for (int u = 0; u < U; ++u)
+                        cp[u] = k0 + u < S.S ? pp[(int64_t)(k0 + u) * S.Z] : PT{};
+#pragma unroll
+                    for (int u = 0; u < U; ++u) {
+                        cx += (double)cp[u].x;
+                        cy += (double)cp[u].y;
+                        cz += (double)cp[u].z;
+                        cw += (double)cp[u].w;
+                    }
                 }
                 Fx += cx;
                 Fy += cy;
@@ -557,14 +570,20 @@ __device__ void phase_combine(const BatchDev& B, int mode, bool energy, char* ld
     }
 }
 
-__device__ void phase_thermostat(const BatchDev& B, int64_t step, int mode, char* lds_raw)
+// Whether system S rescales its velocities at the end of step `step`.
+__device__ __forceinline__ bool rescales_at(const SysDev& S, int64_t step, int mode)
+{
+    return mode && S.rescale_every > 0 && (step + 1) % S.rescale_every == 0;
+}
+
+// Systems first, first + stride, ... (one workgroup each).
+__device__ void phase_thermostat(const BatchDev& B, int64_t step, int mode, char* lds_raw,
+                                 int first, int stride)
 {
     double* red = reinterpret_cast<double*>(lds_raw);
-    for (int s = blockIdx.x; s < B.nsys; s += gridDim.x) {
+    for (int s = first; s < B.nsys; s += stride) {
         const SysDev& S = B.sys[s];
-        const bool thermo =
-            mode && S.rescale_every > 0 && (step + 1) % S.rescale_every == 0;
-        if (!thermo) {
+        if (!rescales_at(S, step, mode)) {
             if (threadIdx.x == 0)
                 B.pending[s] = 1.0;
             continue;
@@ -635,7 +654,7 @@ void k_batch_step(BatchDev B, int mode)
     if (thermo) {
         if (!grid_sync(B, &s_flag))
             return;
-        phase_thermostat(B, step, mode, lds);
+        phase_thermostat(B, step, mode, lds, blockIdx.x, gridDim.x);
     }
     if (mode && blockIdx.x == 0 && threadIdx.x == 0)
         *B.step = step + 1;
@@ -658,11 +677,18 @@ __global__ __launch_bounds__(BW) void k_ph_rank(BatchDev B, int mode)
 {
     phase_rank<P>(B, *B.step, mode);
 }
+// Waves per SIMD the force phase is compiled for.  Without a bound the
+// compiler takes up to 138 VGPRs for the compacting items (three waves).
+// Five keeps it within 96 VGPRs without spills; six (80 VGPRs) spills a few
+// registers but ran the mixed-precision variant-3 steps 4 % faster on the
+// 15-system grid, while it slowed variant 1, which stays at five.
 template <class P, int M, int V>
-// At least five waves per SIMD: the compiler keeps the force phase within 96
-// VGPRs (without the bound it takes up to 138 for the compacting items, and
-// the phase runs with three).
-__global__ __launch_bounds__(BW) __attribute__((amdgpu_waves_per_eu(5))) void k_ph_forces(BatchDev B, int mode)
+constexpr int ph_force_waves()
+{
+    return (std::is_same<P, MixedPolicy>::value && M == MODE_FORCE && V == 3) ? 6 : 5;
+}
+template <class P, int M, int V>
+__global__ __launch_bounds__(BW) __attribute__((amdgpu_waves_per_eu(ph_force_waves<P, M, V>()))) void k_ph_forces(BatchDev B, int mode)
 {
     __shared__ __align__(16) char lds[batch_lds<P, V>()];
     __shared__ int s_item;
@@ -692,21 +718,71 @@ void launch_pair_phase(const BatchDev& dev, int precision, unsigned g, hipStream
             k_ph_forces<MixedPolicy, M, V><<<g, BW, 0, s>>>(dev, 0);
     });
 }
-template <class P>
-__global__ __launch_bounds__(BW) void k_ph_combine(BatchDev B, int mode, int energy)
+// Two-level arrival count (thread 0 of each workgroup; no waiting): workgroup
+// b arrives on the counter of group b mod BAR_GROUPS, the last member of a
+// group on the root.  True in the one workgroup that arrives last.  Every
+// counter is back at zero afterwards.  With `ordered`, each arrival is a
+// release and the last one an acquire at agent scope, so the last workgroup
+// sees every workgroup's earlier writes.
+__device__ bool last_arrival(unsigned* ctr, bool ordered)
 {
-    __shared__ __align__(16) char lds[64];
-    phase_combine<P>(B, mode, energy != 0, lds);
+    const unsigned nb = gridDim.x;
+    const unsigned grp = blockIdx.x % BAR_GROUPS;
+    const unsigned ngrp = nb < BAR_GROUPS ? nb : BAR_GROUPS;
+    const unsigned gsize = nb / BAR_GROUPS + (grp < nb % BAR_GROUPS ? 1u : 0u);
+    unsigned* grp_w = ctr + (2 + grp) * BAR_STRIDE;
+    unsigned* root_w = ctr + BAR_STRIDE;
+    if (ordered)
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
+    if (__hip_atomic_fetch_add(grp_w, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) + 1u != gsize)
+        return false;
+    __hip_atomic_store(grp_w, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    if (ordered)
+        __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "agent");
+    if (__hip_atomic_fetch_add(root_w, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) + 1u != ngrp)
+        return false;
+    __hip_atomic_store(root_w, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    if (ordered)
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+    return true;
 }
-__global__ __launch_bounds__(BW) void k_ph_thermostat(BatchDev B, int mode)
+
+// The combine phase.  With `tail`, the last workgroup to finish then runs
+// the thermostat phase for every system and, in a step, advances the step
+// counter, so a step needs no launches after the combine.  Every workgroup
+// reads the step counter before it arrives, so the last one may advance it.
+// Only on a step where some system rescales does the last workgroup read the
+// others' kinetic-energy partials, and only then are the arrivals ordered by
+// agent-scope fences: on this multi-XCD GPU those write back and invalidate
+// L2, which costs tens of microseconds per launch when every workgroup
+// issues them.
+template <class P>
+__global__ __launch_bounds__(BW) void k_ph_combine(BatchDev B, int mode, int energy, int tail)
 {
     __shared__ __align__(16) char lds[BW * 8];
-    phase_thermostat(B, *B.step, mode, lds);
-}
-__global__ void k_ph_advance(BatchDev B)
-{
+    __shared__ int s_last, s_rescale;
+    __shared__ int64_t s_step;
+    if (tail && threadIdx.x == 0) {
+        const int64_t step = *B.step;
+        bool any = false;
+        for (int s = 0; s < B.nsys; ++s)
+            any |= rescales_at(B.sys[s], step, mode);
+        s_step = step;
+        s_rescale = any;
+    }
+    phase_combine<P>(B, mode, energy != 0, lds);
+    if (!tail)
+        return;
+    __syncthreads();
     if (threadIdx.x == 0)
-        *B.step += 1;
+        s_last = last_arrival(B.queue, s_rescale != 0);
+    __syncthreads();
+    if (!s_last)
+        return;
+    const int64_t step = s_step;
+    phase_thermostat(B, step, mode, lds, 0, 1);
+    if (mode && threadIdx.x == 0)
+        *B.step = step + 1;
 }
 
 // Apply the pending thermostat scale to the velocities (end of a step call).
@@ -747,10 +823,10 @@ __global__ void k_batch_init_scalars(BatchDev B, int64_t step0)
         B.barrier[k] = 0u;
     if (threadIdx.x == 0) {
         *B.step = step0;
-        B.queue[0] = 0u;
-        B.queue[1] = 0u;
         *B.err = 0u;
     }
+    for (int k = threadIdx.x; k < QUEUE_WORDS; k += blockDim.x)
+        B.queue[k] = 0u;
     if (threadIdx.x < (unsigned)B.nsys) {
         B.pending[threadIdx.x] = 1.0;
         B.pairs[threadIdx.x] = 0ull;
@@ -761,10 +837,8 @@ __global__ void k_batch_zero_pairs(BatchDev B)
 {
     if (threadIdx.x < (unsigned)B.nsys)
         B.pairs[threadIdx.x] = 0ull;
-    if (threadIdx.x == 0) {
-        B.queue[0] = 0u;
-        B.queue[1] = 0u;
-    }
+    for (int k = threadIdx.x; k < QUEUE_WORDS; k += blockDim.x)
+        B.queue[k] = 0u;
 }
 
 __global__ __launch_bounds__(BW) void k_batch_partial(const double* x, int64_t n, int kind,
@@ -943,7 +1017,7 @@ size_t batch_carve(Carver& cv, const BatchLayout& lay, int nsys, int precision, 
     b.pending = cv.take<double>(nsys);
     b.step = cv.take<int64_t>(1);
     b.barrier = cv.take<unsigned>(BAR_WORDS);
-    b.queue = cv.take<unsigned>(2);
+    b.queue = cv.take<unsigned>(QUEUE_WORDS);
     b.err = cv.take<uint32_t>(1);
     b.pairs = cv.take<unsigned long long>(nsys);
     b.red = cv.take<double>(256);
@@ -953,6 +1027,14 @@ size_t batch_carve(Carver& cv, const BatchLayout& lay, int nsys, int precision, 
     if (d)
         *d = b;
     return cv.size();
+}
+
+// Grid of the kernels that walk the 256-particle chunks: one workgroup per
+// chunk, at most the multi-kernel grid.
+static unsigned chunk_grid(const pasta_batch* bt)
+{
+    const int64_t c = bt->dev.total_chunks;
+    return (unsigned)(c < (int64_t)bt->phase_grid ? (c > 0 ? c : 1) : bt->phase_grid);
 }
 
 // Steps (mode 1) accumulate forces only; the initial evaluation (mode 0)
@@ -970,11 +1052,11 @@ int launch_step(pasta_batch* bt, int mode)
                 k_batch_step<P, MODE_ENERGY, V><<<bt->grid, BW, 0, s>>>(bt->dev, mode);
         });
     } else {
-        const unsigned g = bt->phase_grid;
-        k_ph_drift<P><<<g, BW, 0, s>>>(bt->dev, mode);
+        const unsigned g = bt->phase_grid, gc = chunk_grid(bt);
+        k_ph_drift<P><<<gc, BW, 0, s>>>(bt->dev, mode);
         k_ph_scan<<<(unsigned)bt->nsys, BW, 0, s>>>(bt->dev, mode);
-        k_ph_scatter<<<g, BW, 0, s>>>(bt->dev, mode);
-        k_ph_rank<P><<<g, BW, 0, s>>>(bt->dev, mode);
+        k_ph_scatter<<<gc, BW, 0, s>>>(bt->dev, mode);
+        k_ph_rank<P><<<gc, BW, 0, s>>>(bt->dev, mode);
         with_batch_variant(bt->dev.nuc_variant, [&](auto vt) {
             constexpr int V = decltype(vt)::value;
             if (mode)
@@ -982,10 +1064,8 @@ int launch_step(pasta_batch* bt, int mode)
             else
                 k_ph_forces<P, MODE_ENERGY, V><<<g, BW, 0, s>>>(bt->dev, mode);
         });
-        k_ph_combine<P><<<g, BW, 0, s>>>(bt->dev, mode, mode ? 0 : 1);
-        k_ph_thermostat<<<(unsigned)bt->nsys, BW, 0, s>>>(bt->dev, mode);
-        if (mode)
-            k_ph_advance<<<1, 64, 0, s>>>(bt->dev);
+        // the combine's last workgroup also runs the thermostat and the advance
+        k_ph_combine<P><<<gc, BW, 0, s>>>(bt->dev, mode, mode ? 0 : 1, 1);
     }
     PASTA_HIP(hipGetLastError());
     return PASTA_OK;
@@ -1279,12 +1359,12 @@ static int batch_refresh_energies(pasta_batch* bt)
         return PASTA_OK;
     hipStream_t s = bt->stream;
     k_batch_zero_pairs<<<1, 1024, 0, s>>>(bt->dev);
-    const unsigned g = bt->phase_grid;
+    const unsigned g = bt->phase_grid, gc = chunk_grid(bt);
     launch_pair_phase<MODE_ENERGY>(bt->dev, bt->precision, g, s);
     if (bt->precision == PASTA_FP64)
-        k_ph_combine<Fp64Policy><<<g, BW, 0, s>>>(bt->dev, 0, 1);
+        k_ph_combine<Fp64Policy><<<gc, BW, 0, s>>>(bt->dev, 0, 1, 0);
     else
-        k_ph_combine<MixedPolicy><<<g, BW, 0, s>>>(bt->dev, 0, 1);
+        k_ph_combine<MixedPolicy><<<gc, BW, 0, s>>>(bt->dev, 0, 1, 0);
     PASTA_HIP(hipGetLastError());
     bt->epot_valid = true;
     return PASTA_OK;
