@@ -352,8 +352,10 @@ int pasta_cluster(int64_t n, double L, const double* d_pos, const uint8_t* d_spe
  * mode 1: the same phases as one kernel launch each.
  * Steps are captured once into a hipGraph of steps_per_graph steps and
  * replayed; the batch works on an internal stream joined to `stream` by
- * events.  d_pos and d_vel hold the state of every system after each
- * pasta_batch_step call (stream-ordered).  h_L_max[s] bounds system s's box. */
+ * events.  The batch keeps the state in its workspace, in the sorted order of
+ * its cell lists: d_pos and d_vel are read at creation and hold the state of
+ * every system after each pasta_batch_step call (stream-ordered); writes to
+ * them between calls are not seen.  h_L_max[s] bounds system s's box. */
 typedef struct pasta_batch pasta_batch;
 int pasta_batch_workspace(const pasta_potential* pot, int32_t precision, int32_t nsys,
                           const int64_t* h_n, const double* h_L_max, size_t* h_bytes);

@@ -54,16 +54,27 @@ struct BatchDev {
     int64_t total_chunks, coul_items, nuc_items;
     PairParams pp;        // L filled per system per step
     double mass;
-    // concatenated particle arrays (caller order within each system)
-    double* pos;
-    double* vel;
+    // the caller's concatenated particle arrays (caller order within each
+    // system): read at creation, written after every step call
+    double* cpos;
+    double* cvel;
     const uint8_t* species;
-    double* force;
-    double* epot;
+    // the state, kept in the sorted order of the last cell build: slot k of
+    // system s holds the particle ids[k] (caller index within the system)
+    double* pos;          // [3N]
+    double* vel;          // [3N]
+    double* force;        // [3N] F of the state's positions
+    double* epot;         // [N] energy shares (when evaluated)
+    int32_t* ids;
+    // the rank phase's copy of the state in the new order (the combine
+    // updates it into pos/vel/ids)
+    double* pos_t;
+    double* vel_t;
+    int32_t* perm;        // new slot -> caller index
     // work arrays
-    int32_t* key;
-    int32_t* tmp;
-    int32_t* perm;
+    int32_t* key;         // bin of each slot's next position
+    int32_t* tmp;         // scatter: new slot -> caller index (the rank key)
+    int32_t* srcix;       // scatter: new slot -> current slot (where the data is)
     int32_t* count;
     int32_t* fill;
     int32_t* start;
@@ -212,7 +223,46 @@ __device__ bool grid_sync(const BatchDev& B, int* s_flag)
 // ------------------------------------------------------------- phases
 // mode: 0 = initial evaluation (bin the given positions, no kick),
 //       1 = a full step.
-__device__ void phase_drift(const BatchDev& B, int64_t step, int mode)
+// A step's first part (half kick, drift, binning) normally runs at the end
+// of the previous step's combine, over the same sorted slots; the drift
+// phase runs it only for the first step of a launch sequence (`first`) and
+// for systems whose thermostat rescaled the velocities at the end of the
+// previous step (the factor is known only after that step's reduction).
+
+// Whether system S's drift for step `step` is left to the drift phase.
+__device__ __forceinline__ bool drift_in_phase(const SysDev& S, int64_t step, int first)
+{
+    return first || (S.rescale_every > 0 && step % S.rescale_every == 0);
+}
+
+// One slot's first part of step `step` (positions move to step + 1): the
+// pending velocity scale sc (1 when none), then the half kick with F and
+// the drift (the single-system path's drift_update), and the bin of the new
+// position.  Updates x and v; returns the bin.
+__device__ __forceinline__ int drift_slot(const BatchDev& B, const SysDev& S, int64_t step,
+                                          double sc, double (&x)[3], double (&v)[3],
+                                          const double (&f)[3], bool proton)
+{
+    const double L_old = box_at(S, step), L_new = box_at(S, step + 1);
+    const Grid gr = grid_at(L_new, B.pp.r_nuc);
+    if (sc != 1.0) {
+        v[0] *= sc;
+        v[1] *= sc;
+        v[2] *= sc;
+    }
+    DriftStep c;
+    c.hdtm = S.hdtm;
+    c.dt = S.dt;
+    c.L_new = L_new;
+    c.ratio = L_new / L_old;
+    c.scale_positions = S.scale_positions;
+    const uint32_t bad = drift_update(x, v, f, c);
+    if (bad)
+        atomicOr(B.err, bad);
+    return particle_bin(x[0], x[1], x[2], proton, gr.inv_w, gr.nc, gr.C, gr.sub);
+}
+
+__device__ void phase_drift(const BatchDev& B, int64_t step, int mode, int first)
 {
     if (blockIdx.x == 0 && threadIdx.x == 0)
         B.queue[0] = 0u;  // work counter of this step's force phase
@@ -231,54 +281,35 @@ __device__ void phase_drift(const BatchDev& B, int64_t step, int mode)
     for (int64_t g = blockIdx.x; g < B.total_chunks; g += gridDim.x) {
         const int s = find_sys_chunk(B, g);
         const SysDev& S = B.sys[s];
+        if (mode && !drift_in_phase(S, step, first))
+            continue;  // the previous combine drifted this system
         const int64_t sl = (g - S.chunk_off) * BW + threadIdx.x;
         if (sl >= S.n)
             continue;
-        const double L_old = box_at(S, step);
-        const double L_new = mode ? box_at(S, step + 1) : L_old;
-        const Grid gr = grid_at(L_new, B.pp.r_nuc);
-        const int64_t i = S.off + (mode ? B.perm[S.off + sl] : sl);
-        double* x = B.pos + 3 * i;
-        double* v = B.vel + 3 * i;
-        double xn[3];
+        const int64_t k = S.off + sl;
+        const bool proton = B.species[S.off + B.ids[k]] == 1;
+        double x[3] = {B.pos[3 * k], B.pos[3 * k + 1], B.pos[3 * k + 2]};
+        int bin;
         if (mode) {
-            // the thermostat of the previous step (if any) left its factor
-            const double sc = (S.rescale_every > 0 && step % S.rescale_every == 0)
-                                  ? B.pending[s] : 1.0;
-            const double ratio = L_new / L_old;
-            uint32_t bad = 0;
+            double v[3] = {B.vel[3 * k], B.vel[3 * k + 1], B.vel[3 * k + 2]};
+            const double f[3] = {B.force[3 * k], B.force[3 * k + 1], B.force[3 * k + 2]};
+            // a thermostat at the end of the previous step left its factor
+            const double sc =
+                (S.rescale_every > 0 && step % S.rescale_every == 0) ? B.pending[s] : 1.0;
+            bin = drift_slot(B, S, step, sc, x, v, f, proton);
 #pragma unroll
             for (int d = 0; d < 3; ++d) {
-                double vv = v[d] * sc + S.hdtm * B.force[3 * i + d];
-                double xx = x[d] + S.dt * vv;
-                if (S.scale_positions)
-                    xx *= ratio;
-                if (xx < 0.0)
-                    xx += L_new;
-                if (xx >= L_new)
-                    xx -= L_new;
-                if (!(xx >= 0.0 && xx < L_new)) {
-                    bad |= isfinite(xx) ? ERR_WRAP : ERR_NONFINITE_POS;
-                    xx = 0.0;
-                }
-                v[d] = vv;
-                x[d] = xx;
-                xn[d] = xx;
+                B.pos[3 * k + d] = x[d];
+                B.vel[3 * k + d] = v[d];
             }
-            if (bad)
-                atomicOr(B.err, bad);
         } else {
-#pragma unroll
-            for (int d = 0; d < 3; ++d) {
-                const double xx = x[d];
-                if (!(xx >= 0.0 && xx < L_new))
-                    atomicOr(B.err, ERR_RANGE);
-                xn[d] = xx;
-            }
+            const double L = box_at(S, step);
+            const Grid gr = grid_at(L, B.pp.r_nuc);
+            if (!(x[0] >= 0.0 && x[0] < L && x[1] >= 0.0 && x[1] < L && x[2] >= 0.0 && x[2] < L))
+                atomicOr(B.err, ERR_RANGE);
+            bin = particle_bin(x[0], x[1], x[2], proton, gr.inv_w, gr.nc, gr.C, gr.sub);
         }
-        const int bin = particle_bin(xn[0], xn[1], xn[2], B.species[i] == 1, gr.inv_w, gr.nc, gr.C,
-                                     gr.sub);
-        B.key[i] = bin;
+        B.key[k] = bin;
         wave_aggregated_add(B.count + S.bin_off, bin);
     }
 }
@@ -364,7 +395,10 @@ __device__ void phase_scan(const BatchDev& B, int64_t step, int mode, char* lds_
     }
 }
 
-__device__ void phase_scatter(const BatchDev& B, int mode)
+// The slots of each bin in the new order, visiting the current (sorted)
+// slots: tmp[new slot] = caller index, srcix[new slot] = current slot, in
+// an order the rank phase then makes stable.
+__device__ void phase_scatter(const BatchDev& B)
 {
     for (int64_t g = blockIdx.x; g < B.total_chunks; g += gridDim.x) {
         const int s = find_sys_chunk(B, g);
@@ -372,10 +406,10 @@ __device__ void phase_scatter(const BatchDev& B, int mode)
         const int64_t sl = (g - S.chunk_off) * BW + threadIdx.x;
         if (sl >= S.n)
             continue;
-        const int32_t il = mode ? B.perm[S.off + sl] : (int32_t)sl;
-        const int b = B.key[S.off + il];
+        const int b = B.key[S.off + sl];
         const int slot = B.start[S.start_off + b] + wave_aggregated_add(B.fill + S.bin_off, b);
-        B.tmp[S.off + slot] = il;
+        B.tmp[S.off + slot] = B.ids[S.off + sl];
+        B.srcix[S.off + slot] = (int32_t)sl;
     }
 }
 
@@ -390,8 +424,9 @@ __device__ void phase_rank(const BatchDev& B, int64_t step, int mode)
         if (sl >= S.n)
             continue;
         const int32_t* tmp = B.tmp + S.off;
-        const int32_t id = tmp[sl];
-        const int b = B.key[S.off + id];
+        const int32_t id = tmp[sl];               // caller index: the rank key
+        const int32_t src = B.srcix[S.off + sl];  // current slot: where its data is
+        const int b = B.key[S.off + src];
         const int beg = B.start[S.start_off + b], end = B.start[S.start_off + b + 1];
         int r = 0, k = beg;
         for (; k + 8 <= end; k += 8) {
@@ -405,10 +440,20 @@ __device__ void phase_rank(const BatchDev& B, int64_t step, int mode)
         }
         for (; k < end; ++k)
             r += tmp[k] < id;
+        // new slot: the bin's start plus the rank of the caller index among
+        // the bin's members, the single-system path's order
         const int dst = beg + r;
-        B.perm[S.off + dst] = id;
-        const int64_t i = S.off + id;
+        const int64_t i = S.off + src, o = S.off + dst;
+        B.perm[o] = id;
+        const uint8_t sp = B.species[S.off + id];
         const double x = B.pos[3 * i], y = B.pos[3 * i + 1], z = B.pos[3 * i + 2];
+        const double vx = B.vel[3 * i], vy = B.vel[3 * i + 1], vz = B.vel[3 * i + 2];
+        B.pos_t[3 * o] = x;
+        B.pos_t[3 * o + 1] = y;
+        B.pos_t[3 * o + 2] = z;
+        B.vel_t[3 * o] = vx;
+        B.vel_t[3 * o + 1] = vy;
+        B.vel_t[3 * o + 2] = vz;
         if constexpr (sizeof(typename P::Src) == sizeof(Q4)) {
             const double L = box_at(S, mode ? step + 1 : step);
             const double qs = 4294967296.0 / L;
@@ -416,10 +461,10 @@ __device__ void phase_rank(const BatchDev& B, int64_t step, int mode)
             q.x = (uint32_t)(uint64_t)(x * qs);
             q.y = (uint32_t)(uint64_t)(y * qs);
             q.z = (uint32_t)(uint64_t)(z * qs);
-            q.w = B.species[i];
-            reinterpret_cast<Q4*>(stg)[S.off + dst] = q;
+            q.w = sp;
+            reinterpret_cast<Q4*>(stg)[o] = q;
         } else {
-            reinterpret_cast<double4*>(stg)[S.off + dst] = make_double4(x, y, z, (double)B.species[i]);
+            reinterpret_cast<double4*>(stg)[o] = make_double4(x, y, z, (double)sp);
         }
     }
 }
@@ -494,6 +539,12 @@ __device__ void phase_forces(const BatchDev& B, int64_t step, int mode, char* ld
     }
 }
 
+// Whether system S rescales its velocities at the end of step `step`.
+__device__ __forceinline__ bool rescales_at(const SysDev& S, int64_t step, int mode)
+{
+    return mode && S.rescale_every > 0 && (step + 1) % S.rescale_every == 0;
+}
+
 // energy: the pair phase accumulated energies; write the shares.
 // The Coulomb partials of a proton are summed in partial order from zero
 // and the sum is added to the nuclear part, as in the single-system
@@ -502,8 +553,18 @@ __device__ void phase_forces(const BatchDev& B, int64_t step, int mode, char* ld
 // summed in FP64, which is exact unless their exponents span more than 29
 // bits, so the two orders give the same bits in practice (FP64 partials
 // can differ in the last bit).
+//
+// The combine walks the new slots: F (written per slot), and with `state`
+// the state moves from the rank phase's copy into pos/vel/ids, in a step
+// (mode 1) with the second half kick (the kinetic-energy partials are of
+// these velocities).  With `drift_next`, a system that does not rescale at
+// the end of this step then takes the first part of step + 1 here (half
+// kick with the same F, drift, bin); the velocities kept are then the
+// half-step ones, which the next combine completes.  Without `state`
+// (energies of the current state) only F and the energy shares are written.
 template <class P>
-__device__ void phase_combine(const BatchDev& B, int mode, bool energy, char* lds_raw)
+__device__ void phase_combine(const BatchDev& B, int64_t step, int mode, bool energy, bool state,
+                              bool drift_next, char* lds_raw)
 {
     using PT = typename P::CPart;
     const PT* part = static_cast<const PT*>(B.coul_part);
@@ -512,9 +573,11 @@ __device__ void phase_combine(const BatchDev& B, int mode, bool energy, char* ld
         const int s = find_sys_chunk(B, g);
         const SysDev& S = B.sys[s];
         const int64_t sl = (g - S.chunk_off) * BW + threadIdx.x;
+        const bool drift = state && drift_next && mode && !rescales_at(S, step, mode);
         double ke = 0.0;
         if (sl < S.n) {
-            const double4 fn = B.fnuc[S.off + sl];
+            const int64_t k = S.off + sl;
+            const double4 fn = B.fnuc[k];
             double Fx = fn.x, Fy = fn.y, Fz = fn.z, V = fn.w;
             if (sl < S.Z) {
                 // partials in order k = 0, 1, ..., loaded eight at a time so
@@ -540,22 +603,36 @@ __device__ void phase_combine(const BatchDev& B, int mode, bool energy, char* ld
                 Fz += cz;
                 V += cw;
             }
-            const int64_t i = S.off + B.perm[S.off + sl];
-            B.force[3 * i + 0] = Fx;
-            B.force[3 * i + 1] = Fy;
-            B.force[3 * i + 2] = Fz;
+            B.force[3 * k + 0] = Fx;
+            B.force[3 * k + 1] = Fy;
+            B.force[3 * k + 2] = Fz;
             if (energy)
-                B.epot[i] = 0.5 * V;
+                B.epot[k] = 0.5 * V;
             if (!(isfinite(Fx) && isfinite(Fy) && isfinite(Fz)))
                 atomicOr(B.err, ERR_NONFINITE_FORCE);
-            if (mode) {
-                double* v = B.vel + 3 * i;
-                const double vx = v[0] + S.hdtm * Fx, vy = v[1] + S.hdtm * Fy,
-                             vz = v[2] + S.hdtm * Fz;
-                v[0] = vx;
-                v[1] = vy;
-                v[2] = vz;
-                ke = 0.5 * B.mass * (vx * vx + vy * vy + vz * vz);
+            if (state) {
+                const int32_t cid = B.perm[k];
+                B.ids[k] = cid;
+                double x[3] = {B.pos_t[3 * k], B.pos_t[3 * k + 1], B.pos_t[3 * k + 2]};
+                double v[3] = {B.vel_t[3 * k], B.vel_t[3 * k + 1], B.vel_t[3 * k + 2]};
+                if (mode) {
+                    v[0] = v[0] + S.hdtm * Fx;
+                    v[1] = v[1] + S.hdtm * Fy;
+                    v[2] = v[2] + S.hdtm * Fz;
+                    ke = 0.5 * B.mass * (v[0] * v[0] + v[1] * v[1] + v[2] * v[2]);
+                }
+                if (drift) {
+                    const double f[3] = {Fx, Fy, Fz};
+                    const bool proton = B.species[S.off + cid] == 1;
+                    const int bin = drift_slot(B, S, step + 1, 1.0, x, v, f, proton);
+                    B.key[k] = bin;
+                    wave_aggregated_add(B.count + S.bin_off, bin);
+                }
+#pragma unroll
+                for (int d = 0; d < 3; ++d) {
+                    B.pos[3 * k + d] = x[d];
+                    B.vel[3 * k + d] = v[d];
+                }
             }
         }
         // fixed-order block reduction of the chunk's kinetic energy
@@ -568,12 +645,6 @@ __device__ void phase_combine(const BatchDev& B, int mode, bool energy, char* ld
             B.ke_chunk[g] = ((red[0] + red[1]) + red[2]) + red[3];
         __syncthreads();
     }
-}
-
-// Whether system S rescales its velocities at the end of step `step`.
-__device__ __forceinline__ bool rescales_at(const SysDev& S, int64_t step, int mode)
-{
-    return mode && S.rescale_every > 0 && (step + 1) % S.rescale_every == 0;
 }
 
 // Systems first, first + stride, ... (one workgroup each).
@@ -623,20 +694,25 @@ constexpr int persist_waves() { return std::is_same<P, MixedPolicy>::value ? 5 :
 
 template <class P, int M, int V>
 __global__ __launch_bounds__(BW) __attribute__((amdgpu_waves_per_eu(persist_waves<P>())))
-void k_batch_step(BatchDev B, int mode)
+void k_batch_step(BatchDev B, int mode, int first, int last)
 {
     __shared__ __align__(16) char lds[batch_lds<P, V>()];
     __shared__ int s_flag, s_item;
     if (__hip_atomic_load(B.err, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) & ERR_BARRIER)
         return;
     const int64_t step = *B.step;
-    phase_drift(B, step, mode);
-    if (!grid_sync(B, &s_flag))
+    phase_drift(B, step, mode, first);
+    // the barrier after the drift phase only when it moved particles (what
+    // else it writes is read after later barriers)
+    bool moved = !mode || first;
+    for (int s = 0; s < B.nsys && !moved; ++s)
+        moved = drift_in_phase(B.sys[s], step, first);
+    if (moved && !grid_sync(B, &s_flag))
         return;
     phase_scan(B, step, mode, lds);
     if (!grid_sync(B, &s_flag))
         return;
-    phase_scatter(B, mode);
+    phase_scatter(B);
     if (!grid_sync(B, &s_flag))
         return;
     phase_rank<P>(B, step, mode);
@@ -645,7 +721,7 @@ void k_batch_step(BatchDev B, int mode)
     phase_forces<P, M, V>(B, step, mode, lds, &s_item);
     if (!grid_sync(B, &s_flag))
         return;
-    phase_combine<P>(B, mode, M != MODE_FORCE, lds);
+    phase_combine<P>(B, step, mode, M != MODE_FORCE, true, !last, lds);
     // the thermostat (and the barrier before it) only in steps where some
     // system rescales; the next step's drift reads the factor only then
     bool thermo = false;
@@ -662,16 +738,16 @@ void k_batch_step(BatchDev B, int mode)
 
 // ---- the same phases as separate kernels (multi-kernel form) -----------
 template <class P>
-__global__ __launch_bounds__(BW) void k_ph_drift(BatchDev B, int mode)
+__global__ __launch_bounds__(BW) void k_ph_drift(BatchDev B, int mode, int first)
 {
-    phase_drift(B, *B.step, mode);
+    phase_drift(B, *B.step, mode, first);
 }
 __global__ __launch_bounds__(BW) void k_ph_scan(BatchDev B, int mode)
 {
     __shared__ __align__(16) char lds[BW * 8];
     phase_scan(B, *B.step, mode, lds);
 }
-__global__ __launch_bounds__(BW) void k_ph_scatter(BatchDev B, int mode) { phase_scatter(B, mode); }
+__global__ __launch_bounds__(BW) void k_ph_scatter(BatchDev B) { phase_scatter(B); }
 template <class P>
 __global__ __launch_bounds__(BW) void k_ph_rank(BatchDev B, int mode)
 {
@@ -757,12 +833,13 @@ __device__ bool last_arrival(unsigned* ctr, bool ordered)
 // L2, which costs tens of microseconds per launch when every workgroup
 // issues them.
 template <class P>
-__global__ __launch_bounds__(BW) void k_ph_combine(BatchDev B, int mode, int energy, int tail)
+__global__ __launch_bounds__(BW) void k_ph_combine(BatchDev B, int mode, int energy, int tail,
+                                                  int state, int drift_next)
 {
     __shared__ __align__(16) char lds[BW * 8];
     __shared__ int s_last, s_rescale;
     __shared__ int64_t s_step;
-    if (tail && threadIdx.x == 0) {
+    if (threadIdx.x == 0) {
         const int64_t step = *B.step;
         bool any = false;
         for (int s = 0; s < B.nsys; ++s)
@@ -770,7 +847,8 @@ __global__ __launch_bounds__(BW) void k_ph_combine(BatchDev B, int mode, int ene
         s_step = step;
         s_rescale = any;
     }
-    phase_combine<P>(B, mode, energy != 0, lds);
+    __syncthreads();
+    phase_combine<P>(B, s_step, mode, energy != 0, state != 0, drift_next != 0, lds);
     if (!tail)
         return;
     __syncthreads();
@@ -785,7 +863,8 @@ __global__ __launch_bounds__(BW) void k_ph_combine(BatchDev B, int mode, int ene
         *B.step = step + 1;
 }
 
-// Apply the pending thermostat scale to the velocities (end of a step call).
+// Apply the pending thermostat scale to the velocities (end of a step call;
+// the velocities are then full-step ones: the last step does not drift).
 __global__ __launch_bounds__(BW) void k_apply_pending(BatchDev B)
 {
     for (int64_t g = blockIdx.x; g < B.total_chunks; g += gridDim.x) {
@@ -807,6 +886,41 @@ __global__ void k_reset_pending(BatchDev B)
 {
     if (threadIdx.x < (unsigned)B.nsys)
         B.pending[threadIdx.x] = 1.0;
+}
+
+// The caller's state into the slots, in caller order (ids = identity).
+__global__ __launch_bounds__(BW) void k_batch_load(BatchDev B, int64_t n)
+{
+    for (int64_t k = (int64_t)blockIdx.x * BW + threadIdx.x; k < n; k += (int64_t)gridDim.x * BW) {
+#pragma unroll
+        for (int d = 0; d < 3; ++d) {
+            B.pos[3 * k + d] = B.cpos[3 * k + d];
+            B.vel[3 * k + d] = B.cvel[3 * k + d];
+        }
+    }
+    for (int s = 0; s < B.nsys; ++s) {
+        const SysDev& S = B.sys[s];
+        for (int64_t k = (int64_t)blockIdx.x * BW + threadIdx.x; k < S.n;
+             k += (int64_t)gridDim.x * BW)
+            B.ids[S.off + k] = (int32_t)k;
+    }
+}
+
+// Slot-ordered arrays of `width` doubles per particle back into caller
+// order: dst[ids[k]] = src[k] within each system.
+__global__ __launch_bounds__(BW) void k_batch_unsort(BatchDev B, const double* __restrict__ src,
+                                                     double* __restrict__ dst, int width)
+{
+    for (int64_t g = blockIdx.x; g < B.total_chunks; g += gridDim.x) {
+        const int s = find_sys_chunk(B, g);
+        const SysDev& S = B.sys[s];
+        const int64_t sl = (g - S.chunk_off) * BW + threadIdx.x;
+        if (sl >= S.n)
+            continue;
+        const int64_t k = S.off + sl, i = S.off + B.ids[k];
+        for (int d = 0; d < width; ++d)
+            dst[width * i + d] = src[width * k + d];
+    }
 }
 
 __global__ __launch_bounds__(BW) void k_batch_zero(int32_t* a, int32_t* b, int64_t m)
@@ -997,11 +1111,17 @@ size_t batch_carve(Carver& cv, const BatchLayout& lay, int nsys, int precision, 
     BatchDev b{};
     const int64_t N = lay.n_total;
     b.sys = cv.take<SysDev>(nsys);
+    b.pos = cv.take<double>(3 * N);
+    b.vel = cv.take<double>(3 * N);
     b.force = cv.take<double>(3 * N);
     b.epot = cv.take<double>(N);
+    b.ids = cv.take<int32_t>(N);
+    b.pos_t = cv.take<double>(3 * N);
+    b.vel_t = cv.take<double>(3 * N);
+    b.perm = cv.take<int32_t>(N);
     b.key = cv.take<int32_t>(N);
     b.tmp = cv.take<int32_t>(N);
-    b.perm = cv.take<int32_t>(N);
+    b.srcix = cv.take<int32_t>(N);
     b.count = cv.take<int32_t>(lay.bins);
     b.fill = cv.take<int32_t>(lay.bins);
     b.start = cv.take<int32_t>(lay.starts);
@@ -1038,24 +1158,26 @@ static unsigned chunk_grid(const pasta_batch* bt)
 }
 
 // Steps (mode 1) accumulate forces only; the initial evaluation (mode 0)
-// also the energies.
+// also the energies.  A run of steps launched back to back marks its first
+// step (the drift phase moves every system) and its last (no drift after the
+// combine, so the state ends at a full step).
 template <class P>
-int launch_step(pasta_batch* bt, int mode)
+int launch_step(pasta_batch* bt, int mode, int first, int last)
 {
     hipStream_t s = bt->stream;
     if (bt->mode == 0) {
         with_batch_variant(bt->dev.nuc_variant, [&](auto vt) {
             constexpr int V = decltype(vt)::value;
             if (mode)
-                k_batch_step<P, MODE_FORCE, V><<<bt->grid, BW, 0, s>>>(bt->dev, mode);
+                k_batch_step<P, MODE_FORCE, V><<<bt->grid, BW, 0, s>>>(bt->dev, mode, first, last);
             else
-                k_batch_step<P, MODE_ENERGY, V><<<bt->grid, BW, 0, s>>>(bt->dev, mode);
+                k_batch_step<P, MODE_ENERGY, V><<<bt->grid, BW, 0, s>>>(bt->dev, mode, 1, 1);
         });
     } else {
         const unsigned g = bt->phase_grid, gc = chunk_grid(bt);
-        k_ph_drift<P><<<gc, BW, 0, s>>>(bt->dev, mode);
+        k_ph_drift<P><<<gc, BW, 0, s>>>(bt->dev, mode, mode ? first : 1);
         k_ph_scan<<<(unsigned)bt->nsys, BW, 0, s>>>(bt->dev, mode);
-        k_ph_scatter<<<gc, BW, 0, s>>>(bt->dev, mode);
+        k_ph_scatter<<<gc, BW, 0, s>>>(bt->dev);
         k_ph_rank<P><<<gc, BW, 0, s>>>(bt->dev, mode);
         with_batch_variant(bt->dev.nuc_variant, [&](auto vt) {
             constexpr int V = decltype(vt)::value;
@@ -1065,16 +1187,17 @@ int launch_step(pasta_batch* bt, int mode)
                 k_ph_forces<P, MODE_ENERGY, V><<<g, BW, 0, s>>>(bt->dev, mode);
         });
         // the combine's last workgroup also runs the thermostat and the advance
-        k_ph_combine<P><<<gc, BW, 0, s>>>(bt->dev, mode, mode ? 0 : 1, 1);
+        k_ph_combine<P><<<gc, BW, 0, s>>>(bt->dev, mode, mode ? 0 : 1, 1, 1,
+                                          mode && !last ? 1 : 0);
     }
     PASTA_HIP(hipGetLastError());
     return PASTA_OK;
 }
 
-int launch_one(pasta_batch* bt, int mode)
+int launch_one(pasta_batch* bt, int mode, int first = 1, int last = 1)
 {
-    return bt->precision == PASTA_FP64 ? launch_step<Fp64Policy>(bt, mode)
-                                       : launch_step<MixedPolicy>(bt, mode);
+    return bt->precision == PASTA_FP64 ? launch_step<Fp64Policy>(bt, mode, first, last)
+                                       : launch_step<MixedPolicy>(bt, mode, first, last);
 }
 
 int check_batch_err(pasta_batch* bt, const char* who)
@@ -1247,8 +1370,8 @@ extern "C" int pasta_batch_create(const pasta_potential* pot, int32_t precision,
     B.mass = pot->mass;
     B.nuc_variant = batch_variant();
     B.chunk = batch_chunk();
-    B.pos = d_pos;
-    B.vel = d_vel;
+    B.cpos = d_pos;
+    B.cvel = d_vel;
     B.species = d_species;
     hipStream_t s = bt->stream;
     if (hipMemcpyAsync((void*)B.sys, bt->sys.data(), sizeof(SysDev) * nsys,
@@ -1256,6 +1379,7 @@ extern "C" int pasta_batch_create(const pasta_potential* pot, int32_t precision,
         return fail_free(fail(PASTA_EHIP, "pasta_batch_create: descriptor copy failed"));
     k_batch_init_scalars<<<1, 1024, 0, s>>>(B, step0);
     k_batch_zero<<<256, BW, 0, s>>>(B.count, B.fill, lay.bins);
+    k_batch_load<<<256, BW, 0, s>>>(B, lay.n_total);
     rc = precision == PASTA_FP64 ? persistent_grid<Fp64Policy>(B.nuc_variant, &bt->grid)
                                  : persistent_grid<MixedPolicy>(B.nuc_variant, &bt->grid);
     if (rc != PASTA_OK)
@@ -1283,7 +1407,7 @@ static int batch_capture(pasta_batch* bt)
     PASTA_HIP(hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal));
     int rc = PASTA_OK;
     for (int k = 0; k < bt->steps_per_graph && rc == PASTA_OK; ++k)
-        rc = launch_one(bt, 1);
+        rc = launch_one(bt, 1, k == 0, k == bt->steps_per_graph - 1);
     hipGraph_t g = nullptr;
     hipError_t e = hipStreamEndCapture(s, &g);
     if (rc != PASTA_OK)
@@ -1317,10 +1441,14 @@ extern "C" int pasta_batch_step(pasta_batch* bt, int64_t nsteps)
         PASTA_HIP(hipGraphLaunch(bt->exec, st));
         left -= bt->steps_per_graph;
     }
-    for (; left > 0; --left)
-        PASTA_TRY(launch_one(bt, 1));
+    for (int64_t k = 0; k < left; ++k)
+        PASTA_TRY(launch_one(bt, 1, k == 0, k == left - 1));
     k_apply_pending<<<bt->grid, BW, 0, st>>>(bt->dev);
     k_reset_pending<<<1, 1024, 0, st>>>(bt->dev);
+    if (nsteps > 0) {  // the state into the caller's arrays
+        k_batch_unsort<<<chunk_grid(bt), BW, 0, st>>>(bt->dev, bt->dev.pos, bt->dev.cpos, 3);
+        k_batch_unsort<<<chunk_grid(bt), BW, 0, st>>>(bt->dev, bt->dev.vel, bt->dev.cvel, 3);
+    }
     PASTA_HIP(hipGetLastError());
     bt->step += nsteps;
     if (nsteps > 0)
@@ -1362,9 +1490,9 @@ static int batch_refresh_energies(pasta_batch* bt)
     const unsigned g = bt->phase_grid, gc = chunk_grid(bt);
     launch_pair_phase<MODE_ENERGY>(bt->dev, bt->precision, g, s);
     if (bt->precision == PASTA_FP64)
-        k_ph_combine<Fp64Policy><<<gc, BW, 0, s>>>(bt->dev, 0, 1, 0);
+        k_ph_combine<Fp64Policy><<<gc, BW, 0, s>>>(bt->dev, 0, 1, 0, 0, 0);
     else
-        k_ph_combine<MixedPolicy><<<gc, BW, 0, s>>>(bt->dev, 0, 1, 0);
+        k_ph_combine<MixedPolicy><<<gc, BW, 0, s>>>(bt->dev, 0, 1, 0, 0, 0);
     PASTA_HIP(hipGetLastError());
     bt->epot_valid = true;
     return PASTA_OK;
@@ -1414,12 +1542,12 @@ extern "C" int pasta_batch_forces(pasta_batch* bt, double* d_force, double* d_ep
     PASTA_TRY(join_in(bt));
     if (d_epot)
         PASTA_TRY(batch_refresh_energies(bt));
+    // slot order to caller order
     if (d_force)
-        PASTA_HIP(hipMemcpyAsync(d_force, bt->dev.force, sizeof(double) * 3 * bt->n_total,
-                                 hipMemcpyDeviceToDevice, bt->stream));
+        k_batch_unsort<<<chunk_grid(bt), BW, 0, bt->stream>>>(bt->dev, bt->dev.force, d_force, 3);
     if (d_epot)
-        PASTA_HIP(hipMemcpyAsync(d_epot, bt->dev.epot, sizeof(double) * bt->n_total,
-                                 hipMemcpyDeviceToDevice, bt->stream));
+        k_batch_unsort<<<chunk_grid(bt), BW, 0, bt->stream>>>(bt->dev, bt->dev.epot, d_epot, 1);
+    PASTA_HIP(hipGetLastError());
     PASTA_TRY(join_out(bt));
     return check_batch_err(bt, "pasta_batch_forces");
 }
