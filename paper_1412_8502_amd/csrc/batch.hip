@@ -472,22 +472,19 @@ __device__ void phase_rank(const BatchDev& B, int64_t step, int mode)
 // M: what the pair items accumulate (MODE_FORCE in steps, MODE_ENERGY when
 // the energies are asked for, MODE_COUNT for the pair counts).
 template <class P, int M, int V>
-__device__ void phase_forces(const BatchDev& B, int64_t step, int mode, char* lds, int* s_item)
+// only < 0: the workgroups take items from the device work counter until
+// it passes the last (persistent form); only >= 0: this workgroup runs item
+// `only` alone (one workgroup per item, balanced by the dispatcher).
+__device__ void phase_forces(const BatchDev& B, int64_t step, int mode, char* lds, int* s_item,
+                             int64_t only)
 {
     const auto* stg = reinterpret_cast<const typename P::Src*>(B.stg);
     const int64_t total = B.coul_items + B.nuc_items;
     unsigned* ctr = B.queue;
-    while (true) {
-        if (threadIdx.x == 0)
-            *s_item = (int)atomicAdd(ctr, 1u);
-        __syncthreads();
-        const int64_t it = __builtin_amdgcn_readfirstlane(*s_item);  // uniform: the item
-        __syncthreads();
-        if (it >= total)
-            break;
+    auto run = [&](const int64_t it) {
         if (it < B.coul_items) {
             if (M == MODE_COUNT)
-                continue;
+                return;
             int s = 0;
             while (s + 1 < B.nsys && B.sys[s + 1].coul_item_off <= it)
                 ++s;
@@ -515,7 +512,7 @@ __device__ void phase_forces(const BatchDev& B, int64_t step, int mode, char* ld
             const SysDev& S = B.sys[s];
             const int local = (int)(jt - S.nuc_item_off);
             if (local >= B.n_items[s])
-                continue;
+                return;
             const NucConsts k = B.nk[s];
             const int2 gnc = B.grid_nc[s];
             NucArgs A{};
@@ -536,6 +533,21 @@ __device__ void phase_forces(const BatchDev& B, int64_t step, int mode, char* ld
             else
                 nuclear_item<P, true, M>(stg + S.off, A, k, local, lds);
         }
+    };
+    if (only >= 0) {
+        if (only < total)
+            run(only);
+        return;
+    }
+    while (true) {
+        if (threadIdx.x == 0)
+            *s_item = (int)atomicAdd(ctr, 1u);
+        __syncthreads();
+        const int64_t it = __builtin_amdgcn_readfirstlane(*s_item);  // uniform: the item
+        __syncthreads();
+        if (it >= total)
+            break;
+        run(it);
     }
 }
 
@@ -718,7 +730,7 @@ void k_batch_step(BatchDev B, int mode, int first, int last)
     phase_rank<P>(B, step, mode);
     if (!grid_sync(B, &s_flag))
         return;
-    phase_forces<P, M, V>(B, step, mode, lds, &s_item);
+    phase_forces<P, M, V>(B, step, mode, lds, &s_item, -1);
     if (!grid_sync(B, &s_flag))
         return;
     phase_combine<P>(B, step, mode, M != MODE_FORCE, true, !last, lds);
@@ -768,7 +780,7 @@ __global__ __launch_bounds__(BW) __attribute__((amdgpu_waves_per_eu(ph_force_wav
 {
     __shared__ __align__(16) char lds[batch_lds<P, V>()];
     __shared__ int s_item;
-    phase_forces<P, M, V>(B, *B.step, mode, lds, &s_item);
+    phase_forces<P, M, V>(B, *B.step, mode, lds, &s_item, (int64_t)blockIdx.x);
 }
 
 template <class F>
@@ -783,9 +795,18 @@ void with_batch_variant(int v, F f)
 }
 
 // The pair phase alone (mode 0: the state in place, no kick).
-template <int M>
-void launch_pair_phase(const BatchDev& dev, int precision, unsigned g, hipStream_t s)
+// Per-phase force launches: one workgroup per work item (every system's
+// Coulomb items, then its nuclear item slots; empty slots exit at once).
+inline unsigned item_grid(const BatchDev& dev)
 {
+    const int64_t t = dev.coul_items + dev.nuc_items;
+    return (unsigned)(t > 0 ? t : 1);
+}
+
+template <int M>
+void launch_pair_phase(const BatchDev& dev, int precision, hipStream_t s)
+{
+    const unsigned g = item_grid(dev);
     with_batch_variant(dev.nuc_variant, [&](auto vt) {
         constexpr int V = decltype(vt)::value;
         if (precision == PASTA_FP64)
@@ -1174,17 +1195,18 @@ int launch_step(pasta_batch* bt, int mode, int first, int last)
                 k_batch_step<P, MODE_ENERGY, V><<<bt->grid, BW, 0, s>>>(bt->dev, mode, 1, 1);
         });
     } else {
-        const unsigned g = bt->phase_grid, gc = chunk_grid(bt);
+        const unsigned gc = chunk_grid(bt);
         k_ph_drift<P><<<gc, BW, 0, s>>>(bt->dev, mode, mode ? first : 1);
         k_ph_scan<<<(unsigned)bt->nsys, BW, 0, s>>>(bt->dev, mode);
         k_ph_scatter<<<gc, BW, 0, s>>>(bt->dev);
         k_ph_rank<P><<<gc, BW, 0, s>>>(bt->dev, mode);
+        const unsigned gi = item_grid(bt->dev);  // one workgroup per work item
         with_batch_variant(bt->dev.nuc_variant, [&](auto vt) {
             constexpr int V = decltype(vt)::value;
             if (mode)
-                k_ph_forces<P, MODE_FORCE, V><<<g, BW, 0, s>>>(bt->dev, mode);
+                k_ph_forces<P, MODE_FORCE, V><<<gi, BW, 0, s>>>(bt->dev, mode);
             else
-                k_ph_forces<P, MODE_ENERGY, V><<<g, BW, 0, s>>>(bt->dev, mode);
+                k_ph_forces<P, MODE_ENERGY, V><<<gi, BW, 0, s>>>(bt->dev, mode);
         });
         // the combine's last workgroup also runs the thermostat and the advance
         k_ph_combine<P><<<gc, BW, 0, s>>>(bt->dev, mode, mode ? 0 : 1, 1, 1,
@@ -1487,8 +1509,8 @@ static int batch_refresh_energies(pasta_batch* bt)
         return PASTA_OK;
     hipStream_t s = bt->stream;
     k_batch_zero_pairs<<<1, 1024, 0, s>>>(bt->dev);
-    const unsigned g = bt->phase_grid, gc = chunk_grid(bt);
-    launch_pair_phase<MODE_ENERGY>(bt->dev, bt->precision, g, s);
+    const unsigned gc = chunk_grid(bt);
+    launch_pair_phase<MODE_ENERGY>(bt->dev, bt->precision, s);
     if (bt->precision == PASTA_FP64)
         k_ph_combine<Fp64Policy><<<gc, BW, 0, s>>>(bt->dev, 0, 1, 0, 0, 0);
     else
@@ -1561,8 +1583,7 @@ extern "C" int pasta_batch_pair_counts(pasta_batch* bt, int64_t* h_nuclear, int6
     k_batch_zero_pairs<<<1, 1024, 0, s>>>(bt->dev);
     // the cell lists and staging of the current state are in place; the
     // count pass rewrites F (same values) without a kick
-    const unsigned g = bt->phase_grid;
-    launch_pair_phase<MODE_COUNT>(bt->dev, bt->precision, g, s);
+    launch_pair_phase<MODE_COUNT>(bt->dev, bt->precision, s);
     PASTA_HIP(hipGetLastError());
     std::vector<unsigned long long> h(bt->nsys);
     PASTA_HIP(hipMemcpyAsync(h.data(), bt->dev.pairs, sizeof(unsigned long long) * bt->nsys,
