@@ -539,15 +539,17 @@ __device__ void phase_forces(const BatchDev& B, int64_t step, int mode, char* ld
             run(only);
         return;
     }
-    while (true) {
+    // the first item of workgroup b is item b; later ones come from the
+    // counter (which starts at zero in every step), fetched when an item
+    // starts so that the fetch overlaps the item's first loads
+    int64_t it = blockIdx.x;
+    while (it < total) {
         if (threadIdx.x == 0)
-            *s_item = (int)atomicAdd(ctr, 1u);
-        __syncthreads();
-        const int64_t it = __builtin_amdgcn_readfirstlane(*s_item);  // uniform: the item
-        __syncthreads();
-        if (it >= total)
-            break;
+            s_item[0] = (int)(gridDim.x + atomicAdd(ctr, 1u));
         run(it);
+        __syncthreads();
+        it = __builtin_amdgcn_readfirstlane(s_item[0]);  // uniform: the next item
+        __syncthreads();
     }
 }
 
