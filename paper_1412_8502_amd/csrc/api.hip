@@ -419,7 +419,7 @@ extern "C" int pasta_forces_workspace(const pasta_potential* pot, int32_t precis
         (precision != PASTA_FP64 && precision != PASTA_MIXED))
         return fail(PASTA_EINVAL, "pasta_forces_workspace: bad argument");
     const ListCfg lc = list_cfg(PASTA_TERM_ALL, L);
-    const Grid g = make_grid(L, cell_cut(pot, lc), CELL_SUB);
+    const Grid g = make_force_grid(L, cell_cut(pot, lc), n, CELL_SUB);
     Carver cv(nullptr);
     *h_bytes = force_carve(cv, nullptr, n, g.C, precision, pot, lc);
     return PASTA_OK;
@@ -455,7 +455,7 @@ static int forces_run(const char* who, const pasta_potential* pot, int32_t preci
     // a call without the nuclear terms uses the cell-sweep layout, which is
     // smaller than the list layout the workspace query may have sized
     const ListCfg lc = list_cfg(terms, L);
-    const Grid g = make_grid(L, cell_cut(pot, lc), CELL_SUB);
+    const Grid g = make_force_grid(L, cell_cut(pot, lc), n, CELL_SUB);
     Carver cv0(nullptr);
     PASTA_TRY(check_work(d_work, work_bytes, force_carve(cv0, nullptr, n, g.C, precision, pot, lc),
                          who));
@@ -575,7 +575,7 @@ extern "C" int pasta_autotune(const pasta_potential* pot, int32_t precision, int
     // candidates use a prefix of it
     const ListCfg lay = cfg_variant(3);
     Carver cvn(nullptr);
-    const Grid g = make_grid(L, pot->r_nuc, CELL_SUB);
+    const Grid g = make_force_grid(L, pot->r_nuc, n, CELL_SUB);
     force_carve(cvn, nullptr, n, g.C, precision, pot, lay);
     cvn.take<double>(4 * (size_t)n);  // scratch force + energy outputs
     PASTA_TRY(check_work(d_work, work_bytes, cvn.size(), "pasta_autotune"));
@@ -705,7 +705,7 @@ extern "C" int pasta_autotune_workspace(const pasta_potential* pot, int32_t prec
     if (!h_bytes || n < 0 || !(L > 0.0) || !std::isfinite(L) ||
         (precision != PASTA_FP64 && precision != PASTA_MIXED))
         return fail(PASTA_EINVAL, "pasta_autotune_workspace: bad argument");
-    const Grid g = make_grid(L, pot->r_nuc, CELL_SUB);
+    const Grid g = make_force_grid(L, pot->r_nuc, n, CELL_SUB);
     Carver cv(nullptr);
     force_carve(cv, nullptr, n, g.C, precision, pot, cfg_variant(3));
     cv.take<double>(3 * (size_t)n);
@@ -814,7 +814,7 @@ extern "C" int pasta_sim_workspace(const pasta_potential* pot, const pasta_integ
         !std::isfinite(L_start) || (precision != PASTA_FP64 && precision != PASTA_MIXED))
         return fail(PASTA_EINVAL, "pasta_sim_workspace: bad argument");
     const ListCfg lc = list_cfg(PASTA_TERM_ALL, L_start);
-    const Grid g = make_grid(L_max > L_start ? L_max : L_start, cell_cut(pot, lc), CELL_SUB);
+    const Grid g = make_force_grid(L_max > L_start ? L_max : L_start, cell_cut(pot, lc), n, CELL_SUB);
     Carver cv(nullptr);
     *h_bytes = sim_carve(cv, nullptr, n, g.C, precision, pot, lc);
     return PASTA_OK;
@@ -825,7 +825,7 @@ static int sim_eval_initial(pasta_sim* sim)
 {
     hipStream_t s = sim->stream;
     const double L = box_side(sim, sim->step);
-    const Grid g = make_grid(L, sim->r_cell, CELL_SUB);
+    const Grid g = make_force_grid(L, sim->r_cell, sim->n, CELL_SUB);
     const PairParams pp = pair_params(&sim->pot, L);
     sim->cur = 0;
     const StateMove mv{sim->vel, nullptr, sim->xs[0], sim->vs[0], sim->ids[0], sim->sps[0]};
@@ -852,7 +852,7 @@ static int sim_refresh_energies(pasta_sim* sim)
     if (sim->epot_valid)
         return PASTA_OK;
     const double L = box_side(sim, sim->step);
-    const Grid g = make_grid(L, sim->r_cell, CELL_SUB);
+    const Grid g = make_force_grid(L, sim->r_cell, sim->n, CELL_SUB);
     KickArgs kick{nullptr, 0.0, sim->pot.mass, nullptr, true};
     eval_forces(sim->precision, PASTA_TERM_ALL, sim->w, g, sim->n, sim->Z,
                 pair_params(&sim->pot, L), sim->force, sim->epot, kick, nullptr, sim->stream,
@@ -899,7 +899,7 @@ extern "C" int pasta_sim_create(const pasta_potential* pot, const pasta_integrat
     // the workspace
     const ListCfg lc = list_cfg(PASTA_TERM_ALL, Lstart);
     sim->r_cell = cell_cut(pot, lc);
-    sim->C_max = make_grid(sim->L_max, sim->r_cell, CELL_SUB).C;
+    sim->C_max = make_force_grid(sim->L_max, sim->r_cell, sim->n, CELL_SUB).C;
     Carver cv0(nullptr);
     const size_t need = sim_carve(cv0, nullptr, n, sim->C_max, precision, pot, lc, 1);
     int rc = check_work(d_work, work_bytes, need, "pasta_sim_create");
@@ -962,7 +962,7 @@ extern "C" int pasta_sim_step(pasta_sim* sim, int64_t nsteps)
         if (!box_ok(L_new))
             return fail(PASTA_EBOX, "pasta_sim_step: box side %g at step %lld is outside "
                         "[2 r_nuc, L_max = %g]", L_new, (long long)(n0 + 1), sim->L_max);
-        const Grid g = make_grid(L_new, sim->r_cell, CELL_SUB);
+        const Grid g = make_force_grid(L_new, sim->r_cell, sim->n, CELL_SUB);
         const int c = sim->cur;
         DriftArgs da;
         da.pos = sim->xs[c];
@@ -1011,7 +1011,7 @@ extern "C" int pasta_sim_step(pasta_sim* sim, int64_t nsteps)
                           box_ok(L_next);
         NextDrift nd{};
         if (fuse) {
-            const Grid g2 = make_grid(L_next, sim->r_cell, CELL_SUB);
+            const Grid g2 = make_force_grid(L_next, sim->r_cell, sim->n, CELL_SUB);
             nd.pos = sim->xs[sim->cur];
             nd.species = sim->sps[sim->cur];
             nd.key = sim->w.cb.key;
@@ -1090,7 +1090,7 @@ extern "C" int pasta_sim_pair_counts(pasta_sim* sim, int64_t* h_nuclear, int64_t
         return fail(PASTA_EINVAL, "pasta_sim_pair_counts: null sim");
     hipStream_t s = sim->stream;
     const double L = box_side(sim, sim->step);
-    const Grid g = make_grid(L, sim->r_cell, CELL_SUB);
+    const Grid g = make_force_grid(L, sim->r_cell, sim->n, CELL_SUB);
     uint64_t* ctr = sim->w.fb.pairs;
     PASTA_HIP(hipMemsetAsync(ctr, 0, 2 * sizeof(uint64_t), s));
     KickArgs kick{nullptr, 0.0, sim->pot.mass, nullptr, true};

@@ -123,14 +123,17 @@ __device__ __forceinline__ double box_at(const SysDev& S, int64_t step)
 // octant bins inside each cell, as in the single-system path
 constexpr int BSUB = 8;
 
-__device__ __forceinline__ Grid grid_at(double L, double r_cut)
+// The cell grid of a system of n particles in a box of side L, as the
+// single-system path builds it (cells of side at least r_cut, at most
+// cap_cells per side in sparse states).
+__device__ __forceinline__ Grid grid_at(double L, double r_cut, int64_t n)
 {
     Grid g;
     g.sub = BSUB;
     int nc = (int)floor(L / r_cut);
     while (nc > 1 && L / (double)nc < r_cut)
         nc--;
-    g.nc = nc < 1 ? 1 : nc;
+    g.nc = cap_cells(nc < 1 ? 1 : nc, n);
     g.C = g.nc * g.nc * g.nc;
     g.inv_w = (double)g.nc / L;
     g.L = L;
@@ -244,7 +247,7 @@ __device__ __forceinline__ int drift_slot(const BatchDev& B, const SysDev& S, in
                                           const double (&f)[3], bool proton)
 {
     const double L_old = box_at(S, step), L_new = box_at(S, step + 1);
-    const Grid gr = grid_at(L_new, B.pp.r_nuc);
+    const Grid gr = grid_at(L_new, B.pp.r_nuc, S.n);
     if (sc != 1.0) {
         v[0] *= sc;
         v[1] *= sc;
@@ -274,7 +277,7 @@ __device__ void phase_drift(const BatchDev& B, int64_t step, int mode, int first
             pp.L = box_at(S, mode ? step + 1 : step);
             B.nk[s] = make_nuc_consts(pp);
             B.ck[s] = make_coul_consts(pp);
-            const Grid gr = grid_at(pp.L, pp.r_nuc);
+            const Grid gr = grid_at(pp.L, pp.r_nuc, S.n);
             B.grid_nc[s] = make_int2(gr.nc, gr.C);
         }
     }
@@ -304,7 +307,7 @@ __device__ void phase_drift(const BatchDev& B, int64_t step, int mode, int first
             }
         } else {
             const double L = box_at(S, step);
-            const Grid gr = grid_at(L, B.pp.r_nuc);
+            const Grid gr = grid_at(L, B.pp.r_nuc, S.n);
             if (!(x[0] >= 0.0 && x[0] < L && x[1] >= 0.0 && x[1] < L && x[2] >= 0.0 && x[2] < L))
                 atomicOr(B.err, ERR_RANGE);
             bin = particle_bin(x[0], x[1], x[2], proton, gr.inv_w, gr.nc, gr.C, gr.sub);
@@ -330,7 +333,7 @@ __device__ void phase_scan(const BatchDev& B, int64_t step, int mode, char* lds_
     for (int s = blockIdx.x; s < B.nsys; s += gridDim.x) {
         const SysDev& S = B.sys[s];
         const double L = box_at(S, mode ? step + 1 : step);
-        const Grid gr = grid_at(L, B.pp.r_nuc);
+        const Grid gr = grid_at(L, B.pp.r_nuc, S.n);
         int32_t* count = B.count + S.bin_off;
         int32_t* fill = B.fill + S.bin_off;
         int32_t* start = B.start + S.start_off;

@@ -94,6 +94,30 @@ inline Grid make_grid(double L, double r_cut, int sub = 1)
     return g;
 }
 
+// Sparse states: the force paths' grids have at most k cells per side, k
+// the largest with k^3 * CELL_MIN_OCC <= n, so that a cell holds about
+// CELL_MIN_OCC particles or more (a full 32-target work item).  Larger cells
+// keep the 27-cell stencil complete (their side only grows past r_cut);
+// they trade the per-item overhead of near-empty cells against more
+// candidates screened per target.  Dense states (the paper's 0.08 fm^-3:
+// about 150 per cell) never reach the cap.
+constexpr int64_t CELL_MIN_OCC = 32;
+__host__ __device__ inline int cap_cells(int nc, int64_t n)
+{
+    int k = 1;
+    while ((int64_t)(k + 1) * (k + 1) * (k + 1) * CELL_MIN_OCC <= n)
+        ++k;
+    return nc < k ? nc : k;
+}
+inline Grid make_force_grid(double L, double r_cut, int64_t n, int sub)
+{
+    Grid g = make_grid(L, r_cut, sub);
+    g.nc = cap_cells(g.nc, n);
+    g.C = g.nc * g.nc * g.nc;
+    g.inv_w = (double)g.nc / L;
+    return g;
+}
+
 // Neighbour-cell offsets along one axis without duplicates: {-1,0,1} when
 // there are at least 3 cells per side, {0,1} for 2, {0} for 1.
 __host__ __device__ inline int axis_lo(int nc) { return nc >= 3 ? -1 : 0; }
