@@ -7,7 +7,8 @@
 //               integer atomic count per bin (order-independent);
 //   scan        exclusive scan of the 2C counts, the nuclear work list (cell,
 //               target chunk), and the reset of the counters: one workgroup
-//               for grids of up to 1024 cells, else two launches of one
+//               for grids of up to 2048 cells (one or two rows of 1024; a
+//               third row would spill registers), else two launches of one
 //               thread per cell;
 //   scatter     one thread per particle: slot = start[bin] + atomic cursor
 //               (arrival order, not yet stable);
@@ -202,6 +203,91 @@ __global__ __launch_bounds__(SCAN_THREADS) void k_scan_oct(int32_t* __restrict__
         start[2 * CS] = (int32_t)(Zt + (tot >> 32));
         if (chunk > 0)
             *n_items = (int32_t)tq;
+    }
+}
+
+// The same for grids of up to ROWS * SCAN_THREADS cells in one workgroup:
+// cell r * SCAN_THREADS + t belongs to thread t (row r), so every load and
+// store of a row is coalesced.  Each row is scanned on its own and offset by
+// the totals of the rows before it; the neutron starts need the proton total
+// of every row, so all rows are scanned before any start is written.
+template <int ROWS>
+__global__ __launch_bounds__(SCAN_THREADS) void k_scan_oct_rows(
+    int32_t* __restrict__ count, int32_t* __restrict__ fill, int32_t* __restrict__ start, int C,
+    int chunk, int32_t* __restrict__ items, int32_t* __restrict__ n_items,
+    const int32_t* __restrict__ gate)
+{
+    __shared__ int64_t lds[64];
+    if (gate && *gate == 0)
+        return;
+    const int64_t CS = (int64_t)C * 8;
+    int4 p0[ROWS], p1[ROWS], n0[ROWS], n1[ROWS];
+#pragma unroll
+    for (int r = 0; r < ROWS; ++r) {
+        const int c = r * SCAN_THREADS + (int)threadIdx.x;
+        p0[r] = p1[r] = n0[r] = n1[r] = int4{0, 0, 0, 0};
+        if (c < C) {
+            const int4* cp = reinterpret_cast<const int4*>(count + 8 * (int64_t)c);
+            const int4* cn = reinterpret_cast<const int4*>(count + CS + 8 * (int64_t)c);
+            p0[r] = cp[0];
+            p1[r] = cp[1];
+            n0[r] = cn[0];
+            n1[r] = cn[1];
+        }
+    }
+    int64_t pre[ROWS], bq[ROWS], kq[ROWS];
+    int64_t run = 0, runq = 0;  // totals of the rows before (uniform)
+#pragma unroll
+    for (int r = 0; r < ROWS; ++r) {
+        const int64_t sp = (int64_t)p0[r].x + p0[r].y + p0[r].z + p0[r].w + p1[r].x + p1[r].y +
+                           p1[r].z + p1[r].w;
+        const int64_t sn = (int64_t)n0[r].x + n0[r].y + n0[r].z + n0[r].w + n1[r].x + n1[r].y +
+                           n1[r].z + n1[r].w;
+        kq[r] = chunk > 0 ? (sp + sn + chunk - 1) / chunk : 0;
+        int64_t tot = 0, tq = 0;
+        pre[r] = run + block_exclusive_scan(sp | (sn << 32), lds, &tot);
+        bq[r] = chunk > 0 ? runq + block_exclusive_scan(kq[r], lds, &tq) : 0;
+        run += tot;
+        runq += tq;
+    }
+    const int64_t Zt = run & 0xffffffffll;  // all protons
+#pragma unroll
+    for (int r = 0; r < ROWS; ++r) {
+        const int c = r * SCAN_THREADS + (int)threadIdx.x;
+        if (c >= C)
+            continue;
+        int32_t b = (int32_t)(pre[r] & 0xffffffffll);
+        int4 s0, s1;
+        s0.x = b; b += p0[r].x; s0.y = b; b += p0[r].y; s0.z = b; b += p0[r].z; s0.w = b;
+        b += p0[r].w;
+        s1.x = b; b += p1[r].x; s1.y = b; b += p1[r].y; s1.z = b; b += p1[r].z; s1.w = b;
+        int4* sp4 = reinterpret_cast<int4*>(start + 8 * (int64_t)c);
+        sp4[0] = s0;
+        sp4[1] = s1;
+        b = (int32_t)(Zt + (pre[r] >> 32));
+        s0.x = b; b += n0[r].x; s0.y = b; b += n0[r].y; s0.z = b; b += n0[r].z; s0.w = b;
+        b += n0[r].w;
+        s1.x = b; b += n1[r].x; s1.y = b; b += n1[r].y; s1.z = b; b += n1[r].z; s1.w = b;
+        int4* sn4 = reinterpret_cast<int4*>(start + CS + 8 * (int64_t)c);
+        sn4[0] = s0;
+        sn4[1] = s1;
+        for (int64_t q = 0; q < kq[r]; ++q) {
+            items[2 * (bq[r] + q) + 0] = c;
+            items[2 * (bq[r] + q) + 1] = (int32_t)q;
+        }
+        // this thread alone read these counters
+        const int4 z{0, 0, 0, 0};
+        int4* zc = reinterpret_cast<int4*>(count + 8 * (int64_t)c);
+        int4* zn = reinterpret_cast<int4*>(count + CS + 8 * (int64_t)c);
+        int4* fc = reinterpret_cast<int4*>(fill + 8 * (int64_t)c);
+        int4* fn = reinterpret_cast<int4*>(fill + CS + 8 * (int64_t)c);
+        zc[0] = z; zc[1] = z; zn[0] = z; zn[1] = z;
+        fc[0] = z; fc[1] = z; fn[0] = z; fn[1] = z;
+    }
+    if (threadIdx.x == 0) {
+        start[2 * CS] = (int32_t)(Zt + (run >> 32));
+        if (chunk > 0)
+            *n_items = (int32_t)runq;
     }
 }
 
@@ -550,6 +636,9 @@ void launch_scan(const CellBuf& cb, const Grid& g, int chunk, hipStream_t s, Tim
     if (g.sub == 8 && g.C <= SCAN_THREADS) {
         k_scan_oct<<<1, SCAN_THREADS, 0, s>>>(cb.count, cb.fill, cb.start, g.C, chunk, cb.items,
                                               cb.n_items, gate);
+    } else if (g.sub == 8 && g.C <= 2 * SCAN_THREADS) {
+        k_scan_oct_rows<2><<<1, SCAN_THREADS, 0, s>>>(cb.count, cb.fill, cb.start, g.C, chunk,
+                                                      cb.items, cb.n_items, gate);
     } else if (g.C > SCAN_THREADS && nblk <= MSCAN_MAX_BLOCKS && (g.sub == 8 || g.sub == 1)) {
         int64_t* blk = reinterpret_cast<int64_t*>(cb.tmp);
         if (g.sub == 8) {
