@@ -122,6 +122,7 @@ __device__ __forceinline__ double box_at(const SysDev& S, int64_t step)
 
 // octant bins inside each cell, as in the single-system path
 constexpr int BSUB = 8;
+constexpr int SCAN_WG = 1024;  // threads of the per-phase scan's workgroups
 
 // The cell grid of a system of n particles in a box of side L, as the
 // single-system path builds it (cells of side at least r_cut, at most
@@ -338,7 +339,7 @@ __device__ void phase_scan(const BatchDev& B, int64_t step, int mode, char* lds_
         int32_t* fill = B.fill + S.bin_off;
         int32_t* start = B.start + S.start_off;
         const int64_t C = gr.C, CS = C * BSUB;
-        const int64_t per = (C + BW - 1) / BW;
+        const int64_t per = (C + blockDim.x - 1) / blockDim.x;
         const int64_t c0 = min((int64_t)threadIdx.x * per, C), c1 = min(c0 + per, C);
         int64_t sp = 0, sn = 0, sq = 0;
         for (int64_t c = c0; c < c1; ++c) {
@@ -759,7 +760,9 @@ __global__ __launch_bounds__(BW) void k_ph_drift(BatchDev B, int mode, int first
 {
     phase_drift(B, *B.step, mode, first);
 }
-__global__ __launch_bounds__(BW) void k_ph_scan(BatchDev B, int mode)
+// one workgroup of SCAN_WG threads per system (the persistent kernel runs the
+// same phase with its BW threads)
+__global__ __launch_bounds__(SCAN_WG) void k_ph_scan(BatchDev B, int mode)
 {
     __shared__ __align__(16) char lds[BW * 8];
     phase_scan(B, *B.step, mode, lds);
@@ -1202,7 +1205,7 @@ int launch_step(pasta_batch* bt, int mode, int first, int last)
     } else {
         const unsigned gc = chunk_grid(bt);
         k_ph_drift<P><<<gc, BW, 0, s>>>(bt->dev, mode, mode ? first : 1);
-        k_ph_scan<<<(unsigned)bt->nsys, BW, 0, s>>>(bt->dev, mode);
+        k_ph_scan<<<(unsigned)bt->nsys, SCAN_WG, 0, s>>>(bt->dev, mode);
         k_ph_scatter<<<gc, BW, 0, s>>>(bt->dev);
         k_ph_rank<P><<<gc, BW, 0, s>>>(bt->dev, mode);
         const unsigned gi = item_grid(bt->dev);  // one workgroup per work item
