@@ -177,6 +177,52 @@ def run_batch(B, torch, states, precision, mode, steps, warmup, spg=10, tune=Fal
                 tuning=best, tuning_table=[[c, round(ms, 5)] for c, ms in table] if table else None)
 
 
+def batch_overhead_section(B, torch, steps=200, warmup=20):
+    """Per-step time of the batched path, per-phase launches against the
+    persistent kernel at 1, 3 and 5 workgroups per CU, from a system whose
+    pair work is negligible up to the headline size: the persistent form's
+    extra cost per step grows with its workgroup count (each workgroup
+    orders its arrivals at every device-wide barrier with agent-scope
+    fences), not with the work."""
+    import numpy as np
+    from paper_1412_8502_amd.inputs import make_state
+    dev = torch.device("cuda:0")
+    cases = (("1 x 2000", [(2000, 0.2, 0.08, 1.0, 1)]),
+             ("1 x 6400", [(6400, 0.2, 0.08, 1.0, 1)]),
+             ("8 x 6400", [(6400, 0.2, 0.08, 1.0, k) for k in range(8)]),
+             ("1 x 51200", [(51200, 0.2, 0.08, 0.75, 1)]))
+    saved = B.pasta_get_tuning()
+    out = {"setting": "nuclear variant 3, pairwise Coulomb items, mixed, n = 0.08 fm^-3, "
+                      "graphs of 10 steps, rescale every 100"}
+    try:
+        for name, specs in cases:
+            sts = [make_state(*c) for c in specs]
+            r = {}
+            for mode, wpc in ((1, 0), (0, 1), (0, 3), (0, 5)):
+                B.pasta_set_tuning(nuclear_variant=3, coulomb_form=1, batch_wgs_per_cu=wpc)
+                pos = torch.tensor(np.concatenate([s["pos"] for s in sts]), device=dev)
+                vel = torch.tensor(np.concatenate([s["vel"] for s in sts]), device=dev)
+                sp = torch.tensor(np.concatenate([s["species"] for s in sts]), device=dev)
+                b = B.Batch(pos, vel, sp, [s["n"] for s in sts], [s["L"] for s in sts],
+                            [dict(dt=2.0, T=s["T"], rescale_every=100) for s in sts],
+                            mode=mode, steps_per_graph=10)
+                b.step(warmup)
+                torch.cuda.synchronize()
+                t0 = time.perf_counter()
+                b.step(steps)
+                torch.cuda.synchronize()
+                us = (time.perf_counter() - t0) / steps * 1e6
+                grid = b.info()["grid"]
+                b.close()
+                key = "per_phase" if mode == 1 else f"persistent_{wpc}_per_cu"
+                r[key] = {"us_per_step": round(us, 1), "grid": grid}
+            out[name] = r
+            print(name, r, file=sys.stderr, flush=True)
+    finally:
+        B.pasta_set_tuning(**saved)
+    return out
+
+
 def single_via_batch(B, torch, st, steps, warmup):
     """One system through the batched path in both modes, each tuned on it."""
     vb = run_batch(B, torch, [st], B.PASTA_MIXED, 1, steps, warmup, tune=True)
@@ -414,7 +460,8 @@ def main():
                     help="skip the N = 409 600 section")
     ap.add_argument("--no-decompression", action="store_true",
                     help="skip the 20 000-step decompression window")
-    ap.add_argument("--section", choices=("large", "decompression", "batch"), default=None,
+    ap.add_argument("--section", choices=("large", "decompression", "batch", "batch-overhead"),
+                    default=None,
                     help="run only this section and print its JSON (for profiler runs)")
     ap.add_argument("--tuning", default=None,
                     help="variant,splits,fused[,coulomb_form[,nuclear_tile]]: use this kernel "
@@ -442,6 +489,9 @@ def main():
         res["single_system_via_batch_path"] = single_via_batch(B, torch, st1, args.steps,
                                                                args.warmup)
         print(json.dumps({"section": "batch", "result": res}))
+        return
+    if args.section == "batch-overhead":
+        print(json.dumps({"section": args.section, "result": batch_overhead_section(B, torch)}))
         return
     if args.section:
         fn = large_section if args.section == "large" else decompression_section
