@@ -105,6 +105,35 @@ def measured_traffic(kernel_name, tuning):
     return None
 
 
+def stencil_candidates(pos, L, r_nuc=11.5, min_occ=32):
+    """Ordered candidate pairs that the 27-cell stencil presents to the
+    nuclear kernels at these positions (self pairs excluded), on the force
+    path's grid: cells of side at least r_nuc, at most k per side with
+    k^3 * min_occ <= N.  The kernels cull this further (the staging keeps
+    the sources within r_nuc of a work item's bounding box); the ratio to
+    the useful ordered pairs measures the stencil's waste."""
+    import numpy as np
+    n = len(pos)
+    nc = int(np.floor(L / r_nuc))
+    while nc > 1 and L / nc < r_nuc:
+        nc -= 1
+    nc = max(nc, 1)
+    k = 1
+    while (k + 1) ** 3 * min_occ <= n:
+        k += 1
+    nc = min(nc, k)
+    c = np.clip(np.floor(np.asarray(pos) * (nc / L)).astype(np.int64), 0, nc - 1)
+    counts = np.bincount((c[:, 0] * nc + c[:, 1]) * nc + c[:, 2],
+                         minlength=nc ** 3).reshape(nc, nc, nc).astype(np.float64)
+    offs = (-1, 0, 1) if nc >= 3 else ((0, 1) if nc == 2 else (0,))
+    neigh = np.zeros_like(counts)
+    for dx in offs:
+        for dy in offs:
+            for dz in offs:
+                neigh += np.roll(counts, (dx, dy, dz), axis=(0, 1, 2))
+    return float((counts * neigh).sum() - n), nc
+
+
 def run_path(B, torch, st, precision, steps, warmup, timing, pot=None):
     dev = torch.device("cuda:0")
     pos = torch.tensor(st["pos"], device=dev)
@@ -138,8 +167,10 @@ def run_path(B, torch, st, precision, steps, warmup, timing, pot=None):
     en = sim.energies()
     ls = sim.list_stats()
     sim.close()
+    stencil, ncell = stencil_candidates(pos.cpu().numpy(), st["L"])
     return dict(seconds=dt_plain, seconds_with_events=dt_timed, nuc_pairs=(nuc0 + nuc1) / 2,
                 coul_pairs=coul, kernel_times=kt, energies=en, list_stats=ls,
+                stencil_candidates=stencil, ncell=ncell,
                 steps=steps + (steps if timing else 0) + warmup)
 
 
@@ -677,6 +708,17 @@ def main():
                    "parallelism": "single GPU"},
         "md_steps_per_s": steps_s,
         "useful_pairs_per_step": {"nuclear": mixed["nuc_pairs"], "coulomb": mixed["coul_pairs"]},
+        "evaluated_pairs_per_step": {
+            "nuclear_stencil_ordered": mixed["stencil_candidates"],
+            "nuclear_useful_ordered": 2 * mixed["nuc_pairs"],
+            "stencil_over_useful": mixed["stencil_candidates"] / max(1.0, 2 * mixed["nuc_pairs"]),
+            "cells_per_side": mixed["ncell"],
+            "coulomb_evaluated": mixed["coul_pairs"],
+            "note": "nuclear: ordered candidate pairs of the 27-cell stencil at the final state "
+                    "(the kernels' staging culls them further to the sources within r_nuc of "
+                    "each work item's bounding box); coulomb: every unordered proton pair once "
+                    "(pairwise form)"},
+        "evaluated_tests_per_s": (mixed["stencil_candidates"] + mixed["coul_pairs"]) * 1e3 / ms_step,
         "fp64": {"ms_per_step": fp64_ms, "md_steps_per_s": 1e3 / fp64_ms,
                  "pair_interactions_per_s": (fp64["nuc_pairs"] + fp64["coul_pairs"]) * 1e3 / fp64_ms,
                  "steps": k64,
