@@ -105,6 +105,32 @@ def measured_traffic(kernel_name, tuning):
     return None
 
 
+def host_environment():
+    """ROCm version and the GPU clocks (rocm-smi, if it answers within a few
+    seconds), read before this process touches the GPU."""
+    import subprocess
+    env = {}
+    try:
+        with open("/opt/rocm/.info/version") as f:
+            env["rocm"] = f.read().strip()
+    except OSError:
+        env["rocm"] = None
+    try:
+        out = subprocess.run(["rocm-smi", "--showclocks"], capture_output=True, text=True,
+                             timeout=10).stdout
+        env["clocks"] = [l.strip() for l in out.splitlines() if "sclk" in l or "mclk" in l][:4]
+    except (OSError, subprocess.SubprocessError):
+        env["clocks"] = None
+    return env
+
+
+def device_environment(torch):
+    p = torch.cuda.get_device_properties(0)
+    return {"device": p.name, "arch": getattr(p, "gcnArchName", None),
+            "compute_units": p.multi_processor_count, "hip": torch.version.hip,
+            "torch": torch.__version__}
+
+
 def stencil_candidates(pos, L, r_nuc=11.5, min_occ=32):
     """Ordered candidate pairs that the 27-cell stencil presents to the
     nuclear kernels at these positions (self pairs excluded), on the force
@@ -134,7 +160,7 @@ def stencil_candidates(pos, L, r_nuc=11.5, min_occ=32):
     return float((counts * neigh).sum() - n), nc
 
 
-def run_path(B, torch, st, precision, steps, warmup, timing, pot=None):
+def run_path(B, torch, st, precision, steps, warmup, timing, pot=None, windows=0):
     dev = torch.device("cuda:0")
     pos = torch.tensor(st["pos"], device=dev)
     vel = torch.tensor(st["vel"], device=dev)
@@ -151,6 +177,15 @@ def run_path(B, torch, st, precision, steps, warmup, timing, pot=None):
     torch.cuda.synchronize()
     dt_plain = time.perf_counter() - t0
     nuc1, _ = sim.pair_counts()
+    # further timed windows of the step loop (their median beside the main window)
+    win = []
+    for _ in range(windows):
+        kw = max(50, steps // 5)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        sim.step(kw)
+        torch.cuda.synchronize()
+        win.append((time.perf_counter() - t0) / kw * 1e3)
     kt = None
     dt_timed = None
     if timing:
@@ -170,7 +205,7 @@ def run_path(B, torch, st, precision, steps, warmup, timing, pot=None):
     stencil, ncell = stencil_candidates(pos.cpu().numpy(), st["L"])
     return dict(seconds=dt_plain, seconds_with_events=dt_timed, nuc_pairs=(nuc0 + nuc1) / 2,
                 coul_pairs=coul, kernel_times=kt, energies=en, list_stats=ls,
-                stencil_candidates=stencil, ncell=ncell,
+                stencil_candidates=stencil, ncell=ncell, windows_ms=win,
                 steps=steps + (steps if timing else 0) + warmup)
 
 
@@ -509,6 +544,7 @@ def main():
               "decomposition of this path is a design, not a measured mode", file=sys.stderr)
         sys.exit(2)
 
+    host_env = host_environment() if not args.section else None
     import numpy as np
     import torch
     from paper_1412_8502_amd import binding as B
@@ -561,7 +597,7 @@ def main():
         tuned, _, table = tune(tpos, tsp, st["L"], B.PASTA_MIXED, use_cache=False, apply=True)
     log(f"kernel setting mixed: {tuned}  fp64: {tuned64}")
     del tpos, tsp
-    mixed_cells = run_path(B, torch, st, B.PASTA_MIXED, K, W, timing=True)
+    mixed_cells = run_path(B, torch, st, B.PASTA_MIXED, K, W, timing=True, windows=5)
     log(f"mixed, cell sweeps: {mixed_cells['seconds'] / K * 1e3:.4f} ms/step")
     if args.headline_only:
         useful = mixed_cells["nuc_pairs"] + mixed_cells["coul_pairs"]
@@ -587,7 +623,7 @@ def main():
     del tpos, tvel, tsp
     log(f"list halo trials (halo, ms/step, builds in 200 steps): {skin_table} -> {skin}")
     old = B.pasta_set_tuning(nuclear_variant=2, list_skin=skin)
-    mixed_lists = run_path(B, torch, st, B.PASTA_MIXED, K, W, timing=True)
+    mixed_lists = run_path(B, torch, st, B.PASTA_MIXED, K, W, timing=True, windows=5)
     B.pasta_set_tuning(**old)
     log(f"mixed, neighbour lists: {mixed_lists['seconds'] / K * 1e3:.4f} ms/step, "
         f"{mixed_lists['list_stats']}")
@@ -707,6 +743,13 @@ def main():
                    "N": N, "Z": Z, "L_fm": st["L"], "precision": "mixed",
                    "parallelism": "single GPU"},
         "md_steps_per_s": steps_s,
+        "timing_windows": {
+            "main_window_ms_per_step": ms_step,
+            "further_windows_ms_per_step": [round(x, 5) for x in mixed["windows_ms"]],
+            "median_of_windows_ms_per_step": float(np.median([ms_step] + mixed["windows_ms"])),
+            "note": "the same simulation, 5 further windows of K/5 steps after the main K; "
+                    "the single-system path launches its kernels per step (no graph to build)"},
+        "environment": dict(device_environment(torch), **(host_env or {})),
         "useful_pairs_per_step": {"nuclear": mixed["nuc_pairs"], "coulomb": mixed["coul_pairs"]},
         "evaluated_pairs_per_step": {
             "nuclear_stencil_ordered": mixed["stencil_candidates"],
