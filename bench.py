@@ -506,11 +506,29 @@ def cpu_baseline(st, pairs_per_target_fn, budget_s=15.0):
         usable = len(os.sched_getaffinity(0))
     except (AttributeError, OSError):
         usable = None
+    # the oracle at the other sizes: one force evaluation and 20 steps at
+    # N = 3200, one force evaluation at N = 409 600 estimated from 64 targets
+    from paper_1412_8502_amd.inputs import workload
+    other = {}
+    s1 = workload("n3200_yp040_n0.040")
+    t0 = time.perf_counter()
+    oracle.forces(s1["pos"], s1["species"], s1["L"], nthreads=threads)
+    other["force_eval_s_n3200"] = round(time.perf_counter() - t0, 4)
+    t0 = time.perf_counter()
+    oracle.run(s1["pos"], s1["vel"], s1["species"], s1["L"], 20, dt=2.0, T=s1["T"],
+               nthreads=threads)
+    other["steps20_s_n3200"] = round(time.perf_counter() - t0, 4)
+    s5 = workload("n409600_yp040_n0.080")
+    few = rng.choice(s5["n"], 64, replace=False)
+    t0 = time.perf_counter()
+    oracle.forces(s5["pos"], s5["species"], s5["L"], targets=few, nthreads=threads)
+    other["force_eval_s_n409600_estimated"] = round((time.perf_counter() - t0) / 64 * s5["n"], 1)
+    other["force_eval_s_n51200_estimated"] = round(t / m * N, 2)
     return dict(value=useful / t, unit="pair interactions/s", cores=threads, kind="oracle",
                 sample=f"{m} of {N} targets of the same state, all {N} sources each "
                        f"(FP64 brute force), {t:.1f} s",
                 md_steps_per_s_equiv=1.0 / (t / m * N), cpu_model=model,
-                nproc=os.cpu_count(), usable_cpus=usable)
+                nproc=os.cpu_count(), usable_cpus=usable, other_sizes=other)
 
 
 def main():
