@@ -289,6 +289,49 @@ def batch_overhead_section(B, torch, steps=200, warmup=20):
     return out
 
 
+def build_section(B, torch, sizes=(4 << 20, 8 << 20, 16 << 20), reps=5):
+    """The standalone cell-list build (pasta_cell_list: bin count, scan,
+    scatter, stable rank; cells of side >= r_nuc, one bin per cell and
+    species) on uniformly random states of 4-16 M particles at 0.08 fm^-3,
+    first in random order, then with the particles already in cell order
+    (the simulation's steady state, where a wavefront's lanes share bins and
+    its atomic increments aggregate).
+    Algorithmic bytes per particle: positions and species read (25 B), the
+    bin key written and read twice (12 B), the scatter's slot array written
+    and read (8 B), the permutation written (4 B): 49 B.  The rank pass
+    also reads every member of the particle's bin (about 75 at this
+    density), which the algorithmic count leaves out."""
+    dev = torch.device("cuda:0")
+    gen = torch.Generator(device=dev)
+    gen.manual_seed(7)
+    out = {"algorithmic_bytes_per_particle": 49, "density_fm3": 0.08, "r_cut_fm": 11.5}
+    for n in sizes:
+        L = (n / 0.08) ** (1.0 / 3.0)
+        pos = torch.rand((n, 3), generator=gen, device=dev, dtype=torch.float64) * L
+        pos = torch.clamp(pos, 0.0, L * (1.0 - 1e-15))
+        sp = (torch.rand(n, generator=gen, device=dev) < 0.3).to(torch.uint8)
+        B.pasta_cell_list(pos, sp, L, 11.5)
+        r = {"L_fm": round(L, 2)}
+        for order in ("random", "cell_sorted"):
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            for _ in range(reps):
+                nc, start, perm = B.pasta_cell_list(pos, sp, L, 11.5)
+            torch.cuda.synchronize()
+            ms = (time.perf_counter() - t0) / reps * 1e3
+            r["cells_per_side"] = nc
+            r[order] = {"ms_per_build": round(ms, 3), "particles_per_s": n / ms * 1e3,
+                        "algorithmic_GB_per_s": round(49 * n / ms * 1e-6, 1)}
+            if order == "random":  # the same particles in cell order
+                idx = perm.long()
+                pos, sp = pos[idx].contiguous(), sp[idx].contiguous()
+                B.pasta_cell_list(pos, sp, L, 11.5)
+        out[f"n{n}"] = r
+        print(n, r, file=sys.stderr, flush=True)
+        del pos, sp, start, perm
+    return out
+
+
 def single_via_batch(B, torch, st, steps, warmup):
     """One system through the batched path in both modes, each tuned on it."""
     vb = run_batch(B, torch, [st], B.PASTA_MIXED, 1, steps, warmup, tune=True)
@@ -544,7 +587,8 @@ def main():
                     help="skip the N = 409 600 section")
     ap.add_argument("--no-decompression", action="store_true",
                     help="skip the 20 000-step decompression window")
-    ap.add_argument("--section", choices=("large", "decompression", "batch", "batch-overhead"),
+    ap.add_argument("--section", choices=("large", "decompression", "batch", "batch-overhead",
+                                          "build"),
                     default=None,
                     help="run only this section and print its JSON (for profiler runs)")
     ap.add_argument("--tuning", default=None,
@@ -574,6 +618,9 @@ def main():
         res["single_system_via_batch_path"] = single_via_batch(B, torch, st1, args.steps,
                                                                args.warmup)
         print(json.dumps({"section": "batch", "result": res}))
+        return
+    if args.section == "build":
+        print(json.dumps({"section": args.section, "result": build_section(B, torch)}))
         return
     if args.section == "batch-overhead":
         print(json.dumps({"section": args.section, "result": batch_overhead_section(B, torch)}))
