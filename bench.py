@@ -131,6 +131,28 @@ def device_environment(torch):
             "torch": torch.__version__}
 
 
+def memory_kernels(per_kernel, n):
+    """Achieved algorithmic GB/s of the memory-side kernels of a step against
+    the 8 TB/s HBM peak.  Bytes per particle: integrate (the combine with the
+    second half kick, the next step's half kick, drift and binning) reads the
+    raw nuclear (F, V) 32 B, positions and velocities 48 B and species 1 B,
+    writes positions and velocities 48 B, F 24 B and the bin key 4 B: 157 B
+    (the Coulomb partials it also sums are left out); build (scatter and
+    rank; the scan is per cell) reads the key twice and the slot array once
+    (12 B), writes the slot array, the permutation and the staging entry
+    (24 B) and moves positions and velocities (96 B): 132 B."""
+    out = {}
+    for name, keys, per in (("integrate", ("combine+kick",), 157),
+                            ("build", ("scan", "scatter", "rank+stage"), 132)):
+        ms = sum(per_kernel.get(k, {}).get("ms_per_step", 0.0) for k in keys)
+        if ms > 0:
+            gbs = per * n / (ms * 1e-3) * 1e-9
+            out[name] = {"kernels": list(keys), "ms_per_step": round(ms, 5),
+                         "algorithmic_bytes": per * n, "GB_per_s": round(gbs, 1),
+                         "frac_of_8TBps": round(gbs / 8000.0, 4)}
+    return out
+
+
 def stencil_candidates(pos, L, r_nuc=11.5, min_occ=32):
     """Ordered candidate pairs that the 27-cell stencil presents to the
     nuclear kernels at these positions (self pairs excluded), on the force
@@ -859,6 +881,7 @@ def main():
                                               if v[1]}},
         "ms_per_step_with_events": mixed["seconds_with_events"] / K * 1e3,
         "per_kernel": per_kernel,
+        "memory_kernels": memory_kernels(per_kernel, N),
         "roofline": roof,
         "fp64_roofline": roof64,
         "coulomb_cut_20fm": cut20_entry,
