@@ -172,6 +172,24 @@ def test_batch_energy_refresh_keeps_trajectory(env, mode):
     assert t.equal(runs[0][0], runs[1][0]) and t.equal(runs[0][1], runs[1][1])
 
 
+@pytest.mark.parametrize("mode", [0, 1])
+def test_batch_forces_after_steps(env, mode):
+    """After steps the batch keeps its state in the cell order of its last
+    build; forces and energy shares handed back must be those of the
+    caller-order state in the caller's arrays, particle by particle."""
+    b, states, pos, vel, offs = make(env, SMALL[:3], prec=0, mode=mode, spg=3,
+                                     integs=[dict(dt=2.0, T=1.0, rescale_every=4)] * 3)
+    b.step(7)
+    f, e = b.forces()
+    f, e = f.cpu().numpy(), e.cpu().numpy()
+    P = pos.cpu().numpy()
+    for k, st in enumerate(states):
+        sl = slice(offs[k], offs[k + 1])
+        of, oe = env["O"].forces(P[sl], st["species"], st["L"])
+        check(f[sl], of, 0, e[sl], oe, what=f"system {k} after 7 steps", say=say)
+    b.close()
+
+
 def test_batch_thermostat_and_pairs(env):
     specs = SMALL[:3]
     b, states, pos, vel, offs = make(env, specs, prec=0, mode=0,
