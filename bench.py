@@ -402,13 +402,18 @@ def kernel_variant(tuning):
     return v
 
 
+# public coulomb_form -> the fused kernel's Coulomb template argument, and a name
+FUSED_COULOMB_ARG = {0: 0, 1: 1, 2: 3}
+COULOMB_FORM_NAMES = {0: "gather", 1: "pairwise", 2: "pairwise fixed-point"}
+
+
 def pair_kernel_name(tuning, use_lists=False):
     if tuning.get("fused_forces") or kernel_variant(tuning) >= 4:
         tile = tuning.get("nuclear_tile", 0)
         return "pair forces (nuclear %s%s + %s Coulomb tiles, one launch)" % (
             "list items" if use_lists else "cell tiles",
             " of %d sources" % tile if tile else "",
-            "pairwise" if tuning.get("coulomb_form") else "gather")
+            COULOMB_FORM_NAMES[tuning.get("coulomb_form", 0)])
     return "nuclear+kick"
 
 
@@ -754,8 +759,8 @@ def main():
         roof = roofline_entry(pair_kernel_name(tuned, use_lists), mixed["nuc_pairs"],
                               mixed["coul_pairs"], avg_ms, B.PASTA_MIXED)
         roof["traffic"] = None if use_lists else measured_traffic(
-            "k_forces_fused<MixedPolicy, 0, %d, %d>" % (kernel_variant(tuned),
-                                                       tuned.get("coulomb_form", 0)), tuned)
+            "k_forces_fused<MixedPolicy, 0, %d, %d>" % (
+                kernel_variant(tuned), FUSED_COULOMB_ARG[tuned.get("coulomb_form", 0)]), tuned)
         roof["traffic_unit"] = "bytes per launch (HBM, counter runs in profiles/)"
     elif dom in ("coulomb", "nuclear+kick"):
         roof = roofline_entry(dom, mixed["nuc_pairs"] if dom == "nuclear+kick" else 0,

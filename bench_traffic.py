@@ -19,7 +19,9 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 SOURCES = ["paper_1412_8502_amd/csrc/forces.hip", "paper_1412_8502_amd/csrc/fp64math.hpp",
            "paper_1412_8502_amd/csrc/internal.hpp", "paper_1412_8502_amd/csrc/list_items.hpp",
            "paper_1412_8502_amd/csrc/pair_items.hpp"]
-SETTINGS = [(3, 32, 1, 0), (3, 0, 1, 1)]
+SETTINGS = [(3, 32, 1, 0), (3, 0, 1, 1), (3, 0, 1, 2)]
+# public coulomb_form -> the fused kernel's Coulomb template argument
+FUSED_COULOMB_ARG = {0: 0, 1: 1, 2: 3}
 COPY_KIB = 256 * 1024
 
 
@@ -38,14 +40,15 @@ def main(prefix):
     entries = []
     for t in SETTINGS:
         tag = "_".join(map(str, t))
-        kname = "k_forces_fused<MixedPolicy, 0, %d, %d>" % (t[0], t[3])
+        cf = FUSED_COULOMB_ARG[t[3]]
+        kname = "k_forces_fused<MixedPolicy, 0, %d, %d>" % (t[0], cf)
         vals, factors = {}, {}
         for c in ("FETCH_SIZE", "WRITE_SIZE"):
             acc = counters("%s_%s_%s/pmc_counter_collection.csv" % (prefix, c, tag))
             copy = [v for (n, g), vs in acc.items() if "copyBuffer" in n and g == "131072"
                     for v in vs]
             kern = [v for (n, g), vs in acc.items()
-                    if "k_forces_fused<pasta::MixedPolicy, 0, %d, %d>" % (t[0], t[3]) in n
+                    if "k_forces_fused<pasta::MixedPolicy, 0, %d, %d>" % (t[0], cf) in n
                     for v in vs]
             factors[c] = COPY_KIB / (sum(copy) / len(copy))
             vals[c] = (sum(kern) / len(kern), len(kern), sum(copy) / len(copy))

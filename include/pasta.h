@@ -140,8 +140,13 @@ typedef struct pasta_integrator {
  *   (Newton's third law), the reaction carried along the wavefront by a
  *   lane rotation; 256-proton super-blocks, one partial per super-block and
  *   proton (used when those partials fit the workspace's partial buffer,
- *   else the gather form).  The batched path reads it at creation and plans
- *   each system's Coulomb term the same way.
+ *   else the gather form); 2 = pairwise, each item adding its per-proton
+ *   sums into 64-bit fixed-point accumulators (2^-43 MeV/fm, integer
+ *   atomics: order-independent, deterministic sums; no partials, no size
+ *   limit; a proton sum outside +-2^19 MeV/fm sets the device error word);
+ *   only in the fused form in mixed precision, elsewhere it runs as 1.  The
+ *   batched path reads it at creation and plans each system's Coulomb term
+ *   as form 0 or 1.
  * list_skin: the halo delta_r of variant 2, fm, in (0, 64] (default 2).
  * batch_wgs_per_cu: workgroups per compute unit of the persistent batched
  *   kernel (mode 0), 1..8, capped at what fits; 0 = as many as fit.  Read
@@ -167,10 +172,12 @@ typedef struct pasta_tuning {
 int pasta_set_tuning(const pasta_tuning* t);
 int pasta_get_tuning(pasta_tuning* out);
 /* Autotuner: builds the cell list of the given state once, then times the
- * Coulomb + nuclear kernels (reps evaluations each, HIP events) for every
+ * Coulomb + nuclear kernels (reps evaluations of the forces each, without
+ * energies as in a simulation step; HIP events) for every
  * candidate setting -- nuclear variant {0, 1, 3, 4 (fused only), 3 with
  * 256- and 1024-source tiles (fused only)} x Coulomb
- * {gather with splits S/2, S, 2S around the automatic S, pairwise} x
+ * {gather with splits S/2, S, 2S around the automatic S, pairwise,
+ * pairwise into fixed-point accumulators (fused, mixed precision)} x
  * fused_forces {0, 1}
  * -- and returns the fastest
  * in *h_best (the list fields copied from the current setting; the list

@@ -42,7 +42,7 @@ std::string describe_device_error(uint32_t bits)
             s += m;
         }
     };
-    add(ERR_NONFINITE_FORCE, "non-finite force");
+    add(ERR_NONFINITE_FORCE, "non-finite force (or a Coulomb sum beyond the fixed-point range)");
     add(ERR_NONFINITE_POS, "non-finite position");
     add(ERR_WRAP, "a particle moved more than one box length in a step");
     add(ERR_UF_LIMIT, "union-find retry bound reached");
@@ -329,7 +329,7 @@ extern "C" int pasta_set_tuning(const pasta_tuning* t)
 {
     if (!t || t->nuclear_variant < 0 || t->nuclear_variant > 4 || t->coulomb_splits < 0 ||
         t->coulomb_splits > 32 || (t->fused_forces != 0 && t->fused_forces != 1) ||
-        (t->coulomb_form != 0 && t->coulomb_form != 1) || !(t->list_skin > 0.0 && t->list_skin <= 64.0) ||
+        t->coulomb_form < 0 || t->coulomb_form > 2 || !(t->list_skin > 0.0 && t->list_skin <= 64.0) ||
         !(t->list_pool_scale > 0.0 && t->list_pool_scale <= 1e3) || t->batch_wgs_per_cu < 0 ||
         t->batch_wgs_per_cu > 8 ||
         (t->nuclear_tile != 0 && t->nuclear_tile != NUC_TILE_SHORT && t->nuclear_tile != 512 &&
@@ -554,12 +554,13 @@ extern "C" int pasta_forces_noalloc(const pasta_potential* pot, int32_t precisio
 }
 
 // -------------------------------------------------------------- tuning
-// Times the two pair kernels (Coulomb + nuclear with its epilogue) on the
-// given state for every candidate setting and keeps the fastest.  Candidates:
-// nuclear variant {dense, compacted, compacted with 8 lanes per target,
-// Newton-3 half stencil (fused only)} x Coulomb {gather with source splits
-// S/2, S, 2S around the automatic S (clamped to 1..32), pairwise} x fused
-// {0, 1}.  The cell list is built once per item size.
+// Times the two pair kernels (Coulomb + nuclear with its epilogue, forces
+// only) on the given state for every candidate setting and keeps the
+// fastest.  Candidates: nuclear variant {dense, compacted, compacted with 8
+// lanes per target, Newton-3 half stencil (fused only)} x Coulomb {gather
+// with source splits S/2, S, 2S around the automatic S (clamped to 1..32),
+// pairwise, pairwise into fixed-point accumulators (fused, mixed precision)}
+// x fused {0, 1}.  The cell list is built once per item size.
 extern "C" int pasta_autotune(const pasta_potential* pot, int32_t precision, int64_t n, double L,
                               const double* d_pos, const uint8_t* d_species, void* d_work,
                               size_t work_bytes, void* stream, int32_t reps, pasta_tuning* h_best,
@@ -577,7 +578,7 @@ extern "C" int pasta_autotune(const pasta_potential* pot, int32_t precision, int
     Carver cvn(nullptr);
     const Grid g = make_force_grid(L, pot->r_nuc, n, CELL_SUB);
     force_carve(cvn, nullptr, n, g.C, precision, pot, lay);
-    cvn.take<double>(4 * (size_t)n);  // scratch force + energy outputs
+    cvn.take<double>(3 * (size_t)n);  // scratch force output
     PASTA_TRY(check_work(d_work, work_bytes, cvn.size(), "pasta_autotune"));
     hipStream_t s = static_cast<hipStream_t>(stream);
     ForceWork w;
@@ -586,7 +587,6 @@ extern "C" int pasta_autotune(const pasta_potential* pot, int32_t precision, int
     const int64_t items32 = w.cb.item_max;
     const int64_t items64 = n / nuclear_chunk_for(1) + g.C + 1;
     double* f = cv.take<double>(3 * (size_t)n);
-    double* e = cv.take<double>((size_t)n);
     const PairParams pp = pair_params(pot, L);
     PASTA_HIP(hipMemsetAsync(w.err, 0, sizeof(uint32_t), s));
     cellbuf_zero(w.cb, g.C, s, g.sub);
@@ -649,6 +649,16 @@ extern "C" int pasta_autotune(const pasta_potential* pot, int32_t precision, int
                 c.coulomb_form = 1;
                 cands.push_back(c);
             }
+            // pairwise into fixed-point accumulators: fused, mixed precision
+            if (Z > 0 && fused && precision == PASTA_MIXED) {
+                pasta_tuning c = saved;
+                c.nuclear_variant = v;
+                c.nuclear_tile = tile;
+                c.coulomb_splits = 0;
+                c.fused_forces = 1;
+                c.coulomb_form = 2;
+                cands.push_back(c);
+            }
         }
     hipEvent_t e0, e1;
     PASTA_HIP(hipEventCreate(&e0));
@@ -660,16 +670,17 @@ extern "C" int pasta_autotune(const pasta_potential* pot, int32_t precision, int
     for (size_t c = 0; c < cands.size() && rc == PASTA_OK; ++c) {
         g_tuning = cands[c];
         cells_for(internal_variant(cands[c]));
-        // one untimed warm-up, then reps timed evaluations
-        eval_forces(precision, PASTA_TERM_ALL, w, g, n, Z, pp, f, e, kick, nullptr, s, nullptr,
-                    d_pos, w.cb.perm);
+        // one untimed warm-up, then reps timed evaluations; forces only, as
+        // a simulation step evaluates them (energies are asked for rarely)
+        eval_forces(precision, PASTA_TERM_ALL, w, g, n, Z, pp, f, nullptr, kick, nullptr, s,
+                    nullptr, d_pos, w.cb.perm);
         if (hipEventRecord(e0, s) != hipSuccess) {
             rc = fail(PASTA_EHIP, "hipEventRecord failed");
             break;
         }
         for (int r = 0; r < reps; ++r)
-            eval_forces(precision, PASTA_TERM_ALL, w, g, n, Z, pp, f, e, kick, nullptr, s,
-                        nullptr, d_pos, w.cb.perm);
+            eval_forces(precision, PASTA_TERM_ALL, w, g, n, Z, pp, f, nullptr, kick, nullptr,
+                        s, nullptr, d_pos, w.cb.perm);
         float ms = 0.f;
         if (hipEventRecord(e1, s) != hipSuccess || hipEventSynchronize(e1) != hipSuccess ||
             hipEventElapsedTime(&ms, e0, e1) != hipSuccess) {
@@ -709,7 +720,6 @@ extern "C" int pasta_autotune_workspace(const pasta_potential* pot, int32_t prec
     Carver cv(nullptr);
     force_carve(cv, nullptr, n, g.C, precision, pot, cfg_variant(3));
     cv.take<double>(3 * (size_t)n);
-    cv.take<double>((size_t)n);
     *h_bytes = cv.size();
     return PASTA_OK;
 }

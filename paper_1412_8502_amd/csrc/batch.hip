@@ -499,8 +499,7 @@ __device__ void phase_forces(const BatchDev& B, int64_t step, int mode, char* ld
             using PT = typename P::CPart;
             PT* part = static_cast<PT*>(B.coul_part) + S.coul_off;
             if (S.coul_form == 1) {
-                coulomb_pair_item<P, M != MODE_FORCE, PT>(stg + S.off, S.Z, k, part, (int)local,
-                                                          lds);
+                coulomb_pair_item<P, M != MODE_FORCE>(stg + S.off, S.Z, k, part, (int)local, lds);
             } else {
                 const int tblock = (int)(local % S.coul_blocks),
                           split = (int)(local / S.coul_blocks);

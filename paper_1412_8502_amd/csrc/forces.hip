@@ -8,7 +8,9 @@
 // Pairwise form: a workgroup owns a pair of 256-proton super-blocks and
 // evaluates each proton pair once, moving sources and their reactions along
 // the lanes.  Either way every proton gets S partial sums, added in fixed
-// order afterwards.
+// order afterwards; or, in the fused launch in mixed precision, the pairwise
+// items add each proton's sum over the item into a 64-bit fixed-point
+// accumulator with integer atomics (order-independent totals, no partials).
 //
 // Nuclear: cell items.  A workgroup owns a chunk of the targets of one cell
 // (taken octant by octant); the neighbour cells' particles within range of
@@ -48,7 +50,7 @@ __global__ __launch_bounds__(WG) void k_coulomb_pair(const typename P::Src* __re
 {
     __shared__ __align__(16) char lds[coulomb_pair_lds_bytes<P>()];
     using PT = typename P::CPart;
-    coulomb_pair_item<P, E, PT>(stg, Z, k, static_cast<PT*>(part), blockIdx.x, lds);
+    coulomb_pair_item<P, E>(stg, Z, k, static_cast<PT*>(part), blockIdx.x, lds);
 }
 
 template <class P, bool NUC, int MODE>
@@ -132,7 +134,9 @@ constexpr int fused_lds_bytes()
 }
 
 // CF: Coulomb form, 0 = gather tiles (coul_blocks x splits items), 1 =
-// pairwise super-block items, 2 = gather tiles with a finite cutoff.
+// pairwise super-block items, 2 = gather tiles with a finite cutoff, 3 =
+// pairwise items that add into the per-proton fixed-point accumulators
+// (A.react) instead of writing partials.
 template <class P, int MODE, int V, int CF>
 __global__ __launch_bounds__(WG) void k_forces_fused(const typename P::Src* __restrict__ stg,
                                                      NucArgs A, const int32_t* __restrict__ n_items,
@@ -165,7 +169,10 @@ __global__ __launch_bounds__(WG) void k_forces_fused(const typename P::Src* __re
     } else {
         const int h = g - item_max;
         if constexpr (CF == 1)
-            coulomb_pair_item<P, MODE != MODE_FORCE, PT>(stg, Z, kc, part, h, lds);
+            coulomb_pair_item<P, MODE != MODE_FORCE>(stg, Z, kc, part, h, lds);
+        else if constexpr (CF == 3)
+            coulomb_pair_item<P, MODE != MODE_FORCE>(
+                stg, Z, kc, FixedPart{A.react, A.err, A.react_stride}, h, lds);
         else
             coulomb_item<P, MODE != MODE_FORCE, PT, CF == 2>(stg, Z, per_split, kc, part,
                                                              h % coul_blocks, h / coul_blocks, lds,
@@ -184,7 +191,11 @@ __global__ __launch_bounds__(WG) void k_forces_fused(const typename P::Src* __re
 // proton's S partial loads are spread over several lanes, all in flight).
 // Blocks [zb, ...) take the neutrons, one lane each.  The slot's own loads
 // (nuclear part, velocity, position, species, reactions) are issued before
-// the partials, so the two latencies overlap.
+// the partials, so the two latencies overlap.  react (optional): the
+// fixed-point accumulators of slots [0, react_n) (Newton-3 reactions of
+// every slot, and/or the Coulomb sums of the protons), added and cleared
+// for the next launch; with the Coulomb sums there the caller passes no
+// partials (S = 0, Z = zb = 0: one lane per slot).
 constexpr int COMB_LANES = 8;
 constexpr int COMB_UNROLL = 8;
 __host__ __device__ inline int64_t combine_proton_blocks(int64_t Z)
@@ -201,7 +212,8 @@ __global__ __launch_bounds__(WG) void k_combine(const double4* __restrict__ fnuc
                                                 double mass, double* __restrict__ ke_part,
                                                 int32_t* __restrict__ n_ke, uint32_t* err,
                                                 NextDrift nd, int has_next,
-                                                unsigned long long* __restrict__ react)
+                                                unsigned long long* __restrict__ react,
+                                                int64_t react_n)
 {
     __shared__ double red[WG / 64];
     const bool prot = (int)blockIdx.x < zb;
@@ -215,6 +227,7 @@ __global__ __launch_bounds__(WG) void k_combine(const double4* __restrict__ fnuc
         sl = (int64_t)Z + (int64_t)(blockIdx.x - zb) * WG + threadIdx.x;
     }
     const bool lead = q == 0 && sl < (prot ? (int64_t)Z : n);
+    const bool has_r = react && sl < react_n;
 
     double4 fn = make_double4(0.0, 0.0, 0.0, 0.0);
     double v0[3] = {0.0, 0.0, 0.0}, x[3] = {0.0, 0.0, 0.0};
@@ -223,10 +236,10 @@ __global__ __launch_bounds__(WG) void k_combine(const double4* __restrict__ fnuc
     int spc = 0;
     if (lead) {
         fn = fnuc[sl];
-        if (react) {
+        if (has_r) {
 #pragma unroll
             for (int c = 0; c < 4; ++c)
-                rq[c] = react[4 * sl + c];
+                rq[c] = react[c * n + sl];
         }
         id = perm ? perm[sl] : sl;
         if (vel) {
@@ -275,15 +288,15 @@ __global__ __launch_bounds__(WG) void k_combine(const double4* __restrict__ fnuc
     double ke = 0.0;
     if (lead) {
         double rx = 0.0, ry = 0.0, rz = 0.0, rw = 0.0;
-        if (react) {
-            // Newton-3 reactions (fixed point), cleared for the next launch
+        if (has_r) {
+            // accumulated reactions and sums (fixed point), cleared for the next launch
             rx = (double)(long long)rq[0] * REACT_UNIT;
             ry = (double)(long long)rq[1] * REACT_UNIT;
             rz = (double)(long long)rq[2] * REACT_UNIT;
             rw = (double)(long long)rq[3] * REACT_UNIT;
 #pragma unroll
             for (int c = 0; c < 4; ++c)
-                react[4 * sl + c] = 0ull;
+                react[c * n + sl] = 0ull;
         }
         const double Fx = (fn.x + rx) + cx, Fy = (fn.y + ry) + cy, Fz = (fn.z + rz) + cz,
                      V = (fn.w + rw) + cw;
@@ -448,15 +461,19 @@ int coulomb_splits(int64_t Z, int64_t cap)
 
 int coulomb_pair_plan_supers(int64_t Z) { return coulomb_pair_supers(Z); }
 
-CoulPlan coulomb_plan(int64_t Z, int64_t coul_max, bool cut)
+CoulPlan coulomb_plan(int64_t Z, int64_t coul_max, bool cut, bool fixed_ok)
 {
     CoulPlan p{0, 0};
     if (Z <= 0)
         return p;
+    const int form = g_tuning.coulomb_form;
     if (cut) {
         p.form = 2;
         p.S = coulomb_splits(Z, coul_max);
-    } else if (g_tuning.coulomb_form == 1 && (int64_t)coulomb_pair_supers(Z) * Z <= coul_max) {
+    } else if (form == 2 && fixed_ok) {
+        p.form = 3;
+        p.S = coulomb_pair_supers(Z);
+    } else if (form >= 1 && (int64_t)coulomb_pair_supers(Z) * Z <= coul_max) {
         p.form = 1;
         p.S = coulomb_pair_supers(Z);
     } else {
@@ -488,16 +505,19 @@ void launch_forces_fused(int precision, const ForceBuf& fb, const CellBuf& cb, c
     const NucConsts k = make_nuc_consts(pp);
     const CoulConsts kc = make_coul_consts(pp);
     const bool cut = std::isfinite(pp.r_coul);
-    const CoulPlan plan = (with_coulomb && Z > 0) ? coulomb_plan(Z, fb.coul_max, cut)
-                                                  : CoulPlan{0, 0};
+    const CoulPlan plan = (with_coulomb && Z > 0)
+                              ? coulomb_plan(Z, fb.coul_max, cut, precision == PASTA_MIXED)
+                              : CoulPlan{0, 0};
+    // fixed-point form: no partials; the combine reads the accumulators
+    const bool fixed = plan.form == 3;
     const CoulCut cc{fb.cut_pos, fb.cut_perm,
                      pair_counter ? reinterpret_cast<unsigned long long*>(pair_counter + 1)
                                   : nullptr};
     const int S = plan.S;
     const int per = S ? (int)((Z + S - 1) / S) : 0;
     const int coul_blocks = S ? (int)((Z + WG - 1) / WG) : 0;
-    const int64_t coul_items = S == 0 ? 0 : (plan.form == 1 ? coulomb_pair_items(Z)
-                                                            : (int64_t)coul_blocks * S);
+    const int64_t coul_items = S == 0 ? 0 : (plan.form == 1 || fixed ? coulomb_pair_items(Z)
+                                                                     : (int64_t)coul_blocks * S);
     NucArgs a{};
     a.start = cb.start;
     a.items = cb.items;
@@ -510,6 +530,7 @@ void launch_forces_fused(int precision, const ForceBuf& fb, const CellBuf& cb, c
     a.err = err;
     a.fnuc = fb.fnuc;
     a.react = fb.react;
+    a.react_stride = n;
     (void)with_nuclear_terms;  // the fused form always carries the nuclear terms
     const int item_max = (int)cb.item_max;
     const unsigned grid = (unsigned)(item_max + coul_items);
@@ -527,17 +548,20 @@ void launch_forces_fused(int precision, const ForceBuf& fb, const CellBuf& cb, c
             constexpr int M = decltype(mtag)::value;
             auto launch = [&](auto ctag) {
                 constexpr int CF = decltype(ctag)::value;
-                if (precision == PASTA_FP64)
-                    k_forces_fused<Fp64Policy, M, V, CF><<<grid, WG, 0, s>>>(
-                        fb.stg64, a, cb.n_items, item_max, k, (int)Z, per, coul_blocks, kc,
-                        fb.coul_part, la, cc);
-                else
+                if (precision == PASTA_FP64) {
+                    if constexpr (CF != 3)  // the fixed-point form is mixed precision only
+                        k_forces_fused<Fp64Policy, M, V, CF><<<grid, WG, 0, s>>>(
+                            fb.stg64, a, cb.n_items, item_max, k, (int)Z, per, coul_blocks, kc,
+                            fb.coul_part, la, cc);
+                } else
                     k_forces_fused<MixedPolicy, M, V, CF><<<grid, WG, 0, s>>>(
                         fb.stgq, a, cb.n_items, item_max, k, (int)Z, per, coul_blocks, kc,
                         fb.coul_part, la, cc);
             };
             if (plan.form == 1)
                 launch(std::integral_constant<int, 1>());
+            else if (fixed)
+                launch(std::integral_constant<int, 3>());
             else if (plan.form == 2)
                 launch(std::integral_constant<int, 2>());
             else
@@ -558,16 +582,19 @@ void launch_forces_fused(int precision, const ForceBuf& fb, const CellBuf& cb, c
     timer_end(t, KC_NUCLEAR, s);
     timer_begin(t, KC_COMBINE, s);
     {
-        // protons (COMB_LANES lanes each) then neutrons (one lane each)
-        const int zb = (int)combine_proton_blocks(Z);
-        const unsigned cgrid = (unsigned)(zb + (n - Z + WG - 1) / WG);
+        // protons (COMB_LANES lanes each) then neutrons (one lane each); with
+        // the fixed-point form every slot takes one lane (no partials)
+        const int64_t Zc = fixed ? 0 : Z;
+        const int zb = (int)combine_proton_blocks(Zc);
+        const unsigned cgrid = (unsigned)(zb + (n - Zc + WG - 1) / WG);
         const NextDrift nd = kick.next ? *kick.next : NextDrift{};
         auto comb = [&](auto* part) {
-            k_combine<<<cgrid, WG, 0, s>>>(fb.fnuc, part, S, (int)Z, zb,
+            k_combine<<<cgrid, WG, 0, s>>>(fb.fnuc, part, fixed ? 0 : S, (int)Zc, zb,
                                            kick.slot_order ? nullptr : cb.perm, n, force, epot,
                                            kick.vel, kick.hdtm, kick.mass, kick.ke_part, fb.n_ke,
                                            err, nd, kick.next ? 1 : 0,
-                                           variant == 4 ? fb.react : nullptr);
+                                           variant == 4 || fixed ? fb.react : nullptr,
+                                           variant == 4 ? n : Z);
         };
         if (precision == PASTA_FP64)
             comb(static_cast<const double4*>(fb.coul_part));

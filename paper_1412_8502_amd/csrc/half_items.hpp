@@ -12,8 +12,8 @@
 // memory.
 //
 // Determinism without floating-point atomics: reactions are accumulated as
-// 64-bit integers in units of 2^-43 MeV/fm (and MeV), whose sums do not
-// depend on the order the lanes and items add them in.  One pair's reaction
+// 64-bit integers in units of 2^-43 MeV/fm (and MeV; react_fixed), whose
+// sums do not depend on the order the lanes and items add them in.  One pair's reaction
 // is rounded to 2^-44 (1e-13 MeV/fm); a particle's total stays below 2^20
 // MeV/fm by a wide margin (a nuclear pair force is at most about 90 MeV/fm).
 // The combine kernel adds the accumulated reactions to the target-side sums
@@ -24,15 +24,8 @@
 
 namespace pasta {
 
-constexpr double REACT_PER_UNIT = 8796093022208.0;       // 2^43 units per MeV/fm
-constexpr double REACT_UNIT = 1.0 / 8796093022208.0;     // MeV/fm per unit
-constexpr int HALF_TPT = 8;                              // lanes per target
-constexpr int HALF_TILE = 256;                           // sources per LDS tile
-
-__device__ __forceinline__ unsigned long long react_fixed(double x)
-{
-    return (unsigned long long)(long long)llrint(x * REACT_PER_UNIT);
-}
+constexpr int HALF_TPT = 8;     // lanes per target
+constexpr int HALF_TILE = 256;  // sources per LDS tile
 
 // One pair's force on the target (MeV/fm, in the policy's units before
 // f_scale) and energy V, zero outside the cutoff or when !valid.
@@ -78,8 +71,8 @@ constexpr int nuclear_half_lds_bytes()
            ITEM_LDS_BYTES;
 }
 
-// react: [n][4] int64 accumulators per sorted slot (fx, fy, fz, V), zero on
-// entry to the launch.  Requires at least 3 cells per side.
+// react: [4][A.react_stride] int64 accumulators per sorted slot (fx, fy, fz,
+// V), zero on entry to the launch.  Requires at least 3 cells per side.
 template <class P, int MODE>
 __device__ void nuclear_item_half(const typename P::Src* __restrict__ stg, const NucArgs& A,
                                   const NucConsts& k, int item, char* lds,
@@ -194,11 +187,11 @@ __device__ void nuclear_item_half(const typename P::Src* __restrict__ stg, const
             __syncthreads();
             for (int p = tid; p < n; p += WG) {
                 unsigned long long* r = racc + 4 * p;
-                unsigned long long* g = react + 4 * (int64_t)tslot[p];
+                unsigned long long* g = react + tslot[p];
 #pragma unroll
                 for (int c = 0; c < 4; ++c) {
                     if (r[c] != 0ull)
-                        atomicAdd(g + c, r[c]);
+                        atomicAdd(g + c * A.react_stride, r[c]);
                     r[c] = 0ull;
                 }
             }

@@ -437,7 +437,7 @@ struct ForceBuf {
     double* ke_part;    // [item_max] kinetic-energy partials of the last kick
     int32_t* n_ke;      // [1] number of valid ke_part entries (fused form)
     double4* fnuc;      // [n] nuclear (F, V) per sorted slot (fused form)
-    unsigned long long* react;  // [n][4] Newton-3 reactions of variant 4, fixed point
+    unsigned long long* react;  // [4][n] fixed point: Newton-3 reactions, Coulomb sums
                                 // (zero between launches)
     uint64_t* pairs;    // [2] diagnostic pair counters (nuclear, Coulomb; ordered)
     // FP64 positions the staging was built from, for a finite Coulomb
@@ -448,15 +448,17 @@ struct ForceBuf {
 // Automatic source splits of the gather form (about 2^19 / Z, at most 32,
 // at most cap / Z); the tuning's coulomb_splits overrides.
 int coulomb_splits(int64_t Z, int64_t cap = 524288);
-// How the Coulomb partials of Z protons are produced: form 0 = gather tiles
+// How the Coulomb sums of Z protons are produced: form 0 = gather tiles
 // with S source splits, 1 = pairwise super-block items (S = super-blocks of
-// 256 protons; used when S Z partials fit coul_max).  Every proton gets S
-// partials.
+// 256 protons; used when S Z partials fit coul_max); every proton then gets
+// S partials.  Form 3 (only where fixed_ok: the fused launch in mixed
+// precision) = pairwise items that add into per-proton fixed-point
+// accumulators, no partials (S = super-blocks).
 struct CoulPlan {
-    int form;  // 0 gather, 1 pairwise, 2 gather with a finite cutoff
+    int form;  // 0 gather, 1 pairwise, 2 gather with a finite cutoff, 3 pairwise fixed point
     int S;
 };
-CoulPlan coulomb_plan(int64_t Z, int64_t coul_max, bool cut = false);
+CoulPlan coulomb_plan(int64_t Z, int64_t coul_max, bool cut = false, bool fixed_ok = false);
 // Partials a force workspace holds for n particles: enough for the gather
 // form's default splits and for the pairwise form up to Z = 0.4 n.
 int64_t coulomb_partial_capacity(int64_t n);

@@ -436,6 +436,54 @@ __device__ __forceinline__ void store_part(float4* p, double x, double y, double
     *p = make_float4((float)x, (float)y, (float)z, (float)w);
 }
 
+// Per-particle fixed-point accumulators: 64-bit integers in units of 2^-43
+// MeV/fm (and MeV), added with integer atomics, so a particle's total does
+// not depend on the order in which work items add to it.  One added value is
+// rounded to 2^-44 (1e-13 MeV/fm); the representable total is +-2^20.
+constexpr double REACT_PER_UNIT = 8796093022208.0;    // 2^43 units per MeV/fm
+constexpr double REACT_UNIT = 1.0 / 8796093022208.0;  // MeV/fm per unit
+
+__device__ __forceinline__ unsigned long long react_fixed(double x)
+{
+    return (unsigned long long)(long long)llrint(x * REACT_PER_UNIT);
+}
+
+// Where a pairwise Coulomb item puts one proton's sum over the item (MeV/fm
+// and MeV).  A partial array: part[X * Z + p], X the other super-block of the
+// item, summed by the combine in super-block order.  FixedPart: the proton's
+// fixed-point accumulators acc[c * stride + p], c = x, y, z, V (the energy
+// only when E), so no partials exist; a sum that is not finite or not below
+// 2^19 in magnitude is not added and sets the error word instead.  The
+// component-major layout puts a wavefront's 64 consecutive protons of one
+// component in 512 contiguous bytes.
+struct FixedPart {
+    unsigned long long* acc;
+    uint32_t* err;
+    int64_t stride;
+};
+template <bool E, class PT>
+__device__ __forceinline__ void put_part(PT* __restrict__ part, int X, int Z, int p, double x,
+                                         double y, double z, double w)
+{
+    store_part(&part[(int64_t)X * Z + p], x, y, z, w);
+}
+template <bool E>
+__device__ __forceinline__ void put_part(const FixedPart& fp, int, int, int p, double x,
+                                         double y, double z, double w)
+{
+    constexpr double lim = 524288.0;  // 2^19
+    if (!(fabs(x) < lim && fabs(y) < lim && fabs(z) < lim && (!E || fabs(w) < lim))) {
+        atomicOr(fp.err, ERR_NONFINITE_FORCE);
+        return;
+    }
+    unsigned long long* a = fp.acc + p;
+    atomicAdd(a, react_fixed(x));
+    atomicAdd(a + fp.stride, react_fixed(y));
+    atomicAdd(a + 2 * fp.stride, react_fixed(z));
+    if (E)
+        atomicAdd(a + 3 * fp.stride, react_fixed(w));
+}
+
 // ============================================================ Coulomb ==
 // Targets are the proton slots [tb, tb + WG) ∩ [0, Z); sources the slots
 // [split * per_split, ...).  Writes part[split * Z + t] = (Fx, Fy, Fz, sum V).
@@ -533,7 +581,8 @@ __device__ void coulomb_item(const typename P::Src* __restrict__ stg, int Z, int
 // Partials: proton p of super-block X receives from item (A, B) the sum of
 // its contributions as part[Y][p], Y the other super-block of the item
 // (Y = X when A == B), i.e. exactly one partial per super-block, which the
-// combine adds in super-block order.
+// combine adds in super-block order; or every item adds that sum into the
+// proton's fixed-point accumulator (FixedPart).
 constexpr int CP_SUPER = 4;  // blocks per super-block (= wavefronts per workgroup)
 static_assert(CP_SUPER * 64 == WG, "one wavefront per block of a super-block");
 
@@ -615,10 +664,9 @@ __host__ __device__ inline void coulomb_pair_ab(int item, int S, int* A_out, int
 // 4 / NT; where a block has more than one, their FP32 sums meet in LDS and
 // are added in FP64 in wavefront order.  The pairs evaluated and the
 // partials written are those of the one-target schedule.
-template <class P, bool E, class PT, int NT = P::COUL_NT>
+template <class P, bool E, class PH, int NT = P::COUL_NT>
 __device__ void coulomb_pair_item_mt(const typename P::Src* __restrict__ stg, int Z,
-                                     const CoulConsts& k, PT* __restrict__ part, int A, int Bs,
-                                     char* lds)
+                                     const CoulConsts& k, PH part, int A, int Bs, char* lds)
 {
     static_assert(NT == 2 || NT == 4, "two or four targets per lane");
     constexpr int TG = CP_SUPER / NT;   // target groups = source blocks per wave
@@ -679,8 +727,8 @@ __device__ void coulomb_pair_item_mt(const typename P::Src* __restrict__ stg, in
         if (TG == 1) {
             // this wave alone covers the source block: its partial from A
             const int p = (J0 + jj) * 64 + lane;
-            store_part(&part[(int64_t)A * Z + p], (double)sx * fsc, (double)sy * fsc,
-                       (double)sz * fsc, (double)se * vsc);
+            put_part<E>(part, A, Z, p, (double)sx * fsc, (double)sy * fsc,
+                        (double)sz * fsc, (double)se * vsc);
         } else {
             CA* a = acc_s + ((w * TG + jj) * 64 + lane) * 4;
             a[0] = sx;
@@ -711,7 +759,7 @@ __device__ void coulomb_pair_item_mt(const typename P::Src* __restrict__ stg, in
             fe += (double)a[3];
         }
         const int t = (CP_SUPER * A + b) * 64 + lane;
-        store_part(&part[(int64_t)Bs * Z + t], fx * fsc, fy * fsc, fz * fsc, fe * vsc);
+        put_part<E>(part, Bs, Z, t, fx * fsc, fy * fsc, fz * fsc, fe * vsc);
     }
     if (TG > 1) {
         const int b = w, s0 = (b / TG) * TG, slot = b % TG;  // waves s0 .. s0 + TG - 1
@@ -724,15 +772,15 @@ __device__ void coulomb_pair_item_mt(const typename P::Src* __restrict__ stg, in
             fe += (double)a[3];
         }
         const int p = (CP_SUPER * Bs + b) * 64 + lane;
-        store_part(&part[(int64_t)A * Z + p], fx * fsc, fy * fsc, fz * fsc, fe * vsc);
+        put_part<E>(part, A, Z, p, fx * fsc, fy * fsc, fz * fsc, fe * vsc);
     }
     __syncthreads();
 }
 
-template <class P, bool E, class PT = double4>
+// part: a partial array (float4* / double4*) or a FixedPart (put_part).
+template <class P, bool E, class PH>
 __device__ void coulomb_pair_item(const typename P::Src* __restrict__ stg, int Z,
-                                  const CoulConsts& k, PT* __restrict__ part, int item,
-                                  char* lds)
+                                  const CoulConsts& k, PH part, int item, char* lds)
 {
     using Src = typename P::Src;
     using CA = typename P::CAcc;
@@ -741,7 +789,7 @@ __device__ void coulomb_pair_item(const typename P::Src* __restrict__ stg, int Z
     int A, Bs;
     coulomb_pair_ab(item, S, &A, &Bs);
     if (A != Bs && CP_SUPER * Bs + CP_SUPER <= Z / 64) {  // A < B, every block full
-        coulomb_pair_item_mt<P, E, PT>(stg, Z, k, part, A, Bs, lds);
+        coulomb_pair_item_mt<P, E, PH>(stg, Z, k, part, A, Bs, lds);
         return;
     }
     const int tid = threadIdx.x, w = tid >> 6, lane = tid & 63;
@@ -855,8 +903,8 @@ __device__ void coulomb_pair_item(const typename P::Src* __restrict__ stg, int Z
         const double fsc = P::coul_fscale(k), vsc = P::coul_vscale(k);
         if (A != Bs) {
             if (tv)
-                store_part(&part[(int64_t)Bs * Z + t], (double)tx * fsc, (double)ty * fsc,
-                           (double)tz * fsc, (double)te * vsc);
+                put_part<E>(part, Bs, Z, t, (double)tx * fsc, (double)ty * fsc,
+                            (double)tz * fsc, (double)te * vsc);
         } else {
             CA* a = acc + ((w * CP_SUPER + (I - CP_SUPER * A)) * 64 + lane) * 4;
             a[0] += tx;
@@ -881,7 +929,7 @@ __device__ void coulomb_pair_item(const typename P::Src* __restrict__ stg, int Z
                 e += (double)a[3];
             }
             const double fsc = P::coul_fscale(k), vsc = P::coul_vscale(k);
-            store_part(&part[(int64_t)A * Z + p], fx * fsc, fy * fsc, fz * fsc, e * vsc);
+            put_part<E>(part, A, Z, p, fx * fsc, fy * fsc, fz * fsc, e * vsc);
         }
     }
     __syncthreads();
@@ -923,7 +971,10 @@ struct NucArgs {
     unsigned long long* pairs;
     uint32_t* err;
     double4* fnuc;           // batch form: raw nuclear (F, V) per sorted slot, no epilogue
-    unsigned long long* react;  // [n][4] Newton-3 reactions (variant 4), fixed point
+    unsigned long long* react;  // [4][react_stride] fixed-point accumulators per sorted
+                                // slot (x, y, z, V): Newton-3 reactions (variant 4) and
+                                // the fixed-point form's Coulomb sums
+    int64_t react_stride;
 };
 
 template <class P, bool NUC, int MODE>

@@ -121,7 +121,8 @@ def test_argument_errors(B):
     assert B.lib.pasta_get_tuning(ctypes.byref(t)) == 0
     for field, value in (("nuclear_variant", 5), ("list_skin", 0.0), ("list_skin", -1.0),
                          ("batch_wgs_per_cu", 9), ("batch_wgs_per_cu", -1),
-                         ("list_pool_scale", 0.0), ("coulomb_form", 2), ("fused_forces", 2),
+                         ("list_pool_scale", 0.0), ("coulomb_form", 3), ("coulomb_form", -1),
+                         ("fused_forces", 2),
                          ("nuclear_tile", 128), ("nuclear_tile", 2048), ("nuclear_tile", -1)):
         bad_t = B.pasta_tuning()
         ctypes.pointer(bad_t)[0] = t

@@ -105,10 +105,13 @@ def test_forces_terms(env, prec, terms):
 
 @pytest.mark.parametrize("prec", [0, 1])
 @pytest.mark.parametrize("name,cf", [("n51200_yp020_n0.080", 0), ("n51200_yp020_n0.080", 1),
+                                     ("n51200_yp020_n0.080", 2),
                                      ("n409600_yp040_n0.080", 0), ("n409600_yp040_n0.080", 1),
+                                     ("n409600_yp040_n0.080", 2),
                                      ("n409600_yp005_n0.080", 1)])
 def test_forces_full_size(env, name, cf, prec):
-    """Full-size workloads, every force on the GPU, both Coulomb forms.  At
+    """Full-size workloads, every force on the GPU, every Coulomb form (form
+    2, the fixed-point accumulators, runs as form 1 in FP64).  At
     N = 51 200 the oracle evaluates every target (all 51 200 exact O(N)
     sums); at N = 409 600 (Y_P = 0.40, and the neutron-rich Y_P = 0.05 of the
     paper's large runs) a seeded sample of 1000 protons and 1000 neutrons
@@ -147,12 +150,12 @@ def test_nuclear_variants_agree(env, prec):
     try:
         for fused in (0, 1):
             for v in (0, 1, 3):
-                for cf in (0, 1):
+                for cf in (0, 1, 2):
                     B.pasta_set_tuning(nuclear_variant=v, fused_forces=fused, coulomb_form=cf)
                     out.append(B.pasta_forces(pos, sp, st["L"], precision=prec))
         # variant 3 with 256- and 1024-source tiles (fused form)
         for tile in (256, 1024):
-            for cf in (0, 1):
+            for cf in (0, 1, 2):
                 B.pasta_set_tuning(nuclear_variant=3, fused_forces=1, coulomb_form=cf,
                                    nuclear_tile=tile)
                 out.append(B.pasta_forces(pos, sp, st["L"], precision=prec))
@@ -192,16 +195,18 @@ def test_trajectory_both_forms(env, fused, variant, cf):
 @pytest.mark.parametrize("case", [
     (3200, 0.40, 0.040, 1000), (1000, 0.30, 0.060, 5), (4097, 0.20, 0.080, 6),
     (6000, 1.00, 0.050, 8), (130, 0.5, 0.008, 12), (700, 0.0915, 0.03, 13)])
-@pytest.mark.parametrize("fused", [0, 1])
-def test_coulomb_pairwise_form(env, case, prec, fused):
+@pytest.mark.parametrize("fused,cf", [(0, 1), (1, 1), (1, 2)])
+def test_coulomb_pairwise_form(env, case, prec, fused, cf):
     """The pairwise Coulomb form (each unordered pair once, reactions carried
     by a lane rotation) against the oracle: full and ragged proton blocks
-    (Z = 1280, 300, 819, 6000, 65, 64), alone and with the nuclear terms."""
+    (Z = 1280, 300, 819, 6000, 65, 64), alone and with the nuclear terms;
+    with partials (form 1) and, fused in mixed precision with the nuclear
+    terms, with fixed-point accumulators (form 2)."""
     B = env["B"]
     N, yp, dens, seed = case
     st = env["I"].make_state(N, yp, dens, 1.0, seed=seed)
     pos, sp = to_dev(env, st)
-    old = B.pasta_set_tuning(coulomb_form=1, fused_forces=fused)
+    old = B.pasta_set_tuning(coulomb_form=cf, fused_forces=fused)
     try:
         for terms in (2, 3):
             f, e = B.pasta_forces(pos, sp, st["L"], precision=prec, terms=terms)
@@ -633,3 +638,102 @@ def test_newton3_trajectory_and_counts(env, prec, tol):
           say=say)
     assert abs(en["epot"] - oe2.sum()) <= 1e-6 * abs(oe2).sum()
     sim.close()
+
+
+# ------------------------- pairwise Coulomb into fixed-point accumulators ---
+@pytest.mark.parametrize("case", [
+    (3200, 0.40, 0.040, 1000),   # the small configuration (Z = 1280)
+    (1000, 0.30, 0.060, 5),      # Z = 300: a ragged super-block
+    (700, 0.0915, 0.03, 13),     # Z = 64: one block
+    (6000, 1.00, 0.050, 8),      # all protons
+    (51200, 0.20, 0.080, 1001),  # the headline state, every target
+])
+def test_coulomb_fixed_form(env, case):
+    """Coulomb form 2 (fused, mixed precision): every pairwise item adds its
+    per-proton sums into 64-bit fixed-point accumulators instead of writing
+    one partial per super-block.  Forces and energy shares against the
+    oracle, the same bits on a repeated call (integer sums do not depend on
+    the order in which the items add), agreement with the partial form to
+    rounding, and with the Newton-3 variant, whose nuclear reactions share
+    the accumulators."""
+    B, t = env["B"], env["torch"]
+    N, yp, dens, seed = case
+    st = env["I"].make_state(N, yp, dens, 1.0, seed=seed)
+    pos, sp = to_dev(env, st)
+    old = B.pasta_set_tuning(nuclear_variant=3, fused_forces=1, coulomb_form=2)
+    try:
+        f, e = B.pasta_forces(pos, sp, st["L"], precision=1)
+        f2, e2 = B.pasta_forces(pos, sp, st["L"], precision=1)
+        B.pasta_set_tuning(nuclear_variant=4)
+        f4, e4 = B.pasta_forces(pos, sp, st["L"], precision=1)
+        B.pasta_set_tuning(nuclear_variant=3, coulomb_form=1)
+        f1, _ = B.pasta_forces(pos, sp, st["L"], precision=1)
+    finally:
+        B.pasta_set_tuning(**old)
+    assert t.equal(f, f2) and t.equal(e, e2)
+    of, oe = env["O"].forces(st["pos"], st["species"], st["L"])
+    check(f.cpu().numpy(), of, 1, e.cpu().numpy(), oe, what=f"fixed {case}", say=say)
+    check(f4.cpu().numpy(), of, 1, e4.cpu().numpy(), oe, what=f"fixed + newton3 {case}",
+          say=say)
+    d = rel(f.cpu().numpy(), f1.cpu().numpy())
+    say(f"  fixed-point vs partials: {d:.2e}")
+    assert d <= 1e-6
+
+
+def test_coulomb_fixed_trajectory_and_counts(env):
+    """Form 2 in a simulation: 20 steps with a thermostat against the oracle,
+    the pair counts (energy accumulators in use), and the forces and energy
+    shares at the final state."""
+    B = env["B"]
+    st = env["I"].workload("n3200_yp040_n0.040")
+    old = B.pasta_set_tuning(nuclear_variant=3, fused_forces=1, coulomb_form=2)
+    try:
+        sim, pos, vel = make_sim(env, st, dt=2.0, T=1.0, rescale_every=7, precision=1)
+        sim.step(20)
+        nn, nc = sim.pair_counts()
+        f, e = sim.forces()
+    finally:
+        B.pasta_set_tuning(**old)
+    op, ov, oL, *_ = env["O"].run(st["pos"], st["vel"], st["species"], st["L"], 20, dt=2.0,
+                                  T=1.0, rescale_every=7)
+    dx = np.abs(wrapped_diff(pos.cpu().numpy(), op, oL)).max()
+    say(f"  fixed-point form: max |dx| {dx:.3e}")
+    assert dx <= 2e-4
+    P = pos.cpu().numpy()
+    assert (nn, nc) == env["O"].pair_counts(P, st["species"], oL)
+    of2, oe2 = env["O"].forces(P, st["species"], oL)
+    check(f.cpu().numpy(), of2, 1, e.cpu().numpy(), oe2, what="fixed after 20 steps", say=say)
+    sim.close()
+
+
+def test_coulomb_fixed_range(env):
+    """Two protons 2^-10 fm apart (both positions exact in the 32-bit fixed
+    point of L = 32 fm): a Coulomb force of about 1.5e6 MeV/fm, past the
+    2^19 MeV/fm that form 2's fixed-point accumulators take.  The call fails
+    with PASTA_EDEVICE instead of returning a wrapped sum, the partial form
+    returns the finite force, and the next call with form 2 on an ordinary
+    state is right (the accumulators were cleared)."""
+    B, t, O = env["B"], env["torch"], env["O"]
+    dev = env["dev"]
+    L = 32.0
+    p = np.array([[8.0, 8.0, 8.0], [8.0 + 2.0 ** -10, 8.0, 8.0], [20.0, 21.0, 22.0]])
+    s = np.array([1, 1, 0], np.uint8)
+    pd, sd = t.tensor(p, device=dev), t.tensor(s, device=dev)
+    old = B.pasta_set_tuning(nuclear_variant=3, fused_forces=1, coulomb_form=2)
+    try:
+        with pytest.raises(B.PastaError) as ex:
+            B.pasta_forces(pd, sd, L, precision=1)
+        assert ex.value.code == -5
+        B.pasta_set_tuning(coulomb_form=1)
+        f, _ = B.pasta_forces(pd, sd, L, precision=1)
+        of, _ = O.forces(p, s, L)
+        assert abs(f[0, 0].item()) > 5.2e5
+        check(f.cpu().numpy(), of, 1, what="close pair, partials", say=say)
+        B.pasta_set_tuning(coulomb_form=2)
+        st = env["I"].make_state(1000, 0.30, 0.060, 1.0, seed=5)
+        pos, sp = to_dev(env, st)
+        f, e = B.pasta_forces(pos, sp, st["L"], precision=1)
+    finally:
+        B.pasta_set_tuning(**old)
+    of, oe = O.forces(st["pos"], st["species"], st["L"])
+    check(f.cpu().numpy(), of, 1, e.cpu().numpy(), oe, what="after the range error", say=say)
