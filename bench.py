@@ -367,26 +367,36 @@ def single_via_batch(B, torch, st, steps, warmup):
 
 
 def run_sequential(B, torch, states, precision, steps, warmup):
-    """The same systems one after another on the single-system path."""
+    """The same systems one after another on the single-system path, each
+    with the kernel setting the autotuner picks on its own start state (the
+    tuning is outside the timed steps; the process-wide setting is restored
+    afterwards)."""
+    from paper_1412_8502_amd.autotune import tune
     dev = torch.device("cuda:0")
-    total, pairs = 0.0, 0.0
-    for st in states:
-        pos = torch.tensor(st["pos"], device=dev)
-        vel = torch.tensor(st["vel"], device=dev)
-        sp = torch.tensor(st["species"], device=dev)
-        sim = B.Sim(pos, vel, sp, st["L"], dt=2.0, T=st["T"], rescale_every=100,
-                    precision=precision)
-        sim.step(warmup)
-        torch.cuda.synchronize()
-        nn, nc = sim.pair_counts()
-        torch.cuda.synchronize()
-        t0 = time.perf_counter()
-        sim.step(steps)
-        torch.cuda.synchronize()
-        total += time.perf_counter() - t0
-        pairs += nn + nc
-        sim.close()
-    return dict(seconds=total, pairs_per_step=pairs)
+    total, pairs, settings = 0.0, 0.0, []
+    old = B.pasta_get_tuning()
+    try:
+        for st in states:
+            pos = torch.tensor(st["pos"], device=dev)
+            vel = torch.tensor(st["vel"], device=dev)
+            sp = torch.tensor(st["species"], device=dev)
+            best, _, _ = tune(pos, sp, st["L"], precision, use_cache=False)
+            settings.append([best["nuclear_variant"], best["fused_forces"], best["coulomb_form"]])
+            sim = B.Sim(pos, vel, sp, st["L"], dt=2.0, T=st["T"], rescale_every=100,
+                        precision=precision)
+            sim.step(warmup)
+            torch.cuda.synchronize()
+            nn, nc = sim.pair_counts()
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            sim.step(steps)
+            torch.cuda.synchronize()
+            total += time.perf_counter() - t0
+            pairs += nn + nc
+            sim.close()
+    finally:
+        B.pasta_set_tuning(**old)
+    return dict(seconds=total, pairs_per_step=pairs, settings=settings)
 
 
 def kernel_ms(kt, steps):
@@ -530,14 +540,16 @@ def batched_section(B, torch, steps, warmup):
                                      tuning_trials_ms=multi["tuning_table"])
     seqm = run_sequential(B, torch, states, B.PASTA_MIXED, steps, warmup)
     log(f"sequential mixed: {seqm['seconds'] / steps * 1e3:.4f} ms/step")
-    out["sequential_mixed"] = entry(seqm)
+    out["sequential_mixed"] = dict(entry(seqm), settings=seqm["settings"],
+                                   settings_fields="[nuclear_variant, fused_forces, coulomb_form]"
+                                                   " per system, autotuned on its start state")
     seq64 = run_sequential(B, torch, states, B.PASTA_FP64, max(50, steps // 5), warmup)
     log(f"sequential fp64: {seq64['seconds'] / max(50, steps // 5) * 1e3:.4f} ms/step")
     k64 = max(50, steps // 5)
     out["sequential_fp64"] = {"ms_per_step": seq64["seconds"] / k64 * 1e3,
                               "system_steps_per_s": nsys * k64 / seq64["seconds"],
                               "pair_interactions_per_s": seq64["pairs_per_step"] * k64 / seq64["seconds"],
-                              "steps": k64}
+                              "steps": k64, "settings": seq64["settings"]}
     best = min(out["persistent_mixed"]["ms_per_step"], out["multi_kernel_mixed"]["ms_per_step"])
     out["speedup_vs_sequential_mixed"] = out["sequential_mixed"]["ms_per_step"] / best
     out["speedup_vs_sequential_fp64"] = out["sequential_fp64"]["ms_per_step"] / best

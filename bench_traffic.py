@@ -19,7 +19,7 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 SOURCES = ["paper_1412_8502_amd/csrc/forces.hip", "paper_1412_8502_amd/csrc/fp64math.hpp",
            "paper_1412_8502_amd/csrc/internal.hpp", "paper_1412_8502_amd/csrc/list_items.hpp",
            "paper_1412_8502_amd/csrc/pair_items.hpp"]
-SETTINGS = [(3, 32, 1, 0), (3, 0, 1, 1), (3, 0, 1, 2)]
+SETTINGS = [(3, 32, 1, 0), (3, 0, 1, 1), (3, 0, 1, 2), (1, 0, 1, 1), (1, 0, 1, 2)]
 # public coulomb_form -> the fused kernel's Coulomb template argument
 FUSED_COULOMB_ARG = {0: 0, 1: 1, 2: 3}
 COPY_KIB = 256 * 1024

@@ -173,7 +173,8 @@ int pasta_set_tuning(const pasta_tuning* t);
 int pasta_get_tuning(pasta_tuning* out);
 /* Autotuner: builds the cell list of the given state once, then times the
  * Coulomb + nuclear kernels (reps evaluations of the forces each, without
- * energies as in a simulation step; HIP events) for every
+ * energies as in a simulation step; HIP events; the list of candidates is
+ * timed twice and each keeps its faster pass) for every
  * candidate setting -- nuclear variant {0, 1, 3, 4 (fused only), 3 with
  * 256- and 1024-source tiles (fused only)} x Coulomb
  * {gather with splits S/2, S, 2S around the automatic S, pairwise,

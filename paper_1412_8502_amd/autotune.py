@@ -49,7 +49,7 @@ def _store_cache(path, data):
     os.replace(tmp, path)
 
 
-def pasta_autotune(pos, species, L: float, precision: int, reps: int = 3, pot=None,
+def pasta_autotune(pos, species, L: float, precision: int, reps: int = 5, pot=None,
                    stream=None):
     """Times every candidate setting on this state (see include/pasta.h).
     Returns (best dict, [(candidate dict, ms), ...])."""
