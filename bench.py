@@ -694,11 +694,15 @@ def main():
         tuned = dict(nuclear_variant=v, coulomb_splits=sp_, fused_forces=fu, coulomb_form=cf,
                      nuclear_tile=tile)
         tuned64, table, table64 = dict(tuned), [], []
+        runoff = runoff64 = None
         B.pasta_set_tuning(**tuned)
     else:
+        from paper_1412_8502_amd import autotune
         tuned64, _, table64 = tune(tpos, tsp, st["L"], B.PASTA_FP64, use_cache=False,
                                    apply=False)
+        runoff64 = autotune.last_runoff
         tuned, _, table = tune(tpos, tsp, st["L"], B.PASTA_MIXED, use_cache=False, apply=True)
+        runoff = autotune.last_runoff
     log(f"kernel setting mixed: {tuned}  fp64: {tuned64}")
     del tpos, tsp
     mixed_cells = run_path(B, torch, st, B.PASTA_MIXED, K, W, timing=True, windows=5)
@@ -879,7 +883,16 @@ def main():
                                                round(ms, 5)] for c, ms in table],
                       "fp64_candidates_ms": [[c["fused_forces"], c["nuclear_variant"],
                                               c.get("coulomb_form", 0), c["coulomb_splits"],
-                                              round(ms, 5)] for c, ms in table64]},
+                                              round(ms, 5)] for c, ms in table64],
+                      "step_runoff": "candidates within 3 % of the fastest force-only time, "
+                                     "timed on simulation steps: [fused_forces, "
+                                     "nuclear_variant, coulomb_form, nuclear_tile, ms per step]",
+                      "mixed_runoff_ms": [[c["fused_forces"], c["nuclear_variant"],
+                                           c.get("coulomb_form", 0), c.get("nuclear_tile", 0),
+                                           round(ms, 5)] for c, ms in (runoff or [])],
+                      "fp64_runoff_ms": [[c["fused_forces"], c["nuclear_variant"],
+                                          c.get("coulomb_form", 0), c.get("nuclear_tile", 0),
+                                          round(ms, 5)] for c, ms in (runoff64 or [])]},
         "dense_nuclear_variant": {"ms_per_step": dense["seconds"] / kd * 1e3,
                                   "nuclear_ms": dense["kernel_times"]["nuclear+kick"][0] / kd},
         "newton3_half_stencil_variant": {"ms_per_step": n3["seconds"] / kn3 * 1e3,

@@ -13,6 +13,7 @@ import ctypes
 import json
 import math
 import os
+import time
 
 import torch
 
@@ -74,9 +75,46 @@ def pasta_autotune(pos, species, L: float, precision: int, reps: int = 5, pot=No
     return {f: getattr(best, f) for f in keys}, table
 
 
-def tune(pos, species, L: float, precision: int, use_cache: bool = True, apply: bool = True):
+# the step runoff of the last measured tune() call: [(setting, ms per step)] or None
+last_runoff = None
+
+
+def step_runoff(pos, species, L: float, precision: int, finalists, seconds: float = 0.25,
+                est_ms: float = 1.0):
+    """Times each finalist setting on simulation steps of this state (zero
+    starting velocities, no thermostat): the per-step cell rebuild and the
+    combine's drift and binning are part of the step, and they are not in
+    the force-only timings of pasta_autotune.  Two alternating passes of
+    about `seconds` each per finalist; each keeps its faster pass.  Leaves
+    the process-wide setting unchanged.  Returns [(setting, ms per step)]."""
+    steps = max(10, min(400, int(seconds / max(est_ms, 1e-3) * 1e3)))
+    best = [float("inf")] * len(finalists)
+    old = B.pasta_get_tuning()
+    try:
+        for _ in range(2):
+            for i, cand in enumerate(finalists):
+                B.pasta_set_tuning(**cand)
+                sim = B.Sim(pos.clone(), torch.zeros_like(pos), species, L, dt=2.0,
+                            precision=precision)
+                sim.step(5)
+                torch.cuda.synchronize()
+                t0 = time.perf_counter()
+                sim.step(steps)
+                torch.cuda.synchronize()
+                best[i] = min(best[i], (time.perf_counter() - t0) / steps * 1e3)
+                sim.close()
+    finally:
+        B.pasta_set_tuning(**old)
+    return list(zip(finalists, best))
+
+
+def tune(pos, species, L: float, precision: int, use_cache: bool = True, apply: bool = True,
+         margin: float = 0.03, max_finalists: int = 4):
     """Cached autotune for this workload shape; applies the result
-    process-wide when `apply`.  Returns (setting, source, table)."""
+    process-wide when `apply`.  The force-only timings of pasta_autotune
+    rank the candidates; those within `margin` of the fastest (at most
+    `max_finalists`) are then timed on simulation steps (step_runoff), and
+    the fastest step wins.  Returns (setting, source, table)."""
     n = pos.shape[0]
     z = int((species == 1).sum().item())
     key = shape_key(n, z, L, precision)
@@ -87,9 +125,21 @@ def tune(pos, species, L: float, precision: int, use_cache: bool = True, apply: 
         best, source = data[key]["best"], "cache"
     else:
         best, table = pasta_autotune(pos, species, L, precision)
+        fast = min(ms for _, ms in table)
+        finalists = []
+        for cand, ms in sorted(table, key=lambda r: r[1]):
+            if ms <= fast * (1.0 + margin) and cand not in finalists:
+                finalists.append(cand)
+        finalists = finalists[:max_finalists]
+        runoff = None
+        if len(finalists) > 1 and n > 0:
+            runoff = step_runoff(pos, species, L, precision, finalists, est_ms=fast)
+            best = min(runoff, key=lambda r: r[1])[0]
+        global last_runoff
+        last_runoff = runoff
         source = "measured"
         if use_cache:
-            data[key] = {"best": best, "table": table}
+            data[key] = {"best": best, "table": table, "runoff": runoff}
             _store_cache(path, data)
     if apply:
         B.pasta_set_tuning(**best)
