@@ -180,14 +180,17 @@ def tune_list_skin(pos, vel, species, L: float, precision: int, T: float, skins=
 
 
 def tune_batch(pos, vel, species, ns, L0s, integs, precision: int, mode: int = 0,
-               variants=(1, 3), coulomb_forms=(0, 1), wgs_per_cu=(3, 4, 5), steps: int = 60,
+               variants=(1, 3), coulomb_forms=None, wgs_per_cu=(3, 4, 5), steps: int = 60,
                warmup: int = 10, steps_per_graph: int = 10):
     """Chooses the batched path's kernel setting on its own workload by timed
-    runs: the nuclear variant, the Coulomb form (gather tiles or pairwise
-    super-block items) and, for the persistent mode, the workgroups per CU
-    of the persistent kernel.  Each candidate advances a copy of the systems
-    `warmup` + `steps` steps.  Leaves the process-wide setting unchanged.
-    Returns (best dict, [(candidate dict, ms per step)])."""
+    runs: the nuclear variant, the Coulomb form (gather tiles, pairwise
+    super-block items with partials, and in mixed precision pairwise items
+    into fixed-point accumulators) and, for the persistent mode, the
+    workgroups per CU of the persistent kernel.  Each candidate advances a
+    copy of the systems `warmup` + `steps` steps.  Leaves the process-wide
+    setting unchanged.  Returns (best dict, [(candidate dict, ms per step)])."""
+    if coulomb_forms is None:
+        coulomb_forms = (0, 1, 2) if precision == B.PASTA_MIXED else (0, 1)
     table = []
     old = B.pasta_get_tuning()
     grids = wgs_per_cu if mode == 0 else (0,)

@@ -82,6 +82,9 @@ struct BatchDev {
     int32_t* n_items;
     void* stg;            // Q4 or double4 per sorted slot
     void* coul_part;      // Coulomb partials, typename P::CPart per entry
+    unsigned long long* react;  // [4][n_total] fixed-point Coulomb sums per slot (the
+                                // fixed-point form; zero between force phases)
+    int64_t n_total;
     double4* fnuc;
     double* ke_chunk;
     double* pending;      // per-system velocity scale pending from the thermostat
@@ -500,6 +503,10 @@ __device__ void phase_forces(const BatchDev& B, int64_t step, int mode, char* ld
             PT* part = static_cast<PT*>(B.coul_part) + S.coul_off;
             if (S.coul_form == 1) {
                 coulomb_pair_item<P, M != MODE_FORCE>(stg + S.off, S.Z, k, part, (int)local, lds);
+            } else if (S.coul_form == 3) {
+                coulomb_pair_item<P, M != MODE_FORCE>(
+                    stg + S.off, S.Z, k, FixedPart{B.react + S.off, B.err, B.n_total},
+                    (int)local, lds);
             } else {
                 const int tblock = (int)(local % S.coul_blocks),
                           split = (int)(local / S.coul_blocks);
@@ -596,7 +603,19 @@ __device__ void phase_combine(const BatchDev& B, int64_t step, int mode, bool en
             const int64_t k = S.off + sl;
             const double4 fn = B.fnuc[k];
             double Fx = fn.x, Fy = fn.y, Fz = fn.z, V = fn.w;
-            if (sl < S.Z) {
+            if (sl < S.Z && S.coul_form == 3) {
+                // fixed-point sums, cleared for the next force phase
+                unsigned long long* r = B.react + k;
+                const int64_t N = B.n_total;
+                Fx += (double)(long long)r[0] * REACT_UNIT;
+                Fy += (double)(long long)r[N] * REACT_UNIT;
+                Fz += (double)(long long)r[2 * N] * REACT_UNIT;
+                V += (double)(long long)r[3 * N] * REACT_UNIT;
+                r[0] = 0ull;
+                r[N] = 0ull;
+                r[2 * N] = 0ull;
+                r[3 * N] = 0ull;
+            } else if (sl < S.Z) {
                 // partials in order k = 0, 1, ..., loaded eight at a time so
                 // that the loads are in flight together
                 constexpr int U = 8;
@@ -1087,7 +1106,8 @@ int batch_variant()
 }
 int batch_chunk() { return nuclear_chunk_for(batch_variant()); }
 
-int batch_layout(const pasta_potential* pot, int nsys, const int64_t* n, const int64_t* Z,
+int batch_layout(const pasta_potential* pot, int precision, int nsys, const int64_t* n,
+                 const int64_t* Z,
                  const double* L_max, BatchLayout* out)
 {
     if (!(pot->r_coul > 0) || std::isfinite(pot->r_coul))
@@ -1111,7 +1131,7 @@ int batch_layout(const pasta_potential* pot, int nsys, const int64_t* n, const i
         // the partial capacity depends on n only (the single-system path's
         // rule), and the plan keeps S * Z within it for the system's Z
         const int64_t cap = coulomb_partial_capacity(n[s]);
-        const CoulPlan cp = coulomb_plan(S.Z, cap, false);
+        const CoulPlan cp = coulomb_plan(S.Z, cap, false, precision == PASTA_MIXED);
         S.coul_form = cp.form;
         S.S = cp.S;
         S.per_split = (S.S && cp.form == 0) ? (int32_t)((S.Z + S.S - 1) / S.S) : 0;
@@ -1127,7 +1147,8 @@ int batch_layout(const pasta_potential* pot, int nsys, const int64_t* n, const i
         lay.items += S.item_max;
         lay.coul += cap;
         lay.total_chunks += S.nchunks;
-        lay.coul_items += cp.form == 1 ? coulomb_pair_items(S.Z) : (int64_t)S.coul_blocks * S.S;
+        lay.coul_items += (cp.form == 1 || cp.form == 3) ? coulomb_pair_items(S.Z)
+                                                         : (int64_t)S.coul_blocks * S.S;
         lay.nuc_items += S.item_max;
     }
     *out = lay;
@@ -1160,6 +1181,8 @@ size_t batch_carve(Carver& cv, const BatchLayout& lay, int nsys, int precision, 
         b.coul_part = cv.take<double4>(lay.coul);
     else
         b.coul_part = cv.take<float4>(lay.coul);
+    b.react = cv.take<unsigned long long>(4 * N);
+    b.n_total = N;
     b.fnuc = cv.take<double4>(N);
     b.ke_chunk = cv.take<double>(lay.total_chunks);
     b.pending = cv.take<double>(nsys);
@@ -1282,7 +1305,7 @@ extern "C" int pasta_batch_workspace(const pasta_potential* pot, int32_t precisi
         (precision != PASTA_FP64 && precision != PASTA_MIXED))
         return fail(PASTA_EINVAL, "pasta_batch_workspace: bad argument");
     BatchLayout lay;
-    PASTA_TRY(batch_layout(pot, nsys, h_n, nullptr, h_L_max, &lay));
+    PASTA_TRY(batch_layout(pot, precision, nsys, h_n, nullptr, h_L_max, &lay));
     Carver cv(nullptr);
     *h_bytes = batch_carve(cv, lay, nsys, precision, nullptr);
     return PASTA_OK;
@@ -1312,7 +1335,7 @@ extern "C" int pasta_batch_create(const pasta_potential* pot, int32_t precision,
                         "[2 r_nuc, L_max]", s, Ls);
     }
     BatchLayout lay;
-    PASTA_TRY(batch_layout(pot, nsys, h_n, nullptr, h_L_max, &lay));
+    PASTA_TRY(batch_layout(pot, precision, nsys, h_n, nullptr, h_L_max, &lay));
     Carver cv0(nullptr);
     const size_t need = batch_carve(cv0, lay, nsys, precision, nullptr);
     if (!d_work || work_bytes < need || (reinterpret_cast<uintptr_t>(d_work) & 255))
@@ -1363,7 +1386,7 @@ extern "C" int pasta_batch_create(const pasta_potential* pot, int32_t precision,
             }
     }
     BatchLayout lay2;
-    int rc = batch_layout(pot, nsys, h_n, Z.data(), h_L_max, &lay2);
+    int rc = batch_layout(pot, precision, nsys, h_n, Z.data(), h_L_max, &lay2);
     if (rc != PASTA_OK)
         return fail_free(rc);
     // the Z-dependent layout fits the carve made with Z = n: the partial
@@ -1408,6 +1431,9 @@ extern "C" int pasta_batch_create(const pasta_potential* pot, int32_t precision,
         return fail_free(fail(PASTA_EHIP, "pasta_batch_create: descriptor copy failed"));
     k_batch_init_scalars<<<1, 1024, 0, s>>>(B, step0);
     k_batch_zero<<<256, BW, 0, s>>>(B.count, B.fill, lay.bins);
+    k_batch_zero<<<256, BW, 0, s>>>(reinterpret_cast<int32_t*>(B.react),
+                                    reinterpret_cast<int32_t*>(B.react) + 4 * lay.n_total,
+                                    4 * lay.n_total);
     k_batch_load<<<256, BW, 0, s>>>(B, lay.n_total);
     rc = precision == PASTA_FP64 ? persistent_grid<Fp64Policy>(B.nuc_variant, &bt->grid)
                                  : persistent_grid<MixedPolicy>(B.nuc_variant, &bt->grid);
@@ -1591,6 +1617,12 @@ extern "C" int pasta_batch_pair_counts(pasta_batch* bt, int64_t* h_nuclear, int6
     // the cell lists and staging of the current state are in place; the
     // count pass rewrites F (same values) without a kick
     launch_pair_phase<MODE_COUNT>(bt->dev, bt->precision, s);
+    // no combine follows: clear the fixed-point Coulomb sums the count pass
+    // added, so the next combine reads only its own force phase's
+    k_batch_zero<<<256, BW, 0, s>>>(reinterpret_cast<int32_t*>(bt->dev.react),
+                                    reinterpret_cast<int32_t*>(bt->dev.react) +
+                                        4 * bt->dev.n_total,
+                                    4 * bt->dev.n_total);
     PASTA_HIP(hipGetLastError());
     std::vector<unsigned long long> h(bt->nsys);
     PASTA_HIP(hipMemcpyAsync(h.data(), bt->dev.pairs, sizeof(unsigned long long) * bt->nsys,

@@ -49,13 +49,15 @@ def make(env, specs, integs=None, prec=1, mode=0, spg=4, L_max=None):
     return b, states, pos, vel, offs
 
 
-@pytest.mark.parametrize("form", [0, 1])
+@pytest.mark.parametrize("form", [0, 1, 2])
 @pytest.mark.parametrize("mode", [0, 1])
 @pytest.mark.parametrize("prec", [0, 1])
 def test_batch_initial_forces(env, prec, mode, form):
     """Forces and energy shares of every system against the oracle, with the
     Coulomb term as gather tiles (form 0) or as pairwise super-block items
-    (form 1; the all-neutron system has none, the all-proton one the most)."""
+    (form 1; the all-neutron system has none, the all-proton one the most),
+    or, in mixed precision, as pairwise items into fixed-point accumulators
+    (form 2; FP64 runs it as form 1)."""
     B = env["B"]
     say("batch initial forces prec", prec, "mode", mode, "coulomb form", form)
     old = B.pasta_set_tuning(coulomb_form=form)
@@ -118,7 +120,7 @@ def test_batch_modes_and_graph_replay_agree(env):
         assert np.abs(v - outs[0][1]).max() <= 1e-12
 
 
-@pytest.mark.parametrize("variant,form", [(1, 0), (3, 0), (3, 1)])
+@pytest.mark.parametrize("variant,form", [(1, 0), (3, 0), (3, 1), (3, 2)])
 def test_batch_matches_single_system_path(env, variant, form):
     """With the same nuclear variant and Coulomb form, the batched and
     single-system paths run the same items in the same order."""
