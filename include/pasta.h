@@ -146,7 +146,7 @@ typedef struct pasta_integrator {
  *   limit; a proton sum outside +-2^19 MeV/fm sets the device error word);
  *   only in the fused form in mixed precision, elsewhere it runs as 1.  The
  *   batched path reads it at creation and plans each system's Coulomb term
- *   as form 0 or 1.
+ *   the same way (form 2 in mixed precision only).
  * list_skin: the halo delta_r of variant 2, fm, in (0, 64] (default 2).
  * batch_wgs_per_cu: workgroups per compute unit of the persistent batched
  *   kernel (mode 0), 1..8, capped at what fits; 0 = as many as fit.  Read
